@@ -1,0 +1,92 @@
+"""Oracle's own parser of the project's circuit text format.
+
+One op per line; '#' starts a comment.  Header lines: QUBITS n, ORDER
+q0 q1 ... (qubit held by each MPS site), SEED q, TARGET T|S.  Ops:
+H S SDG T TDG X Y Z q | CX CZ a b | M q | R q | DEP1 q | DEP2 a b | XERR q |
+TICK.  Channels (DEP1, DEP2, XERR) are numbered in text order, as are
+measurements.  The noise semantics follow Section 4 (uniform depolarising,
+any of the 4^k-1 non-identity Paulis with probability p/(4^k-1)).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+ONE_Q = {"H", "S", "SDG", "T", "TDG", "X", "Y", "Z"}
+TWO_Q = {"CX", "CZ"}
+
+
+@dataclass
+class OCircuit:
+    n: int
+    ops: list                          # tuples, see parse()
+    order: list
+    seed: int
+    target: str
+    n_channels: int
+    n_meas: int
+    channel_arity: list = field(default_factory=list)   # 1 or 2 per channel
+    channel_kind: list = field(default_factory=list)    # "DEP1"|"DEP2"|"XERR"
+
+
+def parse(text: str) -> OCircuit:
+    """Parse circuit text into ('g1', name, q) / ('g2', name, a, b) /
+    ('m', q, meas_idx) / ('r', q) / ('ch', kind, chan_idx, qubits)."""
+    n = None
+    order = None
+    seed = 0
+    target = "T"
+    ops = []
+    nch = 0
+    nm = 0
+    arity = []
+    kinds = []
+    for raw in text.splitlines():
+        line = raw.split("#", 1)[0].strip()
+        if not line:
+            continue
+        tok = line.split()
+        op = tok[0].upper()
+        args = tok[1:]
+        if op == "QUBITS":
+            n = int(args[0])
+        elif op == "ORDER":
+            order = [int(a) for a in args]
+        elif op == "SEED":
+            seed = int(args[0])
+        elif op == "TARGET":
+            target = args[0].upper()
+        elif op == "TICK":
+            continue
+        elif op in ONE_Q:
+            ops.append(("g1", op, int(args[0])))
+        elif op in TWO_Q:
+            a, b = int(args[0]), int(args[1])
+            if a == b:
+                raise ValueError("two-qubit gate on one qubit")
+            ops.append(("g2", op, a, b))
+        elif op == "M":
+            ops.append(("m", int(args[0]), nm))
+            nm += 1
+        elif op == "R":
+            ops.append(("r", int(args[0])))
+        elif op in ("DEP1", "XERR"):
+            ops.append(("ch", op, nch, (int(args[0]),)))
+            arity.append(1)
+            kinds.append(op)
+            nch += 1
+        elif op == "DEP2":
+            ops.append(("ch", op, nch, (int(args[0]), int(args[1]))))
+            arity.append(2)
+            kinds.append(op)
+            nch += 1
+        else:
+            raise ValueError(f"unknown op {op!r}")
+    if n is None:
+        raise ValueError("missing QUBITS")
+    if order is None:
+        order = list(range(n))
+    if sorted(order) != list(range(n)):
+        raise ValueError("ORDER is not a permutation")
+    return OCircuit(n=n, ops=ops, order=order, seed=seed, target=target,
+                    n_channels=nch, n_meas=nm, channel_arity=arity,
+                    channel_kind=kinds)

@@ -57,7 +57,8 @@ def reweight(n, a, e, M: int, p: float):
         pacc += b * a[w] / n[w]
         ple_num += b * e[w] / n[w]
     wmax = len(n) - 1
-    B = max(0.0, 1.0 - sum(binom_pmf(M, w, p) for w in range(wmax + 1)))
+    # B is the tail sum itself (Appendix "Systematics"), not 1 - head
+    B = sum(binom_pmf(M, w, p) for w in range(wmax + 1, M + 1))
     return dict(p_acc=pacc, p_acc_le=ple_num,
                 p_le=(ple_num / pacc) if pacc > 0 else float("nan"), B=B)
 

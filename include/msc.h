@@ -1,0 +1,236 @@
+/*
+ * msc.h -- C ABI of the batched exact-MPS magic-state-cultivation shot
+ * simulator for MI355X (gfx950).
+ *
+ * Conventions shared by every entry point
+ *  - Every function that can fail returns int: MSC_OK (0) or a negative
+ *    msc_status.  msc_last_error() returns a thread-local message for the
+ *    most recent failure.  No C++ exception crosses this boundary.
+ *  - Handles (msc_ctx, msc_circuit) are created and freed by the library.
+ *    Every array is owned by the caller.  Arguments documented as "device"
+ *    must be device pointers on the context's GPU (for example the data of a
+ *    torch tensor); arguments documented as "host" must be host pointers.
+ *  - Device entry points run on the context's stream and return after the
+ *    stream has finished the call (results are ready on return).
+ *
+ * Circuit text format (one op per line, '#' comments):
+ *   QUBITS n | ORDER q0 q1 ... (qubit held by MPS site i) | SEED q |
+ *   TARGET T|S | H S SDG T TDG X Y Z q | CX CZ a b | M q | R q |
+ *   DEP1 q | DEP2 a b | XERR q | TICK
+ * Channels (DEP1, DEP2, XERR) and measurements are numbered in text order.
+ * R is legal only as the first op on a qubit or when the last op on that
+ * qubit was M.
+ */
+#ifndef MSC_H
+#define MSC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum msc_status {
+    MSC_OK = 0,
+    MSC_E_PARSE = -1,            /* malformed circuit text                    */
+    MSC_E_INVALID = -2,          /* bad argument, size or pointer             */
+    MSC_E_NONDETERMINISTIC = -3, /* noiseless run: some p(e_m) != 1 or f != 1 */
+    MSC_E_CAPACITY = -4,         /* caller-provided capacity too small        */
+    MSC_E_DEVICE = -5,           /* HIP error (message has the HIP text)      */
+    MSC_E_OOM = -6,              /* device allocation failed                  */
+    MSC_E_STATE = -7             /* call not valid in the current state       */
+};
+
+enum msc_precision {
+    MSC_FP64 = 0,   /* complex128 tensors and contractions                    */
+    MSC_FP32 = 1    /* complex64 tensors, FP32 contractions, FP64 truncation,
+                       norms and probabilities                                */
+};
+
+/* bits of msc_shot_result.status */
+enum msc_shot_status {
+    MSC_SHOT_DONE = 1,          /* reached the end of the circuit             */
+    MSC_SHOT_REJECTED = 2,      /* an expected outcome had p < tau_rej        */
+    MSC_SHOT_CHI_CAP = 4,       /* chi_max bound with weight > 1e-12 dropped  */
+    MSC_SHOT_NOCONV = 8         /* an SVD hit its sweep limit                 */
+};
+
+typedef struct msc_ctx msc_ctx;
+typedef struct msc_circuit msc_circuit;
+
+typedef struct {
+    int32_t n_qubits;
+    int32_t n_meas;
+    int32_t n_channels;   /* M of Eq. (reweight)                             */
+    int32_t n_decided;    /* measurements decided by the offline screen      */
+    int32_t seed_qubit;
+    int32_t target;       /* 'T' or 'S'                                      */
+    int32_t words;        /* uint64 words per pre-screen signature           */
+    int32_t calibrated;   /* expected outcomes known (msc_circuit_calibrate) */
+    int64_t n_ops;        /* compiled MPS op stream length                   */
+    int64_t n_twosite;    /* two-site updates in one full shot               */
+    int64_t n_swaps;      /* of which routing SWAPs                          */
+} msc_circuit_info;
+
+typedef struct {
+    int32_t precision;    /* msc_precision                                   */
+    int32_t chi_max;      /* bond cap (must not bind in the exact regime)    */
+    double tau_trunc;     /* keep sigma_i > tau_trunc * sigma_0; <= 0: auto
+                             (1e-12 for MSC_FP64, 1e-5 for MSC_FP32)          */
+    double tau_rej;       /* reject when p(e_m) < tau_rej (default 1e-6)     */
+    double tau_fail;      /* logical failure iff 1 - f > tau_fail (1e-4)     */
+    int32_t n_slots;      /* persistent workgroups; 0 = auto                 */
+    int32_t reserved;
+} msc_sim_opts;
+
+typedef struct {
+    double p_acc;         /* prod_m p(e_m): post-selection probability       */
+    double infid;         /* 1 - |<target|rho_seed|target>| (0 if rejected)  */
+    double disc_weight;   /* sum of dropped sigma^2 over the shot            */
+    int32_t chi_peak;     /* largest bond dimension reached                  */
+    int32_t status;       /* msc_shot_status bits                            */
+    int32_t rejected_at;  /* measurement index that rejected, or -1          */
+    int32_t fail;         /* 1 iff accepted (p_acc > 0) and infid > tau_fail */
+    int64_t n2q;          /* two-site updates executed                       */
+    double flops;         /* algorithmic flops of those updates: per update
+                             32 cl cm cr (contraction) + 32 cl^2 cr (Gram)
+                             + 32 r cl cr (projection) + 104 cl^3 (eigen-
+                             solve) with cl, cm, cr the bonds around the two
+                             sites and r the new bond                      */
+    int64_t reserved;
+} msc_shot_result;
+
+typedef struct {
+    double p_acc;         /* Eq. (reweight), first line                      */
+    double p_acc_le;      /* Eq. (reweight), second line                     */
+    double p_le;          /* p_acc_le / p_acc                                */
+    double trunc_bound;   /* B = sum_{w > w_max} Bin_w(p)                     */
+} msc_estimate;
+
+/* Message of the last failure on this thread (never NULL). */
+const char* msc_last_error(void);
+
+/* Library version string. */
+const char* msc_version(void);
+
+/* ---------------------------------------------------------------------- */
+/* Context: one GPU, one stream, grow-only device scratch.                 */
+
+/* Create a context on HIP device `device` with its own non-blocking stream
+   (default priority).  Fails with MSC_E_DEVICE when no GPU is usable.    */
+int msc_ctx_create(int device, msc_ctx** out);
+void msc_ctx_destroy(msc_ctx* ctx);
+/* Duration in ms of the last kernel launched by the named call, measured
+   with HIP events on the context's stream ("simulate", "prescreen",
+   "twosite").  Returns a negative value if none was timed.               */
+double msc_ctx_last_kernel_ms(msc_ctx* ctx, const char* which);
+
+/* ---------------------------------------------------------------------- */
+/* Circuit: parse + compile on the host (no GPU needed).                  */
+
+/* Parse `len` bytes of circuit text and compile it: MPS layout (site order
+   from `order` if non-NULL (host, n_qubits entries: order[site] = qubit),
+   else the text's ORDER line, else identity), SWAP routing of non-adjacent
+   two-qubit gates (Section 3.1: long-range gates touch every bond in
+   between), the channel table (Section 4) and the offline-screening
+   tables (Section 4.2).  Errors: MSC_E_PARSE, MSC_E_INVALID.             */
+int msc_circuit_load(const char* text, size_t len, const int32_t* order,
+                     msc_circuit** out);
+int msc_circuit_get_info(const msc_circuit* c, msc_circuit_info* out);
+/* Expected outcome e_m of every measurement (host, n_meas bytes).  Before
+   calibration these are all 0 (the paper's rule: kept iff all outcomes are
+   0, Section 4).                                                          */
+int msc_circuit_expected(const msc_circuit* c, uint8_t* out);
+/* Noiseless FP64 run on the GPU: records e_m and checks that every
+   measurement is deterministic (p(e_m) = 1 +- 1e-10) and the final
+   fidelity is 1 (Appendix "Post-selection and logical error").  Returns
+   MSC_E_NONDETERMINISTIC otherwise.  Required before msc_simulate.       */
+int msc_circuit_calibrate(msc_ctx* ctx, msc_circuit* c);
+void msc_circuit_free(msc_circuit* c);
+
+/* ---------------------------------------------------------------------- */
+/* Fault sampling (Section 4.1, subset sampling), host.                    */
+
+/* Draw faults for shots first_shot .. first_shot+n_shots-1 with seed
+   `seed`.  Per shot: weight w = weights[i] if `weights` (host, n_shots) is
+   non-NULL, else w ~ Bin(M, p); a uniform w-subset of the M channels
+   (Floyd); a uniform non-identity Pauli per chosen channel (3 for DEP1, 15
+   for DEP2, X for XERR).  Output CSR (host): shot_off[n_shots+1] (int64),
+   chan[nnz] (int32, ascending within a shot), pauli[nnz] (uint8, bit0 x_a,
+   bit1 z_a, bit2 x_b, bit3 z_b).  MSC_E_CAPACITY if more than nnz_cap
+   faults are needed (nnz_out then holds the required count).            */
+int msc_sample_faults(const msc_circuit* c, uint64_t seed, uint64_t first_shot,
+                      int64_t n_shots, const int32_t* weights, double p,
+                      int64_t* shot_off, int32_t* chan, uint8_t* pauli,
+                      int64_t nnz_cap, int64_t* nnz_out);
+
+/* ---------------------------------------------------------------------- */
+/* Offline screening (Section 4.2).                                        */
+
+/* Copy the pre-screen tables to host arrays (either may be NULL):
+   sig[(4*channel + k)*words + j] (k: X_a, Z_a, X_b, Z_b) is the bitmask of
+   decided measurements flipped by that basis fault; decided[i] is the
+   measurement index of decided measurement i (n_decided entries).        */
+int msc_prescreen_tables(const msc_circuit* c, uint64_t* sig, int32_t* decided);
+
+/* Bit-exact screen of n_shots shots given as a device CSR.  Writes
+   survive_bits (device, ceil(n_shots/64) words; bit set = must be
+   simulated), and, if survivor_idx (device, n_shots capacity) is non-NULL,
+   the indices of surviving shots in ascending order; n_survivors (host)
+   receives their count.                                                   */
+int msc_prescreen(msc_ctx* ctx, const msc_circuit* c, int64_t n_shots,
+                  const int64_t* shot_off, const int32_t* chan,
+                  const uint8_t* pauli, uint64_t* survive_bits,
+                  int64_t* survivor_idx, int64_t* n_survivors);
+
+/* ---------------------------------------------------------------------- */
+/* Batched exact MPS simulation (Sections 3.1, 4, 4.3).                    */
+
+/* Simulate shots of a device CSR holding n_shots shots (as produced by
+   msc_sample_faults and copied to the device).  If shot_idx (device, n_sel
+   entries) is non-NULL only those shots are simulated and out[i] belongs to
+   shot shot_idx[i] (entries outside [0, n_shots) are not simulated: their
+   record has status 0); otherwise n_sel is ignored and out[i] belongs to
+   shot i.  out: device array of msc_shot_result, one per simulated shot.
+   Every shot runs the compiled op stream on its own ragged MPS, stops at
+   the first expected outcome with p < tau_rej (online screening), and
+   reports P_acc = prod_m p(e_m) and the seed qubit's infidelity against
+   the target.  Requires a calibrated circuit.                             */
+int msc_simulate(msc_ctx* ctx, const msc_circuit* c, const msc_sim_opts* opts,
+                 int64_t n_shots, const int64_t* shot_off, const int32_t* chan,
+                 const uint8_t* pauli, const int64_t* shot_idx, int64_t n_sel,
+                 msc_shot_result* out);
+
+/* ---------------------------------------------------------------------- */
+/* Two-site contraction on MFMA (Section 3.1), standalone.                 */
+
+/* theta_b = G * (A_b . B_b) for `batch` independent two-site updates with
+   chi_l = chi_m = chi_r = chi, FP32 split complex on MFMA with FP32
+   accumulation.  Layouts (device, float): A and B are [batch][2 (re,im)]
+   [chi*2][chi] and [batch][2][chi][2*chi] (row-major, rows (a,i) resp. c,
+   columns c resp. (j,b)); gate (device, 32 floats) is the 4x4 complex gate
+   in row-major (re,im) pairs over |i j>; theta is [batch][2][2*chi][2*chi]
+   with rows (a,i) and columns (j,b).  chi must be a multiple of 64 in
+   [64, 1024].                                                             */
+int msc_twosite_contract(msc_ctx* ctx, int32_t chi, int32_t batch,
+                         const float* A, const float* B, const float* gate,
+                         float* theta);
+
+/* ---------------------------------------------------------------------- */
+/* Re-weighting (Section 4.1, Eq. (reweight); Appendix "Systematics").     */
+
+/* Per-bin sums (host, n_bins each): bin_n[w] shots, bin_acc[w] = sum of
+   P_acc, bin_fail[w] = sum of P_acc * fail.  For each p in p_grid (host,
+   n_p) writes out[k] (host): p_acc, p_acc * p_le, p_le and the truncation
+   bound B = sum_{w >= n_bins} Bin_w(p).  Bins with bin_n[w] == 0 are
+   skipped.                                                                */
+int msc_reweight(const double* bin_n, const double* bin_acc,
+                 const double* bin_fail, int32_t n_bins, int64_t M,
+                 const double* p_grid, int32_t n_p, msc_estimate* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSC_H */

@@ -1,0 +1,162 @@
+"""Batched exact-MPS simulation of noisy magic-state-cultivation shots on
+MI355X: Python binding of the C ABI in include/msc.h.
+
+The functions below have the names of the C entry points (without the
+``msc_`` prefix) and only marshal arguments; every step of the method runs
+in libmsc.so (host C++ and HIP kernels for gfx950).  Device arrays are torch
+tensors on the context's GPU.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from ._lib import (MSC_FP32, MSC_FP64, SHOT_CHI_CAP, SHOT_DONE, SHOT_DTYPE,  # noqa: F401
+                   SHOT_NOCONV, SHOT_REJECTED, CircuitInfo, Estimate, MscError, SimOpts,
+                   _check, _ptr, lib)
+
+__all__ = ["Ctx", "Circuit", "sample_faults", "prescreen", "simulate", "reweight",
+           "twosite_contract", "prescreen_tables", "version", "MscError",
+           "MSC_FP64", "MSC_FP32", "SHOT_DTYPE"]
+
+
+def version() -> str:
+    return lib().msc_version().decode()
+
+
+class Ctx:
+    """msc_ctx: one GPU, one stream, device scratch."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        _check(lib().msc_ctx_create(device, C.byref(h)))
+        self.h = h
+        self.device = device
+
+    def close(self) -> None:
+        if self.h:
+            lib().msc_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_kernel_ms(self, which: str) -> float:
+        return lib().msc_ctx_last_kernel_ms(self.h, which.encode())
+
+
+class Circuit:
+    """msc_circuit: parsed and compiled circuit."""
+
+    def __init__(self, text: str, order=None):
+        h = C.c_void_p()
+        b = text.encode()
+        o = None
+        if order is not None:
+            o = np.ascontiguousarray(order, dtype=np.int32)
+        _check(lib().msc_circuit_load(b, len(b), _ptr(o), C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().msc_circuit_free(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        i = CircuitInfo()
+        _check(lib().msc_circuit_get_info(self.h, C.byref(i)))
+        return {k: getattr(i, k) for k, _ in CircuitInfo._fields_}
+
+    def expected(self) -> np.ndarray:
+        out = np.zeros(self.info()["n_meas"], dtype=np.uint8)
+        _check(lib().msc_circuit_expected(self.h, _ptr(out)))
+        return out
+
+    def calibrate(self, ctx: Ctx) -> None:
+        _check(lib().msc_circuit_calibrate(ctx.h, self.h))
+
+
+def sample_faults(circ: Circuit, seed: int, first_shot: int, n_shots: int,
+                  weights=None, p: float = 0.0):
+    """Host CSR (shot_off int64, chan int32, pauli uint8) of the shots."""
+    off = np.zeros(n_shots + 1, dtype=np.int64)
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.int32)
+    cap = max(16, 4 * n_shots)
+    while True:
+        chan = np.zeros(cap, dtype=np.int32)
+        pa = np.zeros(cap, dtype=np.uint8)
+        nnz = C.c_int64()
+        rc = lib().msc_sample_faults(circ.h, seed, first_shot, n_shots, _ptr(w), p, _ptr(off),
+                                     _ptr(chan), _ptr(pa), cap, C.byref(nnz))
+        if rc == -4:   # capacity: retry with the size the library asked for
+            cap = nnz.value
+            continue
+        _check(rc)
+        return off, chan[:nnz.value].copy(), pa[:nnz.value].copy()
+
+
+def prescreen_tables(circ: Circuit):
+    """(sig uint64[4*M, words], decided int32[n_decided])."""
+    inf = circ.info()
+    sig = np.zeros((4 * inf["n_channels"], inf["words"]), dtype=np.uint64)
+    dec = np.zeros(max(1, inf["n_decided"]), dtype=np.int32)
+    _check(lib().msc_prescreen_tables(circ.h, _ptr(sig), _ptr(dec)))
+    return sig, dec[:inf["n_decided"]]
+
+
+def prescreen(ctx: Ctx, circ: Circuit, off, chan, pauli, with_index: bool = True):
+    """Device screen: returns (survive_bits uint64 tensor, survivor index
+    int64 tensor or None, count)."""
+    import torch
+    n = off.numel() - 1
+    dev = off.device
+    bits = torch.zeros((n + 63) // 64, dtype=torch.int64, device=dev)
+    idx = torch.empty(max(n, 1), dtype=torch.int64, device=dev) if with_index else None
+    cnt = C.c_int64()
+    _check(lib().msc_prescreen(ctx.h, circ.h, n, _ptr(off), _ptr(chan), _ptr(pauli), _ptr(bits),
+                               _ptr(idx), C.byref(cnt)))
+    return bits, (idx[:cnt.value] if idx is not None else None), cnt.value
+
+
+def simulate(ctx: Ctx, circ: Circuit, off, chan, pauli, shot_idx=None, precision=MSC_FP64,
+             chi_max: int = 256, tau_trunc: float = 0.0, tau_rej: float = 1e-6,
+             tau_fail: float = 1e-4, n_slots: int = 0, out=None):
+    """Simulate shots (device CSR); returns a uint8 device tensor holding
+    msc_shot_result records (view them with ``results_numpy``)."""
+    import torch
+    n_shots = off.numel() - 1
+    n = shot_idx.numel() if shot_idx is not None else n_shots
+    if out is None:
+        out = torch.empty(max(n, 1) * SHOT_DTYPE.itemsize, dtype=torch.uint8, device=off.device)
+    o = SimOpts(precision, chi_max, tau_trunc, tau_rej, tau_fail, n_slots, 0)
+    _check(lib().msc_simulate(ctx.h, circ.h, C.byref(o), n_shots, _ptr(off), _ptr(chan),
+                              _ptr(pauli), _ptr(shot_idx), n, _ptr(out)))
+    return out[: n * SHOT_DTYPE.itemsize]
+
+
+def results_numpy(out) -> np.ndarray:
+    return np.frombuffer(out.cpu().numpy().tobytes(), dtype=SHOT_DTYPE)
+
+
+def twosite_contract(ctx: Ctx, chi: int, batch: int, A, B, gate, theta) -> None:
+    _check(lib().msc_twosite_contract(ctx.h, chi, batch, _ptr(A), _ptr(B), _ptr(gate),
+                                      _ptr(theta)))
+
+
+def reweight(bin_n, bin_acc, bin_fail, M: int, p_grid) -> list:
+    n = np.ascontiguousarray(bin_n, dtype=np.float64)
+    a = np.ascontiguousarray(bin_acc, dtype=np.float64)
+    e = np.ascontiguousarray(bin_fail, dtype=np.float64)
+    pg = np.ascontiguousarray(p_grid, dtype=np.float64)
+    out = (Estimate * len(pg))()
+    _check(lib().msc_reweight(_ptr(n), _ptr(a), _ptr(e), len(n), M, _ptr(pg), len(pg),
+                              C.cast(out, C.c_void_p)))
+    return [dict(p_acc=o.p_acc, p_acc_le=o.p_acc_le, p_le=o.p_le, trunc_bound=o.trunc_bound)
+            for o in out]

@@ -1,0 +1,129 @@
+"""ctypes binding of libmsc.so (the C ABI declared in include/msc.h).
+
+Argument marshalling only: every step of the simulation runs inside the
+library.  Device arrays are torch tensors on the context's GPU; host arrays
+are numpy arrays.  The library must have been built in-tree
+(``python -m paper_2609_19116_amd.build``); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from pathlib import Path
+
+import numpy as np
+
+_PKG = Path(__file__).resolve().parent
+LIB_PATH = _PKG / "libmsc.so"
+
+MSC_OK = 0
+MSC_E_PARSE = -1
+MSC_E_INVALID = -2
+MSC_E_NONDETERMINISTIC = -3
+MSC_E_CAPACITY = -4
+MSC_E_DEVICE = -5
+MSC_E_OOM = -6
+MSC_E_STATE = -7
+
+MSC_FP64 = 0
+MSC_FP32 = 1
+
+SHOT_DONE = 1
+SHOT_REJECTED = 2
+SHOT_CHI_CAP = 4
+SHOT_NOCONV = 8
+
+
+class CircuitInfo(C.Structure):
+    _fields_ = [("n_qubits", C.c_int32), ("n_meas", C.c_int32), ("n_channels", C.c_int32),
+                ("n_decided", C.c_int32), ("seed_qubit", C.c_int32), ("target", C.c_int32),
+                ("words", C.c_int32), ("calibrated", C.c_int32), ("n_ops", C.c_int64),
+                ("n_twosite", C.c_int64), ("n_swaps", C.c_int64)]
+
+
+class SimOpts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("chi_max", C.c_int32), ("tau_trunc", C.c_double),
+                ("tau_rej", C.c_double), ("tau_fail", C.c_double), ("n_slots", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class ShotResult(C.Structure):
+    _fields_ = [("p_acc", C.c_double), ("infid", C.c_double), ("disc_weight", C.c_double),
+                ("chi_peak", C.c_int32), ("status", C.c_int32), ("rejected_at", C.c_int32),
+                ("fail", C.c_int32), ("n2q", C.c_int64), ("flops", C.c_double),
+                ("reserved", C.c_int64)]
+
+
+SHOT_DTYPE = np.dtype([("p_acc", "<f8"), ("infid", "<f8"), ("disc_weight", "<f8"),
+                       ("chi_peak", "<i4"), ("status", "<i4"), ("rejected_at", "<i4"),
+                       ("fail", "<i4"), ("n2q", "<i8"), ("flops", "<f8"),
+                       ("reserved", "<i8")])
+assert SHOT_DTYPE.itemsize == C.sizeof(ShotResult) == 64
+
+
+class Estimate(C.Structure):
+    _fields_ = [("p_acc", C.c_double), ("p_acc_le", C.c_double), ("p_le", C.c_double),
+                ("trunc_bound", C.c_double)]
+
+
+# every exported symbol of include/msc.h with its signature
+_P = C.c_void_p
+_SIGS = {
+    "msc_last_error": (C.c_char_p, []),
+    "msc_version": (C.c_char_p, []),
+    "msc_ctx_create": (C.c_int, [C.c_int, C.POINTER(_P)]),
+    "msc_ctx_destroy": (None, [_P]),
+    "msc_ctx_last_kernel_ms": (C.c_double, [_P, C.c_char_p]),
+    "msc_circuit_load": (C.c_int, [C.c_char_p, C.c_size_t, _P, C.POINTER(_P)]),
+    "msc_circuit_get_info": (C.c_int, [_P, C.POINTER(CircuitInfo)]),
+    "msc_circuit_expected": (C.c_int, [_P, _P]),
+    "msc_circuit_calibrate": (C.c_int, [_P, _P]),
+    "msc_circuit_free": (None, [_P]),
+    "msc_sample_faults": (C.c_int, [_P, C.c_uint64, C.c_uint64, C.c_int64, _P, C.c_double,
+                                    _P, _P, _P, C.c_int64, C.POINTER(C.c_int64)]),
+    "msc_prescreen_tables": (C.c_int, [_P, _P, _P]),
+    "msc_prescreen": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P, _P, _P, C.POINTER(C.c_int64)]),
+    "msc_simulate": (C.c_int, [_P, _P, C.POINTER(SimOpts), C.c_int64, _P, _P, _P, _P,
+                               C.c_int64, _P]),
+    "msc_twosite_contract": (C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, _P, _P]),
+    "msc_reweight": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, _P, C.c_int32, _P]),
+}
+
+_lib = None
+
+
+class MscError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"msc error {code}: {msg}")
+        self.code = code
+
+
+def lib() -> C.CDLL:
+    """Load libmsc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2609_19116_amd.build`")
+        L = C.CDLL(str(LIB_PATH))
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> None:
+    if rc != MSC_OK:
+        raise MscError(rc, lib().msc_last_error().decode())
+
+
+def _ptr(a) -> int:
+    """Raw pointer of a numpy array or torch tensor (None -> NULL)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        assert a.flags["C_CONTIGUOUS"]
+        return a.ctypes.data
+    assert a.is_contiguous()
+    return a.data_ptr()

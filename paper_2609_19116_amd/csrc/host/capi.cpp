@@ -1,0 +1,421 @@
+// C ABI: context, circuit lifetime, device dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../kernels/kernels.h"
+#include "../msc_internal.h"
+
+namespace msc {
+
+static thread_local std::string g_err = "no error";
+
+int set_error(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+}  // namespace msc
+
+using namespace msc;
+
+#define MSC_HIP(call)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return set_error(MSC_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct msc_ctx {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    int n_cu = 0;
+    std::map<std::string, DevBuf> bufs;       // grow-only scratch
+    std::map<std::string, double> last_ms;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+static int ctx_buf(msc_ctx* ctx, const std::string& name, size_t bytes, void** out) {
+    DevBuf& b = ctx->bufs[name];
+    if (b.bytes < bytes) {
+        if (b.p) (void)hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+        hipError_t e = hipMalloc(&b.p, std::max<size_t>(bytes, 256));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(MSC_E_OOM, "hipMalloc(" + std::to_string(bytes) + ") for " + name +
+                                            ": " + hipGetErrorString(e));
+        }
+        b.bytes = std::max<size_t>(bytes, 256);
+    }
+    *out = b.p;
+    return MSC_OK;
+}
+
+extern "C" const char* msc_last_error(void) { return g_err.c_str(); }
+
+extern "C" const char* msc_version(void) { return "msc-mps 0.1 (gfx950)"; }
+
+extern "C" int msc_ctx_create(int device, msc_ctx** out) {
+    if (!out) return set_error(MSC_E_INVALID, "null out");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return set_error(MSC_E_DEVICE, "no HIP device available");
+    }
+    if (device < 0 || device >= n) return set_error(MSC_E_INVALID, "device index out of range");
+    std::unique_ptr<msc_ctx> ctx(new msc_ctx());
+    ctx->device = device;
+    MSC_HIP(hipSetDevice(device));
+    MSC_HIP(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+    MSC_HIP(hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, device));
+    MSC_HIP(hipEventCreate(&ctx->ev0));
+    MSC_HIP(hipEventCreate(&ctx->ev1));
+    *out = ctx.release();
+    return MSC_OK;
+}
+
+extern "C" void msc_ctx_destroy(msc_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (auto& kv : ctx->bufs)
+        if (kv.second.p) (void)hipFree(kv.second.p);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+extern "C" double msc_ctx_last_kernel_ms(msc_ctx* ctx, const char* which) {
+    if (!ctx || !which) return -1.0;
+    auto it = ctx->last_ms.find(which);
+    return it == ctx->last_ms.end() ? -1.0 : it->second;
+}
+
+// ---------------------------------------------------------------------------
+// circuits
+
+extern "C" int msc_circuit_load(const char* text, size_t len, const int32_t* order,
+                                msc_circuit** out) {
+    if (!text || !out) return set_error(MSC_E_INVALID, "null argument");
+    *out = nullptr;
+    std::unique_ptr<msc_circuit> c(new msc_circuit());
+    int rc = parse_circuit(text, len, c.get());
+    if (rc) return rc;
+    if (c->n > kMaxSites) return set_error(MSC_E_INVALID, "more than 128 qubits");
+    if (order) c->order.assign(order, order + c->n);
+    rc = compile_circuit(c.get());
+    if (rc) return rc;
+    rc = prescreen_compile(c.get());
+    if (rc) return rc;
+    *out = c.release();
+    return MSC_OK;
+}
+
+extern "C" int msc_circuit_get_info(const msc_circuit* c, msc_circuit_info* o) {
+    if (!c || !o) return set_error(MSC_E_INVALID, "null argument");
+    o->n_qubits = c->n;
+    o->n_meas = c->n_meas;
+    o->n_channels = c->n_channels;
+    o->n_decided = static_cast<int32_t>(c->decided.size());
+    o->seed_qubit = c->seed;
+    o->target = c->target;
+    o->words = c->words;
+    o->calibrated = c->calibrated ? 1 : 0;
+    o->n_ops = static_cast<int64_t>(c->ops.size());
+    o->n_twosite = c->n_twosite;
+    o->n_swaps = c->n_swaps;
+    return MSC_OK;
+}
+
+extern "C" int msc_circuit_expected(const msc_circuit* c, uint8_t* out) {
+    if (!c || !out) return set_error(MSC_E_INVALID, "null argument");
+    std::copy(c->expected.begin(), c->expected.end(), out);
+    return MSC_OK;
+}
+
+static void free_device(msc_circuit* c) {
+    if (c->dev < 0) return;
+    (void)hipSetDevice(c->dev);
+    for (void** p : {&c->d_ops, &c->d_g1, &c->d_g4, &c->d_sig, &c->d_expected}) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+    c->dev = -1;
+}
+
+extern "C" void msc_circuit_free(msc_circuit* c) {
+    if (!c) return;
+    free_device(c);
+    delete c;
+}
+
+static int upload(msc_ctx* ctx, msc_circuit* c) {
+    if (c->dev == ctx->device && c->d_ops) return MSC_OK;
+    free_device(c);
+    MSC_HIP(hipSetDevice(ctx->device));
+    std::vector<double> g1(G1_COUNT * 8), g4(G4_COUNT * 32);
+    for (int g = 0; g < G1_COUNT; ++g) gate1_matrix(g, &g1[g * 8]);
+    for (int g = 0; g < G4_COUNT; ++g) gate4_matrix(g, &g4[g * 32]);
+    auto put = [&](void** dst, const void* src, size_t bytes) -> int {
+        MSC_HIP(hipMalloc(dst, std::max<size_t>(bytes, 64)));
+        if (bytes) MSC_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+        return MSC_OK;
+    };
+    c->dev = ctx->device;
+    int rc;
+    if ((rc = put(&c->d_ops, c->ops.data(), c->ops.size() * sizeof(DevOp)))) return rc;
+    if ((rc = put(&c->d_g1, g1.data(), g1.size() * sizeof(double)))) return rc;
+    if ((rc = put(&c->d_g4, g4.data(), g4.size() * sizeof(double)))) return rc;
+    if ((rc = put(&c->d_sig, c->sig.data(), c->sig.size() * sizeof(uint64_t)))) return rc;
+    if ((rc = put(&c->d_expected, c->expected.data(), c->expected.size()))) return rc;
+    return MSC_OK;
+}
+
+extern "C" int msc_prescreen_tables(const msc_circuit* c, uint64_t* sig, int32_t* decided) {
+    if (!c) return set_error(MSC_E_INVALID, "null circuit");
+    if (sig) std::copy(c->sig.begin(), c->sig.end(), sig);
+    if (decided) std::copy(c->decided.begin(), c->decided.end(), decided);
+    return MSC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// simulation
+
+namespace {
+
+struct Layout {
+    std::vector<int32_t> cap;
+    std::vector<int64_t> off, half;
+    int64_t slot_elems = 0;     // elements of T per slot
+    int64_t scratch = 0;        // doubles per slot
+};
+
+Layout make_layout(int n, int chi_max) {
+    Layout L;
+    L.cap.resize(n + 1);
+    for (int k = 0; k <= n; ++k) {
+        int e = std::min(k, n - k);
+        int64_t c = e >= 30 ? (1ll << 30) : (1ll << e);
+        L.cap[k] = static_cast<int32_t>(std::min<int64_t>(c, chi_max));
+    }
+    L.off.resize(n);
+    L.half.resize(n);
+    int64_t pos = 0;
+    for (int k = 0; k < n; ++k) {
+        int64_t elems = static_cast<int64_t>(L.cap[k]) * 2 * L.cap[k + 1];
+        elems = (elems + 31) / 32 * 32;   // 128-byte aligned planes for FP32
+        L.off[k] = pos;
+        L.half[k] = elems;
+        pos += 2 * elems;
+    }
+    L.slot_elems = (pos + 63) / 64 * 64;
+    int64_t s = 2ll * chi_max;
+    L.scratch = 4 * s * s + 64;
+    return L;
+}
+
+}  // namespace
+
+static int run_shots(msc_ctx* ctx, const msc_circuit* c, int precision, int chi_max, double tau,
+                     double tau_rej, double tau_fail, int n_slots, int64_t n,
+                     int64_t n_csr, const int64_t* off, const int32_t* chan, const uint8_t* pauli,
+                     const int64_t* shot_idx, msc_shot_result* out, int calibrate,
+                     double* cal_p, uint8_t* cal_e, const char* timer) {
+    Layout L = make_layout(c->n, chi_max);
+    if (n_slots <= 0) {
+        const bool small = chi_max <= 16;
+        n_slots = ctx->n_cu * (small ? 6 : 2);
+    }
+    n_slots = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(n_slots, n)));
+    const size_t tsize = precision == MSC_FP64 ? sizeof(double) : sizeof(float);
+    void *arena, *scratch, *dcap, *doff, *dhalf;
+    int rc;
+    if ((rc = ctx_buf(ctx, "arena", static_cast<size_t>(n_slots) * L.slot_elems * tsize, &arena))) return rc;
+    if ((rc = ctx_buf(ctx, "scratch", static_cast<size_t>(n_slots) * L.scratch * sizeof(double), &scratch))) return rc;
+    if ((rc = ctx_buf(ctx, "cap", L.cap.size() * sizeof(int32_t), &dcap))) return rc;
+    if ((rc = ctx_buf(ctx, "off", L.off.size() * sizeof(int64_t), &doff))) return rc;
+    if ((rc = ctx_buf(ctx, "half", L.half.size() * sizeof(int64_t), &dhalf))) return rc;
+    MSC_HIP(hipMemcpyAsync(dcap, L.cap.data(), L.cap.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+    MSC_HIP(hipMemcpyAsync(doff, L.off.data(), L.off.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+    MSC_HIP(hipMemcpyAsync(dhalf, L.half.data(), L.half.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+    MpsArgs a{};
+    a.ops = static_cast<const DevOp*>(c->d_ops);
+    a.n_ops = static_cast<int32_t>(c->ops.size());
+    a.n_sites = c->n;
+    a.g1 = static_cast<const double*>(c->d_g1);
+    a.g4 = static_cast<const double*>(c->d_g4);
+    a.shot_off = off;
+    a.chan = chan;
+    a.pauli = pauli;
+    a.shot_idx = shot_idx;
+    a.n_shots = n;
+    a.n_csr = n_csr;
+    a.expected = static_cast<const uint8_t*>(c->d_expected);
+    a.out = out;
+    a.arena = arena;
+    a.slot_stride = L.slot_elems;
+    a.site_off = static_cast<const int64_t*>(doff);
+    a.site_half = static_cast<const int64_t*>(dhalf);
+    a.cap = static_cast<const int32_t*>(dcap);
+    a.scratch = static_cast<double*>(scratch);
+    a.scratch_stride = L.scratch;
+    a.chi_max = chi_max;
+    a.tau = tau;
+    a.tau_rej = tau_rej;
+    a.tau_fail = tau_fail;
+    const double r = 1.0 / std::sqrt(2.0);
+    a.t0r = r;
+    a.t0i = 0.0;
+    if (c->target == 'T') {
+        a.t1r = 0.5;
+        a.t1i = 0.5;
+    } else {
+        a.t1r = 0.0;
+        a.t1i = r;
+    }
+    a.calibrate = calibrate;
+    a.cal_p = cal_p;
+    a.cal_e = cal_e;
+    const bool small = chi_max <= 16;
+    MSC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
+    MSC_HIP(launch_mps(precision, small, a, n_slots, ctx->stream));
+    MSC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
+    MSC_HIP(hipStreamSynchronize(ctx->stream));
+    float ms = 0.f;
+    MSC_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    if (timer) ctx->last_ms[timer] = ms;
+    return MSC_OK;
+}
+
+extern "C" int msc_circuit_calibrate(msc_ctx* ctx, msc_circuit* c) {
+    if (!ctx || !c) return set_error(MSC_E_INVALID, "null argument");
+    MSC_HIP(hipSetDevice(ctx->device));
+    int rc = upload(ctx, c);
+    if (rc) return rc;
+    void *doff, *dchan, *dpa, *dout, *dp, *de;
+    const int nm = std::max(1, c->n_meas);
+    if ((rc = ctx_buf(ctx, "cal_off", 2 * sizeof(int64_t), &doff))) return rc;
+    if ((rc = ctx_buf(ctx, "cal_chan", 64, &dchan))) return rc;
+    if ((rc = ctx_buf(ctx, "cal_pa", 64, &dpa))) return rc;
+    if ((rc = ctx_buf(ctx, "cal_out", sizeof(msc_shot_result), &dout))) return rc;
+    if ((rc = ctx_buf(ctx, "cal_p", nm * sizeof(double), &dp))) return rc;
+    if ((rc = ctx_buf(ctx, "cal_e", nm, &de))) return rc;
+    int64_t zero[2] = {0, 0};
+    MSC_HIP(hipMemcpy(doff, zero, sizeof(zero), hipMemcpyHostToDevice));
+    int chi_max = kMaxChiKernel;
+    rc = run_shots(ctx, c, MSC_FP64, chi_max, 1e-12, 0.0, 1e-4, 1, 1, 1,
+                   static_cast<int64_t*>(doff), static_cast<int32_t*>(dchan),
+                   static_cast<uint8_t*>(dpa), nullptr, static_cast<msc_shot_result*>(dout), 1,
+                   static_cast<double*>(dp), static_cast<uint8_t*>(de), "calibrate");
+    if (rc) return rc;
+    std::vector<double> p(nm);
+    std::vector<uint8_t> e(nm);
+    msc_shot_result res;
+    MSC_HIP(hipMemcpy(p.data(), dp, nm * sizeof(double), hipMemcpyDeviceToHost));
+    MSC_HIP(hipMemcpy(e.data(), de, nm, hipMemcpyDeviceToHost));
+    MSC_HIP(hipMemcpy(&res, dout, sizeof(res), hipMemcpyDeviceToHost));
+    for (int m = 0; m < c->n_meas; ++m) {
+        if (!(std::fabs(p[m] - 1.0) <= 1e-10))
+            return set_error(MSC_E_NONDETERMINISTIC, "measurement " + std::to_string(m) +
+                                                         " has p(e) = " + std::to_string(p[m]));
+    }
+    if (!(res.infid <= 1e-10))
+        return set_error(MSC_E_NONDETERMINISTIC,
+                         "noiseless infidelity " + std::to_string(res.infid));
+    if (res.status & MSC_SHOT_CHI_CAP)
+        return set_error(MSC_E_NONDETERMINISTIC, "noiseless run exceeded the bond cap");
+    for (int m = 0; m < c->n_meas; ++m) c->expected[m] = e[m];
+    MSC_HIP(hipMemcpy(c->d_expected, c->expected.data(), c->n_meas, hipMemcpyHostToDevice));
+    c->calibrated = true;
+    return MSC_OK;
+}
+
+extern "C" int msc_simulate(msc_ctx* ctx, const msc_circuit* c, const msc_sim_opts* opts,
+                            int64_t n_shots, const int64_t* shot_off, const int32_t* chan,
+                            const uint8_t* pauli, const int64_t* shot_idx, int64_t n_sel,
+                            msc_shot_result* out) {
+    if (!ctx || !c || !opts || n_shots < 0 || !shot_off || (shot_idx && n_sel < 0))
+        return set_error(MSC_E_INVALID, "null argument");
+    const int64_t n = shot_idx ? n_sel : n_shots;
+    if (n > 0 && !out) return set_error(MSC_E_INVALID, "null out");
+    if (!c->calibrated) return set_error(MSC_E_STATE, "circuit not calibrated");
+    if (opts->precision != MSC_FP64 && opts->precision != MSC_FP32)
+        return set_error(MSC_E_INVALID, "unknown precision");
+    if (opts->chi_max < 1 || opts->chi_max > kMaxChiKernel)
+        return set_error(MSC_E_INVALID, "chi_max must be in [1, 256]");
+    if (n == 0) return MSC_OK;
+    MSC_HIP(hipSetDevice(ctx->device));
+    // the library only uploads into circuits it owns; const is logical here
+    int rc = upload(ctx, const_cast<msc_circuit*>(c));
+    if (rc) return rc;
+    double tau = opts->tau_trunc > 0 ? opts->tau_trunc : (opts->precision == MSC_FP64 ? 1e-12 : 1e-5);
+    double tau_rej = opts->tau_rej > 0 ? opts->tau_rej : 1e-6;
+    double tau_fail = opts->tau_fail > 0 ? opts->tau_fail : 1e-4;
+    return run_shots(ctx, c, opts->precision, opts->chi_max, tau, tau_rej, tau_fail,
+                     opts->n_slots, n, n_shots, shot_off, chan, pauli, shot_idx, out, 0,
+                     nullptr, nullptr, "simulate");
+}
+
+extern "C" int msc_prescreen(msc_ctx* ctx, const msc_circuit* c, int64_t n_shots,
+                             const int64_t* shot_off, const int32_t* chan, const uint8_t* pauli,
+                             uint64_t* survive_bits, int64_t* survivor_idx,
+                             int64_t* n_survivors) {
+    if (!ctx || !c || n_shots < 0 || !shot_off || !survive_bits || !n_survivors)
+        return set_error(MSC_E_INVALID, "null argument");
+    if (c->words > 8) return set_error(MSC_E_INVALID, "more than 512 decided measurements");
+    *n_survivors = 0;
+    if (n_shots == 0) return MSC_OK;
+    MSC_HIP(hipSetDevice(ctx->device));
+    int rc = upload(ctx, const_cast<msc_circuit*>(c));
+    if (rc) return rc;
+    const int64_t nt = prescreen_tmp_words(n_shots);
+    void* tmp;
+    if ((rc = ctx_buf(ctx, "screen_tmp", nt * sizeof(int64_t), &tmp))) return rc;
+    MSC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
+    MSC_HIP(launch_prescreen(c->words, c->n_channels, n_shots, shot_off, chan, pauli,
+                             static_cast<const uint64_t*>(c->d_sig), survive_bits, survivor_idx,
+                             static_cast<int64_t*>(tmp), nt, ctx->stream));
+    MSC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
+    int64_t cnt = 0;
+    const int64_t nb = (n_shots + 255) / 256;
+    MSC_HIP(hipMemcpyAsync(&cnt, static_cast<int64_t*>(tmp) + nb, sizeof(int64_t),
+                           hipMemcpyDeviceToHost, ctx->stream));
+    MSC_HIP(hipStreamSynchronize(ctx->stream));
+    float ms = 0.f;
+    MSC_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    ctx->last_ms["prescreen"] = ms;
+    *n_survivors = cnt;
+    return MSC_OK;
+}
+
+extern "C" int msc_twosite_contract(msc_ctx* ctx, int32_t chi, int32_t batch, const float* A,
+                                    const float* B, const float* gate, float* theta) {
+    if (!ctx || !A || !B || !gate || !theta) return set_error(MSC_E_INVALID, "null argument");
+    if (chi < 64 || chi > 1024 || chi % 64 != 0 || batch < 1 || batch > 65535)
+        return set_error(MSC_E_INVALID, "chi must be a multiple of 64 in [64, 1024], batch in [1, 65535]");
+    MSC_HIP(hipSetDevice(ctx->device));
+    MSC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
+    MSC_HIP(launch_twosite(chi, batch, A, B, gate, theta, ctx->stream));
+    MSC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
+    MSC_HIP(hipStreamSynchronize(ctx->stream));
+    float ms = 0.f;
+    MSC_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    ctx->last_ms["twosite"] = ms;
+    return MSC_OK;
+}

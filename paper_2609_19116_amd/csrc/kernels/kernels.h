@@ -1,0 +1,58 @@
+// Launch interfaces of the HIP kernels (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../msc_internal.h"
+
+namespace msc {
+
+constexpr int kMaxSites = 128;     // MPS sites per circuit
+constexpr int kMaxChiKernel = 256; // bond cap handled by the shot kernel
+
+struct MpsArgs {
+    const DevOp* ops;
+    int32_t n_ops;
+    int32_t n_sites;
+    const double* g1;          // 2x2 complex gates, 8 doubles each
+    const double* g4;          // 4x4 complex gates, 32 doubles each
+    const int64_t* shot_off;   // fault CSR
+    const int32_t* chan;
+    const uint8_t* pauli;
+    const int64_t* shot_idx;   // optional subset
+    int64_t n_shots;           // shots to simulate (entries of shot_idx)
+    int64_t n_csr;             // shots held by the CSR
+    const uint8_t* expected;   // e_m per measurement
+    msc_shot_result* out;
+    void* arena;               // n_slots * slot_stride elements of T
+    int64_t slot_stride;
+    const int64_t* site_off;   // per-site offset (elements of T) of Re part
+    const int64_t* site_half;  // per-site offset of Im part from Re part
+    const int32_t* cap;        // bond capacities [n_sites + 1]
+    double* scratch;           // n_slots * scratch_stride doubles
+    int64_t scratch_stride;
+    int32_t chi_max;
+    double tau;                // keep sigma > tau * sigma_0
+    double tau_rej;
+    double tau_fail;
+    double t0r, t0i, t1r, t1i; // target state amplitudes
+    int32_t calibrate;         // 1: choose the likelier outcome and record it
+    double* cal_p;             // [n_meas] probability of the chosen outcome
+    uint8_t* cal_e;            // [n_meas] chosen outcome
+};
+
+// precision: MSC_FP64 or MSC_FP32; small: use the 32-wide LDS variant
+hipError_t launch_mps(int precision, bool small, const MpsArgs& a, int grid, hipStream_t s);
+
+hipError_t launch_prescreen(int words, int32_t n_channels, int64_t n, const int64_t* off, const int32_t* chan,
+                            const uint8_t* pauli, const uint64_t* sig, uint64_t* survive_bits,
+                            int64_t* survivor_idx, int64_t* block_tmp, int64_t n_blocks_tmp,
+                            hipStream_t s);
+int64_t prescreen_tmp_words(int64_t n);
+
+hipError_t launch_twosite(int chi, int batch, const float* A, const float* B, const float* gate,
+                          float* theta, hipStream_t s);
+
+}  // namespace msc

@@ -1,0 +1,533 @@
+// Persistent batched MPS shot kernel for gfx950.
+//
+// One workgroup (4 wavefronts) owns one MPS slot in HBM and runs whole shots
+// through the compiled op stream, taking shots blockIdx.x, blockIdx.x +
+// gridDim.x, ...  Each shot has its own ragged bond dimensions, kept in LDS,
+// and stops at the first measurement whose expected outcome has probability
+// below tau_rej (online screening, Section 4.3), so a rejected shot frees
+// its workgroup for the next one at once.
+//
+// Per op (Section 3.1 for the MPS, Section 4 for the shot semantics):
+//  * 1q gates and Pauli faults act on one site tensor (chi_l x 2 x chi_r);
+//  * a two-site update contracts A[k] A[k+1] (complex, in the tensor
+//    precision T), applies the 4x4 gate, and factorises the result exactly:
+//    one-sided Jacobi (Hestenes) SVD in FP64 on the columns (centre moves
+//    right) or rows (centre moves left) of theta, held in LDS when both
+//    sides are at most SMAX, else in the slot's HBM scratch; singular values
+//    sigma_i <= tau * sigma_0 are dropped (numerical zeros), the bond becomes
+//    the number kept, the isometric factor is the normalised orthogonal
+//    vectors and the centre factor is the projection of theta on them,
+//    renormalised in FP64 (Section 3.1, "exact regime" of Section 5.1);
+//  * a measurement, taken with the centre on the site, computes
+//    p_e = ||A[:, e, :]||^2 / ||A||^2 in FP64, rejects if p_e < tau_rej,
+//    otherwise projects, renormalises and multiplies P_acc by p_e;
+//  * the final op reads the seed qubit's reduced density matrix and the
+//    fidelity with the target (Appendix "Post-selection and logical error").
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace msc {
+namespace {
+
+constexpr int NT = 256;
+constexpr int NW = NT / 64;
+constexpr int MAXV = 2 * kMaxChiKernel;   // vectors in a two-site SVD
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* red) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[w * K + k] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < NW; ++j) s += red[j * K + k];
+        v[k] = s;
+    }
+}
+
+__device__ __forceinline__ double block_max(double v, double* red) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double m = red[0];
+#pragma unroll
+    for (int j = 1; j < NW; ++j) m = fmax(m, red[j]);
+    return m;
+}
+
+// Round-robin ("circle") pairing: slot 0 fixed, the others rotate each step.
+__device__ __forceinline__ int player(int slot, int t, int nv) {
+    return slot == 0 ? 0 : 1 + (slot - 1 + t) % (nv - 1);
+}
+
+// One-sided Jacobi on nv vectors of length len (planar FP64 at vre/vim,
+// vector v at v*len).  Returns the number of sweeps used (or -1 when the
+// sweep limit was reached).
+__device__ int hestenes(double* vre, double* vim, int nv, int len, double floor2,
+                        double tol, int* sflag) {
+    const int tid = threadIdx.x;
+    if (nv < 2) return 0;
+    const int npairs = nv / 2;
+    int tpp = NT / npairs;
+    if (tpp > 64) tpp = 64;
+    if (tpp < 1) tpp = 1;
+    // round down to a power of two
+    int t2 = 1;
+    while (t2 * 2 <= tpp) t2 *= 2;
+    tpp = t2;
+    const int groups = NT / tpp;
+    const int gl = tid % tpp;
+    const int gi = tid / tpp;
+    const int nsteps = nv - 1;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        int rotated = 0;
+        for (int t = 0; t < nsteps; ++t) {
+            for (int pb = 0; pb < npairs; pb += groups) {
+                const int pi = pb + gi;
+                const bool active = pi < npairs;
+                int p = 0, q = 0;
+                double a = 0.0, b = 0.0, gr = 0.0, gim = 0.0;
+                if (active) {
+                    p = player(pi, t, nv);
+                    q = player(nv - 1 - pi, t, nv);
+                    const double* xr = vre + (size_t)p * len;
+                    const double* xi = vim + (size_t)p * len;
+                    const double* yr = vre + (size_t)q * len;
+                    const double* yi = vim + (size_t)q * len;
+                    for (int e = gl; e < len; e += tpp) {
+                        double x0 = xr[e], x1 = xi[e], y0 = yr[e], y1 = yi[e];
+                        a += x0 * x0 + x1 * x1;
+                        b += y0 * y0 + y1 * y1;
+                        gr += x0 * y0 + x1 * y1;
+                        gim += x0 * y1 - x1 * y0;
+                    }
+                }
+                for (int o = tpp >> 1; o > 0; o >>= 1) {
+                    a += __shfl_xor(a, o);
+                    b += __shfl_xor(b, o);
+                    gr += __shfl_xor(gr, o);
+                    gim += __shfl_xor(gim, o);
+                }
+                if (active) {
+                    const double g = sqrt(gr * gr + gim * gim);
+                    if (a > floor2 && b > floor2 && g > tol * sqrt(a * b)) {
+                        rotated = 1;
+                        const double zeta = (b - a) / (2.0 * g);
+                        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) /
+                                          (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                        const double c = 1.0 / sqrt(1.0 + tt * tt);
+                        const double s = c * tt;
+                        // y~ = y * conj(gamma)/|gamma|
+                        const double pr = gr / g, pim = gim / g;
+                        double* xr = vre + (size_t)p * len;
+                        double* xi = vim + (size_t)p * len;
+                        double* yr = vre + (size_t)q * len;
+                        double* yi = vim + (size_t)q * len;
+                        for (int e = gl; e < len; e += tpp) {
+                            double x0 = xr[e], x1 = xi[e];
+                            double y0 = yr[e] * pr + yi[e] * pim;
+                            double y1 = yi[e] * pr - yr[e] * pim;
+                            xr[e] = c * x0 - s * y0;
+                            xi[e] = c * x1 - s * y1;
+                            yr[e] = s * x0 + c * y0;
+                            yi[e] = s * x1 + c * y1;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (!__syncthreads_or(rotated)) return sweep + 1;
+    }
+    (void)sflag;
+    return -1;
+}
+
+template <typename T>
+struct SiteView {
+    T* re;
+    T* im;
+};
+
+template <typename T, int SMAX>
+__global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
+    __shared__ int s_chi[kMaxSites + 1];
+    __shared__ int s_laste[kMaxSites];
+    __shared__ double s_vre[SMAX * SMAX];
+    __shared__ double s_vim[SMAX * SMAX];
+    __shared__ double s_nrm[MAXV];
+    __shared__ int s_sel[MAXV];
+    __shared__ double s_red[NW * 4];
+    __shared__ int s_misc[4];
+    __shared__ double s_gate[32];
+
+    const int tid = threadIdx.x;
+    const int N = P.n_sites;
+    T* slot_base = static_cast<T*>(P.arena) + (size_t)blockIdx.x * P.slot_stride;
+    double* scr = P.scratch + (size_t)blockIdx.x * P.scratch_stride;
+
+    auto site = [&](int k) {
+        SiteView<T> v;
+        v.re = slot_base + P.site_off[k];
+        v.im = v.re + P.site_half[k];
+        return v;
+    };
+
+    for (int64_t it = blockIdx.x; it < P.n_shots; it += gridDim.x) {
+        const int64_t shot = P.shot_idx ? P.shot_idx[it] : it;
+        if (shot < 0 || shot >= P.n_csr) {
+            if (tid == 0) {
+                msc_shot_result bad{};
+                bad.rejected_at = -1;
+                P.out[it] = bad;
+            }
+            continue;
+        }
+        // ---- initial product state |0...0>
+        for (int k = tid; k <= N; k += NT) s_chi[k] = 1;
+        for (int k = tid; k < N; k += NT) {
+            s_laste[k] = 0;
+            SiteView<T> v = site(k);
+            v.re[0] = T(1);
+            v.re[1] = T(0);
+            v.im[0] = T(0);
+            v.im[1] = T(0);
+        }
+        __syncthreads();
+        double p_acc = 1.0, disc = 0.0, infid = 0.0;
+        int chi_peak = 1, status = 0, rej_at = -1;
+        int64_t n2q = 0;
+        double flops = 0.0;
+        int64_t fcur = P.shot_off[shot];
+        const int64_t fend = P.shot_off[shot + 1];
+        bool alive = true;
+
+        for (int oi = 0; oi < P.n_ops && alive; ++oi) {
+            const DevOp op = P.ops[oi];
+            if (op.kind == OP_G1 || op.kind == OP_FAULT || op.kind == OP_RESET) {
+                // ---- local 2x2 on one site (two for a two-qubit fault)
+                int g0 = -1, g1 = -1;
+                if (op.kind == OP_G1) {
+                    g0 = op.aux;
+                } else if (op.kind == OP_RESET) {
+                    if (s_laste[op.a] == 1) g0 = G_X;
+                } else {
+                    int code = 0;
+                    if (fcur < fend && P.chan[fcur] == op.aux) {
+                        code = P.pauli[fcur];
+                        ++fcur;
+                    }
+                    const int x0 = code & 1, z0 = (code >> 1) & 1;
+                    const int x1 = (code >> 2) & 1, z1 = (code >> 3) & 1;
+                    if (x0 | z0) g0 = (x0 && z0) ? G_Y : (x0 ? G_X : G_Z);
+                    if ((x1 | z1) && op.b >= 0) g1 = (x1 && z1) ? G_Y : (x1 ? G_X : G_Z);
+                }
+                for (int h = 0; h < 2; ++h) {
+                    const int gid = h == 0 ? g0 : g1;
+                    if (gid < 0) continue;
+                    const int k = h == 0 ? op.a : op.b;
+                    const double* m = P.g1 + gid * 8;
+                    const double m0 = m[0], m1 = m[1], m2 = m[2], m3 = m[3];
+                    const double m4 = m[4], m5 = m[5], m6 = m[6], m7 = m[7];
+                    SiteView<T> v = site(k);
+                    const int cl = s_chi[k], cr = s_chi[k + 1];
+                    for (int idx = tid; idx < cl * cr; idx += NT) {
+                        const int a = idx / cr, b = idx - a * cr;
+                        const int i0 = (a * 2) * cr + b, i1 = i0 + cr;
+                        const double x0r = v.re[i0], x0i = v.im[i0], x1r = v.re[i1], x1i = v.im[i1];
+                        v.re[i0] = T(m0 * x0r - m1 * x0i + m2 * x1r - m3 * x1i);
+                        v.im[i0] = T(m0 * x0i + m1 * x0r + m2 * x1i + m3 * x1r);
+                        v.re[i1] = T(m4 * x0r - m5 * x0i + m6 * x1r - m7 * x1i);
+                        v.im[i1] = T(m4 * x0i + m5 * x0r + m6 * x1i + m7 * x1r);
+                    }
+                    __syncthreads();
+                }
+            } else if (op.kind == OP_MEAS) {
+                const int k = op.a;
+                SiteView<T> v = site(k);
+                const int cl = s_chi[k], cr = s_chi[k + 1];
+                double pp[2] = {0.0, 0.0};
+                for (int idx = tid; idx < cl * cr; idx += NT) {
+                    const int a = idx / cr, b = idx - a * cr;
+                    const int i0 = (a * 2) * cr + b, i1 = i0 + cr;
+                    const double x0r = v.re[i0], x0i = v.im[i0], x1r = v.re[i1], x1i = v.im[i1];
+                    pp[0] += x0r * x0r + x0i * x0i;
+                    pp[1] += x1r * x1r + x1i * x1i;
+                }
+                block_sum<2>(pp, s_red);
+                const double tot = pp[0] + pp[1];
+                int e;
+                if (P.calibrate) e = pp[1] > pp[0] ? 1 : 0;
+                else e = P.expected[op.aux];
+                const double raw = pp[e];
+                const double pe = tot > 0.0 ? raw / tot : 0.0;
+                if (P.calibrate && tid == 0) {
+                    P.cal_p[op.aux] = pe;
+                    P.cal_e[op.aux] = static_cast<uint8_t>(e);
+                }
+                if (!(pe >= P.tau_rej)) {
+                    alive = false;
+                    status |= MSC_SHOT_REJECTED;
+                    rej_at = op.aux;
+                    p_acc = 0.0;
+                    break;
+                }
+                p_acc *= pe;
+                const double sc = 1.0 / sqrt(raw);
+                for (int idx = tid; idx < cl * cr; idx += NT) {
+                    const int a = idx / cr, b = idx - a * cr;
+                    const int ie = (a * 2 + e) * cr + b, io = (a * 2 + 1 - e) * cr + b;
+                    v.re[ie] = T(static_cast<double>(v.re[ie]) * sc);
+                    v.im[ie] = T(static_cast<double>(v.im[ie]) * sc);
+                    v.re[io] = T(0);
+                    v.im[io] = T(0);
+                }
+                if (tid == 0) s_laste[k] = e;
+                __syncthreads();
+            } else if (op.kind == OP_FINAL) {
+                const int k = op.a;
+                SiteView<T> v = site(k);
+                const int cl = s_chi[k], cr = s_chi[k + 1];
+                double r[4] = {0.0, 0.0, 0.0, 0.0};   // r00, r11, Re r01, Im r01
+                for (int idx = tid; idx < cl * cr; idx += NT) {
+                    const int a = idx / cr, b = idx - a * cr;
+                    const int i0 = (a * 2) * cr + b, i1 = i0 + cr;
+                    const double x0r = v.re[i0], x0i = v.im[i0], x1r = v.re[i1], x1i = v.im[i1];
+                    r[0] += x0r * x0r + x0i * x0i;
+                    r[1] += x1r * x1r + x1i * x1i;
+                    // rho01 = x0 * conj(x1)
+                    r[2] += x0r * x1r + x0i * x1i;
+                    r[3] += x0i * x1r - x0r * x1i;
+                }
+                block_sum<4>(r, s_red);
+                const double tr = r[0] + r[1];
+                // f = |t0|^2 rho00 + |t1|^2 rho11 + 2 Re(conj(t0) t1 rho01)
+                const double ctr = P.t0r * P.t1r + P.t0i * P.t1i;   // conj(t0) t1
+                const double cti = P.t0r * P.t1i - P.t0i * P.t1r;
+                const double f = ((P.t0r * P.t0r + P.t0i * P.t0i) * r[0] +
+                                  (P.t1r * P.t1r + P.t1i * P.t1i) * r[1] +
+                                  2.0 * (ctr * r[2] - cti * r[3])) / tr;
+                infid = fmax(0.0, 1.0 - f);
+            } else if (op.kind == OP_G2) {
+                // ---- two-site update on sites k, k+1
+                const int k = op.a, dir = op.b;
+                const int cl = s_chi[k], cm = s_chi[k + 1], cr = s_chi[k + 2];
+                const int m = 2 * cl, n = 2 * cr;
+                SiteView<T> A = site(k), B = site(k + 1);
+                double* thr = scr;
+                double* thi = scr + (size_t)m * n;
+                const int nv = dir ? n : m, len = dir ? m : n;
+                const bool lds = nv <= SMAX && len <= SMAX;
+                double* vre = lds ? s_vre : scr + 2 * (size_t)m * n;
+                double* vim = lds ? s_vim : vre + (size_t)nv * len;
+                const bool ident = op.aux == G4_I;
+                if (!ident && tid < 32) s_gate[tid] = P.g4[op.aux * 32 + tid];
+                __syncthreads();
+                double nsum[1] = {0.0};
+                for (int idx = tid; idx < cl * cr; idx += NT) {
+                    const int a = idx / cr, b = idx - a * cr;
+                    T sr[4] = {T(0), T(0), T(0), T(0)}, si[4] = {T(0), T(0), T(0), T(0)};
+                    const T* a0r = A.re + (a * 2) * cm;
+                    const T* a0i = A.im + (a * 2) * cm;
+                    for (int c = 0; c < cm; ++c) {
+                        const T x0r = a0r[c], x0i = a0i[c], x1r = a0r[cm + c], x1i = a0i[cm + c];
+                        const int b0 = (c * 2) * cr + b, b1 = b0 + cr;
+                        const T y0r = B.re[b0], y0i = B.im[b0], y1r = B.re[b1], y1i = B.im[b1];
+                        // S[i'j'] += A[a,i',c] B[c,j',b]
+                        sr[0] += x0r * y0r - x0i * y0i; si[0] += x0r * y0i + x0i * y0r;
+                        sr[1] += x0r * y1r - x0i * y1i; si[1] += x0r * y1i + x0i * y1r;
+                        sr[2] += x1r * y0r - x1i * y0i; si[2] += x1r * y0i + x1i * y0r;
+                        sr[3] += x1r * y1r - x1i * y1i; si[3] += x1r * y1i + x1i * y1r;
+                    }
+                    double tr_[4], ti_[4];
+                    if (ident) {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) { tr_[j] = sr[j]; ti_[j] = si[j]; }
+                    } else {
+#pragma unroll
+                        for (int o = 0; o < 4; ++o) {
+                            double xr = 0.0, xi = 0.0;
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) {
+                                const double gr = s_gate[2 * (4 * o + j)], gi = s_gate[2 * (4 * o + j) + 1];
+                                xr += gr * static_cast<double>(sr[j]) - gi * static_cast<double>(si[j]);
+                                xi += gr * static_cast<double>(si[j]) + gi * static_cast<double>(sr[j]);
+                            }
+                            tr_[o] = xr;
+                            ti_[o] = xi;
+                        }
+                    }
+#pragma unroll
+                    for (int o = 0; o < 4; ++o) {
+                        const int i = o >> 1, j = o & 1;
+                        const int row = a * 2 + i, col = j * cr + b;
+                        thr[(size_t)row * n + col] = tr_[o];
+                        thi[(size_t)row * n + col] = ti_[o];
+                        const size_t vi = dir ? (size_t)col * len + row : (size_t)row * len + col;
+                        vre[vi] = tr_[o];
+                        vim[vi] = ti_[o];
+                        nsum[0] += tr_[o] * tr_[o] + ti_[o] * ti_[o];
+                    }
+                }
+                block_sum<1>(nsum, s_red);
+                const double total = nsum[0];
+                const double tau2 = P.tau * P.tau;
+                const double floor2 = 1e-4 * tau2 * total;
+                const double tol = static_cast<double>(len) * DBL_EPSILON;
+                const int sweeps = hestenes(vre, vim, nv, len, floor2, tol, s_misc);
+                if (sweeps < 0) status |= MSC_SHOT_NOCONV;
+                // squared norms of the orthogonalised vectors
+                for (int v = tid; v < nv; v += NT) {
+                    double s = 0.0;
+                    const double* xr = vre + (size_t)v * len;
+                    const double* xi = vim + (size_t)v * len;
+                    for (int e = 0; e < len; ++e) s += xr[e] * xr[e] + xi[e] * xi[e];
+                    s_nrm[v] = s;
+                }
+                __syncthreads();
+                double mx = 0.0;
+                for (int v = tid; v < nv; v += NT) mx = fmax(mx, s_nrm[v]);
+                mx = block_max(mx, s_red);
+                const int capb = min(P.chi_max, P.cap[k + 1]);
+                double kd[3] = {0.0, 0.0, 0.0};   // kept count, kept norm, dropped norm
+                for (int v = tid; v < nv; v += NT) {
+                    const double x = s_nrm[v];
+                    int rank = 0;
+                    for (int u2 = 0; u2 < nv; ++u2) {
+                        const double y = s_nrm[u2];
+                        rank += (y > x) || (y == x && u2 < v);
+                    }
+                    const bool keep = (x > tau2 * mx || rank == 0) && rank < capb;
+                    if (keep) {
+                        s_sel[rank] = v;
+                        kd[0] += 1.0;
+                        kd[1] += x;
+                    } else {
+                        kd[2] += x;
+                    }
+                }
+                block_sum<3>(kd, s_red);
+                const int r = static_cast<int>(kd[0] + 0.5);
+                const double kept = kd[1];
+                disc += kd[2];
+                if (kd[2] > 1e-12 * total && r == capb) status |= MSC_SHOT_CHI_CAP;
+                const double renorm = 1.0 / sqrt(kept);
+                // isometric factor: normalised vectors; centre factor: projection
+                if (dir) {
+                    // A[k] (cl,2,r): U[row][c] = w_sel[c][row] / |w|
+                    for (int idx = tid; idx < m * r; idx += NT) {
+                        const int row = idx / r, c = idx - row * r;
+                        const int v = s_sel[c];
+                        const double is = 1.0 / sqrt(s_nrm[v]);
+                        A.re[idx] = T(vre[(size_t)v * len + row] * is);
+                        A.im[idx] = T(vim[(size_t)v * len + row] * is);
+                    }
+                    // A[k+1] (r,2,cr): R[c][col] = sum_row conj(U[row][c]) theta[row][col]
+                    for (int idx = tid; idx < r * n; idx += NT) {
+                        const int c = idx / n, col = idx - c * n;
+                        const int v = s_sel[c];
+                        const double is = renorm / sqrt(s_nrm[v]);
+                        const double* ur = vre + (size_t)v * len;
+                        const double* ui = vim + (size_t)v * len;
+                        double xr = 0.0, xi = 0.0;
+                        for (int row = 0; row < m; ++row) {
+                            const double a0 = ur[row], a1 = ui[row];
+                            const double t0 = thr[(size_t)row * n + col], t1 = thi[(size_t)row * n + col];
+                            xr += a0 * t0 + a1 * t1;
+                            xi += a0 * t1 - a1 * t0;
+                        }
+                        B.re[idx] = T(xr * is);
+                        B.im[idx] = T(xi * is);
+                    }
+                } else {
+                    // A[k+1] (r,2,cr): V[c][col] = w_sel[c][col] / |w|
+                    for (int idx = tid; idx < r * n; idx += NT) {
+                        const int c = idx / n, col = idx - c * n;
+                        const int v = s_sel[c];
+                        const double is = 1.0 / sqrt(s_nrm[v]);
+                        B.re[idx] = T(vre[(size_t)v * len + col] * is);
+                        B.im[idx] = T(vim[(size_t)v * len + col] * is);
+                    }
+                    // A[k] (cl,2,r): L[row][c] = sum_col theta[row][col] conj(V[c][col])
+                    for (int idx = tid; idx < m * r; idx += NT) {
+                        const int row = idx / r, c = idx - row * r;
+                        const int v = s_sel[c];
+                        const double is = renorm / sqrt(s_nrm[v]);
+                        const double* wr = vre + (size_t)v * len;
+                        const double* wi = vim + (size_t)v * len;
+                        double xr = 0.0, xi = 0.0;
+                        for (int col = 0; col < n; ++col) {
+                            const double t0 = thr[(size_t)row * n + col], t1 = thi[(size_t)row * n + col];
+                            const double b0 = wr[col], b1 = wi[col];
+                            xr += t0 * b0 + t1 * b1;
+                            xi += t1 * b0 - t0 * b1;
+                        }
+                        A.re[idx] = T(xr * is);
+                        A.im[idx] = T(xi * is);
+                    }
+                }
+                __syncthreads();
+                if (tid == 0) s_chi[k + 1] = r;
+                chi_peak = max(chi_peak, r);
+                ++n2q;
+                {
+                    const double dl = cl, dm = cm, dr = cr, dk = r;
+                    flops += 32.0 * dl * dm * dr + 32.0 * dl * dl * dr + 32.0 * dk * dl * dr +
+                             104.0 * dl * dl * dl;
+                }
+                __syncthreads();
+            }
+        }
+        if (tid == 0) {
+            msc_shot_result res;
+            res.p_acc = p_acc;
+            res.infid = alive ? infid : 0.0;
+            res.disc_weight = disc;
+            res.chi_peak = chi_peak;
+            res.status = status | (alive ? MSC_SHOT_DONE : 0);
+            res.rejected_at = rej_at;
+            res.fail = (alive && p_acc > 0.0 && infid > P.tau_fail) ? 1 : 0;
+            res.n2q = n2q;
+            res.flops = flops;
+            res.reserved = 0;
+            P.out[it] = res;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+hipError_t launch_mps(int precision, bool small, const MpsArgs& a, int grid, hipStream_t s) {
+    if (precision == MSC_FP64) {
+        if (small) hipLaunchKernelGGL((mps_kernel<double, 32>), dim3(grid), dim3(NT), 0, s, a);
+        else hipLaunchKernelGGL((mps_kernel<double, 64>), dim3(grid), dim3(NT), 0, s, a);
+    } else {
+        if (small) hipLaunchKernelGGL((mps_kernel<float, 32>), dim3(grid), dim3(NT), 0, s, a);
+        else hipLaunchKernelGGL((mps_kernel<float, 64>), dim3(grid), dim3(NT), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace msc

@@ -1,0 +1,158 @@
+// Offline-screening kernel (Section 4.2): one shot per lane.
+//
+// A shot's signature over the decided measurements is the XOR of the
+// precompiled signatures of its faults' basis components (X_a, Z_a, X_b,
+// Z_b); the shot must be simulated iff that signature is zero.  Each lane
+// streams its shot's CSR slice from HBM, XORs <= W-word signatures from the
+// L2-resident table in registers, and the wavefront's verdicts are packed
+// with a 64-lane ballot into one uint64 of the survivor bitmap (lane j of
+// wave w <-> shot 64 w + j).  A second pass turns the bitmap into an
+// ascending survivor index list: per-block popcounts, one scan block, and a
+// scatter with a per-wave prefix from the ballot mask.  Integer only.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace msc {
+namespace {
+
+constexpr int PT = 256;   // threads per block (4 waves, 256 shots)
+
+template <int W>
+__global__ __launch_bounds__(PT) void screen_kernel(int32_t nch, int64_t n,
+                                                    const int64_t* __restrict__ off,
+                                                    const int32_t* __restrict__ chan,
+                                                    const uint8_t* __restrict__ pauli,
+                                                    const uint64_t* __restrict__ sig,
+                                                    uint64_t* __restrict__ bits,
+                                                    int64_t* __restrict__ block_cnt) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * PT + threadIdx.x;
+    bool alive = false;
+    if (i < n) {
+        uint64_t acc[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) acc[w] = 0;
+        const int64_t f0 = off[i], f1 = off[i + 1];
+        for (int64_t f = f0; f < f1; ++f) {
+            const int64_t c = chan[f];
+            if (c < 0 || c >= nch) continue;   // not a channel of this circuit
+            const int p = pauli[f];
+            const uint64_t* s = sig + c * 4 * W;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if ((p >> k) & 1) {
+#pragma unroll
+                    for (int w = 0; w < W; ++w) acc[w] ^= s[k * W + w];
+                }
+            }
+        }
+        uint64_t any = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) any |= acc[w];
+        alive = any == 0;
+    }
+    const uint64_t mask = __ballot(alive);
+    const int lane = threadIdx.x & 63;
+    const int64_t word = (static_cast<int64_t>(blockIdx.x) * PT + (threadIdx.x & ~63)) >> 6;
+    __shared__ int s_cnt[PT / 64];
+    if (lane == 0) {
+        if (word * 64 < n) bits[word] = mask;
+        s_cnt[threadIdx.x >> 6] = __popcll(mask);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && block_cnt) {
+        int64_t t = 0;
+        for (int w = 0; w < PT / 64; ++w) t += s_cnt[w];
+        block_cnt[blockIdx.x] = t;
+    }
+}
+
+// exclusive scan of block counts in place (one block), total at [nb]
+__global__ __launch_bounds__(1024) void scan_kernel(int64_t* cnt, int64_t nb) {
+    __shared__ int64_t part[1024];
+    const int tid = threadIdx.x;
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t lo = tid * per, hi = (lo + per < nb) ? lo + per : nb;
+    int64_t s = 0;
+    for (int64_t j = lo; j < hi; ++j) s += cnt[j];
+    part[tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+        int64_t run = 0;
+        for (int j = 0; j < 1024; ++j) {
+            int64_t v = part[j];
+            part[j] = run;
+            run += v;
+        }
+        cnt[nb] = run;
+    }
+    __syncthreads();
+    int64_t run = part[tid];
+    for (int64_t j = lo; j < hi; ++j) {
+        int64_t v = cnt[j];
+        cnt[j] = run;
+        run += v;
+    }
+}
+
+__global__ __launch_bounds__(PT) void scatter_kernel(int64_t n, const uint64_t* __restrict__ bits,
+                                                     const int64_t* __restrict__ block_off,
+                                                     int64_t* __restrict__ idx) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * PT + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int64_t word = (static_cast<int64_t>(blockIdx.x) * PT + (threadIdx.x & ~63)) >> 6;
+    const uint64_t mask = (word * 64 < n) ? bits[word] : 0ull;
+    __shared__ int s_pre[PT / 64];
+    if (lane == 0) s_pre[wv] = __popcll(mask);
+    __syncthreads();
+    int64_t base = block_off[blockIdx.x];
+    for (int w = 0; w < wv; ++w) base += s_pre[w];
+    if (i < n && ((mask >> lane) & 1)) {
+        const uint64_t below = lane ? (mask & ((1ull << lane) - 1)) : 0ull;
+        idx[base + __popcll(below)] = i;
+    }
+}
+
+}  // namespace
+
+int64_t prescreen_tmp_words(int64_t n) { return (n + PT - 1) / PT + 1; }
+
+hipError_t launch_prescreen(int words, int32_t n_channels, int64_t n, const int64_t* off, const int32_t* chan,
+                            const uint8_t* pauli, const uint64_t* sig, uint64_t* bits,
+                            int64_t* survivor_idx, int64_t* block_tmp, int64_t n_blocks_tmp,
+                            hipStream_t s) {
+    const int64_t nb = (n + PT - 1) / PT;
+    if (nb == 0) return hipSuccess;
+    if (n_blocks_tmp < nb + 1) return hipErrorInvalidValue;
+    dim3 grid(static_cast<unsigned>(nb));
+    switch (words) {
+#define MSC_SCREEN_CASE(WW)                                                                   \
+    case WW:                                                                                  \
+        hipLaunchKernelGGL(screen_kernel<WW>, grid, dim3(PT), 0, s, n_channels, n, off, chan,  \
+                           pauli, sig, bits, block_tmp);                                      \
+        break;
+        MSC_SCREEN_CASE(1)
+        MSC_SCREEN_CASE(2)
+        MSC_SCREEN_CASE(3)
+        MSC_SCREEN_CASE(4)
+        MSC_SCREEN_CASE(5)
+        MSC_SCREEN_CASE(6)
+        MSC_SCREEN_CASE(7)
+        MSC_SCREEN_CASE(8)
+#undef MSC_SCREEN_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, block_tmp, nb);
+    e = hipGetLastError();
+    if (e != hipSuccess || !survivor_idx) return e;
+    hipLaunchKernelGGL(scatter_kernel, grid, dim3(PT), 0, s, n, bits, block_tmp, survivor_idx);
+    return hipGetLastError();
+}
+
+}  // namespace msc

@@ -1,0 +1,185 @@
+// Batched two-site contraction + gate on MFMA (Section 3.1), FP32 split
+// complex with FP32 accumulation.
+//
+// theta[(a,i),(j,b)] = sum_{i'j'} G[ij][i'j'] sum_c A[(a,i'),c] B[c,(j',b)]
+//
+// The complex product is four real GEMMs on v_mfma_f32_16x16x4f32:
+// Re += Ar Br + (-Ai) Bi, Im += Ar Bi + Ai Br.  A workgroup (4 waves) owns a
+// 128-row x (64 b, both j') tile of one batch element; K = chi is streamed
+// through double-buffered LDS in steps of 16.  Each wave keeps a 64 x (32 b,
+// both j') accumulator block, so the four (i', j') partial products of an
+// output (a, b) sit in the same lane and the 4x4 gate is applied in
+// registers before the single store of theta.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace msc {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int TM = 128;   // rows (a,i) per workgroup
+constexpr int TB = 64;    // b columns per workgroup (times 2 for j')
+constexpr int TK = 16;    // k per LDS stage
+constexpr int NTH = 256;
+
+__global__ __launch_bounds__(NTH) void twosite_kernel(int chi, const float* __restrict__ Ag,
+                                                      const float* __restrict__ Bg,
+                                                      const float* __restrict__ gate,
+                                                      float* __restrict__ Tg) {
+    // LDS: [stage][plane][k][col]
+    __shared__ float As[2][2][TK][TM];
+    __shared__ float Bs[2][2][TK][2 * TB];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int m = 2 * chi;                    // rows of A and theta
+    const int n = 2 * chi;                    // columns of B and theta
+    const int rows_tiles = m / TM;
+    const int tile = blockIdx.x;
+    const int R0 = (tile % rows_tiles) * TM;
+    const int B0 = (tile / rows_tiles) * TB;
+    const size_t bidx = blockIdx.y;
+    const float* A = Ag + bidx * 2 * (size_t)m * chi;
+    const float* Bm = Bg + bidx * 2 * (size_t)chi * n;
+    float* T = Tg + bidx * 2 * (size_t)m * n;
+
+    float g[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) g[j] = gate[j];
+
+    floatx4 acc[4][2][2][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int d = 0; d < 2; ++d) acc[a][b][c][d] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    float4 ra[4], rb[4];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int idx = tid + NTH * s;
+            const int plane = idx >> 9, rem = idx & 511;
+            const int row = rem >> 2, kq = rem & 3;
+            ra[s] = *reinterpret_cast<const float4*>(A + (size_t)plane * m * chi +
+                                                     (size_t)(R0 + row) * chi + k0 + 4 * kq);
+            const int kr = rem >> 5, cq = rem & 31;
+            const int cl = 4 * cq;
+            const int col = (cl >> 6) * chi + B0 + (cl & 63);
+            rb[s] = *reinterpret_cast<const float4*>(Bm + (size_t)plane * chi * n +
+                                                     (size_t)(k0 + kr) * n + col);
+        }
+    };
+    auto lstore = [&](int st) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int idx = tid + NTH * s;
+            const int plane = idx >> 9, rem = idx & 511;
+            const int row = rem >> 2, kq = rem & 3;
+            As[st][plane][4 * kq + 0][row] = ra[s].x;
+            As[st][plane][4 * kq + 1][row] = ra[s].y;
+            As[st][plane][4 * kq + 2][row] = ra[s].z;
+            As[st][plane][4 * kq + 3][row] = ra[s].w;
+            const int kr = rem >> 5, cq = rem & 31;
+            *reinterpret_cast<float4*>(&Bs[st][plane][kr][4 * cq]) = rb[s];
+        }
+    };
+
+    const int nk = chi / TK;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int st = kt & 1;
+        if (kt + 1 < nk) gload((kt + 1) * TK);
+#pragma unroll
+        for (int ks = 0; ks < TK / 4; ++ks) {
+            const int kk = 4 * ks + (lane >> 4);
+            float ar[4], ai[4], br[2][2], bi[2][2];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const int r = wm * 64 + mt * 16 + (lane & 15);
+                ar[mt] = As[st][0][kk][r];
+                ai[mt] = As[st][1][kk][r];
+            }
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                for (int jp = 0; jp < 2; ++jp) {
+                    const int c = jp * TB + wn * 32 + nt * 16 + (lane & 15);
+                    br[nt][jp] = Bs[st][0][kk][c];
+                    bi[nt][jp] = Bs[st][1][kk][c];
+                }
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                    for (int jp = 0; jp < 2; ++jp) {
+                        floatx4& re = acc[mt][nt][jp][0];
+                        floatx4& im = acc[mt][nt][jp][1];
+                        re = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[mt], br[nt][jp], re, 0, 0, 0);
+                        re = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai[mt], bi[nt][jp], re, 0, 0, 0);
+                        im = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[mt], bi[nt][jp], im, 0, 0, 0);
+                        im = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[mt], br[nt][jp], im, 0, 0, 0);
+                    }
+        }
+        if (kt + 1 < nk) lstore(st ^ 1);
+        __syncthreads();
+    }
+
+    // epilogue: gate on the physical legs, then store theta
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int rp = 0; rp < 2; ++rp) {
+                // rows 4*(lane/16) + 2 rp + i' of this 16x16 tile
+                const int row0 = R0 + wm * 64 + mt * 16 + 4 * (lane >> 4) + 2 * rp;
+                const int b = B0 + wn * 32 + nt * 16 + (lane & 15);
+                float sr[4], si[4];   // S[i'j'] at index 2 i' + j'
+#pragma unroll
+                for (int ip = 0; ip < 2; ++ip)
+#pragma unroll
+                    for (int jp = 0; jp < 2; ++jp) {
+                        sr[2 * ip + jp] = acc[mt][nt][jp][0][2 * rp + ip];
+                        si[2 * ip + jp] = acc[mt][nt][jp][1][2 * rp + ip];
+                    }
+#pragma unroll
+                for (int o = 0; o < 4; ++o) {
+                    float xr = 0.f, xi = 0.f;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float gr = g[2 * (4 * o + j)], gi = g[2 * (4 * o + j) + 1];
+                        xr += gr * sr[j] - gi * si[j];
+                        xi += gr * si[j] + gi * sr[j];
+                    }
+                    const int i = o >> 1, j = o & 1;
+                    const size_t at = (size_t)(row0 + i) * n + (size_t)j * chi + b;
+                    T[at] = xr;
+                    T[(size_t)m * n + at] = xi;
+                }
+            }
+}
+
+}  // namespace
+
+hipError_t launch_twosite(int chi, int batch, const float* A, const float* B, const float* gate,
+                          float* theta, hipStream_t s) {
+    if (chi % 64 != 0 || chi < 64) return hipErrorInvalidValue;
+    const int tiles = (2 * chi / TM) * (chi / TB);
+    hipLaunchKernelGGL(twosite_kernel, dim3(tiles, batch), dim3(NTH), 0, s, chi, A, B, gate, theta);
+    return hipGetLastError();
+}
+
+}  // namespace msc

@@ -1,0 +1,85 @@
+// Internal declarations shared by the host library and the HIP kernels.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/msc.h"
+
+namespace msc {
+
+// ---------------------------------------------------------------------------
+// Compiled MPS op stream (device).  Sites are MPS positions, not qubits.
+enum OpKind : int32_t {
+    OP_G1 = 0,     // a = site, aux = 1q gate id (gate2 table)
+    OP_G2 = 1,     // a = k (sites k, k+1), b = dir (1: centre -> k+1,
+                   // 0: centre -> k), aux = 4x4 gate id (gate4 table)
+    OP_FAULT = 2,  // a = site of the channel's first qubit, b = second or -1,
+                   // aux = channel index
+    OP_MEAS = 3,   // a = site, aux = measurement index
+    OP_RESET = 4,  // a = site: X^e with e the outcome last projected there
+    OP_FINAL = 5   // a = site of the seed qubit
+};
+
+struct DevOp {
+    int32_t kind, a, b, aux;
+};
+
+// 1q gate ids (rows of the 2x2 complex table)
+enum Gate1 : int32_t { G_H = 0, G_S, G_SDG, G_T, G_TDG, G_X, G_Y, G_Z, G1_COUNT };
+// 4x4 gate ids in site order |s_k s_{k+1}>
+enum Gate4 : int32_t { G4_I = 0, G4_SWAP, G4_CX01, G4_CX10, G4_CZ, G4_COUNT };
+
+// Parsed circuit op (qubit level)
+enum IrKind : int32_t { IR_G1 = 0, IR_G2, IR_M, IR_R, IR_CH };
+enum ChanKind : int32_t { CH_DEP1 = 0, CH_DEP2 = 1, CH_XERR = 2 };
+struct IrOp {
+    int32_t kind;
+    int32_t g;     // IR_G1: Gate1; IR_G2: 0 CX, 1 CZ; IR_CH: ChanKind
+    int32_t a, b;  // qubits (b = -1 if unused)
+    int32_t idx;   // measurement or channel index
+};
+
+void gate1_matrix(int g, double out[8]);    // (re,im) row-major 2x2
+void gate4_matrix(int g, double out[32]);   // (re,im) row-major 4x4
+
+// Error helpers (capi.cpp)
+int set_error(int code, const std::string& msg);
+
+}  // namespace msc
+
+struct msc_circuit {
+    int n = 0;
+    int seed = 0;
+    int target = 'T';
+    std::vector<int32_t> order;          // site -> qubit
+    std::vector<msc::IrOp> ir;
+    int n_meas = 0, n_channels = 0;
+    std::vector<int32_t> chan_kind;
+    std::vector<int32_t> chan_q0, chan_q1;
+    // compiled MPS op stream
+    std::vector<msc::DevOp> ops;
+    int64_t n_twosite = 0, n_swaps = 0;
+    int final_site = 0;
+    // expected outcomes
+    std::vector<uint8_t> expected;
+    bool calibrated = false;
+    // offline screening tables
+    int words = 0;
+    std::vector<int32_t> decided;        // measurement index per decided slot
+    std::vector<uint64_t> sig;           // [4*n_channels][words]
+    // device copies (owned), on device `dev`
+    int dev = -1;
+    void* d_ops = nullptr;
+    void* d_g1 = nullptr;
+    void* d_g4 = nullptr;
+    void* d_sig = nullptr;
+    void* d_expected = nullptr;
+};
+
+namespace msc {
+int compile_circuit(msc_circuit* c);        // ops from ir + layout
+int prescreen_compile(msc_circuit* c);      // decided set + signatures
+int parse_circuit(const char* text, size_t len, msc_circuit* c);
+}  // namespace msc

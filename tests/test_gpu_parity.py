@@ -1,0 +1,195 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Per-shot branch probabilities are compared, not sampled bits: P_acc and
+1 - f within 1e-10 for the FP64 path and 1e-5 for the mixed-precision path,
+rejection index and failure flag exactly; the pre-screen bit-exactly.
+"""
+import numpy as np
+import pytest
+
+import paper_2609_19116_amd as msc
+from paper_2609_19116_amd import MSC_FP32, MSC_FP64, results_numpy
+from tests.helpers import oracle_csr, oracle_discards, oracle_results, say, to_dev
+from workloads.circuits import config_circuit
+
+pytestmark = pytest.mark.gpu
+
+TOL = {MSC_FP64: 1e-10, MSC_FP32: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    c = msc.Ctx(0)
+    yield c
+    c.close()
+
+
+def _circuit(ctx, name, target="T"):
+    cc = config_circuit(name, target)
+    c = msc.Circuit(cc.text)
+    say(f"calibrate {name} {target}")
+    c.calibrate(ctx)
+    return cc, c
+
+
+def _lib_csr(c, seed, n, weights=None, p=0.0, first=0):
+    return msc.sample_faults(c, seed, first, n, weights=weights, p=p)
+
+
+def _same_csr(a, b):
+    return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def _run(ctx, c, csr, precision, **kw):
+    off, ch, pa = to_dev(*csr)
+    out = msc.simulate(ctx, c, off, ch, pa, precision=precision, **kw)
+    return results_numpy(out)
+
+
+def _compare(res, ref, tol):
+    p_err = np.abs(res["p_acc"] - ref[:, 0])
+    f_err = np.abs(np.where(ref[:, 0] > 0, res["infid"] - ref[:, 1], 0.0))
+    assert p_err.max() <= tol, (p_err.max(), int(p_err.argmax()))
+    assert f_err.max() <= tol, (f_err.max(), int(f_err.argmax()))
+    assert np.array_equal(res["rejected_at"], ref[:, 2].astype(np.int32))
+    fail_ref = (ref[:, 0] > 0) & (ref[:, 1] > 1e-4)
+    assert np.array_equal(res["fail"].astype(bool), fail_ref)
+
+
+def test_calibration_all_circuits(ctx):
+    for name in ("tiny", "c1", "c3"):
+        for tg in ("T", "S"):
+            cc, c = _circuit(ctx, name, tg)
+            inf = c.info()
+            assert inf["calibrated"] == 1
+            assert not c.expected().any()   # every noiseless outcome is 0
+
+
+@pytest.mark.parametrize("precision", [MSC_FP64, MSC_FP32])
+@pytest.mark.parametrize("name", ["tiny", "c1"])
+def test_parity_small_circuits(ctx, name, precision):
+    cc, c = _circuit(ctx, name)
+    n = 160
+    w = np.arange(n) % 5                       # subset sampling w = 0..4
+    csr = _lib_csr(c, 0x5EED0002, n, weights=w)
+    circ, ocsr = oracle_csr(cc.text, 0x5EED0002, n, weights=w)
+    assert _same_csr(csr, ocsr)
+    ref = oracle_results(circ, ocsr)
+    say(f"simulate {name} precision={precision} n={n}")
+    res = _run(ctx, c, csr, precision)
+    _compare(res, ref, TOL[precision])
+    acc = ref[:, 0] > 0
+    assert acc.sum() >= 32                     # w = 0 shots at least
+
+
+def test_parity_c1_binomial_fp64_against_state_vector(ctx):
+    cc, c = _circuit(ctx, "c1")
+    n = 40
+    csr = _lib_csr(c, 0x5EED0001, n, p=1e-2)
+    circ, ocsr = oracle_csr(cc.text, 0x5EED0001, n, p=1e-2)
+    assert _same_csr(csr, ocsr)
+    ref = oracle_results(circ, ocsr, engine="sv")
+    say("simulate c1 binomial fp64 vs state vector")
+    res = _run(ctx, c, csr, MSC_FP64)
+    _compare(res, ref, 1e-10)
+
+
+@pytest.mark.parametrize("precision", [MSC_FP64, MSC_FP32])
+def test_parity_c3_stratified(ctx, precision):
+    cc, c = _circuit(ctx, "c3")
+    w = np.array([0, 0, 1, 1, 1, 2, 2, 2, 3, 3, 4, 4])
+    csr = _lib_csr(c, 0x5EED0003, len(w), weights=w)
+    circ, ocsr = oracle_csr(cc.text, 0x5EED0003, len(w), weights=w)
+    assert _same_csr(csr, ocsr)
+    ref = oracle_results(circ, ocsr)
+    say(f"simulate c3 stratified precision={precision}")
+    res = _run(ctx, c, csr, precision)
+    _compare(res, ref, TOL[precision])
+
+
+def test_edge_cases(ctx):
+    import torch
+    cc, c = _circuit(ctx, "c1")
+    n = 20
+    csr = _lib_csr(c, 7, n, weights=np.zeros(n, dtype=np.int32))
+    off, ch, pa = to_dev(*csr)
+    say("edge: empty batch")
+    out = msc.simulate(ctx, c, off, ch, pa, shot_idx=torch.zeros(0, dtype=torch.int64).cuda())
+    assert out.numel() == 0
+    say("edge: all w=0")
+    r = results_numpy(msc.simulate(ctx, c, off, ch, pa))
+    assert np.allclose(r["p_acc"], 1.0, atol=1e-12) and np.all(r["infid"] < 1e-12)
+    assert np.all(r["status"] == msc.SHOT_DONE)
+    # subset via shot_idx, more slots than shots
+    w = np.arange(n) % 4
+    csr = _lib_csr(c, 8, n, weights=w)
+    off, ch, pa = to_dev(*csr)
+    full = results_numpy(msc.simulate(ctx, c, off, ch, pa, n_slots=4))
+    idx = torch.tensor([19, 3, 3, 0], dtype=torch.int64).cuda()
+    say("edge: shot_idx subset")
+    sub = results_numpy(msc.simulate(ctx, c, off, ch, pa, shot_idx=idx, n_slots=64))
+    assert np.array_equal(sub["p_acc"], full["p_acc"][[19, 3, 3, 0]])
+    # determinism: same inputs, bit-identical FP64 output
+    say("edge: determinism")
+    again = results_numpy(msc.simulate(ctx, c, off, ch, pa, n_slots=7))
+    assert np.array_equal(again["p_acc"], full["p_acc"])
+    assert np.array_equal(again["infid"], full["infid"])
+    # a binding bond cap is flagged
+    say("edge: chi cap")
+    capped = results_numpy(msc.simulate(ctx, c, off, ch, pa, chi_max=2))
+    assert np.any(capped["status"] & msc.SHOT_CHI_CAP)
+    # argument errors
+    with pytest.raises(msc.MscError):
+        msc.simulate(ctx, c, off, ch, pa, chi_max=0)
+    with pytest.raises(msc.MscError):
+        msc.simulate(ctx, c, off, ch, pa, chi_max=512)
+
+
+def test_uncalibrated_circuit_is_refused(ctx):
+    c = msc.Circuit(config_circuit("tiny").text)
+    csr = _lib_csr(c, 1, 4, weights=[0, 0, 0, 0])
+    off, ch, pa = to_dev(*csr)
+    with pytest.raises(msc.MscError):
+        msc.simulate(ctx, c, off, ch, pa)
+
+
+@pytest.mark.parametrize("name,n,p", [("c1", 20000, 1e-2), ("c3", 6000, 2e-3),
+                                      ("c4", 1500, 1e-3), ("tiny", 4097, 5e-2)])
+def test_prescreen_bit_exact(ctx, name, n, p):
+    cc = config_circuit(name)
+    c = msc.Circuit(cc.text)
+    csr = _lib_csr(c, 0x5EED0005, n, p=p)
+    circ, ocsr = oracle_csr(cc.text, 0x5EED0005, n, p=p)
+    assert _same_csr(csr, ocsr)
+    ref_discard = oracle_discards(circ, ocsr)
+    off, ch, pa = to_dev(*csr)
+    say(f"prescreen {name} n={n}")
+    bits, idx, cnt = msc.prescreen(ctx, c, off, ch, pa)
+    b = bits.cpu().numpy().view(np.uint64)
+    alive = np.array([(b[i >> 6] >> np.uint64(i & 63)) & np.uint64(1) for i in range(n)],
+                     dtype=bool)
+    assert np.array_equal(alive, ~ref_discard)
+    assert cnt == int((~ref_discard).sum())
+    assert np.array_equal(idx.cpu().numpy(), np.nonzero(~ref_discard)[0])
+
+
+@pytest.mark.parametrize("chi,batch,gate", [(64, 3, "haar"), (128, 2, "cx"), (256, 1, "haar")])
+def test_twosite_contract(ctx, chi, batch, gate):
+    import torch
+    from workloads.tensors import random_twosite
+    A, B, G, Ac, Bc, _ = random_twosite(chi, batch, 0x5EED0103, gate)
+    Gc = G.reshape(4, 4, 2).astype(np.float64)
+    Gc = Gc[..., 0] + 1j * Gc[..., 1]
+    dA, dB, dG = to_dev(A, B, G)
+    th = torch.zeros(batch * 2 * (2 * chi) ** 2, dtype=torch.float32).cuda()
+    say(f"twosite chi={chi} batch={batch}")
+    msc.twosite_contract(ctx, chi, batch, dA, dB, dG, th)
+    got = th.cpu().numpy().reshape(batch, 2, 2 * chi, 2 * chi)
+    got = got[:, 0].astype(np.float64) + 1j * got[:, 1]
+    for b in range(batch):
+        T = (Ac[b] @ Bc[b]).reshape(chi, 2, 2, chi)       # (a, i', j', b)
+        ref = np.einsum("ijkl,aklb->aijb", Gc.reshape(2, 2, 2, 2), T).reshape(2 * chi, 2 * chi)
+        err = np.linalg.norm(got[b] - ref) / np.linalg.norm(ref)
+        assert err < 1e-5, err

@@ -98,7 +98,7 @@ typedef struct {
                              + 32 r cl cr (projection) + 104 cl^3 (eigen-
                              solve) with cl, cm, cr the bonds around the two
                              sites and r the new bond                      */
-    int64_t reserved;
+    int64_t sweeps;       /* Jacobi sweeps summed over the shot's SVDs       */
 } msc_shot_result;
 
 typedef struct {

@@ -50,13 +50,13 @@ class ShotResult(C.Structure):
     _fields_ = [("p_acc", C.c_double), ("infid", C.c_double), ("disc_weight", C.c_double),
                 ("chi_peak", C.c_int32), ("status", C.c_int32), ("rejected_at", C.c_int32),
                 ("fail", C.c_int32), ("n2q", C.c_int64), ("flops", C.c_double),
-                ("reserved", C.c_int64)]
+                ("sweeps", C.c_int64)]
 
 
 SHOT_DTYPE = np.dtype([("p_acc", "<f8"), ("infid", "<f8"), ("disc_weight", "<f8"),
                        ("chi_peak", "<i4"), ("status", "<i4"), ("rejected_at", "<i4"),
                        ("fail", "<i4"), ("n2q", "<i8"), ("flops", "<f8"),
-                       ("reserved", "<i8")])
+                       ("sweeps", "<i8")])
 assert SHOT_DTYPE.itemsize == C.sizeof(ShotResult) == 64
 
 

@@ -219,6 +219,7 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
         int chi_peak = 1, status = 0, rej_at = -1;
         int64_t n2q = 0;
         double flops = 0.0;
+        int64_t sweeps_total = 0;
         int64_t fcur = P.shot_off[shot];
         const int64_t fend = P.shot_off[shot + 1];
         bool alive = true;
@@ -397,6 +398,7 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                 const double tol = static_cast<double>(len) * DBL_EPSILON;
                 const int sweeps = hestenes(vre, vim, nv, len, floor2, tol, s_misc);
                 if (sweeps < 0) status |= MSC_SHOT_NOCONV;
+                sweeps_total += sweeps < 0 ? 40 : sweeps;
                 // squared norms of the orthogonalised vectors
                 for (int v = tid; v < nv; v += NT) {
                     double s = 0.0;
@@ -510,7 +512,7 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
             res.fail = (alive && p_acc > 0.0 && infid > P.tau_fail) ? 1 : 0;
             res.n2q = n2q;
             res.flops = flops;
-            res.reserved = 0;
+            res.sweeps = sweeps_total;
             P.out[it] = res;
         }
         __syncthreads();

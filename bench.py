@@ -50,6 +50,7 @@ def main() -> int:
                     help="shots of the batch run through the CPU oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--lds-width", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build simulates each shot on one "
@@ -92,7 +93,7 @@ def main() -> int:
         res = None
         if cnt:
             out = msc.simulate(ctx, circ, off, ch, pa, shot_idx=idx, precision=msc.MSC_FP32,
-                               chi_max=args.chi_max)
+                               chi_max=args.chi_max, lds_width=args.lds_width)
             res = msc.results_numpy(out)
         t_sim = ctx.last_kernel_ms("simulate") if cnt else 0.0
         if accumulate:

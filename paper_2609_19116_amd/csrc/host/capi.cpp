@@ -226,22 +226,20 @@ Layout make_layout(int n, int chi_max) {
     }
     L.slot_elems = (pos + 63) / 64 * 64;
     int64_t s = 2ll * chi_max;
-    L.scratch = 4 * s * s + 64;
+    L.scratch = 4 * s * s + 4 * s + 64;   // theta copy + padded vectors
     return L;
 }
 
 }  // namespace
 
 static int run_shots(msc_ctx* ctx, const msc_circuit* c, int precision, int chi_max, double tau,
-                     double tau_rej, double tau_fail, int n_slots, int64_t n,
+                     double tau_rej, double tau_fail, int n_slots, int lds_width, int64_t n,
                      int64_t n_csr, const int64_t* off, const int32_t* chan, const uint8_t* pauli,
                      const int64_t* shot_idx, msc_shot_result* out, int calibrate,
                      double* cal_p, uint8_t* cal_e, const char* timer) {
     Layout L = make_layout(c->n, chi_max);
-    if (n_slots <= 0) {
-        const bool small = chi_max <= 16;
-        n_slots = ctx->n_cu * (small ? 6 : 2);
-    }
+    const bool small = lds_width == 32;
+    if (n_slots <= 0) n_slots = ctx->n_cu * mps_blocks_per_cu(precision, small);
     n_slots = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(n_slots, n)));
     const size_t tsize = precision == MSC_FP64 ? sizeof(double) : sizeof(float);
     void *arena, *scratch, *dcap, *doff, *dhalf;
@@ -292,7 +290,6 @@ static int run_shots(msc_ctx* ctx, const msc_circuit* c, int precision, int chi_
     a.calibrate = calibrate;
     a.cal_p = cal_p;
     a.cal_e = cal_e;
-    const bool small = chi_max <= 16;
     MSC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
     MSC_HIP(launch_mps(precision, small, a, n_slots, ctx->stream));
     MSC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
@@ -319,7 +316,7 @@ extern "C" int msc_circuit_calibrate(msc_ctx* ctx, msc_circuit* c) {
     int64_t zero[2] = {0, 0};
     MSC_HIP(hipMemcpy(doff, zero, sizeof(zero), hipMemcpyHostToDevice));
     int chi_max = kMaxChiKernel;
-    rc = run_shots(ctx, c, MSC_FP64, chi_max, 1e-12, 0.0, 1e-4, 1, 1, 1,
+    rc = run_shots(ctx, c, MSC_FP64, chi_max, 1e-12, 0.0, 1e-4, 1, 64, 1, 1,
                    static_cast<int64_t*>(doff), static_cast<int32_t*>(dchan),
                    static_cast<uint8_t*>(dpa), nullptr, static_cast<msc_shot_result*>(dout), 1,
                    static_cast<double*>(dp), static_cast<uint8_t*>(de), "calibrate");
@@ -367,8 +364,10 @@ extern "C" int msc_simulate(msc_ctx* ctx, const msc_circuit* c, const msc_sim_op
     double tau = opts->tau_trunc > 0 ? opts->tau_trunc : (opts->precision == MSC_FP64 ? 1e-12 : 1e-5);
     double tau_rej = opts->tau_rej > 0 ? opts->tau_rej : 1e-6;
     double tau_fail = opts->tau_fail > 0 ? opts->tau_fail : 1e-4;
+    if (opts->lds_width != 0 && opts->lds_width != 32 && opts->lds_width != 64)
+        return set_error(MSC_E_INVALID, "lds_width must be 0, 32 or 64");
     return run_shots(ctx, c, opts->precision, opts->chi_max, tau, tau_rej, tau_fail,
-                     opts->n_slots, n, n_shots, shot_off, chan, pauli, shot_idx, out, 0,
+                     opts->n_slots, opts->lds_width == 32 ? 32 : 64, n, n_shots, shot_off, chan, pauli, shot_idx, out, 0,
                      nullptr, nullptr, "simulate");
 }
 

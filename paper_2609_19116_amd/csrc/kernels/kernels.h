@@ -45,6 +45,8 @@ struct MpsArgs {
 
 // precision: MSC_FP64 or MSC_FP32; small: use the 32-wide LDS variant
 hipError_t launch_mps(int precision, bool small, const MpsArgs& a, int grid, hipStream_t s);
+// resident workgroups per CU of the chosen variant (sizes the persistent grid)
+int mps_blocks_per_cu(int precision, bool small);
 
 hipError_t launch_prescreen(int words, int32_t n_channels, int64_t n, const int64_t* off, const int32_t* chan,
                             const uint8_t* pauli, const uint64_t* sig, uint64_t* survive_bits,

@@ -82,9 +82,9 @@ __device__ __forceinline__ int player(int slot, int t, int nv) {
 }
 
 // One-sided Jacobi on nv vectors of length len (planar FP64 at vre/vim,
-// vector v at v*len).  Returns the number of sweeps used (or -1 when the
+// vector v at v*ld, ld >= len padded against LDS bank conflicts).  Returns the number of sweeps used (or -1 when the
 // sweep limit was reached).
-__device__ int hestenes(double* vre, double* vim, int nv, int len, double floor2,
+__device__ int hestenes(double* vre, double* vim, int nv, int len, int ld, double floor2,
                         double tol, int* sflag) {
     const int tid = threadIdx.x;
     if (nv < 2) return 0;
@@ -111,10 +111,10 @@ __device__ int hestenes(double* vre, double* vim, int nv, int len, double floor2
                 if (active) {
                     p = player(pi, t, nv);
                     q = player(nv - 1 - pi, t, nv);
-                    const double* xr = vre + (size_t)p * len;
-                    const double* xi = vim + (size_t)p * len;
-                    const double* yr = vre + (size_t)q * len;
-                    const double* yi = vim + (size_t)q * len;
+                    const double* xr = vre + (size_t)p * ld;
+                    const double* xi = vim + (size_t)p * ld;
+                    const double* yr = vre + (size_t)q * ld;
+                    const double* yi = vim + (size_t)q * ld;
                     for (int e = gl; e < len; e += tpp) {
                         double x0 = xr[e], x1 = xi[e], y0 = yr[e], y1 = yi[e];
                         a += x0 * x0 + x1 * x1;
@@ -140,10 +140,10 @@ __device__ int hestenes(double* vre, double* vim, int nv, int len, double floor2
                         const double s = c * tt;
                         // y~ = y * conj(gamma)/|gamma|
                         const double pr = gr / g, pim = gim / g;
-                        double* xr = vre + (size_t)p * len;
-                        double* xi = vim + (size_t)p * len;
-                        double* yr = vre + (size_t)q * len;
-                        double* yi = vim + (size_t)q * len;
+                        double* xr = vre + (size_t)p * ld;
+                        double* xi = vim + (size_t)p * ld;
+                        double* yr = vre + (size_t)q * ld;
+                        double* yi = vim + (size_t)q * ld;
                         for (int e = gl; e < len; e += tpp) {
                             double x0 = xr[e], x1 = xi[e];
                             double y0 = yr[e] * pr + yi[e] * pim;
@@ -174,13 +174,14 @@ template <typename T, int SMAX>
 __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
     __shared__ int s_chi[kMaxSites + 1];
     __shared__ int s_laste[kMaxSites];
-    __shared__ double s_vre[SMAX * SMAX];
-    __shared__ double s_vim[SMAX * SMAX];
+    __shared__ double s_vre[SMAX * (SMAX + 1)];
+    __shared__ double s_vim[SMAX * (SMAX + 1)];
     __shared__ double s_nrm[MAXV];
     __shared__ int s_sel[MAXV];
     __shared__ double s_red[NW * 4];
     __shared__ int s_misc[4];
-    __shared__ double s_gate[32];
+    __shared__ double s_gph[8];
+    __shared__ int s_gsrc[4];
 
     const int tid = threadIdx.x;
     const int N = P.n_sites;
@@ -339,11 +340,22 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                 double* thr = scr;
                 double* thi = scr + (size_t)m * n;
                 const int nv = dir ? n : m, len = dir ? m : n;
+                const int ld = len + 1;
                 const bool lds = nv <= SMAX && len <= SMAX;
                 double* vre = lds ? s_vre : scr + 2 * (size_t)m * n;
-                double* vim = lds ? s_vim : vre + (size_t)nv * len;
-                const bool ident = op.aux == G4_I;
-                if (!ident && tid < 32) s_gate[tid] = P.g4[op.aux * 32 + tid];
+                double* vim = lds ? s_vim : vre + (size_t)nv * ld;
+                if (tid < 4) {
+                    // the 4x4 gates of the op stream are monomial: one
+                    // nonzero per row, found here once per update
+                    const double* g = P.g4 + op.aux * 32 + tid * 8;
+                    int src = 0;
+                    for (int j = 1; j < 4; ++j)
+                        if (fabs(g[2 * j]) + fabs(g[2 * j + 1]) > fabs(g[2 * src]) + fabs(g[2 * src + 1]))
+                            src = j;
+                    s_gsrc[tid] = src;
+                    s_gph[2 * tid] = g[2 * src];
+                    s_gph[2 * tid + 1] = g[2 * src + 1];
+                }
                 __syncthreads();
                 double nsum[1] = {0.0};
                 for (int idx = tid; idx < cl * cr; idx += NT) {
@@ -361,23 +373,15 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                         sr[2] += x1r * y0r - x1i * y0i; si[2] += x1r * y0i + x1i * y0r;
                         sr[3] += x1r * y1r - x1i * y1i; si[3] += x1r * y1i + x1i * y1r;
                     }
+                    // monomial gate: output o = phase[o] * S[src[o]]
                     double tr_[4], ti_[4];
-                    if (ident) {
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) { tr_[j] = sr[j]; ti_[j] = si[j]; }
-                    } else {
-#pragma unroll
-                        for (int o = 0; o < 4; ++o) {
-                            double xr = 0.0, xi = 0.0;
-#pragma unroll
-                            for (int j = 0; j < 4; ++j) {
-                                const double gr = s_gate[2 * (4 * o + j)], gi = s_gate[2 * (4 * o + j) + 1];
-                                xr += gr * static_cast<double>(sr[j]) - gi * static_cast<double>(si[j]);
-                                xi += gr * static_cast<double>(si[j]) + gi * static_cast<double>(sr[j]);
-                            }
-                            tr_[o] = xr;
-                            ti_[o] = xi;
-                        }
+                    for (int o = 0; o < 4; ++o) {
+                        const int j = s_gsrc[o];
+                        const double xr = static_cast<double>(sr[j]), xi = static_cast<double>(si[j]);
+                        const double pr = s_gph[2 * o], pim = s_gph[2 * o + 1];
+                        tr_[o] = pr * xr - pim * xi;
+                        ti_[o] = pr * xi + pim * xr;
                     }
 #pragma unroll
                     for (int o = 0; o < 4; ++o) {
@@ -385,7 +389,7 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                         const int row = a * 2 + i, col = j * cr + b;
                         thr[(size_t)row * n + col] = tr_[o];
                         thi[(size_t)row * n + col] = ti_[o];
-                        const size_t vi = dir ? (size_t)col * len + row : (size_t)row * len + col;
+                        const size_t vi = dir ? (size_t)col * ld + row : (size_t)row * ld + col;
                         vre[vi] = tr_[o];
                         vim[vi] = ti_[o];
                         nsum[0] += tr_[o] * tr_[o] + ti_[o] * ti_[o];
@@ -396,18 +400,47 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                 const double tau2 = P.tau * P.tau;
                 const double floor2 = 1e-4 * tau2 * total;
                 const double tol = static_cast<double>(len) * DBL_EPSILON;
-                const int sweeps = hestenes(vre, vim, nv, len, floor2, tol, s_misc);
-                if (sweeps < 0) status |= MSC_SHOT_NOCONV;
-                sweeps_total += sweeps < 0 ? 40 : sweeps;
-                // squared norms of the orthogonalised vectors
+                // squared norms, then one parallel pass over every pair: if
+                // all columns are already orthogonal (the common case) no
+                // Jacobi sweep is needed at all
                 for (int v = tid; v < nv; v += NT) {
                     double s = 0.0;
-                    const double* xr = vre + (size_t)v * len;
-                    const double* xi = vim + (size_t)v * len;
+                    const double* xr = vre + (size_t)v * ld;
+                    const double* xi = vim + (size_t)v * ld;
                     for (int e = 0; e < len; ++e) s += xr[e] * xr[e] + xi[e] * xi[e];
                     s_nrm[v] = s;
                 }
                 __syncthreads();
+                int nonorth = 0;
+                for (int t = tid; t < nv * nv; t += NT) {
+                    const int p = t / nv, q = t - p * nv;
+                    if (q <= p) continue;
+                    const double a = s_nrm[p], b = s_nrm[q];
+                    if (!(a > floor2 && b > floor2)) continue;
+                    const double* xr = vre + (size_t)p * ld;
+                    const double* xi = vim + (size_t)p * ld;
+                    const double* yr = vre + (size_t)q * ld;
+                    const double* yi = vim + (size_t)q * ld;
+                    double gr = 0.0, gim = 0.0;
+                    for (int e = 0; e < len; ++e) {
+                        gr += xr[e] * yr[e] + xi[e] * yi[e];
+                        gim += xr[e] * yi[e] - xi[e] * yr[e];
+                    }
+                    if (gr * gr + gim * gim > tol * tol * a * b) nonorth = 1;
+                }
+                if (__syncthreads_or(nonorth)) {
+                    const int sweeps = hestenes(vre, vim, nv, len, ld, floor2, tol, s_misc);
+                    if (sweeps < 0) status |= MSC_SHOT_NOCONV;
+                    sweeps_total += sweeps < 0 ? 40 : sweeps;
+                    for (int v = tid; v < nv; v += NT) {
+                        double s = 0.0;
+                        const double* xr = vre + (size_t)v * ld;
+                        const double* xi = vim + (size_t)v * ld;
+                        for (int e = 0; e < len; ++e) s += xr[e] * xr[e] + xi[e] * xi[e];
+                        s_nrm[v] = s;
+                    }
+                    __syncthreads();
+                }
                 double mx = 0.0;
                 for (int v = tid; v < nv; v += NT) mx = fmax(mx, s_nrm[v]);
                 mx = block_max(mx, s_red);
@@ -442,16 +475,16 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                         const int row = idx / r, c = idx - row * r;
                         const int v = s_sel[c];
                         const double is = 1.0 / sqrt(s_nrm[v]);
-                        A.re[idx] = T(vre[(size_t)v * len + row] * is);
-                        A.im[idx] = T(vim[(size_t)v * len + row] * is);
+                        A.re[idx] = T(vre[(size_t)v * ld + row] * is);
+                        A.im[idx] = T(vim[(size_t)v * ld + row] * is);
                     }
                     // A[k+1] (r,2,cr): R[c][col] = sum_row conj(U[row][c]) theta[row][col]
                     for (int idx = tid; idx < r * n; idx += NT) {
                         const int c = idx / n, col = idx - c * n;
                         const int v = s_sel[c];
                         const double is = renorm / sqrt(s_nrm[v]);
-                        const double* ur = vre + (size_t)v * len;
-                        const double* ui = vim + (size_t)v * len;
+                        const double* ur = vre + (size_t)v * ld;
+                        const double* ui = vim + (size_t)v * ld;
                         double xr = 0.0, xi = 0.0;
                         for (int row = 0; row < m; ++row) {
                             const double a0 = ur[row], a1 = ui[row];
@@ -468,16 +501,16 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                         const int c = idx / n, col = idx - c * n;
                         const int v = s_sel[c];
                         const double is = 1.0 / sqrt(s_nrm[v]);
-                        B.re[idx] = T(vre[(size_t)v * len + col] * is);
-                        B.im[idx] = T(vim[(size_t)v * len + col] * is);
+                        B.re[idx] = T(vre[(size_t)v * ld + col] * is);
+                        B.im[idx] = T(vim[(size_t)v * ld + col] * is);
                     }
                     // A[k] (cl,2,r): L[row][c] = sum_col theta[row][col] conj(V[c][col])
                     for (int idx = tid; idx < m * r; idx += NT) {
                         const int row = idx / r, c = idx - row * r;
                         const int v = s_sel[c];
                         const double is = renorm / sqrt(s_nrm[v]);
-                        const double* wr = vre + (size_t)v * len;
-                        const double* wi = vim + (size_t)v * len;
+                        const double* wr = vre + (size_t)v * ld;
+                        const double* wi = vim + (size_t)v * ld;
                         double xr = 0.0, xi = 0.0;
                         for (int col = 0; col < n; ++col) {
                             const double t0 = thr[(size_t)row * n + col], t1 = thi[(size_t)row * n + col];
@@ -520,6 +553,22 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
 }
 
 }  // namespace
+
+int mps_blocks_per_cu(int precision, bool small) {
+    int b = 0;
+    hipError_t e;
+    if (precision == MSC_FP64)
+        e = small ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, mps_kernel<double, 32>, NT, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, mps_kernel<double, 64>, NT, 0);
+    else
+        e = small ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, mps_kernel<float, 32>, NT, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, mps_kernel<float, 64>, NT, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return b < 1 ? 1 : b;
+}
 
 hipError_t launch_mps(int precision, bool small, const MpsArgs& a, int grid, hipStream_t s) {
     if (precision == MSC_FP64) {

@@ -96,16 +96,16 @@ def test_parity_c1_binomial_fp64_against_state_vector(ctx):
     _compare(res, ref, 1e-10)
 
 
-@pytest.mark.parametrize("precision", [MSC_FP64, MSC_FP32])
-def test_parity_c3_stratified(ctx, precision):
+@pytest.mark.parametrize("precision,lds_width", [(MSC_FP64, 0), (MSC_FP32, 0), (MSC_FP32, 32)])
+def test_parity_c3_stratified(ctx, precision, lds_width):
     cc, c = _circuit(ctx, "c3")
     w = np.array([0, 0, 1, 1, 1, 2, 2, 2, 3, 3, 4, 4])
     csr = _lib_csr(c, 0x5EED0003, len(w), weights=w)
     circ, ocsr = oracle_csr(cc.text, 0x5EED0003, len(w), weights=w)
     assert _same_csr(csr, ocsr)
     ref = oracle_results(circ, ocsr)
-    say(f"simulate c3 stratified precision={precision}")
-    res = _run(ctx, c, csr, precision)
+    say(f"simulate c3 stratified precision={precision} lds_width={lds_width}")
+    res = _run(ctx, c, csr, precision, lds_width=lds_width)
     _compare(res, ref, TOL[precision])
 
 

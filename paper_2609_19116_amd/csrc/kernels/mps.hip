@@ -399,7 +399,10 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                 const double total = nsum[0];
                 const double tau2 = P.tau * P.tau;
                 const double floor2 = 1e-4 * tau2 * total;
-                const double tol = static_cast<double>(len) * DBL_EPSILON;
+                // orthogonality tolerance: a few ulps of the tensor precision
+                const double tol = sizeof(T) == sizeof(double)
+                                       ? static_cast<double>(len) * DBL_EPSILON
+                                       : 8.0 * static_cast<double>(FLT_EPSILON);
                 // squared norms, then one parallel pass over every pair: if
                 // all columns are already orthogonal (the common case) no
                 // Jacobi sweep is needed at all
@@ -411,7 +414,7 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                     s_nrm[v] = s;
                 }
                 __syncthreads();
-                int nonorth = 0;
+                int nonorth = 0;   // block-uniform after the OR below
                 for (int t = tid; t < nv * nv; t += NT) {
                     const int p = t / nv, q = t - p * nv;
                     if (q <= p) continue;
@@ -428,7 +431,8 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                     }
                     if (gr * gr + gim * gim > tol * tol * a * b) nonorth = 1;
                 }
-                if (__syncthreads_or(nonorth)) {
+                const bool rotated = __syncthreads_or(nonorth) != 0;
+                if (rotated) {
                     const int sweeps = hestenes(vre, vim, nv, len, ld, floor2, tol, s_misc);
                     if (sweeps < 0) status |= MSC_SHOT_NOCONV;
                     sweeps_total += sweeps < 0 ? 40 : sweeps;
@@ -468,8 +472,42 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                 disc += kd[2];
                 if (kd[2] > 1e-12 * total && r == capb) status |= MSC_SHOT_CHI_CAP;
                 const double renorm = 1.0 / sqrt(kept);
-                // isometric factor: normalised vectors; centre factor: projection
-                if (dir) {
+                // isometric factor: normalised vectors; centre factor: the
+                // projection of theta on them.  When no rotation was needed the
+                // vectors are theta's own columns (rows), so the projection is
+                // sigma_c on the selected column (row) and zero elsewhere, up
+                // to overlaps below the orthogonality tolerance.
+                if (!rotated) {
+                    if (dir) {
+                        for (int idx = tid; idx < m * r; idx += NT) {
+                            const int row = idx / r, c = idx - row * r;
+                            const int v = s_sel[c];
+                            const double is = 1.0 / sqrt(s_nrm[v]);
+                            A.re[idx] = T(vre[(size_t)v * ld + row] * is);
+                            A.im[idx] = T(vim[(size_t)v * ld + row] * is);
+                        }
+                        for (int idx = tid; idx < r * n; idx += NT) {
+                            const int c = idx / n, col = idx - c * n;
+                            const int v = s_sel[c];
+                            B.re[idx] = T(col == v ? sqrt(s_nrm[v]) * renorm : 0.0);
+                            B.im[idx] = T(0);
+                        }
+                    } else {
+                        for (int idx = tid; idx < r * n; idx += NT) {
+                            const int c = idx / n, col = idx - c * n;
+                            const int v = s_sel[c];
+                            const double is = 1.0 / sqrt(s_nrm[v]);
+                            B.re[idx] = T(vre[(size_t)v * ld + col] * is);
+                            B.im[idx] = T(vim[(size_t)v * ld + col] * is);
+                        }
+                        for (int idx = tid; idx < m * r; idx += NT) {
+                            const int row = idx / r, c = idx - row * r;
+                            const int v = s_sel[c];
+                            A.re[idx] = T(row == v ? sqrt(s_nrm[v]) * renorm : 0.0);
+                            A.im[idx] = T(0);
+                        }
+                    }
+                } else if (dir) {
                     // A[k] (cl,2,r): U[row][c] = w_sel[c][row] / |w|
                     for (int idx = tid; idx < m * r; idx += NT) {
                         const int row = idx / r, c = idx - row * r;

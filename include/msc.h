@@ -69,8 +69,12 @@ typedef struct {
     int32_t words;        /* uint64 words per pre-screen signature           */
     int32_t calibrated;   /* expected outcomes known (msc_circuit_calibrate) */
     int64_t n_ops;        /* compiled MPS op stream length                   */
-    int64_t n_twosite;    /* two-site updates in one full shot               */
+    int64_t n_twosite;    /* two-site SVD updates in one full shot           */
     int64_t n_swaps;      /* of which routing SWAPs                          */
+    int64_t n_product_swaps; /* routing SWAPs of a qubit that is unentangled
+                             in every shot (a reset or measured ancilla):
+                             applied without an SVD                        */
+    int64_t n_moves;      /* one-site moves of the orthogonality centre      */
 } msc_circuit_info;
 
 typedef struct {

@@ -37,7 +37,8 @@ class CircuitInfo(C.Structure):
     _fields_ = [("n_qubits", C.c_int32), ("n_meas", C.c_int32), ("n_channels", C.c_int32),
                 ("n_decided", C.c_int32), ("seed_qubit", C.c_int32), ("target", C.c_int32),
                 ("words", C.c_int32), ("calibrated", C.c_int32), ("n_ops", C.c_int64),
-                ("n_twosite", C.c_int64), ("n_swaps", C.c_int64)]
+                ("n_twosite", C.c_int64), ("n_swaps", C.c_int64),
+                ("n_product_swaps", C.c_int64), ("n_moves", C.c_int64)]
 
 
 class SimOpts(C.Structure):

@@ -140,6 +140,8 @@ extern "C" int msc_circuit_get_info(const msc_circuit* c, msc_circuit_info* o) {
     o->n_ops = static_cast<int64_t>(c->ops.size());
     o->n_twosite = c->n_twosite;
     o->n_swaps = c->n_swaps;
+    o->n_product_swaps = c->n_product_swaps;
+    o->n_moves = c->n_moves;
     return MSC_OK;
 }
 
@@ -209,11 +211,9 @@ struct Layout {
 Layout make_layout(int n, int chi_max) {
     Layout L;
     L.cap.resize(n + 1);
-    for (int k = 0; k <= n; ++k) {
-        int e = std::min(k, n - k);
-        int64_t c = e >= 30 ? (1ll << 30) : (1ll << e);
-        L.cap[k] = static_cast<int32_t>(std::min<int64_t>(c, chi_max));
-    }
+    // every inner bond may reach chi_max: swapping an unentangled qubit
+    // moves a bond dimension to a neighbouring bond unchanged
+    for (int k = 0; k <= n; ++k) L.cap[k] = (k == 0 || k == n) ? 1 : chi_max;
     L.off.resize(n);
     L.half.resize(n);
     int64_t pos = 0;

@@ -199,14 +199,21 @@ struct LOp {          // logical op before centre scheduling
 
 struct Router {
     std::vector<int> site_of, qubit_at, home;
+    std::vector<char> product;   // qubit known to be unentangled in every shot
     std::vector<LOp> out;
-    int64_t swaps = 0;
+    int64_t swaps = 0, pswaps = 0;
 
+    static bool is_swap(const LOp& o) {
+        return (o.kind == OP_G2 && o.aux == G4_SWAP) || o.kind == OP_SWAPP;
+    }
     void swap_bond(int k) {
-        if (!out.empty() && out.back().kind == OP_G2 && out.back().a == k &&
-            out.back().aux == G4_SWAP) {
+        if (!out.empty() && is_swap(out.back()) && out.back().a == k) {
+            (out.back().kind == OP_SWAPP ? pswaps : swaps) -= 1;
             out.pop_back();          // SWAP . SWAP = identity
-            --swaps;
+        } else if (product[qubit_at[k + 1]] || product[qubit_at[k]]) {
+            // a product qubit swaps without an SVD
+            out.push_back({OP_SWAPP, k, product[qubit_at[k + 1]] ? 1 : 0, -1});
+            ++pswaps;
         } else {
             out.push_back({OP_G2, k, -1, G4_SWAP});
             ++swaps;
@@ -249,6 +256,7 @@ int compile_circuit(msc_circuit* c) {
     R.qubit_at = c->order;
     for (int s = 0; s < n; ++s) R.site_of[c->order[s]] = s;
     R.home = R.site_of;
+    R.product.assign(n, 1);      // |0...0>: every qubit starts unentangled
 
     // index of 2q gates for the mover choice
     std::vector<int> g2pos;
@@ -311,6 +319,11 @@ int compile_circuit(msc_circuit* c) {
             default:
                 break;
         }
+        // product status: a projective measurement or a reset leaves the
+        // qubit unentangled; a two-qubit gate may entangle both operands;
+        // one-qubit gates and Pauli faults keep the status
+        if (o.kind == IR_M || o.kind == IR_R) R.product[o.a] = 1;
+        if (o.kind == IR_G2) R.product[o.a] = R.product[o.b] = 0;
         if (o.kind == IR_M) last_meas_site_op[o.a] = 1;
         else if (o.kind == IR_G1 || o.kind == IR_G2) {
             last_meas_site_op[o.a] = -1;
@@ -329,23 +342,26 @@ int compile_circuit(msc_circuit* c) {
         next_need[i] = needs(R.out[i]) ? i : next_need[i + 1];
     c->ops.clear();
     c->n_twosite = 0;
+    c->n_moves = 0;
     int centre = 0;
     auto move_to = [&](int lo, int hi) {
         while (centre < lo) {
-            c->ops.push_back({OP_G2, centre, 1, G4_I});
+            c->ops.push_back({OP_MOVE, centre, 1, G4_I});
             ++centre;
-            ++c->n_twosite;
+            ++c->n_moves;
         }
         while (centre > hi) {
-            c->ops.push_back({OP_G2, centre - 1, 0, G4_I});
+            c->ops.push_back({OP_MOVE, centre - 1, 0, G4_I});
             --centre;
-            ++c->n_twosite;
+            ++c->n_moves;
         }
     };
     for (size_t i = 0; i < R.out.size(); ++i) {
         LOp o = R.out[i];
         if (!needs(o)) {
             c->ops.push_back({o.kind, o.a, o.b, o.aux});
+            // the unentangled qubit's partner takes over the centre
+            if (o.kind == OP_SWAPP && (centre == o.a || centre == o.a + 1)) centre = o.a + o.b;
             continue;
         }
         move_to(need_lo(o), need_hi(o));
@@ -366,6 +382,7 @@ int compile_circuit(msc_circuit* c) {
         }
     }
     c->n_swaps = R.swaps;
+    c->n_product_swaps = R.pswaps;
     return MSC_OK;
 }
 

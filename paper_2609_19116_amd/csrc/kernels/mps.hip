@@ -164,6 +164,80 @@ __device__ int hestenes(double* vre, double* vim, int nv, int len, int ld, doubl
     return -1;
 }
 
+// Squared norms of nv vectors (stride ld) into nrm.
+__device__ void vector_norms(const double* vre, const double* vim, int nv, int len, int ld,
+                             double* nrm) {
+    for (int v = threadIdx.x; v < nv; v += NT) {
+        double s = 0.0;
+        const double* xr = vre + (size_t)v * ld;
+        const double* xi = vim + (size_t)v * ld;
+        for (int e = 0; e < len; ++e) s += xr[e] * xr[e] + xi[e] * xi[e];
+        nrm[v] = s;
+    }
+    __syncthreads();
+}
+
+// One parallel pass over every pair of vectors whose squared norms exceed
+// floor2: true (block-uniform) if some pair overlaps by more than tol.
+__device__ bool not_orthogonal(const double* vre, const double* vim, int nv, int len, int ld,
+                               const double* nrm, double floor2, double tol) {
+    int bad = 0;
+    for (int t = threadIdx.x; t < nv * nv; t += NT) {
+        const int p = t / nv, q = t - p * nv;
+        if (q <= p) continue;
+        const double a = nrm[p], b = nrm[q];
+        if (!(a > floor2 && b > floor2)) continue;
+        const double* xr = vre + (size_t)p * ld;
+        const double* xi = vim + (size_t)p * ld;
+        const double* yr = vre + (size_t)q * ld;
+        const double* yi = vim + (size_t)q * ld;
+        double gr = 0.0, gim = 0.0;
+        for (int e = 0; e < len; ++e) {
+            gr += xr[e] * yr[e] + xi[e] * yi[e];
+            gim += xr[e] * yi[e] - xi[e] * yr[e];
+        }
+        if (gr * gr + gim * gim > tol * tol * a * b) bad = 1;
+    }
+    return __syncthreads_or(bad) != 0;
+}
+
+struct Kept {
+    int r;
+    double kept, dropped;
+};
+
+// Keep the vectors with sigma^2 > tau2 * sigma_0^2 (at most capb), ordered by
+// decreasing norm: sel[0..r) are their indices.
+__device__ Kept select_kept(const double* nrm, int nv, double tau2, int capb, int* sel,
+                            double* red) {
+    double mx = 0.0;
+    for (int v = threadIdx.x; v < nv; v += NT) mx = fmax(mx, nrm[v]);
+    mx = block_max(mx, red);
+    double kd[3] = {0.0, 0.0, 0.0};
+    for (int v = threadIdx.x; v < nv; v += NT) {
+        const double x = nrm[v];
+        int rank = 0;
+        for (int u = 0; u < nv; ++u) {
+            const double y = nrm[u];
+            rank += (y > x) || (y == x && u < v);
+        }
+        const bool keep = (x > tau2 * mx || rank == 0) && rank < capb;
+        if (keep) {
+            sel[rank] = v;
+            kd[0] += 1.0;
+            kd[1] += x;
+        } else {
+            kd[2] += x;
+        }
+    }
+    block_sum<3>(kd, red);
+    Kept k;
+    k.r = static_cast<int>(kd[0] + 0.5);
+    k.kept = kd[1];
+    k.dropped = kd[2];
+    return k;
+}
+
 template <typename T>
 struct SiteView {
     T* re;
@@ -227,6 +301,100 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
 
         for (int oi = 0; oi < P.n_ops && alive; ++oi) {
             const DevOp op = P.ops[oi];
+            bool twosite = op.kind == OP_G2;
+            int gate_id = op.aux;
+            if (op.kind == OP_MOVE) {
+                // ---- move the centre by one site with a one-site split; when
+                // the site's vectors are already orthogonal (they are after a
+                // split that left the centre there) this is a selection and a
+                // rescaling, else fall back to the two-site identity update
+                const int k = op.a, dir = op.b;
+                const int cl = s_chi[k], cm = s_chi[k + 1], cr = s_chi[k + 2];
+                SiteView<T> A = site(k), B = site(k + 1);
+                const int nv = cm, len = dir ? 2 * cl : 2 * cr, ld = len + 1;
+                bool fast = false;
+                if (nv <= SMAX && len <= SMAX) {
+                    for (int idx = tid; idx < nv * len; idx += NT) {
+                        const int v = idx / len, e = idx - v * len;
+                        const int at = dir ? e * cm + v : v * len + e;
+                        const SiteView<T>& S = dir ? A : B;
+                        s_vre[v * ld + e] = static_cast<double>(S.re[at]);
+                        s_vim[v * ld + e] = static_cast<double>(S.im[at]);
+                    }
+                    __syncthreads();
+                    vector_norms(s_vre, s_vim, nv, len, ld, s_nrm);
+                    double tsum[1] = {0.0};
+                    for (int v = tid; v < nv; v += NT) tsum[0] += s_nrm[v];
+                    block_sum<1>(tsum, s_red);
+                    const double tau2 = P.tau * P.tau;
+                    const double tol = sizeof(T) == sizeof(double)
+                                           ? static_cast<double>(len) * DBL_EPSILON
+                                           : 8.0 * static_cast<double>(FLT_EPSILON);
+                    if (!not_orthogonal(s_vre, s_vim, nv, len, ld, s_nrm, 1e-4 * tau2 * tsum[0], tol)) {
+                        const int capb = min(P.chi_max, P.cap[k + 1]);
+                        const Kept kp = select_kept(s_nrm, nv, tau2, capb, s_sel, s_red);
+                        const int r = kp.r;
+                        disc += kp.dropped;
+                        if (kp.dropped > 1e-12 * tsum[0] && r == capb) status |= MSC_SHOT_CHI_CAP;
+                        const double renorm = 1.0 / sqrt(kp.kept);
+                        double* tr_ = scr;
+                        double* ti_ = scr + (size_t)2 * cl * cm + (size_t)2 * cm * cr;
+                        if (dir) {
+                            // A[k] <- normalised columns; A[k+1] <- its selected rows
+                            for (int idx = tid; idx < 2 * cl * r; idx += NT) {
+                                const int e = idx / r, c = idx - e * r;
+                                const int v = s_sel[c];
+                                const double is = 1.0 / sqrt(s_nrm[v]);
+                                A.re[idx] = T(s_vre[v * ld + e] * is);
+                                A.im[idx] = T(s_vim[v * ld + e] * is);
+                            }
+                            const int w = 2 * cr;
+                            for (int idx = tid; idx < r * w; idx += NT) {
+                                const int c = idx / w, x = idx - c * w;
+                                const int v = s_sel[c];
+                                const double sc = sqrt(s_nrm[v]) * renorm;
+                                tr_[idx] = static_cast<double>(B.re[v * w + x]) * sc;
+                                ti_[idx] = static_cast<double>(B.im[v * w + x]) * sc;
+                            }
+                            __syncthreads();
+                            for (int idx = tid; idx < r * w; idx += NT) {
+                                B.re[idx] = T(tr_[idx]);
+                                B.im[idx] = T(ti_[idx]);
+                            }
+                        } else {
+                            // A[k+1] <- normalised rows; A[k] <- its selected columns
+                            const int w = 2 * cr;
+                            for (int idx = tid; idx < r * w; idx += NT) {
+                                const int c = idx / w, e = idx - c * w;
+                                const int v = s_sel[c];
+                                const double is = 1.0 / sqrt(s_nrm[v]);
+                                B.re[idx] = T(s_vre[v * ld + e] * is);
+                                B.im[idx] = T(s_vim[v * ld + e] * is);
+                            }
+                            for (int idx = tid; idx < 2 * cl * r; idx += NT) {
+                                const int row = idx / r, c = idx - row * r;
+                                const int v = s_sel[c];
+                                const double sc = sqrt(s_nrm[v]) * renorm;
+                                tr_[idx] = static_cast<double>(A.re[row * cm + v]) * sc;
+                                ti_[idx] = static_cast<double>(A.im[row * cm + v]) * sc;
+                            }
+                            __syncthreads();
+                            for (int idx = tid; idx < 2 * cl * r; idx += NT) {
+                                A.re[idx] = T(tr_[idx]);
+                                A.im[idx] = T(ti_[idx]);
+                            }
+                        }
+                        __syncthreads();
+                        if (tid == 0) s_chi[k + 1] = r;
+                        __syncthreads();
+                        fast = true;
+                    }
+                }
+                if (!fast) {
+                    twosite = true;
+                    gate_id = G4_I;
+                }
+            }
             if (op.kind == OP_G1 || op.kind == OP_FAULT || op.kind == OP_RESET) {
                 // ---- local 2x2 on one site (two for a two-qubit fault)
                 int g0 = -1, g1 = -1;
@@ -265,6 +433,99 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                     }
                     __syncthreads();
                 }
+            } else if (op.kind == OP_SWAPP) {
+                // ---- SWAP with a qubit that is unentangled in every shot:
+                // its tensor is psi (x) M, so the swap moves psi to the other
+                // site as psi (x) I and folds M into the neighbour (no SVD;
+                // canonical form is kept because psi is normalised)
+                const int k = op.a, side = op.b;
+                const int ps = k + side, os = k + 1 - side;
+                SiteView<T> Pv = site(ps), Ov = site(os);
+                const int pl = s_chi[ps], pr = s_chi[ps + 1];
+                double r4[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int idx = tid; idx < pl * pr; idx += NT) {
+                    const int a = idx / pr, b = idx - a * pr;
+                    const int i0 = (a * 2) * pr + b, i1 = i0 + pr;
+                    const double x0r = Pv.re[i0], x0i = Pv.im[i0], x1r = Pv.re[i1], x1i = Pv.im[i1];
+                    r4[0] += x0r * x0r + x0i * x0i;
+                    r4[1] += x1r * x1r + x1i * x1i;
+                    r4[2] += x0r * x1r + x0i * x1i;     // rho01 = x0 conj(x1)
+                    r4[3] += x0i * x1r - x0r * x1i;
+                }
+                block_sum<4>(r4, s_red);
+                const double tr = r4[0] + r4[1];
+                double p0r, p0i, p1r, p1i;               // psi, unit norm
+                if (r4[1] > r4[0]) {
+                    const double d = 1.0 / sqrt(r4[1] * tr);
+                    p0r = r4[2] * d;
+                    p0i = r4[3] * d;
+                    p1r = r4[1] * d;
+                    p1i = 0.0;
+                } else {
+                    const double d = 1.0 / sqrt(r4[0] * tr);
+                    p0r = r4[0] * d;
+                    p0i = 0.0;
+                    p1r = r4[2] * d;                     // rho10 = conj(rho01)
+                    p1i = -r4[3] * d;
+                }
+                // M = sum_i conj(psi_i) P[:, i, :]   (pl x pr, FP64)
+                const bool mlds = pl * pr <= SMAX * (SMAX + 1);
+                double* mr = mlds ? s_vre : scr;
+                double* mi = mlds ? s_vim : scr + (size_t)pl * pr;
+                for (int idx = tid; idx < pl * pr; idx += NT) {
+                    const int a = idx / pr, b = idx - a * pr;
+                    const int i0 = (a * 2) * pr + b, i1 = i0 + pr;
+                    const double x0r = Pv.re[i0], x0i = Pv.im[i0], x1r = Pv.re[i1], x1i = Pv.im[i1];
+                    mr[idx] = p0r * x0r + p0i * x0i + p1r * x1r + p1i * x1i;
+                    mi[idx] = p0r * x0i - p0i * x0r + p1r * x1i - p1i * x1r;
+                }
+                __syncthreads();
+                int newb;
+                if (side) {
+                    // product on k+1: new A[k+1] = A[k] M  (ol, 2, pr)
+                    const int ol = s_chi[k];
+                    for (int idx = tid; idx < ol * 2 * pr; idx += NT) {
+                        const int row = idx / pr, c = idx - row * pr;
+                        double xr = 0.0, xi = 0.0;
+                        for (int b = 0; b < pl; ++b) {
+                            const double ar = Ov.re[row * pl + b], ai = Ov.im[row * pl + b];
+                            const double br = mr[b * pr + c], bi = mi[b * pr + c];
+                            xr += ar * br - ai * bi;
+                            xi += ar * bi + ai * br;
+                        }
+                        Pv.re[idx] = T(xr);
+                        Pv.im[idx] = T(xi);
+                    }
+                    newb = ol;
+                } else {
+                    // product on k: new A[k] = M A[k+1]  (pl, 2, ocr)
+                    const int ocr = s_chi[k + 2];
+                    const int w = 2 * ocr;
+                    for (int idx = tid; idx < pl * w; idx += NT) {
+                        const int a = idx / w, rem = idx - a * w;
+                        double xr = 0.0, xi = 0.0;
+                        for (int b = 0; b < pr; ++b) {
+                            const double ar = mr[a * pr + b], ai = mi[a * pr + b];
+                            const double br = Ov.re[b * w + rem], bi = Ov.im[b * w + rem];
+                            xr += ar * br - ai * bi;
+                            xi += ar * bi + ai * br;
+                        }
+                        Pv.re[idx] = T(xr);
+                        Pv.im[idx] = T(xi);
+                    }
+                    newb = ocr;
+                }
+                __syncthreads();
+                // the unentangled qubit on the other site: psi (x) identity
+                for (int idx = tid; idx < newb * 2 * newb; idx += NT) {
+                    const int a = idx / (2 * newb), rem = idx - a * 2 * newb;
+                    const int i = rem / newb, a2 = rem - i * newb;
+                    const bool on = a == a2;
+                    Ov.re[idx] = T(on ? (i ? p1r : p0r) : 0.0);
+                    Ov.im[idx] = T(on ? (i ? p1i : p0i) : 0.0);
+                }
+                if (tid == 0) s_chi[k + 1] = newb;
+                __syncthreads();
             } else if (op.kind == OP_MEAS) {
                 const int k = op.a;
                 SiteView<T> v = site(k);
@@ -331,7 +592,8 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                                   (P.t1r * P.t1r + P.t1i * P.t1i) * r[1] +
                                   2.0 * (ctr * r[2] - cti * r[3])) / tr;
                 infid = fmax(0.0, 1.0 - f);
-            } else if (op.kind == OP_G2) {
+            }
+            if (twosite) {
                 // ---- two-site update on sites k, k+1
                 const int k = op.a, dir = op.b;
                 const int cl = s_chi[k], cm = s_chi[k + 1], cr = s_chi[k + 2];
@@ -347,7 +609,7 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                 if (tid < 4) {
                     // the 4x4 gates of the op stream are monomial: one
                     // nonzero per row, found here once per update
-                    const double* g = P.g4 + op.aux * 32 + tid * 8;
+                    const double* g = P.g4 + gate_id * 32 + tid * 8;
                     int src = 0;
                     for (int j = 1; j < 4; ++j)
                         if (fabs(g[2 * j]) + fabs(g[2 * j + 1]) > fabs(g[2 * src]) + fabs(g[2 * src + 1]))
@@ -404,73 +666,22 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                                        ? static_cast<double>(len) * DBL_EPSILON
                                        : 8.0 * static_cast<double>(FLT_EPSILON);
                 // squared norms, then one parallel pass over every pair: if
-                // all columns are already orthogonal (the common case) no
+                // all vectors are already orthogonal (the common case) no
                 // Jacobi sweep is needed at all
-                for (int v = tid; v < nv; v += NT) {
-                    double s = 0.0;
-                    const double* xr = vre + (size_t)v * ld;
-                    const double* xi = vim + (size_t)v * ld;
-                    for (int e = 0; e < len; ++e) s += xr[e] * xr[e] + xi[e] * xi[e];
-                    s_nrm[v] = s;
-                }
-                __syncthreads();
-                int nonorth = 0;   // block-uniform after the OR below
-                for (int t = tid; t < nv * nv; t += NT) {
-                    const int p = t / nv, q = t - p * nv;
-                    if (q <= p) continue;
-                    const double a = s_nrm[p], b = s_nrm[q];
-                    if (!(a > floor2 && b > floor2)) continue;
-                    const double* xr = vre + (size_t)p * ld;
-                    const double* xi = vim + (size_t)p * ld;
-                    const double* yr = vre + (size_t)q * ld;
-                    const double* yi = vim + (size_t)q * ld;
-                    double gr = 0.0, gim = 0.0;
-                    for (int e = 0; e < len; ++e) {
-                        gr += xr[e] * yr[e] + xi[e] * yi[e];
-                        gim += xr[e] * yi[e] - xi[e] * yr[e];
-                    }
-                    if (gr * gr + gim * gim > tol * tol * a * b) nonorth = 1;
-                }
-                const bool rotated = __syncthreads_or(nonorth) != 0;
+                vector_norms(vre, vim, nv, len, ld, s_nrm);
+                const bool rotated = not_orthogonal(vre, vim, nv, len, ld, s_nrm, floor2, tol);
                 if (rotated) {
                     const int sweeps = hestenes(vre, vim, nv, len, ld, floor2, tol, s_misc);
                     if (sweeps < 0) status |= MSC_SHOT_NOCONV;
                     sweeps_total += sweeps < 0 ? 40 : sweeps;
-                    for (int v = tid; v < nv; v += NT) {
-                        double s = 0.0;
-                        const double* xr = vre + (size_t)v * ld;
-                        const double* xi = vim + (size_t)v * ld;
-                        for (int e = 0; e < len; ++e) s += xr[e] * xr[e] + xi[e] * xi[e];
-                        s_nrm[v] = s;
-                    }
-                    __syncthreads();
+                    vector_norms(vre, vim, nv, len, ld, s_nrm);
                 }
-                double mx = 0.0;
-                for (int v = tid; v < nv; v += NT) mx = fmax(mx, s_nrm[v]);
-                mx = block_max(mx, s_red);
                 const int capb = min(P.chi_max, P.cap[k + 1]);
-                double kd[3] = {0.0, 0.0, 0.0};   // kept count, kept norm, dropped norm
-                for (int v = tid; v < nv; v += NT) {
-                    const double x = s_nrm[v];
-                    int rank = 0;
-                    for (int u2 = 0; u2 < nv; ++u2) {
-                        const double y = s_nrm[u2];
-                        rank += (y > x) || (y == x && u2 < v);
-                    }
-                    const bool keep = (x > tau2 * mx || rank == 0) && rank < capb;
-                    if (keep) {
-                        s_sel[rank] = v;
-                        kd[0] += 1.0;
-                        kd[1] += x;
-                    } else {
-                        kd[2] += x;
-                    }
-                }
-                block_sum<3>(kd, s_red);
-                const int r = static_cast<int>(kd[0] + 0.5);
-                const double kept = kd[1];
-                disc += kd[2];
-                if (kd[2] > 1e-12 * total && r == capb) status |= MSC_SHOT_CHI_CAP;
+                const Kept kp = select_kept(s_nrm, nv, tau2, capb, s_sel, s_red);
+                const int r = kp.r;
+                const double kept = kp.kept;
+                disc += kp.dropped;
+                if (kp.dropped > 1e-12 * total && r == capb) status |= MSC_SHOT_CHI_CAP;
                 const double renorm = 1.0 / sqrt(kept);
                 // isometric factor: normalised vectors; centre factor: the
                 // projection of theta on them.  When no rotation was needed the

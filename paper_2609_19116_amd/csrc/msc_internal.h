@@ -19,7 +19,11 @@ enum OpKind : int32_t {
                    // aux = channel index
     OP_MEAS = 3,   // a = site, aux = measurement index
     OP_RESET = 4,  // a = site: X^e with e the outcome last projected there
-    OP_FINAL = 5   // a = site of the seed qubit
+    OP_FINAL = 5,  // a = site of the seed qubit
+    OP_SWAPP = 6,  // a = k: SWAP of sites k, k+1 where the qubit on site
+                   // k + b (b = 0 or 1) is in a product state with the rest
+    OP_MOVE = 7    // a = k: move the orthogonality centre from k to k+1
+                   // (b = 1) or from k+1 to k (b = 0)
 };
 
 struct DevOp {
@@ -60,7 +64,7 @@ struct msc_circuit {
     std::vector<int32_t> chan_q0, chan_q1;
     // compiled MPS op stream
     std::vector<msc::DevOp> ops;
-    int64_t n_twosite = 0, n_swaps = 0;
+    int64_t n_twosite = 0, n_swaps = 0, n_product_swaps = 0, n_moves = 0;
     int final_site = 0;
     // expected outcomes
     std::vector<uint8_t> expected;

@@ -86,7 +86,7 @@ typedef struct {
     double tau_fail;      /* logical failure iff 1 - f > tau_fail (1e-4)     */
     int32_t n_slots;      /* persistent workgroups; 0 = auto                 */
     int32_t lds_width;    /* largest two-site SVD side kept in LDS: 32 or 64;
-                             larger sides use the slot's HBM scratch; 0 = 64 */
+                             larger sides use the slot's HBM scratch; 0 = 32 */
 } msc_sim_opts;
 
 typedef struct {

@@ -367,7 +367,7 @@ extern "C" int msc_simulate(msc_ctx* ctx, const msc_circuit* c, const msc_sim_op
     if (opts->lds_width != 0 && opts->lds_width != 32 && opts->lds_width != 64)
         return set_error(MSC_E_INVALID, "lds_width must be 0, 32 or 64");
     return run_shots(ctx, c, opts->precision, opts->chi_max, tau, tau_rej, tau_fail,
-                     opts->n_slots, opts->lds_width == 32 ? 32 : 64, n, n_shots, shot_off, chan, pauli, shot_idx, out, 0,
+                     opts->n_slots, opts->lds_width == 64 ? 64 : 32, n, n_shots, shot_off, chan, pauli, shot_idx, out, 0,
                      nullptr, nullptr, "simulate");
 }
 

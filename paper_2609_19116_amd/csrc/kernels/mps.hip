@@ -33,7 +33,7 @@
 namespace msc {
 namespace {
 
-constexpr int NT = 256;
+constexpr int NT = 128;
 constexpr int NW = NT / 64;
 constexpr int MAXV = 2 * kMaxChiKernel;   // vectors in a two-site SVD
 
@@ -81,87 +81,82 @@ __device__ __forceinline__ int player(int slot, int t, int nv) {
     return slot == 0 ? 0 : 1 + (slot - 1 + t) % (nv - 1);
 }
 
-// One-sided Jacobi on nv vectors of length len (planar FP64 at vre/vim,
-// vector v at v*ld, ld >= len padded against LDS bank conflicts).  Returns the number of sweeps used (or -1 when the
-// sweep limit was reached).
-__device__ int hestenes(double* vre, double* vim, int nv, int len, int ld, double floor2,
-                        double tol, int* sflag) {
+// One sweep of one-sided Jacobi (Hestenes) over nv vectors of length len
+// (planar FP64 at vre/vim, vector v at v*ld, ld >= len padded against LDS
+// bank conflicts): every pair (p, q) once, in round-robin order so that the
+// nv/2 pairs of a step are disjoint and rotate in parallel.  The 2x2 rotation
+// makes the pair orthogonal: with gamma = x^H y, zeta = (|y|^2 - |x|^2) /
+// (2|gamma|), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1+t^2),
+// s = c t and y~ = y conj(gamma)/|gamma|: x <- c x - s y~, y <- s x + c y~.
+__device__ void jacobi_sweep(double* vre, double* vim, int nv, int len, int ld, double floor2,
+                             double tol) {
     const int tid = threadIdx.x;
-    if (nv < 2) return 0;
+    if (nv < 2) return;
     const int npairs = nv / 2;
     int tpp = NT / npairs;
     if (tpp > 64) tpp = 64;
     if (tpp < 1) tpp = 1;
-    // round down to a power of two
     int t2 = 1;
     while (t2 * 2 <= tpp) t2 *= 2;
     tpp = t2;
     const int groups = NT / tpp;
     const int gl = tid % tpp;
     const int gi = tid / tpp;
-    const int nsteps = nv - 1;
-    for (int sweep = 0; sweep < 40; ++sweep) {
-        int rotated = 0;
-        for (int t = 0; t < nsteps; ++t) {
-            for (int pb = 0; pb < npairs; pb += groups) {
-                const int pi = pb + gi;
-                const bool active = pi < npairs;
-                int p = 0, q = 0;
-                double a = 0.0, b = 0.0, gr = 0.0, gim = 0.0;
-                if (active) {
-                    p = player(pi, t, nv);
-                    q = player(nv - 1 - pi, t, nv);
-                    const double* xr = vre + (size_t)p * ld;
-                    const double* xi = vim + (size_t)p * ld;
-                    const double* yr = vre + (size_t)q * ld;
-                    const double* yi = vim + (size_t)q * ld;
+    for (int t = 0; t < nv - 1; ++t) {
+        for (int pb = 0; pb < npairs; pb += groups) {
+            const int pi = pb + gi;
+            const bool active = pi < npairs;
+            int p = 0, q = 0;
+            double a = 0.0, b = 0.0, gr = 0.0, gim = 0.0;
+            if (active) {
+                p = player(pi, t, nv);
+                q = player(nv - 1 - pi, t, nv);
+                const double* xr = vre + (size_t)p * ld;
+                const double* xi = vim + (size_t)p * ld;
+                const double* yr = vre + (size_t)q * ld;
+                const double* yi = vim + (size_t)q * ld;
+                for (int e = gl; e < len; e += tpp) {
+                    double x0 = xr[e], x1 = xi[e], y0 = yr[e], y1 = yi[e];
+                    a += x0 * x0 + x1 * x1;
+                    b += y0 * y0 + y1 * y1;
+                    gr += x0 * y0 + x1 * y1;
+                    gim += x0 * y1 - x1 * y0;
+                }
+            }
+            for (int o = tpp >> 1; o > 0; o >>= 1) {
+                a += __shfl_xor(a, o);
+                b += __shfl_xor(b, o);
+                gr += __shfl_xor(gr, o);
+                gim += __shfl_xor(gim, o);
+            }
+            if (active) {
+                const double g = sqrt(gr * gr + gim * gim);
+                if (a > floor2 && b > floor2 && g > tol * sqrt(a * b)) {
+                    const double ig = 1.0 / g;
+                    const double zeta = 0.5 * (b - a) * ig;
+                    const double tt = (zeta >= 0.0 ? 1.0 : -1.0) /
+                                      (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    const double c = 1.0 / sqrt(1.0 + tt * tt);
+                    const double s = c * tt;
+                    const double pr = gr * ig, pim = gim * ig;
+                    double* xr = vre + (size_t)p * ld;
+                    double* xi = vim + (size_t)p * ld;
+                    double* yr = vre + (size_t)q * ld;
+                    double* yi = vim + (size_t)q * ld;
                     for (int e = gl; e < len; e += tpp) {
-                        double x0 = xr[e], x1 = xi[e], y0 = yr[e], y1 = yi[e];
-                        a += x0 * x0 + x1 * x1;
-                        b += y0 * y0 + y1 * y1;
-                        gr += x0 * y0 + x1 * y1;
-                        gim += x0 * y1 - x1 * y0;
-                    }
-                }
-                for (int o = tpp >> 1; o > 0; o >>= 1) {
-                    a += __shfl_xor(a, o);
-                    b += __shfl_xor(b, o);
-                    gr += __shfl_xor(gr, o);
-                    gim += __shfl_xor(gim, o);
-                }
-                if (active) {
-                    const double g = sqrt(gr * gr + gim * gim);
-                    if (a > floor2 && b > floor2 && g > tol * sqrt(a * b)) {
-                        rotated = 1;
-                        const double zeta = (b - a) / (2.0 * g);
-                        const double tt = (zeta >= 0.0 ? 1.0 : -1.0) /
-                                          (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                        const double c = 1.0 / sqrt(1.0 + tt * tt);
-                        const double s = c * tt;
-                        // y~ = y * conj(gamma)/|gamma|
-                        const double pr = gr / g, pim = gim / g;
-                        double* xr = vre + (size_t)p * ld;
-                        double* xi = vim + (size_t)p * ld;
-                        double* yr = vre + (size_t)q * ld;
-                        double* yi = vim + (size_t)q * ld;
-                        for (int e = gl; e < len; e += tpp) {
-                            double x0 = xr[e], x1 = xi[e];
-                            double y0 = yr[e] * pr + yi[e] * pim;
-                            double y1 = yi[e] * pr - yr[e] * pim;
-                            xr[e] = c * x0 - s * y0;
-                            xi[e] = c * x1 - s * y1;
-                            yr[e] = s * x0 + c * y0;
-                            yi[e] = s * x1 + c * y1;
-                        }
+                        double x0 = xr[e], x1 = xi[e];
+                        double y0 = yr[e] * pr + yi[e] * pim;
+                        double y1 = yi[e] * pr - yr[e] * pim;
+                        xr[e] = c * x0 - s * y0;
+                        xi[e] = c * x1 - s * y1;
+                        yr[e] = s * x0 + c * y0;
+                        yi[e] = s * x1 + c * y1;
                     }
                 }
             }
-            __syncthreads();
         }
-        if (!__syncthreads_or(rotated)) return sweep + 1;
+        __syncthreads();
     }
-    (void)sflag;
-    return -1;
 }
 
 // Squared norms of nv vectors (stride ld) into nrm.
@@ -253,7 +248,6 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
     __shared__ double s_nrm[MAXV];
     __shared__ int s_sel[MAXV];
     __shared__ double s_red[NW * 4];
-    __shared__ int s_misc[4];
     __shared__ double s_gph[8];
     __shared__ int s_gsrc[4];
 
@@ -671,10 +665,17 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                 vector_norms(vre, vim, nv, len, ld, s_nrm);
                 const bool rotated = not_orthogonal(vre, vim, nv, len, ld, s_nrm, floor2, tol);
                 if (rotated) {
-                    const int sweeps = hestenes(vre, vim, nv, len, ld, floor2, tol, s_misc);
-                    if (sweeps < 0) status |= MSC_SHOT_NOCONV;
-                    sweeps_total += sweeps < 0 ? 40 : sweeps;
-                    vector_norms(vre, vim, nv, len, ld, s_nrm);
+                    // sweep until the parallel check finds every pair orthogonal
+                    int sweeps = 0;
+                    bool again = true;
+                    while (again && sweeps < 40) {
+                        jacobi_sweep(vre, vim, nv, len, ld, floor2, tol);
+                        ++sweeps;
+                        vector_norms(vre, vim, nv, len, ld, s_nrm);
+                        again = not_orthogonal(vre, vim, nv, len, ld, s_nrm, floor2, tol);
+                    }
+                    if (again) status |= MSC_SHOT_NOCONV;
+                    sweeps_total += sweeps;
                 }
                 const int capb = min(P.chi_max, P.cap[k + 1]);
                 const Kept kp = select_kept(s_nrm, nv, tau2, capb, s_sel, s_red);

@@ -242,13 +242,14 @@ static int run_shots(msc_ctx* ctx, const msc_circuit* c, int precision, int chi_
     if (n_slots <= 0) n_slots = ctx->n_cu * mps_blocks_per_cu(precision, small);
     n_slots = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(n_slots, n)));
     const size_t tsize = precision == MSC_FP64 ? sizeof(double) : sizeof(float);
-    void *arena, *scratch, *dcap, *doff, *dhalf;
+    void *arena, *scratch, *dcap, *doff, *dhalf, *dperm;
     int rc;
     if ((rc = ctx_buf(ctx, "arena", static_cast<size_t>(n_slots) * L.slot_elems * tsize, &arena))) return rc;
     if ((rc = ctx_buf(ctx, "scratch", static_cast<size_t>(n_slots) * L.scratch * sizeof(double), &scratch))) return rc;
     if ((rc = ctx_buf(ctx, "cap", L.cap.size() * sizeof(int32_t), &dcap))) return rc;
     if ((rc = ctx_buf(ctx, "off", L.off.size() * sizeof(int64_t), &doff))) return rc;
     if ((rc = ctx_buf(ctx, "half", L.half.size() * sizeof(int64_t), &dhalf))) return rc;
+    if ((rc = ctx_buf(ctx, "perm", static_cast<size_t>(n) * sizeof(int64_t), &dperm))) return rc;
     MSC_HIP(hipMemcpyAsync(dcap, L.cap.data(), L.cap.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
     MSC_HIP(hipMemcpyAsync(doff, L.off.data(), L.off.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
     MSC_HIP(hipMemcpyAsync(dhalf, L.half.data(), L.half.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
@@ -262,6 +263,7 @@ static int run_shots(msc_ctx* ctx, const msc_circuit* c, int precision, int chi_
     a.chan = chan;
     a.pauli = pauli;
     a.shot_idx = shot_idx;
+    a.perm = static_cast<const int64_t*>(dperm);
     a.n_shots = n;
     a.n_csr = n_csr;
     a.expected = static_cast<const uint8_t*>(c->d_expected);
@@ -291,6 +293,7 @@ static int run_shots(msc_ctx* ctx, const msc_circuit* c, int precision, int chi_
     a.cal_p = cal_p;
     a.cal_e = cal_e;
     MSC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
+    MSC_HIP(launch_order(n, off, shot_idx, n_csr, static_cast<int64_t*>(dperm), ctx->stream));
     MSC_HIP(launch_mps(precision, small, a, n_slots, ctx->stream));
     MSC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
     MSC_HIP(hipStreamSynchronize(ctx->stream));

@@ -22,6 +22,7 @@ struct MpsArgs {
     const int32_t* chan;
     const uint8_t* pauli;
     const int64_t* shot_idx;   // optional subset
+    const int64_t* perm;       // processing order of the n_shots entries
     int64_t n_shots;           // shots to simulate (entries of shot_idx)
     int64_t n_csr;             // shots held by the CSR
     const uint8_t* expected;   // e_m per measurement
@@ -45,6 +46,9 @@ struct MpsArgs {
 
 // precision: MSC_FP64 or MSC_FP32; small: use the 32-wide LDS variant
 hipError_t launch_mps(int precision, bool small, const MpsArgs& a, int grid, hipStream_t s);
+// perm[0..n): stable order of the shots by fault count, fewest first
+hipError_t launch_order(int64_t n, const int64_t* shot_off, const int64_t* shot_idx, int64_t n_csr,
+                        int64_t* perm, hipStream_t s);
 // resident workgroups per CU of the chosen variant (sizes the persistent grid)
 int mps_blocks_per_cu(int precision, bool small);
 

@@ -263,7 +263,8 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
         return v;
     };
 
-    for (int64_t it = blockIdx.x; it < P.n_shots; it += gridDim.x) {
+    for (int64_t j = blockIdx.x; j < P.n_shots; j += gridDim.x) {
+        const int64_t it = P.perm ? P.perm[j] : j;
         const int64_t shot = P.shot_idx ? P.shot_idx[it] : it;
         if (shot < 0 || shot >= P.n_csr) {
             if (tid == 0) {
@@ -802,6 +803,48 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
     }
 }
 
+// Processing order of the shots: a stable counting sort by fault count
+// (capped at 15), fewest faults first.  Low-weight shots are the ones that
+// run to the end of the circuit (online screening stops the others early),
+// so starting them first keeps the tail of the persistent grid short.
+__global__ __launch_bounds__(1024) void order_kernel(int64_t n, const int64_t* shot_off,
+                                                     const int64_t* shot_idx, int64_t n_csr,
+                                                     int64_t* perm) {
+    __shared__ int64_t s_base;
+    __shared__ int s_wcnt[16];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) s_base = 0;
+    __syncthreads();
+    for (int key = 0; key < 16; ++key) {
+        for (int64_t base = 0; base < n; base += 1024) {
+            const int64_t j = base + tid;
+            bool hit = false;
+            if (j < n) {
+                const int64_t sh = shot_idx ? shot_idx[j] : j;
+                int c = 15;
+                if (sh >= 0 && sh < n_csr) {
+                    const int64_t f = shot_off[sh + 1] - shot_off[sh];
+                    c = f < 15 ? static_cast<int>(f) : 15;
+                }
+                hit = c == key;
+            }
+            const uint64_t m = __ballot(hit);
+            if (lane == 0) s_wcnt[w] = __popcll(m);
+            __syncthreads();
+            int64_t off = s_base;
+            for (int q = 0; q < w; ++q) off += s_wcnt[q];
+            if (hit) perm[off + __popcll(m & ((1ull << lane) - 1ull))] = j;
+            __syncthreads();
+            if (tid == 0) {
+                int64_t t = 0;
+                for (int q = 0; q < 16; ++q) t += s_wcnt[q];
+                s_base += t;
+            }
+            __syncthreads();
+        }
+    }
+}
+
 }  // namespace
 
 int mps_blocks_per_cu(int precision, bool small) {
@@ -818,6 +861,13 @@ int mps_blocks_per_cu(int precision, bool small) {
         return 1;
     }
     return b < 1 ? 1 : b;
+}
+
+hipError_t launch_order(int64_t n, const int64_t* shot_off, const int64_t* shot_idx, int64_t n_csr,
+                        int64_t* perm, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, s, n, shot_off, shot_idx, n_csr, perm);
+    return hipGetLastError();
 }
 
 hipError_t launch_mps(int precision, bool small, const MpsArgs& a, int grid, hipStream_t s) {

@@ -51,6 +51,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--lds-width", type=int, default=0)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only copy this many bytes device-to-device (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build simulates each shot on one "
@@ -59,6 +61,18 @@ def main() -> int:
         return 2
 
     import torch
+
+    if args.copy_probe:
+        # a plain copy of known size: the HBM counters of this kernel give the
+        # scale factor between counter bytes and real bytes
+        n_el = args.copy_probe // 4
+        src = torch.ones(n_el, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n_el * 4, "copy_bytes_written": n_el * 4}))
+        return 0
 
     import paper_2609_19116_amd as msc
     from workloads.circuits import config_circuit

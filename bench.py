@@ -171,7 +171,7 @@ def main() -> int:
                       "prescreen_mean": float(np.mean(screen_ms))},
         "roofline": {"bound": "alu", "kernel": "mps_kernel<float,64>",
                      "achieved": achieved, "peak": PEAK_FP64_VECTOR, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_VECTOR, "traffic": None,
+                     "frac": achieved / PEAK_FP64_VECTOR, "traffic": measured_traffic(),
                      "flops_per_launch": float(np.mean(flops))},
         "estimates": {str(p): e for p, e in zip([5e-4, 1e-3, 2e-3], est)},
     }
@@ -233,6 +233,25 @@ def main() -> int:
     ctx.close()
     print(json.dumps(result), flush=True)
     return 0
+
+
+def measured_traffic():
+    """HBM bytes per shot-kernel launch from the committed counter summary,
+    or None when the kernel source changed since the counters were taken."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2609_19116_amd", "csrc", "kernels", "mps.hip")
+    summ = os.path.join(ROOT, "profiles", "mps_kernel_c3_hbm_counters.md")
+    if not os.path.exists(summ):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    vals = {}
+    for line in open(summ):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_sha256_16"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_sha256_16") != sha:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(text: str, args, n: int) -> dict:

@@ -332,8 +332,12 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                         disc += kp.dropped;
                         if (kp.dropped > 1e-12 * tsum[0] && r == capb) status |= MSC_SHOT_CHI_CAP;
                         const double renorm = 1.0 / sqrt(kp.kept);
-                        double* tr_ = scr;
-                        double* ti_ = scr + (size_t)2 * cl * cm + (size_t)2 * cm * cr;
+                        // staging for the rescaled neighbour: LDS (free once the
+                        // normalised vectors are written) when it fits
+                        const int tmp_n = dir ? r * 2 * cr : 2 * cl * r;
+                        const bool tlds = tmp_n <= SMAX * (SMAX + 1);
+                        double* tr_ = tlds ? s_vre : scr;
+                        double* ti_ = tlds ? s_vim : scr + (size_t)2 * cl * cm + (size_t)2 * cm * cr;
                         if (dir) {
                             // A[k] <- normalised columns; A[k+1] <- its selected rows
                             for (int idx = tid; idx < 2 * cl * r; idx += NT) {
@@ -343,6 +347,7 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                                 A.re[idx] = T(s_vre[v * ld + e] * is);
                                 A.im[idx] = T(s_vim[v * ld + e] * is);
                             }
+                            __syncthreads();
                             const int w = 2 * cr;
                             for (int idx = tid; idx < r * w; idx += NT) {
                                 const int c = idx / w, x = idx - c * w;
@@ -366,6 +371,7 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                                 B.re[idx] = T(s_vre[v * ld + e] * is);
                                 B.im[idx] = T(s_vim[v * ld + e] * is);
                             }
+                            __syncthreads();
                             for (int idx = tid; idx < 2 * cl * r; idx += NT) {
                                 const int row = idx / r, c = idx - row * r;
                                 const int v = s_sel[c];
@@ -644,8 +650,6 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                     for (int o = 0; o < 4; ++o) {
                         const int i = o >> 1, j = o & 1;
                         const int row = a * 2 + i, col = j * cr + b;
-                        thr[(size_t)row * n + col] = tr_[o];
-                        thi[(size_t)row * n + col] = ti_[o];
                         const size_t vi = dir ? (size_t)col * ld + row : (size_t)row * ld + col;
                         vre[vi] = tr_[o];
                         vim[vi] = ti_[o];
@@ -666,6 +670,13 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                 vector_norms(vre, vim, nv, len, ld, s_nrm);
                 const bool rotated = not_orthogonal(vre, vim, nv, len, ld, s_nrm, floor2, tol);
                 if (rotated) {
+                    // keep theta for the projection (the vectors still hold it)
+                    for (int idx = tid; idx < m * n; idx += NT) {
+                        const int row = idx / n, col = idx - row * n;
+                        const size_t vi = dir ? (size_t)col * ld + row : (size_t)row * ld + col;
+                        thr[idx] = vre[vi];
+                        thi[idx] = vim[vi];
+                    }
                     // sweep until the parallel check finds every pair orthogonal
                     int sweeps = 0;
                     bool again = true;

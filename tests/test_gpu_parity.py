@@ -193,3 +193,31 @@ def test_twosite_contract(ctx, chi, batch, gate):
         ref = np.einsum("ijkl,aklb->aijb", Gc.reshape(2, 2, 2, 2), T).reshape(2 * chi, 2 * chi)
         err = np.linalg.norm(got[b] - ref) / np.linalg.norm(ref)
         assert err < 1e-5, err
+
+
+def test_full_size_c3_batch_sampled_against_oracle(ctx):
+    """The 49-qubit workload at full size in the launch configuration the
+    bench times (4096 shots, p = 1e-3, screen + FP32 batched simulation):
+    every survivor's record is checked for validity, and a stratified sample
+    of survivors against the oracle one by one."""
+    cc, c = _circuit(ctx, "c3")
+    n = 4096
+    csr = _lib_csr(c, 0x5EED0003, n, p=1e-3, first=n)
+    off, ch, pa = to_dev(*csr)
+    say("full-size c3: screen + simulate")
+    bits, idx, cnt = msc.prescreen(ctx, c, off, ch, pa)
+    res = results_numpy(msc.simulate(ctx, c, off, ch, pa, shot_idx=idx, precision=MSC_FP32))
+    assert cnt == len(res) > 1000
+    assert np.all((res["p_acc"] >= 0) & (res["p_acc"] <= 1 + 1e-6))
+    assert np.all(res["status"] & (msc.SHOT_DONE | msc.SHOT_REJECTED))
+    assert not np.any(res["status"] & (msc.SHOT_CHI_CAP | msc.SHOT_NOCONV))
+    assert np.all(res["chi_peak"] <= 256)
+    circ, ocsr = oracle_csr(cc.text, 0x5EED0003, n, p=1e-3, first=n)
+    assert _same_csr(csr, ocsr)
+    surv = idx.cpu().numpy()
+    w = np.diff(csr[0])[surv]
+    pick = []
+    for cond in (res["p_acc"] == 0, (res["p_acc"] > 0) & (w == 0), (res["p_acc"] > 0) & (w > 0)):
+        pick += list(np.nonzero(cond)[0][:6])
+    ref = oracle_results(circ, ocsr, idx=[int(surv[i]) for i in pick])
+    _compare(res[pick], ref, TOL[MSC_FP32])

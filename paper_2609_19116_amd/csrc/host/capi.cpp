@@ -226,7 +226,8 @@ Layout make_layout(int n, int chi_max) {
     }
     L.slot_elems = (pos + 63) / 64 * 64;
     int64_t s = 2ll * chi_max;
-    L.scratch = 4 * s * s + 4 * s + 64;   // theta copy + padded vectors
+    // theta copy + padded vectors, then per-vector arrays (4 x 512 doubles)
+    L.scratch = 4 * s * s + 4 * s + 64 + 4 * 2 * kMaxChiKernel;
     return L;
 }
 

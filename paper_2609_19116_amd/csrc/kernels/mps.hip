@@ -81,18 +81,20 @@ __device__ __forceinline__ int player(int slot, int t, int nv) {
     return slot == 0 ? 0 : 1 + (slot - 1 + t) % (nv - 1);
 }
 
-// One sweep of one-sided Jacobi (Hestenes) over nv vectors of length len
-// (planar FP64 at vre/vim, vector v at v*ld, ld >= len padded against LDS
-// bank conflicts): every pair (p, q) once, in round-robin order so that the
-// nv/2 pairs of a step are disjoint and rotate in parallel.  The 2x2 rotation
+// One sweep of one-sided Jacobi (Hestenes) over the nv vectors list[0..nv)
+// of length len (planar FP64 at vre/vim, vector v at v*ld, ld >= len padded
+// against LDS bank conflicts): every pair (p, q) once, in round-robin order
+// so that the pairs of a step are disjoint and rotate in parallel (an odd
+// count gets a dummy slot).  The 2x2 rotation
 // makes the pair orthogonal: with gamma = x^H y, zeta = (|y|^2 - |x|^2) /
 // (2|gamma|), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1+t^2),
 // s = c t and y~ = y conj(gamma)/|gamma|: x <- c x - s y~, y <- s x + c y~.
-__device__ void jacobi_sweep(double* vre, double* vim, int nv, int len, int ld, double floor2,
-                             double tol) {
+__device__ void jacobi_sweep(double* vre, double* vim, const int* list, int nv, int len, int ld,
+                             double floor2, double tol) {
     const int tid = threadIdx.x;
     if (nv < 2) return;
-    const int npairs = nv / 2;
+    const int nve = nv + (nv & 1);   // the slot nv (if odd) is a dummy
+    const int npairs = nve / 2;
     int tpp = NT / npairs;
     if (tpp > 64) tpp = 64;
     if (tpp < 1) tpp = 1;
@@ -102,15 +104,17 @@ __device__ void jacobi_sweep(double* vre, double* vim, int nv, int len, int ld, 
     const int groups = NT / tpp;
     const int gl = tid % tpp;
     const int gi = tid / tpp;
-    for (int t = 0; t < nv - 1; ++t) {
+    for (int t = 0; t < nve - 1; ++t) {
         for (int pb = 0; pb < npairs; pb += groups) {
             const int pi = pb + gi;
-            const bool active = pi < npairs;
+            const int sp = pi < npairs ? player(pi, t, nve) : 0;
+            const int sq = pi < npairs ? player(nve - 1 - pi, t, nve) : 0;
+            const bool active = pi < npairs && sp < nv && sq < nv;
             int p = 0, q = 0;
             double a = 0.0, b = 0.0, gr = 0.0, gim = 0.0;
             if (active) {
-                p = player(pi, t, nv);
-                q = player(nv - 1 - pi, t, nv);
+                p = list[sp];
+                q = list[sq];
                 const double* xr = vre + (size_t)p * ld;
                 const double* xi = vim + (size_t)p * ld;
                 const double* yr = vre + (size_t)q * ld;
@@ -173,13 +177,19 @@ __device__ void vector_norms(const double* vre, const double* vim, int nv, int l
 }
 
 // One parallel pass over every pair of vectors whose squared norms exceed
-// floor2: true (block-uniform) if some pair overlaps by more than tol.
+// floor2 (only pairs with a vector flagged in `only`, if given): marks in
+// `bad` every vector of a pair that overlaps by more than tol and returns
+// true (block-uniform) if there is one.
 __device__ bool not_orthogonal(const double* vre, const double* vim, int nv, int len, int ld,
-                               const double* nrm, double floor2, double tol) {
-    int bad = 0;
+                               const double* nrm, double floor2, double tol, int* bad,
+                               const int* only) {
+    for (int v = threadIdx.x; v < nv; v += NT) bad[v] = 0;
+    __syncthreads();
+    int any = 0;
     for (int t = threadIdx.x; t < nv * nv; t += NT) {
         const int p = t / nv, q = t - p * nv;
         if (q <= p) continue;
+        if (only && !(only[p] | only[q])) continue;
         const double a = nrm[p], b = nrm[q];
         if (!(a > floor2 && b > floor2)) continue;
         const double* xr = vre + (size_t)p * ld;
@@ -191,9 +201,33 @@ __device__ bool not_orthogonal(const double* vre, const double* vim, int nv, int
             gr += xr[e] * yr[e] + xi[e] * yi[e];
             gim += xr[e] * yi[e] - xi[e] * yr[e];
         }
-        if (gr * gr + gim * gim > tol * tol * a * b) bad = 1;
+        if (gr * gr + gim * gim > tol * tol * a * b) {
+            any = 1;
+            bad[p] = 1;   // benign race: every writer stores 1
+            bad[q] = 1;
+        }
     }
-    return __syncthreads_or(bad) != 0;
+    return __syncthreads_or(any) != 0;
+}
+
+// Compacts the flagged vectors into list (ascending); returns their count.
+__device__ int flagged_list(const int* flag, int nv, int* list, int* red) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    int base = 0;
+    for (int b0 = 0; b0 < nv; b0 += NT) {
+        const int v = b0 + tid;
+        const bool f = v < nv && flag[v];
+        const uint64_t m = __ballot(f);
+        __syncthreads();
+        if (lane == 0) red[w] = __popcll(m);
+        __syncthreads();
+        int off = base;
+        for (int q = 0; q < w; ++q) off += red[q];
+        if (f) list[off + __popcll(m & ((1ull << lane) - 1ull))] = v;
+        for (int q = 0; q < NW; ++q) base += red[q];
+    }
+    __syncthreads();
+    return base;
 }
 
 struct Kept {
@@ -245,8 +279,11 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
     __shared__ int s_laste[kMaxSites];
     __shared__ double s_vre[SMAX * (SMAX + 1)];
     __shared__ double s_vim[SMAX * (SMAX + 1)];
-    __shared__ double s_nrm[MAXV];
-    __shared__ int s_sel[MAXV];
+    __shared__ double s_nrm[SMAX];
+    __shared__ int s_sel[SMAX];
+    __shared__ int s_bad[SMAX];
+    __shared__ int s_list[SMAX];
+    __shared__ int s_ired[NW];
     __shared__ double s_red[NW * 4];
     __shared__ double s_gph[8];
     __shared__ int s_gsrc[4];
@@ -255,6 +292,11 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
     const int N = P.n_sites;
     T* slot_base = static_cast<T*>(P.arena) + (size_t)blockIdx.x * P.slot_stride;
     double* scr = P.scratch + (size_t)blockIdx.x * P.scratch_stride;
+    // per-vector arrays of SVDs too large for LDS, at the end of the slot's scratch
+    double* g_nrm = scr + P.scratch_stride - 4 * MAXV;
+    int* g_sel = reinterpret_cast<int*>(g_nrm + MAXV);
+    int* g_bad = g_sel + MAXV;
+    int* g_list = g_bad + MAXV;
 
     auto site = [&](int k) {
         SiteView<T> v;
@@ -325,7 +367,8 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                     const double tol = sizeof(T) == sizeof(double)
                                            ? static_cast<double>(len) * DBL_EPSILON
                                            : 8.0 * static_cast<double>(FLT_EPSILON);
-                    if (!not_orthogonal(s_vre, s_vim, nv, len, ld, s_nrm, 1e-4 * tau2 * tsum[0], tol)) {
+                    if (!not_orthogonal(s_vre, s_vim, nv, len, ld, s_nrm, 1e-4 * tau2 * tsum[0], tol,
+                                        s_bad, nullptr)) {
                         const int capb = min(P.chi_max, P.cap[k + 1]);
                         const Kept kp = select_kept(s_nrm, nv, tau2, capb, s_sel, s_red);
                         const int r = kp.r;
@@ -607,6 +650,10 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                 const bool lds = nv <= SMAX && len <= SMAX;
                 double* vre = lds ? s_vre : scr + 2 * (size_t)m * n;
                 double* vim = lds ? s_vim : vre + (size_t)nv * ld;
+                double* nrm = lds ? s_nrm : g_nrm;
+                int* sel = lds ? s_sel : g_sel;
+                int* bad = lds ? s_bad : g_bad;
+                int* list = lds ? s_list : g_list;
                 if (tid < 4) {
                     // the 4x4 gates of the op stream are monomial: one
                     // nonzero per row, found here once per update
@@ -667,8 +714,9 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                 // squared norms, then one parallel pass over every pair: if
                 // all vectors are already orthogonal (the common case) no
                 // Jacobi sweep is needed at all
-                vector_norms(vre, vim, nv, len, ld, s_nrm);
-                const bool rotated = not_orthogonal(vre, vim, nv, len, ld, s_nrm, floor2, tol);
+                vector_norms(vre, vim, nv, len, ld, nrm);
+                const bool rotated =
+                    not_orthogonal(vre, vim, nv, len, ld, nrm, floor2, tol, bad, nullptr);
                 if (rotated) {
                     // keep theta for the projection (the vectors still hold it)
                     for (int idx = tid; idx < m * n; idx += NT) {
@@ -678,19 +726,24 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                         thi[idx] = vim[vi];
                     }
                     // sweep until the parallel check finds every pair orthogonal
+                    // only vectors of an overlapping pair need rotating: the
+                    // others stay orthogonal to every combination of them
                     int sweeps = 0;
                     bool again = true;
                     while (again && sweeps < 40) {
-                        jacobi_sweep(vre, vim, nv, len, ld, floor2, tol);
+                        const int nb = flagged_list(bad, nv, list, s_ired);
+                        jacobi_sweep(vre, vim, list, nb, len, ld, floor2, tol);
                         ++sweeps;
-                        vector_norms(vre, vim, nv, len, ld, s_nrm);
-                        again = not_orthogonal(vre, vim, nv, len, ld, s_nrm, floor2, tol);
+                        vector_norms(vre, vim, nv, len, ld, nrm);
+                        for (int v = tid; v < nv; v += NT) sel[v] = bad[v];
+                        __syncthreads();
+                        again = not_orthogonal(vre, vim, nv, len, ld, nrm, floor2, tol, bad, sel);
                     }
                     if (again) status |= MSC_SHOT_NOCONV;
                     sweeps_total += sweeps;
                 }
                 const int capb = min(P.chi_max, P.cap[k + 1]);
-                const Kept kp = select_kept(s_nrm, nv, tau2, capb, s_sel, s_red);
+                const Kept kp = select_kept(nrm, nv, tau2, capb, sel, s_red);
                 const int r = kp.r;
                 const double kept = kp.kept;
                 disc += kp.dropped;
@@ -705,29 +758,29 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                     if (dir) {
                         for (int idx = tid; idx < m * r; idx += NT) {
                             const int row = idx / r, c = idx - row * r;
-                            const int v = s_sel[c];
-                            const double is = 1.0 / sqrt(s_nrm[v]);
+                            const int v = sel[c];
+                            const double is = 1.0 / sqrt(nrm[v]);
                             A.re[idx] = T(vre[(size_t)v * ld + row] * is);
                             A.im[idx] = T(vim[(size_t)v * ld + row] * is);
                         }
                         for (int idx = tid; idx < r * n; idx += NT) {
                             const int c = idx / n, col = idx - c * n;
-                            const int v = s_sel[c];
-                            B.re[idx] = T(col == v ? sqrt(s_nrm[v]) * renorm : 0.0);
+                            const int v = sel[c];
+                            B.re[idx] = T(col == v ? sqrt(nrm[v]) * renorm : 0.0);
                             B.im[idx] = T(0);
                         }
                     } else {
                         for (int idx = tid; idx < r * n; idx += NT) {
                             const int c = idx / n, col = idx - c * n;
-                            const int v = s_sel[c];
-                            const double is = 1.0 / sqrt(s_nrm[v]);
+                            const int v = sel[c];
+                            const double is = 1.0 / sqrt(nrm[v]);
                             B.re[idx] = T(vre[(size_t)v * ld + col] * is);
                             B.im[idx] = T(vim[(size_t)v * ld + col] * is);
                         }
                         for (int idx = tid; idx < m * r; idx += NT) {
                             const int row = idx / r, c = idx - row * r;
-                            const int v = s_sel[c];
-                            A.re[idx] = T(row == v ? sqrt(s_nrm[v]) * renorm : 0.0);
+                            const int v = sel[c];
+                            A.re[idx] = T(row == v ? sqrt(nrm[v]) * renorm : 0.0);
                             A.im[idx] = T(0);
                         }
                     }
@@ -735,16 +788,16 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                     // A[k] (cl,2,r): U[row][c] = w_sel[c][row] / |w|
                     for (int idx = tid; idx < m * r; idx += NT) {
                         const int row = idx / r, c = idx - row * r;
-                        const int v = s_sel[c];
-                        const double is = 1.0 / sqrt(s_nrm[v]);
+                        const int v = sel[c];
+                        const double is = 1.0 / sqrt(nrm[v]);
                         A.re[idx] = T(vre[(size_t)v * ld + row] * is);
                         A.im[idx] = T(vim[(size_t)v * ld + row] * is);
                     }
                     // A[k+1] (r,2,cr): R[c][col] = sum_row conj(U[row][c]) theta[row][col]
                     for (int idx = tid; idx < r * n; idx += NT) {
                         const int c = idx / n, col = idx - c * n;
-                        const int v = s_sel[c];
-                        const double is = renorm / sqrt(s_nrm[v]);
+                        const int v = sel[c];
+                        const double is = renorm / sqrt(nrm[v]);
                         const double* ur = vre + (size_t)v * ld;
                         const double* ui = vim + (size_t)v * ld;
                         double xr = 0.0, xi = 0.0;
@@ -761,16 +814,16 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                     // A[k+1] (r,2,cr): V[c][col] = w_sel[c][col] / |w|
                     for (int idx = tid; idx < r * n; idx += NT) {
                         const int c = idx / n, col = idx - c * n;
-                        const int v = s_sel[c];
-                        const double is = 1.0 / sqrt(s_nrm[v]);
+                        const int v = sel[c];
+                        const double is = 1.0 / sqrt(nrm[v]);
                         B.re[idx] = T(vre[(size_t)v * ld + col] * is);
                         B.im[idx] = T(vim[(size_t)v * ld + col] * is);
                     }
                     // A[k] (cl,2,r): L[row][c] = sum_col theta[row][col] conj(V[c][col])
                     for (int idx = tid; idx < m * r; idx += NT) {
                         const int row = idx / r, c = idx - row * r;
-                        const int v = s_sel[c];
-                        const double is = renorm / sqrt(s_nrm[v]);
+                        const int v = sel[c];
+                        const double is = renorm / sqrt(nrm[v]);
                         const double* wr = vre + (size_t)v * ld;
                         const double* wi = vim + (size_t)v * ld;
                         double xr = 0.0, xi = 0.0;

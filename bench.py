@@ -28,6 +28,7 @@ if ROOT not in sys.path:
 
 PEAK_FP64_VECTOR = 78.6     # TFLOP/s, MI355X
 PEAK_FP32_MFMA = 157.3      # TFLOP/s, MI355X dense
+PEAK_BF16_MFMA = 2500.0     # TFLOP/s, MI355X dense (BF16x3 does 3 products per product)
 SEED = 0x5EED0003
 METRIC = "MPS shots/sec at chi=256, batched mixed-precision vs plain FP64, same GPU"
 
@@ -169,7 +170,8 @@ def main() -> int:
         "jacobi_sweeps_per_update": sweeps / max(1, sum(n2q)),
         "kernel_ms": {"simulate_mean": float(np.mean(sim_ms)),
                       "prescreen_mean": float(np.mean(screen_ms))},
-        "roofline": {"bound": "alu", "kernel": "mps_kernel<float,64>",
+        "roofline": {"bound": "alu",
+                     "kernel": f"mps_kernel<float,{64 if args.lds_width == 64 else 32}>",
                      "achieved": achieved, "peak": PEAK_FP64_VECTOR, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_VECTOR, "traffic": measured_traffic(),
                      "flops_per_launch": float(np.mean(flops))},
@@ -207,25 +209,31 @@ def main() -> int:
                                   "max_abs_infid": float(df.max()),
                                   "fail_mismatch": int((res32["fail"] != out64["fail"]).sum()),
                                   "shots": int(len(dp))}
-        # fixed-shape chi = 256 two-site contraction on MFMA
+        # fixed-shape chi = 256 two-site contraction on MFMA, FP32 and BF16x3
         from workloads.tensors import random_twosite
         chi, batch = 256, 512
         A, B, G, _, _, _ = random_twosite(chi, 1, 0x5EED0103)
         dA = torch.from_numpy(A).cuda().repeat(batch, 1, 1, 1).contiguous()
         dB = torch.from_numpy(B).cuda().repeat(batch, 1, 1, 1).contiguous()
         dG = torch.from_numpy(G).cuda()
-        th = torch.empty(batch * 2 * (2 * chi) ** 2, dtype=torch.float32, device="cuda")
-        msc.twosite_contract(ctx, chi, batch, dA, dB, dG, th)
-        ms = []
-        for _ in range(5):
-            msc.twosite_contract(ctx, chi, batch, dA, dB, dG, th)
-            ms.append(ctx.last_kernel_ms("twosite"))
-        fl = batch * (32.0 * chi ** 3 + 128.0 * chi ** 2)
-        tf = fl / (np.mean(ms) * 1e-3) / 1e12
-        result["contraction_chi256"] = {"kernel": "twosite_kernel", "batch": batch,
-                                        "ms": float(np.mean(ms)), "achieved": tf,
-                                        "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
-                                        "frac": tf / PEAK_FP32_MFMA}
+        outs = {}
+        for name, prec, peak in (("fp32", msc.MSC_FP32, PEAK_FP32_MFMA),
+                                 ("bf16x3", msc.MSC_BF16X3, PEAK_BF16_MFMA / 3.0)):
+            th = torch.empty(batch * 2 * (2 * chi) ** 2, dtype=torch.float32, device="cuda")
+            msc.twosite_contract(ctx, chi, batch, dA, dB, dG, th, precision=prec)
+            ms = []
+            for _ in range(5):
+                msc.twosite_contract(ctx, chi, batch, dA, dB, dG, th, precision=prec)
+                ms.append(ctx.last_kernel_ms("twosite"))
+            fl = batch * (32.0 * chi ** 3 + 128.0 * chi ** 2)
+            tf = fl / (np.mean(ms) * 1e-3) / 1e12
+            outs[name] = th[: 2 * (2 * chi) ** 2].double().cpu().numpy()
+            result["contraction_chi256_" + name] = {
+                "kernel": "twosite_kernel" if name == "fp32" else "twosite_bf16x3_kernel",
+                "batch": batch, "ms": float(np.mean(ms)), "achieved": tf, "peak": peak,
+                "unit": "TFLOP/s", "frac": tf / peak}
+        rel = float(np.linalg.norm(outs["bf16x3"] - outs["fp32"]) / np.linalg.norm(outs["fp32"]))
+        result["contraction_chi256_bf16x3"]["rel_error_vs_fp32"] = rel
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(cc.text, args, n)

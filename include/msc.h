@@ -44,8 +44,11 @@ enum msc_status {
 
 enum msc_precision {
     MSC_FP64 = 0,   /* complex128 tensors and contractions                    */
-    MSC_FP32 = 1    /* complex64 tensors, FP32 contractions, FP64 truncation,
+    MSC_FP32 = 1,   /* complex64 tensors, FP32 contractions, FP64 truncation,
                        norms and probabilities                                */
+    MSC_BF16X3 = 2  /* two-site contraction only: FP32 inputs split into
+                       bf16 hi + lo, three bf16 products per real product,
+                       FP32 accumulation (relative error ~1e-5)               */
 };
 
 /* bits of msc_shot_result.status */
@@ -211,16 +214,17 @@ int msc_simulate(msc_ctx* ctx, const msc_circuit* c, const msc_sim_opts* opts,
 /* Two-site contraction on MFMA (Section 3.1), standalone.                 */
 
 /* theta_b = G * (A_b . B_b) for `batch` independent two-site updates with
-   chi_l = chi_m = chi_r = chi, FP32 split complex on MFMA with FP32
-   accumulation.  Layouts (device, float): A and B are [batch][2 (re,im)]
+   chi_l = chi_m = chi_r = chi on MFMA, FP32 split complex with FP32
+   accumulation (precision MSC_FP32) or BF16x3 split precision
+   (MSC_BF16X3).  Layouts (device, float): A and B are [batch][2 (re,im)]
    [chi*2][chi] and [batch][2][chi][2*chi] (row-major, rows (a,i) resp. c,
    columns c resp. (j,b)); gate (device, 32 floats) is the 4x4 complex gate
    in row-major (re,im) pairs over |i j>; theta is [batch][2][2*chi][2*chi]
    with rows (a,i) and columns (j,b).  chi must be a multiple of 64 in
    [64, 1024].                                                             */
-int msc_twosite_contract(msc_ctx* ctx, int32_t chi, int32_t batch,
-                         const float* A, const float* B, const float* gate,
-                         float* theta);
+int msc_twosite_contract(msc_ctx* ctx, int32_t precision, int32_t chi,
+                         int32_t batch, const float* A, const float* B,
+                         const float* gate, float* theta);
 
 /* ---------------------------------------------------------------------- */
 /* Re-weighting (Section 4.1, Eq. (reweight); Appendix "Systematics").     */

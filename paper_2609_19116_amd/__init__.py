@@ -12,13 +12,13 @@ import ctypes as C
 
 import numpy as np
 
-from ._lib import (MSC_FP32, MSC_FP64, SHOT_CHI_CAP, SHOT_DONE, SHOT_DTYPE,  # noqa: F401
+from ._lib import (MSC_BF16X3, MSC_FP32, MSC_FP64, SHOT_CHI_CAP, SHOT_DONE, SHOT_DTYPE,  # noqa: F401
                    SHOT_NOCONV, SHOT_REJECTED, CircuitInfo, Estimate, MscError, SimOpts,
                    _check, _ptr, lib)
 
 __all__ = ["Ctx", "Circuit", "sample_faults", "prescreen", "simulate", "reweight",
            "twosite_contract", "prescreen_tables", "version", "MscError",
-           "MSC_FP64", "MSC_FP32", "SHOT_DTYPE"]
+           "MSC_FP64", "MSC_FP32", "MSC_BF16X3", "SHOT_DTYPE"]
 
 
 def version() -> str:
@@ -145,8 +145,9 @@ def results_numpy(out) -> np.ndarray:
     return np.frombuffer(out.cpu().numpy().tobytes(), dtype=SHOT_DTYPE)
 
 
-def twosite_contract(ctx: Ctx, chi: int, batch: int, A, B, gate, theta) -> None:
-    _check(lib().msc_twosite_contract(ctx.h, chi, batch, _ptr(A), _ptr(B), _ptr(gate),
+def twosite_contract(ctx: Ctx, chi: int, batch: int, A, B, gate, theta,
+                     precision: int = MSC_FP32) -> None:
+    _check(lib().msc_twosite_contract(ctx.h, precision, chi, batch, _ptr(A), _ptr(B), _ptr(gate),
                                       _ptr(theta)))
 
 

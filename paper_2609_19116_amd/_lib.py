@@ -26,6 +26,7 @@ MSC_E_STATE = -7
 
 MSC_FP64 = 0
 MSC_FP32 = 1
+MSC_BF16X3 = 2
 
 SHOT_DONE = 1
 SHOT_REJECTED = 2
@@ -85,7 +86,7 @@ _SIGS = {
     "msc_prescreen": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P, _P, _P, C.POINTER(C.c_int64)]),
     "msc_simulate": (C.c_int, [_P, _P, C.POINTER(SimOpts), C.c_int64, _P, _P, _P, _P,
                                C.c_int64, _P]),
-    "msc_twosite_contract": (C.c_int, [_P, C.c_int32, C.c_int32, _P, _P, _P, _P]),
+    "msc_twosite_contract": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, _P]),
     "msc_reweight": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, _P, C.c_int32, _P]),
 }
 

@@ -407,14 +407,16 @@ extern "C" int msc_prescreen(msc_ctx* ctx, const msc_circuit* c, int64_t n_shots
     return MSC_OK;
 }
 
-extern "C" int msc_twosite_contract(msc_ctx* ctx, int32_t chi, int32_t batch, const float* A,
-                                    const float* B, const float* gate, float* theta) {
+extern "C" int msc_twosite_contract(msc_ctx* ctx, int32_t precision, int32_t chi, int32_t batch,
+                                    const float* A, const float* B, const float* gate, float* theta) {
     if (!ctx || !A || !B || !gate || !theta) return set_error(MSC_E_INVALID, "null argument");
     if (chi < 64 || chi > 1024 || chi % 64 != 0 || batch < 1 || batch > 65535)
         return set_error(MSC_E_INVALID, "chi must be a multiple of 64 in [64, 1024], batch in [1, 65535]");
     MSC_HIP(hipSetDevice(ctx->device));
     MSC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
-    MSC_HIP(launch_twosite(chi, batch, A, B, gate, theta, ctx->stream));
+    if (precision != MSC_FP32 && precision != MSC_BF16X3)
+        return set_error(MSC_E_INVALID, "twosite precision must be MSC_FP32 or MSC_BF16X3");
+    MSC_HIP(launch_twosite(precision, chi, batch, A, B, gate, theta, ctx->stream));
     MSC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
     MSC_HIP(hipStreamSynchronize(ctx->stream));
     float ms = 0.f;

@@ -58,7 +58,7 @@ hipError_t launch_prescreen(int words, int32_t n_channels, int64_t n, const int6
                             hipStream_t s);
 int64_t prescreen_tmp_words(int64_t n);
 
-hipError_t launch_twosite(int chi, int batch, const float* A, const float* B, const float* gate,
-                          float* theta, hipStream_t s);
+hipError_t launch_twosite(int precision, int chi, int batch, const float* A, const float* B,
+                          const float* gate, float* theta, hipStream_t s);
 
 }  // namespace msc

@@ -1,5 +1,5 @@
-// Batched two-site contraction + gate on MFMA (Section 3.1), FP32 split
-// complex with FP32 accumulation.
+// Batched two-site contraction + gate on MFMA (Section 3.1): FP32 split
+// complex with FP32 accumulation, or BF16x3 split precision.
 //
 // theta[(a,i),(j,b)] = sum_{i'j'} G[ij][i'j'] sum_c A[(a,i'),c] B[c,(j',b)]
 //
@@ -172,13 +172,215 @@ __global__ __launch_bounds__(NTH) void twosite_kernel(int chi, const float* __re
             }
 }
 
+// ---------------------------------------------------------------------------
+// BF16x3 split precision: every FP32 operand x is split into x_hi = bf16(x)
+// and x_lo = bf16(x - x_hi) (round to nearest even), and a real product is
+// x_hi y_hi + x_hi y_lo + x_lo y_hi with FP32 accumulation on
+// v_mfma_f32_16x16x32_bf16 (the x_lo y_lo term, ~2^-16 relative, is dropped).
+// Workgroup tile: 64 rows x (64 b, both j'); each of the 4 waves keeps a
+// 32 x (32 b, both j') block; K = chi streamed in steps of 32 through LDS
+// with the next step prefetched into registers.
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int BM = 64;    // rows per workgroup
+constexpr int BB = 64;    // b columns per workgroup (times 2 for j')
+constexpr int BK = 32;    // k per step (one MFMA)
+constexpr int BKP = 40;   // padded k stride in LDS (bf16 elements)
+
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+    const unsigned int u = __float_as_uint(x);
+    const unsigned int r = u + 0x7FFFu + ((u >> 16) & 1u);
+    return static_cast<unsigned short>(r >> 16);
+}
+__device__ __forceinline__ float bf16_val(unsigned short h) {
+    return __uint_as_float(static_cast<unsigned int>(h) << 16);
+}
+
+__global__ __launch_bounds__(NTH) void twosite_bf16x3_kernel(int chi, const float* __restrict__ Ag,
+                                                             const float* __restrict__ Bg,
+                                                             const float* __restrict__ gate,
+                                                             float* __restrict__ Tg) {
+    // planes: 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo; A as [row][k], B as [col][k]
+    __shared__ __attribute__((aligned(16))) unsigned short As[4][BM][BKP];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[4][2 * BB][BKP];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int m = 2 * chi, n = 2 * chi;
+    const int rows_tiles = m / BM;
+    const int R0 = (blockIdx.x % rows_tiles) * BM;
+    const int B0 = (blockIdx.x / rows_tiles) * BB;
+    const size_t bidx = blockIdx.y;
+    const float* A = Ag + bidx * 2 * (size_t)m * chi;
+    const float* Bm = Bg + bidx * 2 * (size_t)chi * n;
+    float* T = Tg + bidx * 2 * (size_t)m * n;
+
+    float g[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) g[j] = gate[j];
+
+    floatx4 acc[2][2][2][2];   // [mt][nt][jp][re/im]
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int d = 0; d < 2; ++d) acc[a][b][c][d] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    float4 ra[4], rb[8];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {          // A: 2 planes x 64 rows x 8 float4
+            const int idx = tid + NTH * s;
+            const int plane = idx >> 9, rem = idx & 511;
+            const int row = rem >> 3, kq = rem & 7;
+            ra[s] = *reinterpret_cast<const float4*>(A + (size_t)plane * m * chi +
+                                                     (size_t)(R0 + row) * chi + k0 + 4 * kq);
+        }
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {          // B: 2 planes x 32 k x 32 float4
+            const int idx = tid + NTH * s;
+            const int plane = idx >> 10, rem = idx & 1023;
+            const int kr = rem >> 5, cq = rem & 31;
+            const int cl = 4 * cq;
+            const int col = (cl >> 6) * chi + B0 + (cl & 63);
+            rb[s] = *reinterpret_cast<const float4*>(Bm + (size_t)plane * chi * n +
+                                                     (size_t)(k0 + kr) * n + col);
+        }
+    };
+    auto split_store = [&](unsigned short* hi, unsigned short* lo, float x) {
+        const unsigned short h = bf16_rne(x);
+        *hi = h;
+        *lo = bf16_rne(x - bf16_val(h));
+    };
+    auto lstore = [&]() {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int idx = tid + NTH * s;
+            const int plane = idx >> 9, rem = idx & 511;
+            const int row = rem >> 3, kq = rem & 7;
+            const float v[4] = {ra[s].x, ra[s].y, ra[s].z, ra[s].w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                split_store(&As[2 * plane][row][4 * kq + e], &As[2 * plane + 1][row][4 * kq + e], v[e]);
+        }
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int idx = tid + NTH * s;
+            const int plane = idx >> 10, rem = idx & 1023;
+            const int kr = rem >> 5, cq = rem & 31;
+            const float v[4] = {rb[s].x, rb[s].y, rb[s].z, rb[s].w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                split_store(&Bs[2 * plane][4 * cq + e][kr], &Bs[2 * plane + 1][4 * cq + e][kr], v[e]);
+        }
+    };
+    auto frag = [&](const unsigned short* p) { return *reinterpret_cast<const bf16x8*>(p); };
+    auto neg = [&](bf16x8 x) {
+        typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+        us8 u = __builtin_bit_cast(us8, x);
+        u ^= (unsigned short)0x8000;
+        return __builtin_bit_cast(bf16x8, u);
+    };
+
+    const int nk = chi / BK;
+    gload(0);
+    for (int kt = 0; kt < nk; ++kt) {
+        lstore();
+        __syncthreads();
+        if (kt + 1 < nk) gload((kt + 1) * BK);
+        const int kk = 8 * (lane >> 4);
+        bf16x8 a[2][6];   // re_hi re_lo im_hi im_lo -im_hi -im_lo
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            const int r = wm * 32 + mt * 16 + (lane & 15);
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl) a[mt][pl] = frag(&As[pl][r][kk]);
+            a[mt][4] = neg(a[mt][2]);
+            a[mt][5] = neg(a[mt][3]);
+        }
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int jp = 0; jp < 2; ++jp) {
+                const int c = jp * BB + wn * 32 + nt * 16 + (lane & 15);
+                bf16x8 b[4];
+#pragma unroll
+                for (int pl = 0; pl < 4; ++pl) b[pl] = frag(&Bs[pl][c][kk]);
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt) {
+                    floatx4& re = acc[mt][nt][jp][0];
+                    floatx4& im = acc[mt][nt][jp][1];
+                    // Re += Ar Br - Ai Bi ; Im += Ar Bi + Ai Br   (each x3)
+                    re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][0], b[0], re, 0, 0, 0);
+                    re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][0], b[1], re, 0, 0, 0);
+                    re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][1], b[0], re, 0, 0, 0);
+                    re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][4], b[2], re, 0, 0, 0);
+                    re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][4], b[3], re, 0, 0, 0);
+                    re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][5], b[2], re, 0, 0, 0);
+                    im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][0], b[2], im, 0, 0, 0);
+                    im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][0], b[3], im, 0, 0, 0);
+                    im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][1], b[2], im, 0, 0, 0);
+                    im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][2], b[0], im, 0, 0, 0);
+                    im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][2], b[1], im, 0, 0, 0);
+                    im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][3], b[0], im, 0, 0, 0);
+                }
+            }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int rp = 0; rp < 2; ++rp) {
+                const int row0 = R0 + wm * 32 + mt * 16 + 4 * (lane >> 4) + 2 * rp;
+                const int b = B0 + wn * 32 + nt * 16 + (lane & 15);
+                float sr[4], si[4];
+#pragma unroll
+                for (int ip = 0; ip < 2; ++ip)
+#pragma unroll
+                    for (int jp = 0; jp < 2; ++jp) {
+                        sr[2 * ip + jp] = acc[mt][nt][jp][0][2 * rp + ip];
+                        si[2 * ip + jp] = acc[mt][nt][jp][1][2 * rp + ip];
+                    }
+#pragma unroll
+                for (int o = 0; o < 4; ++o) {
+                    float xr = 0.f, xi = 0.f;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float gr = g[2 * (4 * o + j)], gi = g[2 * (4 * o + j) + 1];
+                        xr += gr * sr[j] - gi * si[j];
+                        xi += gr * si[j] + gi * sr[j];
+                    }
+                    const int i = o >> 1, j = o & 1;
+                    const size_t at = (size_t)(row0 + i) * n + (size_t)j * chi + b;
+                    T[at] = xr;
+                    T[(size_t)m * n + at] = xi;
+                }
+            }
+}
+
 }  // namespace
 
-hipError_t launch_twosite(int chi, int batch, const float* A, const float* B, const float* gate,
-                          float* theta, hipStream_t s) {
+hipError_t launch_twosite(int precision, int chi, int batch, const float* A, const float* B,
+                          const float* gate, float* theta, hipStream_t s) {
     if (chi % 64 != 0 || chi < 64) return hipErrorInvalidValue;
-    const int tiles = (2 * chi / TM) * (chi / TB);
-    hipLaunchKernelGGL(twosite_kernel, dim3(tiles, batch), dim3(NTH), 0, s, chi, A, B, gate, theta);
+    if (precision == MSC_BF16X3) {
+        const int tiles = (2 * chi / BM) * (chi / BB);
+        hipLaunchKernelGGL(twosite_bf16x3_kernel, dim3(tiles, batch), dim3(NTH), 0, s, chi, A, B,
+                           gate, theta);
+    } else {
+        const int tiles = (2 * chi / TM) * (chi / TB);
+        hipLaunchKernelGGL(twosite_kernel, dim3(tiles, batch), dim3(NTH), 0, s, chi, A, B, gate,
+                           theta);
+    }
     return hipGetLastError();
 }
 

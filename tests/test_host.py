@@ -155,4 +155,4 @@ def test_device_calls_reject_null_context():
     cnt = C.c_int64()
     assert L.msc_prescreen(None, None, 0, None, None, None, None, None, C.byref(cnt)) \
         == _lib.MSC_E_INVALID
-    assert L.msc_twosite_contract(None, 64, 1, None, None, None, None) == _lib.MSC_E_INVALID
+    assert L.msc_twosite_contract(None, 1, 64, 1, None, None, None, None) == _lib.MSC_E_INVALID

@@ -188,3 +188,49 @@ def discard(decided, flips, faults: dict) -> bool:
         if d and bin(f & v).count("1") & 1:
             return True
     return False
+
+
+def signature_table(circ, decided, flips):
+    """The oracle's own per-basis-fault signatures, derived from its flip
+    vectors: sig[4c + k] has bit d set iff basis fault (c, k) flips the d-th
+    decided measurement.  Returned as a uint64 array [4M, W]."""
+    import numpy as np
+    dlist = [m for m, d in enumerate(decided) if d]
+    W = max(1, (len(dlist) + 63) // 64)
+    sig = np.zeros((4 * circ.n_channels, W), dtype=np.uint64)
+    for d, m in enumerate(dlist):
+        f = flips[m]
+        while f:
+            b = (f & -f).bit_length() - 1
+            f &= f - 1
+            sig[b, d >> 6] |= np.uint64(1) << np.uint64(d & 63)
+    return sig
+
+
+def discard_csr(sig, off, chan, pauli, chunk: int = 1 << 20):
+    """Vectorised discard decisions for a CSR shot list: a shot's signature
+    is the XOR of its faults' signatures (each the XOR of its basis
+    components); processed in chunks of shots."""
+    import numpy as np
+    n = len(off) - 1
+    out = np.zeros(n, dtype=bool)
+    W = sig.shape[1]
+    for s0 in range(0, n, chunk):
+        s1 = min(n, s0 + chunk)
+        f0, f1 = int(off[s0]), int(off[s1])
+        if f1 == f0:
+            continue
+        ch = chan[f0:f1].astype(np.int64)
+        pa = pauli[f0:f1]
+        fs = np.zeros((f1 - f0, W), dtype=np.uint64)
+        for k in range(4):
+            on = ((pa >> k) & 1).astype(bool)
+            fs[on] ^= sig[4 * ch[on] + k]
+        starts = off[s0:s1] - f0
+        cnt = np.diff(off[s0:s1 + 1])
+        nz = cnt > 0
+        red = np.bitwise_xor.reduceat(fs, starts[nz], axis=0)
+        acc = np.zeros((s1 - s0, W), dtype=np.uint64)
+        acc[nz] = red
+        out[s0:s1] = acc.any(axis=1)
+    return out

@@ -28,7 +28,28 @@ G2 = {
     "CZ": np.diag([1, 1, 1, -1]).astype(np.complex128),
     "SWAP": np.array([[1, 0, 0, 0], [0, 0, 1, 0], [0, 1, 0, 0], [0, 0, 0, 1]],
                      dtype=np.complex128),
+    "CS": np.diag([1, 1, 1, 1j]).astype(np.complex128),
+    "CSDG": np.diag([1, 1, 1, -1j]).astype(np.complex128),
 }
+
+# CCZ = diag(1, ..., 1, -1) as a Clifford+T sequence (the textbook Toffoli
+# circuit with the target's Hadamards removed); the state vector applies CCZ
+# from its definition, the MPS from this sequence.
+def ccz_sequence(a, b, c):
+    return [("CX", b, c), ("TDG", c), ("CX", a, c), ("T", c), ("CX", b, c), ("TDG", c),
+            ("CX", a, c), ("T", b), ("T", c), ("CX", a, b), ("T", a), ("TDG", b),
+            ("CX", a, b)]
+
+
+def fault_paulis(code: int, qubits):
+    """(qubit, 2x2 Pauli) pairs of a fault code: bits 2j, 2j+1 are the x, z
+    bits of the channel's j-th qubit."""
+    out = []
+    for j, q in enumerate(qubits):
+        x, z = code >> (2 * j) & 1, code >> (2 * j + 1) & 1
+        if x or z:
+            out.append((q, pauli_from_bits(x, z)))
+    return out
 
 
 def pauli_from_bits(x: int, z: int) -> np.ndarray:

@@ -2,17 +2,21 @@
 
 One op per line; '#' starts a comment.  Header lines: QUBITS n, ORDER
 q0 q1 ... (qubit held by each MPS site), SEED q, TARGET T|S.  Ops:
-H S SDG T TDG X Y Z q | CX CZ a b | M q | R q | DEP1 q | DEP2 a b | XERR q |
-TICK.  Channels (DEP1, DEP2, XERR) are numbered in text order, as are
-measurements.  The noise semantics follow Section 4 (uniform depolarising,
-any of the 4^k-1 non-identity Paulis with probability p/(4^k-1)).
+H S SDG T TDG X Y Z q | CX CZ CS CSDG a b | CCZ a b c | M q | R q | DEP1 q |
+DEP2 a b | DEP3 a b c | XERR q | TICK.  Channels (DEP1, DEP2, DEP3, XERR)
+are numbered in text order, as are measurements.  CS/CSDG are controlled-S
+and controlled-S^dagger, CCZ the doubly controlled Z: the diagonal
+non-Clifford gates of the paper's checks (Section 2, Section 4.2).  The
+noise semantics follow Section 4 (uniform depolarising, any of the 4^k-1
+non-identity Paulis with probability p/(4^k-1)).
 """
 from __future__ import annotations
 
 from dataclasses import dataclass, field
 
 ONE_Q = {"H", "S", "SDG", "T", "TDG", "X", "Y", "Z"}
-TWO_Q = {"CX", "CZ"}
+TWO_Q = {"CX", "CZ", "CS", "CSDG"}
+THREE_Q = {"CCZ"}
 
 
 @dataclass
@@ -24,13 +28,14 @@ class OCircuit:
     target: str
     n_channels: int
     n_meas: int
-    channel_arity: list = field(default_factory=list)   # 1 or 2 per channel
-    channel_kind: list = field(default_factory=list)    # "DEP1"|"DEP2"|"XERR"
+    channel_arity: list = field(default_factory=list)   # 1, 2 or 3 per channel
+    channel_kind: list = field(default_factory=list)    # DEP1|DEP2|DEP3|XERR
 
 
 def parse(text: str) -> OCircuit:
     """Parse circuit text into ('g1', name, q) / ('g2', name, a, b) /
-    ('m', q, meas_idx) / ('r', q) / ('ch', kind, chan_idx, qubits)."""
+    ('g3', name, a, b, c) / ('m', q, meas_idx) / ('r', q) /
+    ('ch', kind, chan_idx, qubits)."""
     n = None
     order = None
     seed = 0
@@ -64,6 +69,11 @@ def parse(text: str) -> OCircuit:
             if a == b:
                 raise ValueError("two-qubit gate on one qubit")
             ops.append(("g2", op, a, b))
+        elif op in THREE_Q:
+            a, b, c = int(args[0]), int(args[1]), int(args[2])
+            if len({a, b, c}) != 3:
+                raise ValueError("three-qubit gate on repeated qubits")
+            ops.append(("g3", op, a, b, c))
         elif op == "M":
             ops.append(("m", int(args[0]), nm))
             nm += 1
@@ -77,6 +87,11 @@ def parse(text: str) -> OCircuit:
         elif op == "DEP2":
             ops.append(("ch", op, nch, (int(args[0]), int(args[1]))))
             arity.append(2)
+            kinds.append(op)
+            nch += 1
+        elif op == "DEP3":
+            ops.append(("ch", op, nch, (int(args[0]), int(args[1]), int(args[2]))))
+            arity.append(3)
             kinds.append(op)
             nch += 1
         else:

@@ -20,7 +20,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .gates import G1, G2, pauli_from_bits, target_state
+from .gates import G1, G2, ccz_sequence, fault_paulis, target_state
 from .statevector import ShotResult
 
 
@@ -128,44 +128,48 @@ def run_shot(circ, faults: dict, expected=None, tau_rej: float = 1e-6,
         qubit_at[k], qubit_at[k + 1] = qb, qa
         site[qa], site[qb] = k + 1, k
 
+    def gate2(name, a, b):
+        g = G2[name]
+        home = site[a]
+        # bring qubit a next to qubit b
+        moves = []
+        while abs(site[a] - site[b]) > 1:
+            if site[a] < site[b]:
+                k = site[a]
+                swap_sites(k)
+                moves.append(("r", k))
+            else:
+                k = site[a] - 1
+                swap_sites_left(k)
+                moves.append(("l", k))
+        k = min(site[a], site[b])
+        if site[a] < site[b]:
+            mps.apply2_adjacent(g, k)
+        else:
+            sw = G2["SWAP"]
+            mps.apply2_adjacent(sw @ g @ sw, k)
+        for d, k in reversed(moves):
+            if d == "r":
+                swap_sites_left(k)
+            else:
+                swap_sites(k)
+        assert site[a] == home
+
     for op in circ.ops:
         kind = op[0]
         if kind == "g1":
             mps.apply1(G1[op[1]], site[op[2]])
         elif kind == "g2":
-            a, b = op[2], op[3]
-            g = G2[op[1]]
-            home = site[a]
-            # bring qubit a next to qubit b
-            moves = []
-            while abs(site[a] - site[b]) > 1:
-                if site[a] < site[b]:
-                    k = site[a]
-                    swap_sites(k)
-                    moves.append(("r", k))
+            gate2(op[1], op[2], op[3])
+        elif kind == "g3":
+            for g in ccz_sequence(op[2], op[3], op[4]):
+                if g[0] == "CX":
+                    gate2("CX", g[1], g[2])
                 else:
-                    k = site[a] - 1
-                    swap_sites_left(k)
-                    moves.append(("l", k))
-            k = min(site[a], site[b])
-            if site[a] < site[b]:
-                mps.apply2_adjacent(g, k)
-            else:
-                sw = G2["SWAP"]
-                mps.apply2_adjacent(sw @ g @ sw, k)
-            for d, k in reversed(moves):
-                if d == "r":
-                    swap_sites_left(k)
-                else:
-                    swap_sites(k)
-            assert site[a] == home
+                    mps.apply1(G1[g[0]], site[g[1]])
         elif kind == "ch":
-            code = faults.get(op[2], 0)
-            if code:
-                qs = op[3]
-                mps.apply1(pauli_from_bits(code & 1, code >> 1 & 1), site[qs[0]])
-                if len(qs) == 2 and code >> 2:
-                    mps.apply1(pauli_from_bits(code >> 2 & 1, code >> 3 & 1), site[qs[1]])
+            for q, P in fault_paulis(faults.get(op[2], 0), op[3]):
+                mps.apply1(P, site[q])
         elif kind == "m":
             q, mi = op[1], op[2]
             e = 0 if expected is None else int(expected[mi])

@@ -6,17 +6,17 @@ oracle tracks a set of independent stabiliser generators of the noiseless
 state through the circuit:
 
 * a Clifford gate conjugates every generator;
-* a diagonal non-Clifford gate (T, T^dagger) on qubit q keeps the largest
-  subgroup that commutes with it (GF(2) elimination on the X bit of q: one
-  generator with X on q becomes the pivot, is multiplied into every other
-  generator with X on q, and is dropped);
+* a diagonal non-Clifford gate (T, T^dagger, CS, CS^dagger, CCZ) keeps the
+  largest subgroup without X/Y on its support (GF(2) elimination, one qubit
+  of the support at a time: one generator with X on q becomes the pivot, is
+  multiplied into every other generator with X on q, and is dropped);
 * a Z measurement is *decided* if Z_q lies in the tracked group; otherwise
   it is undecided and, since only its expected outcome is ever accepted,
   +Z_q joins the group after the standard measurement update.
 
 Pauli noise only changes generator signs (Section 4.2).  Each generator
 therefore carries a GF(2) vector over "basis faults" (channel c, component
-X_a, Z_a, X_b, Z_b): bit b is set iff basis fault b anticommutes with the
+X_a, Z_a, X_b, Z_b, X_c, Z_c): bit b is set iff basis fault b anticommutes with the
 generator at the time it is injected.  Products of generators XOR these
 vectors.  A decided measurement's flip vector is the XOR over the
 generators whose product is Z_q; a shot is discarded iff, for some decided
@@ -24,6 +24,9 @@ measurement, the parity of (its flip vector AND the shot's basis faults) is
 odd.  The rule has no false discards: a discarded shot has P_acc = 0.
 """
 from __future__ import annotations
+
+# basis faults per channel: X and Z on each of up to three qubits
+NCOMP = 6
 
 
 class Tableau:
@@ -132,7 +135,8 @@ def analyse(circ):
 
     Returns (decided, flips): ``decided[m]`` is True for decided
     measurements and ``flips[m]`` their basis-fault flip vector (Python int,
-    bit 4*c + k for channel c and component k in X_a, Z_a, X_b, Z_b)."""
+    bit NCOMP*c + k for channel c and component k in X_a, Z_a, X_b, Z_b,
+    X_c, Z_c)."""
     tab = Tableau(circ.n)
     decided = [False] * circ.n_meas
     flips = [0] * circ.n_meas
@@ -150,16 +154,20 @@ def analyse(circ):
         elif kind == "g2":
             if op[1] == "CX":
                 tab.cx(op[2], op[3])
-            else:
+            elif op[1] == "CZ":
                 tab.cz(op[2], op[3])
+            else:                               # CS, CS^dagger: diagonal
+                tab.drop_x(op[2])
+                tab.drop_x(op[3])
+        elif kind == "g3":                      # CCZ: diagonal
+            for q in op[2:5]:
+                tab.drop_x(q)
         elif kind == "ch":
             c, qs = op[2], op[3]
-            base = 4 * c
-            tab.inject(qs[0], 1, 0, 1 << base)
-            tab.inject(qs[0], 0, 1, 1 << (base + 1))
-            if len(qs) == 2:
-                tab.inject(qs[1], 1, 0, 1 << (base + 2))
-                tab.inject(qs[1], 0, 1, 1 << (base + 3))
+            base = NCOMP * c
+            for j, q in enumerate(qs):
+                tab.inject(q, 1, 0, 1 << (base + 2 * j))
+                tab.inject(q, 0, 1, 1 << (base + 2 * j + 1))
         elif kind == "m":
             q, mi = op[1], op[2]
             f = tab.express(0, 1 << q)
@@ -173,12 +181,12 @@ def analyse(circ):
 
 
 def fault_vector(faults: dict) -> int:
-    """Basis-fault bitmask of a shot {channel: 4-bit Pauli code}."""
+    """Basis-fault bitmask of a shot {channel: 6-bit Pauli code}."""
     v = 0
     for c, code in faults.items():
-        for k in range(4):
+        for k in range(NCOMP):
             if code >> k & 1:
-                v |= 1 << (4 * c + k)
+                v |= 1 << (NCOMP * c + k)
     return v
 
 
@@ -192,12 +200,12 @@ def discard(decided, flips, faults: dict) -> bool:
 
 def signature_table(circ, decided, flips):
     """The oracle's own per-basis-fault signatures, derived from its flip
-    vectors: sig[4c + k] has bit d set iff basis fault (c, k) flips the d-th
-    decided measurement.  Returned as a uint64 array [4M, W]."""
+    vectors: sig[NCOMP c + k] has bit d set iff basis fault (c, k) flips the
+    d-th decided measurement.  Returned as a uint64 array [NCOMP M, W]."""
     import numpy as np
     dlist = [m for m, d in enumerate(decided) if d]
     W = max(1, (len(dlist) + 63) // 64)
-    sig = np.zeros((4 * circ.n_channels, W), dtype=np.uint64)
+    sig = np.zeros((NCOMP * circ.n_channels, W), dtype=np.uint64)
     for d, m in enumerate(dlist):
         f = flips[m]
         while f:
@@ -223,9 +231,9 @@ def discard_csr(sig, off, chan, pauli, chunk: int = 1 << 20):
         ch = chan[f0:f1].astype(np.int64)
         pa = pauli[f0:f1]
         fs = np.zeros((f1 - f0, W), dtype=np.uint64)
-        for k in range(4):
+        for k in range(NCOMP):
             on = ((pa >> k) & 1).astype(bool)
-            fs[on] ^= sig[4 * ch[on] + k]
+            fs[on] ^= sig[NCOMP * ch[on] + k]
         starts = off[s0:s1] - f0
         cnt = np.diff(off[s0:s1 + 1])
         nz = cnt > 0

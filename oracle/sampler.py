@@ -4,8 +4,8 @@ A shot is a fault configuration: a weight w (either given per shot, or
 drawn from Bin(M, p) as in Section 4.1), a uniform w-subset of the M
 channels (valid because all channels share p), and for each chosen channel
 a uniform non-identity Pauli: 3 choices for a 1-qubit depolarising channel,
-15 for a 2-qubit one, X only for an X-flip channel (Section 4 and
-Appendix "Noise model").
+15 for a 2-qubit one, 63 for a 3-qubit one, X only for an X-flip channel
+(Section 4 and Appendix "Noise model").
 
 Random numbers come from published generators written here from their
 definitions, keyed by (seed, shot index) so any shot can be regenerated:
@@ -104,7 +104,7 @@ def floyd_subset(rng: SplitMix64, M: int, w: int) -> list:
 
 
 def sample_shot(circ, seed: int, shot: int, weight=None, cdf=None) -> dict:
-    """One shot's faults as {channel: 4-bit Pauli code}."""
+    """One shot's faults as {channel: Pauli code, bits 2j, 2j+1 = x, z of qubit j}."""
     rng = SplitMix64(seed, shot)
     M = circ.n_channels
     w = weight if weight is not None else draw_weight(rng, cdf)
@@ -117,8 +117,10 @@ def sample_shot(circ, seed: int, shot: int, weight=None, cdf=None) -> dict:
             out[c] = 1
         elif kind == "DEP1":
             out[c] = 1 + rng.bounded(3)
-        else:
+        elif kind == "DEP2":
             out[c] = 1 + rng.bounded(15)
+        else:
+            out[c] = 1 + rng.bounded(63)
     return out
 
 

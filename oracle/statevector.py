@@ -23,7 +23,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .gates import G1, pauli_from_bits, target_state
+from .gates import G1, fault_paulis, target_state
 
 
 @dataclass
@@ -50,13 +50,36 @@ def _cx(psi: np.ndarray, c: int, t: int, n: int) -> np.ndarray:
     return v.reshape(-1)
 
 
-def _cz(psi: np.ndarray, a: int, b: int, n: int) -> np.ndarray:
+def _phase(psi: np.ndarray, qs, ph: complex, n: int) -> np.ndarray:
+    """Multiply the amplitudes with every qubit of qs equal to 1 by ph
+    (CZ, CS, CS^dagger, CCZ are all of this form)."""
     v = psi.reshape((2,) * n).copy()
     idx = [slice(None)] * n
-    idx[a] = 1
-    idx[b] = 1
-    v[tuple(idx)] *= -1
+    for q in qs:
+        idx[q] = 1
+    v[tuple(idx)] *= ph
     return v.reshape(-1)
+
+
+_PHASE = {"CZ": -1.0, "CS": 1j, "CSDG": -1j, "CCZ": -1.0}
+
+
+def _apply_op(psi, op, n, faults):
+    kind = op[0]
+    if kind == "g1":
+        return _apply1(psi, G1[op[1]], op[2], n)
+    if kind == "g2":
+        if op[1] == "CX":
+            return _cx(psi, op[2], op[3], n)
+        return _phase(psi, (op[2], op[3]), _PHASE[op[1]], n)
+    if kind == "g3":
+        return _phase(psi, (op[2], op[3], op[4]), _PHASE[op[1]], n)
+    if kind == "ch":
+        code = faults.get(op[2], 0)
+        for q, P in fault_paulis(code, op[3]):
+            psi = _apply1(psi, P, q, n)
+        return psi
+    raise ValueError(kind)
 
 
 def _slice_prob(psi: np.ndarray, q: int, n: int, e: int) -> float:
@@ -66,8 +89,8 @@ def _slice_prob(psi: np.ndarray, q: int, n: int, e: int) -> float:
 
 def run_shot(circ, faults: dict, expected=None, tau_rej: float = 1e-6,
              record: bool = False) -> ShotResult:
-    """Simulate one shot.  ``faults`` maps channel index -> 4-bit Pauli code
-    (bit0 x_a, bit1 z_a, bit2 x_b, bit3 z_b).  ``expected`` maps measurement
+    """Simulate one shot.  ``faults`` maps channel index -> Pauli code
+    (bits 2j, 2j+1 = x, z bits of the channel's j-th qubit).  ``expected`` maps measurement
     index -> expected outcome (default 0, the paper's acceptance rule)."""
     n = circ.n
     if n > 22:
@@ -78,20 +101,8 @@ def run_shot(circ, faults: dict, expected=None, tau_rej: float = 1e-6,
     probs = []
     for op in circ.ops:
         kind = op[0]
-        if kind == "g1":
-            psi = _apply1(psi, G1[op[1]], op[2], n)
-        elif kind == "g2":
-            if op[1] == "CX":
-                psi = _cx(psi, op[2], op[3], n)
-            else:
-                psi = _cz(psi, op[2], op[3], n)
-        elif kind == "ch":
-            code = faults.get(op[2], 0)
-            if code:
-                qs = op[3]
-                psi = _apply1(psi, pauli_from_bits(code & 1, code >> 1 & 1), qs[0], n)
-                if len(qs) == 2 and code >> 2:
-                    psi = _apply1(psi, pauli_from_bits(code >> 2 & 1, code >> 3 & 1), qs[1], n)
+        if kind in ("g1", "g2", "g3", "ch"):
+            psi = _apply_op(psi, op, n, faults)
         elif kind == "m":
             q, mi = op[1], op[2]
             e = 0 if expected is None else int(expected[mi])
@@ -129,17 +140,8 @@ def final_state(circ, faults: dict) -> np.ndarray:
     psi[0] = 1.0
     for op in circ.ops:
         kind = op[0]
-        if kind == "g1":
-            psi = _apply1(psi, G1[op[1]], op[2], n)
-        elif kind == "g2":
-            psi = _cx(psi, op[2], op[3], n) if op[1] == "CX" else _cz(psi, op[2], op[3], n)
-        elif kind == "ch":
-            code = faults.get(op[2], 0)
-            if code:
-                qs = op[3]
-                psi = _apply1(psi, pauli_from_bits(code & 1, code >> 1 & 1), qs[0], n)
-                if len(qs) == 2 and code >> 2:
-                    psi = _apply1(psi, pauli_from_bits(code >> 2 & 1, code >> 3 & 1), qs[1], n)
+        if kind in ("g1", "g2", "g3", "ch"):
+            psi = _apply_op(psi, op, n, faults)
         elif kind == "m":
             q = op[1]
             v = psi.reshape(2 ** q, 2, 2 ** (n - q - 1)).copy()

@@ -19,7 +19,7 @@ from oracle import mps as omps
 from oracle import prescreen as ops
 from oracle import sampler as osamp
 from oracle import statevector as sv
-from oracle.gates import G1, G2, target_state
+from oracle.gates import G1, G2, ccz_sequence, fault_paulis, target_state
 from oracle.ir import parse
 from workloads.circuits import config_circuit, make_circuit
 
@@ -34,6 +34,39 @@ def one_qubit(prep: str, fault_kind: str = "") -> str:
 
 
 # ---------------------------------------------------------------- closed forms
+def _embed(ops_, n=3):
+    """Matrix of a gate list on n qubits (qubit 0 most significant)."""
+    u = np.eye(2 ** n, dtype=complex)
+    for g in ops_:
+        if g[0] == "CX":
+            c_, t_ = g[1], g[2]
+            m = np.zeros((2 ** n, 2 ** n), dtype=complex)
+            for x in range(2 ** n):
+                y = x ^ (1 << (n - 1 - t_)) if x >> (n - 1 - c_) & 1 else x
+                m[y, x] = 1
+        else:
+            m = np.array([[1]], dtype=complex)
+            for q in range(n):
+                m = np.kron(m, G1[g[0]] if q == g[1] else np.eye(2))
+        u = m @ u
+    return u
+
+
+def test_controlled_phase_gates_from_definitions():
+    # CCZ = diag(1,...,1,-1) (the MPS applies it as a CNOT + T network);
+    # CS = diag(1,1,1,i): CS^2 = CZ, CS CS^dagger = I
+    for a, b, c in itertools.permutations(range(3)):
+        assert np.allclose(_embed(ccz_sequence(a, b, c)), np.diag([1] * 7 + [-1]), atol=1e-14)
+    assert sum(1 for g in ccz_sequence(0, 1, 2) if g[0] in ("T", "TDG")) == 7
+    assert np.allclose(G2["CS"] @ G2["CS"], G2["CZ"], atol=1e-15)
+    assert np.allclose(G2["CS"] @ G2["CSDG"], np.eye(4), atol=1e-15)
+    # bits 2j, 2j+1 of a fault code are the x, z bits of the j-th qubit
+    got = dict((q, P) for q, P in fault_paulis(0b110110, (5, 6, 7)))
+    assert np.allclose(got[5], G1["Z"]) and np.allclose(got[6], G1["X"])
+    assert np.allclose(got[7], G1["Y"])
+    assert [q for q, _ in fault_paulis(0b000100, (5, 6))] == [6]
+
+
 def test_gates_unitary_and_t_state():
     for u in list(G1.values()) + list(G2.values()):
         assert np.allclose(u.conj().T @ u, np.eye(u.shape[0]), atol=1e-15)
@@ -67,7 +100,7 @@ def test_s_target_fidelity():
 
 
 # ---------------------------------------------------------------- invariants
-@pytest.mark.parametrize("name", ["tiny", "c1"])
+@pytest.mark.parametrize("name", ["tiny", "c1", "tiny_ghz", "c1_ghz"])
 @pytest.mark.parametrize("target", ["T", "S"])
 def test_noiseless_circuits_are_deterministic(name, target):
     # every measurement has p(e_m) = 1 and the decoded seed equals the target
@@ -109,7 +142,8 @@ def test_pacc_chain_rule_equals_projected_norm():
     assert seen_partial > 0
 
 
-@pytest.mark.parametrize("name,n_shots", [("tiny", 200), ("c1", 25)])
+@pytest.mark.parametrize("name,n_shots", [("tiny", 200), ("c1", 25), ("tiny_ghz", 150),
+                                          ("c1_ghz", 12)])
 def test_mps_agrees_with_state_vector(name, n_shots):
     c = parse(config_circuit(name).text)
     rng = random.Random(11)
@@ -228,9 +262,57 @@ def test_clifford_measurement_probabilities_are_0_half_1():
 def _all_single_faults(c):
     for ch in range(c.n_channels):
         k = c.channel_kind[ch]
-        codes = [1] if k == "XERR" else range(1, 4 if k == "DEP1" else 16)
+        codes = [1] if k == "XERR" else range(1, {"DEP1": 4, "DEP2": 16, "DEP3": 64}[k])
         for code in codes:
             yield {ch: code}
+
+
+def test_prescreen_exhaustive_single_faults_ghz_gadgets():
+    # CS, CS^dagger and CCZ inside the GHZ-controlled checks (Section 4.2:
+    # the only non-Cliffords are diagonal); no discarded single fault may
+    # have a nonzero acceptance probability.
+    c = parse(config_circuit("tiny_ghz").text)
+    assert any(o[0] == "g3" for o in c.ops)
+    assert any(o[0] == "g2" and o[1] in ("CS", "CSDG") for o in c.ops)
+    dec, fl = ops.analyse(c)
+    n_disc = 0
+    for f in _all_single_faults(c):
+        if ops.discard(dec, fl, f):
+            n_disc += 1
+            assert sv.run_shot(c, f).p_acc == 0.0
+    assert n_disc > 300
+
+
+@pytest.mark.parametrize("gate", ["CS 0 1", "CSDG 1 0", "CCZ 0 1 2", "CCZ 2 0 1"])
+def test_prescreen_diagonal_gates_undecide_what_they_entangle(gate):
+    # a diagonal non-Clifford between |+> qubits makes the later X-basis
+    # read-out of its support random: the measurement must not be decided,
+    # otherwise the Z fault in front of it would be a false discard.
+    text = f"QUBITS 3\nH 0\nH 1\nH 2\nDEP1 0\nDEP1 1\n{gate}\nH 0\nM 0\nH 1\nM 1\n"
+    c = parse(text)
+    dec, fl = ops.analyse(c)
+    assert dec == [False, False]
+    for f in _all_single_faults(c):
+        r = sv.run_shot(c, f, tau_rej=0.0)
+        assert r.p_acc > 0.1
+        assert not ops.discard(dec, fl, f)
+
+
+def test_prescreen_exact_on_clifford_three_qubit_channels():
+    # every component of a three-qubit channel is injected: on a Clifford
+    # circuit the screen is exact (discard iff P_acc = 0)
+    text = ("QUBITS 4\nH 0\nCX 0 1\nCX 1 2\nH 3\nDEP3 0 1 2\nDEP3 3 2 0\n"
+            "CX 1 2\nCX 0 1\nH 0\nH 3\nM 0\nM 1\nM 2\nM 3\n")
+    c = parse(text)
+    dec, fl = ops.analyse(c)
+    assert all(dec)
+    third_only = 0
+    for f in _all_single_faults(c):
+        d = ops.discard(dec, fl, f)
+        assert d == (sv.run_shot(c, f).p_acc == 0.0)
+        (code,) = f.values()
+        third_only += d and code & 0b1111 == 0
+    assert third_only > 0      # a fault on the third qubit alone is caught
 
 
 @pytest.mark.parametrize("target", ["T", "S"])

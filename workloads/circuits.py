@@ -21,6 +21,17 @@ same stage structure (Section 2 and Appendix "Circuits"):
    logical state is compared with the target (Appendix "Post-selection and
    logical error").
 
+Optionally (``ghz_checks``), rounds outside a frame end with GHZ-controlled
+check gadgets shaped like the paper's controlled-H_XY checks (Section 2 and
+Appendix "Circuits": GHZ ancillas, controlled-S on single qubits, CCZ on
+qubit pairs, controlled-X): for an X check X_S the gadget measures
+V X_S V^dagger = X_S with V = (S on every qubit of S) (CZ on consecutive
+pairs of S), applied as controlled-V^dagger, controlled-X_S, controlled-V
+with the controls spread over a GHZ(k) state.  Noiselessly the CS and CCZ
+gates cancel and every GHZ outcome is 0; a fault between them is conjugated
+into a non-Pauli operator, which is what the pre-screen's diagonal-gate
+rule and the MPS have to handle.
+
 Noise (Appendix "Noise model", read as in the project's design notes):
 DEP1/DEP2 after every noisy 1q/2q gate, an X flip after every reset and
 before every measurement; no idle noise; the noiseless tail has none.
@@ -206,6 +217,12 @@ class _Writer:
             self.lines.append(f"DEP2 {a} {b}")
             self.n_channels += 1
 
+    def g3(self, name, a, b, c):
+        self.lines.append(f"{name} {a} {b} {c}")
+        if self.noisy:
+            self.lines.append(f"DEP3 {a} {b} {c}")
+            self.n_channels += 1
+
     def reset(self, q):
         self.lines.append(f"R {q}")
         if self.noisy:
@@ -250,7 +267,8 @@ def _frame_ops(target: str, k: int, inverse: bool):
 def make_circuit(kind: str = "rot", d: int = 3, plain_rounds: int = 3,
                  t_layers: int = 1, framed_rounds: int = 1,
                  final_rounds: int = 1, target: str = "T",
-                 order: str = "snake") -> Circuit:
+                 order: str = "snake", ghz_checks: int = 0,
+                 ghz_size: int = 3) -> Circuit:
     """Write one cultivation-like circuit (see the module docstring)."""
     patch = rotated_patch(d) if kind == "rot" else unrotated_patch(d)
     coords = list(patch.data) + [c[1] for c in patch.checks]
@@ -318,6 +336,36 @@ def make_circuit(kind: str = "rot", d: int = 3, plain_rounds: int = 3,
             w.g2("CX", op[1], op[2])
     first_use = set()
 
+    ancillas = sorted([a for a, _ in zchk] + [a for a, _ in xchk], key=lambda q: site_of[q])
+
+    def ghz_check(a0, nb):
+        # GHZ(k) on the k free ancillas nearest to the check's own ancilla
+        near = sorted(ancillas, key=lambda q: (abs(site_of[q] - site_of[a0]), site_of[q]))
+        g = sorted(near[:ghz_size], key=lambda q: site_of[q])
+        k = len(g)
+        pairs = [(nb[i], nb[i + 1]) for i in range(0, len(nb) - 1, 2)]
+        L.append("TICK")
+        for q in g:
+            w.reset(q)
+        w.g1("H", g[0])
+        for i in range(k - 1):
+            w.g2("CX", g[i], g[i + 1])
+        for j, q in enumerate(nb):                 # controlled V^dagger
+            w.g2("CSDG", g[j % k], q)
+        for j, (x, y) in enumerate(pairs):
+            w.g3("CCZ", g[(j + 1) % k], x, y)
+        for j, q in enumerate(nb):                 # controlled X_S
+            w.g2("CX", g[(j + 2) % k], q)
+        for j, (x, y) in enumerate(pairs):         # controlled V
+            w.g3("CCZ", g[(j + 1) % k], x, y)
+        for j, q in enumerate(nb):
+            w.g2("CS", g[j % k], q)
+        for i in reversed(range(k - 1)):
+            w.g2("CX", g[i], g[i + 1])
+        w.g1("H", g[0])
+        for q in g:
+            w.meas(q)
+
     def round_(frame):
         L.append("TICK")
         for a, nb in zchk:
@@ -340,6 +388,9 @@ def make_circuit(kind: str = "rot", d: int = 3, plain_rounds: int = 3,
         for q in data:
             for g in fwd:
                 w.g1(g, q)
+        if frame == 0:
+            for a, nb in xchk[:ghz_checks]:
+                ghz_check(a, nb)
 
     for _ in range(plain_rounds):
         round_(0)
@@ -361,6 +412,7 @@ def make_circuit(kind: str = "rot", d: int = 3, plain_rounds: int = 3,
 
     # 4. noiseless tail
     w.noisy = False
+    ghz_checks = 0
     round_(0)
     L.append("TICK")
     for op in reversed(enc):
@@ -377,7 +429,8 @@ def make_circuit(kind: str = "rot", d: int = 3, plain_rounds: int = 3,
                    coords={qid[c]: c for c in coords},
                    meta=dict(kind=kind, d=d, plain_rounds=plain_rounds,
                              t_layers=t_layers, framed_rounds=framed_rounds,
-                             final_rounds=final_rounds))
+                             final_rounds=final_rounds, ghz_checks=ghz_checks,
+                             ghz_size=ghz_size))
 
 
 # --------------------------------------------------------------------------
@@ -398,4 +451,12 @@ def config_circuit(name: str, target: str = "T") -> Circuit:
     if name == "tiny":
         return make_circuit("rot", 2, plain_rounds=1, t_layers=1,
                             framed_rounds=1, final_rounds=0, target=target)
+    if name == "tiny_ghz":
+        return make_circuit("rot", 2, plain_rounds=1, t_layers=1,
+                            framed_rounds=1, final_rounds=0, target=target,
+                            ghz_checks=1, ghz_size=2)
+    if name in ("c1_ghz", "rot3_ghz"):
+        return make_circuit("rot", 3, plain_rounds=2, t_layers=1,
+                            framed_rounds=1, final_rounds=1, target=target,
+                            ghz_checks=2, ghz_size=3)
     raise KeyError(name)

@@ -15,9 +15,12 @@
  *
  * Circuit text format (one op per line, '#' comments):
  *   QUBITS n | ORDER q0 q1 ... (qubit held by MPS site i) | SEED q |
- *   TARGET T|S | H S SDG T TDG X Y Z q | CX CZ a b | M q | R q |
- *   DEP1 q | DEP2 a b | XERR q | TICK
- * Channels (DEP1, DEP2, XERR) and measurements are numbered in text order.
+ *   TARGET T|S | H S SDG T TDG X Y Z q | CX CZ CS CSDG a b | CCZ a b c |
+ *   M q | R q | DEP1 q | DEP2 a b | DEP3 a b c | XERR q | TICK
+ * CS/CSDG are controlled-S and controlled-S^dagger, CCZ the doubly
+ * controlled Z: with T and T^dagger the diagonal non-Clifford gates of the
+ * method (Sections 2 and 4.2).  Channels (DEP1, DEP2, DEP3, XERR) and
+ * measurements are numbered in text order.
  * R is legal only as the first op on a qubit or when the last op on that
  * qubit was M.
  */
@@ -164,9 +167,10 @@ void msc_circuit_free(msc_circuit* c);
    `seed`.  Per shot: weight w = weights[i] if `weights` (host, n_shots) is
    non-NULL, else w ~ Bin(M, p); a uniform w-subset of the M channels
    (Floyd); a uniform non-identity Pauli per chosen channel (3 for DEP1, 15
-   for DEP2, X for XERR).  Output CSR (host): shot_off[n_shots+1] (int64),
-   chan[nnz] (int32, ascending within a shot), pauli[nnz] (uint8, bit0 x_a,
-   bit1 z_a, bit2 x_b, bit3 z_b).  MSC_E_CAPACITY if more than nnz_cap
+   for DEP2, 63 for DEP3, X for XERR).  Output CSR (host):
+   shot_off[n_shots+1] (int64), chan[nnz] (int32, ascending within a shot),
+   pauli[nnz] (uint8, bits 2j and 2j+1 = x and z bit of the channel's j-th
+   qubit, j < 3).  MSC_E_CAPACITY if more than nnz_cap
    faults are needed (nnz_out then holds the required count).            */
 int msc_sample_faults(const msc_circuit* c, uint64_t seed, uint64_t first_shot,
                       int64_t n_shots, const int32_t* weights, double p,
@@ -177,8 +181,9 @@ int msc_sample_faults(const msc_circuit* c, uint64_t seed, uint64_t first_shot,
 /* Offline screening (Section 4.2).                                        */
 
 /* Copy the pre-screen tables to host arrays (either may be NULL):
-   sig[(4*channel + k)*words + j] (k: X_a, Z_a, X_b, Z_b) is the bitmask of
-   decided measurements flipped by that basis fault; decided[i] is the
+   sig[(6*channel + k)*words + j] (k = 2j' + z: X or Z on the channel's
+   j'-th qubit, zero rows for qubits a channel does not have) is the bitmask
+   of decided measurements flipped by that basis fault; decided[i] is the
    measurement index of decided measurement i (n_decided entries).        */
 int msc_prescreen_tables(const msc_circuit* c, uint64_t* sig, int32_t* decided);
 

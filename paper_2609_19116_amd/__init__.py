@@ -103,9 +103,9 @@ def sample_faults(circ: Circuit, seed: int, first_shot: int, n_shots: int,
 
 
 def prescreen_tables(circ: Circuit):
-    """(sig uint64[4*M, words], decided int32[n_decided])."""
+    """(sig uint64[6*M, words], decided int32[n_decided])."""
     inf = circ.info()
-    sig = np.zeros((4 * inf["n_channels"], inf["words"]), dtype=np.uint64)
+    sig = np.zeros((6 * inf["n_channels"], inf["words"]), dtype=np.uint64)
     dec = np.zeros(max(1, inf["n_decided"]), dtype=np.int32)
     _check(lib().msc_prescreen_tables(circ.h, _ptr(sig), _ptr(dec)))
     return sig, dec[:inf["n_decided"]]

@@ -49,6 +49,8 @@ void gate4_matrix(int g, double o[32]) {
         case G4_CX01: one(0, 0); one(1, 1); one(2, 3); one(3, 2); break;   // control s_k
         case G4_CX10: one(0, 0); one(1, 3); one(2, 2); one(3, 1); break;   // control s_{k+1}
         case G4_CZ: one(0, 0); one(1, 1); one(2, 2); o[2 * 15] = -1.0; break;
+        case G4_CS: one(0, 0); one(1, 1); one(2, 2); o[2 * 15 + 1] = 1.0; break;
+        case G4_CSDG: one(0, 0); one(1, 1); one(2, 2); o[2 * 15 + 1] = -1.0; break;
         default: break;
     }
 }
@@ -117,6 +119,7 @@ int parse_circuit(const char* text, size_t len, msc_circuit* c) {
         } else {
             IrOp o{};
             o.b = -1;
+            o.c = -1;
             o.idx = -1;
             static const char* g1n[] = {"H", "S", "SDG", "T", "TDG", "X", "Y", "Z"};
             int g1 = -1;
@@ -127,13 +130,22 @@ int parse_circuit(const char* text, size_t len, msc_circuit* c) {
                 o.kind = IR_G1;
                 o.g = g1;
                 o.a = args[0];
-            } else if (op == "CX" || op == "CZ") {
+            } else if (op == "CX" || op == "CZ" || op == "CS" || op == "CSDG") {
                 if (!need(2) || !qok(args[0]) || !qok(args[1]) || args[0] == args[1])
                     return perr("bad 2q gate operands");
                 o.kind = IR_G2;
-                o.g = op == "CX" ? 0 : 1;
+                o.g = op == "CX" ? G2_CX : op == "CZ" ? G2_CZ : op == "CS" ? G2_CS : G2_CSDG;
                 o.a = args[0];
                 o.b = args[1];
+            } else if (op == "CCZ") {
+                if (!need(3) || !qok(args[0]) || !qok(args[1]) || !qok(args[2]) ||
+                    args[0] == args[1] || args[0] == args[2] || args[1] == args[2])
+                    return perr("bad CCZ operands");
+                o.kind = IR_G3;
+                o.g = 0;
+                o.a = args[0];
+                o.b = args[1];
+                o.c = args[2];
             } else if (op == "M") {
                 if (!need(1) || !qok(args[0])) return perr("bad M operand");
                 o.kind = IR_M;
@@ -157,6 +169,16 @@ int parse_circuit(const char* text, size_t len, msc_circuit* c) {
                 o.a = args[0];
                 o.b = args[1];
                 o.idx = c->n_channels++;
+            } else if (op == "DEP3") {
+                if (!need(3) || !qok(args[0]) || !qok(args[1]) || !qok(args[2]) ||
+                    args[0] == args[1] || args[0] == args[2] || args[1] == args[2])
+                    return perr("bad DEP3 operands");
+                o.kind = IR_CH;
+                o.g = CH_DEP3;
+                o.a = args[0];
+                o.b = args[1];
+                o.c = args[2];
+                o.idx = c->n_channels++;
             } else {
                 return perr("unknown op '" + tok[0] + "'");
             }
@@ -177,12 +199,11 @@ int parse_circuit(const char* text, size_t len, msc_circuit* c) {
         if (o.kind == IR_CH) continue;   // noise does not change legality
         last[o.a] = o.kind;
         if (o.b >= 0) last[o.b] = o.kind;
+        if (o.c >= 0) last[o.c] = o.kind;
     }
     for (const auto& o : c->ir) {
         if (o.kind != IR_CH) continue;
         c->chan_kind.push_back(o.g);
-        c->chan_q0.push_back(o.a);
-        c->chan_q1.push_back(o.b);
     }
     c->expected.assign(c->n_meas, 0);
     return MSC_OK;
@@ -238,6 +259,17 @@ struct Router {
 
 }  // namespace
 
+// CCZ(a, b, c) = diag(1, ..., 1, -1) as CNOT + T gates: the textbook
+// Toffoli network with the target's Hadamards dropped (seven T-type gates,
+// six CNOTs); the MPS applies it gate by gate.
+static void expand_ccz(const IrOp& o, std::vector<IrOp>& out) {
+    auto g1 = [&](int g, int q) { out.push_back({IR_G1, g, q, -1, -1, -1}); };
+    auto cx = [&](int a, int b) { out.push_back({IR_G2, G2_CX, a, b, -1, -1}); };
+    const int a = o.a, b = o.b, t = o.c;
+    cx(b, t); g1(G_TDG, t); cx(a, t); g1(G_T, t); cx(b, t); g1(G_TDG, t); cx(a, t);
+    g1(G_T, b); g1(G_T, t); cx(a, b); g1(G_T, a); g1(G_TDG, b); cx(a, b);
+}
+
 int compile_circuit(msc_circuit* c) {
     const int n = c->n;
     if (c->order.empty()) {
@@ -251,6 +283,13 @@ int compile_circuit(msc_circuit* c) {
             seen[q] = 1;
         }
     }
+    // the router and the scheduler see CCZ as its one- and two-qubit gates
+    std::vector<IrOp> ir;
+    ir.reserve(c->ir.size());
+    for (const auto& o : c->ir) {
+        if (o.kind == IR_G3) expand_ccz(o, ir);
+        else ir.push_back(o);
+    }
     Router R;
     R.site_of.assign(n, 0);
     R.qubit_at = c->order;
@@ -260,10 +299,10 @@ int compile_circuit(msc_circuit* c) {
 
     // index of 2q gates for the mover choice
     std::vector<int> g2pos;
-    for (size_t i = 0; i < c->ir.size(); ++i)
-        if (c->ir[i].kind == IR_G2) g2pos.push_back(static_cast<int>(i));
+    for (size_t i = 0; i < ir.size(); ++i)
+        if (ir[i].kind == IR_G2) g2pos.push_back(static_cast<int>(i));
     auto shares = [&](int i, int j) {
-        const IrOp &x = c->ir[i], &y = c->ir[j];
+        const IrOp &x = ir[i], &y = ir[j];
         if (x.a == y.a || x.a == y.b) return x.a;
         if (x.b == y.a || x.b == y.b) return x.b;
         return -1;
@@ -271,14 +310,15 @@ int compile_circuit(msc_circuit* c) {
     int walker = -1;   // qubit currently away from home (lazy return)
     std::vector<int> last_meas_site_op(n, -1);
     int g2i = 0;
-    for (size_t i = 0; i < c->ir.size(); ++i) {
-        const IrOp& o = c->ir[i];
+    for (size_t i = 0; i < ir.size(); ++i) {
+        const IrOp& o = ir[i];
         switch (o.kind) {
             case IR_G1:
                 R.out.push_back({OP_G1, R.site_of[o.a], -1, o.g});
                 break;
             case IR_CH:
                 R.out.push_back({OP_FAULT, R.site_of[o.a], o.b >= 0 ? R.site_of[o.b] : -1, o.idx});
+                if (o.c >= 0) R.out.push_back({OP_FAULT3, R.site_of[o.c], -1, o.idx});
                 break;
             case IR_M:
                 R.out.push_back({OP_MEAS, R.site_of[o.a], -1, o.idx});
@@ -311,8 +351,10 @@ int compile_circuit(msc_circuit* c) {
                 }
                 int k = std::min(R.site_of[o.a], R.site_of[o.b]);
                 int g;
-                if (o.g == 0) g = (R.site_of[o.a] == k) ? G4_CX01 : G4_CX10;
-                else g = G4_CZ;
+                if (o.g == G2_CX) g = (R.site_of[o.a] == k) ? G4_CX01 : G4_CX10;
+                else if (o.g == G2_CZ) g = G4_CZ;
+                else if (o.g == G2_CS) g = G4_CS;      // diagonal and symmetric
+                else g = G4_CSDG;
                 R.out.push_back({OP_G2, k, -1, g});
                 break;
             }

@@ -2,14 +2,14 @@
 //
 // Pass 1 walks a sign-free stabiliser tableau of the noiseless circuit:
 // Clifford gates conjugate the tracked generators, each diagonal
-// non-Clifford gate (T, T^dagger) keeps the largest subgroup without X/Y on
-// its qubit, and each Z measurement is either decided (Z_q is in the tracked
+// non-Clifford gate (T, T^dagger, CS, CS^dagger, CCZ) keeps the largest
+// subgroup without X/Y on its support, and each Z measurement is either decided (Z_q is in the tracked
 // group) or undecided; an undecided measurement adds +Z_q (only the expected
 // outcome is ever accepted) and gets a destabiliser: a Pauli that
 // anticommutes with Z_q and commutes with every other tracked generator.
 //
-// Pass 2 propagates every basis fault (channel c, component X_a, Z_a, X_b,
-// Z_b) as a Pauli frame, 64 faults per machine word (bit-sliced frames):
+// Pass 2 propagates every basis fault (channel c, component X or Z on each
+// of the channel's up to three qubits) as a Pauli frame, 64 faults per machine word (bit-sliced frames):
 // Cliffords conjugate the frame, diagonal non-Cliffords leave it alone,
 // a decided measurement records whether the frame anticommutes with Z_q
 // (the outcome flips), an undecided one multiplies in the destabiliser where
@@ -189,8 +189,17 @@ int prescreen_compile(msc_circuit* c) {
                 else if (o.g == G_T || o.g == G_TDG) tab.drop_x(o.a);
                 break;
             case IR_G2:
-                if (o.g == 0) tab.cx(o.a, o.b);
-                else tab.cz(o.a, o.b);
+                if (o.g == G2_CX) tab.cx(o.a, o.b);
+                else if (o.g == G2_CZ) tab.cz(o.a, o.b);
+                else {                         // CS, CS^dagger: diagonal
+                    tab.drop_x(o.a);
+                    tab.drop_x(o.b);
+                }
+                break;
+            case IR_G3:                        // CCZ: diagonal
+                tab.drop_x(o.a);
+                tab.drop_x(o.b);
+                tab.drop_x(o.c);
                 break;
             case IR_M: {
                 Pauli zq;
@@ -217,7 +226,8 @@ int prescreen_compile(msc_circuit* c) {
     const int nd = static_cast<int>(c->decided.size());
     const int W = std::max(1, (nd + 63) / 64);
     c->words = W;
-    const int nb = 4 * c->n_channels;
+    constexpr int NC = kFaultComponents;
+    const int nb = NC * c->n_channels;
     c->sig.assign(static_cast<size_t>(nb) * W, 0);
     // channel -> ir position
     std::vector<int> chan_pos(c->n_channels, -1);
@@ -227,17 +237,17 @@ int prescreen_compile(msc_circuit* c) {
     for (int base = 0; base < nb; base += 64) {
         std::fill(fx.begin(), fx.end(), 0);
         std::fill(fz.begin(), fz.end(), 0);
-        int first_chan = base / 4;
-        int last_chan = std::min(c->n_channels - 1, (base + 63) / 4);
+        int first_chan = base / NC;
+        int last_chan = std::min(c->n_channels - 1, (base + 63) / NC);
         for (size_t i = chan_pos[first_chan]; i < c->ir.size(); ++i) {
             const IrOp& o = c->ir[i];
             switch (o.kind) {
                 case IR_CH: {
                     if (o.idx < first_chan || o.idx > last_chan) break;
-                    for (int k = 0; k < 4; ++k) {
-                        int b = 4 * o.idx + k - base;
+                    for (int k = 0; k < NC; ++k) {
+                        int b = NC * o.idx + k - base;
                         if (b < 0 || b >= 64) continue;
-                        int q = (k < 2) ? o.a : o.b;
+                        int q = k < 2 ? o.a : k < 4 ? o.b : o.c;
                         if (q < 0) continue;
                         if (k % 2 == 0) fx[q] ^= 1ull << b;
                         else fz[q] ^= 1ull << b;
@@ -249,14 +259,14 @@ int prescreen_compile(msc_circuit* c) {
                     else if (o.g == G_S || o.g == G_SDG) fz[o.a] ^= fx[o.a];
                     break;   // Paulis and diagonal non-Cliffords: frame unchanged
                 case IR_G2:
-                    if (o.g == 0) {
+                    if (o.g == G2_CX) {
                         fx[o.b] ^= fx[o.a];
                         fz[o.a] ^= fz[o.b];
-                    } else {
+                    } else if (o.g == G2_CZ) {
                         fz[o.a] ^= fx[o.b];
                         fz[o.b] ^= fx[o.a];
                     }
-                    break;
+                    break;   // CS, CS^dagger (and CCZ, IR_G3): frame unchanged
                 case IR_M: {
                     uint64_t m = fx[o.a];
                     if (mclass[o.idx] == M_DECIDED) {

@@ -105,7 +105,8 @@ void draw_shot(const msc_circuit* c, uint64_t seed, uint64_t shot, int64_t w_giv
         uint8_t code;
         if (k == CH_XERR) code = 1;
         else if (k == CH_DEP1) code = static_cast<uint8_t>(1 + rng.bounded(3));
-        else code = static_cast<uint8_t>(1 + rng.bounded(15));
+        else if (k == CH_DEP2) code = static_cast<uint8_t>(1 + rng.bounded(15));
+        else code = static_cast<uint8_t>(1 + rng.bounded(63));
         paulis.push_back(code);
     }
 }

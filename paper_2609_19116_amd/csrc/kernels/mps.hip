@@ -334,6 +334,7 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
         int64_t sweeps_total = 0;
         int64_t fcur = P.shot_off[shot];
         const int64_t fend = P.shot_off[shot + 1];
+        int fcode = 0;     // code of the last channel read (three-qubit faults)
         bool alive = true;
 
         for (int oi = 0; oi < P.n_ops && alive; ++oi) {
@@ -439,19 +440,24 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                     gate_id = G4_I;
                 }
             }
-            if (op.kind == OP_G1 || op.kind == OP_FAULT || op.kind == OP_RESET) {
+            if (op.kind == OP_G1 || op.kind == OP_FAULT || op.kind == OP_FAULT3 ||
+                op.kind == OP_RESET) {
                 // ---- local 2x2 on one site (two for a two-qubit fault)
                 int g0 = -1, g1 = -1;
                 if (op.kind == OP_G1) {
                     g0 = op.aux;
                 } else if (op.kind == OP_RESET) {
                     if (s_laste[op.a] == 1) g0 = G_X;
+                } else if (op.kind == OP_FAULT3) {
+                    const int x2 = (fcode >> 4) & 1, z2 = (fcode >> 5) & 1;
+                    if (x2 | z2) g0 = (x2 && z2) ? G_Y : (x2 ? G_X : G_Z);
                 } else {
                     int code = 0;
                     if (fcur < fend && P.chan[fcur] == op.aux) {
                         code = P.pauli[fcur];
                         ++fcur;
                     }
+                    fcode = code;
                     const int x0 = code & 1, z0 = (code >> 1) & 1;
                     const int x1 = (code >> 2) & 1, z1 = (code >> 3) & 1;
                     if (x0 | z0) g0 = (x0 && z0) ? G_Y : (x0 ? G_X : G_Z);

@@ -1,8 +1,9 @@
 // Offline-screening kernel (Section 4.2): one shot per lane.
 //
 // A shot's signature over the decided measurements is the XOR of the
-// precompiled signatures of its faults' basis components (X_a, Z_a, X_b,
-// Z_b); the shot must be simulated iff that signature is zero.  Each lane
+// precompiled signatures of its faults' basis components (X and Z on each of
+// the channel's up to three qubits); the shot must be simulated iff that
+// signature is zero.  Each lane
 // streams its shot's CSR slice from HBM, XORs <= W-word signatures from the
 // L2-resident table in registers, and the wavefront's verdicts are packed
 // with a 64-lane ballot into one uint64 of the survivor bitmap (lane j of
@@ -39,9 +40,9 @@ __global__ __launch_bounds__(PT) void screen_kernel(int32_t nch, int64_t n,
             const int64_t c = chan[f];
             if (c < 0 || c >= nch) continue;   // not a channel of this circuit
             const int p = pauli[f];
-            const uint64_t* s = sig + c * 4 * W;
+            const uint64_t* s = sig + c * kFaultComponents * W;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < kFaultComponents; ++k) {
                 if ((p >> k) & 1) {
 #pragma unroll
                     for (int w = 0; w < W; ++w) acc[w] ^= s[k * W + w];

@@ -16,14 +16,16 @@ enum OpKind : int32_t {
     OP_G2 = 1,     // a = k (sites k, k+1), b = dir (1: centre -> k+1,
                    // 0: centre -> k), aux = 4x4 gate id (gate4 table)
     OP_FAULT = 2,  // a = site of the channel's first qubit, b = second or -1,
-                   // aux = channel index
+                   // aux = channel index (reads the shot's code for it)
     OP_MEAS = 3,   // a = site, aux = measurement index
     OP_RESET = 4,  // a = site: X^e with e the outcome last projected there
     OP_FINAL = 5,  // a = site of the seed qubit
     OP_SWAPP = 6,  // a = k: SWAP of sites k, k+1 where the qubit on site
                    // k + b (b = 0 or 1) is in a product state with the rest
-    OP_MOVE = 7    // a = k: move the orthogonality centre from k to k+1
+    OP_MOVE = 7,   // a = k: move the orthogonality centre from k to k+1
                    // (b = 1) or from k+1 to k (b = 0)
+    OP_FAULT3 = 8  // a = site of a three-qubit channel's third qubit; uses
+                   // bits 4, 5 of the code read by the OP_FAULT right before
 };
 
 struct DevOp {
@@ -33,16 +35,21 @@ struct DevOp {
 // 1q gate ids (rows of the 2x2 complex table)
 enum Gate1 : int32_t { G_H = 0, G_S, G_SDG, G_T, G_TDG, G_X, G_Y, G_Z, G1_COUNT };
 // 4x4 gate ids in site order |s_k s_{k+1}>
-enum Gate4 : int32_t { G4_I = 0, G4_SWAP, G4_CX01, G4_CX10, G4_CZ, G4_COUNT };
+enum Gate4 : int32_t { G4_I = 0, G4_SWAP, G4_CX01, G4_CX10, G4_CZ, G4_CS, G4_CSDG, G4_COUNT };
 
 // Parsed circuit op (qubit level)
-enum IrKind : int32_t { IR_G1 = 0, IR_G2, IR_M, IR_R, IR_CH };
-enum ChanKind : int32_t { CH_DEP1 = 0, CH_DEP2 = 1, CH_XERR = 2 };
+enum IrKind : int32_t { IR_G1 = 0, IR_G2, IR_M, IR_R, IR_CH, IR_G3 };
+enum ChanKind : int32_t { CH_DEP1 = 0, CH_DEP2 = 1, CH_XERR = 2, CH_DEP3 = 3 };
+// IR_G2 gate codes
+enum Gate2 : int32_t { G2_CX = 0, G2_CZ = 1, G2_CS = 2, G2_CSDG = 3 };
+// basis faults per channel in the screening signatures: X and Z on each of
+// up to three qubits
+constexpr int kFaultComponents = 6;
 struct IrOp {
     int32_t kind;
-    int32_t g;     // IR_G1: Gate1; IR_G2: 0 CX, 1 CZ; IR_CH: ChanKind
-    int32_t a, b;  // qubits (b = -1 if unused)
-    int32_t idx;   // measurement or channel index
+    int32_t g;        // IR_G1: Gate1; IR_G2: Gate2; IR_G3: 0 (CCZ); IR_CH: ChanKind
+    int32_t a, b, c;  // qubits (-1 if unused)
+    int32_t idx;      // measurement or channel index
 };
 
 void gate1_matrix(int g, double out[8]);    // (re,im) row-major 2x2
@@ -61,7 +68,6 @@ struct msc_circuit {
     std::vector<msc::IrOp> ir;
     int n_meas = 0, n_channels = 0;
     std::vector<int32_t> chan_kind;
-    std::vector<int32_t> chan_q0, chan_q1;
     // compiled MPS op stream
     std::vector<msc::DevOp> ops;
     int64_t n_twosite = 0, n_swaps = 0, n_product_swaps = 0, n_moves = 0;
@@ -72,7 +78,7 @@ struct msc_circuit {
     // offline screening tables
     int words = 0;
     std::vector<int32_t> decided;        // measurement index per decided slot
-    std::vector<uint64_t> sig;           // [4*n_channels][words]
+    std::vector<uint64_t> sig;           // [6*n_channels][words]
     // device copies (owned), on device `dev`
     int dev = -1;
     void* d_ops = nullptr;

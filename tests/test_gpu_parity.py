@@ -59,7 +59,7 @@ def _compare(res, ref, tol):
 
 
 def test_calibration_all_circuits(ctx):
-    for name in ("tiny", "c1", "c3"):
+    for name in ("tiny", "c1", "c3", "tiny_ghz", "c1_ghz"):
         for tg in ("T", "S"):
             cc, c = _circuit(ctx, name, tg)
             inf = c.info()
@@ -68,8 +68,10 @@ def test_calibration_all_circuits(ctx):
 
 
 @pytest.mark.parametrize("precision", [MSC_FP64, MSC_FP32])
-@pytest.mark.parametrize("name", ["tiny", "c1"])
+@pytest.mark.parametrize("name", ["tiny", "c1", "tiny_ghz", "c1_ghz"])
 def test_parity_small_circuits(ctx, name, precision):
+    # the *_ghz circuits add GHZ-controlled checks made of CS, CS^dagger,
+    # CCZ (a CNOT + T network on the MPS) and three-qubit channels
     cc, c = _circuit(ctx, name)
     n = 160
     w = np.arange(n) % 5                       # subset sampling w = 0..4
@@ -156,7 +158,8 @@ def test_uncalibrated_circuit_is_refused(ctx):
 
 
 @pytest.mark.parametrize("name,n,p", [("c1", 20000, 1e-2), ("c3", 6000, 2e-3),
-                                      ("c4", 1500, 1e-3), ("tiny", 4097, 5e-2)])
+                                      ("c4", 1500, 1e-3), ("tiny", 4097, 5e-2),
+                                      ("c1_ghz", 8000, 1e-2), ("tiny_ghz", 3000, 5e-2)])
 def test_prescreen_bit_exact(ctx, name, n, p):
     cc = config_circuit(name)
     c = msc.Circuit(cc.text)

@@ -14,6 +14,8 @@ import paper_2609_19116_amd as msc
 from paper_2609_19116_amd import _lib
 from tests.helpers import oracle_csr, oracle_discards
 from oracle import estimators as est
+from oracle import prescreen as ops
+from oracle.ir import parse
 from workloads.circuits import config_circuit
 
 ROOT = Path(__file__).resolve().parent.parent
@@ -43,6 +45,10 @@ def test_struct_sizes_match_header():
     ("QUBITS 2\nH 0\nR 0\n", "not at start"),
     ("QUBITS 2\nORDER 0 0\n", "permutation"),
     ("QUBITS 2\nTARGET Q\n", "TARGET"),
+    ("QUBITS 3\nCCZ 0 1 1\n", "CCZ"),
+    ("QUBITS 3\nCCZ 0 1\n", "CCZ"),
+    ("QUBITS 3\nDEP3 0 2 2\n", "DEP3"),
+    ("QUBITS 3\nCS 1 1\n", "2q gate"),
 ])
 def test_parse_errors(text, frag):
     with pytest.raises(msc.MscError) as e:
@@ -56,7 +62,7 @@ def test_reset_after_measure_is_legal_and_compiles():
     assert inf["n_meas"] == 2 and inf["n_channels"] == 1
 
 
-@pytest.mark.parametrize("name", ["tiny", "c1", "c3", "c4"])
+@pytest.mark.parametrize("name", ["tiny", "c1", "c3", "c4", "tiny_ghz", "c1_ghz"])
 def test_circuit_info(name):
     cc = config_circuit(name)
     inf = msc.Circuit(cc.text).info()
@@ -83,6 +89,7 @@ def test_ctx_without_gpu_fails_cleanly():
     ("c3", 0x5EED0003, 200, 1e-3, None),
     ("c4", 0x5EED0004, 100, 1e-3, None),
     ("tiny", 17, 300, 0.2, None),
+    ("c1_ghz", 0x5EED0006, 400, 2e-2, None),
 ])
 def test_sampler_matches_oracle_twin(name, seed, n, p, weights):
     cc = config_circuit(name)
@@ -106,7 +113,47 @@ def test_sampler_capacity_error():
     assert rc == _lib.MSC_E_CAPACITY and nnz.value == 30
 
 
-@pytest.mark.parametrize("name,n,p", [("c1", 3000, 1e-2), ("c3", 800, 3e-3), ("tiny", 1000, 0.1)])
+def _canonical_columns(sig):
+    """Decided-measurement columns (ints over basis faults), each reduced
+    modulo the span of the earlier columns.  Adding an earlier decided
+    column to a later one leaves the discard rule unchanged (the shot is
+    already discarded when the earlier measurement flips), so two tables
+    define the same screen iff their canonical columns are equal."""
+    nd = sig.shape[1] * 64
+    cols = []
+    for d in range(nd):
+        bits = (sig[:, d >> 6] >> np.uint64(d & 63)) & np.uint64(1)
+        cols.append(int("".join("1" if b else "0" for b in bits[::-1]) or "0", 2))
+    basis = {}                       # pivot bit -> vector (reduced echelon)
+    out = []
+    for v in cols:
+        for pb, bv in basis.items():
+            if v >> pb & 1:
+                v ^= bv
+        out.append(v)
+        if v:
+            pb = v.bit_length() - 1
+            for k in list(basis):
+                if basis[k] >> pb & 1:
+                    basis[k] ^= v
+            basis[pb] = v
+    return out
+
+
+@pytest.mark.parametrize("name", ["tiny", "c1", "tiny_ghz", "c1_ghz"])
+def test_prescreen_signatures_equal_oracle_table(name):
+    cc = config_circuit(name)
+    sig, dec = msc.prescreen_tables(msc.Circuit(cc.text))
+    circ = parse(cc.text)
+    odec, flips = ops.analyse(circ)
+    assert list(dec) == [m for m, d in enumerate(odec) if d]
+    ref = ops.signature_table(circ, odec, flips)
+    assert sig.shape == ref.shape
+    assert _canonical_columns(sig) == _canonical_columns(ref)
+
+
+@pytest.mark.parametrize("name,n,p", [("c1", 3000, 1e-2), ("c3", 800, 3e-3), ("tiny", 1000, 0.1),
+                                      ("c1_ghz", 1500, 1e-2)])
 def test_prescreen_tables_match_oracle(name, n, p):
     cc = config_circuit(name)
     c = msc.Circuit(cc.text)
@@ -118,9 +165,9 @@ def test_prescreen_tables_match_oracle(name, n, p):
     for i in range(n):
         acc = np.zeros(sig.shape[1], dtype=np.uint64)
         for cc_, code in zip(ch[off[i]:off[i + 1]], pa[off[i]:off[i + 1]]):
-            for k in range(4):
+            for k in range(6):
                 if code >> k & 1:
-                    acc ^= sig[4 * cc_ + k]
+                    acc ^= sig[6 * cc_ + k]
         got[i] = acc.any()
     assert np.array_equal(got, ref)
     assert ref.any() and not ref.all()

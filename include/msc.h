@@ -177,6 +177,19 @@ int msc_sample_faults(const msc_circuit* c, uint64_t seed, uint64_t first_shot,
                       int64_t* shot_off, int32_t* chan, uint8_t* pauli,
                       int64_t nnz_cap, int64_t* nnz_out);
 
+/* The same draws on the context's GPU, one shot per lane: the CSR is
+   bit-identical to msc_sample_faults for the same arguments.  weights
+   (device, n_shots int32) or NULL for w ~ Bin(M, p); shot_off (device,
+   n_shots+1 int64), chan and pauli (device, nnz_cap entries; may be NULL
+   only if nnz_cap is 0).  nnz_out (host) receives the total fault count.
+   MSC_E_CAPACITY if it exceeds nnz_cap: shot_off is then complete, chan
+   and pauli hold only the shots that fit (never written past nnz_cap).   */
+int msc_sample_faults_device(msc_ctx* ctx, const msc_circuit* c, uint64_t seed,
+                             uint64_t first_shot, int64_t n_shots,
+                             const int32_t* weights, double p, int64_t* shot_off,
+                             int32_t* chan, uint8_t* pauli, int64_t nnz_cap,
+                             int64_t* nnz_out);
+
 /* ---------------------------------------------------------------------- */
 /* Offline screening (Section 4.2).                                        */
 

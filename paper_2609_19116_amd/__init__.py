@@ -102,6 +102,41 @@ def sample_faults(circ: Circuit, seed: int, first_shot: int, n_shots: int,
         return off, chan[:nnz.value].copy(), pa[:nnz.value].copy()
 
 
+def sample_faults_device(ctx: Ctx, circ: Circuit, seed: int, first_shot: int, n_shots: int,
+                         weights=None, p: float = 0.0, nnz_cap=None):
+    """Device CSR (shot_off int64, chan int32, pauli uint8 torch tensors on
+    the context's GPU), bit-identical to sample_faults.  ``weights`` may be
+    a host array or a device int32 tensor."""
+    import torch
+    dev = torch.device("cuda", ctx.device)
+    M = circ.info()["n_channels"]
+    w = None
+    if weights is not None:
+        if isinstance(weights, torch.Tensor):
+            w = weights.to(device=dev, dtype=torch.int32).contiguous()
+            need = int(w.clamp(0, M).sum().item()) if n_shots else 0
+        else:
+            wn = np.ascontiguousarray(weights, dtype=np.int32)
+            need = int(np.clip(wn[:n_shots], 0, M).sum())
+            w = torch.from_numpy(wn).to(dev)
+        cap = need if nnz_cap is None else nnz_cap
+    else:
+        mean = n_shots * M * p
+        cap = int(mean + 8.0 * np.sqrt(mean + 1.0) + 64) if nnz_cap is None else nnz_cap
+    off = torch.empty(n_shots + 1, dtype=torch.int64, device=dev)
+    while True:
+        chan = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        pa = torch.empty(max(cap, 1), dtype=torch.uint8, device=dev)
+        nnz = C.c_int64()
+        rc = lib().msc_sample_faults_device(ctx.h, circ.h, seed, first_shot, n_shots, _ptr(w), p,
+                                            _ptr(off), _ptr(chan), _ptr(pa), cap, C.byref(nnz))
+        if rc == -4 and nnz_cap is None:   # capacity: retry with the exact size
+            cap = nnz.value
+            continue
+        _check(rc)
+        return off, chan[:nnz.value], pa[:nnz.value]
+
+
 def prescreen_tables(circ: Circuit):
     """(sig uint64[6*M, words], decided int32[n_decided])."""
     inf = circ.info()

@@ -82,6 +82,9 @@ _SIGS = {
     "msc_circuit_free": (None, [_P]),
     "msc_sample_faults": (C.c_int, [_P, C.c_uint64, C.c_uint64, C.c_int64, _P, C.c_double,
                                     _P, _P, _P, C.c_int64, C.POINTER(C.c_int64)]),
+    "msc_sample_faults_device": (C.c_int, [_P, _P, C.c_uint64, C.c_uint64, C.c_int64, _P,
+                                           C.c_double, _P, _P, _P, C.c_int64,
+                                           C.POINTER(C.c_int64)]),
     "msc_prescreen_tables": (C.c_int, [_P, _P, _P]),
     "msc_prescreen": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P, _P, _P, C.POINTER(C.c_int64)]),
     "msc_simulate": (C.c_int, [_P, _P, C.POINTER(SimOpts), C.c_int64, _P, _P, _P, _P,

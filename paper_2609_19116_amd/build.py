@@ -26,6 +26,7 @@ SOURCES = [
     CSRC / "host" / "capi.cpp",
     CSRC / "kernels" / "mps.hip",
     CSRC / "kernels" / "prescreen.hip",
+    CSRC / "kernels" / "sampler.hip",
     CSRC / "kernels" / "twosite.hip",
 ]
 

@@ -154,7 +154,7 @@ extern "C" int msc_circuit_expected(const msc_circuit* c, uint8_t* out) {
 static void free_device(msc_circuit* c) {
     if (c->dev < 0) return;
     (void)hipSetDevice(c->dev);
-    for (void** p : {&c->d_ops, &c->d_g1, &c->d_g4, &c->d_sig, &c->d_expected}) {
+    for (void** p : {&c->d_ops, &c->d_g1, &c->d_g4, &c->d_sig, &c->d_expected, &c->d_kind}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
@@ -186,6 +186,8 @@ static int upload(msc_ctx* ctx, msc_circuit* c) {
     if ((rc = put(&c->d_g4, g4.data(), g4.size() * sizeof(double)))) return rc;
     if ((rc = put(&c->d_sig, c->sig.data(), c->sig.size() * sizeof(uint64_t)))) return rc;
     if ((rc = put(&c->d_expected, c->expected.data(), c->expected.size()))) return rc;
+    std::vector<uint8_t> kind(c->chan_kind.begin(), c->chan_kind.end());
+    if ((rc = put(&c->d_kind, kind.data(), kind.size()))) return rc;
     return MSC_OK;
 }
 
@@ -404,6 +406,53 @@ extern "C" int msc_prescreen(msc_ctx* ctx, const msc_circuit* c, int64_t n_shots
     MSC_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
     ctx->last_ms["prescreen"] = ms;
     *n_survivors = cnt;
+    return MSC_OK;
+}
+
+extern "C" int msc_sample_faults_device(msc_ctx* ctx, const msc_circuit* c, uint64_t seed,
+                                        uint64_t first_shot, int64_t n_shots,
+                                        const int32_t* weights, double p, int64_t* shot_off,
+                                        int32_t* chan, uint8_t* pauli, int64_t nnz_cap,
+                                        int64_t* nnz_out) {
+    if (!ctx || !c || n_shots < 0 || !shot_off || !nnz_out || nnz_cap < 0)
+        return set_error(MSC_E_INVALID, "null argument");
+    if ((!chan || !pauli) && nnz_cap > 0) return set_error(MSC_E_INVALID, "null chan/pauli");
+    if (!weights && !(p >= 0.0 && p <= 1.0)) return set_error(MSC_E_INVALID, "p outside [0,1]");
+    *nnz_out = 0;
+    MSC_HIP(hipSetDevice(ctx->device));
+    int rc = upload(ctx, const_cast<msc_circuit*>(c));
+    if (rc) return rc;
+    if (n_shots == 0) {
+        const int64_t zero = 0;
+        MSC_HIP(hipMemcpy(shot_off, &zero, sizeof(zero), hipMemcpyHostToDevice));
+        return MSC_OK;
+    }
+    std::vector<double> cdf;
+    void* dcdf = nullptr;
+    if (!weights) {
+        cdf = binomial_cdf(c->n_channels, p);
+        if ((rc = ctx_buf(ctx, "cdf", cdf.size() * sizeof(double), &dcdf))) return rc;
+        MSC_HIP(hipMemcpyAsync(dcdf, cdf.data(), cdf.size() * sizeof(double),
+                               hipMemcpyHostToDevice, ctx->stream));
+    }
+    const int64_t nt = sampler_tmp_words(n_shots);
+    void* tmp;
+    if ((rc = ctx_buf(ctx, "sample_tmp", nt * sizeof(int64_t), &tmp))) return rc;
+    MSC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
+    MSC_HIP(launch_sampler(n_shots, seed, first_shot, weights, static_cast<const double*>(dcdf),
+                           static_cast<int32_t>(cdf.size()), c->n_channels,
+                           static_cast<const uint8_t*>(c->d_kind), nnz_cap, shot_off, chan, pauli,
+                           static_cast<int64_t*>(tmp), nt, ctx->stream));
+    MSC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
+    int64_t total = 0;
+    MSC_HIP(hipMemcpyAsync(&total, static_cast<int64_t*>(tmp) + (nt - 1), sizeof(int64_t),
+                           hipMemcpyDeviceToHost, ctx->stream));
+    MSC_HIP(hipStreamSynchronize(ctx->stream));
+    float ms = 0.f;
+    MSC_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    ctx->last_ms["sample"] = ms;
+    *nnz_out = total;
+    if (total > nnz_cap) return set_error(MSC_E_CAPACITY, "nnz_cap too small");
     return MSC_OK;
 }
 

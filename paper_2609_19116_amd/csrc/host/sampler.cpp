@@ -56,6 +56,8 @@ double pow_int(double x, int64_t k) {
     return r;
 }
 
+}  // namespace
+
 std::vector<double> binomial_cdf(int64_t M, double p) {
     double q = 1.0 - p;
     double b = pow_int(q, M);
@@ -70,6 +72,8 @@ std::vector<double> binomial_cdf(int64_t M, double p) {
     }
     return cdf;
 }
+
+namespace {
 
 struct ShotDraw {
     std::vector<int32_t> chan;

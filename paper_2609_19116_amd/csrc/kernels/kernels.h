@@ -58,6 +58,14 @@ hipError_t launch_prescreen(int words, int32_t n_channels, int64_t n, const int6
                             hipStream_t s);
 int64_t prescreen_tmp_words(int64_t n);
 
+// device fault sampler: CSR of shots first .. first+n-1 (see sampler.hip);
+// tmp holds sampler_tmp_words(n) int64, its last used entry the nnz total
+hipError_t launch_sampler(int64_t n, uint64_t seed, uint64_t first, const int32_t* weights,
+                          const double* cdf, int32_t n_cdf, int64_t M, const uint8_t* kind,
+                          int64_t nnz_cap, int64_t* shot_off, int32_t* chan, uint8_t* pauli,
+                          int64_t* tmp, int64_t n_tmp, hipStream_t s);
+int64_t sampler_tmp_words(int64_t n);
+
 hipError_t launch_twosite(int precision, int chi, int batch, const float* A, const float* B,
                           const float* gate, float* theta, hipStream_t s);
 

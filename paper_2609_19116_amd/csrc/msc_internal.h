@@ -55,6 +55,9 @@ struct IrOp {
 void gate1_matrix(int g, double out[8]);    // (re,im) row-major 2x2
 void gate4_matrix(int g, double out[32]);   // (re,im) row-major 4x4
 
+// FP64 cumulative Bin(M, p) table of the sampler (sampler.cpp)
+std::vector<double> binomial_cdf(int64_t M, double p);
+
 // Error helpers (capi.cpp)
 int set_error(int code, const std::string& msg);
 
@@ -86,6 +89,7 @@ struct msc_circuit {
     void* d_g4 = nullptr;
     void* d_sig = nullptr;
     void* d_expected = nullptr;
+    void* d_kind = nullptr;              // uint8 ChanKind per channel
 };
 
 namespace msc {

@@ -93,6 +93,13 @@ typedef struct {
     int32_t n_slots;      /* persistent workgroups; 0 = auto                 */
     int32_t lds_width;    /* largest two-site SVD side kept in LDS: 32 or 64;
                              larger sides use the slot's HBM scratch; 0 = 32 */
+    int32_t prefix;       /* 1: fork every shot from a checkpoint of the
+                             noiseless run taken before its first fault (w = 0
+                             shots from the one before the read-out); the
+                             checkpoints are built once per circuit and option
+                             set (first call) and results are bit-identical
+                             to prefix = 0.  0: every shot from |0...0>.     */
+    int32_t reserved;     /* must be 0                                       */
 } msc_sim_opts;
 
 typedef struct {

@@ -162,7 +162,8 @@ def prescreen(ctx: Ctx, circ: Circuit, off, chan, pauli, with_index: bool = True
 
 def simulate(ctx: Ctx, circ: Circuit, off, chan, pauli, shot_idx=None, precision=MSC_FP64,
              chi_max: int = 256, tau_trunc: float = 0.0, tau_rej: float = 1e-6,
-             tau_fail: float = 1e-4, n_slots: int = 0, lds_width: int = 0, out=None):
+             tau_fail: float = 1e-4, n_slots: int = 0, lds_width: int = 0, prefix: bool = False,
+             out=None):
     """Simulate shots (device CSR); returns a uint8 device tensor holding
     msc_shot_result records (view them with ``results_numpy``)."""
     import torch
@@ -170,7 +171,8 @@ def simulate(ctx: Ctx, circ: Circuit, off, chan, pauli, shot_idx=None, precision
     n = shot_idx.numel() if shot_idx is not None else n_shots
     if out is None:
         out = torch.empty(max(n, 1) * SHOT_DTYPE.itemsize, dtype=torch.uint8, device=off.device)
-    o = SimOpts(precision, chi_max, tau_trunc, tau_rej, tau_fail, n_slots, lds_width)
+    o = SimOpts(precision, chi_max, tau_trunc, tau_rej, tau_fail, n_slots, lds_width,
+                1 if prefix else 0, 0)
     _check(lib().msc_simulate(ctx.h, circ.h, C.byref(o), n_shots, _ptr(off), _ptr(chan),
                               _ptr(pauli), _ptr(shot_idx), n, _ptr(out)))
     return out[: n * SHOT_DTYPE.itemsize]

@@ -45,7 +45,7 @@ class CircuitInfo(C.Structure):
 class SimOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("chi_max", C.c_int32), ("tau_trunc", C.c_double),
                 ("tau_rej", C.c_double), ("tau_fail", C.c_double), ("n_slots", C.c_int32),
-                ("lds_width", C.c_int32)]
+                ("lds_width", C.c_int32), ("prefix", C.c_int32), ("reserved", C.c_int32)]
 
 
 class ShotResult(C.Structure):

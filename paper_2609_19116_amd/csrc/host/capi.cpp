@@ -151,7 +151,19 @@ extern "C" int msc_circuit_expected(const msc_circuit* c, uint8_t* out) {
     return MSC_OK;
 }
 
+static void free_prefix(PrefixCk& pk) {
+    if (pk.dev >= 0) {
+        (void)hipSetDevice(pk.dev);
+        for (void** p : {&pk.d_op, &pk.d_avail, &pk.d_off, &pk.d_hdr, &pk.d_data}) {
+            if (*p) (void)hipFree(*p);
+            *p = nullptr;
+        }
+    }
+    pk = PrefixCk();
+}
+
 static void free_device(msc_circuit* c) {
+    free_prefix(c->prefix);
     if (c->dev < 0) return;
     (void)hipSetDevice(c->dev);
     for (void** p : {&c->d_ops, &c->d_g1, &c->d_g4, &c->d_sig, &c->d_expected, &c->d_kind}) {
@@ -239,7 +251,8 @@ static int run_shots(msc_ctx* ctx, const msc_circuit* c, int precision, int chi_
                      double tau_rej, double tau_fail, int n_slots, int lds_width, int64_t n,
                      int64_t n_csr, const int64_t* off, const int32_t* chan, const uint8_t* pauli,
                      const int64_t* shot_idx, msc_shot_result* out, int calibrate,
-                     double* cal_p, uint8_t* cal_e, const char* timer) {
+                     double* cal_p, uint8_t* cal_e, const char* timer, int ck_mode = 0,
+                     const PrefixCk* pk = nullptr) {
     Layout L = make_layout(c->n, chi_max);
     const bool small = lds_width == 32;
     if (n_slots <= 0) n_slots = ctx->n_cu * mps_blocks_per_cu(precision, small);
@@ -295,8 +308,20 @@ static int run_shots(msc_ctx* ctx, const msc_circuit* c, int precision, int chi_
     a.calibrate = calibrate;
     a.cal_p = cal_p;
     a.cal_e = cal_e;
+    a.ck_mode = pk ? ck_mode : 0;
+    if (a.ck_mode) {
+        a.n_ck = pk->n_ck;
+        a.ck_k = pk->ck_k;
+        a.ck_op = static_cast<const int32_t*>(pk->d_op);
+        a.ck_avail = static_cast<int32_t*>(pk->d_avail);
+        a.ck_off = static_cast<int64_t*>(pk->d_off);
+        a.ck_hdr = static_cast<CkHdr*>(pk->d_hdr);
+        a.ck_data = pk->d_data;
+        a.ck_cap = pk->cap;
+    }
     MSC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
-    MSC_HIP(launch_order(n, off, shot_idx, n_csr, static_cast<int64_t*>(dperm), ctx->stream));
+    MSC_HIP(launch_order(n, off, shot_idx, n_csr, chan, a.ck_mode == 2 ? c->n_channels : 0,
+                         static_cast<int64_t*>(dperm), ctx->stream));
     MSC_HIP(launch_mps(precision, small, a, n_slots, ctx->stream));
     MSC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
     MSC_HIP(hipStreamSynchronize(ctx->stream));
@@ -346,6 +371,87 @@ extern "C" int msc_circuit_calibrate(msc_ctx* ctx, msc_circuit* c) {
     for (int m = 0; m < c->n_meas; ++m) c->expected[m] = e[m];
     MSC_HIP(hipMemcpy(c->d_expected, c->expected.data(), c->n_meas, hipMemcpyHostToDevice));
     c->calibrated = true;
+    free_prefix(c->prefix);   // checkpoints follow the expected outcomes
+    return MSC_OK;
+}
+
+// Checkpoints of the noiseless run (the shot with no fault) in the batch's
+// precision and kernel variant: one before the fault op of every ck_k-th
+// channel (ck_k chosen for at most 256 of them) and one before the final
+// read-out, written densely while they fit in kPrefixBytes.  A shot whose
+// first fault is on channel c forks from checkpoint c / ck_k; the ops it
+// skips are exactly the fault-free ops it would have run, in the same
+// kernel with the same arithmetic, so its result does not change.
+static constexpr int64_t kPrefixBytes = int64_t(2) << 30;
+
+static int ensure_prefix(msc_ctx* ctx, msc_circuit* c, int precision, int chi_max, double tau,
+                         double tau_rej, double tau_fail, int lds_width) {
+    PrefixCk& pk = c->prefix;
+    if (pk.valid && pk.dev == ctx->device && pk.precision == precision &&
+        pk.chi_max == chi_max && pk.lds_width == lds_width && pk.tau == tau &&
+        pk.tau_rej == tau_rej)
+        return MSC_OK;
+    free_prefix(pk);
+    pk.dev = ctx->device;
+    const int M = c->n_channels;
+    pk.ck_k = std::max(1, (M + 255) / 256);
+    const int n_reg = (M + pk.ck_k - 1) / pk.ck_k;
+    pk.n_ck = n_reg + 1;
+    std::vector<int32_t> ck_op(pk.n_ck);
+    for (int j = 0; j < n_reg; ++j) ck_op[j] = c->chan_op[static_cast<size_t>(j) * pk.ck_k];
+    ck_op[n_reg] = static_cast<int32_t>(c->ops.size()) - 1;   // OP_FINAL
+    for (int j = 0; j + 1 < pk.n_ck; ++j)
+        if (!(ck_op[j] >= 0 && ck_op[j] < ck_op[j + 1]))
+            return set_error(MSC_E_INVALID, "checkpoint ops not increasing");
+    const size_t tsize = precision == MSC_FP64 ? sizeof(double) : sizeof(float);
+    pk.cap = kPrefixBytes / static_cast<int64_t>(tsize);
+    auto dmalloc = [&](void** p, size_t bytes) -> int {
+        hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 64));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            *p = nullptr;
+            return set_error(MSC_E_OOM, std::string("checkpoints: ") + hipGetErrorString(e));
+        }
+        return MSC_OK;
+    };
+    int rc;
+    if ((rc = dmalloc(&pk.d_op, pk.n_ck * sizeof(int32_t)))) return rc;
+    if ((rc = dmalloc(&pk.d_avail, sizeof(int32_t)))) return rc;
+    if ((rc = dmalloc(&pk.d_off, pk.n_ck * sizeof(int64_t)))) return rc;
+    if ((rc = dmalloc(&pk.d_hdr, pk.n_ck * sizeof(CkHdr)))) return rc;
+    if ((rc = dmalloc(&pk.d_data, static_cast<size_t>(pk.cap) * tsize))) return rc;
+    const int32_t zero = 0;
+    MSC_HIP(hipMemcpy(pk.d_op, ck_op.data(), pk.n_ck * sizeof(int32_t), hipMemcpyHostToDevice));
+    MSC_HIP(hipMemcpy(pk.d_avail, &zero, sizeof(zero), hipMemcpyHostToDevice));
+    void *doff, *dchan, *dpa, *dout;
+    if ((rc = ctx_buf(ctx, "cal_off", 2 * sizeof(int64_t), &doff))) return rc;
+    if ((rc = ctx_buf(ctx, "cal_chan", 64, &dchan))) return rc;
+    if ((rc = ctx_buf(ctx, "cal_pa", 64, &dpa))) return rc;
+    if ((rc = ctx_buf(ctx, "cal_out", sizeof(msc_shot_result), &dout))) return rc;
+    int64_t zz[2] = {0, 0};
+    MSC_HIP(hipMemcpy(doff, zz, sizeof(zz), hipMemcpyHostToDevice));
+    rc = run_shots(ctx, c, precision, chi_max, tau, tau_rej, tau_fail, 1, lds_width, 1, 1,
+                   static_cast<int64_t*>(doff), static_cast<int32_t*>(dchan),
+                   static_cast<uint8_t*>(dpa), nullptr, static_cast<msc_shot_result*>(dout), 0,
+                   nullptr, nullptr, "prefix", 1, &pk);
+    if (rc) {
+        free_prefix(pk);
+        return rc;
+    }
+    MSC_HIP(hipMemcpy(&pk.avail, pk.d_avail, sizeof(int32_t), hipMemcpyDeviceToHost));
+    msc_shot_result res;
+    MSC_HIP(hipMemcpy(&res, dout, sizeof(res), hipMemcpyDeviceToHost));
+    if (!(res.status & MSC_SHOT_DONE)) {
+        free_prefix(pk);
+        return set_error(MSC_E_NONDETERMINISTIC, "noiseless run rejected in the batch precision");
+    }
+    pk.precision = precision;
+    pk.chi_max = chi_max;
+    pk.lds_width = lds_width;
+    pk.tau = tau;
+    pk.tau_rej = tau_rej;
+    pk.build_ms = static_cast<float>(ctx->last_ms["prefix"]);
+    pk.valid = true;
     return MSC_OK;
 }
 
@@ -372,9 +478,18 @@ extern "C" int msc_simulate(msc_ctx* ctx, const msc_circuit* c, const msc_sim_op
     double tau_fail = opts->tau_fail > 0 ? opts->tau_fail : 1e-4;
     if (opts->lds_width != 0 && opts->lds_width != 32 && opts->lds_width != 64)
         return set_error(MSC_E_INVALID, "lds_width must be 0, 32 or 64");
+    if (opts->prefix != 0 && opts->prefix != 1) return set_error(MSC_E_INVALID, "prefix must be 0 or 1");
+    if (opts->reserved != 0) return set_error(MSC_E_INVALID, "reserved must be 0");
+    const int lds_width = opts->lds_width == 64 ? 64 : 32;
+    if (opts->prefix) {
+        rc = ensure_prefix(ctx, const_cast<msc_circuit*>(c), opts->precision, opts->chi_max, tau,
+                           tau_rej, tau_fail, lds_width);
+        if (rc) return rc;
+    }
     return run_shots(ctx, c, opts->precision, opts->chi_max, tau, tau_rej, tau_fail,
-                     opts->n_slots, opts->lds_width == 64 ? 64 : 32, n, n_shots, shot_off, chan, pauli, shot_idx, out, 0,
-                     nullptr, nullptr, "simulate");
+                     opts->n_slots, lds_width, n, n_shots, shot_off, chan, pauli, shot_idx, out, 0,
+                     nullptr, nullptr, "simulate", opts->prefix ? 2 : 0,
+                     opts->prefix ? &c->prefix : nullptr);
 }
 
 extern "C" int msc_prescreen(msc_ctx* ctx, const msc_circuit* c, int64_t n_shots,

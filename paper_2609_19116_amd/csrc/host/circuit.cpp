@@ -383,6 +383,7 @@ int compile_circuit(msc_circuit* c) {
     for (int i = static_cast<int>(R.out.size()) - 1; i >= 0; --i)
         next_need[i] = needs(R.out[i]) ? i : next_need[i + 1];
     c->ops.clear();
+    c->chan_op.assign(c->n_channels, -1);
     c->n_twosite = 0;
     c->n_moves = 0;
     int centre = 0;
@@ -401,6 +402,7 @@ int compile_circuit(msc_circuit* c) {
     for (size_t i = 0; i < R.out.size(); ++i) {
         LOp o = R.out[i];
         if (!needs(o)) {
+            if (o.kind == OP_FAULT) c->chan_op[o.aux] = static_cast<int32_t>(c->ops.size());
             c->ops.push_back({o.kind, o.a, o.b, o.aux});
             // the unentangled qubit's partner takes over the centre
             if (o.kind == OP_SWAPP && (centre == o.a || centre == o.a + 1)) centre = o.a + o.b;

@@ -12,6 +12,16 @@ namespace msc {
 constexpr int kMaxSites = 128;     // MPS sites per circuit
 constexpr int kMaxChiKernel = 256; // bond cap handled by the shot kernel
 
+// Header of one noiseless-prefix checkpoint: the shot state right before a
+// given op of the noiseless run (the tensors themselves are stored densely,
+// site after site, real plane then imaginary plane, at ck_off[j]).
+struct CkHdr {
+    double p_acc, disc;
+    int32_t chi_peak, status;
+    int32_t chi[kMaxSites + 1];
+    int32_t laste[kMaxSites];
+};
+
 struct MpsArgs {
     const DevOp* ops;
     int32_t n_ops;
@@ -42,13 +52,27 @@ struct MpsArgs {
     int32_t calibrate;         // 1: choose the likelier outcome and record it
     double* cal_p;             // [n_meas] probability of the chosen outcome
     uint8_t* cal_e;            // [n_meas] chosen outcome
+    // noiseless-prefix checkpoints: ck_mode 0 off, 1 record them from the
+    // (single, fault-free) shot, 2 start every shot from one of them
+    int32_t ck_mode;
+    int32_t n_ck;              // checkpoint j < n_ck - 1 sits before the fault
+                               // op of channel j * ck_k, the last before OP_FINAL
+    int32_t ck_k;
+    const int32_t* ck_op;      // [n_ck] op index of each checkpoint
+    int32_t* ck_avail;         // checkpoints written (record) / usable (fork)
+    int64_t* ck_off;           // [n_ck] element offset of each checkpoint's tensors
+    CkHdr* ck_hdr;             // [n_ck]
+    void* ck_data;             // ck_cap elements of T
+    int64_t ck_cap;
 };
 
 // precision: MSC_FP64 or MSC_FP32; small: use the 32-wide LDS variant
 hipError_t launch_mps(int precision, bool small, const MpsArgs& a, int grid, hipStream_t s);
-// perm[0..n): stable order of the shots by fault count, fewest first
+// perm[0..n): stable order of the shots, by fault count (fewest first) or,
+// with n_channels > 0, by first faulty channel (earliest first, fault-free
+// shots last): the order in which their remaining work shrinks
 hipError_t launch_order(int64_t n, const int64_t* shot_off, const int64_t* shot_idx, int64_t n_csr,
-                        int64_t* perm, hipStream_t s);
+                        const int32_t* chan, int32_t n_channels, int64_t* perm, hipStream_t s);
 // resident workgroups per CU of the chosen variant (sizes the persistent grid)
 int mps_blocks_per_cu(int precision, bool small);
 

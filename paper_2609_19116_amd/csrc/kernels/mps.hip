@@ -1,6 +1,6 @@
 // Persistent batched MPS shot kernel for gfx950.
 //
-// One workgroup (4 wavefronts) owns one MPS slot in HBM and runs whole shots
+// One workgroup (4 wavefronts, one per SIMD) owns one MPS slot in HBM and runs whole shots
 // through the compiled op stream, taking shots blockIdx.x, blockIdx.x +
 // gridDim.x, ...  Each shot has its own ragged bond dimensions, kept in LDS,
 // and stops at the first measurement whose expected outcome has probability
@@ -33,9 +33,10 @@
 namespace msc {
 namespace {
 
-constexpr int NT = 128;
+constexpr int NT = 256;
 constexpr int NW = NT / 64;
 constexpr int MAXV = 2 * kMaxChiKernel;   // vectors in a two-site SVD
+constexpr int kStage = 2048;               // doubles of LDS staging per workgroup
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -287,6 +288,13 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
     __shared__ double s_red[NW * 4];
     __shared__ double s_gph[8];
     __shared__ int s_gsrc[4];
+    // per-site layout of the slot and bond caps, read once per launch
+    __shared__ int64_t s_soff[kMaxSites];
+    __shared__ int64_t s_shalf[kMaxSites];
+    __shared__ int s_cap[kMaxSites + 1];
+    // staging: the two site tensors of an update (tensor type), then the
+    // copy of theta kept for the projection (FP64)
+    __shared__ double s_u[kStage];
 
     const int tid = threadIdx.x;
     const int N = P.n_sites;
@@ -298,10 +306,17 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
     int* g_bad = g_sel + MAXV;
     int* g_list = g_bad + MAXV;
 
+    for (int k = tid; k < N; k += NT) {
+        s_soff[k] = P.site_off[k];
+        s_shalf[k] = P.site_half[k];
+    }
+    for (int k = tid; k <= N; k += NT) s_cap[k] = P.cap[k];
+    __syncthreads();
+
     auto site = [&](int k) {
         SiteView<T> v;
-        v.re = slot_base + P.site_off[k];
-        v.im = v.re + P.site_half[k];
+        v.re = slot_base + s_soff[k];
+        v.im = v.re + s_shalf[k];
         return v;
     };
 
@@ -316,17 +331,6 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
             }
             continue;
         }
-        // ---- initial product state |0...0>
-        for (int k = tid; k <= N; k += NT) s_chi[k] = 1;
-        for (int k = tid; k < N; k += NT) {
-            s_laste[k] = 0;
-            SiteView<T> v = site(k);
-            v.re[0] = T(1);
-            v.re[1] = T(0);
-            v.im[0] = T(0);
-            v.im[1] = T(0);
-        }
-        __syncthreads();
         double p_acc = 1.0, disc = 0.0, infid = 0.0;
         int chi_peak = 1, status = 0, rej_at = -1;
         int64_t n2q = 0;
@@ -336,9 +340,91 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
         const int64_t fend = P.shot_off[shot + 1];
         int fcode = 0;     // code of the last channel read (three-qubit faults)
         bool alive = true;
+        int start = 0;
+        int jck = -1;
+        if (P.ck_mode == 2) {
+            // fork from the last checkpoint of the noiseless run before the
+            // shot's first fault (the ops before it are fault-free here)
+            const int navail = *P.ck_avail;
+            int j = fcur < fend ? P.chan[fcur] / P.ck_k : P.n_ck - 1;
+            jck = j < navail ? j : navail - 1;
+        }
+        if (jck >= 0) {
+            const CkHdr& h = P.ck_hdr[jck];
+            for (int k = tid; k <= N; k += NT) s_chi[k] = h.chi[k];
+            for (int k = tid; k < N; k += NT) s_laste[k] = h.laste[k];
+            __syncthreads();
+            const T* src = static_cast<const T*>(P.ck_data) + P.ck_off[jck];
+            int64_t o = 0;
+            for (int k = 0; k < N; ++k) {
+                const int ne = s_chi[k] * 2 * s_chi[k + 1];
+                SiteView<T> v = site(k);
+                for (int idx = tid; idx < ne; idx += NT) {
+                    v.re[idx] = src[o + idx];
+                    v.im[idx] = src[o + ne + idx];
+                }
+                o += 2 * ne;
+            }
+            p_acc = h.p_acc;
+            disc = h.disc;
+            chi_peak = h.chi_peak;
+            status = h.status;
+            start = P.ck_op[jck];
+        } else {
+            // ---- initial product state |0...0>
+            for (int k = tid; k <= N; k += NT) s_chi[k] = 1;
+            for (int k = tid; k < N; k += NT) {
+                s_laste[k] = 0;
+                SiteView<T> v = site(k);
+                v.re[0] = T(1);
+                v.re[1] = T(0);
+                v.im[0] = T(0);
+                v.im[1] = T(0);
+            }
+        }
+        __syncthreads();
+        int next_ck = 0;           // record mode: next checkpoint to take
+        int64_t ck_pos = 0;        // record mode: elements written so far
+        bool ck_full = false;
 
-        for (int oi = 0; oi < P.n_ops && alive; ++oi) {
-            const DevOp op = P.ops[oi];
+        DevOp next_op = start < P.n_ops ? P.ops[start] : DevOp{};
+        for (int oi = start; oi < P.n_ops && alive; ++oi) {
+            if (P.ck_mode == 1 && !ck_full && next_ck < P.n_ck && P.ck_op[next_ck] == oi) {
+                // ---- record: the state before op oi, densely, site by site
+                int64_t sz = 0;
+                for (int k = 0; k < N; ++k) sz += 4 * (int64_t)s_chi[k] * s_chi[k + 1];
+                if (ck_pos + sz <= P.ck_cap) {
+                    T* dst = static_cast<T*>(P.ck_data) + ck_pos;
+                    int64_t o = 0;
+                    for (int k = 0; k < N; ++k) {
+                        const int ne = s_chi[k] * 2 * s_chi[k + 1];
+                        SiteView<T> v = site(k);
+                        for (int idx = tid; idx < ne; idx += NT) {
+                            dst[o + idx] = v.re[idx];
+                            dst[o + ne + idx] = v.im[idx];
+                        }
+                        o += 2 * ne;
+                    }
+                    CkHdr& h = P.ck_hdr[next_ck];
+                    for (int k = tid; k <= N; k += NT) h.chi[k] = s_chi[k];
+                    for (int k = tid; k < N; k += NT) h.laste[k] = s_laste[k];
+                    if (tid == 0) {
+                        h.p_acc = p_acc;
+                        h.disc = disc;
+                        h.chi_peak = chi_peak;
+                        h.status = status;
+                        P.ck_off[next_ck] = ck_pos;
+                    }
+                    ck_pos += sz;
+                    __syncthreads();
+                    if (tid == 0) *P.ck_avail = next_ck + 1;
+                    ++next_ck;
+                } else {
+                    ck_full = true;
+                }
+            }
+            const DevOp op = next_op;
+            if (oi + 1 < P.n_ops) next_op = P.ops[oi + 1];   // in flight during this op
             bool twosite = op.kind == OP_G2;
             int gate_id = op.aux;
             if (op.kind == OP_MOVE) {
@@ -370,7 +456,7 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                                            : 8.0 * static_cast<double>(FLT_EPSILON);
                     if (!not_orthogonal(s_vre, s_vim, nv, len, ld, s_nrm, 1e-4 * tau2 * tsum[0], tol,
                                         s_bad, nullptr)) {
-                        const int capb = min(P.chi_max, P.cap[k + 1]);
+                        const int capb = min(P.chi_max, s_cap[k + 1]);
                         const Kept kp = select_kept(s_nrm, nv, tau2, capb, s_sel, s_red);
                         const int r = kp.r;
                         disc += kp.dropped;
@@ -649,8 +735,9 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                 const int cl = s_chi[k], cm = s_chi[k + 1], cr = s_chi[k + 2];
                 const int m = 2 * cl, n = 2 * cr;
                 SiteView<T> A = site(k), B = site(k + 1);
-                double* thr = scr;
-                double* thi = scr + (size_t)m * n;
+                // theta's copy for the projection: LDS staging when it fits
+                double* thr = 2 * (size_t)m * n <= (size_t)kStage ? s_u : scr;
+                double* thi = thr + (size_t)m * n;
                 const int nv = dir ? n : m, len = dir ? m : n;
                 const int ld = len + 1;
                 const bool lds = nv <= SMAX && len <= SMAX;
@@ -672,17 +759,39 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                     s_gph[2 * tid] = g[2 * src];
                     s_gph[2 * tid + 1] = g[2 * src + 1];
                 }
+                // both site tensors into LDS with one coalesced pass when they
+                // fit: the contraction then reads each element from LDS
+                const int na = cl * 2 * cm, nb = cm * 2 * cr;
+                const T* Ar = A.re;
+                const T* Ai = A.im;
+                const T* Br = B.re;
+                const T* Bi = B.im;
+                if ((size_t)2 * (na + nb) * sizeof(T) <= kStage * sizeof(double)) {
+                    T* st = reinterpret_cast<T*>(s_u);
+                    for (int i = tid; i < na; i += NT) {
+                        st[i] = A.re[i];
+                        st[na + i] = A.im[i];
+                    }
+                    for (int i = tid; i < nb; i += NT) {
+                        st[2 * na + i] = B.re[i];
+                        st[2 * na + nb + i] = B.im[i];
+                    }
+                    Ar = st;
+                    Ai = st + na;
+                    Br = st + 2 * na;
+                    Bi = Br + nb;
+                }
                 __syncthreads();
                 double nsum[1] = {0.0};
                 for (int idx = tid; idx < cl * cr; idx += NT) {
                     const int a = idx / cr, b = idx - a * cr;
                     T sr[4] = {T(0), T(0), T(0), T(0)}, si[4] = {T(0), T(0), T(0), T(0)};
-                    const T* a0r = A.re + (a * 2) * cm;
-                    const T* a0i = A.im + (a * 2) * cm;
+                    const T* a0r = Ar + (a * 2) * cm;
+                    const T* a0i = Ai + (a * 2) * cm;
                     for (int c = 0; c < cm; ++c) {
                         const T x0r = a0r[c], x0i = a0i[c], x1r = a0r[cm + c], x1i = a0i[cm + c];
                         const int b0 = (c * 2) * cr + b, b1 = b0 + cr;
-                        const T y0r = B.re[b0], y0i = B.im[b0], y1r = B.re[b1], y1i = B.im[b1];
+                        const T y0r = Br[b0], y0i = Bi[b0], y1r = Br[b1], y1i = Bi[b1];
                         // S[i'j'] += A[a,i',c] B[c,j',b]
                         sr[0] += x0r * y0r - x0i * y0i; si[0] += x0r * y0i + x0i * y0r;
                         sr[1] += x0r * y1r - x0i * y1i; si[1] += x0r * y1i + x0i * y1r;
@@ -748,7 +857,7 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                     if (again) status |= MSC_SHOT_NOCONV;
                     sweeps_total += sweeps;
                 }
-                const int capb = min(P.chi_max, P.cap[k + 1]);
+                const int capb = min(P.chi_max, s_cap[k + 1]);
                 const Kept kp = select_kept(nrm, nv, tau2, capb, sel, s_red);
                 const int r = kp.r;
                 const double kept = kp.kept;
@@ -873,12 +982,16 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
     }
 }
 
-// Processing order of the shots: a stable counting sort by fault count
-// (capped at 15), fewest faults first.  Low-weight shots are the ones that
-// run to the end of the circuit (online screening stops the others early),
-// so starting them first keeps the tail of the persistent grid short.
+// Processing order of the shots: a stable counting sort into 16 buckets,
+// the longest-running shots first so that the tail of the persistent grid
+// stays short.  Without checkpoints the key is the fault count (capped at
+// 15): low-weight shots are the ones that run to the end of the circuit,
+// online screening stops the others early.  With checkpoints a shot starts
+// at its first fault, so the key is the position of that channel in the
+// circuit (fault-free shots, which only read out, last).
 __global__ __launch_bounds__(1024) void order_kernel(int64_t n, const int64_t* shot_off,
                                                      const int64_t* shot_idx, int64_t n_csr,
+                                                     const int32_t* chan, int32_t n_channels,
                                                      int64_t* perm) {
     __shared__ int64_t s_base;
     __shared__ int s_wcnt[16];
@@ -893,8 +1006,14 @@ __global__ __launch_bounds__(1024) void order_kernel(int64_t n, const int64_t* s
                 const int64_t sh = shot_idx ? shot_idx[j] : j;
                 int c = 15;
                 if (sh >= 0 && sh < n_csr) {
-                    const int64_t f = shot_off[sh + 1] - shot_off[sh];
-                    c = f < 15 ? static_cast<int>(f) : 15;
+                    const int64_t f0 = shot_off[sh], f = shot_off[sh + 1] - f0;
+                    if (n_channels > 0) {
+                        const int64_t ch = f > 0 ? chan[f0] : n_channels;
+                        c = ch < 0 ? 0 : ch >= n_channels ? 15
+                                                          : static_cast<int>(ch * 15 / n_channels);
+                    } else {
+                        c = f < 15 ? static_cast<int>(f) : 15;
+                    }
                 }
                 hit = c == key;
             }
@@ -934,9 +1053,10 @@ int mps_blocks_per_cu(int precision, bool small) {
 }
 
 hipError_t launch_order(int64_t n, const int64_t* shot_off, const int64_t* shot_idx, int64_t n_csr,
-                        int64_t* perm, hipStream_t s) {
+                        const int32_t* chan, int32_t n_channels, int64_t* perm, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, s, n, shot_off, shot_idx, n_csr, perm);
+    hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, s, n, shot_off, shot_idx, n_csr, chan,
+                       n_channels, perm);
     return hipGetLastError();
 }
 

@@ -63,6 +63,22 @@ int set_error(int code, const std::string& msg);
 
 }  // namespace msc
 
+// Device checkpoints of the noiseless run for one option set (see the
+// shot kernel): built on first use by msc_simulate with prefix = 1.
+struct PrefixCk {
+    bool valid = false;
+    int dev = -1, precision = -1, chi_max = 0, lds_width = 0;
+    double tau = 0.0, tau_rej = 0.0;
+    int n_ck = 0, ck_k = 1, avail = 0;
+    int64_t cap = 0;           // elements of the tensor type
+    float build_ms = 0.f;
+    void* d_op = nullptr;      // int32[n_ck]
+    void* d_avail = nullptr;   // int32
+    void* d_off = nullptr;     // int64[n_ck]
+    void* d_hdr = nullptr;     // CkHdr[n_ck]
+    void* d_data = nullptr;
+};
+
 struct msc_circuit {
     int n = 0;
     int seed = 0;
@@ -75,6 +91,7 @@ struct msc_circuit {
     std::vector<msc::DevOp> ops;
     int64_t n_twosite = 0, n_swaps = 0, n_product_swaps = 0, n_moves = 0;
     int final_site = 0;
+    std::vector<int32_t> chan_op;        // op index of each channel's OP_FAULT
     // expected outcomes
     std::vector<uint8_t> expected;
     bool calibrated = false;
@@ -90,6 +107,7 @@ struct msc_circuit {
     void* d_sig = nullptr;
     void* d_expected = nullptr;
     void* d_kind = nullptr;              // uint8 ChanKind per channel
+    PrefixCk prefix;
 };
 
 namespace msc {

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_sizes_match_header():
     assert C.sizeof(_lib.ShotResult) == 64
-    assert C.sizeof(_lib.SimOpts) == 40
+    assert C.sizeof(_lib.SimOpts) == 48
     assert C.sizeof(_lib.CircuitInfo) == 72
 
 

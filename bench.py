@@ -4,8 +4,12 @@ A step is one pass of the hot path over one batch of shots: subset-sampled
 faults drawn on the GPU from the seed (Section 4.1), the bit-exact offline
 screen over the batch, batched mixed-precision MPS simulation (FP32
 contractions, FP64 SVD, norms and probabilities) of the survivors, and the
-per-weight bin sums that feed Eq. (reweight).  Workload: the 49-qubit rotated d=5 circuit (6 noisy rounds,
-two transversal T layers), p = 1e-3, 4096 shots per batch, chi_max = 256.
+per-weight bin sums that feed Eq. (reweight).  Workload: the 49-qubit
+rotated d=5 circuit (6 noisy rounds, two transversal T layers), p = 1e-3,
+4096 shots per batch, chi_max = 256.  Steps run on --streams host threads,
+each with its own context and HIP stream, so the long-running shots of one
+step overlap the next steps (a shot's latency, not the GPU's capacity, sets
+the length of a single step).
 
 Also measured on the same GPU and shot list: the plain FP64 path one shot
 per launch (bounded sample, scaled), the FP32-vs-FP64 probability error,
@@ -18,6 +22,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -40,7 +45,7 @@ def log(*a):
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=24)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--shots", type=int, default=4096)
     ap.add_argument("--p", type=float, default=1e-3)
@@ -52,12 +57,25 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--lds-width", type=int, default=0)
+    ap.add_argument("--slots", type=int, default=0,
+                    help="persistent workgroups (MPS slots) per context; 0 = one per "
+                         "resident workgroup of the GPU")
+    ap.add_argument("--streams", type=int, default=8,
+                    help="steps in flight: each host thread runs whole steps on its own "
+                         "context (HIP stream), so one step's long-running shots overlap "
+                         "the next step's work")
     ap.add_argument("--no-prefix", action="store_true",
                     help="start every shot from |0...0> instead of forking it from the "
                          "noiseless-run checkpoint before its first fault")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device (counter calibration)")
     args = ap.parse_args()
+    # one hardware queue per stream in flight plus torch's own: with fewer,
+    # streams share queues and their kernels run one after the other.  Read
+    # by the HIP runtime when it initialises, so set before any GPU use.
+    need = min(32, args.streams + 1)
+    if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < need:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(need)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build simulates each shot on one "
               "device and has no multi-GPU path (see DESIGN.md for how it would shard)",
@@ -93,67 +111,73 @@ def main() -> int:
     log(f"circuit: {info}")
 
     wmax = 64
-    bin_n = np.zeros(wmax + 1)
-    bin_a = np.zeros(wmax + 1)
-    bin_e = np.zeros(wmax + 1)
+    S = max(1, args.streams)
+    ctxs = [ctx] + [msc.Ctx(0) for _ in range(S - 1)]
 
-    def sample(b):
-        return msc.sample_faults_device(ctx, circ, SEED, b * n, n, p=args.p)
+    def sample(c, b):
+        return msc.sample_faults_device(c, circ, SEED, b * n, n, p=args.p)
 
-    def step(b, accumulate):
-        # one pass of the whole path over one batch: fault sampling, offline
-        # screen, batched MPS of the survivors, per-weight bin sums
-        off, ch, pa = sample(b)
-        t_sample = ctx.last_kernel_ms("sample")
-        bits, idx, cnt = msc.prescreen(ctx, circ, off, ch, pa)
-        t_screen = ctx.last_kernel_ms("prescreen")
-        res = None
-        if cnt:
-            out = msc.simulate(ctx, circ, off, ch, pa, shot_idx=idx, precision=msc.MSC_FP32,
-                               chi_max=args.chi_max, lds_width=args.lds_width,
-                               prefix=not args.no_prefix)
-            res = msc.results_numpy(out)
-        t_sim = ctx.last_kernel_ms("simulate") if cnt else 0.0
-        if accumulate:
-            ww = np.minimum(np.diff(off.cpu().numpy()), wmax)
-            np.add.at(bin_n, ww, 1.0)
-            if res is not None:
-                sel = ww[idx.cpu().numpy()]
-                np.add.at(bin_a, sel, res["p_acc"])
-                np.add.at(bin_e, sel, res["p_acc"] * res["fail"])
-        return cnt, res, t_screen, t_sim, idx, t_sample
+    def step(c, b):
+        # one pass of the whole path over one batch on the context's stream:
+        # fault sampling, offline screen, batched MPS of the survivors and
+        # the per-weight bin sums, with one synchronisation at the end
+        bins, st = msc.run_batch(c, circ, SEED, b * n, n, args.p, n_bins=wmax + 1,
+                                 precision=msc.MSC_FP32, chi_max=args.chi_max,
+                                 lds_width=args.lds_width, prefix=not args.no_prefix,
+                                 n_slots=args.slots)
+        return st, bins
 
     prefix_ms = None
     if not args.no_prefix:
         # checkpoints of the noiseless run, once per circuit and option set
         # (like compilation and calibration, outside the per-batch work)
-        off0, ch0, pa0 = sample(0)
+        off0, ch0, pa0 = sample(ctx, 0)
         msc.simulate(ctx, circ, off0, ch0, pa0, shot_idx=torch.zeros(1, dtype=torch.int64,
                                                                      device="cuda"),
                      precision=msc.MSC_FP32, chi_max=args.chi_max, lds_width=args.lds_width,
                      prefix=True)
         prefix_ms = ctx.last_kernel_ms("prefix")
         log(f"noiseless-prefix checkpoints built in {prefix_ms:.1f} ms")
-    for b in range(args.warmup):
-        step(b, False)
+    # untimed warmup steps, at least one per context (sizes its buffers)
+    warmup = max(args.warmup, S)
+    for b in range(warmup):
+        step(ctxs[b % S], b)
     torch.cuda.synchronize()
+    per = [None] * args.steps
+    errors = []
+
+    def worker(t):
+        try:
+            for i in range(t, args.steps, S):
+                per[i] = step(ctxs[t], warmup + i)
+        except BaseException as e:    # re-raised by the main thread
+            errors.append(e)
+
     t0 = time.perf_counter()
-    per = []
-    for b in range(args.warmup, nb):
-        per.append(step(b, True))
+    threads = [threading.Thread(target=worker, args=(t,)) for t in range(S)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if errors:
+        raise errors[0]
     wall = t1 - t0
     value = args.steps * n / wall
-    n_surv = [p[0] for p in per]
-    sim_ms = [p[3] for p in per]
-    screen_ms = [p[2] for p in per]
-    sample_ms = [p[5] for p in per]
-    flops = [float(p[1]["flops"].sum()) if p[1] is not None else 0.0 for p in per]
-    n2q = [int(p[1]["n2q"].sum()) if p[1] is not None else 0 for p in per]
-    chi_peak = max(int(p[1]["chi_peak"].max()) for p in per if p[1] is not None)
-    achieved = sum(flops) / (sum(sim_ms) * 1e-3) / 1e12
-    sweeps = sum(int(p[1]["sweeps"].sum()) if p[1] is not None else 0 for p in per)
+    bin_n, bin_a, bin_e = sum(p[1] for p in per)
+    sts = [p[0] for p in per]
+    n_surv = [st["n_survivors"] for st in sts]
+    sim_ms = [st["ms_simulate"] for st in sts]
+    screen_ms = [st["ms_screen"] for st in sts]
+    sample_ms = [st["ms_sample"] for st in sts]
+    flops = [st["flops"] for st in sts]
+    n2q = [st["n2q"] for st in sts]
+    chi_peak = max(st["chi_peak"] for st in sts)
+    # algorithmic flops of the timed steps over the timed wall time (the
+    # steps overlap, so per-launch durations would double count)
+    achieved = sum(flops) / wall / 1e12
+    sweeps = sum(st["sweeps"] for st in sts)
     log(f"steps={args.steps} wall={wall:.3f}s value={value:.1f} shots/s survivors={n_surv} "
         f"sim_ms={sim_ms} screen_ms={screen_ms} sample_ms={sample_ms}")
     est = msc.reweight(bin_n, bin_a, bin_e, M, [5e-4, 1e-3, 2e-3])
@@ -164,7 +188,7 @@ def main() -> int:
         "unit": "shots/s",
         "n_gpus": 1,
         "steps": args.steps,
-        "warmup": args.warmup,
+        "warmup": warmup,
         "ms_per_step": wall / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
@@ -176,11 +200,12 @@ def main() -> int:
         "config": {"workload": "rotated d=5 cultivation-like circuit, 49 qubits (25 data + 24 "
                                "ancilla) snake-ordered, 6 noisy rounds, two T layers; p=1e-3 "
                                "depolarising; faults w~Bin(M,p), seed 0x5EED0003; 4096 shots "
-                               "per batch; GPU fault sampling + offline screen + batched MPS, "
-                               "chi_max=256",
+                               "per batch (step); GPU fault sampling + offline screen + batched "
+                               "MPS, chi_max=256; up to steps_in_flight steps overlap",
                    "shots_per_step": n, "chi_max": args.chi_max, "p": args.p,
                    "n_channels": M, "twosite_updates_per_full_shot": info["n_twosite"]},
         "survivors_per_step": float(np.mean(n_surv)),
+        "steps_in_flight": S,
         "prefix_sharing": None if args.no_prefix else {
             "checkpoint_build_ms": prefix_ms,
             "note": "shots fork from checkpoints of the noiseless run taken before their "
@@ -202,8 +227,12 @@ def main() -> int:
 
     if not args.no_extras:
         # plain FP64 path, one shot per launch, on survivors of the first timed batch
-        off, ch, pa = sample(args.warmup)
-        idx0 = per[0][4]
+        off, ch, pa = sample(ctx, warmup)
+        _, idx0, _ = msc.prescreen(ctx, circ, off, ch, pa)
+        res32 = msc.results_numpy(msc.simulate(ctx, circ, off, ch, pa, shot_idx=idx0,
+                                               precision=msc.MSC_FP32, chi_max=args.chi_max,
+                                               lds_width=args.lds_width,
+                                               prefix=not args.no_prefix))
         k = min(args.fp64_sample, int(idx0.numel()))
         t64 = 0.0
         r64 = []
@@ -223,7 +252,6 @@ def main() -> int:
         # precision: FP32 batched vs FP64 batched on all survivors of that batch
         out64 = msc.results_numpy(msc.simulate(ctx, circ, off, ch, pa, shot_idx=idx0,
                                                precision=msc.MSC_FP64, chi_max=args.chi_max))
-        res32 = per[0][1]
         dp = np.abs(res32["p_acc"] - out64["p_acc"])
         acc = out64["p_acc"] > 0
         df = np.abs(res32["infid"] - out64["infid"])[acc] if acc.any() else np.zeros(1)
@@ -261,7 +289,8 @@ def main() -> int:
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(cc.text, args, n)
 
-    ctx.close()
+    for c in ctxs:
+        c.close()
     print(json.dumps(result), flush=True)
     return 0
 

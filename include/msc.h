@@ -126,6 +126,21 @@ typedef struct {
     double trunc_bound;   /* B = sum_{w > w_max} Bin_w(p)                     */
 } msc_estimate;
 
+typedef struct {
+    int64_t n_shots;      /* shots drawn                                     */
+    int64_t nnz;          /* faults drawn                                    */
+    int64_t n_survivors;  /* shots left by the offline screen                */
+    int64_t n_accepted;   /* survivors with P_acc > 0                        */
+    int64_t n2q;          /* two-site updates executed                       */
+    int64_t sweeps;       /* Jacobi sweeps                                   */
+    double flops;         /* algorithmic flops of the two-site updates       */
+    int32_t chi_peak;     /* largest bond dimension over the batch           */
+    int32_t status_or;    /* OR of the survivors' msc_shot_status bits       */
+    double ms_sample;     /* kernel time of the sampling (ms, context stream) */
+    double ms_screen;     /* kernel time of the offline screen               */
+    double ms_simulate;   /* kernel time of the shots                        */
+} msc_batch_stats;
+
 /* Message of the last failure on this thread (never NULL). */
 const char* msc_last_error(void);
 
@@ -234,6 +249,26 @@ int msc_simulate(msc_ctx* ctx, const msc_circuit* c, const msc_sim_opts* opts,
                  int64_t n_shots, const int64_t* shot_off, const int32_t* chan,
                  const uint8_t* pauli, const int64_t* shot_idx, int64_t n_sel,
                  msc_shot_result* out);
+
+/* One batch of the whole path on the context's stream with a single
+   synchronisation at the end (no host round trip between the stages, so
+   calls on different contexts overlap on the GPU): shots first_shot ..
+   first_shot+n_shots-1 drawn as by msc_sample_faults with w ~ Bin(M, p)
+   (Section 4.1), screened as by msc_prescreen (Section 4.2), the survivors
+   simulated as by msc_simulate with `opts` (Sections 3.1, 4, 4.3), and the
+   results reduced per fault weight for Eq. (reweight): bins (host,
+   3 * n_bins doubles, 1 <= n_bins <= 1024) receives bins[w] = number of
+   shots of weight w, bins[n_bins + w] = sum of their P_acc and
+   bins[2 n_bins + w] = sum of P_acc * fail (weights >= n_bins - 1 share
+   the last bin; screened shots count with P_acc = 0), summed in a fixed
+   order.  stats (host) is optional.  out (device, n_shots records) is
+   optional: out[i] is the result of shot i (screened shots: all zero,
+   rejected_at -1).  The fault buffer is sized for the largest weight the
+   Bin(M, p) table can draw; MSC_E_CAPACITY if that exceeds 2^28 faults.   */
+int msc_run_batch(msc_ctx* ctx, const msc_circuit* c, const msc_sim_opts* opts,
+                  uint64_t seed, uint64_t first_shot, int64_t n_shots, double p,
+                  int32_t n_bins, double* bins, msc_batch_stats* stats,
+                  msc_shot_result* out);
 
 /* ---------------------------------------------------------------------- */
 /* Two-site contraction on MFMA (Section 3.1), standalone.                 */

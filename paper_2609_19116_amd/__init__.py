@@ -12,7 +12,7 @@ import ctypes as C
 
 import numpy as np
 
-from ._lib import (MSC_BF16X3, MSC_FP32, MSC_FP64, SHOT_CHI_CAP, SHOT_DONE, SHOT_DTYPE,  # noqa: F401
+from ._lib import (BatchStats, MSC_BF16X3, MSC_FP32, MSC_FP64, SHOT_CHI_CAP, SHOT_DONE, SHOT_DTYPE,  # noqa: F401
                    SHOT_NOCONV, SHOT_REJECTED, CircuitInfo, Estimate, MscError, SimOpts,
                    _check, _ptr, lib)
 
@@ -176,6 +176,27 @@ def simulate(ctx: Ctx, circ: Circuit, off, chan, pauli, shot_idx=None, precision
     _check(lib().msc_simulate(ctx.h, circ.h, C.byref(o), n_shots, _ptr(off), _ptr(chan),
                               _ptr(pauli), _ptr(shot_idx), n, _ptr(out)))
     return out[: n * SHOT_DTYPE.itemsize]
+
+
+def run_batch(ctx: Ctx, circ: Circuit, seed: int, first_shot: int, n_shots: int, p: float,
+              n_bins: int = 65, precision=MSC_FP32, chi_max: int = 256, tau_trunc: float = 0.0,
+              tau_rej: float = 1e-6, tau_fail: float = 1e-4, n_slots: int = 0,
+              lds_width: int = 0, prefix: bool = True, out=None):
+    """One batch of the whole path (sampling, screen, shots, bin sums) on the
+    context's stream with one synchronisation.  Returns (bins float64
+    [3, n_bins]: shots, sum P_acc, sum P_acc * fail per weight; stats dict).
+    ``out`` (optional uint8 device tensor of n_shots records) receives the
+    per-shot results, indexed by shot."""
+    o = SimOpts(precision, chi_max, tau_trunc, tau_rej, tau_fail, n_slots, lds_width,
+                1 if prefix else 0, 0)
+    bins = np.zeros(3 * n_bins, dtype=np.float64)
+    st = BatchStats()
+    if out is not None:
+        assert out.numel() >= n_shots * SHOT_DTYPE.itemsize
+    _check(lib().msc_run_batch(ctx.h, circ.h, C.byref(o), seed, first_shot, n_shots, p, n_bins,
+                               _ptr(bins), C.byref(st), _ptr(out)))
+    stats = {f: getattr(st, f) for f, _ in BatchStats._fields_}
+    return bins.reshape(3, n_bins), stats
 
 
 def results_numpy(out) -> np.ndarray:

@@ -48,6 +48,13 @@ class SimOpts(C.Structure):
                 ("lds_width", C.c_int32), ("prefix", C.c_int32), ("reserved", C.c_int32)]
 
 
+class BatchStats(C.Structure):
+    _fields_ = [("n_shots", C.c_int64), ("nnz", C.c_int64), ("n_survivors", C.c_int64),
+                ("n_accepted", C.c_int64), ("n2q", C.c_int64), ("sweeps", C.c_int64),
+                ("flops", C.c_double), ("chi_peak", C.c_int32), ("status_or", C.c_int32),
+                ("ms_sample", C.c_double), ("ms_screen", C.c_double), ("ms_simulate", C.c_double)]
+
+
 class ShotResult(C.Structure):
     _fields_ = [("p_acc", C.c_double), ("infid", C.c_double), ("disc_weight", C.c_double),
                 ("chi_peak", C.c_int32), ("status", C.c_int32), ("rejected_at", C.c_int32),
@@ -89,6 +96,8 @@ _SIGS = {
     "msc_prescreen": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P, _P, _P, C.POINTER(C.c_int64)]),
     "msc_simulate": (C.c_int, [_P, _P, C.POINTER(SimOpts), C.c_int64, _P, _P, _P, _P,
                                C.c_int64, _P]),
+    "msc_run_batch": (C.c_int, [_P, _P, C.POINTER(SimOpts), C.c_uint64, C.c_uint64, C.c_int64,
+                                C.c_double, C.c_int32, _P, C.POINTER(BatchStats), _P]),
     "msc_twosite_contract": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, _P]),
     "msc_reweight": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, _P, C.c_int32, _P]),
 }

@@ -27,6 +27,7 @@ SOURCES = [
     CSRC / "kernels" / "mps.hip",
     CSRC / "kernels" / "prescreen.hip",
     CSRC / "kernels" / "sampler.hip",
+    CSRC / "kernels" / "batch.hip",
     CSRC / "kernels" / "twosite.hip",
 ]
 

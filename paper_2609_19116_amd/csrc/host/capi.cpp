@@ -43,7 +43,16 @@ struct msc_ctx {
     int n_cu = 0;
     std::map<std::string, DevBuf> bufs;       // grow-only scratch
     std::map<std::string, double> last_ms;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
+    // what the slot-layout and Bin(M, p) buffers currently hold
+    int layout_n = -1, layout_chi = -1;
+    int64_t cdf_m = -1;
+    double cdf_p = -1.0;
+    int32_t cdf_len = 0;
+    // host-mapped pinned block the batch reduction writes into
+    void* hmap = nullptr;
+    void* hmap_dev = nullptr;
+    size_t hmap_bytes = 0;
 };
 
 static int ctx_buf(msc_ctx* ctx, const std::string& name, size_t bytes, void** out) {
@@ -85,6 +94,8 @@ extern "C" int msc_ctx_create(int device, msc_ctx** out) {
     MSC_HIP(hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, device));
     MSC_HIP(hipEventCreate(&ctx->ev0));
     MSC_HIP(hipEventCreate(&ctx->ev1));
+    MSC_HIP(hipEventCreate(&ctx->ev2));
+    MSC_HIP(hipEventCreate(&ctx->ev3));
     *out = ctx.release();
     return MSC_OK;
 }
@@ -95,8 +106,9 @@ extern "C" void msc_ctx_destroy(msc_ctx* ctx) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     for (auto& kv : ctx->bufs)
         if (kv.second.p) (void)hipFree(kv.second.p);
-    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
-    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    for (hipEvent_t ev : {ctx->ev0, ctx->ev1, ctx->ev2, ctx->ev3})
+        if (ev) (void)hipEventDestroy(ev);
+    if (ctx->hmap) (void)hipHostFree(ctx->hmap);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -240,19 +252,21 @@ Layout make_layout(int n, int chi_max) {
     }
     L.slot_elems = (pos + 63) / 64 * 64;
     int64_t s = 2ll * chi_max;
-    // theta copy + padded vectors, then per-vector arrays (4 x 512 doubles)
-    L.scratch = 4 * s * s + 4 * s + 64 + 4 * 2 * kMaxChiKernel;
+    // theta copy + padded vectors, then per-vector arrays (6 x 512 doubles)
+    L.scratch = 4 * s * s + 4 * s + 64 + 6 * 2 * kMaxChiKernel;
     return L;
 }
 
 }  // namespace
 
-static int run_shots(msc_ctx* ctx, const msc_circuit* c, int precision, int chi_max, double tau,
-                     double tau_rej, double tau_fail, int n_slots, int lds_width, int64_t n,
-                     int64_t n_csr, const int64_t* off, const int32_t* chan, const uint8_t* pauli,
-                     const int64_t* shot_idx, msc_shot_result* out, int calibrate,
-                     double* cal_p, uint8_t* cal_e, const char* timer, int ck_mode = 0,
-                     const PrefixCk* pk = nullptr) {
+// Enqueues the order and shot kernels on the context's stream (no wait).
+// n bounds the shots (a device count n_dev, if given, may be smaller).
+static int enqueue_shots(msc_ctx* ctx, const msc_circuit* c, int precision, int chi_max,
+                         double tau, double tau_rej, double tau_fail, int n_slots, int lds_width,
+                         int64_t n, int64_t n_csr, const int64_t* off, const int32_t* chan,
+                         const uint8_t* pauli, const int64_t* shot_idx, msc_shot_result* out,
+                         int calibrate, double* cal_p, uint8_t* cal_e, int ck_mode,
+                         const PrefixCk* pk, const int64_t* n_dev) {
     Layout L = make_layout(c->n, chi_max);
     const bool small = lds_width == 32;
     if (n_slots <= 0) n_slots = ctx->n_cu * mps_blocks_per_cu(precision, small);
@@ -266,9 +280,15 @@ static int run_shots(msc_ctx* ctx, const msc_circuit* c, int precision, int chi_
     if ((rc = ctx_buf(ctx, "off", L.off.size() * sizeof(int64_t), &doff))) return rc;
     if ((rc = ctx_buf(ctx, "half", L.half.size() * sizeof(int64_t), &dhalf))) return rc;
     if ((rc = ctx_buf(ctx, "perm", static_cast<size_t>(n) * sizeof(int64_t), &dperm))) return rc;
-    MSC_HIP(hipMemcpyAsync(dcap, L.cap.data(), L.cap.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
-    MSC_HIP(hipMemcpyAsync(doff, L.off.data(), L.off.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
-    MSC_HIP(hipMemcpyAsync(dhalf, L.half.data(), L.half.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+    if (ctx->layout_n != c->n || ctx->layout_chi != chi_max) {
+        // the layout depends on (n, chi_max) only: uploaded when it changes
+        MSC_HIP(hipMemcpyAsync(dcap, L.cap.data(), L.cap.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+        MSC_HIP(hipMemcpyAsync(doff, L.off.data(), L.off.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+        MSC_HIP(hipMemcpyAsync(dhalf, L.half.data(), L.half.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+        MSC_HIP(hipStreamSynchronize(ctx->stream));
+        ctx->layout_n = c->n;
+        ctx->layout_chi = chi_max;
+    }
     MpsArgs a{};
     a.ops = static_cast<const DevOp*>(c->d_ops);
     a.n_ops = static_cast<int32_t>(c->ops.size());
@@ -281,6 +301,7 @@ static int run_shots(msc_ctx* ctx, const msc_circuit* c, int precision, int chi_
     a.shot_idx = shot_idx;
     a.perm = static_cast<const int64_t*>(dperm);
     a.n_shots = n;
+    a.n_dev = n_dev;
     a.n_csr = n_csr;
     a.expected = static_cast<const uint8_t*>(c->d_expected);
     a.out = out;
@@ -319,10 +340,24 @@ static int run_shots(msc_ctx* ctx, const msc_circuit* c, int precision, int chi_
         a.ck_data = pk->d_data;
         a.ck_cap = pk->cap;
     }
-    MSC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
-    MSC_HIP(launch_order(n, off, shot_idx, n_csr, chan, a.ck_mode == 2 ? c->n_channels : 0,
-                         static_cast<int64_t*>(dperm), ctx->stream));
+    MSC_HIP(launch_order(n, n_dev, off, shot_idx, n_csr, chan,
+                         a.ck_mode == 2 ? c->n_channels : 0, static_cast<int64_t*>(dperm),
+                         ctx->stream));
     MSC_HIP(launch_mps(precision, small, a, n_slots, ctx->stream));
+    return MSC_OK;
+}
+
+static int run_shots(msc_ctx* ctx, const msc_circuit* c, int precision, int chi_max, double tau,
+                     double tau_rej, double tau_fail, int n_slots, int lds_width, int64_t n,
+                     int64_t n_csr, const int64_t* off, const int32_t* chan, const uint8_t* pauli,
+                     const int64_t* shot_idx, msc_shot_result* out, int calibrate,
+                     double* cal_p, uint8_t* cal_e, const char* timer, int ck_mode = 0,
+                     const PrefixCk* pk = nullptr) {
+    MSC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
+    int rc = enqueue_shots(ctx, c, precision, chi_max, tau, tau_rej, tau_fail, n_slots,
+                           lds_width, n, n_csr, off, chan, pauli, shot_idx, out, calibrate, cal_p,
+                           cal_e, ck_mode, pk, nullptr);
+    if (rc) return rc;
     MSC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
     MSC_HIP(hipStreamSynchronize(ctx->stream));
     float ms = 0.f;
@@ -524,6 +559,25 @@ extern "C" int msc_prescreen(msc_ctx* ctx, const msc_circuit* c, int64_t n_shots
     return MSC_OK;
 }
 
+// The Bin(M, p) cumulative table on the device, uploaded when (M, p) changes.
+static int device_cdf(msc_ctx* ctx, int64_t M, double p, void** out, int32_t* len) {
+    int rc;
+    if (ctx->cdf_m != M || !(ctx->cdf_p == p)) {
+        std::vector<double> cdf = binomial_cdf(M, p);
+        void* d;
+        if ((rc = ctx_buf(ctx, "cdf", cdf.size() * sizeof(double), &d))) return rc;
+        MSC_HIP(hipMemcpyAsync(d, cdf.data(), cdf.size() * sizeof(double), hipMemcpyHostToDevice,
+                               ctx->stream));
+        MSC_HIP(hipStreamSynchronize(ctx->stream));
+        ctx->cdf_m = M;
+        ctx->cdf_p = p;
+        ctx->cdf_len = static_cast<int32_t>(cdf.size());
+    }
+    if ((rc = ctx_buf(ctx, "cdf", ctx->cdf_len * sizeof(double), out))) return rc;
+    *len = ctx->cdf_len;
+    return MSC_OK;
+}
+
 extern "C" int msc_sample_faults_device(msc_ctx* ctx, const msc_circuit* c, uint64_t seed,
                                         uint64_t first_shot, int64_t n_shots,
                                         const int32_t* weights, double p, int64_t* shot_off,
@@ -542,20 +596,15 @@ extern "C" int msc_sample_faults_device(msc_ctx* ctx, const msc_circuit* c, uint
         MSC_HIP(hipMemcpy(shot_off, &zero, sizeof(zero), hipMemcpyHostToDevice));
         return MSC_OK;
     }
-    std::vector<double> cdf;
     void* dcdf = nullptr;
-    if (!weights) {
-        cdf = binomial_cdf(c->n_channels, p);
-        if ((rc = ctx_buf(ctx, "cdf", cdf.size() * sizeof(double), &dcdf))) return rc;
-        MSC_HIP(hipMemcpyAsync(dcdf, cdf.data(), cdf.size() * sizeof(double),
-                               hipMemcpyHostToDevice, ctx->stream));
-    }
+    int32_t ncdf = 0;
+    if (!weights && (rc = device_cdf(ctx, c->n_channels, p, &dcdf, &ncdf))) return rc;
     const int64_t nt = sampler_tmp_words(n_shots);
     void* tmp;
     if ((rc = ctx_buf(ctx, "sample_tmp", nt * sizeof(int64_t), &tmp))) return rc;
     MSC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
     MSC_HIP(launch_sampler(n_shots, seed, first_shot, weights, static_cast<const double*>(dcdf),
-                           static_cast<int32_t>(cdf.size()), c->n_channels,
+                           ncdf, c->n_channels,
                            static_cast<const uint8_t*>(c->d_kind), nnz_cap, shot_off, chan, pauli,
                            static_cast<int64_t*>(tmp), nt, ctx->stream));
     MSC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
@@ -568,6 +617,121 @@ extern "C" int msc_sample_faults_device(msc_ctx* ctx, const msc_circuit* c, uint
     ctx->last_ms["sample"] = ms;
     *nnz_out = total;
     if (total > nnz_cap) return set_error(MSC_E_CAPACITY, "nnz_cap too small");
+    return MSC_OK;
+}
+
+extern "C" int msc_run_batch(msc_ctx* ctx, const msc_circuit* c, const msc_sim_opts* opts,
+                             uint64_t seed, uint64_t first_shot, int64_t n_shots, double p,
+                             int32_t n_bins, double* bins, msc_batch_stats* stats,
+                             msc_shot_result* out) {
+    if (!ctx || !c || !opts || !bins || n_shots < 0) return set_error(MSC_E_INVALID, "null argument");
+    if (n_bins < 1 || n_bins > kMaxBins) return set_error(MSC_E_INVALID, "n_bins must be in [1, 1024]");
+    if (!(p >= 0.0 && p <= 1.0)) return set_error(MSC_E_INVALID, "p outside [0,1]");
+    if (!c->calibrated) return set_error(MSC_E_STATE, "circuit not calibrated");
+    if (opts->precision != MSC_FP64 && opts->precision != MSC_FP32)
+        return set_error(MSC_E_INVALID, "unknown precision");
+    if (opts->chi_max < 1 || opts->chi_max > kMaxChiKernel)
+        return set_error(MSC_E_INVALID, "chi_max must be in [1, 256]");
+    if (opts->lds_width != 0 && opts->lds_width != 32 && opts->lds_width != 64)
+        return set_error(MSC_E_INVALID, "lds_width must be 0, 32 or 64");
+    if (opts->prefix != 0 && opts->prefix != 1) return set_error(MSC_E_INVALID, "prefix must be 0 or 1");
+    if (opts->reserved != 0) return set_error(MSC_E_INVALID, "reserved must be 0");
+    if (c->words > 8) return set_error(MSC_E_INVALID, "more than 512 decided measurements");
+    MSC_HIP(hipSetDevice(ctx->device));
+    int rc = upload(ctx, const_cast<msc_circuit*>(c));
+    if (rc) return rc;
+    const double tau = opts->tau_trunc > 0 ? opts->tau_trunc : (opts->precision == MSC_FP64 ? 1e-12 : 1e-5);
+    const double tau_rej = opts->tau_rej > 0 ? opts->tau_rej : 1e-6;
+    const double tau_fail = opts->tau_fail > 0 ? opts->tau_fail : 1e-4;
+    const int lds_width = opts->lds_width == 64 ? 64 : 32;
+    if (opts->prefix && (rc = ensure_prefix(ctx, const_cast<msc_circuit*>(c), opts->precision,
+                                            opts->chi_max, tau, tau_rej, tau_fail, lds_width)))
+        return rc;
+    // host-mapped block for the reduction: bins, then the totals
+    const size_t hbytes = 3 * static_cast<size_t>(n_bins) * sizeof(double) + sizeof(BatchTotals);
+    if (ctx->hmap_bytes < hbytes) {
+        if (ctx->hmap) (void)hipHostFree(ctx->hmap);
+        ctx->hmap = nullptr;
+        ctx->hmap_bytes = 0;
+        MSC_HIP(hipHostMalloc(&ctx->hmap, hbytes, hipHostMallocMapped | hipHostMallocCoherent));
+        MSC_HIP(hipHostGetDevicePointer(&ctx->hmap_dev, ctx->hmap, 0));
+        ctx->hmap_bytes = hbytes;
+    }
+    void* dcdf;
+    int32_t ncdf;
+    if ((rc = device_cdf(ctx, c->n_channels, p, &dcdf, &ncdf))) return rc;
+    // every shot draws at most the table's largest weight (and at most M)
+    const int64_t wmax = std::min<int64_t>(c->n_channels, std::max<int32_t>(0, ncdf - 1));
+    const int64_t cap = std::max<int64_t>(1, n_shots * wmax);
+    if (cap > (int64_t(1) << 28)) return set_error(MSC_E_CAPACITY, "fault buffer above 2^28 entries");
+    const int64_t nts = sampler_tmp_words(n_shots), ntp = prescreen_tmp_words(n_shots);
+    void *doff, *dchan, *dpa, *dbits, *didx, *dres, *dts, *dtp;
+    if ((rc = ctx_buf(ctx, "b_off", (n_shots + 1) * sizeof(int64_t), &doff))) return rc;
+    if ((rc = ctx_buf(ctx, "b_chan", cap * sizeof(int32_t), &dchan))) return rc;
+    if ((rc = ctx_buf(ctx, "b_pauli", cap, &dpa))) return rc;
+    if ((rc = ctx_buf(ctx, "b_bits", ((n_shots + 63) / 64 + 1) * sizeof(uint64_t), &dbits))) return rc;
+    if ((rc = ctx_buf(ctx, "b_idx", std::max<int64_t>(1, n_shots) * sizeof(int64_t), &didx))) return rc;
+    if ((rc = ctx_buf(ctx, "b_res", std::max<int64_t>(1, n_shots) * sizeof(msc_shot_result), &dres))) return rc;
+    if ((rc = ctx_buf(ctx, "b_tmp_s", nts * sizeof(int64_t), &dts))) return rc;
+    if ((rc = ctx_buf(ctx, "b_tmp_p", std::max<int64_t>(2, ntp) * sizeof(int64_t), &dtp))) return rc;
+    int64_t* offp = static_cast<int64_t*>(doff);
+    int64_t* idxp = static_cast<int64_t*>(didx);
+    int64_t* nsurv = static_cast<int64_t*>(dtp) + (ntp - 1);   // the screen's total
+    int64_t* nnz = static_cast<int64_t*>(dts) + (nts - 1);     // the sampler's total
+    double* hbins = static_cast<double*>(ctx->hmap_dev);
+    BatchTotals* htot = reinterpret_cast<BatchTotals*>(hbins + 3 * static_cast<size_t>(n_bins));
+    msc_shot_result* res = static_cast<msc_shot_result*>(dres);
+    if (n_shots == 0) {
+        for (int32_t b = 0; b < 3 * n_bins; ++b) bins[b] = 0.0;
+        if (stats) *stats = msc_batch_stats{};
+        return MSC_OK;
+    }
+    MSC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
+    MSC_HIP(launch_sampler(n_shots, seed, first_shot, nullptr, static_cast<const double*>(dcdf),
+                           ncdf, c->n_channels, static_cast<const uint8_t*>(c->d_kind), cap, offp,
+                           static_cast<int32_t*>(dchan), static_cast<uint8_t*>(dpa),
+                           static_cast<int64_t*>(dts), nts, ctx->stream));
+    MSC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
+    MSC_HIP(launch_prescreen(c->words, c->n_channels, n_shots, offp, static_cast<int32_t*>(dchan),
+                             static_cast<uint8_t*>(dpa), static_cast<const uint64_t*>(c->d_sig),
+                             static_cast<uint64_t*>(dbits), idxp, static_cast<int64_t*>(dtp), ntp,
+                             ctx->stream));
+    MSC_HIP(hipEventRecord(ctx->ev2, ctx->stream));
+    rc = enqueue_shots(ctx, c, opts->precision, opts->chi_max, tau, tau_rej, tau_fail,
+                       opts->n_slots, lds_width, n_shots, n_shots, offp,
+                       static_cast<int32_t*>(dchan), static_cast<uint8_t*>(dpa), idxp, res, 0,
+                       nullptr, nullptr, opts->prefix ? 2 : 0, opts->prefix ? &c->prefix : nullptr,
+                       nsurv);
+    if (rc) return rc;
+    MSC_HIP(hipEventRecord(ctx->ev3, ctx->stream));
+    MSC_HIP(launch_batch_reduce(n_shots, offp, idxp, nsurv, res, n_bins, nnz, hbins, htot,
+                                ctx->stream));
+    if (out) MSC_HIP(launch_scatter_results(n_shots, nsurv, idxp, res, out, ctx->stream));
+    MSC_HIP(hipStreamSynchronize(ctx->stream));
+    const double* hb = static_cast<const double*>(ctx->hmap);
+    for (int32_t b = 0; b < 3 * n_bins; ++b) bins[b] = hb[b];
+    const BatchTotals* ht = reinterpret_cast<const BatchTotals*>(hb + 3 * static_cast<size_t>(n_bins));
+    float t01 = 0.f, t12 = 0.f, t23 = 0.f;
+    MSC_HIP(hipEventElapsedTime(&t01, ctx->ev0, ctx->ev1));
+    MSC_HIP(hipEventElapsedTime(&t12, ctx->ev1, ctx->ev2));
+    MSC_HIP(hipEventElapsedTime(&t23, ctx->ev2, ctx->ev3));
+    ctx->last_ms["sample"] = t01;
+    ctx->last_ms["prescreen"] = t12;
+    ctx->last_ms["simulate"] = t23;
+    if (stats) {
+        stats->n_shots = n_shots;
+        stats->nnz = ht->nnz;
+        stats->n_survivors = ht->n_survivors;
+        stats->n_accepted = ht->n_accepted;
+        stats->n2q = ht->n2q;
+        stats->sweeps = ht->sweeps;
+        stats->flops = ht->flops;
+        stats->chi_peak = ht->chi_peak;
+        stats->status_or = ht->status_or;
+        stats->ms_sample = t01;
+        stats->ms_screen = t12;
+        stats->ms_simulate = t23;
+    }
     return MSC_OK;
 }
 

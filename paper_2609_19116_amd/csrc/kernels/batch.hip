@@ -1,0 +1,153 @@
+// End of a batch: per-weight bins and batch statistics (Section 4.1,
+// Eq. (reweight)), written straight into host-mapped memory so that the
+// host reads them after one stream synchronisation, without a copy.
+//
+// One 256-thread workgroup.  Counts use LDS integer atomics (exact); the
+// FP64 sums are reduced in a fixed order (per bin, each thread walks a
+// fixed strided subset of the survivors, then a fixed tree), so the bins
+// are bit-reproducible.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace msc {
+namespace {
+
+constexpr int RT = 256;
+
+__device__ double block_sum_fixed(double v, double* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int j = 0; j < RT / 64; ++j) s += red[j];
+    return s;
+}
+
+__global__ __launch_bounds__(RT) void batch_reduce_kernel(int64_t n, const int64_t* __restrict__ off,
+                                                          const int64_t* __restrict__ idx,
+                                                          const int64_t* __restrict__ n_surv,
+                                                          const msc_shot_result* __restrict__ res,
+                                                          int nb, const int64_t* __restrict__ nnz,
+                                                          double* __restrict__ bins,
+                                                          BatchTotals* __restrict__ tot) {
+    __shared__ int s_cnt[kMaxBins];
+    __shared__ int s_scnt[kMaxBins];
+    __shared__ double s_red[RT / 64];
+    __shared__ unsigned long long s_n2q, s_sweeps;
+    __shared__ int s_acc, s_chi, s_status;
+    const int tid = threadIdx.x;
+    for (int b = tid; b < nb; b += RT) {
+        s_cnt[b] = 0;
+        s_scnt[b] = 0;
+    }
+    if (tid == 0) {
+        s_n2q = 0;
+        s_sweeps = 0;
+        s_acc = 0;
+        s_chi = 0;
+        s_status = 0;
+    }
+    __syncthreads();
+    auto weight = [&](int64_t s) {
+        const int64_t w = off[s + 1] - off[s];
+        return static_cast<int>(w < nb - 1 ? w : nb - 1);
+    };
+    for (int64_t i = tid; i < n; i += RT) atomicAdd(&s_cnt[weight(i)], 1);
+    const int64_t ns = *n_surv;
+    double fl = 0.0;
+    for (int64_t s = tid; s < ns; s += RT) {
+        atomicAdd(&s_scnt[weight(idx[s])], 1);
+        const msc_shot_result& r = res[s];
+        atomicAdd(&s_n2q, static_cast<unsigned long long>(r.n2q));
+        atomicAdd(&s_sweeps, static_cast<unsigned long long>(r.sweeps));
+        if (r.p_acc > 0.0) atomicAdd(&s_acc, 1);
+        atomicMax(&s_chi, r.chi_peak);
+        atomicOr(&s_status, r.status);
+        fl += r.flops;
+    }
+    fl = block_sum_fixed(fl, s_red);
+    for (int b = 0; b < nb; ++b) {
+        if (s_scnt[b] == 0) {            // block-uniform
+            if (tid == 0) {
+                bins[nb + b] = 0.0;
+                bins[2 * nb + b] = 0.0;
+            }
+            continue;
+        }
+        double a = 0.0, e = 0.0;
+        for (int64_t s = tid; s < ns; s += RT) {
+            if (weight(idx[s]) != b) continue;
+            a += res[s].p_acc;
+            e += res[s].p_acc * res[s].fail;
+        }
+        a = block_sum_fixed(a, s_red);
+        e = block_sum_fixed(e, s_red);
+        if (tid == 0) {
+            bins[nb + b] = a;
+            bins[2 * nb + b] = e;
+        }
+    }
+    __syncthreads();
+    for (int b = tid; b < nb; b += RT) bins[b] = s_cnt[b];
+    if (tid == 0) {
+        tot->nnz = *nnz;
+        tot->n_survivors = ns;
+        tot->n_accepted = s_acc;
+        tot->n2q = static_cast<int64_t>(s_n2q);
+        tot->sweeps = static_cast<int64_t>(s_sweeps);
+        tot->flops = fl;
+        tot->chi_peak = s_chi;
+        tot->status_or = s_status;
+    }
+}
+
+// zero records (rejected_at -1) for every shot of a shot-indexed output
+__global__ __launch_bounds__(RT) void fill_results_kernel(int64_t n, msc_shot_result* out) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * RT + threadIdx.x;
+    if (i >= n) return;
+    msc_shot_result z{};
+    z.rejected_at = -1;
+    out[i] = z;
+}
+
+// survivor-indexed results to shot-indexed ones
+__global__ __launch_bounds__(RT) void scatter_results_kernel(int64_t n, const int64_t* n_surv,
+                                                             const int64_t* idx,
+                                                             const msc_shot_result* res,
+                                                             msc_shot_result* out) {
+    const int64_t s = static_cast<int64_t>(blockIdx.x) * RT + threadIdx.x;
+    if (s >= *n_surv || s >= n) return;
+    const int64_t i = idx[s];
+    if (i >= 0 && i < n) out[i] = res[s];
+}
+
+}  // namespace
+
+hipError_t launch_batch_reduce(int64_t n, const int64_t* off, const int64_t* idx,
+                               const int64_t* n_surv, const msc_shot_result* res, int nb,
+                               const int64_t* nnz, double* bins, BatchTotals* tot, hipStream_t s) {
+    if (nb < 1 || nb > kMaxBins) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3(1), dim3(RT), 0, s, n, off, idx, n_surv, res, nb,
+                       nnz, bins, tot);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_results(int64_t n, const int64_t* n_surv, const int64_t* idx,
+                                  const msc_shot_result* res, msc_shot_result* out,
+                                  hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const dim3 grid(static_cast<unsigned>((n + RT - 1) / RT));
+    hipLaunchKernelGGL(fill_results_kernel, grid, dim3(RT), 0, s, n, out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(scatter_results_kernel, grid, dim3(RT), 0, s, n, n_surv, idx, res, out);
+    return hipGetLastError();
+}
+
+}  // namespace msc

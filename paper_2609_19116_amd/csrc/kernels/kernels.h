@@ -34,6 +34,7 @@ struct MpsArgs {
     const int64_t* shot_idx;   // optional subset
     const int64_t* perm;       // processing order of the n_shots entries
     int64_t n_shots;           // shots to simulate (entries of shot_idx)
+    const int64_t* n_dev;      // if set: the count on the device (<= n_shots)
     int64_t n_csr;             // shots held by the CSR
     const uint8_t* expected;   // e_m per measurement
     msc_shot_result* out;
@@ -71,8 +72,9 @@ hipError_t launch_mps(int precision, bool small, const MpsArgs& a, int grid, hip
 // perm[0..n): stable order of the shots, by fault count (fewest first) or,
 // with n_channels > 0, by first faulty channel (earliest first, fault-free
 // shots last): the order in which their remaining work shrinks
-hipError_t launch_order(int64_t n, const int64_t* shot_off, const int64_t* shot_idx, int64_t n_csr,
-                        const int32_t* chan, int32_t n_channels, int64_t* perm, hipStream_t s);
+hipError_t launch_order(int64_t n, const int64_t* n_dev, const int64_t* shot_off,
+                        const int64_t* shot_idx, int64_t n_csr, const int32_t* chan,
+                        int32_t n_channels, int64_t* perm, hipStream_t s);
 // resident workgroups per CU of the chosen variant (sizes the persistent grid)
 int mps_blocks_per_cu(int precision, bool small);
 
@@ -89,6 +91,20 @@ hipError_t launch_sampler(int64_t n, uint64_t seed, uint64_t first, const int32_
                           int64_t nnz_cap, int64_t* shot_off, int32_t* chan, uint8_t* pauli,
                           int64_t* tmp, int64_t n_tmp, hipStream_t s);
 int64_t sampler_tmp_words(int64_t n);
+
+// batch reduction into host-mapped memory (batch.hip)
+constexpr int kMaxBins = 1024;
+struct BatchTotals {
+    int64_t nnz, n_survivors, n_accepted, n2q, sweeps;
+    double flops;
+    int32_t chi_peak, status_or;
+};
+hipError_t launch_batch_reduce(int64_t n, const int64_t* off, const int64_t* idx,
+                               const int64_t* n_surv, const msc_shot_result* res, int nb,
+                               const int64_t* nnz, double* bins, BatchTotals* tot, hipStream_t s);
+hipError_t launch_scatter_results(int64_t n, const int64_t* n_surv, const int64_t* idx,
+                                  const msc_shot_result* res, msc_shot_result* out,
+                                  hipStream_t s);
 
 hipError_t launch_twosite(int precision, int chi, int batch, const float* A, const float* B,
                           const float* gate, float* theta, hipStream_t s);

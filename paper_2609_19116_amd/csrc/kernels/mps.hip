@@ -1,11 +1,12 @@
 // Persistent batched MPS shot kernel for gfx950.
 //
-// One workgroup (4 wavefronts, one per SIMD) owns one MPS slot in HBM and runs whole shots
-// through the compiled op stream, taking shots blockIdx.x, blockIdx.x +
-// gridDim.x, ...  Each shot has its own ragged bond dimensions, kept in LDS,
-// and stops at the first measurement whose expected outcome has probability
-// below tau_rej (online screening, Section 4.3), so a rejected shot frees
-// its workgroup for the next one at once.
+// One workgroup (4 wavefronts, one per SIMD) owns one MPS slot in HBM and
+// runs whole shots through the compiled op stream, taking shots blockIdx.x,
+// blockIdx.x + gridDim.x, ...  Each shot has its own ragged bond
+// dimensions, kept in LDS, and stops at the first measurement whose
+// expected outcome has probability below tau_rej (online screening,
+// Section 4.3), so a rejected shot frees its workgroup for the next one at
+// once.
 //
 // Per op (Section 3.1 for the MPS, Section 4 for the shot semantics):
 //  * 1q gates and Pauli faults act on one site tensor (chi_l x 2 x chi_r);
@@ -23,6 +24,13 @@
 //    otherwise projects, renormalises and multiplies P_acc by p_e;
 //  * the final op reads the seed qubit's reduced density matrix and the
 //    fidelity with the target (Appendix "Post-selection and logical error").
+//
+// Latency, not arithmetic, bounds a shot: the ops are small and strictly
+// sequential.  Small factorisations (both sides of theta at most 32, the
+// bulk of the updates) and centre moves therefore run on wavefront 0 alone
+// with wave-level synchronisation while the other three wavefronts wait at
+// the op's one workgroup barrier; larger ones use the whole workgroup.  Op
+// descriptors, gate tables and the slot layout are served from LDS.
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -37,74 +45,158 @@ constexpr int NT = 256;
 constexpr int NW = NT / 64;
 constexpr int MAXV = 2 * kMaxChiKernel;   // vectors in a two-site SVD
 constexpr int kStage = 2048;               // doubles of LDS staging per workgroup
+constexpr int kOpBuf = 256;                // op descriptors per LDS refill
+constexpr int kWaveSide = 16;              // largest theta side factorised by one wave
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+// A team is either the whole workgroup (W == NT) or wavefront 0 (W == 64).
+template <int W>
+struct Team {
+    static __device__ __forceinline__ int rank() { return W == 64 ? (threadIdx.x & 63) : threadIdx.x; }
+    static __device__ __forceinline__ void sync() {
+        if constexpr (W == NT) {
+            __syncthreads();
+        } else {
+            // a workgroup-scope fence without the barrier: this wavefront's
+            // LDS and global writes become visible to all its lanes
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
+    }
+    static __device__ __forceinline__ bool any(int v) {
+        if constexpr (W == NT) {
+            return __syncthreads_or(v) != 0;
+        } else {
+            sync();
+            return __ballot(v) != 0ull;
+        }
+    }
+};
+
+// A double moved between lanes of a row of 16 by a DPP pattern (two 32-bit
+// lane moves): quad_perm [1,0,3,2] = 0xB1, quad_perm [2,3,0,1] = 0x4E,
+// row_half_mirror = 0x141, row_mirror = 0x140.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over aligned groups of g consecutive lanes (g a power of two <= 64),
+// every lane of a group receiving it: pairs within quads, then the two
+// quads of each half row (mirror), then the two halves of a row (mirror),
+// then across rows.
+__device__ __forceinline__ double group_sum(double v, int g) {
+    if (g >= 2) v += dpp_move<0xB1>(v);
+    if (g >= 4) v += dpp_move<0x4E>(v);
+    if (g >= 8) v += dpp_move<0x141>(v);
+    if (g >= 16) v += dpp_move<0x140>(v);
+    if (g >= 32) v += __shfl_xor(v, 16);
+    if (g >= 64) v += __shfl_xor(v, 32);
     return v;
 }
 
-template <int K>
-__device__ __forceinline__ void block_sum(double (&v)[K], double* red) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+__device__ __forceinline__ double wave_sum(double v) { return group_sum(v, 64); }
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+template <int W, int K>
+__device__ __forceinline__ void team_sum(double (&v)[K], double* red) {
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
-    __syncthreads();
-    if (lane == 0) {
+    if constexpr (W == NT) {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        __syncthreads();
+        if (lane == 0) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) red[w * K + k] = v[k];
-    }
-    __syncthreads();
+            for (int k = 0; k < K; ++k) red[w * K + k] = v[k];
+        }
+        __syncthreads();
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        double s = 0.0;
+        for (int k = 0; k < K; ++k) {
+            double s = 0.0;
 #pragma unroll
-        for (int j = 0; j < NW; ++j) s += red[j * K + k];
-        v[k] = s;
+            for (int j = 0; j < NW; ++j) s += red[j * K + k];
+            v[k] = s;
+        }
     }
 }
 
-__device__ __forceinline__ double block_max(double v, double* red) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+template <int W>
+__device__ __forceinline__ double team_max(double v, double* red) {
+    v = wave_max(v);
+    if constexpr (W == NT) {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        __syncthreads();
+        if (lane == 0) red[w] = v;
+        __syncthreads();
+        double m = red[0];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    __syncthreads();
-    if (lane == 0) red[w] = v;
-    __syncthreads();
-    double m = red[0];
-#pragma unroll
-    for (int j = 1; j < NW; ++j) m = fmax(m, red[j]);
-    return m;
+        for (int j = 1; j < NW; ++j) m = fmax(m, red[j]);
+        v = m;
+    }
+    return v;
 }
 
 // Round-robin ("circle") pairing: slot 0 fixed, the others rotate each step.
 __device__ __forceinline__ int player(int slot, int t, int nv) {
-    return slot == 0 ? 0 : 1 + (slot - 1 + t) % (nv - 1);
+    if (slot == 0) return 0;
+    int p = slot - 1 + t;
+    if (p >= nv - 1) p -= nv - 1;
+    return 1 + p;
+}
+
+// Pointers into LDS and into global memory with their address space in the
+// type, so that the compiler emits ds_read/ds_write and global_load/store
+// rather than generic flat accesses in the hot loops.
+typedef __attribute__((address_space(3))) double ldsd;
+typedef __attribute__((address_space(3))) int ldsi;
+typedef __attribute__((address_space(1))) double glbd;
+typedef __attribute__((address_space(1))) int glbi;
+
+template <typename X>
+__device__ __forceinline__ __attribute__((address_space(3))) X* to_lds(X* p) {
+    return (__attribute__((address_space(3))) X*)p;
+}
+template <typename X>
+__device__ __forceinline__ __attribute__((address_space(1))) X* to_glb(X* p) {
+    return (__attribute__((address_space(1))) X*)p;
 }
 
 // One sweep of one-sided Jacobi (Hestenes) over the nv vectors list[0..nv)
 // of length len (planar FP64 at vre/vim, vector v at v*ld, ld >= len padded
 // against LDS bank conflicts): every pair (p, q) once, in round-robin order
 // so that the pairs of a step are disjoint and rotate in parallel (an odd
-// count gets a dummy slot).  The 2x2 rotation
-// makes the pair orthogonal: with gamma = x^H y, zeta = (|y|^2 - |x|^2) /
-// (2|gamma|), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1+t^2),
-// s = c t and y~ = y conj(gamma)/|gamma|: x <- c x - s y~, y <- s x + c y~.
-__device__ void jacobi_sweep(double* vre, double* vim, const int* list, int nv, int len, int ld,
-                             double floor2, double tol) {
-    const int tid = threadIdx.x;
+// count gets a dummy slot).  The 2x2 rotation makes the pair orthogonal:
+// with gamma = x^H y, d = |y|^2 - |x|^2, the tangent t = sign(d) / (|zeta| +
+// sqrt(1 + zeta^2)) of zeta = d / (2|gamma|), c = 1/sqrt(1+t^2), s = c t,
+// x <- c x - s y conj(gamma)/|gamma| and y <- c y + s x gamma/|gamma| (the
+// second vector keeps the phase of gamma, which leaves the pair orthogonal
+// and spares a division).  With D = |d| + sqrt(d^2 + 4|gamma|^2) and
+// rq = 1/sqrt(D^2 + 4|gamma|^2) this is c = D rq and s/|gamma| = 2 sign(d) rq:
+// one square root and one reciprocal square root per pair.
+template <int W, typename DP, typename IP>
+__device__ void jacobi_sweep(DP vre, DP vim, IP list, int nv, int len, int ld, double floor2,
+                             double tol) {
+    const int tid = Team<W>::rank();
     if (nv < 2) return;
     const int nve = nv + (nv & 1);   // the slot nv (if odd) is a dummy
     const int npairs = nve / 2;
-    int tpp = NT / npairs;
+    int tpp = W / npairs;
     if (tpp > 64) tpp = 64;
     if (tpp < 1) tpp = 1;
     int t2 = 1;
     while (t2 * 2 <= tpp) t2 *= 2;
     tpp = t2;
-    const int groups = NT / tpp;
+    const int groups = W / tpp;
     const int gl = tid % tpp;
     const int gi = tid / tpp;
+    const double tol2 = tol * tol;
     for (int t = 0; t < nve - 1; ++t) {
         for (int pb = 0; pb < npairs; pb += groups) {
             const int pi = pb + gi;
@@ -116,10 +208,11 @@ __device__ void jacobi_sweep(double* vre, double* vim, const int* list, int nv, 
             if (active) {
                 p = list[sp];
                 q = list[sq];
-                const double* xr = vre + (size_t)p * ld;
-                const double* xi = vim + (size_t)p * ld;
-                const double* yr = vre + (size_t)q * ld;
-                const double* yi = vim + (size_t)q * ld;
+                DP xr = vre + (size_t)p * ld;
+                DP xi = vim + (size_t)p * ld;
+                DP yr = vre + (size_t)q * ld;
+                DP yi = vim + (size_t)q * ld;
+#pragma unroll 4
                 for (int e = gl; e < len; e += tpp) {
                     double x0 = xr[e], x1 = xi[e], y0 = yr[e], y1 = yi[e];
                     a += x0 * x0 + x1 * x1;
@@ -128,106 +221,123 @@ __device__ void jacobi_sweep(double* vre, double* vim, const int* list, int nv, 
                     gim += x0 * y1 - x1 * y0;
                 }
             }
-            for (int o = tpp >> 1; o > 0; o >>= 1) {
-                a += __shfl_xor(a, o);
-                b += __shfl_xor(b, o);
-                gr += __shfl_xor(gr, o);
-                gim += __shfl_xor(gim, o);
-            }
+            a = group_sum(a, tpp);
+            b = group_sum(b, tpp);
+            gr = group_sum(gr, tpp);
+            gim = group_sum(gim, tpp);
             if (active) {
-                const double g = sqrt(gr * gr + gim * gim);
-                if (a > floor2 && b > floor2 && g > tol * sqrt(a * b)) {
-                    const double ig = 1.0 / g;
-                    const double zeta = 0.5 * (b - a) * ig;
-                    const double tt = (zeta >= 0.0 ? 1.0 : -1.0) /
-                                      (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double c = 1.0 / sqrt(1.0 + tt * tt);
-                    const double s = c * tt;
-                    const double pr = gr * ig, pim = gim * ig;
-                    double* xr = vre + (size_t)p * ld;
-                    double* xi = vim + (size_t)p * ld;
-                    double* yr = vre + (size_t)q * ld;
-                    double* yi = vim + (size_t)q * ld;
+                const double g2 = gr * gr + gim * gim;
+                if (a > floor2 && b > floor2 && g2 > tol2 * a * b) {
+                    const double d = b - a;
+                    const double D = fabs(d) + sqrt(d * d + 4.0 * g2);
+                    const double rq = 1.0 / sqrt(D * D + 4.0 * g2);
+                    const double c = D * rq;
+                    const double sg = (d >= 0.0 ? 2.0 : -2.0) * rq;  // s / |gamma|
+                    const double pr = sg * gr, pim = sg * gim;        // (s/|gamma|) gamma
+                    DP xr = vre + (size_t)p * ld;
+                    DP xi = vim + (size_t)p * ld;
+                    DP yr = vre + (size_t)q * ld;
+                    DP yi = vim + (size_t)q * ld;
+#pragma unroll 4
                     for (int e = gl; e < len; e += tpp) {
-                        double x0 = xr[e], x1 = xi[e];
-                        double y0 = yr[e] * pr + yi[e] * pim;
-                        double y1 = yi[e] * pr - yr[e] * pim;
-                        xr[e] = c * x0 - s * y0;
-                        xi[e] = c * x1 - s * y1;
-                        yr[e] = s * x0 + c * y0;
-                        yi[e] = s * x1 + c * y1;
+                        const double x0 = xr[e], x1 = xi[e], y0 = yr[e], y1 = yi[e];
+                        // x - (s/|g|) conj(gamma) y and y + (s/|g|) gamma x
+                        xr[e] = c * x0 - (pr * y0 + pim * y1);
+                        xi[e] = c * x1 - (pr * y1 - pim * y0);
+                        yr[e] = c * y0 + (pr * x0 - pim * x1);
+                        yi[e] = c * y1 + (pr * x1 + pim * x0);
                     }
                 }
             }
         }
-        __syncthreads();
+        Team<W>::sync();
     }
 }
 
 // Squared norms of nv vectors (stride ld) into nrm.
-__device__ void vector_norms(const double* vre, const double* vim, int nv, int len, int ld,
-                             double* nrm) {
-    for (int v = threadIdx.x; v < nv; v += NT) {
-        double s = 0.0;
-        const double* xr = vre + (size_t)v * ld;
-        const double* xi = vim + (size_t)v * ld;
-        for (int e = 0; e < len; ++e) s += xr[e] * xr[e] + xi[e] * xi[e];
-        nrm[v] = s;
+template <int W, typename DP>
+__device__ void vector_norms(DP vre, DP vim, int nv, int len, int ld, DP nrm) {
+    for (int v = Team<W>::rank(); v < nv; v += W) {
+        double s0 = 0.0, s1 = 0.0;
+        DP xr = vre + (size_t)v * ld;
+        DP xi = vim + (size_t)v * ld;
+#pragma unroll 4
+        for (int e = 0; e < len; ++e) {
+            s0 += xr[e] * xr[e];
+            s1 += xi[e] * xi[e];
+        }
+        nrm[v] = s0 + s1;
     }
-    __syncthreads();
+    Team<W>::sync();
 }
 
 // One parallel pass over every pair of vectors whose squared norms exceed
 // floor2 (only pairs with a vector flagged in `only`, if given): marks in
 // `bad` every vector of a pair that overlaps by more than tol and returns
-// true (block-uniform) if there is one.
-__device__ bool not_orthogonal(const double* vre, const double* vim, int nv, int len, int ld,
-                               const double* nrm, double floor2, double tol, int* bad,
-                               const int* only) {
-    for (int v = threadIdx.x; v < nv; v += NT) bad[v] = 0;
-    __syncthreads();
+// true (team-uniform) if there is one.
+template <int W, typename DP, typename IP>
+__device__ bool not_orthogonal(DP vre, DP vim, int nv, int len, int ld, DP nrm, double floor2,
+                               double tol, IP bad, IP only) {
+    const int tid = Team<W>::rank();
+    for (int v = tid; v < nv; v += W) bad[v] = 0;
+    Team<W>::sync();
     int any = 0;
-    for (int t = threadIdx.x; t < nv * nv; t += NT) {
-        const int p = t / nv, q = t - p * nv;
-        if (q <= p) continue;
+    const int npair = nv * (nv - 1) / 2;
+    const double tol2 = tol * tol;
+    // pair index t -> (p, q), p < q, walking the upper triangle row by row
+    int p = 0, rowlen = nv - 1, t0 = 0;
+    for (int t = tid; t < npair; t += W) {
+        while (t >= t0 + rowlen) {
+            t0 += rowlen;
+            ++p;
+            --rowlen;
+        }
+        const int q = p + 1 + (t - t0);
         if (only && !(only[p] | only[q])) continue;
         const double a = nrm[p], b = nrm[q];
         if (!(a > floor2 && b > floor2)) continue;
-        const double* xr = vre + (size_t)p * ld;
-        const double* xi = vim + (size_t)p * ld;
-        const double* yr = vre + (size_t)q * ld;
-        const double* yi = vim + (size_t)q * ld;
+        DP xr = vre + (size_t)p * ld;
+        DP xi = vim + (size_t)p * ld;
+        DP yr = vre + (size_t)q * ld;
+        DP yi = vim + (size_t)q * ld;
         double gr = 0.0, gim = 0.0;
+#pragma unroll 4
         for (int e = 0; e < len; ++e) {
             gr += xr[e] * yr[e] + xi[e] * yi[e];
             gim += xr[e] * yi[e] - xi[e] * yr[e];
         }
-        if (gr * gr + gim * gim > tol * tol * a * b) {
+        if (gr * gr + gim * gim > tol2 * a * b) {
             any = 1;
             bad[p] = 1;   // benign race: every writer stores 1
             bad[q] = 1;
         }
     }
-    return __syncthreads_or(any) != 0;
+    return Team<W>::any(any);
 }
 
 // Compacts the flagged vectors into list (ascending); returns their count.
-__device__ int flagged_list(const int* flag, int nv, int* list, int* red) {
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+template <int W, typename IP>
+__device__ int flagged_list(IP flag, int nv, IP list, int* red) {
+    const int tid = Team<W>::rank(), lane = tid & 63, w = tid >> 6;
     int base = 0;
-    for (int b0 = 0; b0 < nv; b0 += NT) {
+    for (int b0 = 0; b0 < nv; b0 += W) {
         const int v = b0 + tid;
         const bool f = v < nv && flag[v];
         const uint64_t m = __ballot(f);
-        __syncthreads();
-        if (lane == 0) red[w] = __popcll(m);
-        __syncthreads();
-        int off = base;
-        for (int q = 0; q < w; ++q) off += red[q];
-        if (f) list[off + __popcll(m & ((1ull << lane) - 1ull))] = v;
-        for (int q = 0; q < NW; ++q) base += red[q];
+        if constexpr (W == NT) {
+            __syncthreads();
+            if (lane == 0) red[w] = __popcll(m);
+            __syncthreads();
+            int off = base;
+            for (int q = 0; q < w; ++q) off += red[q];
+            if (f) list[off + __popcll(m & ((1ull << lane) - 1ull))] = v;
+            for (int q = 0; q < NW; ++q) base += red[q];
+        } else {
+            if (f) list[base + __popcll(m & ((1ull << lane) - 1ull))] = v;
+            base += __popcll(m);
+        }
     }
-    __syncthreads();
+    Team<W>::sync();
     return base;
 }
 
@@ -237,14 +347,17 @@ struct Kept {
 };
 
 // Keep the vectors with sigma^2 > tau2 * sigma_0^2 (at most capb), ordered by
-// decreasing norm: sel[0..r) are their indices.
-__device__ Kept select_kept(const double* nrm, int nv, double tau2, int capb, int* sel,
+// decreasing norm: sel[0..r) are their indices, isq[c] = 1/sigma and
+// sq[c] = sigma of the c-th kept vector (each computed once here).
+template <int W, typename DP, typename IP>
+__device__ Kept select_kept(DP nrm, int nv, double tau2, int capb, IP sel, DP isq, DP sq,
                             double* red) {
+    const int tid = Team<W>::rank();
     double mx = 0.0;
-    for (int v = threadIdx.x; v < nv; v += NT) mx = fmax(mx, nrm[v]);
-    mx = block_max(mx, red);
+    for (int v = tid; v < nv; v += W) mx = fmax(mx, nrm[v]);
+    mx = team_max<W>(mx, red);
     double kd[3] = {0.0, 0.0, 0.0};
-    for (int v = threadIdx.x; v < nv; v += NT) {
+    for (int v = tid; v < nv; v += W) {
         const double x = nrm[v];
         int rank = 0;
         for (int u = 0; u < nv; ++u) {
@@ -253,14 +366,18 @@ __device__ Kept select_kept(const double* nrm, int nv, double tau2, int capb, in
         }
         const bool keep = (x > tau2 * mx || rank == 0) && rank < capb;
         if (keep) {
+            const double s = sqrt(x);
             sel[rank] = v;
+            sq[rank] = s;
+            isq[rank] = 1.0 / s;
             kd[0] += 1.0;
             kd[1] += x;
         } else {
             kd[2] += x;
         }
     }
-    block_sum<3>(kd, red);
+    team_sum<W, 3>(kd, red);
+    Team<W>::sync();
     Kept k;
     k.r = static_cast<int>(kd[0] + 0.5);
     k.kept = kd[1];
@@ -268,11 +385,486 @@ __device__ Kept select_kept(const double* nrm, int nv, double tau2, int capb, in
     return k;
 }
 
+// A site tensor in the slot (global memory): real and imaginary planes.
 template <typename T>
 struct SiteView {
-    T* re;
-    T* im;
+    __attribute__((address_space(1))) T* re;
+    __attribute__((address_space(1))) T* im;
 };
+
+// LDS of a workgroup, shared by the op implementations.
+struct Smem {
+    int* chi;            // [kMaxSites + 1] bond dimensions
+    double* vre;         // SVD vectors (SMAX x (SMAX + 1)), planar
+    double* vim;
+    double* nrm;         // [SMAX]
+    double* isq;         // [SMAX]
+    double* sq;          // [SMAX]
+    int* sel;
+    int* bad;
+    int* list;
+    int* ired;           // [NW]
+    double* red;         // [NW * 4]
+    const int* cap;      // [kMaxSites + 1] bond capacities
+    double* u;           // [kStage] staging
+    const int* g4src;    // [G4_COUNT * 4] monomial 4x4 gates: source column
+    const double* g4ph;  // [G4_COUNT * 8] and phase of each row
+};
+
+// Per-vector work arrays of a factorisation: in LDS or in the slot's HBM
+// scratch (DP, IP carry the address space).
+template <typename DP, typename IP>
+struct Vecs {
+    DP vre, vim, nrm, isq, sq;
+    IP sel, bad, list;
+};
+
+// Per-shot counters, reported by thread 0.
+struct ShotAcc {
+    int status = 0;
+    int chi_peak = 1;
+    double disc = 0.0;
+    int64_t n2q = 0;
+    double flops = 0.0;
+    int64_t sweeps = 0;
+};
+
+// Centre move from site k to k+1 (dir 1) or k+1 to k (dir 0) when the
+// centre site's vectors (columns for dir 1, rows for dir 0) are already
+// orthogonal, as they are after a split that left the centre there: a
+// selection of the kept vectors, their normalisation and a rescaling of the
+// neighbour.  Returns false (team-uniform) when a pair overlaps; the caller
+// then falls back to a two-site identity update.  Requires nv, len <= SMAX.
+template <typename T, int SMAX, int W>
+__device__ bool move_fast(const MpsArgs& P, const Smem& S, SiteView<T> A, SiteView<T> B, int k,
+                          int dir, double* scr, ShotAcc& acc) {
+    typedef __attribute__((address_space(1))) T gT;
+    const int tid = Team<W>::rank();
+    const int cl = S.chi[k], cm = S.chi[k + 1], cr = S.chi[k + 2];
+    const int nv = cm, len = dir ? 2 * cl : 2 * cr, ld = len + 1;
+    ldsd* vre = to_lds(S.vre);
+    ldsd* vim = to_lds(S.vim);
+    ldsd* nrm = to_lds(S.nrm);
+    ldsd* isq = to_lds(S.isq);
+    ldsd* sq = to_lds(S.sq);
+    ldsi* sel = to_lds(S.sel);
+    gT* Are = A.re;
+    gT* Aim = A.im;
+    gT* Bre = B.re;
+    gT* Bim = B.im;
+    {
+        gT* Xre = dir ? Are : Bre;
+        gT* Xim = dir ? Aim : Bim;
+        for (int idx = tid; idx < nv * len; idx += W) {
+            const int v = idx / len, e = idx - v * len;
+            const int at = dir ? e * cm + v : v * len + e;
+            vre[v * ld + e] = static_cast<double>(Xre[at]);
+            vim[v * ld + e] = static_cast<double>(Xim[at]);
+        }
+    }
+    Team<W>::sync();
+    vector_norms<W>(vre, vim, nv, len, ld, nrm);
+    double tsum[1] = {0.0};
+    for (int v = tid; v < nv; v += W) tsum[0] += nrm[v];
+    team_sum<W, 1>(tsum, S.red);
+    const double tau2 = P.tau * P.tau;
+    const double tol = sizeof(T) == sizeof(double) ? static_cast<double>(len) * DBL_EPSILON
+                                                   : 8.0 * static_cast<double>(FLT_EPSILON);
+    if (not_orthogonal<W>(vre, vim, nv, len, ld, nrm, 1e-4 * tau2 * tsum[0], tol,
+                          to_lds(S.bad), (ldsi*)nullptr))
+        return false;
+    const int capb = min(P.chi_max, S.cap[k + 1]);
+    const Kept kp = select_kept<W>(nrm, nv, tau2, capb, sel, isq, sq, S.red);
+    const int r = kp.r;
+    acc.disc += kp.dropped;
+    if (kp.dropped > 1e-12 * tsum[0] && r == capb) acc.status |= MSC_SHOT_CHI_CAP;
+    const double renorm = 1.0 / sqrt(kp.kept);
+    if (dir) {
+        // A[k] <- normalised columns; A[k+1] <- its selected rows, rescaled
+        // (rows c of the new A[k+1] are rows sel[c] of the old one, so they
+        // are read before any is written: staged through LDS when it fits)
+        for (int idx = tid; idx < 2 * cl * r; idx += W) {
+            const int e = idx / r, c = idx - e * r;
+            const int v = sel[c];
+            const double is = isq[c];
+            Are[idx] = T(vre[v * ld + e] * is);
+            Aim[idx] = T(vim[v * ld + e] * is);
+        }
+        const int w = 2 * cr;
+        Team<W>::sync();
+        if (r * w <= SMAX * (SMAX + 1)) {
+            for (int idx = tid; idx < r * w; idx += W) {
+                const int c = idx / w, x = idx - c * w;
+                const int v = sel[c];
+                const double sc = sq[c] * renorm;
+                vre[idx] = static_cast<double>(Bre[v * w + x]) * sc;
+                vim[idx] = static_cast<double>(Bim[v * w + x]) * sc;
+            }
+            Team<W>::sync();
+            for (int idx = tid; idx < r * w; idx += W) {
+                Bre[idx] = T(vre[idx]);
+                Bim[idx] = T(vim[idx]);
+            }
+        } else {
+            glbd* tr_ = to_glb(scr);
+            glbd* ti_ = tr_ + (size_t)r * w;
+            for (int idx = tid; idx < r * w; idx += W) {
+                const int c = idx / w, x = idx - c * w;
+                const int v = sel[c];
+                const double sc = sq[c] * renorm;
+                tr_[idx] = static_cast<double>(Bre[v * w + x]) * sc;
+                ti_[idx] = static_cast<double>(Bim[v * w + x]) * sc;
+            }
+            Team<W>::sync();
+            for (int idx = tid; idx < r * w; idx += W) {
+                Bre[idx] = T(tr_[idx]);
+                Bim[idx] = T(ti_[idx]);
+            }
+        }
+    } else {
+        // A[k+1] <- normalised rows; A[k] <- its selected columns, rescaled
+        const int w = 2 * cr;
+        for (int idx = tid; idx < r * w; idx += W) {
+            const int c = idx / w, e = idx - c * w;
+            const int v = sel[c];
+            const double is = isq[c];
+            Bre[idx] = T(vre[v * ld + e] * is);
+            Bim[idx] = T(vim[v * ld + e] * is);
+        }
+        Team<W>::sync();
+        if (2 * cl * r <= SMAX * (SMAX + 1)) {
+            for (int idx = tid; idx < 2 * cl * r; idx += W) {
+                const int row = idx / r, c = idx - row * r;
+                const int v = sel[c];
+                const double sc = sq[c] * renorm;
+                vre[idx] = static_cast<double>(Are[row * cm + v]) * sc;
+                vim[idx] = static_cast<double>(Aim[row * cm + v]) * sc;
+            }
+            Team<W>::sync();
+            for (int idx = tid; idx < 2 * cl * r; idx += W) {
+                Are[idx] = T(vre[idx]);
+                Aim[idx] = T(vim[idx]);
+            }
+        } else {
+            glbd* tr_ = to_glb(scr);
+            glbd* ti_ = tr_ + (size_t)2 * cl * r;
+            for (int idx = tid; idx < 2 * cl * r; idx += W) {
+                const int row = idx / r, c = idx - row * r;
+                const int v = sel[c];
+                const double sc = sq[c] * renorm;
+                tr_[idx] = static_cast<double>(Are[row * cm + v]) * sc;
+                ti_[idx] = static_cast<double>(Aim[row * cm + v]) * sc;
+            }
+            Team<W>::sync();
+            for (int idx = tid; idx < 2 * cl * r; idx += W) {
+                Are[idx] = T(tr_[idx]);
+                Aim[idx] = T(ti_[idx]);
+            }
+        }
+    }
+    Team<W>::sync();
+    if (tid == 0) S.chi[k + 1] = r;
+    return true;
+}
+
+// theta = G . (A[k] A[k+1]) for the rows a of A[k]: written into the vectors
+// (columns of theta for dir 1, rows for dir 0) with their total squared
+// norm returned per thread.
+template <typename T, int W, typename AP, typename DP>
+__device__ double contract(AP Ar, AP Ai, AP Br, AP Bi, int cl, int cm, int cr, const int* gsrc,
+                           const double* gph, int dir, int ld, DP vre, DP vim) {
+    const int tid = Team<W>::rank();
+    double nsum = 0.0;
+    for (int idx = tid; idx < cl * cr; idx += W) {
+        const int a = idx / cr, b = idx - a * cr;
+        T sr[4] = {T(0), T(0), T(0), T(0)}, si[4] = {T(0), T(0), T(0), T(0)};
+        AP a0r = Ar + (a * 2) * cm;
+        AP a0i = Ai + (a * 2) * cm;
+#pragma unroll 4
+        for (int c = 0; c < cm; ++c) {
+            const T x0r = a0r[c], x0i = a0i[c], x1r = a0r[cm + c], x1i = a0i[cm + c];
+            const int b0 = (c * 2) * cr + b, b1 = b0 + cr;
+            const T y0r = Br[b0], y0i = Bi[b0], y1r = Br[b1], y1i = Bi[b1];
+            // S[i'j'] += A[a,i',c] B[c,j',b]
+            sr[0] += x0r * y0r - x0i * y0i; si[0] += x0r * y0i + x0i * y0r;
+            sr[1] += x0r * y1r - x0i * y1i; si[1] += x0r * y1i + x0i * y1r;
+            sr[2] += x1r * y0r - x1i * y0i; si[2] += x1r * y0i + x1i * y0r;
+            sr[3] += x1r * y1r - x1i * y1i; si[3] += x1r * y1i + x1i * y1r;
+        }
+        // monomial gate: output o = phase[o] * S[src[o]]
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const int j = gsrc[o];
+            const double xr = static_cast<double>(sr[j]), xi = static_cast<double>(si[j]);
+            const double pr = gph[2 * o], pim = gph[2 * o + 1];
+            const double tr_ = pr * xr - pim * xi;
+            const double ti_ = pr * xi + pim * xr;
+            const int i = o >> 1, jj = o & 1;
+            const int row = a * 2 + i, col = jj * cr + b;
+            const size_t vi = dir ? (size_t)col * ld + row : (size_t)row * ld + col;
+            vre[vi] = tr_;
+            vim[vi] = ti_;
+            nsum += tr_ * tr_ + ti_ * ti_;
+        }
+    }
+    return nsum;
+}
+
+// Projection of theta (m x n, planar FP64 at thr/thi) on the kept vectors:
+// R[c][col] = sum_row conj(U[row][c]) theta[row][col] into B (dir 1), or
+// L[row][c] = sum_col theta[row][col] conj(V[c][col]) into A (dir 0).
+template <typename T, int W, typename DP, typename IP, typename TP>
+__device__ void project(TP thr, TP thi, int m, int n, int r, int dir, int ld, const Vecs<DP, IP>& V,
+                        double renorm, __attribute__((address_space(1))) T* ore,
+                        __attribute__((address_space(1))) T* oim) {
+    const int tid = Team<W>::rank();
+    if (dir) {
+        for (int idx = tid; idx < r * n; idx += W) {
+            const int c = idx / n, col = idx - c * n;
+            const int v = V.sel[c];
+            const double is = renorm * V.isq[c];
+            DP ur = V.vre + (size_t)v * ld;
+            DP ui = V.vim + (size_t)v * ld;
+            double xr = 0.0, xi = 0.0;
+#pragma unroll 4
+            for (int row = 0; row < m; ++row) {
+                const double a0 = ur[row], a1 = ui[row];
+                const double t0 = thr[(size_t)row * n + col], t1 = thi[(size_t)row * n + col];
+                xr += a0 * t0 + a1 * t1;
+                xi += a0 * t1 - a1 * t0;
+            }
+            ore[idx] = T(xr * is);
+            oim[idx] = T(xi * is);
+        }
+    } else {
+        for (int idx = tid; idx < m * r; idx += W) {
+            const int row = idx / r, c = idx - row * r;
+            const int v = V.sel[c];
+            const double is = renorm * V.isq[c];
+            DP wr = V.vre + (size_t)v * ld;
+            DP wi = V.vim + (size_t)v * ld;
+            double xr = 0.0, xi = 0.0;
+#pragma unroll 4
+            for (int col = 0; col < n; ++col) {
+                const double t0 = thr[(size_t)row * n + col], t1 = thi[(size_t)row * n + col];
+                const double b0 = wr[col], b1 = wi[col];
+                xr += t0 * b0 + t1 * b1;
+                xi += t1 * b0 - t0 * b1;
+            }
+            ore[idx] = T(xr * is);
+            oim[idx] = T(xi * is);
+        }
+    }
+}
+
+// Two-site update of sites k, k+1 with the 4x4 gate gate_id; the centre
+// ends on k+1 (dir 1) or k (dir 0).  Sets chi[k+1] to the new bond.  V holds
+// the vectors (LDS for sides <= SMAX, else the slot's scratch).
+template <typename T, int SMAX, int W, typename DP, typename IP>
+__device__ void twosite_update(const MpsArgs& P, const Smem& S, SiteView<T> A, SiteView<T> B,
+                               int k, int dir, int gate_id, double* scr, const Vecs<DP, IP>& V,
+                               ShotAcc& acc) {
+    typedef __attribute__((address_space(1))) T gT;
+    typedef __attribute__((address_space(3))) T lT;
+    const int tid = Team<W>::rank();
+    const int cl = S.chi[k], cm = S.chi[k + 1], cr = S.chi[k + 2];
+    const int m = 2 * cl, n = 2 * cr;
+    const int nv = dir ? n : m, len = dir ? m : n;
+    const int ld = len + 1;
+    DP vre = V.vre, vim = V.vim, nrm = V.nrm;
+    IP sel = V.sel, bad = V.bad, list = V.list;
+    gT* Are = A.re;
+    gT* Aim = A.im;
+    gT* Bre = B.re;
+    gT* Bim = B.im;
+    // the 4x4 gates of the op stream are monomial: one nonzero per row
+    const int* gsrc = S.g4src + gate_id * 4;
+    const double* gph = S.g4ph + gate_id * 8;
+    // both site tensors into LDS with one coalesced pass when they fit: the
+    // contraction then reads each element from LDS
+    const int na = cl * 2 * cm, nb = cm * 2 * cr;
+    double nsum[1];
+    if ((size_t)2 * (na + nb) * sizeof(T) <= kStage * sizeof(double)) {
+        lT* st = to_lds(reinterpret_cast<T*>(S.u));
+        for (int i = tid; i < na; i += W) {
+            st[i] = Are[i];
+            st[na + i] = Aim[i];
+        }
+        for (int i = tid; i < nb; i += W) {
+            st[2 * na + i] = Bre[i];
+            st[2 * na + nb + i] = Bim[i];
+        }
+        Team<W>::sync();
+        nsum[0] = contract<T, W>(st, st + na, st + 2 * na, st + 2 * na + nb, cl, cm, cr, gsrc, gph,
+                                 dir, ld, vre, vim);
+    } else {
+        nsum[0] = contract<T, W>(Are, Aim, Bre, Bim, cl, cm, cr, gsrc, gph, dir, ld, vre, vim);
+    }
+    team_sum<W, 1>(nsum, S.red);
+    Team<W>::sync();
+    const double total = nsum[0];
+    const double tau2 = P.tau * P.tau;
+    const double floor2 = 1e-4 * tau2 * total;
+    // orthogonality tolerance: a few ulps of the tensor precision
+    const double tol = sizeof(T) == sizeof(double) ? static_cast<double>(len) * DBL_EPSILON
+                                                   : 8.0 * static_cast<double>(FLT_EPSILON);
+    // squared norms, then one parallel pass over every pair: if all vectors
+    // are already orthogonal (the common case) no Jacobi sweep is needed
+    vector_norms<W>(vre, vim, nv, len, ld, nrm);
+    const bool rotated = not_orthogonal<W>(vre, vim, nv, len, ld, nrm, floor2, tol, bad, (IP)nullptr);
+    // theta's copy for the projection: LDS staging when it fits
+    const bool th_lds = 2 * (size_t)m * n <= (size_t)kStage;
+    if (rotated) {
+        // keep theta for the projection (the vectors still hold it)
+        if (th_lds) {
+            ldsd* thr = to_lds(S.u);
+            ldsd* thi = thr + (size_t)m * n;
+            for (int idx = tid; idx < m * n; idx += W) {
+                const int row = idx / n, col = idx - row * n;
+                const size_t vi = dir ? (size_t)col * ld + row : (size_t)row * ld + col;
+                thr[idx] = vre[vi];
+                thi[idx] = vim[vi];
+            }
+        } else {
+            glbd* thr = to_glb(scr);
+            glbd* thi = thr + (size_t)m * n;
+            for (int idx = tid; idx < m * n; idx += W) {
+                const int row = idx / n, col = idx - row * n;
+                const size_t vi = dir ? (size_t)col * ld + row : (size_t)row * ld + col;
+                thr[idx] = vre[vi];
+                thi[idx] = vim[vi];
+            }
+        }
+        // sweep until the parallel check finds every pair orthogonal; only
+        // vectors of an overlapping pair need rotating: the others stay
+        // orthogonal to every combination of them
+        int sweeps = 0;
+        bool again = true;
+        while (again && sweeps < 40) {
+            const int nbad = flagged_list<W>(bad, nv, list, S.ired);
+            jacobi_sweep<W>(vre, vim, list, nbad, len, ld, floor2, tol);
+            ++sweeps;
+            vector_norms<W>(vre, vim, nv, len, ld, nrm);
+            for (int v = tid; v < nv; v += W) sel[v] = bad[v];
+            Team<W>::sync();
+            again = not_orthogonal<W>(vre, vim, nv, len, ld, nrm, floor2, tol, bad, sel);
+        }
+        if (again) acc.status |= MSC_SHOT_NOCONV;
+        acc.sweeps += sweeps;
+    }
+    const int capb = min(P.chi_max, S.cap[k + 1]);
+    const Kept kp = select_kept<W>(nrm, nv, tau2, capb, sel, V.isq, V.sq, S.red);
+    const int r = kp.r;
+    acc.disc += kp.dropped;
+    if (kp.dropped > 1e-12 * total && r == capb) acc.status |= MSC_SHOT_CHI_CAP;
+    const double renorm = 1.0 / sqrt(kp.kept);
+    // isometric factor: normalised vectors; centre factor: the projection
+    // of theta on them.  When no rotation was needed the vectors are
+    // theta's own columns (rows), so the projection is sigma_c on the
+    // selected column (row) and zero elsewhere, up to overlaps below the
+    // orthogonality tolerance.
+    if (dir) {
+        // A[k] (cl,2,r): U[row][c] = w_sel[c][row] / |w|
+        for (int idx = tid; idx < m * r; idx += W) {
+            const int row = idx / r, c = idx - row * r;
+            const int v = sel[c];
+            const double is = V.isq[c];
+            Are[idx] = T(vre[(size_t)v * ld + row] * is);
+            Aim[idx] = T(vim[(size_t)v * ld + row] * is);
+        }
+    } else {
+        // A[k+1] (r,2,cr): V[c][col] = w_sel[c][col] / |w|
+        for (int idx = tid; idx < r * n; idx += W) {
+            const int c = idx / n, col = idx - c * n;
+            const int v = sel[c];
+            const double is = V.isq[c];
+            Bre[idx] = T(vre[(size_t)v * ld + col] * is);
+            Bim[idx] = T(vim[(size_t)v * ld + col] * is);
+        }
+    }
+    if (!rotated) {
+        if (dir) {
+            for (int idx = tid; idx < r * n; idx += W) {
+                const int c = idx / n, col = idx - c * n;
+                const int v = sel[c];
+                Bre[idx] = T(col == v ? V.sq[c] * renorm : 0.0);
+                Bim[idx] = T(0);
+            }
+        } else {
+            for (int idx = tid; idx < m * r; idx += W) {
+                const int row = idx / r, c = idx - row * r;
+                const int v = sel[c];
+                Are[idx] = T(row == v ? V.sq[c] * renorm : 0.0);
+                Aim[idx] = T(0);
+            }
+        }
+    } else if (th_lds) {
+        ldsd* thr = to_lds(S.u);
+        project<T, W>(thr, thr + (size_t)m * n, m, n, r, dir, ld, V, renorm, dir ? Bre : Are,
+                      dir ? Bim : Aim);
+    } else {
+        glbd* thr = to_glb(scr);
+        project<T, W>(thr, thr + (size_t)m * n, m, n, r, dir, ld, V, renorm, dir ? Bre : Are,
+                      dir ? Bim : Aim);
+    }
+    if (tid == 0) S.chi[k + 1] = r;
+    acc.chi_peak = max(acc.chi_peak, r);
+    ++acc.n2q;
+    const double dl = cl, dm = cm, dr = cr, dk = r;
+    acc.flops += 32.0 * dl * dm * dr + 32.0 * dl * dl * dr + 32.0 * dk * dl * dr + 104.0 * dl * dl * dl;
+}
+
+// The fold of a product swap: with psi the unentangled qubit's state on
+// site ps (tensor P, pl x 2 x pr), M = sum_i conj(psi_i) P[:, i, :] is
+// formed in FP64 at mr/mi, then the product site receives the neighbour
+// times M: A[k] M (side 1, neighbour ol x 2 x pl) or M A[k+1] (side 0,
+// neighbour pr x 2 x ocr).  Whole workgroup; ends after the writes.
+template <typename T, typename MP, typename OP>
+__device__ void fold_product(MP mr, MP mi, OP ore, OP oim, SiteView<T> Pv, double p0r,
+                             double p0i, double p1r, double p1i, int side, int ol, int pl, int pr,
+                             int ocr) {
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < pl * pr; idx += NT) {
+        const int a = idx / pr, b = idx - a * pr;
+        const int i0 = (a * 2) * pr + b, i1 = i0 + pr;
+        const double x0r = Pv.re[i0], x0i = Pv.im[i0], x1r = Pv.re[i1], x1i = Pv.im[i1];
+        mr[idx] = p0r * x0r + p0i * x0i + p1r * x1r + p1i * x1i;
+        mi[idx] = p0r * x0i - p0i * x0r + p1r * x1i - p1i * x1r;
+    }
+    __syncthreads();
+    if (side) {
+        // product on k+1: new A[k+1] = A[k] M  (ol, 2, pr)
+        for (int idx = tid; idx < ol * 2 * pr; idx += NT) {
+            const int row = idx / pr, c = idx - row * pr;
+            double xr = 0.0, xi = 0.0;
+#pragma unroll 4
+            for (int b = 0; b < pl; ++b) {
+                const double ar = ore[row * pl + b], ai = oim[row * pl + b];
+                const double br = mr[b * pr + c], bi = mi[b * pr + c];
+                xr += ar * br - ai * bi;
+                xi += ar * bi + ai * br;
+            }
+            Pv.re[idx] = T(xr);
+            Pv.im[idx] = T(xi);
+        }
+    } else {
+        // product on k: new A[k] = M A[k+1]  (pl, 2, ocr)
+        const int w = 2 * ocr;
+        for (int idx = tid; idx < pl * w; idx += NT) {
+            const int a = idx / w, rem = idx - a * w;
+            double xr = 0.0, xi = 0.0;
+#pragma unroll 4
+            for (int b = 0; b < pr; ++b) {
+                const double ar = mr[a * pr + b], ai = mi[a * pr + b];
+                const double br = ore[b * w + rem], bi = oim[b * w + rem];
+                xr += ar * br - ai * bi;
+                xi += ar * bi + ai * br;
+            }
+            Pv.re[idx] = T(xr);
+            Pv.im[idx] = T(xi);
+        }
+    }
+}
 
 template <typename T, int SMAX>
 __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
@@ -281,17 +873,23 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
     __shared__ double s_vre[SMAX * (SMAX + 1)];
     __shared__ double s_vim[SMAX * (SMAX + 1)];
     __shared__ double s_nrm[SMAX];
+    __shared__ double s_isq[SMAX];
+    __shared__ double s_sq[SMAX];
     __shared__ int s_sel[SMAX];
     __shared__ int s_bad[SMAX];
     __shared__ int s_list[SMAX];
     __shared__ int s_ired[NW];
     __shared__ double s_red[NW * 4];
-    __shared__ double s_gph[8];
-    __shared__ int s_gsrc[4];
-    // per-site layout of the slot and bond caps, read once per launch
+    __shared__ int s_flag[1];
+    // gate tables, per-site layout of the slot and bond caps, read once
+    __shared__ double s_g1[G1_COUNT * 8];
+    __shared__ int s_g4src[G4_COUNT * 4];
+    __shared__ double s_g4ph[G4_COUNT * 8];
     __shared__ int64_t s_soff[kMaxSites];
     __shared__ int64_t s_shalf[kMaxSites];
     __shared__ int s_cap[kMaxSites + 1];
+    // op descriptors, kOpBuf at a time
+    __shared__ DevOp s_ops[kOpBuf];
     // staging: the two site tensors of an update (tensor type), then the
     // copy of theta kept for the projection (FP64)
     __shared__ double s_u[kStage];
@@ -301,8 +899,10 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
     T* slot_base = static_cast<T*>(P.arena) + (size_t)blockIdx.x * P.slot_stride;
     double* scr = P.scratch + (size_t)blockIdx.x * P.scratch_stride;
     // per-vector arrays of SVDs too large for LDS, at the end of the slot's scratch
-    double* g_nrm = scr + P.scratch_stride - 4 * MAXV;
-    int* g_sel = reinterpret_cast<int*>(g_nrm + MAXV);
+    double* g_nrm = scr + P.scratch_stride - 6 * MAXV;
+    double* g_isq = g_nrm + MAXV;
+    double* g_sq = g_isq + MAXV;
+    int* g_sel = reinterpret_cast<int*>(g_sq + MAXV);
     int* g_bad = g_sel + MAXV;
     int* g_list = g_bad + MAXV;
 
@@ -311,16 +911,46 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
         s_shalf[k] = P.site_half[k];
     }
     for (int k = tid; k <= N; k += NT) s_cap[k] = P.cap[k];
+    for (int i = tid; i < G1_COUNT * 8; i += NT) s_g1[i] = P.g1[i];
+    if (tid < G4_COUNT * 4) {
+        // the nonzero of each row of each monomial 4x4 gate, found once
+        const double* g = P.g4 + (tid >> 2) * 32 + (tid & 3) * 8;
+        int src = 0;
+        for (int j = 1; j < 4; ++j)
+            if (fabs(g[2 * j]) + fabs(g[2 * j + 1]) > fabs(g[2 * src]) + fabs(g[2 * src + 1]))
+                src = j;
+        s_g4src[tid] = src;
+        s_g4ph[2 * tid] = g[2 * src];
+        s_g4ph[2 * tid + 1] = g[2 * src + 1];
+    }
     __syncthreads();
+
+    Smem S;
+    S.chi = s_chi;
+    S.vre = s_vre;
+    S.vim = s_vim;
+    S.nrm = s_nrm;
+    S.isq = s_isq;
+    S.sq = s_sq;
+    S.sel = s_sel;
+    S.bad = s_bad;
+    S.list = s_list;
+    S.ired = s_ired;
+    S.red = s_red;
+    S.cap = s_cap;
+    S.u = s_u;
+    S.g4src = s_g4src;
+    S.g4ph = s_g4ph;
 
     auto site = [&](int k) {
         SiteView<T> v;
-        v.re = slot_base + s_soff[k];
+        v.re = to_glb(slot_base + s_soff[k]);
         v.im = v.re + s_shalf[k];
         return v;
     };
 
-    for (int64_t j = blockIdx.x; j < P.n_shots; j += gridDim.x) {
+    const int64_t n_run = P.n_dev ? min(*P.n_dev, P.n_shots) : P.n_shots;
+    for (int64_t j = blockIdx.x; j < n_run; j += gridDim.x) {
         const int64_t it = P.perm ? P.perm[j] : j;
         const int64_t shot = P.shot_idx ? P.shot_idx[it] : it;
         if (shot < 0 || shot >= P.n_csr) {
@@ -331,13 +961,13 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
             }
             continue;
         }
-        double p_acc = 1.0, disc = 0.0, infid = 0.0;
-        int chi_peak = 1, status = 0, rej_at = -1;
-        int64_t n2q = 0;
-        double flops = 0.0;
-        int64_t sweeps_total = 0;
+        ShotAcc acc;
+        double p_acc = 1.0, infid = 0.0;
+        int rej_at = -1;
         int64_t fcur = P.shot_off[shot];
         const int64_t fend = P.shot_off[shot + 1];
+        // channel of the shot's next fault, loaded ahead of its op
+        int next_ch = fcur < fend ? P.chan[fcur] : -1;
         int fcode = 0;     // code of the last channel read (three-qubit faults)
         bool alive = true;
         int start = 0;
@@ -346,15 +976,16 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
             // fork from the last checkpoint of the noiseless run before the
             // shot's first fault (the ops before it are fault-free here)
             const int navail = *P.ck_avail;
-            int j = fcur < fend ? P.chan[fcur] / P.ck_k : P.n_ck - 1;
-            jck = j < navail ? j : navail - 1;
+            const int jj = fcur < fend ? next_ch / P.ck_k : P.n_ck - 1;
+            jck = jj < navail ? jj : navail - 1;
         }
         if (jck >= 0) {
             const CkHdr& h = P.ck_hdr[jck];
             for (int k = tid; k <= N; k += NT) s_chi[k] = h.chi[k];
             for (int k = tid; k < N; k += NT) s_laste[k] = h.laste[k];
             __syncthreads();
-            const T* src = static_cast<const T*>(P.ck_data) + P.ck_off[jck];
+            const __attribute__((address_space(1))) T* src =
+                to_glb(static_cast<const T*>(P.ck_data)) + P.ck_off[jck];
             int64_t o = 0;
             for (int k = 0; k < N; ++k) {
                 const int ne = s_chi[k] * 2 * s_chi[k + 1];
@@ -366,9 +997,9 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                 o += 2 * ne;
             }
             p_acc = h.p_acc;
-            disc = h.disc;
-            chi_peak = h.chi_peak;
-            status = h.status;
+            acc.disc = h.disc;
+            acc.chi_peak = h.chi_peak;
+            acc.status = h.status;
             start = P.ck_op[jck];
         } else {
             // ---- initial product state |0...0>
@@ -383,18 +1014,25 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
             }
         }
         __syncthreads();
-        int next_ck = 0;           // record mode: next checkpoint to take
-        int64_t ck_pos = 0;        // record mode: elements written so far
+        int next_ck = 0;              // record mode: next checkpoint to take
+        int64_t ck_pos = 0;           // record mode: elements written so far
         bool ck_full = false;
+        int ops_lo = 0, ops_hi = 0;   // op range held in s_ops
 
-        DevOp next_op = start < P.n_ops ? P.ops[start] : DevOp{};
         for (int oi = start; oi < P.n_ops && alive; ++oi) {
+            if (oi >= ops_hi) {
+                __syncthreads();
+                ops_lo = oi;
+                ops_hi = min(P.n_ops, oi + kOpBuf);
+                for (int i = tid; i < ops_hi - ops_lo; i += NT) s_ops[i] = P.ops[ops_lo + i];
+                __syncthreads();
+            }
             if (P.ck_mode == 1 && !ck_full && next_ck < P.n_ck && P.ck_op[next_ck] == oi) {
                 // ---- record: the state before op oi, densely, site by site
                 int64_t sz = 0;
                 for (int k = 0; k < N; ++k) sz += 4 * (int64_t)s_chi[k] * s_chi[k + 1];
                 if (ck_pos + sz <= P.ck_cap) {
-                    T* dst = static_cast<T*>(P.ck_data) + ck_pos;
+                    __attribute__((address_space(1))) T* dst = to_glb(static_cast<T*>(P.ck_data)) + ck_pos;
                     int64_t o = 0;
                     for (int k = 0; k < N; ++k) {
                         const int ne = s_chi[k] * 2 * s_chi[k + 1];
@@ -410,9 +1048,9 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                     for (int k = tid; k < N; k += NT) h.laste[k] = s_laste[k];
                     if (tid == 0) {
                         h.p_acc = p_acc;
-                        h.disc = disc;
-                        h.chi_peak = chi_peak;
-                        h.status = status;
+                        h.disc = acc.disc;
+                        h.chi_peak = acc.chi_peak;
+                        h.status = acc.status;
                         P.ck_off[next_ck] = ck_pos;
                     }
                     ck_pos += sz;
@@ -423,102 +1061,28 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                     ck_full = true;
                 }
             }
-            const DevOp op = next_op;
-            if (oi + 1 < P.n_ops) next_op = P.ops[oi + 1];   // in flight during this op
+            const DevOp op = s_ops[oi - ops_lo];
             bool twosite = op.kind == OP_G2;
             int gate_id = op.aux;
             if (op.kind == OP_MOVE) {
-                // ---- move the centre by one site with a one-site split; when
-                // the site's vectors are already orthogonal (they are after a
-                // split that left the centre there) this is a selection and a
-                // rescaling, else fall back to the two-site identity update
+                // ---- move the centre by one site: one wavefront does the
+                // usual case (orthogonal vectors, small sides)
                 const int k = op.a, dir = op.b;
                 const int cl = s_chi[k], cm = s_chi[k + 1], cr = s_chi[k + 2];
+                const int nv = cm, len = dir ? 2 * cl : 2 * cr;
                 SiteView<T> A = site(k), B = site(k + 1);
-                const int nv = cm, len = dir ? 2 * cl : 2 * cr, ld = len + 1;
                 bool fast = false;
                 if (nv <= SMAX && len <= SMAX) {
-                    for (int idx = tid; idx < nv * len; idx += NT) {
-                        const int v = idx / len, e = idx - v * len;
-                        const int at = dir ? e * cm + v : v * len + e;
-                        const SiteView<T>& S = dir ? A : B;
-                        s_vre[v * ld + e] = static_cast<double>(S.re[at]);
-                        s_vim[v * ld + e] = static_cast<double>(S.im[at]);
-                    }
-                    __syncthreads();
-                    vector_norms(s_vre, s_vim, nv, len, ld, s_nrm);
-                    double tsum[1] = {0.0};
-                    for (int v = tid; v < nv; v += NT) tsum[0] += s_nrm[v];
-                    block_sum<1>(tsum, s_red);
-                    const double tau2 = P.tau * P.tau;
-                    const double tol = sizeof(T) == sizeof(double)
-                                           ? static_cast<double>(len) * DBL_EPSILON
-                                           : 8.0 * static_cast<double>(FLT_EPSILON);
-                    if (!not_orthogonal(s_vre, s_vim, nv, len, ld, s_nrm, 1e-4 * tau2 * tsum[0], tol,
-                                        s_bad, nullptr)) {
-                        const int capb = min(P.chi_max, s_cap[k + 1]);
-                        const Kept kp = select_kept(s_nrm, nv, tau2, capb, s_sel, s_red);
-                        const int r = kp.r;
-                        disc += kp.dropped;
-                        if (kp.dropped > 1e-12 * tsum[0] && r == capb) status |= MSC_SHOT_CHI_CAP;
-                        const double renorm = 1.0 / sqrt(kp.kept);
-                        // staging for the rescaled neighbour: LDS (free once the
-                        // normalised vectors are written) when it fits
-                        const int tmp_n = dir ? r * 2 * cr : 2 * cl * r;
-                        const bool tlds = tmp_n <= SMAX * (SMAX + 1);
-                        double* tr_ = tlds ? s_vre : scr;
-                        double* ti_ = tlds ? s_vim : scr + (size_t)2 * cl * cm + (size_t)2 * cm * cr;
-                        if (dir) {
-                            // A[k] <- normalised columns; A[k+1] <- its selected rows
-                            for (int idx = tid; idx < 2 * cl * r; idx += NT) {
-                                const int e = idx / r, c = idx - e * r;
-                                const int v = s_sel[c];
-                                const double is = 1.0 / sqrt(s_nrm[v]);
-                                A.re[idx] = T(s_vre[v * ld + e] * is);
-                                A.im[idx] = T(s_vim[v * ld + e] * is);
-                            }
-                            __syncthreads();
-                            const int w = 2 * cr;
-                            for (int idx = tid; idx < r * w; idx += NT) {
-                                const int c = idx / w, x = idx - c * w;
-                                const int v = s_sel[c];
-                                const double sc = sqrt(s_nrm[v]) * renorm;
-                                tr_[idx] = static_cast<double>(B.re[v * w + x]) * sc;
-                                ti_[idx] = static_cast<double>(B.im[v * w + x]) * sc;
-                            }
-                            __syncthreads();
-                            for (int idx = tid; idx < r * w; idx += NT) {
-                                B.re[idx] = T(tr_[idx]);
-                                B.im[idx] = T(ti_[idx]);
-                            }
-                        } else {
-                            // A[k+1] <- normalised rows; A[k] <- its selected columns
-                            const int w = 2 * cr;
-                            for (int idx = tid; idx < r * w; idx += NT) {
-                                const int c = idx / w, e = idx - c * w;
-                                const int v = s_sel[c];
-                                const double is = 1.0 / sqrt(s_nrm[v]);
-                                B.re[idx] = T(s_vre[v * ld + e] * is);
-                                B.im[idx] = T(s_vim[v * ld + e] * is);
-                            }
-                            __syncthreads();
-                            for (int idx = tid; idx < 2 * cl * r; idx += NT) {
-                                const int row = idx / r, c = idx - row * r;
-                                const int v = s_sel[c];
-                                const double sc = sqrt(s_nrm[v]) * renorm;
-                                tr_[idx] = static_cast<double>(A.re[row * cm + v]) * sc;
-                                ti_[idx] = static_cast<double>(A.im[row * cm + v]) * sc;
-                            }
-                            __syncthreads();
-                            for (int idx = tid; idx < 2 * cl * r; idx += NT) {
-                                A.re[idx] = T(tr_[idx]);
-                                A.im[idx] = T(ti_[idx]);
-                            }
+                    if (nv <= kWaveSide && len <= kWaveSide) {
+                        if (tid < 64) {
+                            const bool f = move_fast<T, SMAX, 64>(P, S, A, B, k, dir, scr, acc);
+                            if (tid == 0) s_flag[0] = f;
                         }
                         __syncthreads();
-                        if (tid == 0) s_chi[k + 1] = r;
+                        fast = s_flag[0] != 0;
+                    } else {
+                        fast = move_fast<T, SMAX, NT>(P, S, A, B, k, dir, scr, acc);
                         __syncthreads();
-                        fast = true;
                     }
                 }
                 if (!fast) {
@@ -539,9 +1103,10 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                     if (x2 | z2) g0 = (x2 && z2) ? G_Y : (x2 ? G_X : G_Z);
                 } else {
                     int code = 0;
-                    if (fcur < fend && P.chan[fcur] == op.aux) {
+                    if (fcur < fend && next_ch == op.aux) {
                         code = P.pauli[fcur];
                         ++fcur;
+                        next_ch = fcur < fend ? P.chan[fcur] : -1;
                     }
                     fcode = code;
                     const int x0 = code & 1, z0 = (code >> 1) & 1;
@@ -553,7 +1118,7 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                     const int gid = h == 0 ? g0 : g1;
                     if (gid < 0) continue;
                     const int k = h == 0 ? op.a : op.b;
-                    const double* m = P.g1 + gid * 8;
+                    const double* m = s_g1 + gid * 8;
                     const double m0 = m[0], m1 = m[1], m2 = m[2], m3 = m[3];
                     const double m4 = m[4], m5 = m[5], m6 = m[6], m7 = m[7];
                     SiteView<T> v = site(k);
@@ -588,7 +1153,7 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                     r4[2] += x0r * x1r + x0i * x1i;     // rho01 = x0 conj(x1)
                     r4[3] += x0i * x1r - x0r * x1i;
                 }
-                block_sum<4>(r4, s_red);
+                team_sum<NT, 4>(r4, s_red);
                 const double tr = r4[0] + r4[1];
                 double p0r, p0i, p1r, p1i;               // psi, unit norm
                 if (r4[1] > r4[0]) {
@@ -604,61 +1169,34 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                     p1r = r4[2] * d;                     // rho10 = conj(rho01)
                     p1i = -r4[3] * d;
                 }
-                // M = sum_i conj(psi_i) P[:, i, :]   (pl x pr, FP64)
-                const bool mlds = pl * pr <= SMAX * (SMAX + 1);
-                double* mr = mlds ? s_vre : scr;
-                double* mi = mlds ? s_vim : scr + (size_t)pl * pr;
-                for (int idx = tid; idx < pl * pr; idx += NT) {
-                    const int a = idx / pr, b = idx - a * pr;
-                    const int i0 = (a * 2) * pr + b, i1 = i0 + pr;
-                    const double x0r = Pv.re[i0], x0i = Pv.im[i0], x1r = Pv.re[i1], x1i = Pv.im[i1];
-                    mr[idx] = p0r * x0r + p0i * x0i + p1r * x1r + p1i * x1i;
-                    mi[idx] = p0r * x0i - p0i * x0r + p1r * x1i - p1i * x1r;
-                }
-                __syncthreads();
-                int newb;
-                if (side) {
-                    // product on k+1: new A[k+1] = A[k] M  (ol, 2, pr)
-                    const int ol = s_chi[k];
-                    for (int idx = tid; idx < ol * 2 * pr; idx += NT) {
-                        const int row = idx / pr, c = idx - row * pr;
-                        double xr = 0.0, xi = 0.0;
-                        for (int b = 0; b < pl; ++b) {
-                            const double ar = Ov.re[row * pl + b], ai = Ov.im[row * pl + b];
-                            const double br = mr[b * pr + c], bi = mi[b * pr + c];
-                            xr += ar * br - ai * bi;
-                            xi += ar * bi + ai * br;
-                        }
-                        Pv.re[idx] = T(xr);
-                        Pv.im[idx] = T(xi);
+                // M = sum_i conj(psi_i) P[:, i, :] (pl x pr, FP64), then the
+                // neighbour times M; in LDS (neighbour staged) when it fits
+                const int ol = s_chi[k], ocr = s_chi[k + 2];
+                const int on = side ? ol * 2 * pl : pr * 2 * ocr;   // neighbour elements
+                const int newb = side ? ol : ocr;
+                if (pl * pr <= SMAX * (SMAX + 1) &&
+                    (size_t)2 * on * sizeof(T) <= kStage * sizeof(double)) {
+                    typedef __attribute__((address_space(3))) T lT;
+                    lT* st = to_lds(reinterpret_cast<T*>(s_u));
+                    for (int idx = tid; idx < on; idx += NT) {
+                        st[idx] = Ov.re[idx];
+                        st[on + idx] = Ov.im[idx];
                     }
-                    newb = ol;
+                    fold_product<T>(to_lds(s_vre), to_lds(s_vim), st, st + on, Pv, p0r, p0i, p1r,
+                                    p1i, side, ol, pl, pr, ocr);
                 } else {
-                    // product on k: new A[k] = M A[k+1]  (pl, 2, ocr)
-                    const int ocr = s_chi[k + 2];
-                    const int w = 2 * ocr;
-                    for (int idx = tid; idx < pl * w; idx += NT) {
-                        const int a = idx / w, rem = idx - a * w;
-                        double xr = 0.0, xi = 0.0;
-                        for (int b = 0; b < pr; ++b) {
-                            const double ar = mr[a * pr + b], ai = mi[a * pr + b];
-                            const double br = Ov.re[b * w + rem], bi = Ov.im[b * w + rem];
-                            xr += ar * br - ai * bi;
-                            xi += ar * bi + ai * br;
-                        }
-                        Pv.re[idx] = T(xr);
-                        Pv.im[idx] = T(xi);
-                    }
-                    newb = ocr;
+                    glbd* mr = to_glb(scr);
+                    fold_product<T>(mr, mr + (size_t)pl * pr, Ov.re, Ov.im, Pv, p0r, p0i, p1r,
+                                    p1i, side, ol, pl, pr, ocr);
                 }
                 __syncthreads();
                 // the unentangled qubit on the other site: psi (x) identity
                 for (int idx = tid; idx < newb * 2 * newb; idx += NT) {
                     const int a = idx / (2 * newb), rem = idx - a * 2 * newb;
                     const int i = rem / newb, a2 = rem - i * newb;
-                    const bool on = a == a2;
-                    Ov.re[idx] = T(on ? (i ? p1r : p0r) : 0.0);
-                    Ov.im[idx] = T(on ? (i ? p1i : p0i) : 0.0);
+                    const bool diag = a == a2;
+                    Ov.re[idx] = T(diag ? (i ? p1r : p0r) : 0.0);
+                    Ov.im[idx] = T(diag ? (i ? p1i : p0i) : 0.0);
                 }
                 if (tid == 0) s_chi[k + 1] = newb;
                 __syncthreads();
@@ -674,7 +1212,7 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                     pp[0] += x0r * x0r + x0i * x0i;
                     pp[1] += x1r * x1r + x1i * x1i;
                 }
-                block_sum<2>(pp, s_red);
+                team_sum<NT, 2>(pp, s_red);
                 const double tot = pp[0] + pp[1];
                 int e;
                 if (P.calibrate) e = pp[1] > pp[0] ? 1 : 0;
@@ -687,7 +1225,7 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                 }
                 if (!(pe >= P.tau_rej)) {
                     alive = false;
-                    status |= MSC_SHOT_REJECTED;
+                    acc.status |= MSC_SHOT_REJECTED;
                     rej_at = op.aux;
                     p_acc = 0.0;
                     break;
@@ -719,7 +1257,7 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                     r[2] += x0r * x1r + x0i * x1i;
                     r[3] += x0i * x1r - x0r * x1i;
                 }
-                block_sum<4>(r, s_red);
+                team_sum<NT, 4>(r, s_red);
                 const double tr = r[0] + r[1];
                 // f = |t0|^2 rho00 + |t1|^2 rho11 + 2 Re(conj(t0) t1 rho01)
                 const double ctr = P.t0r * P.t1r + P.t0i * P.t1i;   // conj(t0) t1
@@ -732,234 +1270,26 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
             if (twosite) {
                 // ---- two-site update on sites k, k+1
                 const int k = op.a, dir = op.b;
-                const int cl = s_chi[k], cm = s_chi[k + 1], cr = s_chi[k + 2];
-                const int m = 2 * cl, n = 2 * cr;
+                const int m = 2 * s_chi[k], n = 2 * s_chi[k + 2];
                 SiteView<T> A = site(k), B = site(k + 1);
-                // theta's copy for the projection: LDS staging when it fits
-                double* thr = 2 * (size_t)m * n <= (size_t)kStage ? s_u : scr;
-                double* thi = thr + (size_t)m * n;
-                const int nv = dir ? n : m, len = dir ? m : n;
-                const int ld = len + 1;
-                const bool lds = nv <= SMAX && len <= SMAX;
-                double* vre = lds ? s_vre : scr + 2 * (size_t)m * n;
-                double* vim = lds ? s_vim : vre + (size_t)nv * ld;
-                double* nrm = lds ? s_nrm : g_nrm;
-                int* sel = lds ? s_sel : g_sel;
-                int* bad = lds ? s_bad : g_bad;
-                int* list = lds ? s_list : g_list;
-                if (tid < 4) {
-                    // the 4x4 gates of the op stream are monomial: one
-                    // nonzero per row, found here once per update
-                    const double* g = P.g4 + gate_id * 32 + tid * 8;
-                    int src = 0;
-                    for (int j = 1; j < 4; ++j)
-                        if (fabs(g[2 * j]) + fabs(g[2 * j + 1]) > fabs(g[2 * src]) + fabs(g[2 * src + 1]))
-                            src = j;
-                    s_gsrc[tid] = src;
-                    s_gph[2 * tid] = g[2 * src];
-                    s_gph[2 * tid + 1] = g[2 * src + 1];
-                }
-                // both site tensors into LDS with one coalesced pass when they
-                // fit: the contraction then reads each element from LDS
-                const int na = cl * 2 * cm, nb = cm * 2 * cr;
-                const T* Ar = A.re;
-                const T* Ai = A.im;
-                const T* Br = B.re;
-                const T* Bi = B.im;
-                if ((size_t)2 * (na + nb) * sizeof(T) <= kStage * sizeof(double)) {
-                    T* st = reinterpret_cast<T*>(s_u);
-                    for (int i = tid; i < na; i += NT) {
-                        st[i] = A.re[i];
-                        st[na + i] = A.im[i];
-                    }
-                    for (int i = tid; i < nb; i += NT) {
-                        st[2 * na + i] = B.re[i];
-                        st[2 * na + nb + i] = B.im[i];
-                    }
-                    Ar = st;
-                    Ai = st + na;
-                    Br = st + 2 * na;
-                    Bi = Br + nb;
-                }
-                __syncthreads();
-                double nsum[1] = {0.0};
-                for (int idx = tid; idx < cl * cr; idx += NT) {
-                    const int a = idx / cr, b = idx - a * cr;
-                    T sr[4] = {T(0), T(0), T(0), T(0)}, si[4] = {T(0), T(0), T(0), T(0)};
-                    const T* a0r = Ar + (a * 2) * cm;
-                    const T* a0i = Ai + (a * 2) * cm;
-                    for (int c = 0; c < cm; ++c) {
-                        const T x0r = a0r[c], x0i = a0i[c], x1r = a0r[cm + c], x1i = a0i[cm + c];
-                        const int b0 = (c * 2) * cr + b, b1 = b0 + cr;
-                        const T y0r = Br[b0], y0i = Bi[b0], y1r = Br[b1], y1i = Bi[b1];
-                        // S[i'j'] += A[a,i',c] B[c,j',b]
-                        sr[0] += x0r * y0r - x0i * y0i; si[0] += x0r * y0i + x0i * y0r;
-                        sr[1] += x0r * y1r - x0i * y1i; si[1] += x0r * y1i + x0i * y1r;
-                        sr[2] += x1r * y0r - x1i * y0i; si[2] += x1r * y0i + x1i * y0r;
-                        sr[3] += x1r * y1r - x1i * y1i; si[3] += x1r * y1i + x1i * y1r;
-                    }
-                    // monomial gate: output o = phase[o] * S[src[o]]
-                    double tr_[4], ti_[4];
-#pragma unroll
-                    for (int o = 0; o < 4; ++o) {
-                        const int j = s_gsrc[o];
-                        const double xr = static_cast<double>(sr[j]), xi = static_cast<double>(si[j]);
-                        const double pr = s_gph[2 * o], pim = s_gph[2 * o + 1];
-                        tr_[o] = pr * xr - pim * xi;
-                        ti_[o] = pr * xi + pim * xr;
-                    }
-#pragma unroll
-                    for (int o = 0; o < 4; ++o) {
-                        const int i = o >> 1, j = o & 1;
-                        const int row = a * 2 + i, col = j * cr + b;
-                        const size_t vi = dir ? (size_t)col * ld + row : (size_t)row * ld + col;
-                        vre[vi] = tr_[o];
-                        vim[vi] = ti_[o];
-                        nsum[0] += tr_[o] * tr_[o] + ti_[o] * ti_[o];
-                    }
-                }
-                block_sum<1>(nsum, s_red);
-                const double total = nsum[0];
-                const double tau2 = P.tau * P.tau;
-                const double floor2 = 1e-4 * tau2 * total;
-                // orthogonality tolerance: a few ulps of the tensor precision
-                const double tol = sizeof(T) == sizeof(double)
-                                       ? static_cast<double>(len) * DBL_EPSILON
-                                       : 8.0 * static_cast<double>(FLT_EPSILON);
-                // squared norms, then one parallel pass over every pair: if
-                // all vectors are already orthogonal (the common case) no
-                // Jacobi sweep is needed at all
-                vector_norms(vre, vim, nv, len, ld, nrm);
-                const bool rotated =
-                    not_orthogonal(vre, vim, nv, len, ld, nrm, floor2, tol, bad, nullptr);
-                if (rotated) {
-                    // keep theta for the projection (the vectors still hold it)
-                    for (int idx = tid; idx < m * n; idx += NT) {
-                        const int row = idx / n, col = idx - row * n;
-                        const size_t vi = dir ? (size_t)col * ld + row : (size_t)row * ld + col;
-                        thr[idx] = vre[vi];
-                        thi[idx] = vim[vi];
-                    }
-                    // sweep until the parallel check finds every pair orthogonal
-                    // only vectors of an overlapping pair need rotating: the
-                    // others stay orthogonal to every combination of them
-                    int sweeps = 0;
-                    bool again = true;
-                    while (again && sweeps < 40) {
-                        const int nb = flagged_list(bad, nv, list, s_ired);
-                        jacobi_sweep(vre, vim, list, nb, len, ld, floor2, tol);
-                        ++sweeps;
-                        vector_norms(vre, vim, nv, len, ld, nrm);
-                        for (int v = tid; v < nv; v += NT) sel[v] = bad[v];
-                        __syncthreads();
-                        again = not_orthogonal(vre, vim, nv, len, ld, nrm, floor2, tol, bad, sel);
-                    }
-                    if (again) status |= MSC_SHOT_NOCONV;
-                    sweeps_total += sweeps;
-                }
-                const int capb = min(P.chi_max, s_cap[k + 1]);
-                const Kept kp = select_kept(nrm, nv, tau2, capb, sel, s_red);
-                const int r = kp.r;
-                const double kept = kp.kept;
-                disc += kp.dropped;
-                if (kp.dropped > 1e-12 * total && r == capb) status |= MSC_SHOT_CHI_CAP;
-                const double renorm = 1.0 / sqrt(kept);
-                // isometric factor: normalised vectors; centre factor: the
-                // projection of theta on them.  When no rotation was needed the
-                // vectors are theta's own columns (rows), so the projection is
-                // sigma_c on the selected column (row) and zero elsewhere, up
-                // to overlaps below the orthogonality tolerance.
-                if (!rotated) {
-                    if (dir) {
-                        for (int idx = tid; idx < m * r; idx += NT) {
-                            const int row = idx / r, c = idx - row * r;
-                            const int v = sel[c];
-                            const double is = 1.0 / sqrt(nrm[v]);
-                            A.re[idx] = T(vre[(size_t)v * ld + row] * is);
-                            A.im[idx] = T(vim[(size_t)v * ld + row] * is);
-                        }
-                        for (int idx = tid; idx < r * n; idx += NT) {
-                            const int c = idx / n, col = idx - c * n;
-                            const int v = sel[c];
-                            B.re[idx] = T(col == v ? sqrt(nrm[v]) * renorm : 0.0);
-                            B.im[idx] = T(0);
-                        }
+                if (m <= SMAX && n <= SMAX) {
+                    const Vecs<ldsd*, ldsi*> V{to_lds(s_vre), to_lds(s_vim), to_lds(s_nrm),
+                                               to_lds(s_isq), to_lds(s_sq), to_lds(s_sel),
+                                               to_lds(s_bad), to_lds(s_list)};
+                    if (m <= kWaveSide && n <= kWaveSide) {
+                        if (tid < 64)
+                            twosite_update<T, SMAX, 64>(P, S, A, B, k, dir, gate_id, scr, V, acc);
                     } else {
-                        for (int idx = tid; idx < r * n; idx += NT) {
-                            const int c = idx / n, col = idx - c * n;
-                            const int v = sel[c];
-                            const double is = 1.0 / sqrt(nrm[v]);
-                            B.re[idx] = T(vre[(size_t)v * ld + col] * is);
-                            B.im[idx] = T(vim[(size_t)v * ld + col] * is);
-                        }
-                        for (int idx = tid; idx < m * r; idx += NT) {
-                            const int row = idx / r, c = idx - row * r;
-                            const int v = sel[c];
-                            A.re[idx] = T(row == v ? sqrt(nrm[v]) * renorm : 0.0);
-                            A.im[idx] = T(0);
-                        }
-                    }
-                } else if (dir) {
-                    // A[k] (cl,2,r): U[row][c] = w_sel[c][row] / |w|
-                    for (int idx = tid; idx < m * r; idx += NT) {
-                        const int row = idx / r, c = idx - row * r;
-                        const int v = sel[c];
-                        const double is = 1.0 / sqrt(nrm[v]);
-                        A.re[idx] = T(vre[(size_t)v * ld + row] * is);
-                        A.im[idx] = T(vim[(size_t)v * ld + row] * is);
-                    }
-                    // A[k+1] (r,2,cr): R[c][col] = sum_row conj(U[row][c]) theta[row][col]
-                    for (int idx = tid; idx < r * n; idx += NT) {
-                        const int c = idx / n, col = idx - c * n;
-                        const int v = sel[c];
-                        const double is = renorm / sqrt(nrm[v]);
-                        const double* ur = vre + (size_t)v * ld;
-                        const double* ui = vim + (size_t)v * ld;
-                        double xr = 0.0, xi = 0.0;
-                        for (int row = 0; row < m; ++row) {
-                            const double a0 = ur[row], a1 = ui[row];
-                            const double t0 = thr[(size_t)row * n + col], t1 = thi[(size_t)row * n + col];
-                            xr += a0 * t0 + a1 * t1;
-                            xi += a0 * t1 - a1 * t0;
-                        }
-                        B.re[idx] = T(xr * is);
-                        B.im[idx] = T(xi * is);
+                        twosite_update<T, SMAX, NT>(P, S, A, B, k, dir, gate_id, scr, V, acc);
                     }
                 } else {
-                    // A[k+1] (r,2,cr): V[c][col] = w_sel[c][col] / |w|
-                    for (int idx = tid; idx < r * n; idx += NT) {
-                        const int c = idx / n, col = idx - c * n;
-                        const int v = sel[c];
-                        const double is = 1.0 / sqrt(nrm[v]);
-                        B.re[idx] = T(vre[(size_t)v * ld + col] * is);
-                        B.im[idx] = T(vim[(size_t)v * ld + col] * is);
-                    }
-                    // A[k] (cl,2,r): L[row][c] = sum_col theta[row][col] conj(V[c][col])
-                    for (int idx = tid; idx < m * r; idx += NT) {
-                        const int row = idx / r, c = idx - row * r;
-                        const int v = sel[c];
-                        const double is = renorm / sqrt(nrm[v]);
-                        const double* wr = vre + (size_t)v * ld;
-                        const double* wi = vim + (size_t)v * ld;
-                        double xr = 0.0, xi = 0.0;
-                        for (int col = 0; col < n; ++col) {
-                            const double t0 = thr[(size_t)row * n + col], t1 = thi[(size_t)row * n + col];
-                            const double b0 = wr[col], b1 = wi[col];
-                            xr += t0 * b0 + t1 * b1;
-                            xi += t1 * b0 - t0 * b1;
-                        }
-                        A.re[idx] = T(xr * is);
-                        A.im[idx] = T(xi * is);
-                    }
-                }
-                __syncthreads();
-                if (tid == 0) s_chi[k + 1] = r;
-                chi_peak = max(chi_peak, r);
-                ++n2q;
-                {
-                    const double dl = cl, dm = cm, dr = cr, dk = r;
-                    flops += 32.0 * dl * dm * dr + 32.0 * dl * dl * dr + 32.0 * dk * dl * dr +
-                             104.0 * dl * dl * dl;
+                    // vectors in the slot's scratch after theta's copy
+                    const int nv = dir ? n : m, ld = (dir ? m : n) + 1;
+                    glbd* vre = to_glb(scr + 2 * (size_t)m * n);
+                    const Vecs<glbd*, glbi*> V{vre, vre + (size_t)nv * ld, to_glb(g_nrm),
+                                               to_glb(g_isq), to_glb(g_sq), to_glb(g_sel),
+                                               to_glb(g_bad), to_glb(g_list)};
+                    twosite_update<T, SMAX, NT>(P, S, A, B, k, dir, gate_id, scr, V, acc);
                 }
                 __syncthreads();
             }
@@ -968,14 +1298,14 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
             msc_shot_result res;
             res.p_acc = p_acc;
             res.infid = alive ? infid : 0.0;
-            res.disc_weight = disc;
-            res.chi_peak = chi_peak;
-            res.status = status | (alive ? MSC_SHOT_DONE : 0);
+            res.disc_weight = acc.disc;
+            res.chi_peak = acc.chi_peak;
+            res.status = acc.status | (alive ? MSC_SHOT_DONE : 0);
             res.rejected_at = rej_at;
             res.fail = (alive && p_acc > 0.0 && infid > P.tau_fail) ? 1 : 0;
-            res.n2q = n2q;
-            res.flops = flops;
-            res.sweeps = sweeps_total;
+            res.n2q = acc.n2q;
+            res.flops = acc.flops;
+            res.sweeps = acc.sweeps;
             P.out[it] = res;
         }
         __syncthreads();
@@ -989,17 +1319,22 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
 // online screening stops the others early.  With checkpoints a shot starts
 // at its first fault, so the key is the position of that channel in the
 // circuit (fault-free shots, which only read out, last).
-__global__ __launch_bounds__(1024) void order_kernel(int64_t n, const int64_t* shot_off,
-                                                     const int64_t* shot_idx, int64_t n_csr,
-                                                     const int32_t* chan, int32_t n_channels,
-                                                     int64_t* perm) {
+// One 256-thread workgroup (small enough to find room beside resident shot
+// kernels of other streams).
+constexpr int OT = 256;
+__global__ __launch_bounds__(OT) void order_kernel(int64_t n, const int64_t* n_dev,
+                                                   const int64_t* shot_off,
+                                                   const int64_t* shot_idx, int64_t n_csr,
+                                                   const int32_t* chan, int32_t n_channels,
+                                                   int64_t* perm) {
     __shared__ int64_t s_base;
-    __shared__ int s_wcnt[16];
+    if (n_dev && *n_dev < n) n = *n_dev;
+    __shared__ int s_wcnt[OT / 64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     if (tid == 0) s_base = 0;
     __syncthreads();
     for (int key = 0; key < 16; ++key) {
-        for (int64_t base = 0; base < n; base += 1024) {
+        for (int64_t base = 0; base < n; base += OT) {
             const int64_t j = base + tid;
             bool hit = false;
             if (j < n) {
@@ -1026,7 +1361,7 @@ __global__ __launch_bounds__(1024) void order_kernel(int64_t n, const int64_t* s
             __syncthreads();
             if (tid == 0) {
                 int64_t t = 0;
-                for (int q = 0; q < 16; ++q) t += s_wcnt[q];
+                for (int q = 0; q < OT / 64; ++q) t += s_wcnt[q];
                 s_base += t;
             }
             __syncthreads();
@@ -1052,11 +1387,12 @@ int mps_blocks_per_cu(int precision, bool small) {
     return b < 1 ? 1 : b;
 }
 
-hipError_t launch_order(int64_t n, const int64_t* shot_off, const int64_t* shot_idx, int64_t n_csr,
-                        const int32_t* chan, int32_t n_channels, int64_t* perm, hipStream_t s) {
+hipError_t launch_order(int64_t n, const int64_t* n_dev, const int64_t* shot_off,
+                        const int64_t* shot_idx, int64_t n_csr, const int32_t* chan,
+                        int32_t n_channels, int64_t* perm, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, s, n, shot_off, shot_idx, n_csr, chan,
-                       n_channels, perm);
+    hipLaunchKernelGGL(order_kernel, dim3(1), dim3(OT), 0, s, n, n_dev, shot_off, shot_idx, n_csr,
+                       chan, n_channels, perm);
     return hipGetLastError();
 }
 

@@ -19,6 +19,10 @@
 namespace msc {
 namespace {
 
+// the one-workgroup scans use 256 threads: small enough to find room beside
+// resident shot kernels of other streams
+constexpr int kScanT = 256;
+
 constexpr int PT = 256;   // threads per block (4 waves, 256 shots)
 
 template <int W>
@@ -71,10 +75,10 @@ __global__ __launch_bounds__(PT) void screen_kernel(int32_t nch, int64_t n,
 }
 
 // exclusive scan of block counts in place (one block), total at [nb]
-__global__ __launch_bounds__(1024) void scan_kernel(int64_t* cnt, int64_t nb) {
-    __shared__ int64_t part[1024];
+__global__ __launch_bounds__(kScanT) void scan_kernel(int64_t* cnt, int64_t nb) {
+    __shared__ int64_t part[kScanT];
     const int tid = threadIdx.x;
-    const int64_t per = (nb + 1023) / 1024;
+    const int64_t per = (nb + kScanT - 1) / kScanT;
     const int64_t lo = tid * per, hi = (lo + per < nb) ? lo + per : nb;
     int64_t s = 0;
     for (int64_t j = lo; j < hi; ++j) s += cnt[j];
@@ -82,7 +86,7 @@ __global__ __launch_bounds__(1024) void scan_kernel(int64_t* cnt, int64_t nb) {
     __syncthreads();
     if (tid == 0) {
         int64_t run = 0;
-        for (int j = 0; j < 1024; ++j) {
+        for (int j = 0; j < kScanT; ++j) {
             int64_t v = part[j];
             part[j] = run;
             run += v;
@@ -149,7 +153,7 @@ hipError_t launch_prescreen(int words, int32_t n_channels, int64_t n, const int6
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, block_tmp, nb);
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanT), 0, s, block_tmp, nb);
     e = hipGetLastError();
     if (e != hipSuccess || !survivor_idx) return e;
     hipLaunchKernelGGL(scatter_kernel, grid, dim3(PT), 0, s, n, bits, block_tmp, survivor_idx);

@@ -27,6 +27,10 @@
 namespace msc {
 namespace {
 
+// the one-workgroup scans use 256 threads: small enough to find room beside
+// resident shot kernels of other streams
+constexpr int kScanT = 256;
+
 constexpr int ST = 256;   // shots per block
 constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
 
@@ -109,23 +113,23 @@ __global__ __launch_bounds__(ST) void weight_kernel(int64_t n, uint64_t seed, ui
 }
 
 // exclusive scan of the block totals in place (one block), grand total at [nb]
-__global__ __launch_bounds__(1024) void total_scan_kernel(int64_t* cnt, int64_t nb) {
-    __shared__ int64_t part[1024];
+__global__ __launch_bounds__(kScanT) void total_scan_kernel(int64_t* cnt, int64_t nb) {
+    __shared__ int64_t part[kScanT];
     const int tid = threadIdx.x;
-    const int64_t per = (nb + 1023) / 1024;
+    const int64_t per = (nb + kScanT - 1) / kScanT;
     const int64_t lo = tid * per, hi = (lo + per < nb) ? lo + per : nb;
     int64_t acc = 0;
     for (int64_t j = lo; j < hi; ++j) acc += cnt[j];
     part[tid] = acc;
     __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
+    for (int d = 1; d < kScanT; d <<= 1) {
         const int64_t v = tid >= d ? part[tid - d] : 0;
         __syncthreads();
         part[tid] += v;
         __syncthreads();
     }
     int64_t run = tid ? part[tid - 1] : 0;
-    if (tid == 1023) cnt[nb] = part[1023];
+    if (tid == kScanT - 1) cnt[nb] = part[kScanT - 1];
     for (int64_t j = lo; j < hi; ++j) {
         const int64_t v = cnt[j];
         cnt[j] = run;
@@ -197,7 +201,7 @@ hipError_t launch_sampler(int64_t n, uint64_t seed, uint64_t first, const int32_
                        shot_off, tmp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(total_scan_kernel, dim3(1), dim3(1024), 0, s, tmp, nb);
+    hipLaunchKernelGGL(total_scan_kernel, dim3(1), dim3(kScanT), 0, s, tmp, nb);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(draw_kernel, grid, dim3(ST), 0, s, n, seed, first, weights, cdf, n_cdf, M,

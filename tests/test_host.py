@@ -35,6 +35,7 @@ def test_struct_sizes_match_header():
     assert C.sizeof(_lib.ShotResult) == 64
     assert C.sizeof(_lib.SimOpts) == 48
     assert C.sizeof(_lib.CircuitInfo) == 72
+    assert C.sizeof(_lib.BatchStats) == 88
 
 
 @pytest.mark.parametrize("text,frag", [

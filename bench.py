@@ -35,6 +35,7 @@ PEAK_FP64_VECTOR = 78.6     # TFLOP/s, MI355X
 PEAK_FP32_MFMA = 157.3      # TFLOP/s, MI355X dense
 PEAK_BF16_MFMA = 2500.0     # TFLOP/s, MI355X dense (BF16x3 does 3 products per product)
 SEED = 0x5EED0003
+SEED_P5E4 = 0x5EED0013
 METRIC = "MPS shots/sec at chi=256, batched mixed-precision vs plain FP64, same GPU"
 
 
@@ -50,7 +51,7 @@ def main() -> int:
     ap.add_argument("--shots", type=int, default=4096)
     ap.add_argument("--p", type=float, default=1e-3)
     ap.add_argument("--chi-max", type=int, default=256)
-    ap.add_argument("--fp64-sample", type=int, default=12,
+    ap.add_argument("--fp64-sample", type=int, default=48,
                     help="survivors timed one per launch on the FP64 path")
     ap.add_argument("--cpu-sample", type=int, default=48,
                     help="shots of the batch run through the CPU oracle")
@@ -117,15 +118,40 @@ def main() -> int:
     def sample(c, b):
         return msc.sample_faults_device(c, circ, SEED, b * n, n, p=args.p)
 
-    def step(c, b):
+    def step(c, b, p=args.p, seed=SEED):
         # one pass of the whole path over one batch on the context's stream:
         # fault sampling, offline screen, batched MPS of the survivors and
         # the per-weight bin sums, with one synchronisation at the end
-        bins, st = msc.run_batch(c, circ, SEED, b * n, n, args.p, n_bins=wmax + 1,
+        bins, st = msc.run_batch(c, circ, seed, b * n, n, p, n_bins=wmax + 1,
                                  precision=msc.MSC_FP32, chi_max=args.chi_max,
                                  lds_width=args.lds_width, prefix=not args.no_prefix,
                                  n_slots=args.slots)
         return st, bins
+
+    def timed(first, steps, p=args.p, seed=SEED):
+        """Steps first .. first+steps-1 over the S contexts; (wall s, results)."""
+        out = [None] * steps
+        errors = []
+
+        def worker(t):
+            try:
+                for i in range(t, steps, S):
+                    out[i] = step(ctxs[t], first + i, p, seed)
+            except BaseException as e:    # re-raised by the main thread
+                errors.append(e)
+
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        threads = [threading.Thread(target=worker, args=(t,)) for t in range(S)]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if errors:
+            raise errors[0]
+        return t1 - t0, out
 
     prefix_ms = None
     if not args.no_prefix:
@@ -142,28 +168,7 @@ def main() -> int:
     warmup = max(args.warmup, S)
     for b in range(warmup):
         step(ctxs[b % S], b)
-    torch.cuda.synchronize()
-    per = [None] * args.steps
-    errors = []
-
-    def worker(t):
-        try:
-            for i in range(t, args.steps, S):
-                per[i] = step(ctxs[t], warmup + i)
-        except BaseException as e:    # re-raised by the main thread
-            errors.append(e)
-
-    t0 = time.perf_counter()
-    threads = [threading.Thread(target=worker, args=(t,)) for t in range(S)]
-    for th in threads:
-        th.start()
-    for th in threads:
-        th.join()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    if errors:
-        raise errors[0]
-    wall = t1 - t0
+    wall, per = timed(warmup, args.steps)
     value = args.steps * n / wall
     bin_n, bin_a, bin_e = sum(p[1] for p in per)
     sts = [p[0] for p in per]
@@ -174,9 +179,12 @@ def main() -> int:
     flops = [st["flops"] for st in sts]
     n2q = [st["n2q"] for st in sts]
     chi_peak = max(st["chi_peak"] for st in sts)
-    # algorithmic flops of the timed steps over the timed wall time (the
-    # steps overlap, so per-launch durations would double count)
-    achieved = sum(flops) / wall / 1e12
+    # roofline of the shot kernel: algorithmic flops per launch over the
+    # launch's average duration (HIP events on its context's stream); the
+    # launches of overlapping steps share the GPU, so the whole-job rate
+    # (all flops over the timed wall time) is reported beside it
+    achieved = float(np.mean(flops)) / (float(np.mean(sim_ms)) * 1e-3) / 1e12
+    achieved_job = sum(flops) / wall / 1e12
     sweeps = sum(st["sweeps"] for st in sts)
     log(f"steps={args.steps} wall={wall:.3f}s value={value:.1f} shots/s survivors={n_surv} "
         f"sim_ms={sim_ms} screen_ms={screen_ms} sample_ms={sample_ms}")
@@ -221,11 +229,20 @@ def main() -> int:
                      "kernel": f"mps_kernel<float,{64 if args.lds_width == 64 else 32}>",
                      "achieved": achieved, "peak": PEAK_FP64_VECTOR, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_VECTOR, "traffic": measured_traffic(),
+                     "launch_ms": float(np.mean(sim_ms)),
+                     "achieved_whole_job": achieved_job,
+                     "frac_whole_job": achieved_job / PEAK_FP64_VECTOR,
                      "flops_per_launch": float(np.mean(flops))},
         "estimates": {str(p): e for p, e in zip([5e-4, 1e-3, 2e-3], est)},
     }
 
     if not args.no_extras:
+        # the second error rate of the workload (its own seed), same pipeline
+        wall2, per2 = timed(0, max(S, args.steps // 2), 5e-4, SEED_P5E4)
+        result["value_p_5e-4"] = {"value": len(per2) * n / wall2, "unit": "shots/s",
+                                  "steps": len(per2), "seed": hex(SEED_P5E4),
+                                  "survivors_per_step": float(np.mean(
+                                      [q[0]["n_survivors"] for q in per2]))}
         # plain FP64 path, one shot per launch, on survivors of the first timed batch
         off, ch, pa = sample(ctx, warmup)
         _, idx0, _ = msc.prescreen(ctx, circ, off, ch, pa)
@@ -233,22 +250,33 @@ def main() -> int:
                                                precision=msc.MSC_FP32, chi_max=args.chi_max,
                                                lds_width=args.lds_width,
                                                prefix=not args.no_prefix))
+        def one_shot_fp64(k, prefix):
+            # the same kernels in FP64, one survivor per launch (one
+            # workgroup), on the first k survivors of the batch; the step
+            # rate adds the batch's mean screen and sampling times
+            if prefix:   # checkpoints of the FP64 noiseless run, built once
+                msc.simulate(ctx, circ, off, ch, pa, shot_idx=idx0[:1].contiguous(),
+                             precision=msc.MSC_FP64, chi_max=args.chi_max, n_slots=1,
+                             prefix=True)
+            t = 0.0
+            for i in range(k):
+                msc.simulate(ctx, circ, off, ch, pa, shot_idx=idx0[i:i + 1].contiguous(),
+                             precision=msc.MSC_FP64, chi_max=args.chi_max, n_slots=1,
+                             prefix=prefix)
+                t += ctx.last_kernel_ms("simulate")
+            per_shot = t / k
+            step_ms = (per_shot * float(np.mean(n_surv)) + float(np.mean(screen_ms)) +
+                       float(np.mean(sample_ms)))
+            rate = n / (step_ms * 1e-3)
+            return {"shots_per_s": rate, "sampled_survivors": k, "ms_per_survivor": per_shot,
+                    "prefix_sharing": prefix, "speedup_of_value": value / rate}
+
         k = min(args.fp64_sample, int(idx0.numel()))
-        t64 = 0.0
-        r64 = []
-        for i in range(k):
-            out = msc.simulate(ctx, circ, off, ch, pa, shot_idx=idx0[i:i + 1].contiguous(),
-                               precision=msc.MSC_FP64, chi_max=args.chi_max, n_slots=1)
-            t64 += ctx.last_kernel_ms("simulate")
-            r64.append(msc.results_numpy(out)[0])
         if k:
-            per_shot = t64 / k
-            fp64_step_ms = (per_shot * float(np.mean(n_surv)) + float(np.mean(screen_ms)) +
-                            float(np.mean(sample_ms)))
-            fp64_rate = n / (fp64_step_ms * 1e-3)
-            result["fp64_one_shot"] = {"shots_per_s": fp64_rate, "sampled_survivors": k,
-                                       "ms_per_survivor": per_shot,
-                                       "speedup_of_value": value / fp64_rate}
+            # the headline comparison: the same shot list, the same prefix
+            # sharing as the batched path; without it as context
+            result["fp64_one_shot"] = one_shot_fp64(k, not args.no_prefix)
+            result["fp64_one_shot_no_prefix"] = one_shot_fp64(min(k, 12), False)
         # precision: FP32 batched vs FP64 batched on all survivors of that batch
         out64 = msc.results_numpy(msc.simulate(ctx, circ, off, ch, pa, shot_idx=idx0,
                                                precision=msc.MSC_FP64, chi_max=args.chi_max))

@@ -170,7 +170,7 @@ def main() -> int:
         step(ctxs[b % S], b)
     wall, per = timed(warmup, args.steps)
     value = args.steps * n / wall
-    bin_n, bin_a, bin_e = sum(p[1] for p in per)
+    bin_n, bin_a, bin_e, bin_k, bin_m = sum(p[1] for p in per)
     sts = [p[0] for p in per]
     n_surv = [st["n_survivors"] for st in sts]
     sim_ms = [st["ms_simulate"] for st in sts]
@@ -189,6 +189,16 @@ def main() -> int:
     log(f"steps={args.steps} wall={wall:.3f}s value={value:.1f} shots/s survivors={n_surv} "
         f"sim_ms={sim_ms} screen_ms={screen_ms} sample_ms={sample_ms}")
     est = msc.reweight(bin_n, bin_a, bin_e, M, [5e-4, 1e-3, 2e-3])
+    # likelihood-ratio intervals (R = 100) of the two reported rates from the
+    # timed shots' accepted / wrong counts (host post-processing, untimed)
+    last = int(np.nonzero(bin_n)[0].max()) + 1
+    intervals = {}
+    for name, f in (("p_acc", msc.MSC_STAT_PACC), ("p_le", msc.MSC_STAT_PLE)):
+        r = msc.lr_interval(bin_n[:last], bin_k[:last], bin_m[:last], M, args.p, f)
+        intervals[name] = {k: r[k] for k in ("estimate", "lo", "hi", "hi_trunc",
+                                             "trunc_bound", "unaccepted")}
+    intervals["counts"] = {"shots": float(bin_n.sum()), "accepted": float(bin_k.sum()),
+                           "wrong": float(bin_m.sum())}
 
     result = {
         "metric": METRIC,
@@ -234,6 +244,7 @@ def main() -> int:
                      "frac_whole_job": achieved_job / PEAK_FP64_VECTOR,
                      "flops_per_launch": float(np.mean(flops))},
         "estimates": {str(p): e for p, e in zip([5e-4, 1e-3, 2e-3], est)},
+        "intervals_r100": intervals,
     }
 
     if not args.no_extras:

@@ -257,11 +257,16 @@ int msc_simulate(msc_ctx* ctx, const msc_circuit* c, const msc_sim_opts* opts,
    (Section 4.1), screened as by msc_prescreen (Section 4.2), the survivors
    simulated as by msc_simulate with `opts` (Sections 3.1, 4, 4.3), and the
    results reduced per fault weight for Eq. (reweight): bins (host,
-   3 * n_bins doubles, 1 <= n_bins <= 1024) receives bins[w] = number of
-   shots of weight w, bins[n_bins + w] = sum of their P_acc and
-   bins[2 n_bins + w] = sum of P_acc * fail (weights >= n_bins - 1 share
-   the last bin; screened shots count with P_acc = 0), summed in a fixed
-   order.  stats (host) is optional.  out (device, n_shots records) is
+   5 * n_bins doubles, 1 <= n_bins <= 1024) receives bins[w] = number of
+   shots of weight w, bins[n_bins + w] = sum of their P_acc,
+   bins[2 n_bins + w] = sum of P_acc * fail (both summed in a fixed
+   order), and the counts of the error analysis's likelihood (Eq.
+   (loglik-split)): bins[3 n_bins + w] = shots counted as accepted, i.e.
+   with u < P_acc for the shot's acceptance uniform u, bins[4 n_bins + w] =
+   those of them whose accepted branch fails.  u = (x >> 11) 2^-53 with x
+   the first output of the SplitMix64 stream keyed as the fault draws but
+   with seed ^ 0x243F6A8885A308D3.  Weights >= n_bins - 1 share the last
+   bin; screened shots count with P_acc = 0.  stats (host) is optional.  out (device, n_shots records) is
    optional: out[i] is the result of shot i (screened shots: all zero,
    rejected_at -1).  The fault buffer is sized for the largest weight the
    Bin(M, p) table can draw; MSC_E_CAPACITY if that exceeds 2^28 faults.   */
@@ -297,6 +302,71 @@ int msc_twosite_contract(msc_ctx* ctx, int32_t precision, int32_t chi,
 int msc_reweight(const double* bin_n, const double* bin_acc,
                  const double* bin_fail, int32_t n_bins, int64_t M,
                  const double* p_grid, int32_t n_p, msc_estimate* out);
+
+/* ---------------------------------------------------------------------- */
+/* Likelihood statistics (Appendix "Error analysis of the subset-sampling  */
+/* estimator"; Appendix "Credible intervals for rate ratios"; Appendix     */
+/* "Losses").  Host only, no device work.                                   */
+
+/* Per-bin counts (host, n_bins each, integer-valued doubles): bin_n[w]
+   shots of weight w, bin_acc[w] = k_w of them accepted, bin_err[w] = m_w of
+   those accepted with a logical failure (0 <= m_w <= k_w <= n_w);
+   msc_run_batch's rows 0, 3 and 4.  Bins with n_w = 0 are unsampled and
+   left out of the likelihood.  p_le^(w) = 0 is imposed for w < d_e (such a
+   bin must have m_w = 0).  Bin_w = C(M, w) p^w (1-p)^(M-w).  The joint
+   log-likelihood is the sum over bins of Eq. (loglik-split).            */
+enum msc_functional {
+    MSC_STAT_PACC = 0,    /* p_acc = sum_w Bin_w p_acc^(w)                     */
+    MSC_STAT_PLE = 1      /* p_le = sum_w Bin_w p_acc^(w) p_le^(w) / p_acc     */
+};
+
+typedef struct {
+    double estimate;      /* the functional at the maximum-likelihood rates  */
+    double lo, hi;        /* Eq. (profile) endpoints at threshold log R       */
+    double hi_trunc;      /* hi + B: the truncation bound added upward only   */
+    double trunc_bound;   /* B = sum_{w >= n_bins} Bin_w(p)                   */
+    double unaccepted;    /* sum over sampled bins with k_w = 0 of
+                             Bin_w (1 - R^(-1/n_w)): their worst case       */
+    double unsampled_mass;/* sum of Bin_w over the bins with n_w = 0          */
+    int32_t n_unsampled;  /* number of those bins                             */
+    int32_t n_bins_used;  /* bins with n_w > 0                                */
+} msc_interval;
+
+/* Eq. (profile) at one value: *out = max over all bin rates with
+   functional = theta of the joint log-likelihood, minus its unconstrained
+   maximum (<= 0; -inf when theta is not attainable).                     */
+int msc_profile_loglik(const double* bin_n, const double* bin_acc,
+                       const double* bin_err, int32_t n_bins, int64_t M,
+                       double p, int32_t d_e, int32_t functional,
+                       double theta, double* out);
+
+/* Likelihood-ratio interval of Eq. (profile): every theta whose profile is
+   at least -log R (R > 1; the paper uses R = 100), endpoints by bisection
+   to 2^-60 of the range.  out (host) as described above.  MSC_E_INVALID if
+   no bin is sampled or the counts are inconsistent.                      */
+int msc_lr_interval(const double* bin_n, const double* bin_acc,
+                    const double* bin_err, int32_t n_bins, int64_t M,
+                    double p, int32_t d_e, int32_t functional, double R,
+                    msc_interval* out);
+
+/* Central credible interval (probability `level`) of the ratio T / S of
+   two logical error rates: T is p_le of the counts given (posterior = the
+   normalised profile likelihood with a prior flat in log theta), S has the
+   Jeffreys posterior Beta(s_err + 1/2, s_acc - s_err + 1/2) from s_acc
+   accepted shots of which s_err failed.  The densities of log T and log S
+   are sampled on the lattice j h (natural log; h in (0, 0.1]) until they
+   are 18 log-units below their maxima on both sides, log T - log S is
+   their discrete convolution, its CDF is read at cell edges (j + 1/2) h
+   and interpolated linearly.  Needs at least one failure in the counts.  */
+int msc_ratio_credible(const double* bin_n, const double* bin_acc,
+                       const double* bin_err, int32_t n_bins, int64_t M,
+                       double p, int32_t d_e, double s_acc, double s_err,
+                       double level, double h, double* lo, double* hi);
+
+/* Multiplicative factor on the expected number of attempts when each of M
+   channels carries an independent, detected loss of probability p_loss:
+   (1 - p_loss)^(-M) (Appendix "Losses").                                  */
+int msc_loss_factor(int64_t M, double p_loss, double* out);
 
 #ifdef __cplusplus
 }

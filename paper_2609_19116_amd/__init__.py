@@ -12,13 +12,15 @@ import ctypes as C
 
 import numpy as np
 
-from ._lib import (BatchStats, MSC_BF16X3, MSC_FP32, MSC_FP64, SHOT_CHI_CAP, SHOT_DONE, SHOT_DTYPE,  # noqa: F401
-                   SHOT_NOCONV, SHOT_REJECTED, CircuitInfo, Estimate, MscError, SimOpts,
-                   _check, _ptr, lib)
+from ._lib import (BatchStats, MSC_BF16X3, MSC_FP32, MSC_FP64, MSC_STAT_PACC,  # noqa: F401
+                   MSC_STAT_PLE, SHOT_CHI_CAP, SHOT_DONE, SHOT_DTYPE, SHOT_NOCONV,
+                   SHOT_REJECTED, CircuitInfo, Estimate, Interval, MscError, SimOpts, _check,
+                   _ptr, lib)
 
-__all__ = ["Ctx", "Circuit", "sample_faults", "prescreen", "simulate", "reweight",
-           "twosite_contract", "prescreen_tables", "version", "MscError",
-           "MSC_FP64", "MSC_FP32", "MSC_BF16X3", "SHOT_DTYPE"]
+__all__ = ["Ctx", "Circuit", "sample_faults", "sample_faults_device", "prescreen", "simulate",
+           "run_batch", "reweight", "profile_loglik", "lr_interval", "ratio_credible",
+           "loss_factor", "twosite_contract", "prescreen_tables", "version", "MscError",
+           "MSC_FP64", "MSC_FP32", "MSC_BF16X3", "MSC_STAT_PACC", "MSC_STAT_PLE", "SHOT_DTYPE"]
 
 
 def version() -> str:
@@ -184,19 +186,20 @@ def run_batch(ctx: Ctx, circ: Circuit, seed: int, first_shot: int, n_shots: int,
               lds_width: int = 0, prefix: bool = True, out=None):
     """One batch of the whole path (sampling, screen, shots, bin sums) on the
     context's stream with one synchronisation.  Returns (bins float64
-    [3, n_bins]: shots, sum P_acc, sum P_acc * fail per weight; stats dict).
+    [5, n_bins]: shots, sum P_acc, sum P_acc * fail, accepted count, wrong
+    count per weight; stats dict).
     ``out`` (optional uint8 device tensor of n_shots records) receives the
     per-shot results, indexed by shot."""
     o = SimOpts(precision, chi_max, tau_trunc, tau_rej, tau_fail, n_slots, lds_width,
                 1 if prefix else 0, 0)
-    bins = np.zeros(3 * n_bins, dtype=np.float64)
+    bins = np.zeros(5 * n_bins, dtype=np.float64)
     st = BatchStats()
     if out is not None:
         assert out.numel() >= n_shots * SHOT_DTYPE.itemsize
     _check(lib().msc_run_batch(ctx.h, circ.h, C.byref(o), seed, first_shot, n_shots, p, n_bins,
                                _ptr(bins), C.byref(st), _ptr(out)))
     stats = {f: getattr(st, f) for f, _ in BatchStats._fields_}
-    return bins.reshape(3, n_bins), stats
+    return bins.reshape(5, n_bins), stats
 
 
 def results_numpy(out) -> np.ndarray:
@@ -219,3 +222,40 @@ def reweight(bin_n, bin_acc, bin_fail, M: int, p_grid) -> list:
                               C.cast(out, C.c_void_p)))
     return [dict(p_acc=o.p_acc, p_acc_le=o.p_acc_le, p_le=o.p_le, trunc_bound=o.trunc_bound)
             for o in out]
+
+
+def _counts(bin_n, bin_acc, bin_err):
+    return tuple(np.ascontiguousarray(x, dtype=np.float64) for x in (bin_n, bin_acc, bin_err))
+
+
+def profile_loglik(bin_n, bin_acc, bin_err, M: int, p: float, functional: int, theta: float,
+                   d_e: int = 0) -> float:
+    n, k, m = _counts(bin_n, bin_acc, bin_err)
+    out = C.c_double()
+    _check(lib().msc_profile_loglik(_ptr(n), _ptr(k), _ptr(m), len(n), M, p, d_e, functional,
+                                    theta, C.byref(out)))
+    return out.value
+
+
+def lr_interval(bin_n, bin_acc, bin_err, M: int, p: float, functional: int, R: float = 100.0,
+                d_e: int = 0) -> dict:
+    n, k, m = _counts(bin_n, bin_acc, bin_err)
+    out = Interval()
+    _check(lib().msc_lr_interval(_ptr(n), _ptr(k), _ptr(m), len(n), M, p, d_e, functional, R,
+                                 C.byref(out)))
+    return {f: getattr(out, f) for f, _ in Interval._fields_}
+
+
+def ratio_credible(bin_n, bin_acc, bin_err, M: int, p: float, s_acc: float, s_err: float,
+                   level: float = 0.95, h: float = 2e-3, d_e: int = 0):
+    n, k, m = _counts(bin_n, bin_acc, bin_err)
+    lo, hi = C.c_double(), C.c_double()
+    _check(lib().msc_ratio_credible(_ptr(n), _ptr(k), _ptr(m), len(n), M, p, d_e, s_acc, s_err,
+                                    level, h, C.byref(lo), C.byref(hi)))
+    return lo.value, hi.value
+
+
+def loss_factor(M: int, p_loss: float) -> float:
+    out = C.c_double()
+    _check(lib().msc_loss_factor(M, p_loss, C.byref(out)))
+    return out.value

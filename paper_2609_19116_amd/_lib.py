@@ -74,6 +74,15 @@ class Estimate(C.Structure):
                 ("trunc_bound", C.c_double)]
 
 
+class Interval(C.Structure):
+    _fields_ = [("estimate", C.c_double), ("lo", C.c_double), ("hi", C.c_double),
+                ("hi_trunc", C.c_double), ("trunc_bound", C.c_double),
+                ("unaccepted", C.c_double), ("unsampled_mass", C.c_double),
+                ("n_unsampled", C.c_int32), ("n_bins_used", C.c_int32)]
+
+
+MSC_STAT_PACC, MSC_STAT_PLE = 0, 1
+
 # every exported symbol of include/msc.h with its signature
 _P = C.c_void_p
 _SIGS = {
@@ -100,6 +109,14 @@ _SIGS = {
                                 C.c_double, C.c_int32, _P, C.POINTER(BatchStats), _P]),
     "msc_twosite_contract": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, _P]),
     "msc_reweight": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, _P, C.c_int32, _P]),
+    "msc_profile_loglik": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, C.c_double, C.c_int32,
+                                     C.c_int32, C.c_double, C.POINTER(C.c_double)]),
+    "msc_lr_interval": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, C.c_double, C.c_int32,
+                                  C.c_int32, C.c_double, C.POINTER(Interval)]),
+    "msc_ratio_credible": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, C.c_double, C.c_int32,
+                                     C.c_double, C.c_double, C.c_double, C.c_double,
+                                     C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "msc_loss_factor": (C.c_int, [C.c_int64, C.c_double, C.POINTER(C.c_double)]),
 }
 
 _lib = None

@@ -23,6 +23,7 @@ SOURCES = [
     CSRC / "host" / "circuit.cpp",
     CSRC / "host" / "prescreen_compile.cpp",
     CSRC / "host" / "sampler.cpp",
+    CSRC / "host" / "stats.cpp",
     CSRC / "host" / "capi.cpp",
     CSRC / "kernels" / "mps.hip",
     CSRC / "kernels" / "prescreen.hip",

@@ -648,7 +648,7 @@ extern "C" int msc_run_batch(msc_ctx* ctx, const msc_circuit* c, const msc_sim_o
                                             opts->chi_max, tau, tau_rej, tau_fail, lds_width)))
         return rc;
     // host-mapped block for the reduction: bins, then the totals
-    const size_t hbytes = 3 * static_cast<size_t>(n_bins) * sizeof(double) + sizeof(BatchTotals);
+    const size_t hbytes = kBinRows * static_cast<size_t>(n_bins) * sizeof(double) + sizeof(BatchTotals);
     if (ctx->hmap_bytes < hbytes) {
         if (ctx->hmap) (void)hipHostFree(ctx->hmap);
         ctx->hmap = nullptr;
@@ -679,10 +679,10 @@ extern "C" int msc_run_batch(msc_ctx* ctx, const msc_circuit* c, const msc_sim_o
     int64_t* nsurv = static_cast<int64_t*>(dtp) + (ntp - 1);   // the screen's total
     int64_t* nnz = static_cast<int64_t*>(dts) + (nts - 1);     // the sampler's total
     double* hbins = static_cast<double*>(ctx->hmap_dev);
-    BatchTotals* htot = reinterpret_cast<BatchTotals*>(hbins + 3 * static_cast<size_t>(n_bins));
+    BatchTotals* htot = reinterpret_cast<BatchTotals*>(hbins + kBinRows * static_cast<size_t>(n_bins));
     msc_shot_result* res = static_cast<msc_shot_result*>(dres);
     if (n_shots == 0) {
-        for (int32_t b = 0; b < 3 * n_bins; ++b) bins[b] = 0.0;
+        for (int32_t b = 0; b < kBinRows * n_bins; ++b) bins[b] = 0.0;
         if (stats) *stats = msc_batch_stats{};
         return MSC_OK;
     }
@@ -704,13 +704,13 @@ extern "C" int msc_run_batch(msc_ctx* ctx, const msc_circuit* c, const msc_sim_o
                        nsurv);
     if (rc) return rc;
     MSC_HIP(hipEventRecord(ctx->ev3, ctx->stream));
-    MSC_HIP(launch_batch_reduce(n_shots, offp, idxp, nsurv, res, n_bins, nnz, hbins, htot,
-                                ctx->stream));
+    MSC_HIP(launch_batch_reduce(n_shots, seed, first_shot, offp, idxp, nsurv, res, n_bins, nnz,
+                                hbins, htot, ctx->stream));
     if (out) MSC_HIP(launch_scatter_results(n_shots, nsurv, idxp, res, out, ctx->stream));
     MSC_HIP(hipStreamSynchronize(ctx->stream));
     const double* hb = static_cast<const double*>(ctx->hmap);
-    for (int32_t b = 0; b < 3 * n_bins; ++b) bins[b] = hb[b];
-    const BatchTotals* ht = reinterpret_cast<const BatchTotals*>(hb + 3 * static_cast<size_t>(n_bins));
+    for (int32_t b = 0; b < kBinRows * n_bins; ++b) bins[b] = hb[b];
+    const BatchTotals* ht = reinterpret_cast<const BatchTotals*>(hb + kBinRows * static_cast<size_t>(n_bins));
     float t01 = 0.f, t12 = 0.f, t23 = 0.f;
     MSC_HIP(hipEventElapsedTime(&t01, ctx->ev0, ctx->ev1));
     MSC_HIP(hipEventElapsedTime(&t12, ctx->ev1, ctx->ev2));

@@ -178,7 +178,7 @@ extern "C" int msc_sample_faults(const msc_circuit* c, uint64_t seed, uint64_t f
 // p_acc^(w) p_le^(w); B = sum_{w > w_max} Bin_w(p) (Appendix
 // "Systematics"), summed over the tail itself so that tiny bounds keep full
 // relative precision.  Bin_w(p) = exp(lgamma terms + w log p + (M-w) log1p(-p)).
-static double log_bin(int64_t M, int64_t w, double p) {
+double msc::log_bin(int64_t M, int64_t w, double p) {
     if (p <= 0.0) return w == 0 ? 0.0 : -INFINITY;
     if (p >= 1.0) return w == M ? 0.0 : -INFINITY;
     return std::lgamma(static_cast<double>(M + 1)) - std::lgamma(static_cast<double>(w + 1)) -

@@ -2,6 +2,15 @@
 // Eq. (reweight)), written straight into host-mapped memory so that the
 // host reads them after one stream synchronisation, without a copy.
 //
+// Besides the sums of P_acc and P_acc * fail, each bin gets the counts that
+// the likelihood of the error analysis works with (Appendix "Error analysis
+// of the subset-sampling estimator", Eq. (loglik-split)): a shot counts as
+// accepted iff u < P_acc for one uniform u of its own, and as wrong iff it
+// is accepted and its accepted branch fails.  u is the first output of the
+// SplitMix64 stream (Steele, Lea, Flood 2014) keyed as the fault draws but
+// with the seed XOR'ed by a fixed constant (the first 64 fraction bits of
+// pi), converted as (x >> 11) 2^-53; screened shots have P_acc = 0.
+//
 // One 256-thread workgroup.  Counts use LDS integer atomics (exact); the
 // FP64 sums are reduced in a fixed order (per bin, each thread walks a
 // fixed strided subset of the survivors, then a fixed tree), so the bins
@@ -16,6 +25,18 @@ namespace msc {
 namespace {
 
 constexpr int RT = 256;
+constexpr uint64_t kAcceptKey = 0x243F6A8885A308D3ull;
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ double acceptance_uniform(uint64_t seed, uint64_t shot) {
+    const uint64_t st = mix64((seed ^ kAcceptKey) ^ mix64(shot)) + 0x9E3779B97F4A7C15ull;
+    return static_cast<double>(mix64(st) >> 11) * (1.0 / 9007199254740992.0);
+}
 
 __device__ double block_sum_fixed(double v, double* red) {
 #pragma unroll
@@ -29,7 +50,8 @@ __device__ double block_sum_fixed(double v, double* red) {
     return s;
 }
 
-__global__ __launch_bounds__(RT) void batch_reduce_kernel(int64_t n, const int64_t* __restrict__ off,
+__global__ __launch_bounds__(RT) void batch_reduce_kernel(int64_t n, uint64_t seed, uint64_t first,
+                                                          const int64_t* __restrict__ off,
                                                           const int64_t* __restrict__ idx,
                                                           const int64_t* __restrict__ n_surv,
                                                           const msc_shot_result* __restrict__ res,
@@ -38,6 +60,8 @@ __global__ __launch_bounds__(RT) void batch_reduce_kernel(int64_t n, const int64
                                                           BatchTotals* __restrict__ tot) {
     __shared__ int s_cnt[kMaxBins];
     __shared__ int s_scnt[kMaxBins];
+    __shared__ int s_kacc[kMaxBins];
+    __shared__ int s_kerr[kMaxBins];
     __shared__ double s_red[RT / 64];
     __shared__ unsigned long long s_n2q, s_sweeps;
     __shared__ int s_acc, s_chi, s_status;
@@ -45,6 +69,8 @@ __global__ __launch_bounds__(RT) void batch_reduce_kernel(int64_t n, const int64
     for (int b = tid; b < nb; b += RT) {
         s_cnt[b] = 0;
         s_scnt[b] = 0;
+        s_kacc[b] = 0;
+        s_kerr[b] = 0;
     }
     if (tid == 0) {
         s_n2q = 0;
@@ -62,8 +88,14 @@ __global__ __launch_bounds__(RT) void batch_reduce_kernel(int64_t n, const int64
     const int64_t ns = *n_surv;
     double fl = 0.0;
     for (int64_t s = tid; s < ns; s += RT) {
-        atomicAdd(&s_scnt[weight(idx[s])], 1);
+        const int64_t i = idx[s];
+        const int wb = weight(i);
+        atomicAdd(&s_scnt[wb], 1);
         const msc_shot_result& r = res[s];
+        if (acceptance_uniform(seed, first + static_cast<uint64_t>(i)) < r.p_acc) {
+            atomicAdd(&s_kacc[wb], 1);
+            if (r.fail) atomicAdd(&s_kerr[wb], 1);
+        }
         atomicAdd(&s_n2q, static_cast<unsigned long long>(r.n2q));
         atomicAdd(&s_sweeps, static_cast<unsigned long long>(r.sweeps));
         if (r.p_acc > 0.0) atomicAdd(&s_acc, 1);
@@ -94,7 +126,11 @@ __global__ __launch_bounds__(RT) void batch_reduce_kernel(int64_t n, const int64
         }
     }
     __syncthreads();
-    for (int b = tid; b < nb; b += RT) bins[b] = s_cnt[b];
+    for (int b = tid; b < nb; b += RT) {
+        bins[b] = s_cnt[b];
+        bins[3 * nb + b] = s_kacc[b];
+        bins[4 * nb + b] = s_kerr[b];
+    }
     if (tid == 0) {
         tot->nnz = *nnz;
         tot->n_survivors = ns;
@@ -129,12 +165,13 @@ __global__ __launch_bounds__(RT) void scatter_results_kernel(int64_t n, const in
 
 }  // namespace
 
-hipError_t launch_batch_reduce(int64_t n, const int64_t* off, const int64_t* idx,
-                               const int64_t* n_surv, const msc_shot_result* res, int nb,
-                               const int64_t* nnz, double* bins, BatchTotals* tot, hipStream_t s) {
+hipError_t launch_batch_reduce(int64_t n, uint64_t seed, uint64_t first, const int64_t* off,
+                               const int64_t* idx, const int64_t* n_surv,
+                               const msc_shot_result* res, int nb, const int64_t* nnz,
+                               double* bins, BatchTotals* tot, hipStream_t s) {
     if (nb < 1 || nb > kMaxBins) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(batch_reduce_kernel, dim3(1), dim3(RT), 0, s, n, off, idx, n_surv, res, nb,
-                       nnz, bins, tot);
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3(1), dim3(RT), 0, s, n, seed, first, off, idx,
+                       n_surv, res, nb, nnz, bins, tot);
     return hipGetLastError();
 }
 

@@ -99,9 +99,11 @@ struct BatchTotals {
     double flops;
     int32_t chi_peak, status_or;
 };
-hipError_t launch_batch_reduce(int64_t n, const int64_t* off, const int64_t* idx,
-                               const int64_t* n_surv, const msc_shot_result* res, int nb,
-                               const int64_t* nnz, double* bins, BatchTotals* tot, hipStream_t s);
+constexpr int kBinRows = 5;   // shots, sum P_acc, sum P_acc*fail, accepted, wrong
+hipError_t launch_batch_reduce(int64_t n, uint64_t seed, uint64_t first, const int64_t* off,
+                               const int64_t* idx, const int64_t* n_surv,
+                               const msc_shot_result* res, int nb, const int64_t* nnz,
+                               double* bins, BatchTotals* tot, hipStream_t s);
 hipError_t launch_scatter_results(int64_t n, const int64_t* n_surv, const int64_t* idx,
                                   const msc_shot_result* res, msc_shot_result* out,
                                   hipStream_t s);

@@ -58,6 +58,9 @@ void gate4_matrix(int g, double out[32]);   // (re,im) row-major 4x4
 // FP64 cumulative Bin(M, p) table of the sampler (sampler.cpp)
 std::vector<double> binomial_cdf(int64_t M, double p);
 
+// log Bin_w(p) = log C(M, w) + w log p + (M - w) log(1 - p) (sampler.cpp)
+double log_bin(int64_t M, int64_t w, double p);
+
 // Error helpers (capi.cpp)
 int set_error(int code, const std::string& msg);
 

@@ -3,7 +3,9 @@
 msc_run_batch runs sampling, screen, shots and the per-weight reduction on
 one stream; its per-shot results must equal those of the separate calls bit
 for bit, its bins the sums of those results, and its bins the oracle's on a
-small circuit.
+small circuit.  The accepted / wrong counts of rows 3 and 4 are compared
+exactly with the oracle's acceptance draws applied to the same per-shot
+results, and to the oracle's own results.
 """
 import threading
 
@@ -12,6 +14,7 @@ import pytest
 
 import paper_2609_19116_amd as msc
 from paper_2609_19116_amd import MSC_FP32, MSC_FP64, results_numpy
+from oracle import stats as ostats
 from tests.helpers import oracle_csr, oracle_results, say
 from workloads.circuits import config_circuit
 
@@ -30,6 +33,8 @@ def ctx():
 
 
 def _separate(ctx, circ, seed, first, n, p, nb, **kw):
+    """Bins from the separate stages: the sums of the per-shot results and
+    the oracle's acceptance counts of those results."""
     import torch
     off, ch, pa = msc.sample_faults_device(ctx, circ, seed, first, n, p=p)
     bits, idx, cnt = msc.prescreen(ctx, circ, off, ch, pa)
@@ -39,10 +44,11 @@ def _separate(ctx, circ, seed, first, n, p, nb, **kw):
         res = results_numpy(msc.simulate(ctx, circ, off, ch, pa, shot_idx=idx, **kw))
         per[idx.cpu().numpy()] = res
     w = np.minimum(np.diff(off.cpu().numpy()), nb - 1)
-    bins = np.zeros((3, nb))
+    bins = np.zeros((5, nb))
     np.add.at(bins[0], w, 1.0)
     np.add.at(bins[1], w, per["p_acc"])
     np.add.at(bins[2], w, per["p_acc"] * per["fail"])
+    _, bins[3], bins[4] = ostats.count_bins(seed, first, w, per["p_acc"], per["fail"], nb)
     return bins, per, int(ch.numel()), cnt
 
 
@@ -68,7 +74,8 @@ def test_run_batch_equals_separate_stages(ctx, name, n, p, precision, prefix):
     for f in FIELDS:
         assert np.array_equal(got[f], per[f]), f
     assert np.array_equal(bins[0], ref_bins[0])
-    assert np.allclose(bins[1:], ref_bins[1:], rtol=1e-12, atol=1e-12)
+    assert np.allclose(bins[1:3], ref_bins[1:3], rtol=1e-12, atol=1e-12)
+    assert np.array_equal(bins[3:], ref_bins[3:])
     assert st["n_shots"] == n and st["nnz"] == nnz and st["n_survivors"] == cnt
     assert st["n_accepted"] == int((per["p_acc"] > 0).sum())
     assert st["n2q"] == int(per["n2q"].sum()) and st["chi_peak"] == int(per["chi_peak"].max())
@@ -89,12 +96,25 @@ def test_run_batch_bins_match_oracle(ctx):
     ref = oracle_results(ocirc, ocsr)        # screened shots carry P_acc 0
     w = np.minimum(np.diff(ocsr[0]), nb - 1)
     fail = (ref[:, 0] > 0) & (ref[:, 1] > 1e-4)
-    rb = np.zeros((3, nb))
+    rb = np.zeros((5, nb))
     np.add.at(rb[0], w, 1.0)
     np.add.at(rb[1], w, ref[:, 0])
     np.add.at(rb[2], w, ref[:, 0] * fail)
+    _, rb[3], rb[4] = ostats.count_bins(seed, 0, w, ref[:, 0], fail, nb)
     assert np.array_equal(bins[0], rb[0])
-    assert np.abs(bins[1:] - rb[1:]).max() <= 1e-10 * n
+    assert np.abs(bins[1:3] - rb[1:3]).max() <= 1e-10 * n
+    # the counts take the same decision u < P_acc on both sides
+    assert np.array_equal(bins[3:], rb[3:])
+    assert bins[3].sum() > 0
+    # the likelihood-ratio intervals from the GPU's counts equal the oracle's
+    last = int(np.nonzero(rb[0])[0].max()) + 1
+    M = circ.info()["n_channels"]
+    pb = ostats.Problem(rb[0][:last], rb[3][:last], rb[4][:last], M, p)
+    for f in (msc.MSC_STAT_PACC, msc.MSC_STAT_PLE):
+        r = msc.lr_interval(bins[0][:last], bins[3][:last], bins[4][:last], M, p, f)
+        o = ostats.lr_interval(pb, f)
+        assert (r["estimate"], r["lo"], r["hi"], r["hi_trunc"]) == pytest.approx(
+            o, rel=1e-8, abs=1e-12)
 
 
 def test_run_batch_on_concurrent_contexts(ctx):

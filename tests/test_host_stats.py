@@ -1,0 +1,147 @@
+"""CPU tests of the library's likelihood statistics (msc_profile_loglik,
+msc_lr_interval, msc_ratio_credible, msc_loss_factor) through the C ABI:
+equal to the oracle's on random count sets, the paper's loss table, the
+coverage of the R = 100 interval measured by a parametric bootstrap as the
+error analysis does, and the argument errors.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import paper_2609_19116_amd as msc
+from oracle import estimators as est
+from oracle import stats as S
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _random_case(rng):
+    nb = int(rng.integers(1, 6))
+    n = rng.integers(5, 300, nb).astype(float)
+    k = np.array([rng.integers(0, x + 1) for x in n], dtype=float)
+    m = np.array([rng.integers(0, x + 1) if x > 0 else 0 for x in k], dtype=float)
+    M = int(nb + rng.integers(2, 50))
+    p = float(rng.uniform(0.001, 0.1))
+    d_e = int(rng.integers(0, 2))
+    if d_e:
+        m[0] = 0.0
+    if nb > 2 and rng.uniform() < 0.3:
+        n[1] = k[1] = m[1] = 0.0               # an unsampled bin
+    return n, k, m, M, p, d_e
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_lr_interval_equals_oracle(case):
+    rng = np.random.default_rng(100 + case)
+    n, k, m, M, p, d_e = _random_case(rng)
+    pb = S.Problem(n, k, m, M, p, d_e)
+    for f in (msc.MSC_STAT_PACC, msc.MSC_STAT_PLE):
+        o = S.lr_interval(pb, f)
+        r = msc.lr_interval(n, k, m, M, p, f, d_e=d_e)
+        got = (r["estimate"], r["lo"], r["hi"], r["hi_trunc"])
+        assert got == pytest.approx(o, rel=1e-8, abs=1e-12), (f, got, o)
+        assert r["trunc_bound"] == pytest.approx(pb.B, rel=1e-12, abs=1e-300)
+        assert r["n_unsampled"] == int((n == 0).sum())
+        assert r["n_bins_used"] == int((n > 0).sum())
+        th = 0.5 * (o[1] + o[2]) * 1.01
+        lo_t, hi_t = pb.theta_range(f)
+        if lo_t <= th <= hi_t:
+            assert msc.profile_loglik(n, k, m, M, p, f, th, d_e=d_e) == pytest.approx(
+                S.profile_loglik(pb, f, th), abs=1e-7)
+
+
+def test_unaccepted_and_unsampled_diagnostics():
+    n, k, m = [100, 0, 50, 40], [60, 0, 0, 3], [0, 0, 0, 1]
+    M, p, R = 30, 0.05, 100.0
+    r = msc.lr_interval(n, k, m, M, p, msc.MSC_STAT_PLE, R=R)
+    b = [est.binom_pmf(M, w, p) for w in range(4)]
+    # bin 2 was sampled (50 shots) and never accepted: worst case
+    # Bin_2 (1 - R^(-1/n_2)), about Bin_2 log(R) / n_2
+    assert r["unaccepted"] == pytest.approx(b[2] * (1 - R ** (-1 / 50)), rel=1e-12)
+    assert r["unsampled_mass"] == pytest.approx(b[1], rel=1e-12)
+    assert r["n_unsampled"] == 1
+
+
+def test_profile_is_zero_at_estimate_and_minus_inf_outside():
+    n, k, m = [200, 100], [150, 30], [0, 5]
+    r = msc.lr_interval(n, k, m, 20, 0.02, msc.MSC_STAT_PACC)
+    assert msc.profile_loglik(n, k, m, 20, 0.02, msc.MSC_STAT_PACC, r["estimate"]) == \
+        pytest.approx(0.0, abs=1e-9)
+    assert msc.profile_loglik(n, k, m, 20, 0.02, msc.MSC_STAT_PLE, 1.5) == -math.inf
+    assert msc.profile_loglik(n, k, m, 20, 0.02, msc.MSC_STAT_PACC, -0.1) == -math.inf
+    assert msc.profile_loglik(n, k, m, 20, 0.02, msc.MSC_STAT_PACC, r["lo"]) == \
+        pytest.approx(-math.log(100.0), abs=1e-6)
+
+
+def test_ratio_credible_equals_oracle():
+    n, k, m = [300, 200, 100], [250, 60, 10], [0, 3, 4]
+    M, p = 40, 0.02
+    pb = S.Problem(n, k, m, M, p, d_e=1)
+    o = S.ratio_credible(pb, 5000, 30, h=1e-2)
+    r = msc.ratio_credible(n, k, m, M, p, 5000, 30, h=1e-2, d_e=1)
+    assert r == pytest.approx(o, rel=1e-7)
+    lo, hi = msc.ratio_credible(n, k, m, M, p, 5000, 30, level=0.5, h=1e-2, d_e=1)
+    assert r[0] < lo < hi < r[1]
+
+
+def test_loss_factor_reproduces_the_paper_table():
+    g = json.load(open(os.path.join(GOLDEN, "loss_table.json")))
+    for row in g["rows"].values():
+        for pl, printed in zip(g["p_loss"], row["factor"]):
+            f = msc.loss_factor(row["M"], pl)
+            assert f == pytest.approx(est.loss_multiplier(row["M"], pl), rel=1e-12)
+            assert abs(f - printed) <= 0.005 + 1e-9
+
+
+def test_bootstrap_coverage_of_r100_interval():
+    # the error analysis's check: take fitted rates as the truth, redraw the
+    # counts with each n_w held, rerun the estimator, count the intervals
+    # that hold the truth; R = 100 is 99.76 % asymptotically
+    rng = np.random.default_rng(11)
+    M, p = 60, 0.03
+    n = np.array([400, 600, 600, 300], dtype=float)
+    a = np.array([0.95, 0.6, 0.3, 0.1])
+    e = np.array([0.0, 0.05, 0.2, 0.4])
+    b = np.array([est.binom_pmf(M, w, p) for w in range(4)])
+    truth = {msc.MSC_STAT_PACC: float(b @ a), msc.MSC_STAT_PLE: float(b @ (a * e) / (b @ a))}
+    reps = 1500
+    miss = {f: 0 for f in truth}
+    for _ in range(reps):
+        k = rng.binomial(n.astype(int), a).astype(float)
+        m = rng.binomial(k.astype(int), e).astype(float)
+        for f, t in truth.items():
+            r = msc.lr_interval(n, k, m, M, p, f)
+            miss[f] += not (r["lo"] <= t <= r["hi"])
+    for f in truth:
+        cov = 1 - miss[f] / reps
+        assert cov >= 0.993, (f, cov)          # expected misses: 3.6 of 1500
+
+
+@pytest.mark.parametrize("args", [
+    dict(n=[10], k=[11], m=[0]),               # k > n
+    dict(n=[10], k=[5], m=[6]),                # m > k
+    dict(n=[10.5], k=[5], m=[1]),              # not a count
+    dict(n=[10, 10], k=[5, 5], m=[1, 0], d_e=1),   # failure below d_e
+])
+def test_statistics_argument_errors(args):
+    d_e = args.pop("d_e", 0)
+    with pytest.raises(msc.MscError):
+        msc.lr_interval(args["n"], args["k"], args["m"], 10, 0.1, msc.MSC_STAT_PACC, d_e=d_e)
+
+
+def test_statistics_bad_options():
+    with pytest.raises(msc.MscError):
+        msc.lr_interval([10], [5], [1], 10, 0.1, 7)
+    with pytest.raises(msc.MscError):
+        msc.lr_interval([10], [5], [1], 10, 0.1, msc.MSC_STAT_PACC, R=1.0)
+    with pytest.raises(msc.MscError):
+        msc.lr_interval([0], [0], [0], 10, 0.1, msc.MSC_STAT_PACC)
+    with pytest.raises(msc.MscError):
+        msc.ratio_credible([10], [5], [0], 10, 0.1, 100, 3)       # T has no failure
+    with pytest.raises(msc.MscError):
+        msc.ratio_credible([10], [5], [1], 10, 0.1, 100, 300)     # s_err > s_acc
+    with pytest.raises(msc.MscError):
+        msc.loss_factor(10, 1.0)

@@ -16,13 +16,14 @@
  * Circuit text format (one op per line, '#' comments):
  *   QUBITS n | ORDER q0 q1 ... (qubit held by MPS site i) | SEED q |
  *   TARGET T|S | H S SDG T TDG X Y Z q | CX CZ CS CSDG a b | CCZ a b c |
- *   M q | R q | DEP1 q | DEP2 a b | DEP3 a b c | XERR q | TICK
+ *   M q | R q | DEP1 q | DEP2 a b | DEP3 a b c | XERR q | TICK | SEGMENT
  * CS/CSDG are controlled-S and controlled-S^dagger, CCZ the doubly
  * controlled Z: with T and T^dagger the diagonal non-Clifford gates of the
  * method (Sections 2 and 4.2).  Channels (DEP1, DEP2, DEP3, XERR) and
  * measurements are numbered in text order.
  * R is legal only as the first op on a qubit or when the last op on that
- * qubit was M.
+ * qubit was M.  SEGMENT starts a new segment of the circuit for the
+ * space-time accounting (no action on the state; see msc_segment).
  */
 #ifndef MSC_H
 #define MSC_H
@@ -64,6 +65,20 @@ enum msc_shot_status {
 
 typedef struct msc_ctx msc_ctx;
 typedef struct msc_circuit msc_circuit;
+
+/* One segment of a circuit (the ops between SEGMENT lines), for the
+   space-time accounting of Appendix "Space-time overhead": its volume is
+   n_qubits x depth.  n_qubits counts the qubits its gates, measurements and
+   resets act on; depth is the layer count of an as-soon-as-possible
+   schedule of those ops (noise channels are not layers).  A shot reaches
+   the segment with the product of its expected-outcome probabilities over
+   measurements 0 .. first_meas - 1 (0 once one has rejected it).         */
+typedef struct {
+    int32_t first_meas;   /* measurements before the segment                 */
+    int32_t n_qubits;
+    int32_t depth;
+    int32_t noisy;        /* 1 iff the segment holds a noise channel         */
+} msc_segment;
 
 typedef struct {
     int32_t n_qubits;
@@ -180,6 +195,15 @@ int msc_circuit_expected(const msc_circuit* c, uint8_t* out);
    fidelity is 1 (Appendix "Post-selection and logical error").  Returns
    MSC_E_NONDETERMINISTIC otherwise.  Required before msc_simulate.       */
 int msc_circuit_calibrate(msc_ctx* ctx, msc_circuit* c);
+/* Record of the calibration's noiseless run (host out): its bond peak,
+   two-site updates and algorithmic flops.  MSC_E_STATE before
+   calibration.                                                           */
+int msc_circuit_noiseless(const msc_circuit* c, msc_shot_result* out);
+/* The circuit's segments (host out, up to cap entries; *n_out = their
+   number, at least 1: a circuit without SEGMENT lines is one segment).
+   MSC_E_CAPACITY if cap is smaller.                                       */
+int msc_circuit_segments(const msc_circuit* c, int32_t cap, msc_segment* out,
+                         int32_t* n_out);
 void msc_circuit_free(msc_circuit* c);
 
 /* ---------------------------------------------------------------------- */
@@ -269,11 +293,18 @@ int msc_simulate(msc_ctx* ctx, const msc_circuit* c, const msc_sim_opts* opts,
    bin; screened shots count with P_acc = 0.  stats (host) is optional.  out (device, n_shots records) is
    optional: out[i] is the result of shot i (screened shots: all zero,
    rejected_at -1).  The fault buffer is sized for the largest weight the
-   Bin(M, p) table can draw; MSC_E_CAPACITY if that exceeds 2^28 faults.   */
+   Bin(M, p) table can draw; MSC_E_CAPACITY if that exceeds 2^28 faults.
+   surv_bins (host, n_bins * n_seg doubles with n_seg from
+   msc_circuit_segments) is optional; if given, the batch runs in
+   space-time mode: the offline screen is skipped (every shot is simulated
+   and stops at its first rejecting measurement, as a physical shot would)
+   and surv_bins[w * n_seg + s] receives the sum over the shots of weight w
+   of their probability of reaching segment s (fixed-order FP64 sums);
+   stats->n_survivors is then n_shots.                                      */
 int msc_run_batch(msc_ctx* ctx, const msc_circuit* c, const msc_sim_opts* opts,
                   uint64_t seed, uint64_t first_shot, int64_t n_shots, double p,
                   int32_t n_bins, double* bins, msc_batch_stats* stats,
-                  msc_shot_result* out);
+                  msc_shot_result* out, double* surv_bins);
 
 /* ---------------------------------------------------------------------- */
 /* Two-site contraction on MFMA (Section 3.1), standalone.                 */
@@ -302,6 +333,25 @@ int msc_twosite_contract(msc_ctx* ctx, int32_t precision, int32_t chi,
 int msc_reweight(const double* bin_n, const double* bin_acc,
                  const double* bin_fail, int32_t n_bins, int64_t M,
                  const double* p_grid, int32_t n_p, msc_estimate* out);
+
+/* ---------------------------------------------------------------------- */
+/* Qubit-order search (Section 3.1: the linear order drives the routing    */
+/* and the bond dimension; an automatic search is the paper's future work).*/
+
+/* Local search for the qubit -> site order of the circuit `text` (len
+   bytes) from `start` (host, n_qubits entries, order[site] = qubit; NULL:
+   the text's ORDER line, else identity).  Cost of an order = algorithmic
+   flops of its noiseless run (msc_circuit_noiseless after calibration on
+   ctx's GPU; +inf if that run exceeds the bond cap).  Each of the `budget`
+   evaluations after the first tries one move drawn from a SplitMix64
+   stream keyed by `seed`: exchange two sites, reverse a run of sites, or
+   move one site (probability 1/3 each); a move is kept iff the cost falls.
+   order_out (host, n_qubits): the best order; cost_out (host, 2 doubles):
+   the start order's cost and the best cost.  Calibration errors other than
+   the bond cap are returned.                                              */
+int msc_order_search(msc_ctx* ctx, const char* text, size_t len,
+                     const int32_t* start, uint64_t seed, int32_t budget,
+                     int32_t* order_out, double* cost_out);
 
 /* ---------------------------------------------------------------------- */
 /* Likelihood statistics (Appendix "Error analysis of the subset-sampling  */
@@ -362,6 +412,18 @@ int msc_ratio_credible(const double* bin_n, const double* bin_acc,
                        const double* bin_err, int32_t n_bins, int64_t M,
                        double p, int32_t d_e, double s_acc, double s_err,
                        double level, double h, double* lo, double* hi);
+
+/* Expected space-time volume (Appendix "Space-time overhead") at physical
+   error rate p from msc_run_batch's space-time mode: bin_n (host, n_bins)
+   shots per weight, surv_bins (host, n_bins * n_seg) their summed reach
+   probabilities, segs (host, n_seg) the circuit's segments.  reach (host,
+   n_seg) receives sum_w Bin_w(p) surv_bins[w][s] / n_w over the sampled
+   bins; volume (host, 2 doubles) the expected volume summed over the noisy
+   segments, n_qubits x depth x reach, and the same plus B times their
+   total volume (B = sum_{w >= n_bins} Bin_w(p), the truncation bound).    */
+int msc_expected_volume(const double* bin_n, const double* surv_bins,
+                        int32_t n_bins, const msc_segment* segs, int32_t n_seg,
+                        int64_t M, double p, double* reach, double* volume);
 
 /* Multiplicative factor on the expected number of attempts when each of M
    channels carries an independent, detected loss of probability p_loss:

@@ -3,12 +3,14 @@
 One op per line; '#' starts a comment.  Header lines: QUBITS n, ORDER
 q0 q1 ... (qubit held by each MPS site), SEED q, TARGET T|S.  Ops:
 H S SDG T TDG X Y Z q | CX CZ CS CSDG a b | CCZ a b c | M q | R q | DEP1 q |
-DEP2 a b | DEP3 a b c | XERR q | TICK.  Channels (DEP1, DEP2, DEP3, XERR)
+DEP2 a b | DEP3 a b c | XERR q | TICK | SEGMENT.  Channels (DEP1, DEP2, DEP3, XERR)
 are numbered in text order, as are measurements.  CS/CSDG are controlled-S
 and controlled-S^dagger, CCZ the doubly controlled Z: the diagonal
 non-Clifford gates of the paper's checks (Section 2, Section 4.2).  The
 noise semantics follow Section 4 (uniform depolarising, any of the 4^k-1
-non-identity Paulis with probability p/(4^k-1)).
+non-identity Paulis with probability p/(4^k-1)).  SEGMENT starts a new
+segment of the circuit for the space-time accounting (Appendix
+"Space-time overhead"); it does not act on the state.
 """
 from __future__ import annotations
 
@@ -30,6 +32,7 @@ class OCircuit:
     n_meas: int
     channel_arity: list = field(default_factory=list)   # 1, 2 or 3 per channel
     channel_kind: list = field(default_factory=list)    # DEP1|DEP2|DEP3|XERR
+    segments: list = field(default_factory=lambda: [0])  # first op index of each
 
 
 def parse(text: str) -> OCircuit:
@@ -45,6 +48,7 @@ def parse(text: str) -> OCircuit:
     nm = 0
     arity = []
     kinds = []
+    segs = [0]
     for raw in text.splitlines():
         line = raw.split("#", 1)[0].strip()
         if not line:
@@ -62,6 +66,9 @@ def parse(text: str) -> OCircuit:
             target = args[0].upper()
         elif op == "TICK":
             continue
+        elif op == "SEGMENT":
+            if len(ops) != segs[-1]:
+                segs.append(len(ops))
         elif op in ONE_Q:
             ops.append(("g1", op, int(args[0])))
         elif op in TWO_Q:
@@ -104,4 +111,4 @@ def parse(text: str) -> OCircuit:
         raise ValueError("ORDER is not a permutation")
     return OCircuit(n=n, ops=ops, order=order, seed=seed, target=target,
                     n_channels=nch, n_meas=nm, channel_arity=arity,
-                    channel_kind=kinds)
+                    channel_kind=kinds, segments=segs)

@@ -13,13 +13,13 @@ import ctypes as C
 import numpy as np
 
 from ._lib import (BatchStats, MSC_BF16X3, MSC_FP32, MSC_FP64, MSC_STAT_PACC,  # noqa: F401
-                   MSC_STAT_PLE, SHOT_CHI_CAP, SHOT_DONE, SHOT_DTYPE, SHOT_NOCONV,
+                   MSC_STAT_PLE, SEGMENT_DTYPE, SHOT_CHI_CAP, SHOT_DONE, SHOT_DTYPE, SHOT_NOCONV,
                    SHOT_REJECTED, CircuitInfo, Estimate, Interval, MscError, SimOpts, _check,
                    _ptr, lib)
 
 __all__ = ["Ctx", "Circuit", "sample_faults", "sample_faults_device", "prescreen", "simulate",
            "run_batch", "reweight", "profile_loglik", "lr_interval", "ratio_credible",
-           "loss_factor", "twosite_contract", "prescreen_tables", "version", "MscError",
+           "loss_factor", "expected_volume", "order_search", "twosite_contract", "prescreen_tables", "version", "MscError",
            "MSC_FP64", "MSC_FP32", "MSC_BF16X3", "MSC_STAT_PACC", "MSC_STAT_PLE", "SHOT_DTYPE"]
 
 
@@ -83,6 +83,33 @@ class Circuit:
 
     def calibrate(self, ctx: Ctx) -> None:
         _check(lib().msc_circuit_calibrate(ctx.h, self.h))
+
+    def segments(self) -> np.ndarray:
+        """The circuit's segments (SEGMENT_DTYPE records)."""
+        n = C.c_int32()
+        lib().msc_circuit_segments(self.h, 0, None, C.byref(n))
+        out = np.zeros(n.value, dtype=SEGMENT_DTYPE)
+        _check(lib().msc_circuit_segments(self.h, n.value, _ptr(out), C.byref(n)))
+        return out
+
+    def noiseless(self) -> dict:
+        """The calibration's noiseless-run record (bond peak, updates, flops)."""
+        r = np.zeros(1, dtype=SHOT_DTYPE)
+        _check(lib().msc_circuit_noiseless(self.h, _ptr(r)))
+        return {k: r[k][0].item() for k in SHOT_DTYPE.names}
+
+
+def order_search(ctx: Ctx, text: str, seed: int, budget: int, start=None):
+    """Local search for the qubit -> site order; returns (order int32 [n],
+    start cost, best cost) with cost = flops of the noiseless run."""
+    b = text.encode()
+    st = None if start is None else np.ascontiguousarray(start, dtype=np.int32)
+    n = Circuit(text).info()["n_qubits"]
+    out = np.zeros(n, dtype=np.int32)
+    cost = np.zeros(2, dtype=np.float64)
+    _check(lib().msc_order_search(ctx.h, b, len(b), _ptr(st), seed, budget, _ptr(out),
+                                  _ptr(cost)))
+    return out, float(cost[0]), float(cost[1])
 
 
 def sample_faults(circ: Circuit, seed: int, first_shot: int, n_shots: int,
@@ -183,11 +210,13 @@ def simulate(ctx: Ctx, circ: Circuit, off, chan, pauli, shot_idx=None, precision
 def run_batch(ctx: Ctx, circ: Circuit, seed: int, first_shot: int, n_shots: int, p: float,
               n_bins: int = 65, precision=MSC_FP32, chi_max: int = 256, tau_trunc: float = 0.0,
               tau_rej: float = 1e-6, tau_fail: float = 1e-4, n_slots: int = 0,
-              lds_width: int = 0, prefix: bool = True, out=None):
+              lds_width: int = 0, prefix: bool = True, out=None, space_time: bool = False):
     """One batch of the whole path (sampling, screen, shots, bin sums) on the
     context's stream with one synchronisation.  Returns (bins float64
     [5, n_bins]: shots, sum P_acc, sum P_acc * fail, accepted count, wrong
-    count per weight; stats dict).
+    count per weight; stats dict).  With ``space_time`` the offline screen
+    is skipped and stats["surv_bins"] holds float64 [n_bins, n_seg]: per
+    weight the summed probabilities of reaching each segment.
     ``out`` (optional uint8 device tensor of n_shots records) receives the
     per-shot results, indexed by shot."""
     o = SimOpts(precision, chi_max, tau_trunc, tau_rej, tau_fail, n_slots, lds_width,
@@ -196,9 +225,14 @@ def run_batch(ctx: Ctx, circ: Circuit, seed: int, first_shot: int, n_shots: int,
     st = BatchStats()
     if out is not None:
         assert out.numel() >= n_shots * SHOT_DTYPE.itemsize
+    surv = None
+    if space_time:
+        surv = np.zeros(n_bins * len(circ.segments()), dtype=np.float64)
     _check(lib().msc_run_batch(ctx.h, circ.h, C.byref(o), seed, first_shot, n_shots, p, n_bins,
-                               _ptr(bins), C.byref(st), _ptr(out)))
+                               _ptr(bins), C.byref(st), _ptr(out), _ptr(surv)))
     stats = {f: getattr(st, f) for f, _ in BatchStats._fields_}
+    if space_time:
+        stats["surv_bins"] = surv.reshape(n_bins, -1)
     return bins.reshape(5, n_bins), stats
 
 
@@ -253,6 +287,19 @@ def ratio_credible(bin_n, bin_acc, bin_err, M: int, p: float, s_acc: float, s_er
     _check(lib().msc_ratio_credible(_ptr(n), _ptr(k), _ptr(m), len(n), M, p, d_e, s_acc, s_err,
                                     level, h, C.byref(lo), C.byref(hi)))
     return lo.value, hi.value
+
+
+def expected_volume(bin_n, surv_bins, segs, M: int, p: float):
+    """(reach probability per segment, expected volume of the noisy
+    segments, the same plus the truncation bound) at error rate p."""
+    n = np.ascontiguousarray(bin_n, dtype=np.float64)
+    sv = np.ascontiguousarray(surv_bins, dtype=np.float64)
+    sg = np.ascontiguousarray(segs, dtype=SEGMENT_DTYPE)
+    reach = np.zeros(len(sg))
+    vol = np.zeros(2)
+    _check(lib().msc_expected_volume(_ptr(n), _ptr(sv), len(n), _ptr(sg), len(sg), M, p,
+                                     _ptr(reach), _ptr(vol)))
+    return reach, float(vol[0]), float(vol[1])
 
 
 def loss_factor(M: int, p_loss: float) -> float:

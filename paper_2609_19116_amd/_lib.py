@@ -83,6 +83,9 @@ class Interval(C.Structure):
 
 MSC_STAT_PACC, MSC_STAT_PLE = 0, 1
 
+SEGMENT_DTYPE = np.dtype([("first_meas", "<i4"), ("n_qubits", "<i4"), ("depth", "<i4"),
+                          ("noisy", "<i4")])
+
 # every exported symbol of include/msc.h with its signature
 _P = C.c_void_p
 _SIGS = {
@@ -95,6 +98,10 @@ _SIGS = {
     "msc_circuit_get_info": (C.c_int, [_P, C.POINTER(CircuitInfo)]),
     "msc_circuit_expected": (C.c_int, [_P, _P]),
     "msc_circuit_calibrate": (C.c_int, [_P, _P]),
+    "msc_circuit_noiseless": (C.c_int, [_P, _P]),
+    "msc_circuit_segments": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_int32)]),
+    "msc_order_search": (C.c_int, [_P, C.c_char_p, C.c_size_t, _P, C.c_uint64, C.c_int32, _P,
+                                   _P]),
     "msc_circuit_free": (None, [_P]),
     "msc_sample_faults": (C.c_int, [_P, C.c_uint64, C.c_uint64, C.c_int64, _P, C.c_double,
                                     _P, _P, _P, C.c_int64, C.POINTER(C.c_int64)]),
@@ -106,7 +113,7 @@ _SIGS = {
     "msc_simulate": (C.c_int, [_P, _P, C.POINTER(SimOpts), C.c_int64, _P, _P, _P, _P,
                                C.c_int64, _P]),
     "msc_run_batch": (C.c_int, [_P, _P, C.POINTER(SimOpts), C.c_uint64, C.c_uint64, C.c_int64,
-                                C.c_double, C.c_int32, _P, C.POINTER(BatchStats), _P]),
+                                C.c_double, C.c_int32, _P, C.POINTER(BatchStats), _P, _P]),
     "msc_twosite_contract": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, _P]),
     "msc_reweight": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, _P, C.c_int32, _P]),
     "msc_profile_loglik": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, C.c_double, C.c_int32,
@@ -117,6 +124,8 @@ _SIGS = {
                                      C.c_double, C.c_double, C.c_double, C.c_double,
                                      C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "msc_loss_factor": (C.c_int, [C.c_int64, C.c_double, C.POINTER(C.c_double)]),
+    "msc_expected_volume": (C.c_int, [_P, _P, C.c_int32, _P, C.c_int32, C.c_int64, C.c_double,
+                                      _P, _P]),
 }
 
 _lib = None

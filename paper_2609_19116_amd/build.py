@@ -24,6 +24,7 @@ SOURCES = [
     CSRC / "host" / "prescreen_compile.cpp",
     CSRC / "host" / "sampler.cpp",
     CSRC / "host" / "stats.cpp",
+    CSRC / "host" / "order.cpp",
     CSRC / "host" / "capi.cpp",
     CSRC / "kernels" / "mps.hip",
     CSRC / "kernels" / "prescreen.hip",

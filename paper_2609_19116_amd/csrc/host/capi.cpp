@@ -157,6 +157,16 @@ extern "C" int msc_circuit_get_info(const msc_circuit* c, msc_circuit_info* o) {
     return MSC_OK;
 }
 
+extern "C" int msc_circuit_segments(const msc_circuit* c, int32_t cap, msc_segment* out,
+                                    int32_t* n_out) {
+    if (!c || !n_out || (cap > 0 && !out)) return set_error(MSC_E_INVALID, "null argument");
+    const int32_t n = static_cast<int32_t>(c->segs.size());
+    *n_out = n;
+    if (cap < n) return set_error(MSC_E_CAPACITY, "cap below the number of segments");
+    std::copy(c->segs.begin(), c->segs.end(), out);
+    return MSC_OK;
+}
+
 extern "C" int msc_circuit_expected(const msc_circuit* c, uint8_t* out) {
     if (!c || !out) return set_error(MSC_E_INVALID, "null argument");
     std::copy(c->expected.begin(), c->expected.end(), out);
@@ -166,7 +176,7 @@ extern "C" int msc_circuit_expected(const msc_circuit* c, uint8_t* out) {
 static void free_prefix(PrefixCk& pk) {
     if (pk.dev >= 0) {
         (void)hipSetDevice(pk.dev);
-        for (void** p : {&pk.d_op, &pk.d_avail, &pk.d_off, &pk.d_hdr, &pk.d_data}) {
+        for (void** p : {&pk.d_op, &pk.d_avail, &pk.d_off, &pk.d_hdr, &pk.d_data, &pk.d_pm}) {
             if (*p) (void)hipFree(*p);
             *p = nullptr;
         }
@@ -178,7 +188,8 @@ static void free_device(msc_circuit* c) {
     free_prefix(c->prefix);
     if (c->dev < 0) return;
     (void)hipSetDevice(c->dev);
-    for (void** p : {&c->d_ops, &c->d_g1, &c->d_g4, &c->d_sig, &c->d_expected, &c->d_kind}) {
+    for (void** p : {&c->d_ops, &c->d_g1, &c->d_g4, &c->d_sig, &c->d_expected, &c->d_kind,
+                     &c->d_segm}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
@@ -212,6 +223,9 @@ static int upload(msc_ctx* ctx, msc_circuit* c) {
     if ((rc = put(&c->d_expected, c->expected.data(), c->expected.size()))) return rc;
     std::vector<uint8_t> kind(c->chan_kind.begin(), c->chan_kind.end());
     if ((rc = put(&c->d_kind, kind.data(), kind.size()))) return rc;
+    std::vector<int32_t> segm;
+    for (const msc_segment& g : c->segs) segm.push_back(g.first_meas);
+    if ((rc = put(&c->d_segm, segm.data(), segm.size() * sizeof(int32_t)))) return rc;
     return MSC_OK;
 }
 
@@ -266,7 +280,7 @@ static int enqueue_shots(msc_ctx* ctx, const msc_circuit* c, int precision, int 
                          int64_t n, int64_t n_csr, const int64_t* off, const int32_t* chan,
                          const uint8_t* pauli, const int64_t* shot_idx, msc_shot_result* out,
                          int calibrate, double* cal_p, uint8_t* cal_e, int ck_mode,
-                         const PrefixCk* pk, const int64_t* n_dev) {
+                         const PrefixCk* pk, const int64_t* n_dev, double* surv = nullptr) {
     Layout L = make_layout(c->n, chi_max);
     const bool small = lds_width == 32;
     if (n_slots <= 0) n_slots = ctx->n_cu * mps_blocks_per_cu(precision, small);
@@ -339,6 +353,12 @@ static int enqueue_shots(msc_ctx* ctx, const msc_circuit* c, int precision, int 
         a.ck_hdr = static_cast<CkHdr*>(pk->d_hdr);
         a.ck_data = pk->d_data;
         a.ck_cap = pk->cap;
+        a.ck_pm = static_cast<double*>(pk->d_pm);
+    }
+    if (surv) {
+        a.surv = surv;
+        a.seg_meas = static_cast<const int32_t*>(c->d_segm);
+        a.n_seg = static_cast<int32_t>(c->segs.size());
     }
     MSC_HIP(launch_order(n, n_dev, off, shot_idx, n_csr, chan,
                          a.ck_mode == 2 ? c->n_channels : 0, static_cast<int64_t*>(dperm),
@@ -393,6 +413,7 @@ extern "C" int msc_circuit_calibrate(msc_ctx* ctx, msc_circuit* c) {
     MSC_HIP(hipMemcpy(p.data(), dp, nm * sizeof(double), hipMemcpyDeviceToHost));
     MSC_HIP(hipMemcpy(e.data(), de, nm, hipMemcpyDeviceToHost));
     MSC_HIP(hipMemcpy(&res, dout, sizeof(res), hipMemcpyDeviceToHost));
+    c->noiseless = res;
     for (int m = 0; m < c->n_meas; ++m) {
         if (!(std::fabs(p[m] - 1.0) <= 1e-10))
             return set_error(MSC_E_NONDETERMINISTIC, "measurement " + std::to_string(m) +
@@ -455,6 +476,8 @@ static int ensure_prefix(msc_ctx* ctx, msc_circuit* c, int precision, int chi_ma
     if ((rc = dmalloc(&pk.d_off, pk.n_ck * sizeof(int64_t)))) return rc;
     if ((rc = dmalloc(&pk.d_hdr, pk.n_ck * sizeof(CkHdr)))) return rc;
     if ((rc = dmalloc(&pk.d_data, static_cast<size_t>(pk.cap) * tsize))) return rc;
+    if ((rc = dmalloc(&pk.d_pm, static_cast<size_t>(std::max(1, c->n_meas)) * sizeof(double))))
+        return rc;
     const int32_t zero = 0;
     MSC_HIP(hipMemcpy(pk.d_op, ck_op.data(), pk.n_ck * sizeof(int32_t), hipMemcpyHostToDevice));
     MSC_HIP(hipMemcpy(pk.d_avail, &zero, sizeof(zero), hipMemcpyHostToDevice));
@@ -623,7 +646,7 @@ extern "C" int msc_sample_faults_device(msc_ctx* ctx, const msc_circuit* c, uint
 extern "C" int msc_run_batch(msc_ctx* ctx, const msc_circuit* c, const msc_sim_opts* opts,
                              uint64_t seed, uint64_t first_shot, int64_t n_shots, double p,
                              int32_t n_bins, double* bins, msc_batch_stats* stats,
-                             msc_shot_result* out) {
+                             msc_shot_result* out, double* surv_bins) {
     if (!ctx || !c || !opts || !bins || n_shots < 0) return set_error(MSC_E_INVALID, "null argument");
     if (n_bins < 1 || n_bins > kMaxBins) return set_error(MSC_E_INVALID, "n_bins must be in [1, 1024]");
     if (!(p >= 0.0 && p <= 1.0)) return set_error(MSC_E_INVALID, "p outside [0,1]");
@@ -648,7 +671,11 @@ extern "C" int msc_run_batch(msc_ctx* ctx, const msc_circuit* c, const msc_sim_o
                                             opts->chi_max, tau, tau_rej, tau_fail, lds_width)))
         return rc;
     // host-mapped block for the reduction: bins, then the totals
-    const size_t hbytes = kBinRows * static_cast<size_t>(n_bins) * sizeof(double) + sizeof(BatchTotals);
+    const bool space_time = surv_bins != nullptr;
+    const int n_seg = space_time ? static_cast<int>(c->segs.size()) : 0;
+    const size_t hbytes = (kBinRows * static_cast<size_t>(n_bins) +
+                           static_cast<size_t>(n_bins) * n_seg) * sizeof(double) +
+                          sizeof(BatchTotals);
     if (ctx->hmap_bytes < hbytes) {
         if (ctx->hmap) (void)hipHostFree(ctx->hmap);
         ctx->hmap = nullptr;
@@ -674,15 +701,21 @@ extern "C" int msc_run_batch(msc_ctx* ctx, const msc_circuit* c, const msc_sim_o
     if ((rc = ctx_buf(ctx, "b_res", std::max<int64_t>(1, n_shots) * sizeof(msc_shot_result), &dres))) return rc;
     if ((rc = ctx_buf(ctx, "b_tmp_s", nts * sizeof(int64_t), &dts))) return rc;
     if ((rc = ctx_buf(ctx, "b_tmp_p", std::max<int64_t>(2, ntp) * sizeof(int64_t), &dtp))) return rc;
+    void* dsurv = nullptr;
+    if (space_time &&
+        (rc = ctx_buf(ctx, "b_surv", std::max<int64_t>(1, n_shots * n_seg) * sizeof(double), &dsurv)))
+        return rc;
     int64_t* offp = static_cast<int64_t*>(doff);
     int64_t* idxp = static_cast<int64_t*>(didx);
     int64_t* nsurv = static_cast<int64_t*>(dtp) + (ntp - 1);   // the screen's total
     int64_t* nnz = static_cast<int64_t*>(dts) + (nts - 1);     // the sampler's total
     double* hbins = static_cast<double*>(ctx->hmap_dev);
     BatchTotals* htot = reinterpret_cast<BatchTotals*>(hbins + kBinRows * static_cast<size_t>(n_bins));
+    double* hsurv = reinterpret_cast<double*>(htot + 1);
     msc_shot_result* res = static_cast<msc_shot_result*>(dres);
     if (n_shots == 0) {
         for (int32_t b = 0; b < kBinRows * n_bins; ++b) bins[b] = 0.0;
+        for (int32_t b = 0; b < n_bins * n_seg; ++b) surv_bins[b] = 0.0;
         if (stats) *stats = msc_batch_stats{};
         return MSC_OK;
     }
@@ -692,25 +725,34 @@ extern "C" int msc_run_batch(msc_ctx* ctx, const msc_circuit* c, const msc_sim_o
                            static_cast<int32_t*>(dchan), static_cast<uint8_t*>(dpa),
                            static_cast<int64_t*>(dts), nts, ctx->stream));
     MSC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
-    MSC_HIP(launch_prescreen(c->words, c->n_channels, n_shots, offp, static_cast<int32_t*>(dchan),
-                             static_cast<uint8_t*>(dpa), static_cast<const uint64_t*>(c->d_sig),
-                             static_cast<uint64_t*>(dbits), idxp, static_cast<int64_t*>(dtp), ntp,
-                             ctx->stream));
+    if (space_time) {
+        // every shot runs to its first rejecting measurement
+        MSC_HIP(launch_identity(n_shots, idxp, nsurv, ctx->stream));
+    } else {
+        MSC_HIP(launch_prescreen(c->words, c->n_channels, n_shots, offp,
+                                 static_cast<int32_t*>(dchan), static_cast<uint8_t*>(dpa),
+                                 static_cast<const uint64_t*>(c->d_sig),
+                                 static_cast<uint64_t*>(dbits), idxp, static_cast<int64_t*>(dtp),
+                                 ntp, ctx->stream));
+    }
     MSC_HIP(hipEventRecord(ctx->ev2, ctx->stream));
     rc = enqueue_shots(ctx, c, opts->precision, opts->chi_max, tau, tau_rej, tau_fail,
                        opts->n_slots, lds_width, n_shots, n_shots, offp,
                        static_cast<int32_t*>(dchan), static_cast<uint8_t*>(dpa), idxp, res, 0,
                        nullptr, nullptr, opts->prefix ? 2 : 0, opts->prefix ? &c->prefix : nullptr,
-                       nsurv);
+                       nsurv, static_cast<double*>(dsurv));
     if (rc) return rc;
     MSC_HIP(hipEventRecord(ctx->ev3, ctx->stream));
     MSC_HIP(launch_batch_reduce(n_shots, seed, first_shot, offp, idxp, nsurv, res, n_bins, nnz,
-                                hbins, htot, ctx->stream));
+                                hbins, htot, static_cast<const double*>(dsurv), n_seg, hsurv,
+                                ctx->stream));
     if (out) MSC_HIP(launch_scatter_results(n_shots, nsurv, idxp, res, out, ctx->stream));
     MSC_HIP(hipStreamSynchronize(ctx->stream));
     const double* hb = static_cast<const double*>(ctx->hmap);
     for (int32_t b = 0; b < kBinRows * n_bins; ++b) bins[b] = hb[b];
     const BatchTotals* ht = reinterpret_cast<const BatchTotals*>(hb + kBinRows * static_cast<size_t>(n_bins));
+    const double* hs = reinterpret_cast<const double*>(ht + 1);
+    for (int32_t b = 0; b < n_bins * n_seg; ++b) surv_bins[b] = hs[b];
     float t01 = 0.f, t12 = 0.f, t23 = 0.f;
     MSC_HIP(hipEventElapsedTime(&t01, ctx->ev0, ctx->ev1));
     MSC_HIP(hipEventElapsedTime(&t12, ctx->ev1, ctx->ev2));

@@ -76,6 +76,7 @@ int parse_circuit(const char* text, size_t len, msc_circuit* c) {
     std::vector<int> order;
     c->n_meas = 0;
     c->n_channels = 0;
+    c->seg_ir.assign(1, 0);
     auto perr = [&](const std::string& msg) {
         return set_error(MSC_E_PARSE, "line " + std::to_string(lineno) + ": " + msg);
     };
@@ -116,6 +117,10 @@ int parse_circuit(const char* text, size_t len, msc_circuit* c) {
             c->target = tok[1][0];
         } else if (op == "TICK") {
             continue;
+        } else if (op == "SEGMENT") {
+            if (!need(0)) return perr("SEGMENT takes no operand");
+            if (c->seg_ir.back() != static_cast<int32_t>(c->ir.size()))
+                c->seg_ir.push_back(static_cast<int32_t>(c->ir.size()));
         } else {
             IrOp o{};
             o.b = -1;
@@ -206,7 +211,49 @@ int parse_circuit(const char* text, size_t len, msc_circuit* c) {
         c->chan_kind.push_back(o.g);
     }
     c->expected.assign(c->n_meas, 0);
+    segment_table(c);
     return MSC_OK;
+}
+
+// Segments for the space-time accounting (Appendix "Space-time overhead"):
+// a segment's volume is the qubits its gates, measurements and resets use
+// times its depth, the layer count of an as-soon-as-possible schedule of
+// those ops (noise channels are not layers); a shot reaches the segment
+// with the product of its outcome probabilities over the first_meas
+// measurements before it.
+void segment_table(msc_circuit* c) {
+    c->segs.clear();
+    const int ns = static_cast<int>(c->seg_ir.size());
+    int meas = 0;
+    for (int s = 0; s < ns; ++s) {
+        const size_t lo = static_cast<size_t>(c->seg_ir[s]);
+        const size_t hi = s + 1 < ns ? static_cast<size_t>(c->seg_ir[s + 1]) : c->ir.size();
+        msc_segment g{};
+        g.first_meas = meas;
+        std::vector<int> layer(c->n, 0);
+        std::vector<char> used(c->n, 0);
+        for (size_t i = lo; i < hi; ++i) {
+            const IrOp& o = c->ir[i];
+            if (o.kind == IR_CH) {
+                g.noisy = 1;
+                continue;
+            }
+            const int qs[3] = {o.a, o.b, o.c};
+            int t = 0;
+            for (int q : qs)
+                if (q >= 0) t = std::max(t, layer[q]);
+            ++t;
+            for (int q : qs)
+                if (q >= 0) {
+                    layer[q] = t;
+                    used[q] = 1;
+                }
+            g.depth = std::max(g.depth, t);
+            if (o.kind == IR_M) ++meas;
+        }
+        for (char u : used) g.n_qubits += u;
+        c->segs.push_back(g);
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -354,3 +354,31 @@ extern "C" int msc_loss_factor(int64_t M, double p_loss, double* out) {
     *out = std::exp(-static_cast<double>(M) * std::log1p(-p_loss));
     return MSC_OK;
 }
+
+extern "C" int msc_expected_volume(const double* bin_n, const double* surv_bins, int32_t n_bins,
+                                   const msc_segment* segs, int32_t n_seg, int64_t M, double p,
+                                   double* reach, double* volume) {
+    if (!bin_n || !surv_bins || !segs || !reach || !volume || n_bins < 1 || n_seg < 1 || M < 0)
+        return set_error(MSC_E_INVALID, "bad expected-volume arguments");
+    if (n_bins > M + 1) return set_error(MSC_E_INVALID, "more bins than M+1");
+    if (!(p >= 0.0 && p <= 1.0)) return set_error(MSC_E_INVALID, "p outside [0,1]");
+    for (int32_t s = 0; s < n_seg; ++s) reach[s] = 0.0;
+    for (int32_t w = 0; w < n_bins; ++w) {
+        if (!(bin_n[w] > 0.0)) continue;
+        const double b = std::exp(log_bin(M, w, p));
+        for (int32_t s = 0; s < n_seg; ++s)
+            reach[s] += b * surv_bins[static_cast<size_t>(w) * n_seg + s] / bin_n[w];
+    }
+    double B = 0.0;
+    for (int64_t w = M; w >= n_bins; --w) B += std::exp(log_bin(M, w, p));
+    double vol = 0.0, vmax = 0.0;
+    for (int32_t s = 0; s < n_seg; ++s) {
+        if (!segs[s].noisy) continue;
+        const double v = static_cast<double>(segs[s].n_qubits) * segs[s].depth;
+        vol += v * reach[s];
+        vmax += v;
+    }
+    volume[0] = vol;
+    volume[1] = vol + B * vmax;
+    return MSC_OK;
+}

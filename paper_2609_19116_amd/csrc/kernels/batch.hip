@@ -57,7 +57,9 @@ __global__ __launch_bounds__(RT) void batch_reduce_kernel(int64_t n, uint64_t se
                                                           const msc_shot_result* __restrict__ res,
                                                           int nb, const int64_t* __restrict__ nnz,
                                                           double* __restrict__ bins,
-                                                          BatchTotals* __restrict__ tot) {
+                                                          BatchTotals* __restrict__ tot,
+                                                          const double* __restrict__ surv,
+                                                          int n_seg, double* __restrict__ sbins) {
     __shared__ int s_cnt[kMaxBins];
     __shared__ int s_scnt[kMaxBins];
     __shared__ int s_kacc[kMaxBins];
@@ -109,8 +111,17 @@ __global__ __launch_bounds__(RT) void batch_reduce_kernel(int64_t n, uint64_t se
             if (tid == 0) {
                 bins[nb + b] = 0.0;
                 bins[2 * nb + b] = 0.0;
+                for (int g = 0; g < n_seg; ++g) sbins[b * n_seg + g] = 0.0;
             }
             continue;
+        }
+        // reach probabilities of the segments (space-time mode)
+        for (int g = 0; g < n_seg; ++g) {
+            double r = 0.0;
+            for (int64_t s = tid; s < ns; s += RT)
+                if (weight(idx[s]) == b) r += surv[s * n_seg + g];
+            r = block_sum_fixed(r, s_red);
+            if (tid == 0) sbins[b * n_seg + g] = r;
         }
         double a = 0.0, e = 0.0;
         for (int64_t s = tid; s < ns; s += RT) {
@@ -143,6 +154,12 @@ __global__ __launch_bounds__(RT) void batch_reduce_kernel(int64_t n, uint64_t se
     }
 }
 
+__global__ __launch_bounds__(RT) void identity_kernel(int64_t n, int64_t* idx, int64_t* count) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * RT + threadIdx.x;
+    if (i < n) idx[i] = i;
+    if (i == 0) *count = n;
+}
+
 // zero records (rejected_at -1) for every shot of a shot-indexed output
 __global__ __launch_bounds__(RT) void fill_results_kernel(int64_t n, msc_shot_result* out) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * RT + threadIdx.x;
@@ -168,10 +185,18 @@ __global__ __launch_bounds__(RT) void scatter_results_kernel(int64_t n, const in
 hipError_t launch_batch_reduce(int64_t n, uint64_t seed, uint64_t first, const int64_t* off,
                                const int64_t* idx, const int64_t* n_surv,
                                const msc_shot_result* res, int nb, const int64_t* nnz,
-                               double* bins, BatchTotals* tot, hipStream_t s) {
-    if (nb < 1 || nb > kMaxBins) return hipErrorInvalidValue;
+                               double* bins, BatchTotals* tot, const double* surv, int n_seg,
+                               double* sbins, hipStream_t s) {
+    if (nb < 1 || nb > kMaxBins || n_seg < 0 || (n_seg > 0 && (!surv || !sbins)))
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(batch_reduce_kernel, dim3(1), dim3(RT), 0, s, n, seed, first, off, idx,
-                       n_surv, res, nb, nnz, bins, tot);
+                       n_surv, res, nb, nnz, bins, tot, surv, n_seg, sbins);
+    return hipGetLastError();
+}
+
+hipError_t launch_identity(int64_t n, int64_t* idx, int64_t* count, hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>(n > 0 ? (n + RT - 1) / RT : 1));
+    hipLaunchKernelGGL(identity_kernel, grid, dim3(RT), 0, s, n, idx, count);
     return hipGetLastError();
 }
 

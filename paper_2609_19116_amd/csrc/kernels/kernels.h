@@ -18,6 +18,7 @@ constexpr int kMaxChiKernel = 256; // bond cap handled by the shot kernel
 struct CkHdr {
     double p_acc, disc;
     int32_t chi_peak, status;
+    int32_t meas_done, pad;    // measurements before the checkpoint's op
     int32_t chi[kMaxSites + 1];
     int32_t laste[kMaxSites];
 };
@@ -65,6 +66,13 @@ struct MpsArgs {
     CkHdr* ck_hdr;             // [n_ck]
     void* ck_data;             // ck_cap elements of T
     int64_t ck_cap;
+    double* ck_pm;             // [n_meas] noiseless running P_acc before each
+                               // measurement (written when recording)
+    // optional reach probabilities: surv[out index * n_seg + s] = P_acc
+    // before measurement seg_meas[s] (0 after a rejection)
+    double* surv;
+    const int32_t* seg_meas;
+    int32_t n_seg;
 };
 
 // precision: MSC_FP64 or MSC_FP32; small: use the 32-wide LDS variant
@@ -100,10 +108,15 @@ struct BatchTotals {
     int32_t chi_peak, status_or;
 };
 constexpr int kBinRows = 5;   // shots, sum P_acc, sum P_acc*fail, accepted, wrong
+// surv (optional): per survivor n_seg reach probabilities, summed per bin
+// into sbins[b * n_seg + s]
 hipError_t launch_batch_reduce(int64_t n, uint64_t seed, uint64_t first, const int64_t* off,
                                const int64_t* idx, const int64_t* n_surv,
                                const msc_shot_result* res, int nb, const int64_t* nnz,
-                               double* bins, BatchTotals* tot, hipStream_t s);
+                               double* bins, BatchTotals* tot, const double* surv, int n_seg,
+                               double* sbins, hipStream_t s);
+// idx[i] = i for i < n and *count = n (every shot a survivor)
+hipError_t launch_identity(int64_t n, int64_t* idx, int64_t* count, hipStream_t s);
 hipError_t launch_scatter_results(int64_t n, const int64_t* n_surv, const int64_t* idx,
                                   const msc_shot_result* res, msc_shot_result* out,
                                   hipStream_t s);

@@ -972,6 +972,8 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
         bool alive = true;
         int start = 0;
         int jck = -1;
+        int next_seg = 0;             // next segment whose reach is unwritten
+        int meas_done = 0;            // measurements projected so far
         if (P.ck_mode == 2) {
             // fork from the last checkpoint of the noiseless run before the
             // shot's first fault (the ops before it are fault-free here)
@@ -1001,6 +1003,15 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
             acc.chi_peak = h.chi_peak;
             acc.status = h.status;
             start = P.ck_op[jck];
+            meas_done = h.meas_done;
+            // reach of the segments before the fork: the noiseless run's
+            // running P_acc, as this shot would have computed it
+            if (P.surv) {
+                while (next_seg < P.n_seg && P.seg_meas[next_seg] < meas_done) {
+                    if (tid == 0) P.surv[it * P.n_seg + next_seg] = P.ck_pm[P.seg_meas[next_seg]];
+                    ++next_seg;
+                }
+            }
         } else {
             // ---- initial product state |0...0>
             for (int k = tid; k <= N; k += NT) s_chi[k] = 1;
@@ -1048,6 +1059,7 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                     for (int k = tid; k < N; k += NT) h.laste[k] = s_laste[k];
                     if (tid == 0) {
                         h.p_acc = p_acc;
+                        h.meas_done = meas_done;
                         h.disc = acc.disc;
                         h.chi_peak = acc.chi_peak;
                         h.status = acc.status;
@@ -1223,6 +1235,14 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                     P.cal_p[op.aux] = pe;
                     P.cal_e[op.aux] = static_cast<uint8_t>(e);
                 }
+                if (P.surv) {
+                    // segments starting at or before this measurement
+                    while (next_seg < P.n_seg && P.seg_meas[next_seg] <= op.aux) {
+                        if (tid == 0) P.surv[it * P.n_seg + next_seg] = p_acc;
+                        ++next_seg;
+                    }
+                }
+                if (P.ck_mode == 1 && P.ck_pm && tid == 0) P.ck_pm[op.aux] = p_acc;
                 if (!(pe >= P.tau_rej)) {
                     alive = false;
                     acc.status |= MSC_SHOT_REJECTED;
@@ -1231,6 +1251,7 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
                     break;
                 }
                 p_acc *= pe;
+                meas_done = op.aux + 1;
                 const double sc = 1.0 / sqrt(raw);
                 for (int idx = tid; idx < cl * cr; idx += NT) {
                     const int a = idx / cr, b = idx - a * cr;
@@ -1295,6 +1316,8 @@ __global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
             }
         }
         if (tid == 0) {
+            if (P.surv)
+                for (int g = next_seg; g < P.n_seg; ++g) P.surv[it * P.n_seg + g] = p_acc;
             msc_shot_result res;
             res.p_acc = p_acc;
             res.infid = alive ? infid : 0.0;

@@ -80,6 +80,7 @@ struct PrefixCk {
     void* d_off = nullptr;     // int64[n_ck]
     void* d_hdr = nullptr;     // CkHdr[n_ck]
     void* d_data = nullptr;
+    void* d_pm = nullptr;     // [n_meas] running P_acc before each measurement
 };
 
 struct msc_circuit {
@@ -98,6 +99,11 @@ struct msc_circuit {
     // expected outcomes
     std::vector<uint8_t> expected;
     bool calibrated = false;
+    msc_shot_result noiseless{};         // the calibration run's record
+    // segments (SEGMENT lines): first IR op of each, and their table
+    std::vector<int32_t> seg_ir;
+    std::vector<msc_segment> segs;
+    void* d_segm = nullptr;              // int32 first_meas per segment
     // offline screening tables
     int words = 0;
     std::vector<int32_t> decided;        // measurement index per decided slot
@@ -117,4 +123,5 @@ namespace msc {
 int compile_circuit(msc_circuit* c);        // ops from ir + layout
 int prescreen_compile(msc_circuit* c);      // decided set + signatures
 int parse_circuit(const char* text, size_t len, msc_circuit* c);
+void segment_table(msc_circuit* c);         // segs from seg_ir and ir
 }  // namespace msc

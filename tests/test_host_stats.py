@@ -1,8 +1,9 @@
 """CPU tests of the library's likelihood statistics (msc_profile_loglik,
-msc_lr_interval, msc_ratio_credible, msc_loss_factor) through the C ABI:
-equal to the oracle's on random count sets, the paper's loss table, the
-coverage of the R = 100 interval measured by a parametric bootstrap as the
-error analysis does, and the argument errors.
+msc_lr_interval, msc_ratio_credible, msc_loss_factor) and space-time
+accounting (msc_circuit_segments, msc_expected_volume) through the C ABI:
+equal to the oracle's on random count sets and on every workload circuit,
+the paper's loss table, the coverage of the R = 100 interval measured by a
+parametric bootstrap as the error analysis does, and the argument errors.
 """
 import json
 import math
@@ -145,3 +146,49 @@ def test_statistics_bad_options():
         msc.ratio_credible([10], [5], [1], 10, 0.1, 100, 300)     # s_err > s_acc
     with pytest.raises(msc.MscError):
         msc.loss_factor(10, 1.0)
+
+
+# ---------------------------------------------------------------- space-time
+from oracle import spacetime as ost  # noqa: E402
+from oracle.ir import parse  # noqa: E402
+from tests.test_oracle_spacetime import HAND  # noqa: E402
+from workloads.circuits import config_circuit  # noqa: E402
+
+
+def _seg_tuples_lib(text):
+    return [tuple(int(v) for v in r) for r in msc.Circuit(text).segments()]
+
+
+def _seg_tuples_oracle(text):
+    return [(g["first_meas"], g["n_qubits"], g["depth"], int(g["noisy"]))
+            for g in ost.segments(parse(text))]
+
+
+@pytest.mark.parametrize("name", ["tiny", "tiny_ghz", "c1", "c1_ghz", "c3", "c4"])
+def test_segment_table_equals_oracle(name):
+    text = config_circuit(name).text
+    assert _seg_tuples_lib(text) == _seg_tuples_oracle(text)
+
+
+def test_segment_table_hand_and_errors():
+    assert _seg_tuples_lib(HAND) == [(0, 2, 2, 1), (0, 3, 2, 0), (1, 1, 1, 0)]
+    assert _seg_tuples_lib("QUBITS 2\nH 0\n") == [(0, 1, 1, 0)]
+    with pytest.raises(msc.MscError):
+        msc.Circuit("QUBITS 2\nSEGMENT 1\n")
+
+
+def test_expected_volume_equals_oracle():
+    rng = np.random.default_rng(5)
+    text = config_circuit("c1").text
+    circ = msc.Circuit(text)
+    segs = circ.segments()
+    osegs = ost.segments(parse(text))
+    M = circ.info()["n_channels"]
+    nb, K = 7, len(segs)
+    bin_n = rng.integers(0, 50, nb).astype(float)
+    bin_surv = rng.uniform(0, 1, (nb, K)) * bin_n[:, None]
+    for p in (1e-4, 1e-3, 1e-2):
+        r, v, vb = msc.expected_volume(bin_n, bin_surv, segs, M, p)
+        ro, vo, vbo = ost.expected_volume(bin_n, bin_surv, osegs, M, p)
+        assert np.allclose(r, ro, rtol=1e-12, atol=1e-300)
+        assert v == pytest.approx(vo, rel=1e-12) and vb == pytest.approx(vbo, rel=1e-12)

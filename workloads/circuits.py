@@ -367,6 +367,8 @@ def make_circuit(kind: str = "rot", d: int = 3, plain_rounds: int = 3,
             w.meas(q)
 
     def round_(frame):
+        # every syndrome round is a segment of the space-time accounting
+        L.append("SEGMENT")
         L.append("TICK")
         for a, nb in zchk:
             w.reset(a)
@@ -396,6 +398,7 @@ def make_circuit(kind: str = "rot", d: int = 3, plain_rounds: int = 3,
         round_(0)
     frame = 0
     for _ in range(t_layers):
+        L.append("SEGMENT")
         L.append("TICK")
         frame += 1
         for q in data:
@@ -403,6 +406,7 @@ def make_circuit(kind: str = "rot", d: int = 3, plain_rounds: int = 3,
         for _ in range(framed_rounds):
             round_(frame)
     if frame:
+        L.append("SEGMENT")
         L.append("TICK")
         for q in data:
             for g in _frame_ops(target, frame, True):
@@ -414,6 +418,7 @@ def make_circuit(kind: str = "rot", d: int = 3, plain_rounds: int = 3,
     w.noisy = False
     ghz_checks = 0
     round_(0)
+    L.append("SEGMENT")
     L.append("TICK")
     for op in reversed(enc):
         if op[0] == "H":

@@ -307,6 +307,39 @@ int msc_run_batch(msc_ctx* ctx, const msc_circuit* c, const msc_sim_opts* opts,
                   msc_shot_result* out, double* surv_bins);
 
 /* ---------------------------------------------------------------------- */
+/* CAMPS (section "Clifford augmented MPS").                               */
+
+/* Simulate shots as msc_simulate does (same arguments, shot selection and
+   result records) with the Clifford-augmented MPS: the state is C|m>, C a
+   Clifford frame held as the images C^dag X_q C, C^dag Z_q C of the
+   single-qubit Paulis, |m> the magic residual, an FP64 MPS.  Clifford
+   gates and Pauli faults act on the frame only; T and T^dagger (CS,
+   CS^dagger and CCZ written over T, T^dagger and CX) become rotations
+   exp(-+i pi/8 C^dag Z C) of the residual and measurements projections
+   (I +- C^dag Z C)/2, applied to the MPS and recompressed in the exact
+   regime (sigma > tau_trunc sigma_max, default 1e-12); after each one that
+   acts on two sites or more, a greedy sweep over its bonds moves the
+   entanglement-lowering two-qubit Clifford of highest purity gain (19
+   classes modulo local Cliffords) into the frame.  opts: precision
+   MSC_FP64, chi_max in [1, 32] (the residual's bond cap: shots that need
+   more end with MSC_SHOT_CHI_CAP and P_acc 0), prefix, lds_width and
+   reserved 0.  out[i].chi_peak is the residual's peak bond dimension,
+   out[i].n2q the disentangling Cliffords applied; disc_weight and flops
+   are 0.  Requires a calibrated circuit with at most 127 qubits.         */
+int msc_simulate_camps(msc_ctx* ctx, const msc_circuit* c, const msc_sim_opts* opts,
+                       int64_t n_shots, const int64_t* shot_off, const int32_t* chan,
+                       const uint8_t* pauli, const int64_t* shot_idx, int64_t n_sel,
+                       msc_shot_result* out);
+
+/* The disentangler's candidates (host out): *n_out = 19; dmat (optional,
+   32 doubles each) their unitaries as (re, im) pairs, row-major over
+   |s_k s_k+1> with the left site the high bit; dtab (optional, 16 bytes
+   each) their Pauli maps: entry x1 | z1 << 1 | x2 << 2 | z2 << 3 gives the
+   image of X1^x1 Z1^z1 X2^x2 Z2^z2 in the same bits plus its phase
+   exponent of i in bits 4-5.                                              */
+int msc_camps_candidates(double* dmat, uint8_t* dtab, int32_t* n_out);
+
+/* ---------------------------------------------------------------------- */
 /* Two-site contraction on MFMA (Section 3.1), standalone.                 */
 
 /* theta_b = G * (A_b . B_b) for `batch` independent two-site updates with

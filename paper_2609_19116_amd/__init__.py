@@ -18,6 +18,7 @@ from ._lib import (BatchStats, MSC_BF16X3, MSC_FP32, MSC_FP64, MSC_STAT_PACC,  #
                    _ptr, lib)
 
 __all__ = ["Ctx", "Circuit", "sample_faults", "sample_faults_device", "prescreen", "simulate",
+           "simulate_camps", "camps_candidates",
            "run_batch", "reweight", "profile_loglik", "lr_interval", "ratio_credible",
            "loss_factor", "expected_volume", "order_search", "twosite_contract", "prescreen_tables", "version", "MscError",
            "MSC_FP64", "MSC_FP32", "MSC_BF16X3", "MSC_STAT_PACC", "MSC_STAT_PLE", "SHOT_DTYPE"]
@@ -205,6 +206,34 @@ def simulate(ctx: Ctx, circ: Circuit, off, chan, pauli, shot_idx=None, precision
     _check(lib().msc_simulate(ctx.h, circ.h, C.byref(o), n_shots, _ptr(off), _ptr(chan),
                               _ptr(pauli), _ptr(shot_idx), n, _ptr(out)))
     return out[: n * SHOT_DTYPE.itemsize]
+
+
+def simulate_camps(ctx: Ctx, circ: Circuit, off, chan, pauli, shot_idx=None,
+                   chi_max: int = 32, tau_trunc: float = 0.0, tau_rej: float = 1e-6,
+                   tau_fail: float = 1e-4, n_slots: int = 0, out=None):
+    """Simulate shots with the Clifford-augmented MPS (FP64); same records
+    as ``simulate`` with chi_peak the magic residual's peak bond."""
+    import torch
+    n_shots = off.numel() - 1
+    n = shot_idx.numel() if shot_idx is not None else n_shots
+    if out is None:
+        out = torch.empty(max(n, 1) * SHOT_DTYPE.itemsize, dtype=torch.uint8, device=off.device)
+    o = SimOpts(MSC_FP64, chi_max, tau_trunc, tau_rej, tau_fail, n_slots, 0, 0, 0)
+    _check(lib().msc_simulate_camps(ctx.h, circ.h, C.byref(o), n_shots, _ptr(off), _ptr(chan),
+                                    _ptr(pauli), _ptr(shot_idx), n, _ptr(out)))
+    return out[: n * SHOT_DTYPE.itemsize]
+
+
+def camps_candidates():
+    """The disentangler's 19 candidates: (unitaries complex [19, 4, 4],
+    Pauli maps uint8 [19, 16])."""
+    n = C.c_int32()
+    _check(lib().msc_camps_candidates(None, None, C.byref(n)))
+    m = np.zeros(32 * n.value, dtype=np.float64)
+    t = np.zeros(16 * n.value, dtype=np.uint8)
+    _check(lib().msc_camps_candidates(_ptr(m), _ptr(t), C.byref(n)))
+    u = m.reshape(n.value, 16, 2)
+    return (u[..., 0] + 1j * u[..., 1]).reshape(n.value, 4, 4), t.reshape(n.value, 16)
 
 
 def run_batch(ctx: Ctx, circ: Circuit, seed: int, first_shot: int, n_shots: int, p: float,

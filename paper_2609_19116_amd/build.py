@@ -25,11 +25,13 @@ SOURCES = [
     CSRC / "host" / "sampler.cpp",
     CSRC / "host" / "stats.cpp",
     CSRC / "host" / "order.cpp",
+    CSRC / "host" / "camps.cpp",
     CSRC / "host" / "capi.cpp",
     CSRC / "kernels" / "mps.hip",
     CSRC / "kernels" / "prescreen.hip",
     CSRC / "kernels" / "sampler.hip",
     CSRC / "kernels" / "batch.hip",
+    CSRC / "kernels" / "camps.hip",
     CSRC / "kernels" / "twosite.hip",
 ]
 

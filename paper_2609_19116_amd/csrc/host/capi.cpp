@@ -189,7 +189,8 @@ static void free_device(msc_circuit* c) {
     if (c->dev < 0) return;
     (void)hipSetDevice(c->dev);
     for (void** p : {&c->d_ops, &c->d_g1, &c->d_g4, &c->d_sig, &c->d_expected, &c->d_kind,
-                     &c->d_segm}) {
+                     &c->d_segm, &c->d_camps_ops, &c->d_chan_q, &c->d_site_of, &c->d_dmat,
+                     &c->d_dtab}) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
@@ -774,6 +775,112 @@ extern "C" int msc_run_batch(msc_ctx* ctx, const msc_circuit* c, const msc_sim_o
         stats->ms_screen = t12;
         stats->ms_simulate = t23;
     }
+    return MSC_OK;
+}
+
+// CAMPS op stream, channel qubits, layout and candidate tables on the device
+static int camps_upload(msc_ctx* ctx, msc_circuit* c) {
+    int rc = upload(ctx, c);
+    if (rc) return rc;
+    if (c->d_camps_ops) return MSC_OK;
+    camps_compile(c);
+    std::vector<double> dmat;
+    std::vector<uint8_t> dtab;
+    camps_candidates(dmat, dtab);
+    if (static_cast<int>(dtab.size()) != 16 * kCampsCand)
+        return set_error(MSC_E_INVALID, "candidate table size");
+    std::vector<int32_t> site_of(c->n);
+    for (int s = 0; s < c->n; ++s) site_of[c->order[s]] = s;
+    auto put = [&](void** dst, const void* src, size_t bytes) -> int {
+        MSC_HIP(hipMalloc(dst, std::max<size_t>(bytes, 64)));
+        if (bytes) MSC_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+        return MSC_OK;
+    };
+    if ((rc = put(&c->d_camps_ops, c->camps_ops.data(), c->camps_ops.size() * sizeof(DevOp)))) return rc;
+    if ((rc = put(&c->d_chan_q, c->chan_q.data(), c->chan_q.size() * sizeof(int32_t)))) return rc;
+    if ((rc = put(&c->d_site_of, site_of.data(), site_of.size() * sizeof(int32_t)))) return rc;
+    if ((rc = put(&c->d_dmat, dmat.data(), dmat.size() * sizeof(double)))) return rc;
+    if ((rc = put(&c->d_dtab, dtab.data(), dtab.size()))) return rc;
+    return MSC_OK;
+}
+
+extern "C" int msc_simulate_camps(msc_ctx* ctx, const msc_circuit* c, const msc_sim_opts* opts,
+                                  int64_t n_shots, const int64_t* shot_off, const int32_t* chan,
+                                  const uint8_t* pauli, const int64_t* shot_idx, int64_t n_sel,
+                                  msc_shot_result* out) {
+    if (!ctx || !c || !opts || n_shots < 0 || !shot_off || (shot_idx && n_sel < 0))
+        return set_error(MSC_E_INVALID, "null argument");
+    const int64_t n = shot_idx ? n_sel : n_shots;
+    if (n > 0 && !out) return set_error(MSC_E_INVALID, "null out");
+    if (!c->calibrated) return set_error(MSC_E_STATE, "circuit not calibrated");
+    if (opts->precision != MSC_FP64) return set_error(MSC_E_INVALID, "CAMPS runs in MSC_FP64");
+    if (opts->chi_max < 1 || opts->chi_max > kCampsCap)
+        return set_error(MSC_E_INVALID, "CAMPS chi_max must be in [1, 32]");
+    if (c->n > kMaxSites - 1) return set_error(MSC_E_INVALID, "CAMPS takes at most 127 qubits");
+    if (opts->prefix != 0 || opts->reserved != 0 || opts->lds_width != 0)
+        return set_error(MSC_E_INVALID, "CAMPS takes no prefix, lds_width or reserved option");
+    if (n == 0) return MSC_OK;
+    MSC_HIP(hipSetDevice(ctx->device));
+    int rc = camps_upload(ctx, const_cast<msc_circuit*>(c));
+    if (rc) return rc;
+    int n_slots = opts->n_slots > 0 ? opts->n_slots : ctx->n_cu * camps_blocks_per_cu();
+    n_slots = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(n_slots, n)));
+    void *arena, *scratch;
+    if ((rc = ctx_buf(ctx, "camps_arena",
+                      static_cast<size_t>(n_slots) * c->n * kCampsSiteDoubles * sizeof(double), &arena)))
+        return rc;
+    if ((rc = ctx_buf(ctx, "camps_scratch", static_cast<size_t>(n_slots) * kCampsScratch * sizeof(double),
+                      &scratch)))
+        return rc;
+    CampsArgs a{};
+    a.ops = static_cast<const DevOp*>(c->d_camps_ops);
+    a.n_ops = static_cast<int32_t>(c->camps_ops.size());
+    a.n = c->n;
+    a.site_of = static_cast<const int32_t*>(c->d_site_of);
+    a.chan_q = static_cast<const int32_t*>(c->d_chan_q);
+    a.shot_off = shot_off;
+    a.chan = chan;
+    a.pauli = pauli;
+    a.shot_idx = shot_idx;
+    a.n_shots = n;
+    a.n_csr = n_shots;
+    a.expected = static_cast<const uint8_t*>(c->d_expected);
+    a.out = out;
+    a.arena = static_cast<double*>(arena);
+    a.scratch = static_cast<double*>(scratch);
+    a.dmat = static_cast<const double*>(c->d_dmat);
+    a.dtab = static_cast<const uint8_t*>(c->d_dtab);
+    a.chi_cap = opts->chi_max;
+    a.tau = opts->tau_trunc > 0 ? opts->tau_trunc : 1e-12;
+    a.tau_rej = opts->tau_rej > 0 ? opts->tau_rej : 1e-6;
+    a.tau_fail = opts->tau_fail > 0 ? opts->tau_fail : 1e-4;
+    const double r = 1.0 / std::sqrt(2.0);
+    if (c->target == 'T') {
+        a.rt[0] = r;
+        a.rt[1] = r;
+    } else {
+        a.rt[0] = 0.0;
+        a.rt[1] = 1.0;
+    }
+    a.rt[2] = 0.0;
+    MSC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
+    MSC_HIP(launch_camps(a, n_slots, ctx->stream));
+    MSC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
+    MSC_HIP(hipStreamSynchronize(ctx->stream));
+    float ms = 0.f;
+    MSC_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    ctx->last_ms["camps"] = ms;
+    return MSC_OK;
+}
+
+extern "C" int msc_camps_candidates(double* dmat, uint8_t* dtab, int32_t* n_out) {
+    if (!n_out) return set_error(MSC_E_INVALID, "null argument");
+    std::vector<double> m;
+    std::vector<uint8_t> t;
+    camps_candidates(m, t);
+    *n_out = static_cast<int32_t>(t.size() / 16);
+    if (dmat) std::copy(m.begin(), m.end(), dmat);
+    if (dtab) std::copy(t.begin(), t.end(), dtab);
     return MSC_OK;
 }
 

@@ -124,4 +124,37 @@ hipError_t launch_scatter_results(int64_t n, const int64_t* n_surv, const int64_
 hipError_t launch_twosite(int precision, int chi, int batch, const float* A, const float* B,
                           const float* gate, float* theta, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// CAMPS shots (camps.hip): Clifford frame + magic-residual MPS in FP64
+constexpr int kCampsK = 64;        // stored bond capacity of the residual
+constexpr int kCampsCap = 32;      // bond cap after every recompression
+constexpr int kCampsCand = 19;     // two-qubit Clifford classes tried per bond
+constexpr int64_t kCampsSiteDoubles = 4LL * kCampsK * kCampsK;   // re + im
+constexpr int64_t kCampsScratch = 98304;                         // doubles per slot
+
+struct CampsArgs {
+    const DevOp* ops;          // CAMPS op stream (CampsKind)
+    int32_t n_ops;
+    int32_t n;                 // qubits = residual sites
+    const int32_t* site_of;    // [n] residual site of each qubit
+    const int32_t* chan_q;     // [3 M] qubits of each channel (-1 unused)
+    const int64_t* shot_off;
+    const int32_t* chan;
+    const uint8_t* pauli;
+    const int64_t* shot_idx;   // optional subset
+    int64_t n_shots;
+    int64_t n_csr;
+    const uint8_t* expected;
+    msc_shot_result* out;
+    double* arena;             // n_slots * n * kCampsSiteDoubles
+    double* scratch;           // n_slots * kCampsScratch
+    const double* dmat;        // [kCampsCand][32] candidate unitaries (re,im) row-major
+    const uint8_t* dtab;       // [kCampsCand][16] Pauli map: bits x1 z1 x2 z2 | phase << 4
+    int32_t chi_cap;           // <= kCampsCap
+    double tau, tau_rej, tau_fail;
+    double rt[3];              // Bloch vector of the target state
+};
+hipError_t launch_camps(const CampsArgs& a, int grid, hipStream_t s);
+int camps_blocks_per_cu();
+
 }  // namespace msc

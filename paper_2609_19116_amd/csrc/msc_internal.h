@@ -32,6 +32,18 @@ struct DevOp {
     int32_t kind, a, b, aux;
 };
 
+// CAMPS op stream (kind of DevOp): qubits are physical qubits
+enum CampsKind : int32_t {
+    CO_G1 = 0,      // a = qubit, aux = Gate1 (Clifford: H S SDG X Y Z)
+    CO_CX = 1,      // a = control, b = target
+    CO_CZ = 2,      // a, b
+    CO_ROT = 3,     // a = qubit, aux = +1 (T) or -1 (T^dagger)
+    CO_FAULT = 4,   // a = channel index
+    CO_MEAS = 5,    // a = qubit, aux = measurement index
+    CO_RESET = 6,   // a = qubit: X^e with e the outcome last projected
+    CO_FINAL = 7    // a = seed qubit
+};
+
 // 1q gate ids (rows of the 2x2 complex table)
 enum Gate1 : int32_t { G_H = 0, G_S, G_SDG, G_T, G_TDG, G_X, G_Y, G_Z, G1_COUNT };
 // 4x4 gate ids in site order |s_k s_{k+1}>
@@ -104,6 +116,14 @@ struct msc_circuit {
     std::vector<int32_t> seg_ir;
     std::vector<msc_segment> segs;
     void* d_segm = nullptr;              // int32 first_meas per segment
+    // CAMPS op stream (built on first use) and its device copies
+    std::vector<msc::DevOp> camps_ops;
+    std::vector<int32_t> chan_q;         // [3 n_channels]
+    void* d_camps_ops = nullptr;
+    void* d_chan_q = nullptr;
+    void* d_site_of = nullptr;
+    void* d_dmat = nullptr;              // candidate tables (camps_candidates)
+    void* d_dtab = nullptr;
     // offline screening tables
     int words = 0;
     std::vector<int32_t> decided;        // measurement index per decided slot
@@ -124,4 +144,8 @@ int compile_circuit(msc_circuit* c);        // ops from ir + layout
 int prescreen_compile(msc_circuit* c);      // decided set + signatures
 int parse_circuit(const char* text, size_t len, msc_circuit* c);
 void segment_table(msc_circuit* c);         // segs from seg_ir and ir
+void camps_compile(msc_circuit* c);         // camps_ops and chan_q from ir
+// candidate two-qubit Cliffords of the disentangler: unitaries (32 doubles
+// each, (re, im) row-major over |s_k s_k+1>) and Pauli maps (16 bytes each)
+void camps_candidates(std::vector<double>& dmat, std::vector<uint8_t>& dtab);
 }  // namespace msc

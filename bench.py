@@ -13,8 +13,10 @@ the length of a single step).
 
 Also measured on the same GPU and shot list: the plain FP64 path one shot
 per launch (bounded sample, scaled), the FP32-vs-FP64 probability error,
-the fixed-shape chi = 256 MFMA contraction, and the CPU oracle timed on the
-host (bounded sample).  Prints one JSON line.
+the CAMPS engine on the same survivors, the space-time accounting mode,
+the qubit-order search, the fixed-shape chi = 256 MFMA contraction, and the
+CPU oracle timed on the host (bounded sample); likelihood-ratio intervals
+of the reported rates come from the timed shots.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -57,6 +59,8 @@ def main() -> int:
                     help="shots of the batch run through the CPU oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--order-budget", type=int, default=24,
+                    help="evaluations of the qubit-order search (extras)")
     ap.add_argument("--lds-width", type=int, default=0)
     ap.add_argument("--slots", type=int, default=0,
                     help="persistent workgroups (MPS slots) per context; 0 = one per "
@@ -299,6 +303,57 @@ def main() -> int:
                                   "max_abs_infid": float(df.max()),
                                   "fail_mismatch": int((res32["fail"] != out64["fail"]).sum()),
                                   "shots": int(len(dp))}
+        # CAMPS (FP64 Clifford frame + magic residual) on the same survivors,
+        # all of them in one persistent launch; the step rate adds the batch's
+        # mean screen and sampling times
+        log("CAMPS on the first batch's survivors")
+        outc = msc.results_numpy(msc.simulate_camps(ctx, circ, off, ch, pa, shot_idx=idx0))
+        camps_ms = ctx.last_kernel_ms("camps")
+        step_c = camps_ms + float(np.mean(screen_ms)) + float(np.mean(sample_ms))
+        dpc = np.abs(outc["p_acc"] - out64["p_acc"])
+        result["camps"] = {"shots_per_s": n / (step_c * 1e-3), "kernel_ms": camps_ms,
+                           "survivors": int(idx0.numel()),
+                           "residual_chi_peak_max": int(outc["chi_peak"].max()),
+                           "residual_chi_peak_mean": float(outc["chi_peak"].mean()),
+                           "mps_chi_peak_max": int(out64["chi_peak"].max()),
+                           "max_abs_p_acc_vs_mps_fp64": float(dpc.max()),
+                           "fail_mismatch_vs_mps_fp64": int((outc["fail"] != out64["fail"]).sum()),
+                           "chi_cap_flagged": int(((outc["status"] & msc.SHOT_CHI_CAP) != 0).sum())}
+        # space-time accounting: batches in space-time mode (screen skipped,
+        # every shot's probability of reaching each segment), then the
+        # expected volume of the noisy segments at p
+        log("space-time mode batches")
+        segs = circ.segments()
+        st_n = np.zeros(wmax + 1)
+        st_s = np.zeros((wmax + 1, len(segs)))
+        t0 = time.perf_counter()
+        n_st = 4
+        for b in range(n_st):
+            bb, sb = msc.run_batch(ctx, circ, SEED, (warmup + b) * n, n, args.p, n_bins=wmax + 1,
+                                   precision=msc.MSC_FP32, chi_max=args.chi_max,
+                                   lds_width=args.lds_width, prefix=not args.no_prefix,
+                                   space_time=True)
+            st_n += bb[0]
+            st_s += sb["surv_bins"]
+        t_st = time.perf_counter() - t0
+        last_st = int(np.nonzero(st_n)[0].max()) + 1
+        reach, vol, vol_b = msc.expected_volume(st_n[:last_st], st_s[:last_st], segs, M, args.p)
+        result["space_time"] = {
+            "expected_volume": vol, "expected_volume_upper_with_B": vol_b,
+            "noisy_volume_if_no_shot_stopped": float(sum(
+                int(g["n_qubits"]) * int(g["depth"]) for g in segs if g["noisy"])),
+            "reach_per_segment": [float(x) for x in reach],
+            "segments": len(segs), "shots": n_st * n,
+            "shots_per_s_single_stream": n_st * n / t_st}
+        # qubit-order search from the workload's snake order (noiseless-run
+        # flops on the GPU as the cost)
+        log("qubit-order search")
+        t0 = time.perf_counter()
+        order, c_start, c_best = msc.order_search(ctx, cc.text, 0x5EED0081, args.order_budget)
+        result["order_search"] = {"budget": args.order_budget, "start_flops": c_start,
+                                  "best_flops": c_best, "ratio": c_best / c_start,
+                                  "seconds": time.perf_counter() - t0,
+                                  "order": [int(q) for q in order]}
         # fixed-shape chi = 256 two-site contraction on MFMA, FP32 and BF16x3
         from workloads.tensors import random_twosite
         chi, batch = 256, 512

@@ -641,6 +641,8 @@ __global__ __launch_bounds__(CT) void camps_kernel(CampsArgs P) {
     __shared__ int s_keep[K];
     __shared__ int s_flag, s_center, s_status, s_sweeps, s_peak, s_best;
     __shared__ double s_pur[kCampsCand + 1];
+    __shared__ double s_dm[(kCampsCand + 1) * 32];   // identity, then the candidates
+    __shared__ double s_part[CT];
     const int tid = threadIdx.x;
     const int n = P.n;
     Frame F;
@@ -660,6 +662,11 @@ __global__ __launch_bounds__(CT) void camps_kernel(CampsArgs P) {
     C.chi_peak = &s_peak;
     C.old = s_old;
     const double c8 = 0.92387953251128675613, s8 = 0.38268343236508977173;   // cos, sin of pi/8
+    for (int e = tid; e < (kCampsCand + 1) * 32; e += CT) {
+        const int c = e / 32, w = e - c * 32;
+        s_dm[e] = c == 0 ? ((w % 2 == 0 && (w / 2) % 5 == 0) ? 1.0 : 0.0) : P.dmat[(c - 1) * 32 + w];
+    }
+    __syncthreads();
 
     for (int64_t it = blockIdx.x; it < P.n_shots; it += gridDim.x) {
         const int64_t shot = P.shot_idx ? P.shot_idx[it] : it;
@@ -709,15 +716,18 @@ __global__ __launch_bounds__(CT) void camps_kernel(CampsArgs P) {
         int64_t n_dis = 0;
         const double tau = P.tau;
 
-        // greedy disentangling sweep over bonds k0..k1
+        // greedy disentangling sweep over bonds k0..k1.  Per bond, theta
+        // (sites k, k+1) and the Gram matrix of its smaller side give the
+        // reduced density matrix of D theta for every candidate D without
+        // forming D theta: rho_D = sum D G D^dag over the bond's own legs.
         auto disentangle = [&](int k0, int k1) {
             move_center(R, C, k0, tau);
             for (int k = k0; k <= k1; ++k) {
                 if (s_status & MSC_SHOT_CHI_CAP) break;     // bonds may exceed the buffers
                 const int cl = s_chi[k], cm = s_chi[k + 1], cr = s_chi[k + 2];
                 const int m = 2 * cl, nn = 2 * cr;
-                double *thr = R.scr + oTH, *thi = thr + 2LL * K * K;
-                double *tcr = R.scr + oTC, *tci = tcr + K * K;
+                double *thr = R.scr + oTC, *thi = thr + K * K;
+                double *gr = R.scr + oF, *gi = R.scr + oTH;
                 const double *ar = R.re(k), *ai = R.im(k), *br = R.re(k + 1), *bi = R.im(k + 1);
                 // theta[(a,i)][(j,b)] = sum_u A[a,i,u] B[u,j,b]
                 for (int e = tid; e < m * nn; e += CT) {
@@ -733,61 +743,94 @@ __global__ __launch_bounds__(CT) void camps_kernel(CampsArgs P) {
                     thi[e] = xi;
                 }
                 __syncthreads();
-                // purity of D theta for D = identity (c = -1) and every candidate
-                for (int cc = -1; cc < kCampsCand; ++cc) {
-                    const double* d = cc >= 0 ? P.dmat + cc * 32 : nullptr;
-                    const double *sr = thr, *si = thi;
-                    if (d) {
-                        for (int e = tid; e < m * nn; e += CT) {
-                            const int row = e / nn, col = e - row * nn;
-                            const int a = row >> 1, i2 = row & 1, j2 = col / cr, b = col - j2 * cr;
-                            const int o = 2 * i2 + j2;
-                            double xr = 0, xi = 0;
-                            for (int in = 0; in < 4; ++in) {
-                                const int i1 = in >> 1, j1 = in & 1;
-                                const double g_r = d[2 * (o * 4 + in)], g_i = d[2 * (o * 4 + in) + 1];
-                                const int src = (a * 2 + i1) * nn + j1 * cr + b;
-                                xr += g_r * thr[src] - g_i * thi[src];
-                                xi += g_r * thi[src] + g_i * thr[src];
-                            }
-                            tcr[e] = xr;
-                            tci[e] = xi;
-                        }
-                        __syncthreads();
-                        sr = tcr;
-                        si = tci;
-                    }
-                    // purity = || T T^dag ||_F^2 over the smaller side
-                    double acc = 0;
-                    if (m <= nn) {
-                        for (int e = tid; e < m * m; e += CT) {
-                            const int x1 = e / m, x2 = e - x1 * m;
-                            double rr = 0, ri = 0;
-                            for (int col = 0; col < nn; ++col) {
-                                const double p_r = sr[x1 * nn + col], p_i = si[x1 * nn + col];
-                                const double q_r = sr[x2 * nn + col], q_i = -si[x2 * nn + col];
-                                rr += p_r * q_r - p_i * q_i;
-                                ri += p_r * q_i + p_i * q_r;
-                            }
-                            acc += rr * rr + ri * ri;
+                // Gram of the smaller side: left G[(a,i,j)][(a2,i2,j2)] =
+                // sum_b th[(a,i),(j,b)] conj(th[(a2,i2),(j2,b)]); right
+                // G[(i,j,b)][(i2,j2,b2)] = sum_a conj(th[(a,i),(j,b)]) th[(a,i2),(j2,b2)]
+                const bool left = cl <= cr;
+                const int sd = left ? cl : cr, gd = 4 * sd;
+                for (int e = tid; e < gd * gd; e += CT) {
+                    const int u = e / gd, v = e - u * gd;
+                    double xr = 0, xi = 0;
+                    if (left) {
+                        const int a = u >> 2, i = (u >> 1) & 1, j = u & 1;
+                        const int a2 = v >> 2, i2 = (v >> 1) & 1, j2 = v & 1;
+                        const double *p_r = thr + (a * 2 + i) * nn + j * cr, *p_i = thi + (a * 2 + i) * nn + j * cr;
+                        const double *q_r = thr + (a2 * 2 + i2) * nn + j2 * cr, *q_i = thi + (a2 * 2 + i2) * nn + j2 * cr;
+                        for (int b = 0; b < cr; ++b) {
+                            xr += p_r[b] * q_r[b] + p_i[b] * q_i[b];
+                            xi += p_i[b] * q_r[b] - p_r[b] * q_i[b];
                         }
                     } else {
-                        for (int e = tid; e < nn * nn; e += CT) {
-                            const int y1 = e / nn, y2 = e - y1 * nn;
-                            double rr = 0, ri = 0;
-                            for (int row = 0; row < m; ++row) {
-                                const double p_r = sr[row * nn + y1], p_i = -si[row * nn + y1];
-                                const double q_r = sr[row * nn + y2], q_i = si[row * nn + y2];
-                                rr += p_r * q_r - p_i * q_i;
-                                ri += p_r * q_i + p_i * q_r;
-                            }
-                            acc += rr * rr + ri * ri;
+                        const int ij = u / cr, b = u - ij * cr, ij2 = v / cr, b2 = v - ij2 * cr;
+                        const int i = ij >> 1, j = ij & 1, i2 = ij2 >> 1, j2 = ij2 & 1;
+                        for (int a = 0; a < cl; ++a) {
+                            const int s1 = (a * 2 + i) * nn + j * cr + b, s2 = (a * 2 + i2) * nn + j2 * cr + b2;
+                            xr += thr[s1] * thr[s2] + thi[s1] * thi[s2];
+                            xi += thr[s1] * thi[s2] - thi[s1] * thr[s2];
                         }
                     }
-                    acc = block_sum(acc, s_red);
-                    if (tid == 0) s_pur[cc + 1] = acc;
-                    __syncthreads();
+                    gr[e] = xr;
+                    gi[e] = xi;
                 }
+                __syncthreads();
+                // purity of every candidate (0 = no gate), kCampsCand + 1 teams
+                // of 12 threads, each summing |rho|^2 over a fixed stride
+                constexpr int TPC = CT / (kCampsCand + 1);
+                const int cand = tid / TPC, lane = tid - cand * TPC;
+                double part = 0.0;
+                if (cand <= kCampsCand) {
+                    const double* d = s_dm + cand * 32;
+                    const int rd = left ? m : nn;           // rho is rd x rd
+                    for (int e = lane; e < rd * rd; e += TPC) {
+                        const int x1 = e / rd, x2 = e - x1 * rd;
+                        double rr = 0, ri = 0;
+                        if (left) {
+                            const int a = x1 >> 1, ip = x1 & 1, a2 = x2 >> 1, i2p = x2 & 1;
+                            for (int jp = 0; jp < 2; ++jp)
+                                for (int in = 0; in < 4; ++in) {
+                                    const int o1 = (2 * ip + jp) * 4 + in;
+                                    const double d1r = d[2 * o1], d1i = d[2 * o1 + 1];
+                                    if (d1r == 0.0 && d1i == 0.0) continue;
+                                    for (int in2 = 0; in2 < 4; ++in2) {
+                                        const int o2 = (2 * i2p + jp) * 4 + in2;
+                                        const double d2r = d[2 * o2], d2i = -d[2 * o2 + 1];
+                                        if (d2r == 0.0 && d2i == 0.0) continue;
+                                        const int g = (a * 4 + in) * gd + (a2 * 4 + in2);
+                                        // d1 * conj(d2') * G
+                                        const double pr_ = d1r * d2r - d1i * d2i, pi_ = d1r * d2i + d1i * d2r;
+                                        rr += pr_ * gr[g] - pi_ * gi[g];
+                                        ri += pr_ * gi[g] + pi_ * gr[g];
+                                    }
+                                }
+                        } else {
+                            const int jp = x1 / cr, b = x1 - jp * cr, j2p = x2 / cr, b2 = x2 - j2p * cr;
+                            for (int ip = 0; ip < 2; ++ip)
+                                for (int in = 0; in < 4; ++in) {
+                                    const int o1 = (2 * ip + jp) * 4 + in;
+                                    const double d1r = d[2 * o1], d1i = -d[2 * o1 + 1];   // conj
+                                    if (d1r == 0.0 && d1i == 0.0) continue;
+                                    for (int in2 = 0; in2 < 4; ++in2) {
+                                        const int o2 = (2 * ip + j2p) * 4 + in2;
+                                        const double d2r = d[2 * o2], d2i = d[2 * o2 + 1];
+                                        if (d2r == 0.0 && d2i == 0.0) continue;
+                                        const int g = (in * cr + b) * gd + (in2 * cr + b2);
+                                        const double pr_ = d1r * d2r - d1i * d2i, pi_ = d1r * d2i + d1i * d2r;
+                                        rr += pr_ * gr[g] - pi_ * gi[g];
+                                        ri += pr_ * gi[g] + pi_ * gr[g];
+                                    }
+                                }
+                        }
+                        part += rr * rr + ri * ri;
+                    }
+                    s_part[tid] = part;
+                }
+                __syncthreads();
+                if (tid <= kCampsCand) {
+                    double acc = 0.0;
+                    for (int l = 0; l < TPC; ++l) acc += s_part[tid * TPC + l];
+                    s_pur[tid] = acc;
+                }
+                __syncthreads();
                 if (tid == 0) {
                     double best = s_pur[0];
                     int choice = -1;
@@ -800,49 +843,46 @@ __global__ __launch_bounds__(CT) void camps_kernel(CampsArgs P) {
                 }
                 __syncthreads();
                 const int choice = s_best;
+                if (choice < 0) {
+                    // nothing gains: just move the centre on
+                    move_right(R, C, k, tau);
+                    continue;
+                }
+                ++n_dis;
                 double *wr = R.scr + oW, *wi = wr + 2LL * K * K;
-                if (choice >= 0) {
-                    ++n_dis;
-                    const double* d = P.dmat + choice * 32;
-                    // W <- (D theta) column-major
-                    for (int e = tid; e < m * nn; e += CT) {
-                        const int row = e / nn, col = e - row * nn;
-                        const int a = row >> 1, i2 = row & 1, j2 = col / cr, b = col - j2 * cr;
-                        const int o = 2 * i2 + j2;
-                        double xr = 0, xi = 0;
-                        for (int in = 0; in < 4; ++in) {
-                            const int i1 = in >> 1, j1 = in & 1;
-                            const double g_r = d[2 * (o * 4 + in)], g_i = d[2 * (o * 4 + in) + 1];
-                            const int src = (a * 2 + i1) * nn + j1 * cr + b;
-                            xr += g_r * thr[src] - g_i * thi[src];
-                            xi += g_r * thi[src] + g_i * thr[src];
-                        }
-                        wr[static_cast<int64_t>(col) * 2 * K + row] = xr;
-                        wi[static_cast<int64_t>(col) * 2 * K + row] = xi;
+                const double* d = s_dm + (choice + 1) * 32;
+                // W <- (D theta) column-major
+                for (int e = tid; e < m * nn; e += CT) {
+                    const int row = e / nn, col = e - row * nn;
+                    const int a = row >> 1, i2 = row & 1, j2 = col / cr, b = col - j2 * cr;
+                    const int o = 2 * i2 + j2;
+                    double xr = 0, xi = 0;
+                    for (int in = 0; in < 4; ++in) {
+                        const int i1 = in >> 1, j1 = in & 1;
+                        const double g_r = d[2 * (o * 4 + in)], g_i = d[2 * (o * 4 + in) + 1];
+                        const int src = (a * 2 + i1) * nn + j1 * cr + b;
+                        xr += g_r * thr[src] - g_i * thi[src];
+                        xi += g_r * thi[src] + g_i * thr[src];
                     }
-                    // frame: every row's part on sites k, k+1 conjugated by D
-                    const uint8_t* tab = P.dtab + choice * 16;
-                    for (int r = tid; r < 2 * n; r += CT) {
-                        const int x1 = getbit(s_x + 2 * r, k), z1 = getbit(s_z + 2 * r, k);
-                        const int x2 = getbit(s_x + 2 * r, k + 1), z2 = getbit(s_z + 2 * r, k + 1);
-                        const int t = tab[x1 | (z1 << 1) | (x2 << 2) | (z2 << 3)];
-                        const int w0 = k >> 6, w1 = (k + 1) >> 6;
-                        const uint64_t m0 = 1ull << (k & 63), m1 = 1ull << ((k + 1) & 63);
-                        s_x[2 * r + w0] = (s_x[2 * r + w0] & ~m0) | ((t & 1) ? m0 : 0);
-                        s_z[2 * r + w0] = (s_z[2 * r + w0] & ~m0) | ((t & 2) ? m0 : 0);
-                        s_x[2 * r + w1] = (s_x[2 * r + w1] & ~m1) | ((t & 4) ? m1 : 0);
-                        s_z[2 * r + w1] = (s_z[2 * r + w1] & ~m1) | ((t & 8) ? m1 : 0);
-                        s_ph[r] = static_cast<uint8_t>((s_ph[r] + (t >> 4)) & 3);
-                    }
-                } else {
-                    for (int e = tid; e < m * nn; e += CT) {
-                        const int row = e / nn, col = e - row * nn;
-                        wr[static_cast<int64_t>(col) * 2 * K + row] = thr[e];
-                        wi[static_cast<int64_t>(col) * 2 * K + row] = thi[e];
-                    }
+                    wr[static_cast<int64_t>(col) * 2 * K + row] = xr;
+                    wi[static_cast<int64_t>(col) * 2 * K + row] = xi;
+                }
+                // frame: every row's part on sites k, k+1 conjugated by D
+                const uint8_t* tab = P.dtab + choice * 16;
+                for (int r = tid; r < 2 * n; r += CT) {
+                    const int x1 = getbit(s_x + 2 * r, k), z1 = getbit(s_z + 2 * r, k);
+                    const int x2 = getbit(s_x + 2 * r, k + 1), z2 = getbit(s_z + 2 * r, k + 1);
+                    const int t = tab[x1 | (z1 << 1) | (x2 << 2) | (z2 << 3)];
+                    const int w0 = k >> 6, w1 = (k + 1) >> 6;
+                    const uint64_t m0 = 1ull << (k & 63), m1 = 1ull << ((k + 1) & 63);
+                    s_x[2 * r + w0] = (s_x[2 * r + w0] & ~m0) | ((t & 1) ? m0 : 0);
+                    s_z[2 * r + w0] = (s_z[2 * r + w0] & ~m0) | ((t & 2) ? m0 : 0);
+                    s_x[2 * r + w1] = (s_x[2 * r + w1] & ~m1) | ((t & 4) ? m1 : 0);
+                    s_z[2 * r + w1] = (s_z[2 * r + w1] & ~m1) | ((t & 8) ? m1 : 0);
+                    s_ph[r] = static_cast<uint8_t>((s_ph[r] + (t >> 4)) & 3);
                 }
                 __syncthreads();
-                // split theta: A_k = U, A_{k+1} = S V^dag
+                // split D theta: A_k = U, A_{k+1} = S V^dag
                 double *vr = R.scr + oV, *vi = vr + K * K;
                 note_sweeps(C, jacobi_cols(wr, wi, m, nn, vr, vi, &s_flag));
                 const int rr = select_cols(wr, wi, m, nn, tau, s_sg, s_keep, s_red);

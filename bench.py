@@ -59,7 +59,7 @@ def main() -> int:
                     help="shots of the batch run through the CPU oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--order-budget", type=int, default=24,
+    ap.add_argument("--order-budget", type=int, default=8,
                     help="evaluations of the qubit-order search (extras)")
     ap.add_argument("--lds-width", type=int, default=0)
     ap.add_argument("--slots", type=int, default=0,

@@ -376,9 +376,10 @@ int msc_reweight(const double* bin_n, const double* bin_acc,
    the text's ORDER line, else identity).  Cost of an order = algorithmic
    flops of its noiseless run (msc_circuit_noiseless after calibration on
    ctx's GPU; +inf if that run exceeds the bond cap).  Each of the `budget`
-   evaluations after the first tries one move drawn from a SplitMix64
-   stream keyed by `seed`: exchange two sites, reverse a run of sites, or
-   move one site (probability 1/3 each); a move is kept iff the cost falls.
+   evaluations after the first tries one local move drawn from a
+   SplitMix64 stream keyed by `seed`: exchange two sites at most 4 apart,
+   reverse the run between them, or move one site onto the other's
+   position (probability 1/3 each); a move is kept iff the cost falls.
    order_out (host, n_qubits): the best order; cost_out (host, 2 doubles):
    the start order's cost and the best cost.  Calibration errors other than
    the bond cap are returned.                                              */

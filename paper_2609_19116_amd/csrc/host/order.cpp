@@ -10,11 +10,15 @@
 // the kernel's bond cap costs +inf.
 //
 // The search is a first-improvement local search from the start order:
-// each step proposes one move -- exchange two sites, reverse a run of
-// sites, or move one site elsewhere (one third each) -- drawn from a
-// SplitMix64 stream (Steele, Lea, Flood 2014) keyed by the seed, and keeps
-// it iff the cost falls.  Every proposal costs one evaluation; the search
-// stops after `budget` evaluations.
+// each step proposes one local move -- exchange two sites at most kReach
+// apart, reverse a run of 2 .. kReach + 1 sites, or move one site by at most
+// kReach positions (one third each) -- drawn from a SplitMix64 stream
+// (Steele, Lea, Flood 2014) keyed by the seed, and keeps it iff the cost
+// falls.  Local moves keep the candidates near the current order, whose
+// noiseless runs cost about as much as its own; long-range moves mostly
+// produce orders whose runs are far costlier to evaluate and never win.
+// Every proposal costs one evaluation; the search stops after `budget`
+// evaluations.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -77,11 +81,15 @@ extern "C" int msc_order_search(msc_ctx* ctx, const char* text, size_t len,
     if ((rc = order_cost(ctx, text, len, cur, &best))) return rc;
     cost_out[0] = best;
     Mix rng(seed ^ 0x6F72646572ull);
+    constexpr int kReach = 4;
     for (int32_t ev = 1; ev < budget && n >= 2; ++ev) {
         std::vector<int32_t> cand = cur;
         const int kind = rng.below(3);
-        int i = rng.below(n), j = rng.below(n - 1);
-        if (j >= i) ++j;                    // j != i
+        // i, j distinct sites at most kReach apart
+        int i = rng.below(n);
+        const int lo = std::max(0, i - kReach), hi = std::min(n - 1, i + kReach);
+        int j = lo + rng.below(hi - lo);
+        if (j >= i) ++j;
         if (kind == 0) {
             std::swap(cand[i], cand[j]);
         } else if (kind == 1) {

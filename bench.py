@@ -304,10 +304,12 @@ def main() -> int:
                                   "fail_mismatch": int((res32["fail"] != out64["fail"]).sum()),
                                   "shots": int(len(dp))}
         # CAMPS (FP64 Clifford frame + magic residual) on the same survivors,
-        # all of them in one persistent launch; the step rate adds the batch's
-        # mean screen and sampling times
+        # all of them in one persistent launch, forking from checkpoints of
+        # the noiseless CAMPS run like the batched path; the step rate adds
+        # the batch's mean screen and sampling times
         log("CAMPS on the first batch's survivors")
-        outc = msc.results_numpy(msc.simulate_camps(ctx, circ, off, ch, pa, shot_idx=idx0))
+        outc = msc.results_numpy(msc.simulate_camps(ctx, circ, off, ch, pa, shot_idx=idx0,
+                                                    prefix=not args.no_prefix))
         camps_ms = ctx.last_kernel_ms("camps")
         step_c = camps_ms + float(np.mean(screen_ms)) + float(np.mean(sample_ms))
         dpc = np.abs(outc["p_acc"] - out64["p_acc"])
@@ -318,7 +320,9 @@ def main() -> int:
                            "mps_chi_peak_max": int(out64["chi_peak"].max()),
                            "max_abs_p_acc_vs_mps_fp64": float(dpc.max()),
                            "fail_mismatch_vs_mps_fp64": int((outc["fail"] != out64["fail"]).sum()),
-                           "chi_cap_flagged": int(((outc["status"] & msc.SHOT_CHI_CAP) != 0).sum())}
+                           "chi_cap_flagged": int(((outc["status"] & msc.SHOT_CHI_CAP) != 0).sum()),
+                           "prefix_sharing": not args.no_prefix,
+                           "checkpoint_build_ms": ctx.last_kernel_ms("camps_prefix")}
         # space-time accounting: batches in space-time mode (screen skipped,
         # every shot's probability of reaching each segment), then the
         # expected volume of the noisy segments at p

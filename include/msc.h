@@ -322,8 +322,10 @@ int msc_run_batch(msc_ctx* ctx, const msc_circuit* c, const msc_sim_opts* opts,
    entanglement-lowering two-qubit Clifford of highest purity gain (19
    classes modulo local Cliffords) into the frame.  opts: precision
    MSC_FP64, chi_max in [1, 32] (the residual's bond cap: shots that need
-   more end with MSC_SHOT_CHI_CAP and P_acc 0), prefix, lds_width and
-   reserved 0.  out[i].chi_peak is the residual's peak bond dimension,
+   more end with MSC_SHOT_CHI_CAP and P_acc 0), lds_width and reserved 0;
+   prefix 1 forks every shot from a checkpoint of the noiseless CAMPS run
+   taken before its first fault (built on first use, <= 2 GiB; results are
+   bit-identical to prefix 0).  out[i].chi_peak is the residual's peak bond dimension,
    out[i].n2q the disentangling Cliffords applied; disc_weight and flops
    are 0.  Requires a calibrated circuit with at most 127 qubits.         */
 int msc_simulate_camps(msc_ctx* ctx, const msc_circuit* c, const msc_sim_opts* opts,
@@ -376,10 +378,11 @@ int msc_reweight(const double* bin_n, const double* bin_acc,
    the text's ORDER line, else identity).  Cost of an order = algorithmic
    flops of its noiseless run (msc_circuit_noiseless after calibration on
    ctx's GPU; +inf if that run exceeds the bond cap).  Each of the `budget`
-   evaluations after the first tries one local move drawn from a
-   SplitMix64 stream keyed by `seed`: exchange two sites at most 4 apart,
-   reverse the run between them, or move one site onto the other's
-   position (probability 1/3 each); a move is kept iff the cost falls.
+   evaluations after the first tries one move drawn from a SplitMix64
+   stream keyed by `seed` between sites i and j at distance
+   1 + floor(-4 ln u): exchange them, reverse the run between them, or move
+   site i to position j (probability 1/3 each); a move is kept iff the
+   cost falls.
    order_out (host, n_qubits): the best order; cost_out (host, 2 doubles):
    the start order's cost and the best cost.  Calibration errors other than
    the bond cap are returned.                                              */

@@ -210,15 +210,17 @@ def simulate(ctx: Ctx, circ: Circuit, off, chan, pauli, shot_idx=None, precision
 
 def simulate_camps(ctx: Ctx, circ: Circuit, off, chan, pauli, shot_idx=None,
                    chi_max: int = 32, tau_trunc: float = 0.0, tau_rej: float = 1e-6,
-                   tau_fail: float = 1e-4, n_slots: int = 0, out=None):
+                   tau_fail: float = 1e-4, n_slots: int = 0, prefix: bool = False, out=None):
     """Simulate shots with the Clifford-augmented MPS (FP64); same records
-    as ``simulate`` with chi_peak the magic residual's peak bond."""
+    as ``simulate`` with chi_peak the magic residual's peak bond.  With
+    ``prefix`` shots fork from checkpoints of the noiseless CAMPS run."""
     import torch
     n_shots = off.numel() - 1
     n = shot_idx.numel() if shot_idx is not None else n_shots
     if out is None:
         out = torch.empty(max(n, 1) * SHOT_DTYPE.itemsize, dtype=torch.uint8, device=off.device)
-    o = SimOpts(MSC_FP64, chi_max, tau_trunc, tau_rej, tau_fail, n_slots, 0, 0, 0)
+    o = SimOpts(MSC_FP64, chi_max, tau_trunc, tau_rej, tau_fail, n_slots, 0,
+                1 if prefix else 0, 0)
     _check(lib().msc_simulate_camps(ctx.h, circ.h, C.byref(o), n_shots, _ptr(off), _ptr(chan),
                                     _ptr(pauli), _ptr(shot_idx), n, _ptr(out)))
     return out[: n * SHOT_DTYPE.itemsize]

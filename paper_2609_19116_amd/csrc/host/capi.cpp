@@ -184,8 +184,21 @@ static void free_prefix(PrefixCk& pk) {
     pk = PrefixCk();
 }
 
+static void free_camps_prefix(CampsPrefix& pk) {
+    if (pk.dev >= 0) {
+        (void)hipSetDevice(pk.dev);
+        for (void** p : {&pk.d_op, &pk.d_avail, &pk.d_off, &pk.d_hdr, &pk.d_frame, &pk.d_ph,
+                         &pk.d_data}) {
+            if (*p) (void)hipFree(*p);
+            *p = nullptr;
+        }
+    }
+    pk = CampsPrefix();
+}
+
 static void free_device(msc_circuit* c) {
     free_prefix(c->prefix);
+    free_camps_prefix(c->camps_prefix);
     if (c->dev < 0) return;
     (void)hipSetDevice(c->dev);
     for (void** p : {&c->d_ops, &c->d_g1, &c->d_g4, &c->d_sig, &c->d_expected, &c->d_kind,
@@ -429,6 +442,7 @@ extern "C" int msc_circuit_calibrate(msc_ctx* ctx, msc_circuit* c) {
     MSC_HIP(hipMemcpy(c->d_expected, c->expected.data(), c->n_meas, hipMemcpyHostToDevice));
     c->calibrated = true;
     free_prefix(c->prefix);   // checkpoints follow the expected outcomes
+    free_camps_prefix(c->camps_prefix);
     return MSC_OK;
 }
 
@@ -804,6 +818,89 @@ static int camps_upload(msc_ctx* ctx, msc_circuit* c) {
     return MSC_OK;
 }
 
+static int run_camps(msc_ctx* ctx, msc_circuit* c, int chi_cap, double tau, double tau_rej,
+                     double tau_fail, int n_slots, int64_t n, int64_t n_csr,
+                     const int64_t* shot_off, const int32_t* chan, const uint8_t* pauli,
+                     const int64_t* shot_idx, msc_shot_result* out, int ck_mode,
+                     CampsPrefix* pk, const char* timer);
+
+// Checkpoints of the noiseless CAMPS run: before the fault op of every
+// ck_k-th channel (at most 256 of them) and before the read-out, densely
+// while they fit in kPrefixBytes.  A shot whose first fault is on channel
+// ch forks from checkpoint ch / ck_k: the ops it skips are exactly the
+// fault-free ops it would have run, in the same kernel, so its result does
+// not change.
+static int ensure_camps_prefix(msc_ctx* ctx, msc_circuit* c, int chi_cap, double tau,
+                               double tau_rej, double tau_fail) {
+    CampsPrefix& pk = c->camps_prefix;
+    if (pk.valid && pk.dev == ctx->device && pk.chi_cap == chi_cap && pk.tau == tau &&
+        pk.tau_rej == tau_rej)
+        return MSC_OK;
+    free_camps_prefix(pk);
+    pk.dev = ctx->device;
+    const int M = c->n_channels;
+    std::vector<int32_t> chan_op(M, -1);
+    for (size_t i = 0; i < c->camps_ops.size(); ++i)
+        if (c->camps_ops[i].kind == CO_FAULT) chan_op[c->camps_ops[i].a] = static_cast<int32_t>(i);
+    pk.ck_k = std::max(1, (M + 255) / 256);
+    const int n_reg = (M + pk.ck_k - 1) / pk.ck_k;
+    pk.n_ck = n_reg + 1;
+    std::vector<int32_t> ck_op(pk.n_ck);
+    for (int j = 0; j < n_reg; ++j) ck_op[j] = chan_op[static_cast<size_t>(j) * pk.ck_k];
+    ck_op[n_reg] = static_cast<int32_t>(c->camps_ops.size()) - 1;   // CO_FINAL
+    for (int j = 0; j + 1 < pk.n_ck; ++j)
+        if (!(ck_op[j] >= 0 && ck_op[j] < ck_op[j + 1]))
+            return set_error(MSC_E_INVALID, "CAMPS checkpoint ops not increasing");
+    pk.cap = kPrefixBytes / static_cast<int64_t>(sizeof(double));
+    auto dmalloc = [&](void** p, size_t bytes) -> int {
+        hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 64));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            *p = nullptr;
+            return set_error(MSC_E_OOM, std::string("CAMPS checkpoints: ") + hipGetErrorString(e));
+        }
+        return MSC_OK;
+    };
+    int rc;
+    if ((rc = dmalloc(&pk.d_op, pk.n_ck * sizeof(int32_t)))) return rc;
+    if ((rc = dmalloc(&pk.d_avail, sizeof(int32_t)))) return rc;
+    if ((rc = dmalloc(&pk.d_off, pk.n_ck * sizeof(int64_t)))) return rc;
+    if ((rc = dmalloc(&pk.d_hdr, pk.n_ck * sizeof(CampsCk)))) return rc;
+    if ((rc = dmalloc(&pk.d_frame, static_cast<size_t>(pk.n_ck) * 8 * kMaxSites * sizeof(uint64_t)))) return rc;
+    if ((rc = dmalloc(&pk.d_ph, static_cast<size_t>(pk.n_ck) * 2 * kMaxSites))) return rc;
+    if ((rc = dmalloc(&pk.d_data, static_cast<size_t>(pk.cap) * sizeof(double)))) return rc;
+    const int32_t zero = 0;
+    MSC_HIP(hipMemcpy(pk.d_op, ck_op.data(), pk.n_ck * sizeof(int32_t), hipMemcpyHostToDevice));
+    MSC_HIP(hipMemcpy(pk.d_avail, &zero, sizeof(zero), hipMemcpyHostToDevice));
+    void *doff, *dchan, *dpa, *dout;
+    if ((rc = ctx_buf(ctx, "cal_off", 2 * sizeof(int64_t), &doff))) return rc;
+    if ((rc = ctx_buf(ctx, "cal_chan", 64, &dchan))) return rc;
+    if ((rc = ctx_buf(ctx, "cal_pa", 64, &dpa))) return rc;
+    if ((rc = ctx_buf(ctx, "cal_out", sizeof(msc_shot_result), &dout))) return rc;
+    int64_t zz[2] = {0, 0};
+    MSC_HIP(hipMemcpy(doff, zz, sizeof(zz), hipMemcpyHostToDevice));
+    rc = run_camps(ctx, c, chi_cap, tau, tau_rej, tau_fail, 1, 1, 1, static_cast<int64_t*>(doff),
+                   static_cast<int32_t*>(dchan), static_cast<uint8_t*>(dpa), nullptr,
+                   static_cast<msc_shot_result*>(dout), 1, &pk, "camps_prefix");
+    if (rc) {
+        free_camps_prefix(pk);
+        return rc;
+    }
+    MSC_HIP(hipMemcpy(&pk.avail, pk.d_avail, sizeof(int32_t), hipMemcpyDeviceToHost));
+    msc_shot_result res;
+    MSC_HIP(hipMemcpy(&res, dout, sizeof(res), hipMemcpyDeviceToHost));
+    if (!(res.status & MSC_SHOT_DONE)) {
+        free_camps_prefix(pk);
+        return set_error(MSC_E_NONDETERMINISTIC, "noiseless CAMPS run did not complete");
+    }
+    pk.chi_cap = chi_cap;
+    pk.tau = tau;
+    pk.tau_rej = tau_rej;
+    pk.build_ms = static_cast<float>(ctx->last_ms["camps_prefix"]);
+    pk.valid = true;
+    return MSC_OK;
+}
+
 extern "C" int msc_simulate_camps(msc_ctx* ctx, const msc_circuit* c, const msc_sim_opts* opts,
                                   int64_t n_shots, const int64_t* shot_off, const int32_t* chan,
                                   const uint8_t* pauli, const int64_t* shot_idx, int64_t n_sel,
@@ -817,13 +914,30 @@ extern "C" int msc_simulate_camps(msc_ctx* ctx, const msc_circuit* c, const msc_
     if (opts->chi_max < 1 || opts->chi_max > kCampsCap)
         return set_error(MSC_E_INVALID, "CAMPS chi_max must be in [1, 32]");
     if (c->n > kMaxSites - 1) return set_error(MSC_E_INVALID, "CAMPS takes at most 127 qubits");
-    if (opts->prefix != 0 || opts->reserved != 0 || opts->lds_width != 0)
-        return set_error(MSC_E_INVALID, "CAMPS takes no prefix, lds_width or reserved option");
+    if ((opts->prefix != 0 && opts->prefix != 1) || opts->reserved != 0 || opts->lds_width != 0)
+        return set_error(MSC_E_INVALID, "CAMPS takes prefix 0 or 1, no lds_width or reserved option");
     if (n == 0) return MSC_OK;
     MSC_HIP(hipSetDevice(ctx->device));
-    int rc = camps_upload(ctx, const_cast<msc_circuit*>(c));
+    msc_circuit* cc = const_cast<msc_circuit*>(c);
+    int rc = camps_upload(ctx, cc);
     if (rc) return rc;
-    int n_slots = opts->n_slots > 0 ? opts->n_slots : ctx->n_cu * camps_blocks_per_cu();
+    const double tau = opts->tau_trunc > 0 ? opts->tau_trunc : 1e-12;
+    const double tau_rej = opts->tau_rej > 0 ? opts->tau_rej : 1e-6;
+    const double tau_fail = opts->tau_fail > 0 ? opts->tau_fail : 1e-4;
+    if (opts->prefix && (rc = ensure_camps_prefix(ctx, cc, opts->chi_max, tau, tau_rej, tau_fail)))
+        return rc;
+    return run_camps(ctx, cc, opts->chi_max, tau, tau_rej, tau_fail, opts->n_slots, n, n_shots,
+                     shot_off, chan, pauli, shot_idx, out, opts->prefix ? 2 : 0,
+                     opts->prefix ? &cc->camps_prefix : nullptr, "camps");
+}
+
+static int run_camps(msc_ctx* ctx, msc_circuit* c, int chi_cap, double tau, double tau_rej,
+                     double tau_fail, int n_slots, int64_t n, int64_t n_csr,
+                     const int64_t* shot_off, const int32_t* chan, const uint8_t* pauli,
+                     const int64_t* shot_idx, msc_shot_result* out, int ck_mode,
+                     CampsPrefix* pk, const char* timer) {
+    int rc;
+    if (n_slots <= 0) n_slots = ctx->n_cu * camps_blocks_per_cu();
     n_slots = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(n_slots, n)));
     void *arena, *scratch;
     if ((rc = ctx_buf(ctx, "camps_arena",
@@ -843,17 +957,30 @@ extern "C" int msc_simulate_camps(msc_ctx* ctx, const msc_circuit* c, const msc_
     a.pauli = pauli;
     a.shot_idx = shot_idx;
     a.n_shots = n;
-    a.n_csr = n_shots;
+    a.n_csr = n_csr;
     a.expected = static_cast<const uint8_t*>(c->d_expected);
     a.out = out;
     a.arena = static_cast<double*>(arena);
     a.scratch = static_cast<double*>(scratch);
     a.dmat = static_cast<const double*>(c->d_dmat);
     a.dtab = static_cast<const uint8_t*>(c->d_dtab);
-    a.chi_cap = opts->chi_max;
-    a.tau = opts->tau_trunc > 0 ? opts->tau_trunc : 1e-12;
-    a.tau_rej = opts->tau_rej > 0 ? opts->tau_rej : 1e-6;
-    a.tau_fail = opts->tau_fail > 0 ? opts->tau_fail : 1e-4;
+    a.chi_cap = chi_cap;
+    a.tau = tau;
+    a.tau_rej = tau_rej;
+    a.tau_fail = tau_fail;
+    a.ck_mode = pk ? ck_mode : 0;
+    if (a.ck_mode) {
+        a.n_ck = pk->n_ck;
+        a.ck_k = pk->ck_k;
+        a.ck_op = static_cast<const int32_t*>(pk->d_op);
+        a.ck_avail = static_cast<int32_t*>(pk->d_avail);
+        a.ck_off = static_cast<int64_t*>(pk->d_off);
+        a.ck_hdr = static_cast<CampsCk*>(pk->d_hdr);
+        a.ck_frame = static_cast<uint64_t*>(pk->d_frame);
+        a.ck_ph = static_cast<uint8_t*>(pk->d_ph);
+        a.ck_data = static_cast<double*>(pk->d_data);
+        a.ck_cap = pk->cap;
+    }
     const double r = 1.0 / std::sqrt(2.0);
     if (c->target == 'T') {
         a.rt[0] = r;
@@ -869,7 +996,7 @@ extern "C" int msc_simulate_camps(msc_ctx* ctx, const msc_circuit* c, const msc_
     MSC_HIP(hipStreamSynchronize(ctx->stream));
     float ms = 0.f;
     MSC_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-    ctx->last_ms["camps"] = ms;
+    ctx->last_ms[timer] = ms;
     return MSC_OK;
 }
 

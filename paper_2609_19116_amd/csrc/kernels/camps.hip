@@ -715,6 +715,51 @@ __global__ __launch_bounds__(CT) void camps_kernel(CampsArgs P) {
         const int64_t fend = P.shot_off[shot + 1];
         int64_t n_dis = 0;
         const double tau = P.tau;
+        int start = 0;
+        if (P.ck_mode == 2) {
+            // fork from the last checkpoint of the noiseless run before the
+            // shot's first fault (the ops before it are fault-free here)
+            const int navail = *P.ck_avail;
+            const int jj = fcur < fend ? P.chan[fcur] / P.ck_k : P.n_ck - 1;
+            const int jck = jj < navail ? jj : navail - 1;
+            if (jck >= 0) {
+                const CampsCk& h = P.ck_hdr[jck];
+                for (int k = tid; k <= n; k += CT) s_chi[k] = h.chi[k];
+                for (int q = tid; q < n; q += CT) s_laste[q] = h.laste[q];
+                const uint64_t* fw = P.ck_frame + static_cast<int64_t>(jck) * 4 * NR;
+                for (int w = tid; w < 4 * n; w += CT) {
+                    s_x[w] = fw[w];
+                    s_z[w] = fw[2 * NR + w];
+                }
+                for (int r = tid; r < 2 * n; r += CT)
+                    s_ph[r] = P.ck_ph[static_cast<int64_t>(jck) * 2 * kMaxSites + r];
+                __syncthreads();
+                const double* src = P.ck_data + P.ck_off[jck];
+                int64_t o = 0;
+                for (int k = 0; k < n; ++k) {
+                    const int ne = s_chi[k] * 2 * s_chi[k + 1];
+                    double *dr = R.re(k), *di = R.im(k);
+                    for (int e = tid; e < ne; e += CT) {
+                        dr[e] = src[o + e];
+                        di[e] = src[o + ne + e];
+                    }
+                    o += 2 * ne;
+                }
+                if (tid == 0) {
+                    s_center = h.center;
+                    s_status = h.status;
+                    s_sweeps = h.sweeps;
+                    s_peak = h.peak;
+                }
+                p_acc = h.p_acc;
+                n_dis = h.n_dis;
+                start = P.ck_op[jck];
+                __syncthreads();
+            }
+        }
+        int next_ck = 0;              // record mode: next checkpoint to take
+        int64_t ck_pos = 0;           // record mode: doubles written so far
+        bool ck_full = false;
 
         // greedy disentangling sweep over bonds k0..k1.  Per bond, theta
         // (sites k, k+1) and the Gram matrix of its smaller side give the
@@ -910,7 +955,50 @@ __global__ __launch_bounds__(CT) void camps_kernel(CampsArgs P) {
             }
         };
 
-        for (int oi = 0; oi < P.n_ops && alive; ++oi) {
+        for (int oi = start; oi < P.n_ops && alive; ++oi) {
+            if (P.ck_mode == 1 && !ck_full && next_ck < P.n_ck && P.ck_op[next_ck] == oi) {
+                // ---- record: the frame and the residual before op oi
+                int64_t sz = 0;
+                for (int k = 0; k < n; ++k) sz += 4LL * s_chi[k] * s_chi[k + 1];
+                if (ck_pos + sz <= P.ck_cap) {
+                    double* dst = P.ck_data + ck_pos;
+                    int64_t o = 0;
+                    for (int k = 0; k < n; ++k) {
+                        const int ne = s_chi[k] * 2 * s_chi[k + 1];
+                        const double *sr = R.re(k), *si = R.im(k);
+                        for (int e = tid; e < ne; e += CT) {
+                            dst[o + e] = sr[e];
+                            dst[o + ne + e] = si[e];
+                        }
+                        o += 2 * ne;
+                    }
+                    uint64_t* fw = P.ck_frame + static_cast<int64_t>(next_ck) * 4 * NR;
+                    for (int w = tid; w < 4 * n; w += CT) {
+                        fw[w] = s_x[w];
+                        fw[2 * NR + w] = s_z[w];
+                    }
+                    for (int r = tid; r < 2 * n; r += CT)
+                        P.ck_ph[static_cast<int64_t>(next_ck) * 2 * kMaxSites + r] = s_ph[r];
+                    CampsCk& h = P.ck_hdr[next_ck];
+                    for (int k = tid; k <= n; k += CT) h.chi[k] = s_chi[k];
+                    for (int q = tid; q < n; q += CT) h.laste[q] = s_laste[q];
+                    if (tid == 0) {
+                        h.p_acc = p_acc;
+                        h.n_dis = n_dis;
+                        h.center = s_center;
+                        h.status = s_status;
+                        h.sweeps = s_sweeps;
+                        h.peak = s_peak;
+                        P.ck_off[next_ck] = ck_pos;
+                    }
+                    ck_pos += sz;
+                    __syncthreads();
+                    if (tid == 0) *P.ck_avail = next_ck + 1;
+                    ++next_ck;
+                } else {
+                    ck_full = true;
+                }
+            }
             const DevOp op = P.ops[oi];
             if (op.kind == CO_G1) {
                 if (tid == 0) {

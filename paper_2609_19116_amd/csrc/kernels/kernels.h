@@ -132,6 +132,17 @@ constexpr int kCampsCand = 19;     // two-qubit Clifford classes tried per bond
 constexpr int64_t kCampsSiteDoubles = 4LL * kCampsK * kCampsK;   // re + im
 constexpr int64_t kCampsScratch = 98304;                         // doubles per slot
 
+// Header of one checkpoint of the noiseless CAMPS run (the frame and the
+// residual right before a given op; tensors densely at ck_off[j], site by
+// site, real plane then imaginary plane)
+struct CampsCk {
+    double p_acc;
+    int64_t n_dis;
+    int32_t center, status, sweeps, peak;
+    int32_t chi[kMaxSites + 1];
+    uint8_t laste[kMaxSites];
+};
+
 struct CampsArgs {
     const DevOp* ops;          // CAMPS op stream (CampsKind)
     int32_t n_ops;
@@ -153,6 +164,19 @@ struct CampsArgs {
     int32_t chi_cap;           // <= kCampsCap
     double tau, tau_rej, tau_fail;
     double rt[3];              // Bloch vector of the target state
+    // checkpoints of the noiseless run: ck_mode 0 off, 1 record them from
+    // the single fault-free shot, 2 start every shot from one of them
+    int32_t ck_mode, n_ck, ck_k;
+    const int32_t* ck_op;      // [n_ck] op index (before channel j * ck_k's
+                               // fault op, the last before CO_FINAL)
+    int32_t* ck_avail;
+    int64_t* ck_off;
+    CampsCk* ck_hdr;
+    uint64_t* ck_frame;        // [n_ck][8 * kMaxSites]: x words, then z words
+                               // (2 words for each of the 2 kMaxSites rows)
+    uint8_t* ck_ph;            // [n_ck][2 * kMaxSites]
+    double* ck_data;
+    int64_t ck_cap;
 };
 hipError_t launch_camps(const CampsArgs& a, int grid, hipStream_t s);
 int camps_blocks_per_cu();

@@ -95,6 +95,19 @@ struct PrefixCk {
     void* d_pm = nullptr;     // [n_meas] running P_acc before each measurement
 };
 
+// Device checkpoints of the noiseless CAMPS run (msc_simulate_camps with
+// prefix = 1), built on first use for one (chi cap, tau, tau_rej) set.
+struct CampsPrefix {
+    bool valid = false;
+    int dev = -1, chi_cap = 0;
+    double tau = 0.0, tau_rej = 0.0;
+    int n_ck = 0, ck_k = 1, avail = 0;
+    int64_t cap = 0;           // doubles of tensor storage
+    float build_ms = 0.f;
+    void *d_op = nullptr, *d_avail = nullptr, *d_off = nullptr, *d_hdr = nullptr;
+    void *d_frame = nullptr, *d_ph = nullptr, *d_data = nullptr;
+};
+
 struct msc_circuit {
     int n = 0;
     int seed = 0;
@@ -124,6 +137,7 @@ struct msc_circuit {
     void* d_site_of = nullptr;
     void* d_dmat = nullptr;              // candidate tables (camps_candidates)
     void* d_dtab = nullptr;
+    CampsPrefix camps_prefix;
     // offline screening tables
     int words = 0;
     std::vector<int32_t> decided;        // measurement index per decided slot

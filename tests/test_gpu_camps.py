@@ -82,6 +82,20 @@ def test_camps_equals_mps_path(ctx, name, n):
           f"camps {ctx.last_kernel_ms('camps'):.1f} ms", flush=True)
 
 
+@pytest.mark.parametrize("name,n", [("c1", 400), ("c3", 256)])
+def test_camps_prefix_bit_identical(ctx, name, n):
+    cc, circ = _circ(ctx, name)
+    say(f"camps prefix {name} n={n}")
+    off, ch, pa = msc.sample_faults_device(ctx, circ, 0x5EED0074, 0, n, p=3e-3)
+    a = results_numpy(msc.simulate_camps(ctx, circ, off, ch, pa))
+    ta = ctx.last_kernel_ms("camps")
+    b = results_numpy(msc.simulate_camps(ctx, circ, off, ch, pa, prefix=True))
+    tb = ctx.last_kernel_ms("camps")
+    for f in ("p_acc", "infid", "chi_peak", "status", "rejected_at", "fail", "n2q", "sweeps"):
+        assert np.array_equal(a[f], b[f]), f
+    print(f"{name}: {ta:.1f} ms from |0...0>, {tb:.1f} ms forked", flush=True)
+
+
 def test_camps_clifford_circuit_has_product_residual(ctx):
     cc, circ = _circ(ctx, "c1", target="S")
     n = 64

@@ -96,3 +96,28 @@ def test_order_search_errors(ctx):
         msc.order_search(ctx, "QUBITS 2\nFOO 0\n", 1, 5)         # parse error
     with pytest.raises(msc.MscError):
         msc.order_search(ctx, "QUBITS 3\nH 0\n", 1, 5, start=[0, 0, 1])
+
+
+def test_benchmark_layout_changes_no_result(ctx):
+    # the 49-qubit workload under the order the benchmark's search finds
+    # (same seed and budget) against its snake order, FP64, sampled shots
+    cc = config_circuit("c3")
+    say("order search c3 budget 64 (the benchmark's), then 128 FP64 shots on both layouts")
+    order, c0, c1 = msc.order_search(ctx, cc.text, 0x5EED0081, 64)
+    assert c1 <= c0
+    snake = msc.Circuit(cc.text)
+    snake.calibrate(ctx)
+    searched = msc.Circuit(cc.text, order=order)
+    searched.calibrate(ctx)
+    n = 128
+    w = np.array([0, 1, 2, 3] * (n // 4), dtype=np.int32)
+    off, ch, pa = msc.sample_faults_device(ctx, snake, 0x5EED0035, 0, n, weights=w)
+    a = results_numpy(msc.simulate(ctx, snake, off, ch, pa, precision=MSC_FP64))
+    b = results_numpy(msc.simulate(ctx, searched, off, ch, pa, precision=MSC_FP64))
+    assert np.array_equal(a["rejected_at"], b["rejected_at"])
+    assert np.allclose(a["p_acc"], b["p_acc"], atol=1e-9, rtol=0)
+    acc = a["p_acc"] > 0
+    assert np.allclose(a["infid"][acc], b["infid"][acc], atol=1e-9, rtol=0)
+    assert np.array_equal(a["fail"], b["fail"])
+    print(f"c3: noiseless flops snake {c0:.4g} searched {c1:.4g}; mean shot flops "
+          f"{a['flops'].mean():.4g} -> {b['flops'].mean():.4g}", flush=True)

@@ -328,8 +328,12 @@ def main() -> int:
         # all of them in one persistent launch, forking from checkpoints of
         # the noiseless CAMPS run like the batched path; the step rate adds
         # the batch's mean screen and sampling times
+        # on the snake layout: the searched order cuts the MPS work but not
+        # the residual's (the frame absorbs what the order buys the MPS)
         log("CAMPS on the first batch's survivors")
-        outc = msc.results_numpy(msc.simulate_camps(ctx, circ, off, ch, pa, shot_idx=idx0,
+        circ_cs = msc.Circuit(cc.text)
+        circ_cs.calibrate(ctx)
+        outc = msc.results_numpy(msc.simulate_camps(ctx, circ_cs, off, ch, pa, shot_idx=idx0,
                                                     prefix=not args.no_prefix))
         camps_ms = ctx.last_kernel_ms("camps")
         step_c = camps_ms + float(np.mean(screen_ms)) + float(np.mean(sample_ms))
@@ -342,7 +346,7 @@ def main() -> int:
                            "max_abs_p_acc_vs_mps_fp64": float(dpc.max()),
                            "fail_mismatch_vs_mps_fp64": int((outc["fail"] != out64["fail"]).sum()),
                            "chi_cap_flagged": int(((outc["status"] & msc.SHOT_CHI_CAP) != 0).sum()),
-                           "prefix_sharing": not args.no_prefix,
+                           "prefix_sharing": not args.no_prefix, "layout": "snake",
                            "checkpoint_build_ms": ctx.last_kernel_ms("camps_prefix")}
         # space-time accounting: batches in space-time mode (screen skipped,
         # every shot's probability of reaching each segment), then the

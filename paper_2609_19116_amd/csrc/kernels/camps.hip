@@ -120,17 +120,126 @@ __device__ __forceinline__ void pauli_elem(int x, int z, int i, int& src, double
     sg = (z && src) ? -1.0 : 1.0;
 }
 
-// One-sided Jacobi on the columns of W (len x nv, column-major, ld 2K):
-// W <- W V with V (nv x nv, column-major, ld K) unitary and the columns of
-// the result mutually orthogonal.  Returns the sweeps used (-1: no
+// Work matrices of one SVD: W (len x nv, column-major, leading dimension
+// ldw) and V (nv x nv, column-major, ldv), in LDS when they fit (len <=
+// kWaveLen, nv <= kWaveCols: one wavefront factorises them without
+// workgroup barriers) and otherwise in the slot's global scratch.
+constexpr int kWaveLen = 64, kWaveCols = 32;
+struct WV {
+    double *wr, *wi, *vr, *vi;
+    int ldw, ldv;
+    bool wave;
+};
+
+// a fence that makes this wavefront's LDS and global writes visible to all
+// of its lanes, without a workgroup barrier
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// one Jacobi rotation of the pair (p, q) by a group of G lanes (lane l):
+// returns whether it rotated
+__device__ __forceinline__ bool jacobi_pair(const WV& w, int len, int nv, int p, int q, int G,
+                                            int l) {
+    const bool live = p < nv && q < nv;
+    double a = 0, b = 0, gr = 0, gi = 0;
+    if (live) {
+        const double *xr = w.wr + p * w.ldw, *xi = w.wi + p * w.ldw;
+        const double *yr = w.wr + q * w.ldw, *yi = w.wi + q * w.ldw;
+        for (int r = l; r < len; r += G) {
+            a += xr[r] * xr[r] + xi[r] * xi[r];
+            b += yr[r] * yr[r] + yi[r] * yi[r];
+            // gamma = x^H y
+            gr += xr[r] * yr[r] + xi[r] * yi[r];
+            gi += xr[r] * yi[r] - xi[r] * yr[r];
+        }
+    }
+    for (int o = G / 2; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+        gr += __shfl_xor(gr, o);
+        gi += __shfl_xor(gi, o);
+    }
+    const double gm = sqrt(gr * gr + gi * gi);
+    if (!(live && a > 1e-300 && b > 1e-300 && gm > 1e-15 * sqrt(a * b))) return false;
+    const double d = b - a;
+    const double D = fabs(d) + sqrt(d * d + 4.0 * gm * gm);
+    const double rq = 1.0 / sqrt(D * D + 4.0 * gm * gm);
+    const double c = D * rq;
+    const double sg = 2.0 * (d >= 0.0 ? 1.0 : -1.0) * rq;
+    // x <- c x - sg conj(gamma) y ; y <- c y + sg gamma x
+    const double ur = sg * gr, ui = sg * gi;
+    auto rot = [&](double* xr, double* xi, double* yr, double* yi, int r) {
+        const double x0r = xr[r], x0i = xi[r], y0r = yr[r], y0i = yi[r];
+        xr[r] = c * x0r - (ur * y0r + ui * y0i);
+        xi[r] = c * x0i - (ur * y0i - ui * y0r);
+        yr[r] = c * y0r + (ur * x0r - ui * x0i);
+        yi[r] = c * y0i + (ur * x0i + ui * x0r);
+    };
+    for (int r = l; r < len; r += G)
+        rot(w.wr + p * w.ldw, w.wi + p * w.ldw, w.wr + q * w.ldw, w.wi + q * w.ldw, r);
+    for (int r = l; r < nv; r += G) rot(w.vr + p * w.ldv, w.vi + p * w.ldv, w.vr + q * w.ldv, w.vi + q * w.ldv, r);
+    return true;
+}
+
+// pair i of round t of the round-robin over m (even) columns
+__device__ __forceinline__ void rr_pair(int i, int t, int m, int& p, int& q) {
+    const int i1 = m - 1 - i;
+    p = i == 0 ? 0 : 1 + (i - 1 + t) % (m - 1);
+    q = i1 == 0 ? 0 : 1 + (i1 - 1 + t) % (m - 1);
+}
+
+// One-sided Jacobi on the columns of W: W <- W V with V unitary and the
+// columns of the result mutually orthogonal.  Whole workgroup; the LDS
+// variant runs on wavefront 0 alone.  Returns the sweeps used (-1: no
 // convergence).
-__device__ int jacobi_cols(double* wr, double* wi, int len, int nv, double* vr, double* vi,
-                           int* s_flag) {
+__device__ int jacobi_cols(const WV& w, int len, int nv, int* s_flag) {
     const int tid = threadIdx.x;
+    if (w.wave) {
+        __shared__ int s_sw;
+        if (tid < 64) {
+            for (int e = tid; e < nv * nv; e += 64) {
+                const int col = e / nv, row = e - col * nv;
+                w.vr[col * w.ldv + row] = row == col ? 1.0 : 0.0;
+                w.vi[col * w.ldv + row] = 0.0;
+            }
+            wave_sync();
+            int used = 0;
+            if (nv >= 2) {
+                const int m = nv + (nv & 1), np = m / 2;
+                int G = 64;
+                while (G > 1 && G * np > 64) G >>= 1;
+                const int g = tid / G, l = tid - g * G;
+                used = -1;
+                for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+                    int rotated = 0;
+                    for (int t = 0; t < m - 1; ++t) {
+                        if (g < np) {
+                            int p, q;
+                            rr_pair(g, t, m, p, q);
+                            if (jacobi_pair(w, len, nv, p, q, G, l)) rotated = 1;
+                        }
+                        wave_sync();
+                    }
+                    if (__ballot(rotated) == 0ull) {
+                        used = sweep + 1;
+                        break;
+                    }
+                }
+            }
+            if (tid == 0) s_sw = used;
+        }
+        __syncthreads();
+        const int used = s_sw;
+        __syncthreads();
+        return used;
+    }
     for (int e = tid; e < nv * nv; e += CT) {
         const int col = e / nv, row = e - col * nv;
-        vr[col * K + row] = row == col ? 1.0 : 0.0;
-        vi[col * K + row] = 0.0;
+        w.vr[col * w.ldv + row] = row == col ? 1.0 : 0.0;
+        w.vi[col * w.ldv + row] = 0.0;
     }
     __syncthreads();
     if (nv < 2) return 0;
@@ -144,53 +253,9 @@ __device__ int jacobi_cols(double* wr, double* wi, int len, int nv, double* vr, 
         __syncthreads();
         for (int t = 0; t < m - 1; ++t) {
             if (g < np) {
-                const int i0 = g, i1 = m - 1 - g;
-                const int p = i0 == 0 ? 0 : 1 + (i0 - 1 + t) % (m - 1);
-                const int q = i1 == 0 ? 0 : 1 + (i1 - 1 + t) % (m - 1);
-                const bool live = p < nv && q < nv;
-                double a = 0, b = 0, gr = 0, gi = 0;
-                if (live) {
-                    const double* xr = wr + static_cast<int64_t>(p) * 2 * K;
-                    const double* xi = wi + static_cast<int64_t>(p) * 2 * K;
-                    const double* yr = wr + static_cast<int64_t>(q) * 2 * K;
-                    const double* yi = wi + static_cast<int64_t>(q) * 2 * K;
-                    for (int r = l; r < len; r += G) {
-                        a += xr[r] * xr[r] + xi[r] * xi[r];
-                        b += yr[r] * yr[r] + yi[r] * yi[r];
-                        // gamma = x^H y
-                        gr += xr[r] * yr[r] + xi[r] * yi[r];
-                        gi += xr[r] * yi[r] - xi[r] * yr[r];
-                    }
-                }
-                for (int o = G / 2; o > 0; o >>= 1) {
-                    a += __shfl_xor(a, o);
-                    b += __shfl_xor(b, o);
-                    gr += __shfl_xor(gr, o);
-                    gi += __shfl_xor(gi, o);
-                }
-                const double gm = sqrt(gr * gr + gi * gi);
-                if (live && a > 1e-300 && b > 1e-300 && gm > 1e-15 * sqrt(a * b)) {
-                    const double d = b - a;
-                    const double D = fabs(d) + sqrt(d * d + 4.0 * gm * gm);
-                    const double rq = 1.0 / sqrt(D * D + 4.0 * gm * gm);
-                    const double c = D * rq;
-                    const double sg = 2.0 * (d >= 0.0 ? 1.0 : -1.0) * rq;
-                    // x <- c x - sg conj(gamma) y ; y <- c y + sg gamma x
-                    const double ur = sg * gr, ui = sg * gi;
-                    auto rot = [&](double* xr, double* xi, double* yr, double* yi, int r) {
-                        const double x0r = xr[r], x0i = xi[r], y0r = yr[r], y0i = yi[r];
-                        xr[r] = c * x0r - (ur * y0r + ui * y0i);
-                        xi[r] = c * x0i - (ur * y0i - ui * y0r);
-                        yr[r] = c * y0r + (ur * x0r - ui * x0i);
-                        yi[r] = c * y0i + (ur * x0i + ui * x0r);
-                    };
-                    for (int r = l; r < len; r += G)
-                        rot(wr + static_cast<int64_t>(p) * 2 * K, wi + static_cast<int64_t>(p) * 2 * K,
-                            wr + static_cast<int64_t>(q) * 2 * K, wi + static_cast<int64_t>(q) * 2 * K, r);
-                    for (int r = l; r < nv; r += G)
-                        rot(vr + p * K, vi + p * K, vr + q * K, vi + q * K, r);
-                    if (l == 0) *s_flag = 1;
-                }
+                int p, q;
+                rr_pair(g, t, m, p, q);
+                if (jacobi_pair(w, len, nv, p, q, G, l) && l == 0) *s_flag = 1;
             }
             __syncthreads();
         }
@@ -203,14 +268,14 @@ __device__ int jacobi_cols(double* wr, double* wi, int len, int nv, double* vr, 
 
 // column norms of W (nv columns) into sg[], kept columns (sigma > tau *
 // sigma_max, in order) into keep[]; returns how many
-__device__ int select_cols(const double* wr, const double* wi, int len, int nv, double tau,
-                           double* sg, int* keep, double* red) {
+__device__ int select_cols(const WV& w, int len, int nv, double tau, double* sg, int* keep,
+                           double* red) {
     const int tid = threadIdx.x;
     for (int col = tid; col < nv; col += CT) {
         double s = 0;
         for (int r = 0; r < len; ++r) {
-            const double a = wr[static_cast<int64_t>(col) * 2 * K + r];
-            const double b = wi[static_cast<int64_t>(col) * 2 * K + r];
+            const double a = w.wr[col * w.ldw + r];
+            const double b = w.wi[col * w.ldw + r];
             s += a * a + b * b;
         }
         sg[col] = sqrt(s);
@@ -244,7 +309,30 @@ struct Ctl {
     int* sweeps;      // LDS: Jacobi sweeps
     int* chi_peak;    // LDS
     int* old;         // LDS [kMaxSites + 1]: bonds before apply_sum
+    double *lwr, *lwi, *lvr, *lvi;   // LDS work matrices of the wave SVDs
 };
+
+__device__ __forceinline__ WV work_mats(const Res& R, const Ctl& c, int len, int nv) {
+    WV w;
+    if (len <= kWaveLen && nv <= kWaveCols) {
+        w.wr = c.lwr;
+        w.wi = c.lwi;
+        w.vr = c.lvr;
+        w.vi = c.lvi;
+        w.ldw = kWaveLen;
+        w.ldv = kWaveCols;
+        w.wave = true;
+    } else {
+        w.wr = R.scr + oW;
+        w.wi = w.wr + 2LL * K * K;
+        w.vr = R.scr + oV;
+        w.vi = w.vr + K * K;
+        w.ldw = 2 * K;
+        w.ldv = K;
+        w.wave = false;
+    }
+    return w;
+}
 
 __device__ void note_sweeps(const Ctl& c, int sw) {
     if (threadIdx.x == 0) {
@@ -257,25 +345,26 @@ __device__ void note_sweeps(const Ctl& c, int sw) {
 __device__ void move_right(const Res& R, const Ctl& c, int k, double tau) {
     const int tid = threadIdx.x;
     const int cl = R.chi[k], cr = R.chi[k + 1], cn = R.chi[k + 2];
-    double *wr = R.scr + oW, *wi = wr + 2LL * K * K;
-    double *vr = R.scr + oV, *vi = vr + K * K;
     const double *ar = R.re(k), *ai = R.im(k);
     const int len = 2 * cl;
+    const WV w = work_mats(R, c, len, cr);
+    double *wr = w.wr, *wi = w.wi, *vr = w.vr, *vi = w.vi;
+    const int ldw = w.ldw, ldv = w.ldv;
     for (int e = tid; e < len * cr; e += CT) {
         const int row = e / cr, b = e - row * cr;
-        wr[static_cast<int64_t>(b) * 2 * K + row] = ar[row * cr + b];
-        wi[static_cast<int64_t>(b) * 2 * K + row] = ai[row * cr + b];
+        wr[b * ldw + row] = ar[row * cr + b];
+        wi[b * ldw + row] = ai[row * cr + b];
     }
     __syncthreads();
-    note_sweeps(c, jacobi_cols(wr, wi, len, cr, vr, vi, c.flag));
-    const int r = select_cols(wr, wi, len, cr, tau, c.sg, c.keep, c.red);
+    note_sweeps(c, jacobi_cols(w, len, cr, c.flag));
+    const int r = select_cols(w, len, cr, tau, c.sg, c.keep, c.red);
     double *Ar = R.re(k), *Ai = R.im(k);
     for (int e = tid; e < len * r; e += CT) {
         const int row = e / r, j = e - row * r;
         const int col = c.keep[j];
         const double s = 1.0 / c.sg[col];
-        Ar[row * r + j] = wr[static_cast<int64_t>(col) * 2 * K + row] * s;
-        Ai[row * r + j] = wi[static_cast<int64_t>(col) * 2 * K + row] * s;
+        Ar[row * r + j] = wr[col * ldw + row] * s;
+        Ai[row * r + j] = wi[col * ldw + row] * s;
     }
     // next site: (S V^dag) A_{k+1}, via TH
     double *tr = R.scr + oTH, *ti = tr + 2LL * K * K;
@@ -288,7 +377,7 @@ __device__ void move_right(const Res& R, const Ctl& c, int k, double tau) {
         double xr = 0, xi = 0;
         for (int b = 0; b < cr; ++b) {
             // conj(V[b][col]) * A[b][col2]
-            const double v_r = vr[col * K + b], v_i = -vi[col * K + b];
+            const double v_r = vr[col * ldv + b], v_i = -vi[col * ldv + b];
             const double a_r = br[b * nb + col2], a_i = bi[b * nb + col2];
             xr += v_r * a_r - v_i * a_i;
             xi += v_r * a_i + v_i * a_r;
@@ -314,26 +403,27 @@ __device__ void move_right(const Res& R, const Ctl& c, int k, double tau) {
 __device__ void move_left(const Res& R, const Ctl& c, int k, double tau) {
     const int tid = threadIdx.x;
     const int cp = R.chi[k - 1], cl = R.chi[k], cr = R.chi[k + 1];
-    double *wr = R.scr + oW, *wi = wr + 2LL * K * K;
-    double *vr = R.scr + oV, *vi = vr + K * K;
     const double *ar = R.re(k), *ai = R.im(k);
     const int len = 2 * cr;
+    const WV w = work_mats(R, c, len, cl);
+    double *wr = w.wr, *wi = w.wi, *vr = w.vr, *vi = w.vi;
+    const int ldw = w.ldw, ldv = w.ldv;
     // W = A^dag: column a holds conj(A[a, :])
     for (int e = tid; e < cl * len; e += CT) {
         const int a = e / len, x = e - a * len;
-        wr[static_cast<int64_t>(a) * 2 * K + x] = ar[a * len + x];
-        wi[static_cast<int64_t>(a) * 2 * K + x] = -ai[a * len + x];
+        wr[a * ldw + x] = ar[a * len + x];
+        wi[a * ldw + x] = -ai[a * len + x];
     }
     __syncthreads();
-    note_sweeps(c, jacobi_cols(wr, wi, len, cl, vr, vi, c.flag));
-    const int r = select_cols(wr, wi, len, cl, tau, c.sg, c.keep, c.red);
+    note_sweeps(c, jacobi_cols(w, len, cl, c.flag));
+    const int r = select_cols(w, len, cl, tau, c.sg, c.keep, c.red);
     double *Ar = R.re(k), *Ai = R.im(k);
     for (int e = tid; e < r * len; e += CT) {
         const int j = e / len, x = e - j * len;
         const int col = c.keep[j];
         const double s = 1.0 / c.sg[col];
-        Ar[j * len + x] = wr[static_cast<int64_t>(col) * 2 * K + x] * s;
-        Ai[j * len + x] = -wi[static_cast<int64_t>(col) * 2 * K + x] * s;
+        Ar[j * len + x] = wr[col * ldw + x] * s;
+        Ai[j * len + x] = -wi[col * ldw + x] * s;
     }
     // previous site: A_{k-1} (V S)
     double *tr = R.scr + oTH, *ti = tr + 2LL * K * K;
@@ -346,7 +436,7 @@ __device__ void move_left(const Res& R, const Ctl& c, int k, double tau) {
         double xr = 0, xi = 0;
         for (int a = 0; a < cl; ++a) {
             const double p_r = pr[row * cl + a], p_i = pi[row * cl + a];
-            const double v_r = vr[col * K + a], v_i = vi[col * K + a];
+            const double v_r = vr[col * ldv + a], v_i = vi[col * ldv + a];
             xr += p_r * v_r - p_i * v_i;
             xi += p_r * v_i + p_i * v_r;
         }
@@ -495,8 +585,6 @@ __device__ bool apply_sum(const Res& R, const Ctl& c, Frame F, int r, double alr
     move_center(R, c, lo, tau);
     for (int k = lo + tid; k <= hi + 1; k += CT) c.old[k] = R.chi[k];
     __syncthreads();
-    double *wr = R.scr + oW, *wi = wr + 2LL * K * K;
-    double *vr = R.scr + oV, *vi = vr + K * K;
     double *cr_ = R.scr + oC, *ci_ = cr_ + K * K;
     double *tr = R.scr + oTH, *ti = tr + 2LL * K * K;
     if (lo == hi) {
@@ -530,6 +618,9 @@ __device__ bool apply_sum(const Res& R, const Ctl& c, Frame F, int r, double alr
         const double *ar = R.re(k), *ai = R.im(k);
         const int D = k == hi ? cr : 2 * cr;          // right bond of the sum tensor
         const int len = 2 * rows;
+        const WV w = work_mats(R, c, len, D);
+        double *wr = w.wr, *wi = w.wi, *vr = w.vr, *vi = w.vi;
+        const int ldw = w.ldw, ldv = w.ldv;
         // M[(j,i)][col] into W (column-major) or, at the last site, TH
         for (int e = tid; e < len * D; e += CT) {
             const int row = e / D, col = e - row * D;
@@ -578,8 +669,8 @@ __device__ bool apply_sum(const Res& R, const Ctl& c, Frame F, int r, double alr
                 tr[e] = xr;
                 ti[e] = xi;
             } else {
-                wr[static_cast<int64_t>(col) * 2 * K + row] = xr;
-                wi[static_cast<int64_t>(col) * 2 * K + row] = xi;
+                wr[col * ldw + row] = xr;
+                wi[col * ldw + row] = xi;
             }
         }
         __syncthreads();
@@ -596,23 +687,23 @@ __device__ bool apply_sum(const Res& R, const Ctl& c, Frame F, int r, double alr
             __syncthreads();
             break;
         }
-        note_sweeps(c, jacobi_cols(wr, wi, len, D, vr, vi, c.flag));
-        const int rn = select_cols(wr, wi, len, D, 1e-14, c.sg, c.keep, c.red);
+        note_sweeps(c, jacobi_cols(w, len, D, c.flag));
+        const int rn = select_cols(w, len, D, 1e-14, c.sg, c.keep, c.red);
         if (rn > K) return false;     // cannot happen: rn <= D <= K
         double *Ar = R.re(k), *Ai = R.im(k);
         for (int e = tid; e < len * rn; e += CT) {
             const int row = e / rn, jj = e - row * rn;
             const int col = c.keep[jj];
             const double s = 1.0 / c.sg[col];
-            Ar[row * rn + jj] = wr[static_cast<int64_t>(col) * 2 * K + row] * s;
-            Ai[row * rn + jj] = wi[static_cast<int64_t>(col) * 2 * K + row] * s;
+            Ar[row * rn + jj] = wr[col * ldw + row] * s;
+            Ai[row * rn + jj] = wi[col * ldw + row] * s;
         }
         // new carry: S V^dag (rn x D)
         for (int e = tid; e < rn * D; e += CT) {
             const int jj = e / D, col2 = e - jj * D;
             const int col = c.keep[jj];
-            cr_[jj * K + col2] = c.sg[col] * vr[col * K + col2];
-            ci_[jj * K + col2] = -c.sg[col] * vi[col * K + col2];
+            cr_[jj * K + col2] = c.sg[col] * vr[col * ldv + col2];
+            ci_[jj * K + col2] = -c.sg[col] * vi[col * ldv + col2];
         }
         if (tid == 0) {
             R.chi[k] = rows;
@@ -643,6 +734,8 @@ __global__ __launch_bounds__(CT) void camps_kernel(CampsArgs P) {
     __shared__ double s_pur[kCampsCand + 1];
     __shared__ double s_dm[(kCampsCand + 1) * 32];   // identity, then the candidates
     __shared__ double s_part[CT];
+    __shared__ double s_lwr[kWaveLen * kWaveCols], s_lwi[kWaveLen * kWaveCols];
+    __shared__ double s_lvr[kWaveCols * kWaveCols], s_lvi[kWaveCols * kWaveCols];
     const int tid = threadIdx.x;
     const int n = P.n;
     Frame F;
@@ -661,6 +754,10 @@ __global__ __launch_bounds__(CT) void camps_kernel(CampsArgs P) {
     C.sweeps = &s_sweeps;
     C.chi_peak = &s_peak;
     C.old = s_old;
+    C.lwr = s_lwr;
+    C.lwi = s_lwi;
+    C.lvr = s_lvr;
+    C.lvi = s_lvi;
     const double c8 = 0.92387953251128675613, s8 = 0.38268343236508977173;   // cos, sin of pi/8
     for (int e = tid; e < (kCampsCand + 1) * 32; e += CT) {
         const int c = e / 32, w = e - c * 32;
@@ -894,7 +991,9 @@ __global__ __launch_bounds__(CT) void camps_kernel(CampsArgs P) {
                     continue;
                 }
                 ++n_dis;
-                double *wr = R.scr + oW, *wi = wr + 2LL * K * K;
+                const WV w = work_mats(R, C, m, nn);
+                double *wr = w.wr, *wi = w.wi, *vr = w.vr, *vi = w.vi;
+                const int ldw = w.ldw, ldv = w.ldv;
                 const double* d = s_dm + (choice + 1) * 32;
                 // W <- (D theta) column-major
                 for (int e = tid; e < m * nn; e += CT) {
@@ -909,8 +1008,8 @@ __global__ __launch_bounds__(CT) void camps_kernel(CampsArgs P) {
                         xr += g_r * thr[src] - g_i * thi[src];
                         xi += g_r * thi[src] + g_i * thr[src];
                     }
-                    wr[static_cast<int64_t>(col) * 2 * K + row] = xr;
-                    wi[static_cast<int64_t>(col) * 2 * K + row] = xi;
+                    wr[col * ldw + row] = xr;
+                    wi[col * ldw + row] = xi;
                 }
                 // frame: every row's part on sites k, k+1 conjugated by D
                 const uint8_t* tab = P.dtab + choice * 16;
@@ -928,22 +1027,21 @@ __global__ __launch_bounds__(CT) void camps_kernel(CampsArgs P) {
                 }
                 __syncthreads();
                 // split D theta: A_k = U, A_{k+1} = S V^dag
-                double *vr = R.scr + oV, *vi = vr + K * K;
-                note_sweeps(C, jacobi_cols(wr, wi, m, nn, vr, vi, &s_flag));
-                const int rr = select_cols(wr, wi, m, nn, tau, s_sg, s_keep, s_red);
+                note_sweeps(C, jacobi_cols(w, m, nn, &s_flag));
+                const int rr = select_cols(w, m, nn, tau, s_sg, s_keep, s_red);
                 double *Ar = R.re(k), *Ai = R.im(k), *Br = R.re(k + 1), *Bi = R.im(k + 1);
                 for (int e = tid; e < m * rr; e += CT) {
                     const int row = e / rr, jj = e - row * rr;
                     const int col = s_keep[jj];
                     const double s = 1.0 / s_sg[col];
-                    Ar[row * rr + jj] = wr[static_cast<int64_t>(col) * 2 * K + row] * s;
-                    Ai[row * rr + jj] = wi[static_cast<int64_t>(col) * 2 * K + row] * s;
+                    Ar[row * rr + jj] = wr[col * ldw + row] * s;
+                    Ai[row * rr + jj] = wi[col * ldw + row] * s;
                 }
                 for (int e = tid; e < rr * nn; e += CT) {
                     const int jj = e / nn, col2 = e - jj * nn;
                     const int col = s_keep[jj];
-                    Br[e] = s_sg[col] * vr[col * K + col2];
-                    Bi[e] = -s_sg[col] * vi[col * K + col2];
+                    Br[e] = s_sg[col] * vr[col * ldv + col2];
+                    Bi[e] = -s_sg[col] * vi[col * ldv + col2];
                 }
                 if (tid == 0) {
                     s_chi[k + 1] = rr;

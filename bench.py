@@ -400,6 +400,28 @@ def main() -> int:
                 "unit": "TFLOP/s", "frac": tf / peak}
         rel = float(np.linalg.norm(outs["bf16x3"] - outs["fp32"]) / np.linalg.norm(outs["fp32"]))
         result["contraction_chi256_bf16x3"]["rel_error_vs_fp32"] = rel
+        # offline screen at scale: 2^24 shots of the 81-qubit circuit's
+        # skeleton (faults drawn on the GPU, p = 1e-3), bit-exact against
+        # the oracle in the test suite; algorithmic bytes per shot: its CSR
+        # offset (8 B), 5 B per fault, the survive bit and a survivor index
+        log("offline screen, 2^24 shots, 81 qubits")
+        c81 = msc.Circuit(config_circuit("c4").text)
+        n81 = 1 << 24
+        o81, ch81, pa81 = msc.sample_faults_device(ctx, c81, 0x5EED0005, 0, n81, p=args.p)
+        msc.prescreen(ctx, c81, o81, ch81, pa81)
+        sms = []
+        for _ in range(3):
+            _, _, cnt81 = msc.prescreen(ctx, c81, o81, ch81, pa81)
+            sms.append(ctx.last_kernel_ms("prescreen"))
+        ms81 = float(np.mean(sms))
+        nnz81 = int(ch81.numel())
+        byts = 8.0 * (n81 + 1) + 5.0 * nnz81 + n81 / 8.0 + 8.0 * cnt81
+        result["prescreen_81q"] = {"shots": n81, "faults": nnz81, "survivors": cnt81,
+                                   "ms": ms81, "shots_per_s": n81 / (ms81 * 1e-3),
+                                   "bound": "hbm", "achieved": byts / (ms81 * 1e-3) / 1e9,
+                                   "peak": 8000.0, "unit": "GB/s",
+                                   "frac": byts / (ms81 * 1e-3) / 1e9 / 8000.0}
+        del o81, ch81, pa81
 
     if not args.no_extras and order is not None:
         # the same pipeline on the snake layout, for comparison (its own

@@ -68,9 +68,11 @@ def main() -> int:
                     help="evaluations of the qubit-order search run before the timed steps "
                          "(0: the snake order)")
     ap.add_argument("--lds-width", type=int, default=0)
-    ap.add_argument("--slots", type=int, default=0,
+    ap.add_argument("--slots", type=int, default=384,
                     help="persistent workgroups (MPS slots) per context; 0 = one per "
-                         "resident workgroup of the GPU")
+                         "resident workgroup of the GPU (768: three per CU).  With 8 "
+                         "contexts in flight, 384 slots of 51 MB (chi_max = 256) each "
+                         "keep the arenas at 157 GB of the 288 GB")
     ap.add_argument("--streams", type=int, default=8,
                     help="steps in flight: each host thread runs whole steps on its own "
                          "context (HIP stream), so one step's long-running shots overlap "

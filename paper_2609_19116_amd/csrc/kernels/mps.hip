@@ -867,7 +867,11 @@ __device__ void fold_product(MP mr, MP mi, OP ore, OP oim, SiteView<T> Pv, doubl
 }
 
 template <typename T, int SMAX>
-__global__ __launch_bounds__(NT) void mps_kernel(MpsArgs P) {
+// Three workgroups per CU: the LDS (43.6 KB per workgroup for SMAX = 32)
+// allows three, the register budget is capped to match (a few spills); the
+// shots are latency-bound, so the third resident shot per CU raises the
+// throughput more than the spills cost.
+__global__ __launch_bounds__(NT, 3) void mps_kernel(MpsArgs P) {
     __shared__ int s_chi[kMaxSites + 1];
     __shared__ int s_laste[kMaxSites];
     __shared__ double s_vre[SMAX * (SMAX + 1)];

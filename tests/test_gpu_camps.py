@@ -108,6 +108,24 @@ def test_camps_clifford_circuit_has_product_residual(ctx):
     assert np.allclose(a["p_acc"], b["p_acc"], atol=1e-10, rtol=0)
 
 
+def test_camps_bond_cap_flags_shots(ctx):
+    # a residual cap below what the shots need: those shots end flagged
+    # with P_acc 0; the others still equal the MPS path
+    cc, circ = _circ(ctx, "c1")
+    n = 96
+    w = np.array([0, 1, 2, 3] * (n // 4), dtype=np.int32)
+    say("camps c1 chi_max=2")
+    off, ch, pa = msc.sample_faults_device(ctx, circ, 0x5EED0075, 0, n, weights=w)
+    a = results_numpy(msc.simulate_camps(ctx, circ, off, ch, pa, chi_max=2))
+    b = results_numpy(msc.simulate(ctx, circ, off, ch, pa, precision=MSC_FP64))
+    capped = (a["status"] & msc.SHOT_CHI_CAP) != 0
+    assert capped.any()
+    assert (a["p_acc"][capped] == 0).all()
+    ok = ~capped
+    assert np.allclose(a["p_acc"][ok], b["p_acc"][ok], atol=1e-9, rtol=0)
+    assert (a["chi_peak"][ok] <= 2).all()
+
+
 def test_camps_argument_errors(ctx):
     import torch
     cc, circ = _circ(ctx, "tiny")

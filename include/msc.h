@@ -169,9 +169,12 @@ const char* msc_version(void);
    (default priority).  Fails with MSC_E_DEVICE when no GPU is usable.    */
 int msc_ctx_create(int device, msc_ctx** out);
 void msc_ctx_destroy(msc_ctx* ctx);
-/* Duration in ms of the last kernel launched by the named call, measured
-   with HIP events on the context's stream ("simulate", "prescreen",
-   "twosite").  Returns a negative value if none was timed.               */
+/* Duration in ms of the last kernel work of the named kind, measured with
+   HIP events on the context's stream: "sample" (device fault draws),
+   "prescreen", "simulate" (shot kernel), "prefix" (checkpoint recording of
+   the noiseless run), "camps", "camps_prefix", "twosite".  msc_run_batch
+   sets "sample", "prescreen" and "simulate".  Returns a negative value if
+   none was timed.                                                         */
 double msc_ctx_last_kernel_ms(msc_ctx* ctx, const char* which);
 
 /* ---------------------------------------------------------------------- */

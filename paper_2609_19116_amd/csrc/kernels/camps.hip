@@ -49,8 +49,7 @@ constexpr int64_t oE = oF + 4LL * K * K;      // 2 x K^2
 constexpr int64_t oE2 = oE + 2LL * K * K;     // 2 x K^2
 constexpr int64_t oTH = oE2 + 2LL * K * K;    // 2 x 2K^2
 constexpr int64_t oTC = oTH + 4LL * K * K;    // 2 x K^2
-constexpr int64_t oRH = oTC + 2LL * K * K;    // 2 x K^2
-static_assert(oRH + 2LL * K * K <= kCampsScratch, "scratch layout");
+static_assert(oTC + 2LL * K * K <= kCampsScratch, "scratch layout");
 
 __device__ __forceinline__ double block_sum(double v, double* red) {
 #pragma unroll

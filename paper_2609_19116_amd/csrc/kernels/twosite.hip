@@ -26,7 +26,15 @@ constexpr int TB = 64;    // b columns per workgroup (times 2 for j')
 constexpr int TK = 16;    // k per LDS stage
 constexpr int NTH = 256;
 
-__global__ __launch_bounds__(NTH) void twosite_kernel(int chi, const float* __restrict__ Ag,
+// Workgroups are dispatched to the 8 XCDs in turn (block h runs on XCD
+// h mod 8).  Block h takes the logical block that makes each XCD work
+// through one contiguous run of logical blocks, so the tiles of one batch
+// element share that XCD's L2 instead of being spread over all eight.
+__device__ __forceinline__ int xcd_block(int h, int nb) {
+    return (nb & 7) ? h : (h & 7) * (nb >> 3) + (h >> 3);
+}
+
+__global__ __launch_bounds__(NTH) void twosite_kernel(int chi, int tiles, const float* __restrict__ Ag,
                                                       const float* __restrict__ Bg,
                                                       const float* __restrict__ gate,
                                                       float* __restrict__ Tg) {
@@ -41,10 +49,11 @@ __global__ __launch_bounds__(NTH) void twosite_kernel(int chi, const float* __re
     const int m = 2 * chi;                    // rows of A and theta
     const int n = 2 * chi;                    // columns of B and theta
     const int rows_tiles = m / TM;
-    const int tile = blockIdx.x;
+    const int lg = xcd_block(blockIdx.x, gridDim.x);
+    const int tile = lg % tiles;
     const int R0 = (tile % rows_tiles) * TM;
     const int B0 = (tile / rows_tiles) * TB;
-    const size_t bidx = blockIdx.y;
+    const size_t bidx = lg / tiles;
     const float* A = Ag + bidx * 2 * (size_t)m * chi;
     const float* Bm = Bg + bidx * 2 * (size_t)chi * n;
     float* T = Tg + bidx * 2 * (size_t)m * n;
@@ -174,33 +183,45 @@ __global__ __launch_bounds__(NTH) void twosite_kernel(int chi, const float* __re
 
 // ---------------------------------------------------------------------------
 // BF16x3 split precision: every FP32 operand x is split into x_hi = bf16(x)
-// and x_lo = bf16(x - x_hi) (round to nearest even), and a real product is
-// x_hi y_hi + x_hi y_lo + x_lo y_hi with FP32 accumulation on
-// v_mfma_f32_16x16x32_bf16 (the x_lo y_lo term, ~2^-16 relative, is dropped).
-// Workgroup tile: 64 rows x (64 b, both j'); each of the 4 waves keeps a
-// 32 x (32 b, both j') block; K = chi streamed in steps of 32 through LDS
-// with the next step prefetched into registers.
+// and x_lo = bf16(x - x_hi) (round to nearest even, v_cvt_pk_bf16_f32), and
+// a real product is x_hi y_hi + x_hi y_lo + x_lo y_hi with FP32
+// accumulation on v_mfma_f32_16x16x32_bf16 (the x_lo y_lo term, ~2^-16
+// relative, is dropped).  Workgroup tile: 64 rows x (64 b, both j'); each of
+// the 4 waves keeps a 32 x (32 b, both j') block; K = chi is streamed in
+// steps of 32 through LDS with the next step prefetched into registers.
+// Every thread splits runs of 8 consecutive k of one row of A or one column
+// of B, so each hi or lo run is one 16-byte LDS store in the k-contiguous
+// layout the MFMA operands are read in.
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 constexpr int BM = 64;    // rows per workgroup
 constexpr int BB = 64;    // b columns per workgroup (times 2 for j')
 constexpr int BK = 32;    // k per step (one MFMA)
 constexpr int BKP = 40;   // padded k stride in LDS (bf16 elements)
 
-__device__ __forceinline__ unsigned short bf16_rne(float x) {
-    const unsigned int u = __float_as_uint(x);
-    const unsigned int r = u + 0x7FFFu + ((u >> 16) & 1u);
-    return static_cast<unsigned short>(r >> 16);
-}
-__device__ __forceinline__ float bf16_val(unsigned short h) {
-    return __uint_as_float(static_cast<unsigned int>(h) << 16);
+// hi/lo split of 8 consecutive values: hi = bf16(x), lo = bf16(x - hi)
+__device__ __forceinline__ void split8(const float (&x)[8], uint4& hi, uint4& lo) {
+    unsigned h[4], l[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const f32x2 v = {x[2 * p], x[2 * p + 1]};
+        const unsigned hu = __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
+        const f32x2 r = {v.x - __uint_as_float(hu << 16), v.y - __uint_as_float(hu & 0xffff0000u)};
+        h[p] = hu;
+        l[p] = __builtin_bit_cast(unsigned, __builtin_convertvector(r, bf16x2));
+    }
+    hi = make_uint4(h[0], h[1], h[2], h[3]);
+    lo = make_uint4(l[0], l[1], l[2], l[3]);
 }
 
-__global__ __launch_bounds__(NTH) void twosite_bf16x3_kernel(int chi, const float* __restrict__ Ag,
-                                                             const float* __restrict__ Bg,
-                                                             const float* __restrict__ gate,
-                                                             float* __restrict__ Tg) {
+__global__ __launch_bounds__(NTH, 2) void twosite_bf16x3_kernel(int chi, int tiles,
+                                                                const float* __restrict__ Ag,
+                                                                const float* __restrict__ Bg,
+                                                                const float* __restrict__ gate,
+                                                                float* __restrict__ Tg) {
     // planes: 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo; A as [row][k], B as [col][k]
     __shared__ __attribute__((aligned(16))) unsigned short As[4][BM][BKP];
     __shared__ __attribute__((aligned(16))) unsigned short Bs[4][2 * BB][BKP];
@@ -211,9 +232,11 @@ __global__ __launch_bounds__(NTH) void twosite_bf16x3_kernel(int chi, const floa
     const int wm = w >> 1, wn = w & 1;
     const int m = 2 * chi, n = 2 * chi;
     const int rows_tiles = m / BM;
-    const int R0 = (blockIdx.x % rows_tiles) * BM;
-    const int B0 = (blockIdx.x / rows_tiles) * BB;
-    const size_t bidx = blockIdx.y;
+    const int lg = xcd_block(blockIdx.x, gridDim.x);
+    const int tile = lg % tiles;
+    const int R0 = (tile % rows_tiles) * BM;
+    const int B0 = (tile / rows_tiles) * BB;
+    const size_t bidx = lg / tiles;
     const float* A = Ag + bidx * 2 * (size_t)m * chi;
     const float* Bm = Bg + bidx * 2 * (size_t)chi * n;
     float* T = Tg + bidx * 2 * (size_t)m * n;
@@ -232,52 +255,43 @@ __global__ __launch_bounds__(NTH) void twosite_bf16x3_kernel(int chi, const floa
 #pragma unroll
                 for (int d = 0; d < 2; ++d) acc[a][b][c][d] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    float4 ra[4], rb[8];
+    // A: 64 rows x 4 runs of 8 k, one (row, run) of both planes per thread
+    // (run index fastest across lanes); B: 2 planes x 32 column quads x 4 runs of 8 k,
+    // one (quad, run) per thread, loaded as 8 rows of 4 columns
+    const int a_row = (tid >> 2) & 63, a_kc = tid & 3;
+    const int b_plane = tid >> 7, b_cq = (tid >> 2) & 31, b_kc = tid & 3;
+    const int b_col = ((4 * b_cq) >> 6) * chi + B0 + ((4 * b_cq) & 63);
+    float4 ra[2][2], rb[8];
     auto gload = [&](int k0) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {          // A: 2 planes x 64 rows x 8 float4
-            const int idx = tid + NTH * s;
-            const int plane = idx >> 9, rem = idx & 511;
-            const int row = rem >> 3, kq = rem & 7;
-            ra[s] = *reinterpret_cast<const float4*>(A + (size_t)plane * m * chi +
-                                                     (size_t)(R0 + row) * chi + k0 + 4 * kq);
+        for (int s = 0; s < 2; ++s) {          // s = plane
+            const float* src = A + (size_t)s * m * chi + (size_t)(R0 + a_row) * chi + k0 + 8 * a_kc;
+            ra[s][0] = *reinterpret_cast<const float4*>(src);
+            ra[s][1] = *reinterpret_cast<const float4*>(src + 4);
         }
+        const float* src = Bm + (size_t)b_plane * chi * n + (size_t)(k0 + 8 * b_kc) * n + b_col;
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {          // B: 2 planes x 32 k x 32 float4
-            const int idx = tid + NTH * s;
-            const int plane = idx >> 10, rem = idx & 1023;
-            const int kr = rem >> 5, cq = rem & 31;
-            const int cl = 4 * cq;
-            const int col = (cl >> 6) * chi + B0 + (cl & 63);
-            rb[s] = *reinterpret_cast<const float4*>(Bm + (size_t)plane * chi * n +
-                                                     (size_t)(k0 + kr) * n + col);
-        }
-    };
-    auto split_store = [&](unsigned short* hi, unsigned short* lo, float x) {
-        const unsigned short h = bf16_rne(x);
-        *hi = h;
-        *lo = bf16_rne(x - bf16_val(h));
+        for (int e = 0; e < 8; ++e) rb[e] = *reinterpret_cast<const float4*>(src + (size_t)e * n);
     };
     auto lstore = [&]() {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int idx = tid + NTH * s;
-            const int plane = idx >> 9, rem = idx & 511;
-            const int row = rem >> 3, kq = rem & 7;
-            const float v[4] = {ra[s].x, ra[s].y, ra[s].z, ra[s].w};
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                split_store(&As[2 * plane][row][4 * kq + e], &As[2 * plane + 1][row][4 * kq + e], v[e]);
+        for (int s = 0; s < 2; ++s) {
+            const float x[8] = {ra[s][0].x, ra[s][0].y, ra[s][0].z, ra[s][0].w,
+                                ra[s][1].x, ra[s][1].y, ra[s][1].z, ra[s][1].w};
+            uint4 hi, lo;
+            split8(x, hi, lo);
+            *reinterpret_cast<uint4*>(&As[2 * s][a_row][8 * a_kc]) = hi;
+            *reinterpret_cast<uint4*>(&As[2 * s + 1][a_row][8 * a_kc]) = lo;
         }
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            const int idx = tid + NTH * s;
-            const int plane = idx >> 10, rem = idx & 1023;
-            const int kr = rem >> 5, cq = rem & 31;
-            const float v[4] = {rb[s].x, rb[s].y, rb[s].z, rb[s].w};
+        for (int c = 0; c < 4; ++c) {
+            float x[8];
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                split_store(&Bs[2 * plane][4 * cq + e][kr], &Bs[2 * plane + 1][4 * cq + e][kr], v[e]);
+            for (int e = 0; e < 8; ++e) x[e] = c == 0 ? rb[e].x : c == 1 ? rb[e].y : c == 2 ? rb[e].z : rb[e].w;
+            uint4 hi, lo;
+            split8(x, hi, lo);
+            *reinterpret_cast<uint4*>(&Bs[2 * b_plane][4 * b_cq + c][8 * b_kc]) = hi;
+            *reinterpret_cast<uint4*>(&Bs[2 * b_plane + 1][4 * b_cq + c][8 * b_kc]) = lo;
         }
     };
     auto frag = [&](const unsigned short* p) { return *reinterpret_cast<const bf16x8*>(p); };
@@ -312,24 +326,19 @@ __global__ __launch_bounds__(NTH) void twosite_bf16x3_kernel(int chi, const floa
                 bf16x8 b[4];
 #pragma unroll
                 for (int pl = 0; pl < 4; ++pl) b[pl] = frag(&Bs[pl][c][kk]);
+                // Re += Ar Br - Ai Bi ; Im += Ar Bi + Ai Br   (each x3); the
+                // four accumulators of (mt, re/im) advance in turn
+                const int ta[6] = {0, 0, 1, 4, 4, 5}, tb[6] = {0, 1, 0, 2, 3, 2};
+                const int ua[6] = {0, 0, 1, 2, 2, 3}, ub[6] = {2, 3, 2, 0, 1, 0};
 #pragma unroll
-                for (int mt = 0; mt < 2; ++mt) {
-                    floatx4& re = acc[mt][nt][jp][0];
-                    floatx4& im = acc[mt][nt][jp][1];
-                    // Re += Ar Br - Ai Bi ; Im += Ar Bi + Ai Br   (each x3)
-                    re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][0], b[0], re, 0, 0, 0);
-                    re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][0], b[1], re, 0, 0, 0);
-                    re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][1], b[0], re, 0, 0, 0);
-                    re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][4], b[2], re, 0, 0, 0);
-                    re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][4], b[3], re, 0, 0, 0);
-                    re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][5], b[2], re, 0, 0, 0);
-                    im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][0], b[2], im, 0, 0, 0);
-                    im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][0], b[3], im, 0, 0, 0);
-                    im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][1], b[2], im, 0, 0, 0);
-                    im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][2], b[0], im, 0, 0, 0);
-                    im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][2], b[1], im, 0, 0, 0);
-                    im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][3], b[0], im, 0, 0, 0);
-                }
+                for (int t = 0; t < 6; ++t)
+#pragma unroll
+                    for (int mt = 0; mt < 2; ++mt) {
+                        floatx4& re = acc[mt][nt][jp][0];
+                        floatx4& im = acc[mt][nt][jp][1];
+                        re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][ta[t]], b[tb[t]], re, 0, 0, 0);
+                        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt][ua[t]], b[ub[t]], im, 0, 0, 0);
+                    }
             }
         __syncthreads();
     }
@@ -374,12 +383,12 @@ hipError_t launch_twosite(int precision, int chi, int batch, const float* A, con
     if (chi % 64 != 0 || chi < 64) return hipErrorInvalidValue;
     if (precision == MSC_BF16X3) {
         const int tiles = (2 * chi / BM) * (chi / BB);
-        hipLaunchKernelGGL(twosite_bf16x3_kernel, dim3(tiles, batch), dim3(NTH), 0, s, chi, A, B,
-                           gate, theta);
+        hipLaunchKernelGGL(twosite_bf16x3_kernel, dim3(tiles * batch), dim3(NTH), 0, s, chi, tiles,
+                           A, B, gate, theta);
     } else {
         const int tiles = (2 * chi / TM) * (chi / TB);
-        hipLaunchKernelGGL(twosite_kernel, dim3(tiles, batch), dim3(NTH), 0, s, chi, A, B, gate,
-                           theta);
+        hipLaunchKernelGGL(twosite_kernel, dim3(tiles * batch), dim3(NTH), 0, s, chi, tiles, A, B,
+                           gate, theta);
     }
     return hipGetLastError();
 }

@@ -64,9 +64,13 @@ def main() -> int:
                     help="shots of the batch run through the CPU oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--order-search", type=int, default=64,
-                    help="evaluations of the qubit-order search run before the timed steps "
-                         "(0: the snake order)")
+    ap.add_argument("--order-search", type=int, default=128,
+                    help="evaluations of each start of the qubit-order search run before the "
+                         "timed steps (0: the snake order)")
+    ap.add_argument("--order-starts", type=int, default=3,
+                    help="independent starts of the order search (seeds ORDER_SEED + i); "
+                         "the cheapest result is kept")
+    ap.add_argument("--order-seed", type=lambda x: int(x, 0), default=ORDER_SEED)
     ap.add_argument("--lds-width", type=int, default=0)
     ap.add_argument("--slots", type=int, default=384,
                     help="persistent workgroups (MPS slots) per context; 0 = one per "
@@ -116,21 +120,33 @@ def main() -> int:
     cc = config_circuit("c3")
     ctx = msc.Ctx(0)
     # the MPS layout: the snake order, or the order the local search finds
-    # from it (noiseless-run flops as the cost); like compilation and
+    # from it (noiseless-run flops plus fixed op costs); like compilation and
     # calibration this is per-circuit set-up outside the timed steps
     order_info = None
     order = None
     if args.order_search > 0:
         t0 = time.perf_counter()
-        order, c_start, c_best = msc.order_search(ctx, cc.text, ORDER_SEED, args.order_search)
-        order_info = {"budget": args.order_search, "seed": hex(ORDER_SEED),
-                      "snake_flops": c_start, "searched_flops": c_best,
+        runs = [msc.order_search(ctx, cc.text, args.order_seed + i, args.order_search)
+                for i in range(max(1, args.order_starts))]
+        best = min(range(len(runs)), key=lambda i: runs[i][2])
+        order, c_start, c_best = runs[best]
+        order_info = {"budget": args.order_search, "starts": len(runs),
+                      "seed": hex(args.order_seed + best),
+                      "cost": "noiseless-run flops + fixed op costs (MSC_ORDER_COST_*)",
+                      "snake_cost": c_start, "searched_cost": c_best,
+                      "costs_of_starts": [r[2] for r in runs],
                       "ratio": c_best / c_start, "seconds": time.perf_counter() - t0,
                       "order": [int(q) for q in order]}
-        log(f"order search: noiseless flops {c_start:.4g} -> {c_best:.4g}")
+        log(f"order search: cost {c_start:.4g} -> {c_best:.4g}")
     circ = msc.Circuit(cc.text, order=order)
     circ.calibrate(ctx)
     info = circ.info()
+    if order_info is not None:
+        snake = msc.Circuit(cc.text)
+        snake.calibrate(ctx)
+        order_info["snake_noiseless_flops"] = snake.noiseless()["flops"]
+        order_info["searched_noiseless_flops"] = circ.noiseless()["flops"]
+        del snake
     M = info["n_channels"]
     n = args.shots
     nb = args.steps + args.warmup
@@ -438,7 +454,7 @@ def main() -> int:
         wall_s, per_s = timed(warmup, k2)
         result["value_snake_layout"] = {
             "value": k2 * n / wall_s, "unit": "shots/s", "steps": k2,
-            "noiseless_flops": order_info["snake_flops"],
+            "noiseless_flops": order_info["snake_noiseless_flops"],
             "survivors_per_step": float(np.mean([q[0]["n_survivors"] for q in per_s])),
             "launch_ms": float(np.mean([q[0]["ms_simulate"] for q in per_s]))}
         circ = circ_searched

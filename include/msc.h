@@ -376,16 +376,28 @@ int msc_reweight(const double* bin_n, const double* bin_acc,
 /* Qubit-order search (Section 3.1: the linear order drives the routing    */
 /* and the bond dimension; an automatic search is the paper's future work).*/
 
+/* Fixed cost of one op of the shot kernel, in flop equivalents, in the
+   order-search cost below: the kernel is latency-bound, so an op costs a
+   number of cycles beyond its flops (measured per op kind on the 49-qubit
+   workload: about 7e3 cycles per product swap, 1.2e4 per centre move,
+   2.5e4 per two-site update at the smallest bonds), priced at 100 flops
+   per cycle, the rate of a two-site update at chi = 32.                    */
+#define MSC_ORDER_COST_PSWAP   7.0e5
+#define MSC_ORDER_COST_MOVE    1.2e6
+#define MSC_ORDER_COST_TWOSITE 2.5e6
+
 /* Local search for the qubit -> site order of the circuit `text` (len
    bytes) from `start` (host, n_qubits entries, order[site] = qubit; NULL:
    the text's ORDER line, else identity).  Cost of an order = algorithmic
    flops of its noiseless run (msc_circuit_noiseless after calibration on
-   ctx's GPU; +inf if that run exceeds the bond cap).  Each of the `budget`
-   evaluations after the first tries one move drawn from a SplitMix64
-   stream keyed by `seed` between sites i and j at distance
-   1 + floor(-4 ln u): exchange them, reverse the run between them, or move
-   site i to position j (probability 1/3 each); a move is kept iff the
-   cost falls.
+   ctx's GPU) + MSC_ORDER_COST_PSWAP * n_product_swaps + MSC_ORDER_COST_MOVE
+   * n_moves + MSC_ORDER_COST_TWOSITE * n_twosite of the circuit compiled
+   with that order (msc_circuit_info); +inf if the noiseless run exceeds
+   the bond cap.  Each of the `budget` evaluations after the first tries
+   one move drawn from a SplitMix64 stream keyed by `seed` between sites i
+   and j at distance 1 + floor(-4 ln u): exchange them, reverse the run
+   between them, or move site i to position j (probability 1/3 each); a
+   move is kept iff the cost falls.
    order_out (host, n_qubits): the best order; cost_out (host, 2 doubles):
    the start order's cost and the best cost.  Calibration errors other than
    the bond cap are returned.                                              */

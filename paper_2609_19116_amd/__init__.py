@@ -13,6 +13,7 @@ import ctypes as C
 import numpy as np
 
 from ._lib import (BatchStats, MSC_BF16X3, MSC_FP32, MSC_FP64, MSC_STAT_PACC,  # noqa: F401
+                   MSC_ORDER_COST_MOVE, MSC_ORDER_COST_PSWAP, MSC_ORDER_COST_TWOSITE,
                    MSC_STAT_PLE, SEGMENT_DTYPE, SHOT_CHI_CAP, SHOT_DONE, SHOT_DTYPE, SHOT_NOCONV,
                    SHOT_REJECTED, CircuitInfo, Estimate, Interval, MscError, SimOpts, _check,
                    _ptr, lib)
@@ -21,7 +22,7 @@ __all__ = ["Ctx", "Circuit", "sample_faults", "sample_faults_device", "prescreen
            "simulate_camps", "camps_candidates",
            "run_batch", "reweight", "profile_loglik", "lr_interval", "ratio_credible",
            "loss_factor", "expected_volume", "order_search", "twosite_contract", "prescreen_tables", "version", "MscError",
-           "MSC_FP64", "MSC_FP32", "MSC_BF16X3", "MSC_STAT_PACC", "MSC_STAT_PLE", "SHOT_DTYPE"]
+           "MSC_FP64", "MSC_FP32", "MSC_BF16X3", "order_cost", "MSC_STAT_PACC", "MSC_STAT_PLE", "SHOT_DTYPE"]
 
 
 def version() -> str:
@@ -102,7 +103,8 @@ class Circuit:
 
 def order_search(ctx: Ctx, text: str, seed: int, budget: int, start=None):
     """Local search for the qubit -> site order; returns (order int32 [n],
-    start cost, best cost) with cost = flops of the noiseless run."""
+    start cost, best cost) with cost = flops of the noiseless run plus the
+    fixed op costs (order_cost)."""
     b = text.encode()
     st = None if start is None else np.ascontiguousarray(start, dtype=np.int32)
     n = Circuit(text).info()["n_qubits"]
@@ -111,6 +113,15 @@ def order_search(ctx: Ctx, text: str, seed: int, budget: int, start=None):
     _check(lib().msc_order_search(ctx.h, b, len(b), _ptr(st), seed, budget, _ptr(out),
                                   _ptr(cost)))
     return out, float(cost[0]), float(cost[1])
+
+
+def order_cost(circ: Circuit) -> float:
+    """The order-search cost of a calibrated circuit: noiseless-run flops +
+    MSC_ORDER_COST_PSWAP * product swaps + MSC_ORDER_COST_MOVE * centre
+    moves + MSC_ORDER_COST_TWOSITE * two-site updates."""
+    inf = circ.info()
+    return (circ.noiseless()["flops"] + MSC_ORDER_COST_PSWAP * inf["n_product_swaps"] +
+            MSC_ORDER_COST_MOVE * inf["n_moves"] + MSC_ORDER_COST_TWOSITE * inf["n_twosite"])
 
 
 def sample_faults(circ: Circuit, seed: int, first_shot: int, n_shots: int,

@@ -28,6 +28,11 @@ MSC_FP64 = 0
 MSC_FP32 = 1
 MSC_BF16X3 = 2
 
+# fixed op costs (flop equivalents) of the order-search cost: MSC_ORDER_COST_*
+MSC_ORDER_COST_PSWAP = 7.0e5
+MSC_ORDER_COST_MOVE = 1.2e6
+MSC_ORDER_COST_TWOSITE = 2.5e6
+
 SHOT_DONE = 1
 SHOT_REJECTED = 2
 SHOT_CHI_CAP = 4

@@ -6,7 +6,10 @@
 // search as future work.  Here the cost of an order is what the simulation
 // actually spends on it: the algorithmic flops (as the shot kernel counts
 // them) of the circuit's noiseless run compiled with that order, evaluated
-// on the GPU by the calibration run.  An order whose noiseless run exceeds
+// on the GPU by the calibration run, plus a fixed cost per op of the
+// compiled stream (product swaps, centre moves, two-site updates): the shot
+// kernel is latency-bound, and an op's latency, not its flops, dominates
+// the small ops that routing adds.  An order whose noiseless run exceeds
 // the kernel's bond cap costs +inf.
 //
 // The search is a first-improvement local search from the start order:
@@ -50,14 +53,18 @@ struct Mix {
 
 using namespace msc;
 
-// cost of one order: flops of the noiseless run, +inf if it cannot run
+// cost of one order: flops of the noiseless run plus the fixed op costs,
+// +inf if it cannot run
 static int order_cost(msc_ctx* ctx, const char* text, size_t len, const std::vector<int32_t>& order,
                       double* cost) {
     msc_circuit* c = nullptr;
     int rc = msc_circuit_load(text, len, order.data(), &c);
     if (rc) return rc;
     rc = msc_circuit_calibrate(ctx, c);
-    if (rc == MSC_OK) *cost = c->noiseless.flops;
+    if (rc == MSC_OK)
+        *cost = c->noiseless.flops + MSC_ORDER_COST_PSWAP * static_cast<double>(c->n_product_swaps) +
+                MSC_ORDER_COST_MOVE * static_cast<double>(c->n_moves) +
+                MSC_ORDER_COST_TWOSITE * static_cast<double>(c->n_twosite);
     else if (rc == MSC_E_NONDETERMINISTIC && (c->noiseless.status & MSC_SHOT_CHI_CAP)) {
         *cost = INFINITY;
         rc = MSC_OK;

@@ -1,7 +1,8 @@
 """GPU: the qubit-order search (msc_order_search).
 
-The search's cost is the noiseless run's algorithmic flops under an order;
-checked here: the contract (a permutation, a cost the calibration
+The search's cost is the noiseless run's algorithmic flops under an order
+plus fixed costs per product swap, centre move and two-site update of the
+compiled op stream; checked here: the contract (a permutation, a cost the calibration
 reproduces, no worse than the start, deterministic in the seed), the
 optimum of an exhaustive enumeration of all 5040 orders of the 7-qubit
 circuit, and that simulating under the order found changes no result:
@@ -33,7 +34,7 @@ def ctx():
 def _cost(ctx, text, order):
     c = msc.Circuit(text, order=order)
     c.calibrate(ctx)
-    return c.noiseless()["flops"]
+    return msc.order_cost(c)
 
 
 def test_order_search_contract(ctx):
@@ -100,10 +101,13 @@ def test_order_search_errors(ctx):
 
 def test_benchmark_layout_changes_no_result(ctx):
     # the 49-qubit workload under the order the benchmark's search finds
-    # (same seed and budget) against its snake order, FP64, sampled shots
+    # (same seeds, starts and budget: the cheapest of three starts of 128
+    # evaluations) against its snake order, FP64, sampled shots
     cc = config_circuit("c3")
-    say("order search c3 budget 64 (the benchmark's), then 128 FP64 shots on both layouts")
-    order, c0, c1 = msc.order_search(ctx, cc.text, 0x5EED0081, 64)
+    say("order search c3, 3 starts x 128 evaluations (the benchmark's), then 128 FP64 shots "
+        "on both layouts")
+    runs = [msc.order_search(ctx, cc.text, 0x5EED0081 + i, 128) for i in range(3)]
+    order, c0, c1 = min(runs, key=lambda r: r[2])
     assert c1 <= c0
     snake = msc.Circuit(cc.text)
     snake.calibrate(ctx)
@@ -119,5 +123,5 @@ def test_benchmark_layout_changes_no_result(ctx):
     acc = a["p_acc"] > 0
     assert np.allclose(a["infid"][acc], b["infid"][acc], atol=1e-9, rtol=0)
     assert np.array_equal(a["fail"], b["fail"])
-    print(f"c3: noiseless flops snake {c0:.4g} searched {c1:.4g}; mean shot flops "
+    print(f"c3: order cost snake {c0:.4g} searched {c1:.4g}; mean shot flops "
           f"{a['flops'].mean():.4g} -> {b['flops'].mean():.4g}", flush=True)

@@ -31,6 +31,14 @@ def test_library_exports_every_declared_symbol():
     assert set(_lib._SIGS) == names
 
 
+def test_order_cost_constants_match_header():
+    header = (ROOT / "include" / "msc.h").read_text()
+    vals = dict(re.findall(r"#define (MSC_ORDER_COST_[A-Z]+)\s+([0-9.e+]+)", header))
+    assert set(vals) == {"MSC_ORDER_COST_PSWAP", "MSC_ORDER_COST_MOVE", "MSC_ORDER_COST_TWOSITE"}
+    for k, v in vals.items():
+        assert getattr(_lib, k) == float(v), k
+
+
 def test_struct_sizes_match_header():
     assert C.sizeof(_lib.ShotResult) == 64
     assert C.sizeof(_lib.SimOpts) == 48

@@ -138,6 +138,8 @@ def main() -> int:
                       "ratio": c_best / c_start, "seconds": time.perf_counter() - t0,
                       "order": [int(q) for q in order]}
         log(f"order search: cost {c_start:.4g} -> {c_best:.4g}")
+    layout_key = (f"search {max(1, args.order_starts)}x{args.order_search} from {args.order_seed:#x}"
+                  if args.order_search > 0 else "snake")
     circ = msc.Circuit(cc.text, order=order)
     circ.calibrate(ctx)
     info = circ.info()
@@ -280,7 +282,7 @@ def main() -> int:
         "roofline": {"bound": "alu",
                      "kernel": f"mps_kernel<float,{64 if args.lds_width == 64 else 32}>",
                      "achieved": achieved, "peak": PEAK_FP64_VECTOR, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_VECTOR, "traffic": measured_traffic(),
+                     "frac": achieved / PEAK_FP64_VECTOR, "traffic": measured_traffic(layout_key),
                      "launch_ms": float(np.mean(sim_ms)),
                      "achieved_whole_job": achieved_job,
                      "frac_whole_job": achieved_job / PEAK_FP64_VECTOR,
@@ -468,9 +470,10 @@ def main() -> int:
     return 0
 
 
-def measured_traffic():
+def measured_traffic(layout_key: str):
     """HBM bytes per shot-kernel launch from the committed counter summary,
-    or None when the kernel source changed since the counters were taken."""
+    or None when the kernel source or the layout changed since the counters
+    were taken."""
     import hashlib
     src = os.path.join(ROOT, "paper_2609_19116_amd", "csrc", "kernels", "mps.hip")
     summ = os.path.join(ROOT, "profiles", "mps_kernel_c3_hbm_counters.md")
@@ -479,10 +482,11 @@ def measured_traffic():
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     vals = {}
     for line in open(summ):
-        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_sha256_16"):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_sha256_16",
+                                                  "layout"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_sha256_16") != sha:
+    if vals.get("kernel_sha256_16") != sha or vals.get("layout") != layout_key:
         return None
     return float(vals["traffic_bytes_per_launch"])
 

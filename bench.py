@@ -276,6 +276,10 @@ def main() -> int:
         "realised_chi_peak": chi_peak,
         "gate_updates_per_s": sum(n2q) / wall,
         "jacobi_sweeps_per_update": sweeps / max(1, sum(n2q)),
+        # exactness flags of the timed survivors: a Jacobi SVD that hit its
+        # sweep limit, or a bond cap that dropped weight above 1e-12
+        "status_flags": {"noconv": any(st["status_or"] & msc.SHOT_NOCONV for st in sts),
+                         "chi_cap": any(st["status_or"] & msc.SHOT_CHI_CAP for st in sts)},
         "kernel_ms": {"simulate_mean": float(np.mean(sim_ms)),
                       "prescreen_mean": float(np.mean(screen_ms)),
                       "sample_mean": float(np.mean(sample_ms))},

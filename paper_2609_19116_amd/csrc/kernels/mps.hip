@@ -97,12 +97,26 @@ __device__ __forceinline__ double group_sum(double v, int g) {
     return v;
 }
 
-__device__ __forceinline__ double wave_sum(double v) { return group_sum(v, 64); }
+// The double held by lane l (v_readlane, the same value in every lane).
+__device__ __forceinline__ double lane_read(double v, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Sum over the whole wavefront (all lanes active), every lane receiving it:
+// the row sums by DPP, then the four rows' sums read from lanes 0, 16, 32
+// and 48 and added in a fixed order.
+__device__ __forceinline__ double wave_sum(double v) {
+    v = group_sum(v, 16);
+    return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
+}
 
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    return v;
+    v = fmax(v, dpp_move<0xB1>(v));
+    v = fmax(v, dpp_move<0x4E>(v));
+    v = fmax(v, dpp_move<0x141>(v));
+    v = fmax(v, dpp_move<0x140>(v));
+    return fmax(fmax(lane_read(v, 0), lane_read(v, 16)), fmax(lane_read(v, 32), lane_read(v, 48)));
 }
 
 template <int W, int K>

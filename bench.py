@@ -53,7 +53,9 @@ def log(*a):
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=24)
+    ap.add_argument("--steps", type=int, default=192,
+                    help="timed steps; with 8 in flight, the fill and drain of the stream "
+                         "pipeline are a few percent of 192 steps")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--shots", type=int, default=4096)
     ap.add_argument("--p", type=float, default=1e-3)

@@ -72,6 +72,9 @@ def main() -> int:
     ap.add_argument("--order-starts", type=int, default=3,
                     help="independent starts of the order search (seeds ORDER_SEED + i); "
                          "the cheapest result is kept")
+    ap.add_argument("--order-refine", type=int, default=4,
+                    help="rounds of the search continued from the best order so far, "
+                         "--order-search evaluations each")
     ap.add_argument("--order-seed", type=lambda x: int(x, 0), default=ORDER_SEED)
     ap.add_argument("--lds-width", type=int, default=0)
     ap.add_argument("--slots", type=int, default=384,
@@ -127,20 +130,13 @@ def main() -> int:
     order_info = None
     order = None
     if args.order_search > 0:
-        t0 = time.perf_counter()
-        runs = [msc.order_search(ctx, cc.text, args.order_seed + i, args.order_search)
-                for i in range(max(1, args.order_starts))]
-        best = min(range(len(runs)), key=lambda i: runs[i][2])
-        order, c_start, c_best = runs[best]
-        order_info = {"budget": args.order_search, "starts": len(runs),
-                      "seed": hex(args.order_seed + best),
-                      "cost": "noiseless-run flops + fixed op costs (MSC_ORDER_COST_*)",
-                      "snake_cost": c_start, "searched_cost": c_best,
-                      "costs_of_starts": [r[2] for r in runs],
-                      "ratio": c_best / c_start, "seconds": time.perf_counter() - t0,
-                      "order": [int(q) for q in order]}
-        log(f"order search: cost {c_start:.4g} -> {c_best:.4g}")
-    layout_key = (f"search {max(1, args.order_starts)}x{args.order_search} from {args.order_seed:#x}"
+        order, order_info = benchmark_layout(msc, ctx, cc.text, args.order_seed,
+                                             args.order_search, args.order_starts,
+                                             args.order_refine)
+        log(f"order search: cost {order_info['snake_cost']:.4g} -> "
+            f"{order_info['searched_cost']:.4g}")
+    layout_key = (f"search {max(1, args.order_starts)}x{args.order_search} "
+                  f"+{args.order_refine} from {args.order_seed:#x}"
                   if args.order_search > 0 else "snake")
     circ = msc.Circuit(cc.text, order=order)
     circ.calibrate(ctx)
@@ -474,6 +470,32 @@ def main() -> int:
         c.close()
     print(json.dumps(result), flush=True)
     return 0
+
+
+def benchmark_layout(msc, ctx, text: str, seed: int = ORDER_SEED, budget: int = 128,
+                     starts: int = 3, refine: int = 4):
+    """The benchmark's MPS layout: the cheapest of `starts` runs of the order
+    search from the snake order (seeds seed + i), then `refine` runs that
+    continue from the cheapest order so far (seeds seed + 16 + j), each of
+    `budget` evaluations.  Returns (order, info)."""
+    t0 = time.perf_counter()
+    runs = [msc.order_search(ctx, text, seed + i, budget) for i in range(max(1, starts))]
+    best = min(range(len(runs)), key=lambda i: runs[i][2])
+    order, c_start, c_best = runs[best]
+    refined = []
+    for j in range(max(0, refine)):
+        o, _, c = msc.order_search(ctx, text, seed + 16 + j, budget, start=order)
+        if c < c_best:
+            order, c_best = o, c
+        refined.append(c_best)
+    info = {"budget": budget, "starts": len(runs), "refine_rounds": max(0, refine),
+            "best_start_seed": hex(seed + best),
+            "cost": "noiseless-run flops + fixed op costs (MSC_ORDER_COST_*)",
+            "snake_cost": c_start, "searched_cost": c_best,
+            "costs_of_starts": [r[2] for r in runs], "costs_after_refine": refined,
+            "ratio": c_best / c_start, "seconds": time.perf_counter() - t0,
+            "order": [int(q) for q in order]}
+    return order, info
 
 
 def measured_traffic(layout_key: str):

@@ -100,14 +100,15 @@ def test_order_search_errors(ctx):
 
 
 def test_benchmark_layout_changes_no_result(ctx):
-    # the 49-qubit workload under the order the benchmark's search finds
-    # (same seeds, starts and budget: the cheapest of three starts of 128
-    # evaluations) against its snake order, FP64, sampled shots
+    # the 49-qubit workload under the order the benchmark's layout search
+    # finds (the benchmark's own procedure and defaults) against its snake
+    # order, FP64, sampled shots
+    from bench import benchmark_layout
     cc = config_circuit("c3")
-    say("order search c3, 3 starts x 128 evaluations (the benchmark's), then 128 FP64 shots "
-        "on both layouts")
-    runs = [msc.order_search(ctx, cc.text, 0x5EED0081 + i, 128) for i in range(3)]
-    order, c0, c1 = min(runs, key=lambda r: r[2])
+    say("benchmark layout search on c3 (3 starts + 4 refinements x 128 evaluations), then "
+        "128 FP64 shots on both layouts")
+    order, info = benchmark_layout(msc, ctx, cc.text)
+    c0, c1 = info["snake_cost"], info["searched_cost"]
     assert c1 <= c0
     snake = msc.Circuit(cc.text)
     snake.calibrate(ctx)

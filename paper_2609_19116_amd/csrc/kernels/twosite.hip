@@ -295,10 +295,10 @@ __global__ __launch_bounds__(NTH, 2) void twosite_bf16x3_kernel(int chi, int til
         }
     };
     auto frag = [&](const unsigned short* p) { return *reinterpret_cast<const bf16x8*>(p); };
-    auto neg = [&](bf16x8 x) {
-        typedef unsigned short us8 __attribute__((ext_vector_type(8)));
-        us8 u = __builtin_bit_cast(us8, x);
-        u ^= (unsigned short)0x8000;
+    auto neg = [&](bf16x8 x) {   // both sign bits of each dword at once
+        typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+        u32x4 u = __builtin_bit_cast(u32x4, x);
+        u ^= 0x80008000u;
         return __builtin_bit_cast(bf16x8, u);
     };
 

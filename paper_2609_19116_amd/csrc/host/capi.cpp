@@ -296,6 +296,8 @@ static int enqueue_shots(msc_ctx* ctx, const msc_circuit* c, int precision, int 
                          int calibrate, double* cal_p, uint8_t* cal_e, int ck_mode,
                          const PrefixCk* pk, const int64_t* n_dev, double* surv = nullptr) {
     Layout L = make_layout(c->n, chi_max);
+    // the shot kernel keeps the site offsets within a slot as 32-bit values
+    if (L.slot_elems >= (int64_t(1) << 31)) return set_error(MSC_E_INVALID, "slot above 2^31 elements");
     const bool small = lds_width == 32;
     if (n_slots <= 0) n_slots = ctx->n_cu * mps_blocks_per_cu(precision, small);
     n_slots = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(n_slots, n)));

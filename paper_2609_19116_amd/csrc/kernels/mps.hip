@@ -45,7 +45,7 @@ constexpr int NT = 256;
 constexpr int NW = NT / 64;
 constexpr int MAXV = 2 * kMaxChiKernel;   // vectors in a two-site SVD
 constexpr int kStage = 2048;               // doubles of LDS staging per workgroup
-constexpr int kOpBuf = 256;                // op descriptors per LDS refill
+constexpr int kOpBuf = 128;                // op descriptors per LDS refill
 constexpr int kWaveSide = 16;              // largest theta side factorised by one wave
 
 // A team is either the whole workgroup (W == NT) or wavefront 0 (W == 64).
@@ -880,12 +880,16 @@ __device__ void fold_product(MP mr, MP mi, OP ore, OP oim, SiteView<T> Pv, doubl
     }
 }
 
+// Resident workgroups per CU the register budget is capped for: the shots
+// are latency-bound, so more resident shots raise the throughput more than
+// the spills of a tighter register cap cost.  The batched FP32 instance
+// (39.6 KB of LDS with SMAX = 32) runs four per CU with 128 VGPRs; the
+// others three (FP64 at SMAX = 32) or what their LDS allows (SMAX = 64).
 template <typename T, int SMAX>
-// Three workgroups per CU: the LDS (43.6 KB per workgroup for SMAX = 32)
-// allows three, the register budget is capped to match (a few spills); the
-// shots are latency-bound, so the third resident shot per CU raises the
-// throughput more than the spills cost.
-__global__ __launch_bounds__(NT, 3) void mps_kernel(MpsArgs P) {
+constexpr int kMpsWavesPerSimd = (sizeof(T) == sizeof(float) && SMAX == 32) ? 4 : 3;
+
+template <typename T, int SMAX>
+__global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(MpsArgs P) {
     __shared__ int s_chi[kMaxSites + 1];
     __shared__ int s_laste[kMaxSites];
     __shared__ double s_vre[SMAX * (SMAX + 1)];
@@ -903,8 +907,8 @@ __global__ __launch_bounds__(NT, 3) void mps_kernel(MpsArgs P) {
     __shared__ double s_g1[G1_COUNT * 8];
     __shared__ int s_g4src[G4_COUNT * 4];
     __shared__ double s_g4ph[G4_COUNT * 8];
-    __shared__ int64_t s_soff[kMaxSites];
-    __shared__ int64_t s_shalf[kMaxSites];
+    __shared__ int32_t s_soff[kMaxSites];    // offsets within a slot (< 2^31 elements)
+    __shared__ int32_t s_shalf[kMaxSites];
     __shared__ int s_cap[kMaxSites + 1];
     // op descriptors, kOpBuf at a time
     __shared__ DevOp s_ops[kOpBuf];

@@ -226,7 +226,7 @@ __device__ void jacobi_sweep(DP vre, DP vim, IP list, int nv, int len, int ld, d
                 DP xi = vim + (size_t)p * ld;
                 DP yr = vre + (size_t)q * ld;
                 DP yi = vim + (size_t)q * ld;
-#pragma unroll 4
+#pragma unroll 2
                 for (int e = gl; e < len; e += tpp) {
                     double x0 = xr[e], x1 = xi[e], y0 = yr[e], y1 = yi[e];
                     a += x0 * x0 + x1 * x1;
@@ -252,7 +252,7 @@ __device__ void jacobi_sweep(DP vre, DP vim, IP list, int nv, int len, int ld, d
                     DP xi = vim + (size_t)p * ld;
                     DP yr = vre + (size_t)q * ld;
                     DP yi = vim + (size_t)q * ld;
-#pragma unroll 4
+#pragma unroll 2
                     for (int e = gl; e < len; e += tpp) {
                         const double x0 = xr[e], x1 = xi[e], y0 = yr[e], y1 = yi[e];
                         // x - (s/|g|) conj(gamma) y and y + (s/|g|) gamma x
@@ -275,7 +275,7 @@ __device__ void vector_norms(DP vre, DP vim, int nv, int len, int ld, DP nrm) {
         double s0 = 0.0, s1 = 0.0;
         DP xr = vre + (size_t)v * ld;
         DP xi = vim + (size_t)v * ld;
-#pragma unroll 4
+#pragma unroll 2
         for (int e = 0; e < len; ++e) {
             s0 += xr[e] * xr[e];
             s1 += xi[e] * xi[e];
@@ -315,7 +315,7 @@ __device__ bool not_orthogonal(DP vre, DP vim, int nv, int len, int ld, DP nrm, 
         DP yr = vre + (size_t)q * ld;
         DP yi = vim + (size_t)q * ld;
         double gr = 0.0, gim = 0.0;
-#pragma unroll 4
+#pragma unroll 2
         for (int e = 0; e < len; ++e) {
             gr += xr[e] * yr[e] + xi[e] * yi[e];
             gim += xr[e] * yi[e] - xi[e] * yr[e];
@@ -594,7 +594,7 @@ __device__ double contract(AP Ar, AP Ai, AP Br, AP Bi, int cl, int cm, int cr, c
         T sr[4] = {T(0), T(0), T(0), T(0)}, si[4] = {T(0), T(0), T(0), T(0)};
         AP a0r = Ar + (a * 2) * cm;
         AP a0i = Ai + (a * 2) * cm;
-#pragma unroll 4
+#pragma unroll 2
         for (int c = 0; c < cm; ++c) {
             const T x0r = a0r[c], x0i = a0i[c], x1r = a0r[cm + c], x1i = a0i[cm + c];
             const int b0 = (c * 2) * cr + b, b1 = b0 + cr;
@@ -640,7 +640,7 @@ __device__ void project(TP thr, TP thi, int m, int n, int r, int dir, int ld, co
             DP ur = V.vre + (size_t)v * ld;
             DP ui = V.vim + (size_t)v * ld;
             double xr = 0.0, xi = 0.0;
-#pragma unroll 4
+#pragma unroll 2
             for (int row = 0; row < m; ++row) {
                 const double a0 = ur[row], a1 = ui[row];
                 const double t0 = thr[(size_t)row * n + col], t1 = thi[(size_t)row * n + col];
@@ -658,7 +658,7 @@ __device__ void project(TP thr, TP thi, int m, int n, int r, int dir, int ld, co
             DP wr = V.vre + (size_t)v * ld;
             DP wi = V.vim + (size_t)v * ld;
             double xr = 0.0, xi = 0.0;
-#pragma unroll 4
+#pragma unroll 2
             for (int col = 0; col < n; ++col) {
                 const double t0 = thr[(size_t)row * n + col], t1 = thi[(size_t)row * n + col];
                 const double b0 = wr[col], b1 = wi[col];
@@ -851,7 +851,7 @@ __device__ void fold_product(MP mr, MP mi, OP ore, OP oim, SiteView<T> Pv, doubl
         for (int idx = tid; idx < ol * 2 * pr; idx += NT) {
             const int row = idx / pr, c = idx - row * pr;
             double xr = 0.0, xi = 0.0;
-#pragma unroll 4
+#pragma unroll 2
             for (int b = 0; b < pl; ++b) {
                 const double ar = ore[row * pl + b], ai = oim[row * pl + b];
                 const double br = mr[b * pr + c], bi = mi[b * pr + c];
@@ -867,7 +867,7 @@ __device__ void fold_product(MP mr, MP mi, OP ore, OP oim, SiteView<T> Pv, doubl
         for (int idx = tid; idx < pl * w; idx += NT) {
             const int a = idx / w, rem = idx - a * w;
             double xr = 0.0, xi = 0.0;
-#pragma unroll 4
+#pragma unroll 2
             for (int b = 0; b < pr; ++b) {
                 const double ar = mr[a * pr + b], ai = mi[a * pr + b];
                 const double br = ore[b * w + rem], bi = oim[b * w + rem];

@@ -79,7 +79,7 @@ def main() -> int:
     ap.add_argument("--lds-width", type=int, default=0)
     ap.add_argument("--slots", type=int, default=192,
                     help="persistent workgroups (MPS slots) per context; 0 = one per "
-                         "resident workgroup of the GPU (768: three per CU).  With 16 "
+                         "resident workgroup of the GPU (1024: four per CU).  With 16 "
                          "contexts in flight, 192 slots of 51 MB (chi_max = 256) each "
                          "keep the arenas at 157 GB of the 288 GB")
     ap.add_argument("--streams", type=int, default=16,

@@ -435,3 +435,14 @@ def test_weight_one_bin_brute_force_matches_sampling():
     M, p = c.n_channels, 1e-6
     r = est.reweight([1, 1], [1.0, exact], [0, 0], M, p)
     assert r["p_acc"] == pytest.approx(1 - M * p * (1 - exact), abs=(M * p) ** 2)
+
+
+def test_bin_sums_hand_example():
+    # five shots by hand: weights 0, 2, 0, 1, 2 with P_acc 1, 1/2, 1/4, 0,
+    # 3/4 and failure flags 0, 1, 0, 0, 1 give per weight the shot counts
+    # (2, 1, 2), the P_acc sums (5/4, 0, 5/4) and the P_acc * fail sums
+    # (0, 0, 1/2 + 3/4)
+    n, a, e = est.bin_sums([0, 2, 0, 1, 2], [1.0, 0.5, 0.25, 0.0, 0.75], [0, 1, 0, 0, 1])
+    assert n == [2.0, 1.0, 2.0]
+    assert a == [1.25, 0.0, 1.25]
+    assert e == [0.0, 0.0, 1.25]

@@ -9,6 +9,8 @@
   p_acc^(w) and p_acc^(w) p_le^(w);
 * truncation bound B = sum_{w > w_max} Bin_w(p), added one-sided
   (Appendix "Systematics");
+* standard errors of the re-weighted sums from the per-bin variances
+  (independent bins);
 * loss multiplier (1 - p_l)^(-M) on the expected attempts (Appendix
   "Losses").
 """
@@ -61,6 +63,30 @@ def reweight(n, a, e, M: int, p: float):
     B = sum(binom_pmf(M, w, p) for w in range(wmax + 1, M + 1))
     return dict(p_acc=pacc, p_acc_le=ple_num,
                 p_le=(ple_num / pacc) if pacc > 0 else float("nan"), B=B)
+
+
+def standard_errors(n, a, e, M: int, p: float, a2=None, e2=None):
+    """Standard errors of the two lines of Eq. (reweight).  The bins are
+    independent samples, bin w holding n_w shots, so the variance of
+    sum_w Bin_w(p) mean_w is sum_w Bin_w(p)^2 var_w / n_w, with var_w the
+    variance of one shot's value in the bin: the unbiased sample variance
+    (sum of squares - sum * mean) / (n_w - 1) when the sums of squares are
+    given and n_w >= 2, else the Bhatia-Davis bound mean (1 - mean) of a
+    variable in [0, 1].  Returns (sem of p_acc, sem of p_acc p_le)."""
+    def var(w, s, s2):
+        mu = s[w] / n[w]
+        if s2 is not None and n[w] >= 2:
+            return max(0.0, (s2[w] - s[w] * mu) / (n[w] - 1))
+        return max(0.0, mu * (1.0 - mu))
+
+    va = ve = 0.0
+    for w in range(len(n)):
+        if n[w] <= 0:
+            continue
+        b = binom_pmf(M, w, p)
+        va += b * b * var(w, a, a2) / n[w]
+        ve += b * b * var(w, e, e2) / n[w]
+    return math.sqrt(va), math.sqrt(ve)
 
 
 def loss_multiplier(M: int, p_loss: float) -> float:

@@ -446,3 +446,48 @@ def test_bin_sums_hand_example():
     assert n == [2.0, 1.0, 2.0]
     assert a == [1.25, 0.0, 1.25]
     assert e == [0.0, 0.0, 1.25]
+
+
+def test_standard_errors_match_replicate_spread():
+    # the standard error of Eq. (reweight) against the spread of the
+    # estimator over replicate samples: per-bin values drawn from known
+    # distributions (Beta for P_acc, Bernoulli failures), 4000 replicates
+    rng = np.random.default_rng(11)
+    M, p = 60, 0.03
+    nw = [40, 25, 15, 8]
+    shapes = [(50.0, 1.0), (3.0, 2.0), (1.0, 1.5), (0.7, 0.9)]
+    pfail = [0.0, 0.1, 0.3, 0.5]
+    R = 4000
+    est_a, est_e, sem_a, sem_e = [], [], [], []
+    for _ in range(R):
+        n, a, e, a2, e2 = [], [], [], [], []
+        for w in range(4):
+            x = rng.beta(*shapes[w], size=nw[w])
+            y = x * (rng.random(nw[w]) < pfail[w])
+            n.append(float(nw[w]))
+            a.append(float(x.sum()))
+            e.append(float(y.sum()))
+            a2.append(float((x * x).sum()))
+            e2.append(float((y * y).sum()))
+        r = est.reweight(n, a, e, M, p)
+        sa, se = est.standard_errors(n, a, e, M, p, a2, e2)
+        est_a.append(r["p_acc"])
+        est_e.append(r["p_acc_le"])
+        sem_a.append(sa)
+        sem_e.append(se)
+    assert abs(np.mean(sem_a) / np.std(est_a) - 1.0) < 0.05
+    assert abs(np.mean(sem_e) / np.std(est_e) - 1.0) < 0.05
+
+
+def test_standard_error_bound_is_exact_for_bernoulli_bins():
+    # for 0/1 values the [0, 1] bound mean (1 - mean) is the variance
+    # itself: the bound's standard error at the true means equals the
+    # closed form sqrt(sum Bin_w^2 q_w (1 - q_w) / n_w)
+    M, p = 30, 0.05
+    q = [0.9, 0.4, 0.2]
+    n = [50.0, 20.0, 10.0]
+    a = [qi * ni for qi, ni in zip(q, n)]
+    sa, _ = est.standard_errors(n, a, [0.0] * 3, M, p)
+    ref = math.sqrt(sum(est.binom_pmf(M, w, p) ** 2 * q[w] * (1 - q[w]) / n[w]
+                        for w in range(3)))
+    assert abs(sa - ref) <= 1e-15 * ref

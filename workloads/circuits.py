@@ -277,6 +277,20 @@ def make_circuit(kind: str = "rot", d: int = 3, plain_rounds: int = 3,
     qid = {c: i for i, c in enumerate(coords)}
     n = len(coords)
     rows = sorted({c[1] for c in coords})
+    if order == "rainbow":
+        # coordinate rows taken from the outside in (first, last, second,
+        # second to last, ...), each left to right: a deliberately poor
+        # linear order whose cuts cross the patch twice (Section 3.1, the
+        # ordering problem), so the exact bond dimension grows
+        nested = []
+        lo, hi = 0, len(rows) - 1
+        while lo <= hi:
+            nested.append(rows[lo])
+            lo += 1
+            if lo <= hi:
+                nested.append(rows[hi])
+                hi -= 1
+        rows = nested
     site_order = []
     for r, y in enumerate(rows):
         row = sorted((c for c in coords if c[1] == y), key=lambda c: c[0])
@@ -443,13 +457,19 @@ def make_circuit(kind: str = "rot", d: int = 3, plain_rounds: int = 3,
 
 
 def config_circuit(name: str, target: str = "T") -> Circuit:
-    """Circuits of the named workloads (17, 49 and 81 qubits)."""
+    """Circuits of the named workloads (17, 49 and 81 qubits; c3_rainbow is
+    the 49-qubit circuit on the rainbow layout, which reaches bond
+    dimension 128 noiselessly)."""
     if name in ("c1", "c2", "rot3"):
         return make_circuit("rot", 3, plain_rounds=3, t_layers=1,
                             framed_rounds=1, final_rounds=1, target=target)
     if name in ("c3", "rot5"):
         return make_circuit("rot", 5, plain_rounds=2, t_layers=2,
                             framed_rounds=2, final_rounds=0, target=target)
+    if name in ("c3_rainbow", "rot5_rainbow"):
+        return make_circuit("rot", 5, plain_rounds=2, t_layers=2,
+                            framed_rounds=2, final_rounds=0, target=target,
+                            order="rainbow")
     if name in ("c4", "unrot5"):
         return make_circuit("unrot", 5, plain_rounds=2, t_layers=2,
                             framed_rounds=3, final_rounds=0, target=target)

@@ -50,7 +50,14 @@ class MPS:
         k, k+1, keeping singular values above tau * sigma_0."""
         cl, _, _, cr = theta.shape
         m = theta.reshape(cl * 2, 2 * cr)
-        u, s, vh = np.linalg.svd(m, full_matrices=False)
+        try:
+            u, s, vh = np.linalg.svd(m, full_matrices=False)
+        except np.linalg.LinAlgError:
+            # LAPACK's divide-and-conquer driver (gesdd) can fail to converge
+            # on exactly degenerate spectra; the QR-iteration driver (gesvd)
+            # computes the same decomposition
+            import scipy.linalg
+            u, s, vh = scipy.linalg.svd(m, full_matrices=False, lapack_driver="gesvd")
         keep = int(np.sum(s > self.tau * s[0])) if s[0] > 0 else 1
         keep = max(keep, 1)
         self.discarded += float(np.sum(s[keep:] ** 2))

@@ -212,7 +212,7 @@ def main() -> int:
         step(ctxs[b % S], b)
     wall, per = timed(warmup, args.steps)
     value = args.steps * n / wall
-    bin_n, bin_a, bin_e, bin_k, bin_m = sum(p[1] for p in per)
+    bin_n, bin_a, bin_e, bin_k, bin_m, bin_a2, bin_e2 = sum(p[1] for p in per)
     sts = [p[0] for p in per]
     n_surv = [st["n_survivors"] for st in sts]
     sim_ms = [st["ms_simulate"] for st in sts]
@@ -230,7 +230,7 @@ def main() -> int:
     sweeps = sum(st["sweeps"] for st in sts)
     log(f"steps={args.steps} wall={wall:.3f}s value={value:.1f} shots/s survivors={n_surv} "
         f"sim_ms={sim_ms} screen_ms={screen_ms} sample_ms={sample_ms}")
-    est = msc.reweight(bin_n, bin_a, bin_e, M, [5e-4, 1e-3, 2e-3])
+    est = msc.reweight(bin_n, bin_a, bin_e, M, [5e-4, 1e-3, 2e-3], bin_a2, bin_e2)
     # likelihood-ratio intervals (R = 100) of the two reported rates from the
     # timed shots' accepted / wrong counts (host post-processing, untimed)
     last = int(np.nonzero(bin_n)[0].max()) + 1

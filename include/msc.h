@@ -50,9 +50,10 @@ enum msc_precision {
     MSC_FP64 = 0,   /* complex128 tensors and contractions                    */
     MSC_FP32 = 1,   /* complex64 tensors, FP32 contractions, FP64 truncation,
                        norms and probabilities                                */
-    MSC_BF16X3 = 2  /* two-site contraction only: FP32 inputs split into
-                       bf16 hi + lo, three bf16 products per real product,
-                       FP32 accumulation (relative error ~1e-5)               */
+    MSC_BF16X3 = 2  /* as MSC_FP32, but the batched engine's contractions
+                       split FP32 inputs into bf16 hi + lo and take three
+                       bf16 products per real product with FP32
+                       accumulation (relative error ~1e-5)                   */
 };
 
 /* bits of msc_shot_result.status */
@@ -114,7 +115,22 @@ typedef struct {
                              checkpoints are built once per circuit and option
                              set (first call) and results are bit-identical
                              to prefix = 0.  0: every shot from |0...0>.     */
+    int32_t large_side;   /* two-site updates whose theta has a side above
+                             this go to the batched engine: the shot parks,
+                             and the updates of all parked shots run together
+                             as ragged MFMA contractions (tensor precision;
+                             BF16x3 splits for MSC_BF16X3), FP64 Gram
+                             matrices on MFMA and FP64 eigen-decompositions of
+                             their overlapping blocks, then the shots resume.
+                             0: 64; -1: off (the shot kernel factorises every
+                             update itself, in HBM scratch when wide); any
+                             other value must be at least 2.                */
+    int32_t use_graphs;   /* 1: one engine round (its ~10 launches) is
+                             captured once as a HIP graph and replayed      */
     int32_t reserved;     /* must be 0                                       */
+    const char* autotune_cache; /* path of an msc_autotune JSON file giving
+                             the engine's tile shapes per precision and bucket
+                             of theta sides; NULL: built-in shapes          */
 } msc_sim_opts;
 
 typedef struct {
@@ -139,6 +155,8 @@ typedef struct {
     double p_acc_le;      /* Eq. (reweight), second line                     */
     double p_le;          /* p_acc_le / p_acc                                */
     double trunc_bound;   /* B = sum_{w > w_max} Bin_w(p)                     */
+    double sem_p_acc;     /* standard error of p_acc (see msc_reweight)      */
+    double sem_p_acc_le;  /* standard error of p_acc_le                      */
 } msc_estimate;
 
 typedef struct {
@@ -165,9 +183,13 @@ const char* msc_version(void);
 /* ---------------------------------------------------------------------- */
 /* Context: one GPU, one stream, grow-only device scratch.                 */
 
-/* Create a context on HIP device `device` with its own non-blocking stream
-   (default priority).  Fails with MSC_E_DEVICE when no GPU is usable.    */
-int msc_ctx_create(int device, msc_ctx** out);
+/* Create a context on HIP device `device`.  `stream` is the hipStream_t
+   every device entry point of the context runs on: NULL gives the context
+   a non-blocking stream of its own (default priority, destroyed with the
+   context); a caller's stream is used as is and stays the caller's (it
+   must belong to `device` and outlive the context).  Fails with
+   MSC_E_DEVICE when no GPU is usable.                                     */
+int msc_ctx_create(int device, void* stream, msc_ctx** out);
 void msc_ctx_destroy(msc_ctx* ctx);
 /* Duration in ms of the last kernel work of the named kind, measured with
    HIP events on the context's stream: "sample" (device fault draws),
@@ -176,6 +198,23 @@ void msc_ctx_destroy(msc_ctx* ctx);
    sets "sample", "prescreen" and "simulate".  Returns a negative value if
    none was timed.                                                         */
 double msc_ctx_last_kernel_ms(msc_ctx* ctx, const char* which);
+
+/* What the batched engine for large two-site updates did in the context's
+   last msc_simulate or msc_run_batch call (zero if nothing parked).       */
+typedef struct {
+    int64_t rounds;         /* engine rounds (each: all parked updates)      */
+    int64_t updates;        /* two-site updates done by the engine           */
+    double contract_flops;  /* algorithmic: 32 cl cm cr per update          */
+    double gram_flops;      /* algorithmic: 4 nv (nv + 1) len per update     */
+    double contract_ms;     /* kernel time of the contractions (HIP events;
+                               0 when the rounds ran as graph replays)      */
+    double gram_ms;         /* kernel time of the Gram matrices             */
+    double factor_ms;       /* kernel time of the factor steps              */
+    double shot_ms;         /* kernel time of the shot kernel's launches     */
+    double total_ms;        /* all of the call's shot work                   */
+} msc_engine_stats;
+
+int msc_ctx_engine_stats(msc_ctx* ctx, msc_engine_stats* out);
 
 /* ---------------------------------------------------------------------- */
 /* Circuit: parse + compile on the host (no GPU needed).                  */
@@ -284,13 +323,15 @@ int msc_simulate(msc_ctx* ctx, const msc_circuit* c, const msc_sim_opts* opts,
    (Section 4.1), screened as by msc_prescreen (Section 4.2), the survivors
    simulated as by msc_simulate with `opts` (Sections 3.1, 4, 4.3), and the
    results reduced per fault weight for Eq. (reweight): bins (host,
-   5 * n_bins doubles, 1 <= n_bins <= 1024) receives bins[w] = number of
+   7 * n_bins doubles, 1 <= n_bins <= 1024) receives bins[w] = number of
    shots of weight w, bins[n_bins + w] = sum of their P_acc,
    bins[2 n_bins + w] = sum of P_acc * fail (both summed in a fixed
    order), and the counts of the error analysis's likelihood (Eq.
    (loglik-split)): bins[3 n_bins + w] = shots counted as accepted, i.e.
    with u < P_acc for the shot's acceptance uniform u, bins[4 n_bins + w] =
-   those of them whose accepted branch fails.  u = (x >> 11) 2^-53 with x
+   those of them whose accepted branch fails; bins[5 n_bins + w] and
+   bins[6 n_bins + w] are the sums of P_acc^2 and (P_acc * fail)^2 (fixed
+   order) for the standard errors of msc_reweight.  u = (x >> 11) 2^-53 with x
    the first output of the SplitMix64 stream keyed as the fault draws but
    with seed ^ 0x243F6A8885A308D3.  Weights >= n_bins - 1 share the last
    bin; screened shots count with P_acc = 0.  stats (host) is optional.  out (device, n_shots records) is
@@ -364,12 +405,19 @@ int msc_twosite_contract(msc_ctx* ctx, int32_t precision, int32_t chi,
 /* Re-weighting (Section 4.1, Eq. (reweight); Appendix "Systematics").     */
 
 /* Per-bin sums (host, n_bins each): bin_n[w] shots, bin_acc[w] = sum of
-   P_acc, bin_fail[w] = sum of P_acc * fail.  For each p in p_grid (host,
-   n_p) writes out[k] (host): p_acc, p_acc * p_le, p_le and the truncation
-   bound B = sum_{w >= n_bins} Bin_w(p).  Bins with bin_n[w] == 0 are
-   skipped.                                                                */
+   P_acc, bin_fail[w] = sum of P_acc * fail, and optionally (host or NULL)
+   bin_acc2[w], bin_fail2[w] the sums of their squares (msc_run_batch's
+   rows 5 and 6).  For each p in p_grid (host, n_p) writes out[k] (host):
+   p_acc, p_acc * p_le, p_le, the truncation bound
+   B = sum_{w >= n_bins} Bin_w(p), and the standard errors of the first two:
+   the bins are independent samples, so sem^2 = sum_w Bin_w(p)^2 var_w / n_w
+   with var_w the unbiased sample variance of the bin's per-shot values
+   when the sums of squares are given and n_w >= 2, else the Bhatia-Davis
+   bound mu_w (1 - mu_w) of a variable in [0, 1] with mean mu_w.  Bins with
+   bin_n[w] == 0 are skipped.                                              */
 int msc_reweight(const double* bin_n, const double* bin_acc,
-                 const double* bin_fail, int32_t n_bins, int64_t M,
+                 const double* bin_fail, const double* bin_acc2,
+                 const double* bin_fail2, int32_t n_bins, int64_t M,
                  const double* p_grid, int32_t n_p, msc_estimate* out);
 
 /* ---------------------------------------------------------------------- */
@@ -404,6 +452,12 @@ int msc_reweight(const double* bin_n, const double* bin_acc,
 int msc_order_search(msc_ctx* ctx, const char* text, size_t len,
                      const int32_t* start, uint64_t seed, int32_t budget,
                      int32_t* order_out, double* cost_out);
+
+/* The search's cost of a calibrated circuit's own order (host out): the
+   algorithmic flops of its noiseless run + MSC_ORDER_COST_PSWAP *
+   n_product_swaps + MSC_ORDER_COST_MOVE * n_moves + MSC_ORDER_COST_TWOSITE *
+   n_twosite.  MSC_E_STATE before calibration.                            */
+int msc_order_cost(const msc_circuit* c, double* out);
 
 /* ---------------------------------------------------------------------- */
 /* Likelihood statistics (Appendix "Error analysis of the subset-sampling  */

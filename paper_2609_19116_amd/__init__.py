@@ -12,7 +12,7 @@ import ctypes as C
 
 import numpy as np
 
-from ._lib import (BatchStats, MSC_BF16X3, MSC_FP32, MSC_FP64, MSC_STAT_PACC,  # noqa: F401
+from ._lib import (BatchStats, EngineStats, MSC_BF16X3, MSC_FP32, MSC_FP64, MSC_STAT_PACC,  # noqa: F401
                    MSC_ORDER_COST_MOVE, MSC_ORDER_COST_PSWAP, MSC_ORDER_COST_TWOSITE,
                    MSC_STAT_PLE, SEGMENT_DTYPE, SHOT_CHI_CAP, SHOT_DONE, SHOT_DTYPE, SHOT_NOCONV,
                    SHOT_REJECTED, CircuitInfo, Estimate, Interval, MscError, SimOpts, _check,
@@ -30,13 +30,17 @@ def version() -> str:
 
 
 class Ctx:
-    """msc_ctx: one GPU, one stream, device scratch."""
+    """msc_ctx: one GPU, one stream, device scratch.  ``stream`` (optional) is
+    a torch.cuda.Stream of that GPU for the context to run on; by default
+    the context creates a stream of its own."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, stream=None):
         h = C.c_void_p()
-        _check(lib().msc_ctx_create(device, C.byref(h)))
+        raw = None if stream is None else C.c_void_p(stream.cuda_stream)
+        _check(lib().msc_ctx_create(device, raw, C.byref(h)))
         self.h = h
         self.device = device
+        self.stream = stream
 
     def close(self) -> None:
         if self.h:
@@ -51,6 +55,12 @@ class Ctx:
 
     def last_kernel_ms(self, which: str) -> float:
         return lib().msc_ctx_last_kernel_ms(self.h, which.encode())
+
+    def engine_stats(self) -> dict:
+        """msc_ctx_engine_stats: the large-update engine in the last shot run."""
+        st = EngineStats()
+        _check(lib().msc_ctx_engine_stats(self.h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in EngineStats._fields_}
 
 
 class Circuit:
@@ -116,12 +126,10 @@ def order_search(ctx: Ctx, text: str, seed: int, budget: int, start=None):
 
 
 def order_cost(circ: Circuit) -> float:
-    """The order-search cost of a calibrated circuit: noiseless-run flops +
-    MSC_ORDER_COST_PSWAP * product swaps + MSC_ORDER_COST_MOVE * centre
-    moves + MSC_ORDER_COST_TWOSITE * two-site updates."""
-    inf = circ.info()
-    return (circ.noiseless()["flops"] + MSC_ORDER_COST_PSWAP * inf["n_product_swaps"] +
-            MSC_ORDER_COST_MOVE * inf["n_moves"] + MSC_ORDER_COST_TWOSITE * inf["n_twosite"])
+    """msc_order_cost: the order-search cost of a calibrated circuit."""
+    out = C.c_double()
+    _check(lib().msc_order_cost(circ.h, C.byref(out)))
+    return out.value
 
 
 def sample_faults(circ: Circuit, seed: int, first_shot: int, n_shots: int,
@@ -201,19 +209,29 @@ def prescreen(ctx: Ctx, circ: Circuit, off, chan, pauli, with_index: bool = True
     return bits, (idx[:cnt.value] if idx is not None else None), cnt.value
 
 
+def _opts(precision, chi_max, tau_trunc, tau_rej, tau_fail, n_slots, lds_width, prefix,
+          large_side=0, use_graphs=False, autotune_cache=None) -> SimOpts:
+    cache = None if autotune_cache is None else str(autotune_cache).encode()
+    return SimOpts(precision, chi_max, tau_trunc, tau_rej, tau_fail, n_slots, lds_width,
+                   1 if prefix else 0, large_side, 1 if use_graphs else 0, 0, cache)
+
+
 def simulate(ctx: Ctx, circ: Circuit, off, chan, pauli, shot_idx=None, precision=MSC_FP64,
              chi_max: int = 256, tau_trunc: float = 0.0, tau_rej: float = 1e-6,
              tau_fail: float = 1e-4, n_slots: int = 0, lds_width: int = 0, prefix: bool = False,
-             out=None):
+             out=None, large_side: int = 0, use_graphs: bool = False, autotune_cache=None):
     """Simulate shots (device CSR); returns a uint8 device tensor holding
-    msc_shot_result records (view them with ``results_numpy``)."""
+    msc_shot_result records (view them with ``results_numpy``).
+    ``large_side`` (0: 64, -1: off) hands wider two-site updates to the
+    batched engine; ``use_graphs`` replays its rounds from a HIP graph;
+    ``autotune_cache`` names an msc_autotune file of tile shapes."""
     import torch
     n_shots = off.numel() - 1
     n = shot_idx.numel() if shot_idx is not None else n_shots
     if out is None:
         out = torch.empty(max(n, 1) * SHOT_DTYPE.itemsize, dtype=torch.uint8, device=off.device)
-    o = SimOpts(precision, chi_max, tau_trunc, tau_rej, tau_fail, n_slots, lds_width,
-                1 if prefix else 0, 0)
+    o = _opts(precision, chi_max, tau_trunc, tau_rej, tau_fail, n_slots, lds_width, prefix,
+              large_side, use_graphs, autotune_cache)
     _check(lib().msc_simulate(ctx.h, circ.h, C.byref(o), n_shots, _ptr(off), _ptr(chan),
                               _ptr(pauli), _ptr(shot_idx), n, _ptr(out)))
     return out[: n * SHOT_DTYPE.itemsize]
@@ -230,8 +248,7 @@ def simulate_camps(ctx: Ctx, circ: Circuit, off, chan, pauli, shot_idx=None,
     n = shot_idx.numel() if shot_idx is not None else n_shots
     if out is None:
         out = torch.empty(max(n, 1) * SHOT_DTYPE.itemsize, dtype=torch.uint8, device=off.device)
-    o = SimOpts(MSC_FP64, chi_max, tau_trunc, tau_rej, tau_fail, n_slots, 0,
-                1 if prefix else 0, 0)
+    o = _opts(MSC_FP64, chi_max, tau_trunc, tau_rej, tau_fail, n_slots, 0, prefix)
     _check(lib().msc_simulate_camps(ctx.h, circ.h, C.byref(o), n_shots, _ptr(off), _ptr(chan),
                                     _ptr(pauli), _ptr(shot_idx), n, _ptr(out)))
     return out[: n * SHOT_DTYPE.itemsize]
@@ -252,18 +269,19 @@ def camps_candidates():
 def run_batch(ctx: Ctx, circ: Circuit, seed: int, first_shot: int, n_shots: int, p: float,
               n_bins: int = 65, precision=MSC_FP32, chi_max: int = 256, tau_trunc: float = 0.0,
               tau_rej: float = 1e-6, tau_fail: float = 1e-4, n_slots: int = 0,
-              lds_width: int = 0, prefix: bool = True, out=None, space_time: bool = False):
+              lds_width: int = 0, prefix: bool = True, out=None, space_time: bool = False,
+              large_side: int = 0, use_graphs: bool = False, autotune_cache=None):
     """One batch of the whole path (sampling, screen, shots, bin sums) on the
     context's stream with one synchronisation.  Returns (bins float64
-    [5, n_bins]: shots, sum P_acc, sum P_acc * fail, accepted count, wrong
-    count per weight; stats dict).  With ``space_time`` the offline screen
+    [7, n_bins]: shots, sum P_acc, sum P_acc * fail, accepted count, wrong
+    count, sum P_acc^2, sum (P_acc * fail)^2 per weight; stats dict).  With ``space_time`` the offline screen
     is skipped and stats["surv_bins"] holds float64 [n_bins, n_seg]: per
     weight the summed probabilities of reaching each segment.
     ``out`` (optional uint8 device tensor of n_shots records) receives the
     per-shot results, indexed by shot."""
-    o = SimOpts(precision, chi_max, tau_trunc, tau_rej, tau_fail, n_slots, lds_width,
-                1 if prefix else 0, 0)
-    bins = np.zeros(5 * n_bins, dtype=np.float64)
+    o = _opts(precision, chi_max, tau_trunc, tau_rej, tau_fail, n_slots, lds_width, prefix,
+              large_side, use_graphs, autotune_cache)
+    bins = np.zeros(7 * n_bins, dtype=np.float64)
     st = BatchStats()
     if out is not None:
         assert out.numel() >= n_shots * SHOT_DTYPE.itemsize
@@ -275,7 +293,7 @@ def run_batch(ctx: Ctx, circ: Circuit, seed: int, first_shot: int, n_shots: int,
     stats = {f: getattr(st, f) for f, _ in BatchStats._fields_}
     if space_time:
         stats["surv_bins"] = surv.reshape(n_bins, -1)
-    return bins.reshape(5, n_bins), stats
+    return bins.reshape(7, n_bins), stats
 
 
 def results_numpy(out) -> np.ndarray:
@@ -288,16 +306,19 @@ def twosite_contract(ctx: Ctx, chi: int, batch: int, A, B, gate, theta,
                                       _ptr(theta)))
 
 
-def reweight(bin_n, bin_acc, bin_fail, M: int, p_grid) -> list:
+def reweight(bin_n, bin_acc, bin_fail, M: int, p_grid, bin_acc2=None, bin_fail2=None) -> list:
+    """Eq. (reweight) per p, with standard errors (from the sums of squares
+    when given, else the [0, 1] variance bound)."""
     n = np.ascontiguousarray(bin_n, dtype=np.float64)
     a = np.ascontiguousarray(bin_acc, dtype=np.float64)
     e = np.ascontiguousarray(bin_fail, dtype=np.float64)
+    a2 = None if bin_acc2 is None else np.ascontiguousarray(bin_acc2, dtype=np.float64)
+    e2 = None if bin_fail2 is None else np.ascontiguousarray(bin_fail2, dtype=np.float64)
     pg = np.ascontiguousarray(p_grid, dtype=np.float64)
     out = (Estimate * len(pg))()
-    _check(lib().msc_reweight(_ptr(n), _ptr(a), _ptr(e), len(n), M, _ptr(pg), len(pg),
-                              C.cast(out, C.c_void_p)))
-    return [dict(p_acc=o.p_acc, p_acc_le=o.p_acc_le, p_le=o.p_le, trunc_bound=o.trunc_bound)
-            for o in out]
+    _check(lib().msc_reweight(_ptr(n), _ptr(a), _ptr(e), _ptr(a2), _ptr(e2), len(n), M,
+                              _ptr(pg), len(pg), C.cast(out, C.c_void_p)))
+    return [{f: getattr(o, f) for f, _ in Estimate._fields_} for o in out]
 
 
 def _counts(bin_n, bin_acc, bin_err):

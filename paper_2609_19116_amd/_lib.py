@@ -50,7 +50,9 @@ class CircuitInfo(C.Structure):
 class SimOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("chi_max", C.c_int32), ("tau_trunc", C.c_double),
                 ("tau_rej", C.c_double), ("tau_fail", C.c_double), ("n_slots", C.c_int32),
-                ("lds_width", C.c_int32), ("prefix", C.c_int32), ("reserved", C.c_int32)]
+                ("lds_width", C.c_int32), ("prefix", C.c_int32), ("large_side", C.c_int32),
+                ("use_graphs", C.c_int32), ("reserved", C.c_int32),
+                ("autotune_cache", C.c_char_p)]
 
 
 class BatchStats(C.Structure):
@@ -74,9 +76,16 @@ SHOT_DTYPE = np.dtype([("p_acc", "<f8"), ("infid", "<f8"), ("disc_weight", "<f8"
 assert SHOT_DTYPE.itemsize == C.sizeof(ShotResult) == 64
 
 
+class EngineStats(C.Structure):
+    _fields_ = [("rounds", C.c_int64), ("updates", C.c_int64), ("contract_flops", C.c_double),
+                ("gram_flops", C.c_double), ("contract_ms", C.c_double), ("gram_ms", C.c_double),
+                ("factor_ms", C.c_double), ("shot_ms", C.c_double), ("total_ms", C.c_double)]
+
+
 class Estimate(C.Structure):
     _fields_ = [("p_acc", C.c_double), ("p_acc_le", C.c_double), ("p_le", C.c_double),
-                ("trunc_bound", C.c_double)]
+                ("trunc_bound", C.c_double), ("sem_p_acc", C.c_double),
+                ("sem_p_acc_le", C.c_double)]
 
 
 class Interval(C.Structure):
@@ -96,9 +105,10 @@ _P = C.c_void_p
 _SIGS = {
     "msc_last_error": (C.c_char_p, []),
     "msc_version": (C.c_char_p, []),
-    "msc_ctx_create": (C.c_int, [C.c_int, C.POINTER(_P)]),
+    "msc_ctx_create": (C.c_int, [C.c_int, _P, C.POINTER(_P)]),
     "msc_ctx_destroy": (None, [_P]),
     "msc_ctx_last_kernel_ms": (C.c_double, [_P, C.c_char_p]),
+    "msc_ctx_engine_stats": (C.c_int, [_P, C.POINTER(EngineStats)]),
     "msc_circuit_load": (C.c_int, [C.c_char_p, C.c_size_t, _P, C.POINTER(_P)]),
     "msc_circuit_get_info": (C.c_int, [_P, C.POINTER(CircuitInfo)]),
     "msc_circuit_expected": (C.c_int, [_P, _P]),
@@ -107,6 +117,7 @@ _SIGS = {
     "msc_circuit_segments": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_int32)]),
     "msc_order_search": (C.c_int, [_P, C.c_char_p, C.c_size_t, _P, C.c_uint64, C.c_int32, _P,
                                    _P]),
+    "msc_order_cost": (C.c_int, [_P, C.POINTER(C.c_double)]),
     "msc_circuit_free": (None, [_P]),
     "msc_sample_faults": (C.c_int, [_P, C.c_uint64, C.c_uint64, C.c_int64, _P, C.c_double,
                                     _P, _P, _P, C.c_int64, C.POINTER(C.c_int64)]),
@@ -123,7 +134,7 @@ _SIGS = {
     "msc_simulate_camps": (C.c_int, [_P, _P, C.POINTER(SimOpts), C.c_int64, _P, _P, _P, _P,
                                      C.c_int64, _P]),
     "msc_camps_candidates": (C.c_int, [_P, _P, C.POINTER(C.c_int32)]),
-    "msc_reweight": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, _P, C.c_int32, _P]),
+    "msc_reweight": (C.c_int, [_P, _P, _P, _P, _P, C.c_int32, C.c_int64, _P, C.c_int32, _P]),
     "msc_profile_loglik": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, C.c_double, C.c_int32,
                                      C.c_int32, C.c_double, C.POINTER(C.c_double)]),
     "msc_lr_interval": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int64, C.c_double, C.c_int32,

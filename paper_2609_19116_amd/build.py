@@ -33,6 +33,7 @@ SOURCES = [
     CSRC / "kernels" / "batch.hip",
     CSRC / "kernels" / "camps.hip",
     CSRC / "kernels" / "twosite.hip",
+    CSRC / "kernels" / "lx.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -3,6 +3,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -40,6 +42,7 @@ struct DevBuf {
 struct msc_ctx {
     int device = -1;
     hipStream_t stream = nullptr;
+    bool own_stream = false;     // created here (destroyed with the context)
     int n_cu = 0;
     std::map<std::string, DevBuf> bufs;       // grow-only scratch
     std::map<std::string, double> last_ms;
@@ -53,6 +56,12 @@ struct msc_ctx {
     void* hmap = nullptr;
     void* hmap_dev = nullptr;
     size_t hmap_bytes = 0;
+    // one round of the large-update engine captured as a graph, and the
+    // bytes of the arguments it was captured with
+    hipGraphExec_t lx_exec = nullptr;
+    std::string lx_key;
+    msc_engine_stats lx_stats{}; // the engine in the last shot run
+    hipEvent_t lxev[6] = {};     // phase boundaries of an engine round
 };
 
 static int ctx_buf(msc_ctx* ctx, const std::string& name, size_t bytes, void** out) {
@@ -73,11 +82,21 @@ static int ctx_buf(msc_ctx* ctx, const std::string& name, size_t bytes, void** o
     return MSC_OK;
 }
 
+// MSC_E_INVALID with the CSR check bits spelled out
+static int csr_error(int bad) {
+    std::string m = "invalid fault CSR:";
+    if (bad & CSR_BAD_CHANNEL) m += " channel index outside [0, M);";
+    if (bad & CSR_NOT_ASCENDING) m += " channels of a shot not strictly ascending;";
+    if (bad & CSR_BAD_PAULI) m += " Pauli code zero or beyond the channel's qubits;";
+    if (bad & CSR_BAD_OFFSETS) m += " shot offsets decreasing or negative;";
+    return set_error(MSC_E_INVALID, m);
+}
+
 extern "C" const char* msc_last_error(void) { return g_err.c_str(); }
 
 extern "C" const char* msc_version(void) { return "msc-mps 0.1 (gfx950)"; }
 
-extern "C" int msc_ctx_create(int device, msc_ctx** out) {
+extern "C" int msc_ctx_create(int device, void* stream, msc_ctx** out) {
     if (!out) return set_error(MSC_E_INVALID, "null out");
     *out = nullptr;
     int n = 0;
@@ -90,12 +109,18 @@ extern "C" int msc_ctx_create(int device, msc_ctx** out) {
     std::unique_ptr<msc_ctx> ctx(new msc_ctx());
     ctx->device = device;
     MSC_HIP(hipSetDevice(device));
-    MSC_HIP(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+    if (stream) {
+        ctx->stream = static_cast<hipStream_t>(stream);
+    } else {
+        MSC_HIP(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+        ctx->own_stream = true;
+    }
     MSC_HIP(hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, device));
     MSC_HIP(hipEventCreate(&ctx->ev0));
     MSC_HIP(hipEventCreate(&ctx->ev1));
     MSC_HIP(hipEventCreate(&ctx->ev2));
     MSC_HIP(hipEventCreate(&ctx->ev3));
+    for (hipEvent_t& ev : ctx->lxev) MSC_HIP(hipEventCreate(&ev));
     *out = ctx.release();
     return MSC_OK;
 }
@@ -108,9 +133,18 @@ extern "C" void msc_ctx_destroy(msc_ctx* ctx) {
         if (kv.second.p) (void)hipFree(kv.second.p);
     for (hipEvent_t ev : {ctx->ev0, ctx->ev1, ctx->ev2, ctx->ev3})
         if (ev) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : ctx->lxev)
+        if (ev) (void)hipEventDestroy(ev);
     if (ctx->hmap) (void)hipHostFree(ctx->hmap);
-    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    if (ctx->lx_exec) (void)hipGraphExecDestroy(ctx->lx_exec);
+    if (ctx->stream && ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
+}
+
+extern "C" int msc_ctx_engine_stats(msc_ctx* ctx, msc_engine_stats* out) {
+    if (!ctx || !out) return set_error(MSC_E_INVALID, "null argument");
+    *out = ctx->lx_stats;
+    return MSC_OK;
 }
 
 extern "C" double msc_ctx_last_kernel_ms(msc_ctx* ctx, const char* which) {
@@ -262,7 +296,9 @@ struct Layout {
     int64_t scratch = 0;        // doubles per slot
 };
 
-Layout make_layout(int n, int chi_max) {
+// side_in: the widest theta the shot kernel factorises itself (in its HBM
+// scratch when wider than its LDS vectors); wider ones go to the engine
+Layout make_layout(int n, int chi_max, int side_in) {
     Layout L;
     L.cap.resize(n + 1);
     // every inner bond may reach chi_max: swapping an unentangled qubit
@@ -279,28 +315,85 @@ Layout make_layout(int n, int chi_max) {
         pos += 2 * elems;
     }
     L.slot_elems = (pos + 63) / 64 * 64;
-    int64_t s = 2ll * chi_max;
-    // theta copy + padded vectors, then per-vector arrays (6 x 512 doubles)
-    L.scratch = 4 * s * s + 4 * s + 64 + 6 * 2 * kMaxChiKernel;
+    const int64_t s = std::min<int64_t>(2ll * chi_max, side_in);
+    const int64_t cm = chi_max;
+    // the shot kernel's FP64 scratch: theta copy + padded vectors of an
+    // in-kernel factorisation, the staged neighbour of a centre move (at
+    // most 64 kept vectors of 2 chi_max), or a product swap's bond matrix,
+    // then the per-vector arrays (6 x 2 kMaxChiKernel doubles)
+    const int64_t work = std::max({4 * s * s + 4 * s, 4 * 64 * cm, 2 * cm * cm});
+    L.scratch = work + 64 + 6 * 2 * kMaxChiKernel;
     return L;
 }
 
+// Options of one shot-kernel run.
+struct RunCfg {
+    int precision = MSC_FP64;
+    int chi_max = 256;
+    double tau = 1e-12, tau_rej = 1e-6, tau_fail = 1e-4;
+    int n_slots = 0;
+    int lds_width = 32;
+    int park_side = 64;          // 0: the shot kernel does every update
+    bool graphs = false;
+    LxTiles tiles[kLxBuckets];
+};
+
 }  // namespace
 
-// Enqueues the order and shot kernels on the context's stream (no wait).
-// n bounds the shots (a device count n_dev, if given, may be smaller).
-static int enqueue_shots(msc_ctx* ctx, const msc_circuit* c, int precision, int chi_max,
-                         double tau, double tau_rej, double tau_fail, int n_slots, int lds_width,
-                         int64_t n, int64_t n_csr, const int64_t* off, const int32_t* chan,
+// The engine's tile shapes when no autotune cache names them: per bucket of
+// theta sides (<= 128, <= 256, <= 512, larger).
+static void default_tiles(int precision, LxTiles* t) {
+    for (int b = 0; b < kLxBuckets; ++b) {
+        if (precision == MSC_FP64) t[b] = b == 0 ? LxTiles{32, 32, 32} : LxTiles{64, 32, 64};
+        else t[b] = b == 0 ? LxTiles{64, 32, 64} : LxTiles{128, 64, 64};
+    }
+}
+
+// One round of the engine on the context's stream: plan, contraction and
+// Gram per bucket, factor, park count cleared, shot kernel resumed.
+// With `timed`, events at the phase boundaries (lxev[0..4]; not in a graph).
+static int enqueue_lx_round(msc_ctx* ctx, const RunCfg& cfg, bool small, const MpsArgs& a,
+                            const LxArgs& lx, const LxFactor& fac, int n_slots, bool timed) {
+    const int grid = ctx->n_cu * 4;
+    hipStream_t s = ctx->stream;
+    if (timed) MSC_HIP(hipEventRecord(ctx->lxev[0], s));
+    MSC_HIP(launch_lx_plan(lx, cfg.tiles, s));
+    for (int b = 0; b < kLxBuckets; ++b)
+        MSC_HIP(launch_lx_contract(cfg.precision, lx, b, cfg.tiles[b], grid, s));
+    if (timed) MSC_HIP(hipEventRecord(ctx->lxev[1], s));
+    for (int b = 0; b < kLxBuckets; ++b)
+        MSC_HIP(launch_lx_gram(cfg.precision, lx, b, cfg.tiles[b], grid, s));
+    if (timed) MSC_HIP(hipEventRecord(ctx->lxev[2], s));
+    MSC_HIP(launch_lx_factor(cfg.precision, lx, fac, n_slots, s));
+    MSC_HIP(launch_lx_clear(a.park_count, s));
+    if (timed) MSC_HIP(hipEventRecord(ctx->lxev[3], s));
+    MSC_HIP(launch_mps(cfg.precision, small, a, n_slots, s));
+    if (timed) MSC_HIP(hipEventRecord(ctx->lxev[4], s));
+    return MSC_OK;
+}
+
+// Enqueues the order and shot kernels on the context's stream.  n bounds the
+// shots (a device count n_dev, if given, may be smaller).  With the engine
+// on (cfg.park_side > 0) the shot kernel parks every shot at a two-site
+// update wider than park_side; the host then runs engine rounds (each does
+// every parked update and resumes the shot kernel) until a launch parks
+// nothing, reading the park count after each round (one stream
+// synchronisation per round).  Otherwise nothing waits here.
+static int enqueue_shots(msc_ctx* ctx, const msc_circuit* c, const RunCfg& cfg, int64_t n,
+                         int64_t n_csr, const int64_t* off, const int32_t* chan,
                          const uint8_t* pauli, const int64_t* shot_idx, msc_shot_result* out,
                          int calibrate, double* cal_p, uint8_t* cal_e, int ck_mode,
                          const PrefixCk* pk, const int64_t* n_dev, double* surv = nullptr) {
-    Layout L = make_layout(c->n, chi_max);
+    const int precision = cfg.precision, chi_max = cfg.chi_max;
+    const bool engine = cfg.park_side > 0;
+    Layout L = make_layout(c->n, chi_max, engine ? cfg.park_side : 2 * chi_max);
     // the shot kernel keeps the site offsets within a slot as 32-bit values
     if (L.slot_elems >= (int64_t(1) << 31)) return set_error(MSC_E_INVALID, "slot above 2^31 elements");
-    const bool small = lds_width == 32;
+    const bool small = cfg.lds_width == 32;
+    int n_slots = cfg.n_slots;
     if (n_slots <= 0) n_slots = ctx->n_cu * mps_blocks_per_cu(precision, small);
     n_slots = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(n_slots, n)));
+    if (engine) n_slots = std::min(n_slots, kLxMaxParked);
     const size_t tsize = precision == MSC_FP64 ? sizeof(double) : sizeof(float);
     void *arena, *scratch, *dcap, *doff, *dhalf, *dperm;
     int rc;
@@ -343,9 +436,9 @@ static int enqueue_shots(msc_ctx* ctx, const msc_circuit* c, int precision, int 
     a.scratch = static_cast<double*>(scratch);
     a.scratch_stride = L.scratch;
     a.chi_max = chi_max;
-    a.tau = tau;
-    a.tau_rej = tau_rej;
-    a.tau_fail = tau_fail;
+    a.tau = cfg.tau;
+    a.tau_rej = cfg.tau_rej;
+    a.tau_fail = cfg.tau_fail;
     const double r = 1.0 / std::sqrt(2.0);
     a.t0r = r;
     a.t0i = 0.0;
@@ -376,29 +469,139 @@ static int enqueue_shots(msc_ctx* ctx, const msc_circuit* c, int precision, int 
         a.seg_meas = static_cast<const int32_t*>(c->d_segm);
         a.n_seg = static_cast<int32_t>(c->segs.size());
     }
+    ctx->lx_stats = msc_engine_stats{};
+    void *dstate = nullptr, *dcount = nullptr, *dlist = nullptr, *dflops = nullptr;
+    if (engine) {
+        if ((rc = ctx_buf(ctx, "lx_state", static_cast<size_t>(n_slots) * sizeof(ShotState), &dstate))) return rc;
+        if ((rc = ctx_buf(ctx, "lx_count", sizeof(int32_t), &dcount))) return rc;
+        if ((rc = ctx_buf(ctx, "lx_list", static_cast<size_t>(n_slots) * sizeof(int32_t), &dlist))) return rc;
+        if ((rc = ctx_buf(ctx, "lx_flops", 2 * sizeof(double), &dflops))) return rc;
+        a.park_side = cfg.park_side;
+        a.state = static_cast<ShotState*>(dstate);
+        a.park_count = static_cast<int32_t*>(dcount);
+        a.park_list = static_cast<int32_t*>(dlist);
+        MSC_HIP(launch_lx_reset(a.state, n_slots, a.park_count, static_cast<double*>(dflops),
+                                ctx->stream));
+    }
     MSC_HIP(launch_order(n, n_dev, off, shot_idx, n_csr, chan,
                          a.ck_mode == 2 ? c->n_channels : 0, static_cast<int64_t*>(dperm),
                          ctx->stream));
+    if (engine) MSC_HIP(hipEventRecord(ctx->lxev[4], ctx->stream));
     MSC_HIP(launch_mps(precision, small, a, n_slots, ctx->stream));
+    if (engine) MSC_HIP(hipEventRecord(ctx->lxev[5], ctx->stream));
+    if (!engine) return MSC_OK;
+    msc_engine_stats& es = ctx->lx_stats;
+    bool first = true;
+
+    // ---- engine rounds until a shot-kernel launch parks nothing
+    LxArgs lx{};
+    LxFactor fac{};
+    bool have_bufs = false;
+    for (;;) {
+        int32_t parked = 0;
+        MSC_HIP(hipMemcpyAsync(&parked, a.park_count, sizeof(parked), hipMemcpyDeviceToHost,
+                               ctx->stream));
+        MSC_HIP(hipStreamSynchronize(ctx->stream));
+        float t = 0.f;
+        if (first) {
+            MSC_HIP(hipEventElapsedTime(&t, ctx->lxev[4], ctx->lxev[5]));
+            es.shot_ms += t;
+            first = false;
+        } else if (!cfg.graphs) {
+            double* acc[4] = {&es.contract_ms, &es.gram_ms, &es.factor_ms, &es.shot_ms};
+            for (int q = 0; q < 4; ++q) {
+                MSC_HIP(hipEventElapsedTime(&t, ctx->lxev[q], ctx->lxev[q + 1]));
+                *acc[q] += t;
+            }
+        }
+        if (parked == 0) break;
+        es.updates += parked;
+        ++es.rounds;
+        if (!have_bufs) {
+            // theta and Gram buffers per slot, sized for sides up to 2 chi_max
+            const int64_t S = 2ll * chi_max;
+            void *dplan, *dtheta, *dgram;
+            if ((rc = ctx_buf(ctx, "lx_plan", sizeof(LxPlan), &dplan))) return rc;
+            if ((rc = ctx_buf(ctx, "lx_theta", static_cast<size_t>(n_slots) * 2 * S * S * tsize, &dtheta))) return rc;
+            if ((rc = ctx_buf(ctx, "lx_gram", static_cast<size_t>(n_slots) * lx_gram_doubles(S) * sizeof(double), &dgram))) return rc;
+            lx.state = a.state;
+            lx.park_count = a.park_count;
+            lx.park_list = a.park_list;
+            lx.plan = static_cast<LxPlan*>(dplan);
+            lx.arena = arena;
+            lx.slot_stride = L.slot_elems;
+            lx.site_off = a.site_off;
+            lx.site_half = a.site_half;
+            lx.g4 = a.g4;
+            lx.theta = dtheta;
+            lx.theta_stride = 2 * S * S;
+            lx.gram = static_cast<double*>(dgram);
+            lx.gram_stride = lx_gram_doubles(S);
+            lx.n_slots = n_slots;
+            lx.flops = static_cast<double*>(dflops);
+            fac.cap = a.cap;
+            fac.chi_max = chi_max;
+            fac.tau = cfg.tau;
+            have_bufs = true;
+        }
+        if (cfg.graphs) {
+            // the round's launches depend only on these argument bytes
+            std::string key(reinterpret_cast<const char*>(&a), sizeof(a));
+            key.append(reinterpret_cast<const char*>(&lx), sizeof(lx));
+            key.append(reinterpret_cast<const char*>(&fac), sizeof(fac));
+            key.append(reinterpret_cast<const char*>(cfg.tiles), sizeof(cfg.tiles));
+            key.append(reinterpret_cast<const char*>(&precision), sizeof(precision));
+            key.append(reinterpret_cast<const char*>(&n_slots), sizeof(n_slots));
+            key.append(small ? "s" : "w");
+            if (!ctx->lx_exec || ctx->lx_key != key) {
+                if (ctx->lx_exec) (void)hipGraphExecDestroy(ctx->lx_exec);
+                ctx->lx_exec = nullptr;
+                hipGraph_t g = nullptr;
+                MSC_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+                const int rc2 = enqueue_lx_round(ctx, cfg, small, a, lx, fac, n_slots, false);
+                hipError_t e2 = hipStreamEndCapture(ctx->stream, &g);
+                if (rc2) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return rc2;
+                }
+                if (e2 != hipSuccess) return set_error(MSC_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e2));
+                e2 = hipGraphInstantiate(&ctx->lx_exec, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e2 != hipSuccess) {
+                    ctx->lx_exec = nullptr;
+                    return set_error(MSC_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e2));
+                }
+                ctx->lx_key = key;
+            }
+            MSC_HIP(hipGraphLaunch(ctx->lx_exec, ctx->stream));
+        } else {
+            if ((rc = enqueue_lx_round(ctx, cfg, small, a, lx, fac, n_slots, true))) return rc;
+        }
+    }
+    if (have_bufs) {
+        double fl[2] = {0.0, 0.0};
+        MSC_HIP(hipMemcpy(fl, lx.flops, sizeof(fl), hipMemcpyDeviceToHost));
+        es.contract_flops = fl[0];
+        es.gram_flops = fl[1];
+    }
     return MSC_OK;
 }
 
-static int run_shots(msc_ctx* ctx, const msc_circuit* c, int precision, int chi_max, double tau,
-                     double tau_rej, double tau_fail, int n_slots, int lds_width, int64_t n,
+static int run_shots(msc_ctx* ctx, const msc_circuit* c, const RunCfg& cfg, int64_t n,
                      int64_t n_csr, const int64_t* off, const int32_t* chan, const uint8_t* pauli,
                      const int64_t* shot_idx, msc_shot_result* out, int calibrate,
                      double* cal_p, uint8_t* cal_e, const char* timer, int ck_mode = 0,
                      const PrefixCk* pk = nullptr) {
     MSC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
-    int rc = enqueue_shots(ctx, c, precision, chi_max, tau, tau_rej, tau_fail, n_slots,
-                           lds_width, n, n_csr, off, chan, pauli, shot_idx, out, calibrate, cal_p,
-                           cal_e, ck_mode, pk, nullptr);
+    int rc = enqueue_shots(ctx, c, cfg, n, n_csr, off, chan, pauli, shot_idx, out, calibrate,
+                           cal_p, cal_e, ck_mode, pk, nullptr);
     if (rc) return rc;
     MSC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
     MSC_HIP(hipStreamSynchronize(ctx->stream));
     float ms = 0.f;
     MSC_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
     if (timer) ctx->last_ms[timer] = ms;
+    ctx->lx_stats.total_ms = ms;
     return MSC_OK;
 }
 
@@ -417,18 +620,30 @@ extern "C" int msc_circuit_calibrate(msc_ctx* ctx, msc_circuit* c) {
     if ((rc = ctx_buf(ctx, "cal_e", nm, &de))) return rc;
     int64_t zero[2] = {0, 0};
     MSC_HIP(hipMemcpy(doff, zero, sizeof(zero), hipMemcpyHostToDevice));
-    int chi_max = kMaxChiKernel;
-    rc = run_shots(ctx, c, MSC_FP64, chi_max, 1e-12, 0.0, 1e-4, 1, 64, 1, 1,
-                   static_cast<int64_t*>(doff), static_cast<int32_t*>(dchan),
-                   static_cast<uint8_t*>(dpa), nullptr, static_cast<msc_shot_result*>(dout), 1,
-                   static_cast<double*>(dp), static_cast<uint8_t*>(de), "calibrate");
-    if (rc) return rc;
+    // the noiseless FP64 run, likelier outcome recorded at every
+    // measurement; bond cap 256 first (small slot), the full cap if it binds
+    msc_shot_result res;
+    for (int chi_max : {256, kMaxChiKernel}) {
+        RunCfg cfg;
+        cfg.precision = MSC_FP64;
+        cfg.chi_max = chi_max;
+        cfg.tau = 1e-12;
+        cfg.tau_rej = 0.0;
+        cfg.n_slots = 1;
+        cfg.lds_width = 64;
+        default_tiles(cfg.precision, cfg.tiles);
+        rc = run_shots(ctx, c, cfg, 1, 1, static_cast<int64_t*>(doff),
+                       static_cast<int32_t*>(dchan), static_cast<uint8_t*>(dpa), nullptr,
+                       static_cast<msc_shot_result*>(dout), 1, static_cast<double*>(dp),
+                       static_cast<uint8_t*>(de), "calibrate");
+        if (rc) return rc;
+        MSC_HIP(hipMemcpy(&res, dout, sizeof(res), hipMemcpyDeviceToHost));
+        if (!(res.status & MSC_SHOT_CHI_CAP)) break;
+    }
     std::vector<double> p(nm);
     std::vector<uint8_t> e(nm);
-    msc_shot_result res;
     MSC_HIP(hipMemcpy(p.data(), dp, nm * sizeof(double), hipMemcpyDeviceToHost));
     MSC_HIP(hipMemcpy(e.data(), de, nm, hipMemcpyDeviceToHost));
-    MSC_HIP(hipMemcpy(&res, dout, sizeof(res), hipMemcpyDeviceToHost));
     c->noiseless = res;
     for (int m = 0; m < c->n_meas; ++m) {
         if (!(std::fabs(p[m] - 1.0) <= 1e-10))
@@ -457,12 +672,13 @@ extern "C" int msc_circuit_calibrate(msc_ctx* ctx, msc_circuit* c) {
 // kernel with the same arithmetic, so its result does not change.
 static constexpr int64_t kPrefixBytes = int64_t(2) << 30;
 
-static int ensure_prefix(msc_ctx* ctx, msc_circuit* c, int precision, int chi_max, double tau,
-                         double tau_rej, double tau_fail, int lds_width) {
+static int ensure_prefix(msc_ctx* ctx, msc_circuit* c, const RunCfg& cfg) {
     PrefixCk& pk = c->prefix;
+    const int precision = cfg.precision, chi_max = cfg.chi_max, lds_width = cfg.lds_width;
+    const double tau = cfg.tau, tau_rej = cfg.tau_rej;
     if (pk.valid && pk.dev == ctx->device && pk.precision == precision &&
         pk.chi_max == chi_max && pk.lds_width == lds_width && pk.tau == tau &&
-        pk.tau_rej == tau_rej)
+        pk.tau_rej == tau_rej && pk.park_side == cfg.park_side)
         return MSC_OK;
     free_prefix(pk);
     pk.dev = ctx->device;
@@ -505,8 +721,9 @@ static int ensure_prefix(msc_ctx* ctx, msc_circuit* c, int precision, int chi_ma
     if ((rc = ctx_buf(ctx, "cal_out", sizeof(msc_shot_result), &dout))) return rc;
     int64_t zz[2] = {0, 0};
     MSC_HIP(hipMemcpy(doff, zz, sizeof(zz), hipMemcpyHostToDevice));
-    rc = run_shots(ctx, c, precision, chi_max, tau, tau_rej, tau_fail, 1, lds_width, 1, 1,
-                   static_cast<int64_t*>(doff), static_cast<int32_t*>(dchan),
+    RunCfg one = cfg;
+    one.n_slots = 1;
+    rc = run_shots(ctx, c, one, 1, 1, static_cast<int64_t*>(doff), static_cast<int32_t*>(dchan),
                    static_cast<uint8_t*>(dpa), nullptr, static_cast<msc_shot_result*>(dout), 0,
                    nullptr, nullptr, "prefix", 1, &pk);
     if (rc) {
@@ -523,11 +740,115 @@ static int ensure_prefix(msc_ctx* ctx, msc_circuit* c, int precision, int chi_ma
     pk.precision = precision;
     pk.chi_max = chi_max;
     pk.lds_width = lds_width;
+    pk.park_side = cfg.park_side;
     pk.tau = tau;
     pk.tau_rej = tau_rej;
     pk.build_ms = static_cast<float>(ctx->last_ms["prefix"]);
     pk.valid = true;
     return MSC_OK;
+}
+
+// Tile shapes for `precision` from an msc_autotune cache file: a JSON object
+// whose "entries" array holds objects with integer fields "precision",
+// "bucket", "rows", "b" and "gram" (other fields are ignored).  Entries of
+// other precisions are skipped; a bucket without an entry keeps its shapes.
+static int read_tune_cache(const char* path, int precision, LxTiles* tiles) {
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return set_error(MSC_E_INVALID, std::string("cannot open autotune cache ") + path);
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+    std::fclose(f);
+    const size_t at = text.find("\"entries\"");
+    if (at == std::string::npos) return set_error(MSC_E_PARSE, "autotune cache without entries");
+    size_t pos = text.find('[', at);
+    const size_t end = text.find(']', pos == std::string::npos ? at : pos);
+    if (pos == std::string::npos || end == std::string::npos)
+        return set_error(MSC_E_PARSE, "autotune cache: entries is not an array");
+    while (true) {
+        const size_t o = text.find('{', pos);
+        if (o == std::string::npos || o > end) break;
+        const size_t cl = text.find('}', o);
+        if (cl == std::string::npos || cl > end) return set_error(MSC_E_PARSE, "autotune cache: open entry");
+        const std::string obj = text.substr(o, cl - o);
+        auto field = [&](const char* name, long* out) {
+            const std::string key = std::string("\"") + name + "\"";
+            const size_t kp = obj.find(key);
+            if (kp == std::string::npos) return false;
+            const size_t colon = obj.find(':', kp + key.size());
+            if (colon == std::string::npos) return false;
+            char* e = nullptr;
+            *out = std::strtol(obj.c_str() + colon + 1, &e, 10);
+            return e != obj.c_str() + colon + 1;
+        };
+        long pr, bk, rows, b, gram;
+        if (!(field("precision", &pr) && field("bucket", &bk) && field("rows", &rows) &&
+              field("b", &b) && field("gram", &gram)))
+            return set_error(MSC_E_PARSE, "autotune cache: entry without precision, bucket, "
+                                          "rows, b or gram");
+        if (pr == precision && bk >= 0 && bk < kLxBuckets) {
+            LxTiles v[16];
+            const int nvar = lx_tile_variants(precision, v, 16);
+            bool known = false;
+            for (int i = 0; i < nvar; ++i)
+                known |= v[i].cm_rows == rows && v[i].cm_b == b && v[i].gram == gram;
+            if (!known) return set_error(MSC_E_INVALID, "autotune cache names a tile shape this "
+                                                        "build does not have");
+            tiles[bk] = LxTiles{static_cast<int32_t>(rows), static_cast<int32_t>(b),
+                                static_cast<int32_t>(gram)};
+        }
+        pos = cl + 1;
+    }
+    return MSC_OK;
+}
+
+// The run options of msc_sim_opts (validated), with the engine's tile shapes
+// from the autotune cache when one is named.
+static int sim_cfg(const msc_sim_opts* o, RunCfg* cfg) {
+    if (o->precision != MSC_FP64 && o->precision != MSC_FP32)
+        return set_error(MSC_E_INVALID, "unknown precision");
+    if (o->chi_max < 1 || o->chi_max > kMaxChiKernel)
+        return set_error(MSC_E_INVALID, "chi_max must be in [1, 1024]");
+    if (o->lds_width != 0 && o->lds_width != 32 && o->lds_width != 64)
+        return set_error(MSC_E_INVALID, "lds_width must be 0, 32 or 64");
+    if (o->prefix != 0 && o->prefix != 1) return set_error(MSC_E_INVALID, "prefix must be 0 or 1");
+    if (o->use_graphs != 0 && o->use_graphs != 1)
+        return set_error(MSC_E_INVALID, "use_graphs must be 0 or 1");
+    if (o->large_side < -1 || o->large_side == 1)
+        return set_error(MSC_E_INVALID, "large_side must be -1, 0 or at least 2");
+    if (o->reserved != 0) return set_error(MSC_E_INVALID, "reserved must be 0");
+    cfg->precision = o->precision;
+    cfg->chi_max = o->chi_max;
+    cfg->tau = o->tau_trunc > 0 ? o->tau_trunc : (o->precision == MSC_FP64 ? 1e-12 : 1e-5);
+    cfg->tau_rej = o->tau_rej > 0 ? o->tau_rej : 1e-6;
+    cfg->tau_fail = o->tau_fail > 0 ? o->tau_fail : 1e-4;
+    cfg->n_slots = o->n_slots;
+    cfg->lds_width = o->lds_width == 64 ? 64 : 32;
+    cfg->park_side = o->large_side == -1 ? 0 : o->large_side == 0 ? 64 : o->large_side;
+    cfg->graphs = o->use_graphs == 1;
+    default_tiles(cfg->precision, cfg->tiles);
+    if (o->autotune_cache) {
+        int rc = read_tune_cache(o->autotune_cache, cfg->precision, cfg->tiles);
+        if (rc) return rc;
+    }
+    return MSC_OK;
+}
+
+// Checks a caller's fault CSR on the device (channel range and order, Pauli
+// codes, offsets) before any kernel relies on it; MSC_E_INVALID if not.
+static int validate_csr(msc_ctx* ctx, const msc_circuit* c, int64_t n, const int64_t* off,
+                        const int32_t* chan, const uint8_t* pauli) {
+    void* dflag;
+    int rc;
+    if ((rc = ctx_buf(ctx, "csr_flag", sizeof(int), &dflag))) return rc;
+    MSC_HIP(launch_validate_csr(c->n_channels, n, off, chan, pauli,
+                                static_cast<const uint8_t*>(c->d_kind), static_cast<int*>(dflag),
+                                ctx->stream));
+    int bad = 0;
+    MSC_HIP(hipMemcpyAsync(&bad, dflag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    MSC_HIP(hipStreamSynchronize(ctx->stream));
+    return bad ? csr_error(bad) : MSC_OK;
 }
 
 extern "C" int msc_simulate(msc_ctx* ctx, const msc_circuit* c, const msc_sim_opts* opts,
@@ -539,32 +860,45 @@ extern "C" int msc_simulate(msc_ctx* ctx, const msc_circuit* c, const msc_sim_op
     const int64_t n = shot_idx ? n_sel : n_shots;
     if (n > 0 && !out) return set_error(MSC_E_INVALID, "null out");
     if (!c->calibrated) return set_error(MSC_E_STATE, "circuit not calibrated");
-    if (opts->precision != MSC_FP64 && opts->precision != MSC_FP32)
-        return set_error(MSC_E_INVALID, "unknown precision");
-    if (opts->chi_max < 1 || opts->chi_max > kMaxChiKernel)
-        return set_error(MSC_E_INVALID, "chi_max must be in [1, 256]");
+    RunCfg cfg;
+    int rc = sim_cfg(opts, &cfg);
+    if (rc) return rc;
     if (n == 0) return MSC_OK;
     MSC_HIP(hipSetDevice(ctx->device));
     // the library only uploads into circuits it owns; const is logical here
-    int rc = upload(ctx, const_cast<msc_circuit*>(c));
-    if (rc) return rc;
-    double tau = opts->tau_trunc > 0 ? opts->tau_trunc : (opts->precision == MSC_FP64 ? 1e-12 : 1e-5);
-    double tau_rej = opts->tau_rej > 0 ? opts->tau_rej : 1e-6;
-    double tau_fail = opts->tau_fail > 0 ? opts->tau_fail : 1e-4;
-    if (opts->lds_width != 0 && opts->lds_width != 32 && opts->lds_width != 64)
-        return set_error(MSC_E_INVALID, "lds_width must be 0, 32 or 64");
-    if (opts->prefix != 0 && opts->prefix != 1) return set_error(MSC_E_INVALID, "prefix must be 0 or 1");
-    if (opts->reserved != 0) return set_error(MSC_E_INVALID, "reserved must be 0");
-    const int lds_width = opts->lds_width == 64 ? 64 : 32;
-    if (opts->prefix) {
-        rc = ensure_prefix(ctx, const_cast<msc_circuit*>(c), opts->precision, opts->chi_max, tau,
-                           tau_rej, tau_fail, lds_width);
-        if (rc) return rc;
-    }
-    return run_shots(ctx, c, opts->precision, opts->chi_max, tau, tau_rej, tau_fail,
-                     opts->n_slots, lds_width, n, n_shots, shot_off, chan, pauli, shot_idx, out, 0,
-                     nullptr, nullptr, "simulate", opts->prefix ? 2 : 0,
+    if ((rc = upload(ctx, const_cast<msc_circuit*>(c)))) return rc;
+    if ((rc = validate_csr(ctx, c, n_shots, shot_off, chan, pauli))) return rc;
+    if (opts->prefix && (rc = ensure_prefix(ctx, const_cast<msc_circuit*>(c), cfg))) return rc;
+    return run_shots(ctx, c, cfg, n, n_shots, shot_off, chan, pauli, shot_idx, out, 0, nullptr,
+                     nullptr, "simulate", opts->prefix ? 2 : 0,
                      opts->prefix ? &c->prefix : nullptr);
+}
+
+// The screen of a device CSR on the context's stream into caller buffers and
+// the tmp words (prescreen_tmp_words(n) of them: block counts, the survivor
+// total, the CSR flag); waits for the stream, reads the total and the flag.
+static int screen_into(msc_ctx* ctx, const msc_circuit* c, int64_t n_shots,
+                       const int64_t* shot_off, const int32_t* chan, const uint8_t* pauli,
+                       uint64_t* survive_bits, int64_t* survivor_idx, int64_t* tmp, int64_t nt,
+                       int64_t* n_survivors) {
+    int* flag = reinterpret_cast<int*>(tmp + (nt - 1));
+    MSC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
+    MSC_HIP(launch_prescreen(c->words, c->n_channels, n_shots, shot_off, chan, pauli,
+                             static_cast<const uint64_t*>(c->d_sig),
+                             static_cast<const uint8_t*>(c->d_kind), survive_bits, survivor_idx,
+                             tmp, nt, flag, ctx->stream));
+    MSC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
+    int64_t tail[2] = {0, 0};   // survivor total, flag word
+    MSC_HIP(hipMemcpyAsync(tail, tmp + (nt - 2), sizeof(tail), hipMemcpyDeviceToHost,
+                           ctx->stream));
+    MSC_HIP(hipStreamSynchronize(ctx->stream));
+    float ms = 0.f;
+    MSC_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    ctx->last_ms["prescreen"] = ms;
+    const int bad = static_cast<int>(tail[1] & 0xffffffff);
+    if (bad) return csr_error(bad);
+    *n_survivors = tail[0];
+    return MSC_OK;
 }
 
 extern "C" int msc_prescreen(msc_ctx* ctx, const msc_circuit* c, int64_t n_shots,
@@ -582,21 +916,8 @@ extern "C" int msc_prescreen(msc_ctx* ctx, const msc_circuit* c, int64_t n_shots
     const int64_t nt = prescreen_tmp_words(n_shots);
     void* tmp;
     if ((rc = ctx_buf(ctx, "screen_tmp", nt * sizeof(int64_t), &tmp))) return rc;
-    MSC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
-    MSC_HIP(launch_prescreen(c->words, c->n_channels, n_shots, shot_off, chan, pauli,
-                             static_cast<const uint64_t*>(c->d_sig), survive_bits, survivor_idx,
-                             static_cast<int64_t*>(tmp), nt, ctx->stream));
-    MSC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
-    int64_t cnt = 0;
-    const int64_t nb = (n_shots + 255) / 256;
-    MSC_HIP(hipMemcpyAsync(&cnt, static_cast<int64_t*>(tmp) + nb, sizeof(int64_t),
-                           hipMemcpyDeviceToHost, ctx->stream));
-    MSC_HIP(hipStreamSynchronize(ctx->stream));
-    float ms = 0.f;
-    MSC_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-    ctx->last_ms["prescreen"] = ms;
-    *n_survivors = cnt;
-    return MSC_OK;
+    return screen_into(ctx, c, n_shots, shot_off, chan, pauli, survive_bits, survivor_idx,
+                       static_cast<int64_t*>(tmp), nt, n_survivors);
 }
 
 // The Bin(M, p) cumulative table on the device, uploaded when (M, p) changes.
@@ -668,25 +989,13 @@ extern "C" int msc_run_batch(msc_ctx* ctx, const msc_circuit* c, const msc_sim_o
     if (n_bins < 1 || n_bins > kMaxBins) return set_error(MSC_E_INVALID, "n_bins must be in [1, 1024]");
     if (!(p >= 0.0 && p <= 1.0)) return set_error(MSC_E_INVALID, "p outside [0,1]");
     if (!c->calibrated) return set_error(MSC_E_STATE, "circuit not calibrated");
-    if (opts->precision != MSC_FP64 && opts->precision != MSC_FP32)
-        return set_error(MSC_E_INVALID, "unknown precision");
-    if (opts->chi_max < 1 || opts->chi_max > kMaxChiKernel)
-        return set_error(MSC_E_INVALID, "chi_max must be in [1, 256]");
-    if (opts->lds_width != 0 && opts->lds_width != 32 && opts->lds_width != 64)
-        return set_error(MSC_E_INVALID, "lds_width must be 0, 32 or 64");
-    if (opts->prefix != 0 && opts->prefix != 1) return set_error(MSC_E_INVALID, "prefix must be 0 or 1");
-    if (opts->reserved != 0) return set_error(MSC_E_INVALID, "reserved must be 0");
+    RunCfg cfg;
+    int rc = sim_cfg(opts, &cfg);
+    if (rc) return rc;
     if (c->words > 8) return set_error(MSC_E_INVALID, "more than 512 decided measurements");
     MSC_HIP(hipSetDevice(ctx->device));
-    int rc = upload(ctx, const_cast<msc_circuit*>(c));
-    if (rc) return rc;
-    const double tau = opts->tau_trunc > 0 ? opts->tau_trunc : (opts->precision == MSC_FP64 ? 1e-12 : 1e-5);
-    const double tau_rej = opts->tau_rej > 0 ? opts->tau_rej : 1e-6;
-    const double tau_fail = opts->tau_fail > 0 ? opts->tau_fail : 1e-4;
-    const int lds_width = opts->lds_width == 64 ? 64 : 32;
-    if (opts->prefix && (rc = ensure_prefix(ctx, const_cast<msc_circuit*>(c), opts->precision,
-                                            opts->chi_max, tau, tau_rej, tau_fail, lds_width)))
-        return rc;
+    if ((rc = upload(ctx, const_cast<msc_circuit*>(c)))) return rc;
+    if (opts->prefix && (rc = ensure_prefix(ctx, const_cast<msc_circuit*>(c), cfg))) return rc;
     // host-mapped block for the reduction: bins, then the totals
     const bool space_time = surv_bins != nullptr;
     const int n_seg = space_time ? static_cast<int>(c->segs.size()) : 0;
@@ -717,14 +1026,17 @@ extern "C" int msc_run_batch(msc_ctx* ctx, const msc_circuit* c, const msc_sim_o
     if ((rc = ctx_buf(ctx, "b_idx", std::max<int64_t>(1, n_shots) * sizeof(int64_t), &didx))) return rc;
     if ((rc = ctx_buf(ctx, "b_res", std::max<int64_t>(1, n_shots) * sizeof(msc_shot_result), &dres))) return rc;
     if ((rc = ctx_buf(ctx, "b_tmp_s", nts * sizeof(int64_t), &dts))) return rc;
-    if ((rc = ctx_buf(ctx, "b_tmp_p", std::max<int64_t>(2, ntp) * sizeof(int64_t), &dtp))) return rc;
+    if ((rc = ctx_buf(ctx, "b_tmp_p", std::max<int64_t>(3, ntp) * sizeof(int64_t), &dtp))) return rc;
     void* dsurv = nullptr;
     if (space_time &&
         (rc = ctx_buf(ctx, "b_surv", std::max<int64_t>(1, n_shots * n_seg) * sizeof(double), &dsurv)))
         return rc;
     int64_t* offp = static_cast<int64_t*>(doff);
     int64_t* idxp = static_cast<int64_t*>(didx);
-    int64_t* nsurv = static_cast<int64_t*>(dtp) + (ntp - 1);   // the screen's total
+    int64_t* nsurv = static_cast<int64_t*>(dtp) + (ntp - 2);   // the screen's total
+    // the CSR check word (this batch's faults come from the library's own
+    // sampler, so it is never set)
+    int* csr_flag = reinterpret_cast<int*>(static_cast<int64_t*>(dtp) + (ntp - 1));
     int64_t* nnz = static_cast<int64_t*>(dts) + (nts - 1);     // the sampler's total
     double* hbins = static_cast<double*>(ctx->hmap_dev);
     BatchTotals* htot = reinterpret_cast<BatchTotals*>(hbins + kBinRows * static_cast<size_t>(n_bins));
@@ -749,15 +1061,15 @@ extern "C" int msc_run_batch(msc_ctx* ctx, const msc_circuit* c, const msc_sim_o
         MSC_HIP(launch_prescreen(c->words, c->n_channels, n_shots, offp,
                                  static_cast<int32_t*>(dchan), static_cast<uint8_t*>(dpa),
                                  static_cast<const uint64_t*>(c->d_sig),
+                                 static_cast<const uint8_t*>(c->d_kind),
                                  static_cast<uint64_t*>(dbits), idxp, static_cast<int64_t*>(dtp),
-                                 ntp, ctx->stream));
+                                 ntp, csr_flag, ctx->stream));
     }
     MSC_HIP(hipEventRecord(ctx->ev2, ctx->stream));
-    rc = enqueue_shots(ctx, c, opts->precision, opts->chi_max, tau, tau_rej, tau_fail,
-                       opts->n_slots, lds_width, n_shots, n_shots, offp,
-                       static_cast<int32_t*>(dchan), static_cast<uint8_t*>(dpa), idxp, res, 0,
-                       nullptr, nullptr, opts->prefix ? 2 : 0, opts->prefix ? &c->prefix : nullptr,
-                       nsurv, static_cast<double*>(dsurv));
+    rc = enqueue_shots(ctx, c, cfg, n_shots, n_shots, offp, static_cast<int32_t*>(dchan),
+                       static_cast<uint8_t*>(dpa), idxp, res, 0, nullptr, nullptr,
+                       opts->prefix ? 2 : 0, opts->prefix ? &c->prefix : nullptr, nsurv,
+                       static_cast<double*>(dsurv));
     if (rc) return rc;
     MSC_HIP(hipEventRecord(ctx->ev3, ctx->stream));
     MSC_HIP(launch_batch_reduce(n_shots, seed, first_shot, offp, idxp, nsurv, res, n_bins, nnz,
@@ -777,6 +1089,7 @@ extern "C" int msc_run_batch(msc_ctx* ctx, const msc_circuit* c, const msc_sim_o
     ctx->last_ms["sample"] = t01;
     ctx->last_ms["prescreen"] = t12;
     ctx->last_ms["simulate"] = t23;
+    ctx->lx_stats.total_ms = t23;
     if (stats) {
         stats->n_shots = n_shots;
         stats->nnz = ht->nnz;
@@ -923,6 +1236,7 @@ extern "C" int msc_simulate_camps(msc_ctx* ctx, const msc_circuit* c, const msc_
     msc_circuit* cc = const_cast<msc_circuit*>(c);
     int rc = camps_upload(ctx, cc);
     if (rc) return rc;
+    if ((rc = validate_csr(ctx, cc, n_shots, shot_off, chan, pauli))) return rc;
     const double tau = opts->tau_trunc > 0 ? opts->tau_trunc : 1e-12;
     const double tau_rej = opts->tau_rej > 0 ? opts->tau_rej : 1e-6;
     const double tau_fail = opts->tau_fail > 0 ? opts->tau_fail : 1e-4;

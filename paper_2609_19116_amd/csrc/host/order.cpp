@@ -53,6 +53,20 @@ struct Mix {
 
 using namespace msc;
 
+// flops of the calibrated circuit's noiseless run plus the fixed op costs
+static double calibrated_cost(const msc_circuit* c) {
+    return c->noiseless.flops + MSC_ORDER_COST_PSWAP * static_cast<double>(c->n_product_swaps) +
+           MSC_ORDER_COST_MOVE * static_cast<double>(c->n_moves) +
+           MSC_ORDER_COST_TWOSITE * static_cast<double>(c->n_twosite);
+}
+
+extern "C" int msc_order_cost(const msc_circuit* c, double* out) {
+    if (!c || !out) return set_error(MSC_E_INVALID, "null argument");
+    if (!c->calibrated) return set_error(MSC_E_STATE, "circuit not calibrated");
+    *out = calibrated_cost(c);
+    return MSC_OK;
+}
+
 // cost of one order: flops of the noiseless run plus the fixed op costs,
 // +inf if it cannot run
 static int order_cost(msc_ctx* ctx, const char* text, size_t len, const std::vector<int32_t>& order,
@@ -62,9 +76,7 @@ static int order_cost(msc_ctx* ctx, const char* text, size_t len, const std::vec
     if (rc) return rc;
     rc = msc_circuit_calibrate(ctx, c);
     if (rc == MSC_OK)
-        *cost = c->noiseless.flops + MSC_ORDER_COST_PSWAP * static_cast<double>(c->n_product_swaps) +
-                MSC_ORDER_COST_MOVE * static_cast<double>(c->n_moves) +
-                MSC_ORDER_COST_TWOSITE * static_cast<double>(c->n_twosite);
+        *cost = calibrated_cost(c);
     else if (rc == MSC_E_NONDETERMINISTIC && (c->noiseless.status & MSC_SHOT_CHI_CAP)) {
         *cost = INFINITY;
         rc = MSC_OK;

@@ -187,26 +187,40 @@ double msc::log_bin(int64_t M, int64_t w, double p) {
 }
 
 extern "C" int msc_reweight(const double* bin_n, const double* bin_acc, const double* bin_fail,
-                            int32_t n_bins, int64_t M, const double* p_grid, int32_t n_p,
-                            msc_estimate* out) {
+                            const double* bin_acc2, const double* bin_fail2, int32_t n_bins,
+                            int64_t M, const double* p_grid, int32_t n_p, msc_estimate* out) {
     if (!bin_n || !bin_acc || !bin_fail || !p_grid || !out || n_bins < 1 || n_p < 0 || M < 0)
         return set_error(MSC_E_INVALID, "bad reweight arguments");
+    if ((bin_acc2 == nullptr) != (bin_fail2 == nullptr))
+        return set_error(MSC_E_INVALID, "give both sums of squares or neither");
     if (n_bins > M + 1) return set_error(MSC_E_INVALID, "more bins than M+1");
+    // variance of one shot's value in a bin: the unbiased sample variance
+    // from the sums, else the Bhatia-Davis bound of a [0, 1] variable
+    auto var = [](double n, double s, const double* s2, int32_t w) {
+        const double mu = s / n;
+        if (s2 && n >= 2.0) return std::max(0.0, (s2[w] - s * mu) / (n - 1.0));
+        return std::max(0.0, mu * (1.0 - mu));
+    };
     for (int32_t k = 0; k < n_p; ++k) {
         double p = p_grid[k];
         if (!(p >= 0.0 && p <= 1.0)) return set_error(MSC_E_INVALID, "p outside [0,1]");
-        double pacc = 0.0, num = 0.0, tail = 0.0;
+        double pacc = 0.0, num = 0.0, tail = 0.0, va = 0.0, ve = 0.0;
         for (int64_t w = M; w >= n_bins; --w) tail += std::exp(log_bin(M, w, p));
         for (int32_t w = 0; w < n_bins; ++w) {
             double b = std::exp(log_bin(M, w, p));
-            if (bin_n[w] <= 0.0) continue;
-            pacc += b * bin_acc[w] / bin_n[w];
-            num += b * bin_fail[w] / bin_n[w];
+            const double n = bin_n[w];
+            if (n <= 0.0) continue;
+            pacc += b * bin_acc[w] / n;
+            num += b * bin_fail[w] / n;
+            va += b * b * var(n, bin_acc[w], bin_acc2, w) / n;
+            ve += b * b * var(n, bin_fail[w], bin_fail2, w) / n;
         }
         out[k].p_acc = pacc;
         out[k].p_acc_le = num;
         out[k].p_le = pacc > 0.0 ? num / pacc : NAN;
         out[k].trunc_bound = tail;
+        out[k].sem_p_acc = std::sqrt(va);
+        out[k].sem_p_acc_le = std::sqrt(ve);
     }
     return MSC_OK;
 }

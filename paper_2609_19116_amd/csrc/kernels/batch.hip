@@ -2,7 +2,8 @@
 // Eq. (reweight)), written straight into host-mapped memory so that the
 // host reads them after one stream synchronisation, without a copy.
 //
-// Besides the sums of P_acc and P_acc * fail, each bin gets the counts that
+// Besides the sums of P_acc and P_acc * fail (and of their squares, for the
+// standard errors), each bin gets the counts that
 // the likelihood of the error analysis works with (Appendix "Error analysis
 // of the subset-sampling estimator", Eq. (loglik-split)): a shot counts as
 // accepted iff u < P_acc for one uniform u of its own, and as wrong iff it
@@ -111,6 +112,8 @@ __global__ __launch_bounds__(RT) void batch_reduce_kernel(int64_t n, uint64_t se
             if (tid == 0) {
                 bins[nb + b] = 0.0;
                 bins[2 * nb + b] = 0.0;
+                bins[5 * nb + b] = 0.0;
+                bins[6 * nb + b] = 0.0;
                 for (int g = 0; g < n_seg; ++g) sbins[b * n_seg + g] = 0.0;
             }
             continue;
@@ -123,17 +126,24 @@ __global__ __launch_bounds__(RT) void batch_reduce_kernel(int64_t n, uint64_t se
             r = block_sum_fixed(r, s_red);
             if (tid == 0) sbins[b * n_seg + g] = r;
         }
-        double a = 0.0, e = 0.0;
+        double a = 0.0, e = 0.0, a2 = 0.0, e2 = 0.0;
         for (int64_t s = tid; s < ns; s += RT) {
             if (weight(idx[s]) != b) continue;
-            a += res[s].p_acc;
-            e += res[s].p_acc * res[s].fail;
+            const double x = res[s].p_acc, y = x * res[s].fail;
+            a += x;
+            e += y;
+            a2 += x * x;
+            e2 += y * y;
         }
         a = block_sum_fixed(a, s_red);
         e = block_sum_fixed(e, s_red);
+        a2 = block_sum_fixed(a2, s_red);
+        e2 = block_sum_fixed(e2, s_red);
         if (tid == 0) {
             bins[nb + b] = a;
             bins[2 * nb + b] = e;
+            bins[5 * nb + b] = a2;
+            bins[6 * nb + b] = e2;
         }
     }
     __syncthreads();

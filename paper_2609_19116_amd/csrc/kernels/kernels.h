@@ -10,7 +10,7 @@
 namespace msc {
 
 constexpr int kMaxSites = 128;     // MPS sites per circuit
-constexpr int kMaxChiKernel = 256; // bond cap handled by the shot kernel
+constexpr int kMaxChiKernel = 1024; // bond cap handled by the shot kernels
 
 // Header of one noiseless-prefix checkpoint: the shot state right before a
 // given op of the noiseless run (the tensors themselves are stored densely,
@@ -19,6 +19,36 @@ struct CkHdr {
     double p_acc, disc;
     int32_t chi_peak, status;
     int32_t meas_done, pad;    // measurements before the checkpoint's op
+    int32_t chi[kMaxSites + 1];
+    int32_t laste[kMaxSites];
+};
+
+// Slot states of the shot kernel when large updates are handed to the
+// batched engine (ShotState.status)
+enum SlotStatus : int32_t {
+    kSlotRun = 0,      // start the slot's next shot (first launch)
+    kSlotParked = 1,   // waiting at a large two-site update
+    kSlotResume = 2,   // the update is done: continue after it
+    kSlotDone = 3      // no shots left for this slot
+};
+
+// Everything a shot carries between ops, saved when it parks at a large
+// two-site update (one record per slot, device memory) and restored when it
+// resumes after the batched engine has done that update.
+struct ShotState {
+    int64_t j;                 // position in the slot's sequence of shots
+    int64_t fcur, fend;        // fault cursor in the CSR
+    int64_t ck_pos;            // record mode: checkpoint elements written
+    int64_t n2q, sweeps;       // per-shot counters
+    double p_acc, infid, disc, flops;
+    int32_t status;            // SlotStatus
+    int32_t oi;                // op to resume at
+    int32_t next_ch, fcode;
+    int32_t meas_done, next_seg, rej_at, alive;
+    int32_t next_ck, ck_full;
+    int32_t shot_status, chi_peak;
+    // the parked update: sites k, k+1, centre direction, 4x4 gate id
+    int32_t k, dir, gate_id, pad;
     int32_t chi[kMaxSites + 1];
     int32_t laste[kMaxSites];
 };
@@ -73,6 +103,15 @@ struct MpsArgs {
     double* surv;
     const int32_t* seg_meas;
     int32_t n_seg;
+    // batched large updates: a two-site update whose theta has a side above
+    // park_side (0: never) parks the shot (state[slot], slot appended to
+    // park_list, park_count incremented) and its workgroup exits; a later
+    // launch with the same arguments resumes every slot marked kSlotResume.
+    // state == nullptr: no parking, every slot starts at its first shot.
+    int32_t park_side;
+    ShotState* state;
+    int32_t* park_count;
+    int32_t* park_list;
 };
 
 // precision: MSC_FP64 or MSC_FP32; small: use the 32-wide LDS variant
@@ -86,11 +125,22 @@ hipError_t launch_order(int64_t n, const int64_t* n_dev, const int64_t* shot_off
 // resident workgroups per CU of the chosen variant (sizes the persistent grid)
 int mps_blocks_per_cu(int precision, bool small);
 
+// Bits of the CSR check flag written by the screen and validation kernels
+enum CsrFlag : int {
+    CSR_BAD_CHANNEL = 1,     // channel index outside [0, M)
+    CSR_NOT_ASCENDING = 2,   // channels of a shot not strictly ascending
+    CSR_BAD_PAULI = 4,       // Pauli code zero or beyond the channel's qubits
+    CSR_BAD_OFFSETS = 8      // shot_off decreasing or negative
+};
+// kind: ChanKind per channel (uint8); flag: one device int, cleared first
 hipError_t launch_prescreen(int words, int32_t n_channels, int64_t n, const int64_t* off, const int32_t* chan,
-                            const uint8_t* pauli, const uint64_t* sig, uint64_t* survive_bits,
-                            int64_t* survivor_idx, int64_t* block_tmp, int64_t n_blocks_tmp,
-                            hipStream_t s);
+                            const uint8_t* pauli, const uint64_t* sig, const uint8_t* kind,
+                            uint64_t* survive_bits, int64_t* survivor_idx, int64_t* block_tmp,
+                            int64_t n_blocks_tmp, int* flag, hipStream_t s);
 int64_t prescreen_tmp_words(int64_t n);
+hipError_t launch_validate_csr(int32_t n_channels, int64_t n, const int64_t* off,
+                               const int32_t* chan, const uint8_t* pauli, const uint8_t* kind,
+                               int* flag, hipStream_t s);
 
 // device fault sampler: CSR of shots first .. first+n-1 (see sampler.hip);
 // tmp holds sampler_tmp_words(n) int64, its last used entry the nnz total
@@ -107,7 +157,8 @@ struct BatchTotals {
     double flops;
     int32_t chi_peak, status_or;
 };
-constexpr int kBinRows = 5;   // shots, sum P_acc, sum P_acc*fail, accepted, wrong
+// shots, sum P_acc, sum P_acc*fail, accepted, wrong, sum P_acc^2, sum (P_acc*fail)^2
+constexpr int kBinRows = 7;
 // surv (optional): per survivor n_seg reach probabilities, summed per bin
 // into sbins[b * n_seg + s]
 hipError_t launch_batch_reduce(int64_t n, uint64_t seed, uint64_t first, const int64_t* off,
@@ -123,6 +174,90 @@ hipError_t launch_scatter_results(int64_t n, const int64_t* n_surv, const int64_
 
 hipError_t launch_twosite(int precision, int chi, int batch, const float* A, const float* B,
                           const float* gate, float* theta, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Batched engine for large two-site updates (lx.hip, mps.hip): the shots
+// parked by the shot kernel (MpsArgs.park_*) are updated together.
+//   plan:     per parked shot its shapes and tile counts, prefix sums
+//   contract: theta = G (A[k] A[k+1]) on MFMA, ragged shapes, one tile list
+//   gram:     G = V^H V of theta's vectors (columns if the centre moves
+//             right, rows if left) in FP64 on MFMA, upper block triangle
+//   factor:   (mps.hip) eigen-decomposition of the overlapping vectors'
+//             block, rotation, selection, new site tensors, slot resumed
+// Every kernel takes its counts from device memory (LxPlan), so a launch
+// sequence does not depend on what the shot kernel parked (graph capture).
+constexpr int kLxMaxParked = 8192;
+// buckets of parked shots by theta's larger side: <= 128, <= 256, <= 512, more
+constexpr int kLxBuckets = 4;
+__host__ __device__ inline int lx_bucket(int side) {
+    return side <= 128 ? 0 : side <= 256 ? 1 : side <= 512 ? 2 : 3;
+}
+struct LxBucket {
+    int32_t count;                     // parked shots in the bucket
+    int32_t ctiles, gtiles;            // total contraction / Gram tiles
+    int32_t pad;
+    int32_t slot[kLxMaxParked];        // slot of the bucket's shot i
+    int32_t coff[kLxMaxParked + 1];    // first contraction tile of shot i
+    int32_t goff[kLxMaxParked + 1];    // first Gram tile of shot i
+};
+struct LxPlan {
+    int32_t count;                     // parked shots
+    int32_t pad[3];
+    int32_t slot[kLxMaxParked];        // slot of parked shot i (park order)
+    LxBucket b[kLxBuckets];
+};
+struct LxArgs {
+    const ShotState* state;            // per slot
+    const int32_t* park_count;
+    const int32_t* park_list;
+    LxPlan* plan;
+    void* arena;                       // slot tensors (element type T)
+    int64_t slot_stride;
+    const int64_t* site_off;           // per site offset of the Re plane
+    const int64_t* site_half;          // Im plane offset from the Re plane
+    const double* g4;                  // 4x4 gates, 32 doubles each
+    void* theta;                       // per slot theta (T), theta_stride elements
+    int64_t theta_stride;
+    double* gram;                      // per slot Gram (FP64 planar), gram_stride doubles
+    int64_t gram_stride;
+    int32_t n_slots;
+    double* flops;                     // [2] running algorithmic flops: contractions
+                                       // (32 cl cm cr each), Gram matrices (4 nv (nv+1) len)
+};
+// contraction tile (rows of (a, i) x b columns of both j') and Gram tile sizes
+struct LxTiles {
+    int32_t cm_rows, cm_b;             // contraction tile: rows (a,i) and b values
+    int32_t gram;                      // Gram tile side
+};
+// precision: MSC_FP32 (FP32 MFMA), MSC_BF16X3 (bf16 hi/lo split), MSC_FP64;
+// t[kLxBuckets]: the tiles of each bucket
+hipError_t launch_lx_plan(const LxArgs& a, const LxTiles* t, hipStream_t s);
+hipError_t launch_lx_contract(int precision, const LxArgs& a, int bucket, const LxTiles& t,
+                              int grid, hipStream_t s);
+hipError_t launch_lx_gram(int precision, const LxArgs& a, int bucket, const LxTiles& t,
+                          int grid, hipStream_t s);
+// slot states to kSlotRun, the park count and the flop counters to 0 (a
+// kernel, not a memset)
+hipError_t launch_lx_reset(ShotState* state, int n_slots, int32_t* park_count, double* flops,
+                           hipStream_t s);
+// the park count to 0
+hipError_t launch_lx_clear(int32_t* park_count, hipStream_t s);
+// the tile shapes compiled for a precision (autotuner candidates)
+int lx_tile_variants(int precision, LxTiles* out, int cap);
+// factor step of the engine (mps.hip); the slot's Gram buffer doubles as
+// its FP64 workspace once the Gram matrix has been read
+struct LxFactor {
+    const int32_t* cap;                // bond capacities [n_sites + 1]
+    int32_t chi_max;
+    double tau;                        // keep sigma_i > tau * sigma_0
+};
+constexpr int kLxFactorMax = 64;       // overlapping vectors diagonalised in LDS
+hipError_t launch_lx_factor(int precision, const LxArgs& a, const LxFactor& f, int grid,
+                            hipStream_t s);
+// doubles of one slot's Gram buffer for theta sides up to S: the Gram
+// matrix (2 S^2), or the workspace of rotated vectors (2 S (S + 1)), then
+// the per-vector arrays (7 S)
+inline int64_t lx_gram_doubles(int64_t S) { return 2 * S * (S + 1) + 7 * S + 64; }
 
 // ---------------------------------------------------------------------------
 // CAMPS shots (camps.hip): Clifford frame + magic-residual MPS in FP64

@@ -360,6 +360,11 @@ struct Kept {
     double kept, dropped;
 };
 
+// A squared norm as the selection orders it: negative or NaN values (only
+// ever numerical garbage) count as 0, so the order below is strict and
+// every rank from 0 up is taken by exactly one vector.
+__device__ __forceinline__ double sel_norm(double x) { return x > 0.0 ? x : 0.0; }
+
 // Keep the vectors with sigma^2 > tau2 * sigma_0^2 (at most capb), ordered by
 // decreasing norm: sel[0..r) are their indices, isq[c] = 1/sigma and
 // sq[c] = sigma of the c-th kept vector (each computed once here).
@@ -368,14 +373,14 @@ __device__ Kept select_kept(DP nrm, int nv, double tau2, int capb, IP sel, DP is
                             double* red) {
     const int tid = Team<W>::rank();
     double mx = 0.0;
-    for (int v = tid; v < nv; v += W) mx = fmax(mx, nrm[v]);
+    for (int v = tid; v < nv; v += W) mx = fmax(mx, sel_norm(nrm[v]));
     mx = team_max<W>(mx, red);
     double kd[3] = {0.0, 0.0, 0.0};
     for (int v = tid; v < nv; v += W) {
-        const double x = nrm[v];
+        const double x = sel_norm(nrm[v]);
         int rank = 0;
         for (int u = 0; u < nv; ++u) {
-            const double y = nrm[u];
+            const double y = sel_norm(nrm[u]);
             rank += (y > x) || (y == x && u < v);
         }
         const bool keep = (x > tau2 * mx || rank == 0) && rank < capb;
@@ -972,7 +977,21 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
     };
 
     const int64_t n_run = P.n_dev ? min(*P.n_dev, P.n_shots) : P.n_shots;
-    for (int64_t j = blockIdx.x; j < n_run; j += gridDim.x) {
+    // with slot states the grid is the slot count and every launch picks up
+    // where the slot's last one stopped
+    ShotState* const st = P.state ? P.state + blockIdx.x : nullptr;
+    int64_t j0 = blockIdx.x;
+    bool resume = false;
+    if (st) {
+        const int status = st->status;
+        if (status == kSlotDone || status == kSlotParked) return;
+        if (status == kSlotResume) {
+            resume = true;
+            j0 = st->j;
+        }
+    }
+    const bool can_park = st && P.park_side > 0;
+    for (int64_t j = j0; j < n_run; j += gridDim.x) {
         const int64_t it = P.perm ? P.perm[j] : j;
         const int64_t shot = P.shot_idx ? P.shot_idx[it] : it;
         if (shot < 0 || shot >= P.n_csr) {
@@ -1002,6 +1021,35 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
             const int navail = *P.ck_avail;
             const int jj = fcur < fend ? next_ch / P.ck_k : P.n_ck - 1;
             jck = jj < navail ? jj : navail - 1;
+        }
+        int next_ck = 0;              // record mode: next checkpoint to take
+        int64_t ck_pos = 0;           // record mode: elements written so far
+        bool ck_full = false;
+        if (resume) {
+            // ---- continue a parked shot after its large update
+            for (int k = tid; k <= N; k += NT) s_chi[k] = st->chi[k];
+            for (int k = tid; k < N; k += NT) s_laste[k] = st->laste[k];
+            fcur = st->fcur;
+            next_ch = st->next_ch;
+            fcode = st->fcode;
+            p_acc = st->p_acc;
+            infid = st->infid;
+            rej_at = st->rej_at;
+            alive = st->alive != 0;
+            start = st->oi;
+            meas_done = st->meas_done;
+            next_seg = st->next_seg;
+            next_ck = st->next_ck;
+            ck_pos = st->ck_pos;
+            ck_full = st->ck_full != 0;
+            acc.status = st->shot_status;
+            acc.chi_peak = st->chi_peak;
+            acc.disc = st->disc;
+            acc.n2q = st->n2q;
+            acc.flops = st->flops;
+            acc.sweeps = st->sweeps;
+            jck = -2;                 // no fork, no initial state
+            resume = false;
         }
         if (jck >= 0) {
             const CkHdr& h = P.ck_hdr[jck];
@@ -1034,7 +1082,7 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
                     ++next_seg;
                 }
             }
-        } else {
+        } else if (jck == -1) {
             // ---- initial product state |0...0>
             for (int k = tid; k <= N; k += NT) s_chi[k] = 1;
             for (int k = tid; k < N; k += NT) {
@@ -1047,9 +1095,6 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
             }
         }
         __syncthreads();
-        int next_ck = 0;              // record mode: next checkpoint to take
-        int64_t ck_pos = 0;           // record mode: elements written so far
-        bool ck_full = false;
         int ops_lo = 0, ops_hi = 0;   // op range held in s_ops
 
         for (int oi = start; oi < P.n_ops && alive; ++oi) {
@@ -1315,6 +1360,41 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
                 const int k = op.a, dir = op.b;
                 const int m = 2 * s_chi[k], n = 2 * s_chi[k + 2];
                 SiteView<T> A = site(k), B = site(k + 1);
+                if (can_park && max(m, n) > P.park_side) {
+                    // ---- hand the update to the batched engine: save the
+                    // shot, queue the slot and free the workgroup
+                    for (int q = tid; q <= N; q += NT) st->chi[q] = s_chi[q];
+                    for (int q = tid; q < N; q += NT) st->laste[q] = s_laste[q];
+                    if (tid == 0) {
+                        st->j = j;
+                        st->fcur = fcur;
+                        st->fend = fend;
+                        st->ck_pos = ck_pos;
+                        st->n2q = acc.n2q;
+                        st->sweeps = acc.sweeps;
+                        st->p_acc = p_acc;
+                        st->infid = infid;
+                        st->disc = acc.disc;
+                        st->flops = acc.flops;
+                        st->oi = oi + 1;
+                        st->next_ch = next_ch;
+                        st->fcode = fcode;
+                        st->meas_done = meas_done;
+                        st->next_seg = next_seg;
+                        st->rej_at = rej_at;
+                        st->alive = alive ? 1 : 0;
+                        st->next_ck = next_ck;
+                        st->ck_full = ck_full ? 1 : 0;
+                        st->shot_status = acc.status;
+                        st->chi_peak = acc.chi_peak;
+                        st->k = k;
+                        st->dir = dir;
+                        st->gate_id = gate_id;
+                        st->status = kSlotParked;
+                        P.park_list[atomicAdd(P.park_count, 1)] = blockIdx.x;
+                    }
+                    return;
+                }
                 if (m <= SMAX && n <= SMAX) {
                     const Vecs<ldsd*, ldsi*> V{to_lds(s_vre), to_lds(s_vim), to_lds(s_nrm),
                                                to_lds(s_isq), to_lds(s_sq), to_lds(s_sel),
@@ -1352,6 +1432,426 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
             res.flops = acc.flops;
             res.sweeps = acc.sweeps;
             P.out[it] = res;
+        }
+        __syncthreads();
+    }
+    if (st && tid == 0) st->status = kSlotDone;
+}
+
+// ---------------------------------------------------------------------------
+// Factor step of the batched engine for large two-site updates (the
+// contraction and the Gram matrix come from lx.hip).  One workgroup per
+// parked shot, with theta (tensor type T) and G = V^H V (FP64) of its
+// vectors V (theta's columns when the centre moves right, rows when left):
+//  * the vectors' squared norms are G's diagonal; a pair (p, q) overlaps if
+//    |G_pq|^2 > tol^2 G_pp G_qq (the same test and tolerance as the shot
+//    kernel's orthogonality check); the flagged vectors F are those of an
+//    overlapping pair, the others are already orthogonal to everything;
+//  * if |F| <= kLxFactorMax the block G_FF is diagonalised in LDS by cyclic
+//    two-sided Jacobi in FP64, W^H G_FF W = diag, and the rotated vectors
+//    Y = X_F W are formed in FP64 from theta; their squared norms are taken
+//    from Y itself, so a direction of G's null space gets a norm of order
+//    eps |X| rather than the sqrt(eps) |X| its eigenvalue carries.  Since X_F
+//    = Y W^H, theta = sum_u y_u conj(W[:, u])^T: the isometric factor is
+//    y_u / sigma_u and the centre factor's row (column) u is sigma_u
+//    conj(W[:, u]) on F (sigma_u e_v for an unflagged vector v), with no
+//    second product;
+//  * otherwise the flagged vectors are orthogonalised by one-sided Jacobi
+//    sweeps in the workspace (as the shot kernel does for wide theta) and the
+//    centre factor is the projection of theta on the isometric factor;
+//  * the kept vectors (sigma_u > tau sigma_0, at most the bond cap) are
+//    written as the new A[k], A[k+1] in FP64-renormalised form, the slot's
+//    state gets the new bond and counters and is marked for resumption.
+// Two-sided Jacobi on a Hermitian pair block [[a, g], [conj(g), b]]: with
+// g = |g| e^{i phi}, zeta = (b - a) / (2 |g|), t = sign(zeta) / (|zeta| +
+// sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2), s = c t, the unitary
+// J = diag(1, e^{-i phi}) [[c, s], [-s, c]] makes J^H A J diagonal (the
+// phase makes the pair's off-diagonal real, the real rotation removes it).
+constexpr int FM = kLxFactorMax;
+constexpr int FLD = FM + 1;
+
+template <typename T>
+__global__ __launch_bounds__(NT) void lx_factor_kernel(LxArgs a, LxFactor f) {
+    __shared__ double s_gr[FM * FLD], s_gi[FM * FLD];   // G_FF, then staging
+    __shared__ double s_wr[FM * FLD], s_wi[FM * FLD];   // W
+    __shared__ double s_pc[FM / 2], s_ps[FM / 2], s_pr[FM / 2], s_pi[FM / 2];
+    __shared__ int s_pp[FM / 2], s_pq[FM / 2];
+    __shared__ double s_red[NW * 4];
+    __shared__ int s_ired[NW];
+    __shared__ int s_any;
+    const int tid = threadIdx.x;
+    const LxPlan* pl = a.plan;
+    const int cnt = pl->count;
+    for (int pi = blockIdx.x; pi < cnt; pi += gridDim.x) {
+        const int slot = pl->slot[pi];
+        ShotState* st = const_cast<ShotState*>(a.state) + slot;
+        const int k = st->k, dir = st->dir;
+        const int cl = st->chi[k], cm = st->chi[k + 1], cr = st->chi[k + 2];
+        const int m = 2 * cl, n = 2 * cr;
+        const int nv = dir ? n : m, len = dir ? m : n;
+        typedef __attribute__((address_space(1))) T gT;
+        const gT* Tr = to_glb(static_cast<const T*>(a.theta) + (size_t)slot * a.theta_stride);
+        const gT* Ti = Tr + (size_t)m * n;
+        glbd* G = to_glb(a.gram + (size_t)slot * a.gram_stride);
+        const glbd* Gr = G;
+        const glbd* Gi = G + (size_t)nv * nv;
+        // per-vector arrays after the workspace (sides up to smax = 2 chi_max)
+        const int64_t smax = 2 * (int64_t)f.chi_max;
+        glbd* d = G + 2 * smax * (smax + 1);
+        glbd* nrm = d + smax;
+        glbd* isq = nrm + smax;
+        glbd* sq = isq + smax;
+        glbi* sel = reinterpret_cast<glbi*>(sq + smax);
+        glbi* bad = sel + smax;
+        glbi* list = bad + smax;
+        glbi* fpos = list + smax;
+        // the slot's site tensors
+        T* base = static_cast<T*>(a.arena) + (size_t)slot * a.slot_stride;
+        gT* Are = to_glb(base + a.site_off[k]);
+        gT* Aim = Are + a.site_half[k];
+        gT* Bre = to_glb(base + a.site_off[k + 1]);
+        gT* Bim = Bre + a.site_half[k + 1];
+        auto X = [&](int v, int e, int plane) -> double {   // vector v, element e
+            const size_t at = dir ? (size_t)e * n + v : (size_t)v * n + e;
+            return static_cast<double>(plane ? Ti[at] : Tr[at]);
+        };
+
+        // ---- norms and the overlap flags from G
+        double tot[1] = {0.0};
+        for (int v = tid; v < nv; v += NT) {
+            const double x = Gr[(size_t)v * nv + v];
+            d[v] = x;
+            bad[v] = 0;
+            tot[0] += x;
+        }
+        team_sum<NT, 1>(tot, s_red);
+        const double total = tot[0];
+        const double tau2 = f.tau * f.tau;
+        const double floor2 = 1e-4 * tau2 * total;
+        const double tol = sizeof(T) == sizeof(double) ? static_cast<double>(len) * DBL_EPSILON
+                                                       : 8.0 * static_cast<double>(FLT_EPSILON);
+        const double tol2 = tol * tol;
+        __syncthreads();
+        {
+            const int npair = nv * (nv - 1) / 2;
+            int p = 0, rowlen = nv - 1, t0 = 0;
+            for (int t = tid; t < npair; t += NT) {
+                while (t >= t0 + rowlen) {
+                    t0 += rowlen;
+                    ++p;
+                    --rowlen;
+                }
+                const int q = p + 1 + (t - t0);
+                const double dp = d[p], dq = d[q];
+                if (!(dp > floor2 && dq > floor2)) continue;
+                const double gr = Gr[(size_t)p * nv + q], gi = Gi[(size_t)p * nv + q];
+                if (gr * gr + gi * gi > tol2 * dp * dq) {
+                    bad[p] = 1;   // benign race: every writer stores 1
+                    bad[q] = 1;
+                }
+            }
+        }
+        __syncthreads();
+        const int nf = flagged_list<NT>(bad, nv, list, s_ired);
+        for (int v = tid; v < nv; v += NT) fpos[v] = -1;
+        __syncthreads();
+        for (int j = tid; j < nf; j += NT) fpos[list[j]] = j;
+        int sweeps = 0;
+        bool noconv = false;
+        const bool small = nf <= FM;
+        // workspace of the rotated vectors: planar FP64, vector j at j * ldy
+        const int ldy = len + 1;
+        glbd* Yr = G;
+        glbd* Yi = G + (size_t)nf * ldy;
+        if (nf > 0 && small) {
+            // ---- G_FF into LDS (Hermitian from the upper triangle), W = I
+            for (int idx = tid; idx < nf * nf; idx += NT) {
+                const int r = idx / nf, c = idx - r * nf;
+                const int p = list[r], q = list[c];
+                double gr, gi;
+                if (p <= q) {
+                    gr = Gr[(size_t)p * nv + q];
+                    gi = Gi[(size_t)p * nv + q];
+                } else {
+                    gr = Gr[(size_t)q * nv + p];
+                    gi = -Gi[(size_t)q * nv + p];
+                }
+                if (p == q) gi = 0.0;
+                s_gr[r * FLD + c] = gr;
+                s_gi[r * FLD + c] = gi;
+                s_wr[r * FLD + c] = r == c ? 1.0 : 0.0;
+                s_wi[r * FLD + c] = 0.0;
+            }
+            __syncthreads();
+            // ---- cyclic two-sided Jacobi, round-robin pairs
+            const int nve = nf + (nf & 1);
+            const int npairs = nve / 2;
+            bool again = true;
+            while (again && sweeps < 40) {
+                if (tid == 0) s_any = 0;
+                __syncthreads();
+                for (int t = 0; t < nve - 1; ++t) {
+                    if (tid < npairs) {
+                        const int sp = player(tid, t, nve), sq2 = player(nve - 1 - tid, t, nve);
+                        double c = 1.0, sn = 0.0, er = 1.0, ei = 0.0;
+                        int p = -1, q = -1;
+                        if (sp < nf && sq2 < nf) {
+                            p = sp < sq2 ? sp : sq2;
+                            q = sp < sq2 ? sq2 : sp;
+                            const double aa = s_gr[p * FLD + p], bb = s_gr[q * FLD + q];
+                            const double gr = s_gr[p * FLD + q], gi = s_gi[p * FLD + q];
+                            const double g2 = gr * gr + gi * gi;
+                            if (aa > floor2 && bb > floor2 && g2 > tol2 * aa * bb) {
+                                // e = exp(-i phi): the columns take J's e^{-i phi},
+                                // the rows its conjugate
+                                const double ga = sqrt(g2);
+                                er = gr / ga;
+                                ei = -gi / ga;
+                                const double zeta = (bb - aa) / (2.0 * ga);
+                                const double tt = (zeta >= 0.0 ? 1.0 : -1.0) /
+                                                  (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                                c = 1.0 / sqrt(1.0 + tt * tt);
+                                sn = c * tt;
+                                s_any = 1;
+                            } else {
+                                p = -1;
+                            }
+                        }
+                        s_pp[tid] = p;
+                        s_pq[tid] = q;
+                        s_pc[tid] = c;
+                        s_ps[tid] = sn;
+                        s_pr[tid] = er;
+                        s_pi[tid] = ei;
+                    }
+                    __syncthreads();
+                    // columns: A <- A J and W <- W J
+                    for (int idx = tid; idx < npairs * nf; idx += NT) {
+                        const int pr = idx / nf, r = idx - pr * nf;
+                        const int p = s_pp[pr];
+                        if (p < 0) continue;
+                        const int q = s_pq[pr];
+                        const double c = s_pc[pr], sn = s_ps[pr], er = s_pr[pr], ei = s_pi[pr];
+                        for (int mat = 0; mat < 2; ++mat) {
+                            double* Mr = mat ? s_wr : s_gr;
+                            double* Mi = mat ? s_wi : s_gi;
+                            const double xr = Mr[r * FLD + p], xi = Mi[r * FLD + p];
+                            const double yr = Mr[r * FLD + q], yi = Mi[r * FLD + q];
+                            // e y
+                            const double eyr = er * yr - ei * yi, eyi = er * yi + ei * yr;
+                            Mr[r * FLD + p] = c * xr - sn * eyr;
+                            Mi[r * FLD + p] = c * xi - sn * eyi;
+                            Mr[r * FLD + q] = sn * xr + c * eyr;
+                            Mi[r * FLD + q] = sn * xi + c * eyi;
+                        }
+                    }
+                    __syncthreads();
+                    // rows: A <- J^H A
+                    for (int idx = tid; idx < npairs * nf; idx += NT) {
+                        const int pr = idx / nf, col = idx - pr * nf;
+                        const int p = s_pp[pr];
+                        if (p < 0) continue;
+                        const int q = s_pq[pr];
+                        const double c = s_pc[pr], sn = s_ps[pr], er = s_pr[pr], ei = -s_pi[pr];
+                        const double xr = s_gr[p * FLD + col], xi = s_gi[p * FLD + col];
+                        const double yr = s_gr[q * FLD + col], yi = s_gi[q * FLD + col];
+                        // conj(e) y
+                        const double eyr = er * yr - ei * yi, eyi = er * yi + ei * yr;
+                        s_gr[p * FLD + col] = c * xr - sn * eyr;
+                        s_gi[p * FLD + col] = c * xi - sn * eyi;
+                        s_gr[q * FLD + col] = sn * xr + c * eyr;
+                        s_gi[q * FLD + col] = sn * xi + c * eyi;
+                    }
+                    __syncthreads();
+                }
+                ++sweeps;
+                again = s_any != 0;
+                __syncthreads();
+            }
+            noconv = again;
+            // ---- Y = X_F W in FP64, 64 elements of every flagged vector staged
+            // in LDS (the G_FF arrays are free now)
+            for (int e0 = 0; e0 < len; e0 += FM) {
+                const int ne = min(FM, len - e0);
+                for (int idx = tid; idx < nf * ne; idx += NT) {
+                    const int j = idx / ne, e = idx - j * ne;
+                    s_gr[j * FLD + e] = X(list[j], e0 + e, 0);
+                    s_gi[j * FLD + e] = X(list[j], e0 + e, 1);
+                }
+                __syncthreads();
+                for (int idx = tid; idx < nf * ne; idx += NT) {
+                    const int i = idx / ne, e = idx - i * ne;
+                    double yr = 0.0, yi = 0.0;
+                    for (int j = 0; j < nf; ++j) {
+                        const double xr = s_gr[j * FLD + e], xi = s_gi[j * FLD + e];
+                        const double wr = s_wr[j * FLD + i], wi = s_wi[j * FLD + i];
+                        yr += xr * wr - xi * wi;
+                        yi += xr * wi + xi * wr;
+                    }
+                    Yr[(size_t)i * ldy + e0 + e] = yr;
+                    Yi[(size_t)i * ldy + e0 + e] = yi;
+                }
+                __syncthreads();
+            }
+        } else if (nf > 0) {
+            // ---- many overlapping vectors: one-sided Jacobi in the workspace
+            for (int idx = tid; idx < nf * len; idx += NT) {
+                const int j = idx / len, e = idx - j * len;
+                Yr[(size_t)j * ldy + e] = X(list[j], e, 0);
+                Yi[(size_t)j * ldy + e] = X(list[j], e, 1);
+            }
+            for (int j = tid; j < nf; j += NT) sel[j] = j;   // identity list
+            __syncthreads();
+            vector_norms<NT>(Yr, Yi, nf, len, ldy, nrm);
+            bool again = true;
+            for (int j = tid; j < nf; j += NT) bad[j] = 1;
+            __syncthreads();
+            while (again && sweeps < 40) {
+                const int nb2 = flagged_list<NT>(bad, nf, sel, s_ired);
+                jacobi_sweep<NT>(Yr, Yi, sel, nb2, len, ldy, floor2, tol);
+                ++sweeps;
+                vector_norms<NT>(Yr, Yi, nf, len, ldy, nrm);
+                again = not_orthogonal<NT>(Yr, Yi, nf, len, ldy, nrm, floor2, tol, bad,
+                                           (glbi*)nullptr);
+            }
+            noconv = again;
+        }
+        __syncthreads();
+        // ---- squared norms of all vectors (rotated ones from Y itself)
+        for (int v = tid; v < nv; v += NT) {
+            const int j = fpos[v];
+            if (j < 0) {
+                nrm[v] = d[v];
+            } else {
+                double s0 = 0.0, s1 = 0.0;
+                const glbd* yr = Yr + (size_t)j * ldy;
+                const glbd* yi = Yi + (size_t)j * ldy;
+                for (int e = 0; e < len; ++e) {
+                    s0 += yr[e] * yr[e];
+                    s1 += yi[e] * yi[e];
+                }
+                nrm[v] = s0 + s1;
+            }
+        }
+        __syncthreads();
+        const int capb = min(f.chi_max, f.cap[k + 1]);
+        const Kept kp = select_kept<NT>(nrm, nv, tau2, capb, sel, isq, sq, s_red);
+        const int r = kp.r;
+        const double renorm = 1.0 / sqrt(kp.kept);
+        // ---- isometric factor: the kept vectors, normalised
+        // (element e of kept vector c)
+        auto kept_elem = [&](int c, int e, double& xr, double& xi) {
+            const int v = sel[c];
+            const int j = fpos[v];
+            if (j < 0) {
+                xr = X(v, e, 0);
+                xi = X(v, e, 1);
+            } else {
+                xr = Yr[(size_t)j * ldy + e];
+                xi = Yi[(size_t)j * ldy + e];
+            }
+        };
+        if (dir) {
+            for (int idx = tid; idx < m * r; idx += NT) {
+                const int row = idx / r, c = idx - row * r;
+                double xr, xi;
+                kept_elem(c, row, xr, xi);
+                Are[idx] = T(xr * isq[c]);
+                Aim[idx] = T(xi * isq[c]);
+            }
+        } else {
+            for (int idx = tid; idx < r * n; idx += NT) {
+                const int c = idx / n, col = idx - c * n;
+                double xr, xi;
+                kept_elem(c, col, xr, xi);
+                Bre[idx] = T(xr * isq[c]);
+                Bim[idx] = T(xi * isq[c]);
+            }
+        }
+        // ---- centre factor
+        if (nf == 0 || small) {
+            // sigma_u conj(W[:, u]) on the flagged positions, sigma_u e_v for
+            // an unflagged vector v (entry (u, v) of Sigma W~^H)
+            auto centre = [&](int c, int v, double& xr, double& xi) {
+                const int u = sel[c];
+                const int ju = fpos[u], jv = fpos[v];
+                const double sc = sq[c] * renorm;
+                if (ju < 0) {
+                    xr = v == u ? sc : 0.0;
+                    xi = 0.0;
+                } else if (jv < 0) {
+                    xr = 0.0;
+                    xi = 0.0;
+                } else {
+                    xr = sc * s_wr[jv * FLD + ju];
+                    xi = -sc * s_wi[jv * FLD + ju];
+                }
+            };
+            if (dir) {
+                for (int idx = tid; idx < r * n; idx += NT) {
+                    const int c = idx / n, col = idx - c * n;
+                    double xr, xi;
+                    centre(c, col, xr, xi);
+                    Bre[idx] = T(xr);
+                    Bim[idx] = T(xi);
+                }
+            } else {
+                for (int idx = tid; idx < m * r; idx += NT) {
+                    const int row = idx / r, c = idx - row * r;
+                    double xr, xi;
+                    centre(c, row, xr, xi);
+                    Are[idx] = T(xr);
+                    Aim[idx] = T(xi);
+                }
+            }
+        } else {
+            // projection of theta on the isometric factor just written
+            __syncthreads();
+            if (dir) {
+                // A[k+1][c][col] = sum_row conj(U[row][c]) theta[row][col]
+                for (int idx = tid; idx < r * n; idx += NT) {
+                    const int c = idx / n, col = idx - c * n;
+                    double xr = 0.0, xi = 0.0;
+                    for (int row = 0; row < m; ++row) {
+                        const double ur = static_cast<double>(Are[row * r + c]);
+                        const double ui = static_cast<double>(Aim[row * r + c]);
+                        const double tr = X(col, row, 0), ti = X(col, row, 1);
+                        xr += ur * tr + ui * ti;
+                        xi += ur * ti - ui * tr;
+                    }
+                    Bre[idx] = T(xr * renorm);
+                    Bim[idx] = T(xi * renorm);
+                }
+            } else {
+                // A[k][row][c] = sum_col theta[row][col] conj(V[c][col])
+                for (int idx = tid; idx < m * r; idx += NT) {
+                    const int row = idx / r, c = idx - row * r;
+                    double xr = 0.0, xi = 0.0;
+                    for (int col = 0; col < n; ++col) {
+                        const double vr = static_cast<double>(Bre[c * n + col]);
+                        const double vi = static_cast<double>(Bim[c * n + col]);
+                        const double tr = X(row, col, 0), ti = X(row, col, 1);
+                        xr += tr * vr + ti * vi;
+                        xi += ti * vr - tr * vi;
+                    }
+                    Are[idx] = T(xr * renorm);
+                    Aim[idx] = T(xi * renorm);
+                }
+            }
+        }
+        // ---- the slot's state: new bond, counters, resume
+        if (tid == 0) {
+            st->chi[k + 1] = r;
+            st->disc += kp.dropped;
+            if (kp.dropped > 1e-12 * total && r == capb) st->shot_status |= MSC_SHOT_CHI_CAP;
+            if (noconv) st->shot_status |= MSC_SHOT_NOCONV;
+            st->sweeps += sweeps;
+            st->chi_peak = max(st->chi_peak, r);
+            st->n2q += 1;
+            const double dl = cl, dm = cm, dr = cr, dk = r;
+            st->flops += 32.0 * dl * dm * dr + 32.0 * dl * dl * dr + 32.0 * dk * dl * dr +
+                         104.0 * dl * dl * dl;
+            st->status = kSlotResume;
         }
         __syncthreads();
     }
@@ -1438,6 +1938,15 @@ hipError_t launch_order(int64_t n, const int64_t* n_dev, const int64_t* shot_off
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(order_kernel, dim3(1), dim3(OT), 0, s, n, n_dev, shot_off, shot_idx, n_csr,
                        chan, n_channels, perm);
+    return hipGetLastError();
+}
+
+hipError_t launch_lx_factor(int precision, const LxArgs& a, const LxFactor& f, int grid,
+                            hipStream_t s) {
+    if (precision == MSC_FP64)
+        hipLaunchKernelGGL(lx_factor_kernel<double>, dim3(grid), dim3(NT), 0, s, a, f);
+    else
+        hipLaunchKernelGGL(lx_factor_kernel<float>, dim3(grid), dim3(NT), 0, s, a, f);
     return hipGetLastError();
 }
 

@@ -10,6 +10,12 @@
 // wave w <-> shot 64 w + j).  A second pass turns the bitmap into an
 // ascending survivor index list: per-block popcounts, one scan block, and a
 // scatter with a per-wave prefix from the ballot mask.  Integer only.
+//
+// The CSR is checked on the way: a channel index outside [0, M), channels
+// not strictly ascending within a shot, a Pauli code that is zero or names
+// a qubit the channel does not have, or decreasing offsets set bits of a
+// device flag word (CsrFlag), and the host turns a nonzero flag into
+// MSC_E_INVALID.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -25,25 +31,48 @@ constexpr int kScanT = 256;
 
 constexpr int PT = 256;   // threads per block (4 waves, 256 shots)
 
+// Largest Pauli code + 1 of each channel kind (ChanKind order): one qubit
+// (x, z bits), two, the X flip (x of qubit 0 only), three.
+__device__ __forceinline__ int code_limit(int kind) {
+    return kind == CH_DEP1 ? 4 : kind == CH_DEP2 ? 16 : kind == CH_XERR ? 2 : 64;
+}
+
+// Checks of one fault against the previous one of its shot (CsrFlag bits).
+__device__ __forceinline__ int fault_check(int64_t c, int64_t prev, int p, int32_t nch,
+                                           const uint8_t* __restrict__ kind) {
+    if (c < 0 || c >= nch) return CSR_BAD_CHANNEL;
+    int bad = c <= prev ? CSR_NOT_ASCENDING : 0;
+    if (p == 0 || p >= code_limit(kind[c])) bad |= CSR_BAD_PAULI;
+    return bad;
+}
+
 template <int W>
 __global__ __launch_bounds__(PT) void screen_kernel(int32_t nch, int64_t n,
                                                     const int64_t* __restrict__ off,
                                                     const int32_t* __restrict__ chan,
                                                     const uint8_t* __restrict__ pauli,
                                                     const uint64_t* __restrict__ sig,
+                                                    const uint8_t* __restrict__ kind,
                                                     uint64_t* __restrict__ bits,
-                                                    int64_t* __restrict__ block_cnt) {
+                                                    int64_t* __restrict__ block_cnt,
+                                                    int* __restrict__ flag) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * PT + threadIdx.x;
     bool alive = false;
+    int bad = 0;
     if (i < n) {
         uint64_t acc[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) acc[w] = 0;
         const int64_t f0 = off[i], f1 = off[i + 1];
+        if (f1 < f0 || f0 < 0) bad |= CSR_BAD_OFFSETS;
+        int64_t prev = -1;
         for (int64_t f = f0; f < f1; ++f) {
             const int64_t c = chan[f];
-            if (c < 0 || c >= nch) continue;   // not a channel of this circuit
             const int p = pauli[f];
+            const int fb = fault_check(c, prev, p, nch, kind);
+            bad |= fb;
+            prev = c;
+            if (fb & CSR_BAD_CHANNEL) continue;   // not a channel of this circuit
             const uint64_t* s = sig + c * kFaultComponents * W;
 #pragma unroll
             for (int k = 0; k < kFaultComponents; ++k) {
@@ -58,6 +87,7 @@ __global__ __launch_bounds__(PT) void screen_kernel(int32_t nch, int64_t n,
         for (int w = 0; w < W; ++w) any |= acc[w];
         alive = any == 0;
     }
+    if (bad) atomicOr(flag, bad);
     const uint64_t mask = __ballot(alive);
     const int lane = threadIdx.x & 63;
     const int64_t word = (static_cast<int64_t>(blockIdx.x) * PT + (threadIdx.x & ~63)) >> 6;
@@ -73,6 +103,30 @@ __global__ __launch_bounds__(PT) void screen_kernel(int32_t nch, int64_t n,
         block_cnt[blockIdx.x] = t;
     }
 }
+
+// The same checks alone, one shot per lane (for the entry points that
+// take a caller's CSR without screening it).
+__global__ __launch_bounds__(PT) void validate_kernel(int32_t nch, int64_t n,
+                                                      const int64_t* __restrict__ off,
+                                                      const int32_t* __restrict__ chan,
+                                                      const uint8_t* __restrict__ pauli,
+                                                      const uint8_t* __restrict__ kind,
+                                                      int* __restrict__ flag) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * PT + threadIdx.x;
+    if (i >= n) return;
+    const int64_t f0 = off[i], f1 = off[i + 1];
+    int bad = (f1 < f0 || f0 < 0) ? CSR_BAD_OFFSETS : 0;
+    int64_t prev = -1;
+    for (int64_t f = f0; f < f1; ++f) {
+        const int64_t c = chan[f];
+        bad |= fault_check(c, prev, pauli[f], nch, kind);
+        prev = c;
+    }
+    if (bad) atomicOr(flag, bad);
+}
+
+// one word set to zero by a kernel (a fill node, not a memset, if captured)
+__global__ void clear_flag_kernel(int* flag) { *flag = 0; }
 
 // exclusive scan of block counts in place (one block), total at [nb]
 __global__ __launch_bounds__(kScanT) void scan_kernel(int64_t* cnt, int64_t nb) {
@@ -123,21 +177,25 @@ __global__ __launch_bounds__(PT) void scatter_kernel(int64_t n, const uint64_t* 
 
 }  // namespace
 
-int64_t prescreen_tmp_words(int64_t n) { return (n + PT - 1) / PT + 1; }
+// block counts, then the survivor total, then the CSR flag (one word each)
+int64_t prescreen_tmp_words(int64_t n) { return (n + PT - 1) / PT + 2; }
 
 hipError_t launch_prescreen(int words, int32_t n_channels, int64_t n, const int64_t* off, const int32_t* chan,
-                            const uint8_t* pauli, const uint64_t* sig, uint64_t* bits,
-                            int64_t* survivor_idx, int64_t* block_tmp, int64_t n_blocks_tmp,
-                            hipStream_t s) {
+                            const uint8_t* pauli, const uint64_t* sig, const uint8_t* kind,
+                            uint64_t* bits, int64_t* survivor_idx, int64_t* block_tmp,
+                            int64_t n_blocks_tmp, int* flag, hipStream_t s) {
     const int64_t nb = (n + PT - 1) / PT;
     if (nb == 0) return hipSuccess;
-    if (n_blocks_tmp < nb + 1) return hipErrorInvalidValue;
+    if (n_blocks_tmp < nb + 1 || !flag) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, s, flag);
+    hipError_t e0 = hipGetLastError();
+    if (e0 != hipSuccess) return e0;
     dim3 grid(static_cast<unsigned>(nb));
     switch (words) {
 #define MSC_SCREEN_CASE(WW)                                                                   \
     case WW:                                                                                  \
         hipLaunchKernelGGL(screen_kernel<WW>, grid, dim3(PT), 0, s, n_channels, n, off, chan,  \
-                           pauli, sig, bits, block_tmp);                                      \
+                           pauli, sig, kind, bits, block_tmp, flag);                          \
         break;
         MSC_SCREEN_CASE(1)
         MSC_SCREEN_CASE(2)
@@ -157,6 +215,19 @@ hipError_t launch_prescreen(int words, int32_t n_channels, int64_t n, const int6
     e = hipGetLastError();
     if (e != hipSuccess || !survivor_idx) return e;
     hipLaunchKernelGGL(scatter_kernel, grid, dim3(PT), 0, s, n, bits, block_tmp, survivor_idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_csr(int32_t n_channels, int64_t n, const int64_t* off,
+                               const int32_t* chan, const uint8_t* pauli, const uint8_t* kind,
+                               int* flag, hipStream_t s) {
+    if (!flag) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, s, flag);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n <= 0) return e;
+    const dim3 grid(static_cast<unsigned>((n + PT - 1) / PT));
+    hipLaunchKernelGGL(validate_kernel, grid, dim3(PT), 0, s, n_channels, n, off, chan, pauli,
+                       kind, flag);
     return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import paper_2609_19116_amd as msc
+from oracle import estimators as est
 from paper_2609_19116_amd import MSC_FP32, MSC_FP64, results_numpy
 from oracle import stats as ostats
 from tests.helpers import oracle_csr, oracle_results, say
@@ -44,11 +45,13 @@ def _separate(ctx, circ, seed, first, n, p, nb, **kw):
         res = results_numpy(msc.simulate(ctx, circ, off, ch, pa, shot_idx=idx, **kw))
         per[idx.cpu().numpy()] = res
     w = np.minimum(np.diff(off.cpu().numpy()), nb - 1)
-    bins = np.zeros((5, nb))
+    bins = np.zeros((7, nb))
     np.add.at(bins[0], w, 1.0)
     np.add.at(bins[1], w, per["p_acc"])
     np.add.at(bins[2], w, per["p_acc"] * per["fail"])
     _, bins[3], bins[4] = ostats.count_bins(seed, first, w, per["p_acc"], per["fail"], nb)
+    np.add.at(bins[5], w, per["p_acc"] ** 2)
+    np.add.at(bins[6], w, (per["p_acc"] * per["fail"]) ** 2)
     return bins, per, int(ch.numel()), cnt
 
 
@@ -75,7 +78,8 @@ def test_run_batch_equals_separate_stages(ctx, name, n, p, precision, prefix):
         assert np.array_equal(got[f], per[f]), f
     assert np.array_equal(bins[0], ref_bins[0])
     assert np.allclose(bins[1:3], ref_bins[1:3], rtol=1e-12, atol=1e-12)
-    assert np.array_equal(bins[3:], ref_bins[3:])
+    assert np.array_equal(bins[3:5], ref_bins[3:5])
+    assert np.allclose(bins[5:7], ref_bins[5:7], rtol=1e-12, atol=1e-12)
     assert st["n_shots"] == n and st["nnz"] == nnz and st["n_survivors"] == cnt
     assert st["n_accepted"] == int((per["p_acc"] > 0).sum())
     assert st["n2q"] == int(per["n2q"].sum()) and st["chi_peak"] == int(per["chi_peak"].max())
@@ -96,19 +100,29 @@ def test_run_batch_bins_match_oracle(ctx):
     ref = oracle_results(ocirc, ocsr)        # screened shots carry P_acc 0
     w = np.minimum(np.diff(ocsr[0]), nb - 1)
     fail = (ref[:, 0] > 0) & (ref[:, 1] > 1e-4)
-    rb = np.zeros((5, nb))
+    rb = np.zeros((7, nb))
     np.add.at(rb[0], w, 1.0)
     np.add.at(rb[1], w, ref[:, 0])
     np.add.at(rb[2], w, ref[:, 0] * fail)
     _, rb[3], rb[4] = ostats.count_bins(seed, 0, w, ref[:, 0], fail, nb)
+    np.add.at(rb[5], w, ref[:, 0] ** 2)
+    np.add.at(rb[6], w, (ref[:, 0] * fail) ** 2)
     assert np.array_equal(bins[0], rb[0])
     assert np.abs(bins[1:3] - rb[1:3]).max() <= 1e-10 * n
+    assert np.abs(bins[5:7] - rb[5:7]).max() <= 1e-10 * n
     # the counts take the same decision u < P_acc on both sides
-    assert np.array_equal(bins[3:], rb[3:])
+    assert np.array_equal(bins[3:5], rb[3:5])
+    # standard errors of Eq. (reweight) from the GPU's sums equal the oracle's
+    M = circ.info()["n_channels"]
+    for pp in (5e-4, 1e-3, 2e-3):
+        got = msc.reweight(bins[0], bins[1], bins[2], M, [pp], bins[5], bins[6])[0]
+        sa, se = est.standard_errors(list(rb[0]), list(rb[1]), list(rb[2]), M, pp,
+                                     list(rb[5]), list(rb[6]))
+        assert got["sem_p_acc"] == pytest.approx(sa, rel=1e-8)
+        assert got["sem_p_acc_le"] == pytest.approx(se, rel=1e-8, abs=1e-15)
     assert bins[3].sum() > 0
     # the likelihood-ratio intervals from the GPU's counts equal the oracle's
     last = int(np.nonzero(rb[0])[0].max()) + 1
-    M = circ.info()["n_channels"]
     pb = ostats.Problem(rb[0][:last], rb[3][:last], rb[4][:last], M, p)
     for f in (msc.MSC_STAT_PACC, msc.MSC_STAT_PLE):
         r = msc.lr_interval(bins[0][:last], bins[3][:last], bins[4][:last], M, p, f)

@@ -1,0 +1,159 @@
+"""GPU parity of the batched engine for large two-site updates.
+
+The engine takes every two-site update whose theta has a side above
+large_side: ragged MFMA contractions, FP64 Gram matrices on MFMA, FP64
+Jacobi eigen-decompositions of their overlapping blocks and the new site
+tensors, for all parked shots at once.  Forcing it onto small updates
+(large_side = 2) runs it on every shape of the small circuits; the results
+are compared per shot with the CPU oracle (P_acc and f within 1e-10
+relative in FP64, 1e-5 in FP32, rejection index and failure flag exact) and
+with the shot kernel alone (large_side = -1).  Graph replay, the slot
+count and prefix forking change no bit of a result.  The 81-qubit circuit reaches bond 64
+(theta sides 128) and the 49-qubit circuit on the rainbow layout bond 128
+(sides 256), where the default large_side = 64 hands the wide updates to the
+engine; their shots are compared with oracle values stored by
+tests/golden/make_large_chi.py.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import paper_2609_19116_amd as msc
+from paper_2609_19116_amd import MSC_FP32, MSC_FP64, results_numpy
+from tests.helpers import oracle_csr, oracle_results, say, to_dev
+from tests.test_gpu_parity import TOL, _compare, _same_csr
+from workloads.circuits import config_circuit
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+FIELDS = ["p_acc", "infid", "disc_weight", "chi_peak", "status", "rejected_at", "fail", "n2q",
+          "flops", "sweeps"]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    c = msc.Ctx(0)
+    yield c
+    c.close()
+
+
+_CIRC = {}
+
+
+def _circuit(ctx, name):
+    if name not in _CIRC:
+        cc = config_circuit(name)
+        c = msc.Circuit(cc.text)
+        say(f"calibrate {name}")
+        c.calibrate(ctx)
+        _CIRC[name] = (cc, c)
+    return _CIRC[name]
+
+
+_REF = {}
+
+
+def _stratified(ctx, name, n, seed):
+    cc, c = _circuit(ctx, name)
+    w = np.arange(n) % 5
+    csr = msc.sample_faults(c, seed, 0, n, weights=w)
+    key = (name, n, seed)
+    if key not in _REF:
+        circ, ocsr = oracle_csr(cc.text, seed, n, weights=w)
+        assert _same_csr(csr, ocsr)
+        _REF[key] = oracle_results(circ, ocsr)
+    return c, csr, _REF[key]
+
+
+@pytest.mark.parametrize("precision", [MSC_FP64, MSC_FP32])
+@pytest.mark.parametrize("name,n", [("tiny", 120), ("c1", 160), ("tiny_ghz", 120),
+                                    ("c1_ghz", 120)])
+def test_engine_on_every_update_matches_oracle(ctx, name, n, precision):
+    c, csr, ref = _stratified(ctx, name, n, 0x5EED0031)
+    off, ch, pa = to_dev(*csr)
+    say(f"engine {name} precision={precision} large_side=2")
+    res = results_numpy(msc.simulate(ctx, c, off, ch, pa, precision=precision, large_side=2))
+    st = ctx.engine_stats()
+    assert st["updates"] > 0 and st["contract_flops"] > 0 and st["gram_flops"] > 0
+    _compare(res, ref, TOL[precision])
+    say(f"shot kernel alone {name} precision={precision}")
+    alone = results_numpy(msc.simulate(ctx, c, off, ch, pa, precision=precision,
+                                       large_side=-1))
+    assert ctx.engine_stats()["updates"] == 0
+    acc = alone["p_acc"] > 0
+    # the two factorisations may pick different bases of degenerate singular
+    # subspaces (the SVD gauge), which can change later centre moves and so
+    # the update count, never a gauge-invariant result
+    assert np.array_equal(res["rejected_at"], alone["rejected_at"])
+    assert np.array_equal(res["fail"], alone["fail"])
+    rel = np.abs(res["p_acc"] - alone["p_acc"])[acc] / alone["p_acc"][acc]
+    assert rel.max() <= TOL[precision]
+
+
+@pytest.mark.parametrize("lds_width", [32, 64])
+def test_engine_graphs_and_prefix_change_no_bit(ctx, lds_width):
+    c, csr, ref = _stratified(ctx, "c1", 160, 0x5EED0032)
+    off, ch, pa = to_dev(*csr)
+    say(f"engine graphs/prefix lds_width={lds_width}")
+    kw = dict(precision=MSC_FP32, large_side=4, lds_width=lds_width)
+    base = results_numpy(msc.simulate(ctx, c, off, ch, pa, **kw))
+    assert ctx.engine_stats()["rounds"] > 0
+    g1 = results_numpy(msc.simulate(ctx, c, off, ch, pa, use_graphs=True, **kw))
+    g2 = results_numpy(msc.simulate(ctx, c, off, ch, pa, use_graphs=True, **kw))
+    pf = results_numpy(msc.simulate(ctx, c, off, ch, pa, prefix=True, **kw))
+    slots = results_numpy(msc.simulate(ctx, c, off, ch, pa, n_slots=7, **kw))
+    for other in (g1, g2, slots):
+        for f in FIELDS:
+            assert np.array_equal(base[f], other[f]), f
+    # a forked shot skips (and does not count) the updates before its fork
+    for f in FIELDS[:7]:
+        assert np.array_equal(base[f], pf[f]), f
+    _compare(base, ref, TOL[MSC_FP32])
+
+
+@pytest.mark.parametrize("precision", [MSC_FP64, MSC_FP32])
+def test_engine_c3_stratified(ctx, precision):
+    c, csr, ref = _stratified(ctx, "c3", 30, 0x5EED0033)
+    off, ch, pa = to_dev(*csr)
+    say(f"engine c3 precision={precision} large_side=8")
+    res = results_numpy(msc.simulate(ctx, c, off, ch, pa, precision=precision, large_side=8))
+    assert ctx.engine_stats()["updates"] > 0
+    _compare(res, ref, TOL[precision])
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, f"large_chi_{name}.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("precision", [MSC_FP64, MSC_FP32])
+@pytest.mark.parametrize("use_graphs", [False, True])
+@pytest.mark.parametrize("name,chi", [("c4", 64), ("c3_rainbow", 128)])
+def test_engine_golden_large_bonds(ctx, name, chi, precision, use_graphs):
+    # the 81-qubit circuit (bond 64) and the 49-qubit circuit on the rainbow
+    # layout (bond 128), shots stored by the oracle-only golden script
+    import torch
+    g = _golden(name)
+    assert g["noiseless"]["chi_peak"] == chi
+    cc, c = _circuit(ctx, name)
+    n = g["candidates"]
+    w = np.full(n, g["weight_of_every_shot"], dtype=np.int32)
+    csr = msc.sample_faults(c, int(g["seed"], 16), 0, n, weights=w)
+    shots = [s["shot"] for s in g["shots"]]
+    ref = np.array([(s["p_acc"], s["infid"], s["rejected_at"]) for s in g["shots"]])
+    assert sum(1 for s in g["shots"] if s["p_acc"] > 0) >= 16
+    off, ch, pa = to_dev(*csr)
+    idx = torch.tensor(shots, dtype=torch.int64, device="cuda")
+    say(f"engine golden {name} precision={precision} graphs={use_graphs}")
+    res = results_numpy(msc.simulate(ctx, c, off, ch, pa, shot_idx=idx, precision=precision,
+                                     use_graphs=use_graphs))
+    assert ctx.engine_stats()["updates"] > 0
+    _compare(res, ref, TOL[precision])
+    acc = ref[:, 0] > 0
+    assert np.all(res["chi_peak"][acc] >= chi)
+    assert not np.any(res["status"] & (msc.SHOT_CHI_CAP | msc.SHOT_NOCONV))

@@ -41,8 +41,9 @@ def test_order_cost_constants_match_header():
 
 def test_struct_sizes_match_header():
     assert C.sizeof(_lib.ShotResult) == 64
-    assert C.sizeof(_lib.SimOpts) == 48
+    assert C.sizeof(_lib.SimOpts) == 64
     assert C.sizeof(_lib.CircuitInfo) == 72
+    assert C.sizeof(_lib.Estimate) == 48
     assert C.sizeof(_lib.BatchStats) == 88
 
 
@@ -194,6 +195,24 @@ def test_reweight_matches_oracle_estimators():
         assert got["p_acc_le"] == pytest.approx(ref["p_acc_le"], rel=1e-12)
         assert got["p_le"] == pytest.approx(ref["p_le"], rel=1e-12)
         assert got["trunc_bound"] == pytest.approx(ref["B"], rel=1e-9, abs=1e-15)
+        # standard errors: from sums of squares, and from the [0, 1] bound
+        a2 = a * rng.uniform(0.3, 1.0, size=6)
+        e2 = e * rng.uniform(0.0, 0.1, size=6)
+        n1 = n.copy()
+        n1[2] = 1.0                           # one-shot bin: the bound
+        a1 = a.copy()
+        a1[2] = 0.4
+        e1 = e.copy()
+        e1[2] = 0.0
+        for nn, aa, ee in ((n, a, e), (n1, a1, e1)):
+            got = msc.reweight(nn, aa, ee, M, [p], a2, e2)[0]
+            sa, se = est.standard_errors(list(nn), list(aa), list(ee), M, p, list(a2), list(e2))
+            assert got["sem_p_acc"] == pytest.approx(sa, rel=1e-12)
+            assert got["sem_p_acc_le"] == pytest.approx(se, rel=1e-12)
+        got = msc.reweight(n, a, e, M, [p])[0]
+        sa, se = est.standard_errors(list(n), list(a), list(e), M, p)
+        assert got["sem_p_acc"] == pytest.approx(sa, rel=1e-12)
+        assert got["sem_p_acc_le"] == pytest.approx(se, rel=1e-12)
 
 
 def test_reweight_errors():

@@ -187,7 +187,8 @@ const char* msc_version(void);
    every device entry point of the context runs on: NULL gives the context
    a non-blocking stream of its own (default priority, destroyed with the
    context); a caller's stream is used as is and stays the caller's (it
-   must belong to `device` and outlive the context).  Fails with
+   must belong to `device` and outlive the context).  The context also
+   readies the device's fixed scratch of msc_prescreen_noalloc.  Fails with
    MSC_E_DEVICE when no GPU is usable.                                     */
 int msc_ctx_create(int device, void* stream, msc_ctx** out);
 void msc_ctx_destroy(msc_ctx* ctx);
@@ -297,6 +298,21 @@ int msc_prescreen(msc_ctx* ctx, const msc_circuit* c, int64_t n_shots,
                   const int64_t* shot_off, const int32_t* chan,
                   const uint8_t* pauli, uint64_t* survive_bits,
                   int64_t* survivor_idx, int64_t* n_survivors);
+
+/* msc_prescreen for callers that cannot allocate device memory (code under
+   HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+   the same screen, bit for bit, with its block counts and CSR check word in
+   a fixed per-device array of the library (2 MiB, held until the process
+   ends) instead of context scratch.  At most 2^26 shots per call (else
+   MSC_E_INVALID, nothing launched).  The circuit's tables must already be
+   on the context's device (msc_circuit_calibrate or an earlier
+   msc_prescreen put them there), else MSC_E_STATE.  Every call on one GPU
+   uses the same array, so calls that overlap on a GPU race; each call
+   overwrites what it reads before reading it.  No allocation, no free.   */
+int msc_prescreen_noalloc(msc_ctx* ctx, const msc_circuit* c, int64_t n_shots,
+                          const int64_t* shot_off, const int32_t* chan,
+                          const uint8_t* pauli, uint64_t* survive_bits,
+                          int64_t* survivor_idx, int64_t* n_survivors);
 
 /* ---------------------------------------------------------------------- */
 /* Batched exact MPS simulation (Sections 3.1, 4, 4.3).                    */

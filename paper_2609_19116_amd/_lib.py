@@ -126,6 +126,8 @@ _SIGS = {
                                            C.POINTER(C.c_int64)]),
     "msc_prescreen_tables": (C.c_int, [_P, _P, _P]),
     "msc_prescreen": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P, _P, _P, C.POINTER(C.c_int64)]),
+    "msc_prescreen_noalloc": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P, _P, _P,
+                                        C.POINTER(C.c_int64)]),
     "msc_simulate": (C.c_int, [_P, _P, C.POINTER(SimOpts), C.c_int64, _P, _P, _P, _P,
                                C.c_int64, _P]),
     "msc_run_batch": (C.c_int, [_P, _P, C.POINTER(SimOpts), C.c_uint64, C.c_uint64, C.c_int64,

@@ -115,6 +115,8 @@ extern "C" int msc_ctx_create(int device, void* stream, msc_ctx** out) {
         MSC_HIP(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
         ctx->own_stream = true;
     }
+    int64_t* fixed = nullptr;   // the device's msc_prescreen_noalloc scratch
+    MSC_HIP(prescreen_noalloc_scratch(device, &fixed));
     MSC_HIP(hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, device));
     MSC_HIP(hipEventCreate(&ctx->ev0));
     MSC_HIP(hipEventCreate(&ctx->ev1));
@@ -918,6 +920,32 @@ extern "C" int msc_prescreen(msc_ctx* ctx, const msc_circuit* c, int64_t n_shots
     if ((rc = ctx_buf(ctx, "screen_tmp", nt * sizeof(int64_t), &tmp))) return rc;
     return screen_into(ctx, c, n_shots, shot_off, chan, pauli, survive_bits, survivor_idx,
                        static_cast<int64_t*>(tmp), nt, n_survivors);
+}
+
+// msc_prescreen without device allocations: the block counts and the flag
+// live in the library's fixed per-device scratch (prescreen.hip), so calls on
+// one GPU share it (overlapping calls race) and each call starts by
+// overwriting what it needs (the flag is cleared by a kernel, every block
+// count is written before the scan reads it).
+extern "C" int msc_prescreen_noalloc(msc_ctx* ctx, const msc_circuit* c, int64_t n_shots,
+                                     const int64_t* shot_off, const int32_t* chan,
+                                     const uint8_t* pauli, uint64_t* survive_bits,
+                                     int64_t* survivor_idx, int64_t* n_survivors) {
+    if (!ctx || !c || n_shots < 0 || !shot_off || !survive_bits || !n_survivors)
+        return set_error(MSC_E_INVALID, "null argument");
+    if (n_shots > kNoAllocShots)
+        return set_error(MSC_E_INVALID, "msc_prescreen_noalloc takes at most 2^26 shots per call");
+    if (c->words > 8) return set_error(MSC_E_INVALID, "more than 512 decided measurements");
+    *n_survivors = 0;
+    if (n_shots == 0) return MSC_OK;
+    if (c->dev != ctx->device || !c->d_sig || !c->d_kind)
+        return set_error(MSC_E_STATE, "the circuit's tables are not on this device yet "
+                                      "(msc_circuit_calibrate or msc_prescreen uploads them)");
+    MSC_HIP(hipSetDevice(ctx->device));
+    int64_t* fixed = nullptr;
+    MSC_HIP(prescreen_noalloc_scratch(ctx->device, &fixed));
+    return screen_into(ctx, c, n_shots, shot_off, chan, pauli, survive_bits, survivor_idx,
+                       fixed, prescreen_tmp_words(n_shots), n_survivors);
 }
 
 // The Bin(M, p) cumulative table on the device, uploaded when (M, p) changes.

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "kernels.h"
 
@@ -229,6 +230,37 @@ hipError_t launch_validate_csr(int32_t n_channels, int64_t n, const int64_t* off
     hipLaunchKernelGGL(validate_kernel, grid, dim3(PT), 0, s, n_channels, n, off, chan, pauli,
                        kind, flag);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fixed scratch of msc_prescreen_noalloc: the block counts and their scan
+// (one word per 256 shots and the total) and the CSR flag, for at most
+// kNoAllocShots shots.  Each device holds its own copy until the process
+// ends.  Host code never passes `scratch` itself to a kernel (on the host it
+// is only a stand-in symbol): the device address is resolved once per device
+// with hipGetSymbolAddress and that pointer is used everywhere.
+namespace {
+constexpr int64_t kNoAllocWords = kNoAllocShots / PT + 2;
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) int64_t scratch[kNoAllocWords];
+
+static std::mutex g_scratch_mu;
+static int64_t* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t prescreen_noalloc_scratch(int device, int64_t** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = static_cast<int64_t*>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
 }
 
 }  // namespace msc

@@ -1,15 +1,15 @@
 """Benchmark of the batched exact-MPS cultivation-shot path on one MI355X.
 
-A step is one pass of the hot path over one batch of shots: subset-sampled
-faults drawn on the GPU from the seed (Section 4.1), the bit-exact offline
-screen over the batch, batched mixed-precision MPS simulation (FP32
-contractions, FP64 SVD, norms and probabilities) of the survivors, and the
+A step is one pass of the hot path over one batch of shots, one library
+call on one HIP stream: subset-sampled faults drawn on the GPU from the
+seed (Section 4.1), the bit-exact offline screen over the batch, batched
+mixed-precision MPS simulation (FP32 contractions, FP64 SVD, norms and
+probabilities) of the survivors in one persistent launch, and the
 per-weight bin sums that feed Eq. (reweight).  Workload: the 49-qubit
 rotated d=5 circuit (6 noisy rounds, two transversal T layers), p = 1e-3,
-4096 shots per batch, chi_max = 256.  Steps run on --streams host threads,
-each with its own context and HIP stream, so the long-running shots of one
-step overlap the next steps (a shot's latency, not the GPU's capacity, sets
-the length of a single step).
+chi_max = 256, 2^19 shots per step (128 batches of the workload's 4096
+shots; one launch long enough that the tail of its longest shots is a few
+percent, so the rate does not depend on the step count).
 
 The MPS layout is the one the qubit-order search finds from the snake
 order before the timed steps (--order-search 0 keeps the snake order); the
@@ -18,9 +18,11 @@ paper likewise reports its MPS runs on the best layout of its search.
 Also measured on the same GPU and shot list: the plain FP64 path one shot
 per launch (bounded sample, scaled), the FP32-vs-FP64 probability error,
 the CAMPS engine on the same survivors, the space-time accounting mode,
-the fixed-shape chi = 256 MFMA contraction, and the CPU oracle timed on the
-host (bounded sample); likelihood-ratio intervals of the reported rates
-come from the timed shots.  Prints one JSON line.
+the fixed-shape chi = 256 MFMA contraction, the offline screen at scale,
+the batched engine for large two-site updates on the bond-64 and bond-128
+workloads (with the autotuned tile shapes), and the CPU oracle timed on the
+host (bounded sample, one core and all cores); likelihood-ratio intervals
+of the reported rates come from the timed shots.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -37,8 +39,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_FP64_VECTOR = 78.6     # TFLOP/s, MI355X
-PEAK_FP32_MFMA = 157.3      # TFLOP/s, MI355X dense
+PEAK_FP64 = 78.6            # TFLOP/s, MI355X, FP64 vector and matrix
+PEAK_FP32 = 157.3           # TFLOP/s, MI355X, FP32 vector and dense matrix
 PEAK_BF16_MFMA = 2500.0     # TFLOP/s, MI355X dense (BF16x3 does 3 products per product)
 SEED = 0x5EED0003
 SEED_P5E4 = 0x5EED0013
@@ -53,11 +55,10 @@ def log(*a):
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=192,
-                    help="timed steps; with 8 in flight, the fill and drain of the stream "
-                         "pipeline are a few percent of 192 steps")
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--shots", type=int, default=4096)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--shots", type=int, default=1 << 19,
+                    help="shots per step (one library call, one shot-kernel launch)")
     ap.add_argument("--p", type=float, default=1e-3)
     ap.add_argument("--chi-max", type=int, default=256)
     ap.add_argument("--fp64-sample", type=int, default=48,
@@ -77,16 +78,17 @@ def main() -> int:
                          "--order-search evaluations each")
     ap.add_argument("--order-seed", type=lambda x: int(x, 0), default=ORDER_SEED)
     ap.add_argument("--lds-width", type=int, default=0)
-    ap.add_argument("--slots", type=int, default=192,
+    ap.add_argument("--slots", type=int, default=0,
                     help="persistent workgroups (MPS slots) per context; 0 = one per "
-                         "resident workgroup of the GPU (1024: four per CU).  With 16 "
-                         "contexts in flight, 192 slots of 51 MB (chi_max = 256) each "
-                         "keep the arenas at 157 GB of the 288 GB")
-    ap.add_argument("--streams", type=int, default=16,
-                    help="steps in flight: each host thread runs whole steps on its own "
-                         "context (HIP stream), so one step's long-running shots overlap "
-                         "the next steps' work (16 measured best: 8 runs 12 %% slower, 24 "
-                         "or more exceed the hardware queues)")
+                         "resident workgroup of the GPU (1024: four per CU; 51 MB each at "
+                         "chi_max = 256)")
+    ap.add_argument("--streams", type=int, default=1,
+                    help="steps in flight, each on its own context and HIP stream (one "
+                         "launch of 2^19 shots fills the GPU; two in flight measured slower)")
+    ap.add_argument("--cpu-procs", type=int, default=0,
+                    help="processes of the all-core CPU baseline (0: os.cpu_count())")
+    ap.add_argument("--engine-shots", type=int, default=2048,
+                    help="shots of the 81-qubit engine lines (1024 on the rainbow layout)")
     ap.add_argument("--no-prefix", action="store_true",
                     help="start every shot from |0...0> instead of forking it from the "
                          "noiseless-run checkpoint before its first fault")
@@ -171,13 +173,21 @@ def main() -> int:
         return st, bins
 
     def timed(first, steps, p=args.p, seed=SEED):
-        """Steps first .. first+steps-1 over the S contexts; (wall s, results)."""
+        """Steps first .. first+steps-1 over the S contexts, each context
+        taking the next step as it finishes one; (wall s, results)."""
         out = [None] * steps
         errors = []
+        nxt = [0]
+        lock = threading.Lock()
 
         def worker(t):
             try:
-                for i in range(t, steps, S):
+                while True:
+                    with lock:
+                        i = nxt[0]
+                        nxt[0] += 1
+                    if i >= steps:
+                        return
                     out[i] = step(ctxs[t], first + i, p, seed)
             except BaseException as e:    # re-raised by the main thread
                 errors.append(e)
@@ -221,10 +231,12 @@ def main() -> int:
     flops = [st["flops"] for st in sts]
     n2q = [st["n2q"] for st in sts]
     chi_peak = max(st["chi_peak"] for st in sts)
-    # roofline of the shot kernel: algorithmic flops per launch over the
-    # launch's average duration (HIP events on its context's stream); the
-    # launches of overlapping steps share the GPU, so the whole-job rate
-    # (all flops over the timed wall time) is reported beside it
+    # roofline of the shot kernel: algorithmic flops of a launch (the
+    # library's per-update count at the realised shapes: contraction, Gram,
+    # projection, eigensolve; SURVEY's per-update model) over the launch's
+    # duration (HIP events on the step's stream around the shot kernel).
+    # With one step in flight the launches do not overlap, so this is the
+    # rate the kernel trace of the same command gives per launch.
     achieved = float(np.mean(flops)) / (float(np.mean(sim_ms)) * 1e-3) / 1e12
     achieved_job = sum(flops) / wall / 1e12
     sweeps = sum(st["sweeps"] for st in sts)
@@ -258,15 +270,15 @@ def main() -> int:
                      "renormalisation, measurement probabilities and P_acc",
         "data": "synthetic: seeded cultivation-like circuit and seeded subset-sampled faults",
         "config": {"workload": "rotated d=5 cultivation-like circuit, 49 qubits (25 data + 24 "
-                               "ancilla), 6 noisy rounds, two T layers; p=1e-3 "
-                               "depolarising; faults w~Bin(M,p), seed 0x5EED0003; 4096 shots "
-                               "per batch (step); GPU fault sampling + offline screen + batched "
-                               "MPS, chi_max=256; up to steps_in_flight steps overlap",
+                               "ancilla), 6 noisy rounds, two T layers; p=1e-3 depolarising; "
+                               "faults w~Bin(M,p), seed 0x5EED0003; 2^19 shots per step (128 "
+                               "batches of 4096): GPU fault sampling + offline screen + "
+                               "batched MPS (one persistent launch), chi_max=256",
                    "layout": "snake" if order is None else "searched from the snake order",
                    "shots_per_step": n, "chi_max": args.chi_max, "p": args.p,
-                   "n_channels": M, "twosite_updates_per_full_shot": info["n_twosite"]},
+                   "n_channels": M, "twosite_updates_per_full_shot": info["n_twosite"],
+                   "steps_in_flight": S},
         "survivors_per_step": float(np.mean(n_surv)),
-        "steps_in_flight": S,
         "prefix_sharing": None if args.no_prefix else {
             "checkpoint_build_ms": prefix_ms,
             "note": "shots fork from checkpoints of the noiseless run taken before their "
@@ -284,12 +296,14 @@ def main() -> int:
                       "sample_mean": float(np.mean(sample_ms))},
         "roofline": {"bound": "alu",
                      "kernel": f"mps_kernel<float,{64 if args.lds_width == 64 else 32}>",
-                     "achieved": achieved, "peak": PEAK_FP64_VECTOR, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_VECTOR, "traffic": measured_traffic(layout_key),
+                     "achieved": achieved, "peak": PEAK_FP32, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32, "traffic": measured_traffic(layout_key),
                      "launch_ms": float(np.mean(sim_ms)),
+                     "flops_per_launch": float(np.mean(flops)),
                      "achieved_whole_job": achieved_job,
-                     "frac_whole_job": achieved_job / PEAK_FP64_VECTOR,
-                     "flops_per_launch": float(np.mean(flops))},
+                     "frac_whole_job": achieved_job / PEAK_FP32,
+                     "note": "FP32 vector peak: the in-kernel contraction is FP32; the "
+                             "Jacobi SVD, norms and projection run in FP64 (78.6 TFLOP/s)"},
         "estimates": {str(p): e for p, e in zip([5e-4, 1e-3, 2e-3], est)},
         "intervals_r100": intervals,
         "order_search": order_info,
@@ -297,14 +311,17 @@ def main() -> int:
 
     if not args.no_extras:
         # the second error rate of the workload (its own seed), same pipeline
-        wall2, per2 = timed(0, max(S, args.steps // 2), 5e-4, SEED_P5E4)
+        wall2, per2 = timed(0, max(S, args.steps // 4), 5e-4, SEED_P5E4)
         result["value_p_5e-4"] = {"value": len(per2) * n / wall2, "unit": "shots/s",
                                   "steps": len(per2), "seed": hex(SEED_P5E4),
                                   "survivors_per_step": float(np.mean(
                                       [q[0]["n_survivors"] for q in per2]))}
-        # plain FP64 path, one shot per launch, on survivors of the first timed batch
-        off, ch, pa = sample(ctx, warmup)
+        # plain FP64 path, one shot per launch, on survivors of the first 4096
+        # shots of the first timed batch (the workload's batch of 4096)
+        off, ch, pa = msc.sample_faults_device(ctx, circ, SEED, warmup * n, 4096, p=args.p)
+        sub_sample_ms = ctx.last_kernel_ms("sample")
         _, idx0, _ = msc.prescreen(ctx, circ, off, ch, pa)
+        sub_screen_ms = ctx.last_kernel_ms("prescreen")
         res32 = msc.results_numpy(msc.simulate(ctx, circ, off, ch, pa, shot_idx=idx0,
                                                precision=msc.MSC_FP32, chi_max=args.chi_max,
                                                lds_width=args.lds_width,
@@ -359,9 +376,9 @@ def main() -> int:
         outc = msc.results_numpy(msc.simulate_camps(ctx, circ_cs, off, ch, pa, shot_idx=idx0,
                                                     prefix=not args.no_prefix))
         camps_ms = ctx.last_kernel_ms("camps")
-        step_c = camps_ms + float(np.mean(screen_ms)) + float(np.mean(sample_ms))
+        step_c = camps_ms + sub_screen_ms + sub_sample_ms   # the 4096-shot batch
         dpc = np.abs(outc["p_acc"] - out64["p_acc"])
-        result["camps"] = {"shots_per_s": n / (step_c * 1e-3), "kernel_ms": camps_ms,
+        result["camps"] = {"shots_per_s": 4096 / (step_c * 1e-3), "kernel_ms": camps_ms,
                            "survivors": int(idx0.numel()),
                            "residual_chi_peak_max": int(outc["chi_peak"].max()),
                            "residual_chi_peak_mean": float(outc["chi_peak"].mean()),
@@ -380,8 +397,10 @@ def main() -> int:
         st_s = np.zeros((wmax + 1, len(segs)))
         t0 = time.perf_counter()
         n_st = 4
+        n4 = 4096
         for b in range(n_st):
-            bb, sb = msc.run_batch(ctx, circ, SEED, (warmup + b) * n, n, args.p, n_bins=wmax + 1,
+            bb, sb = msc.run_batch(ctx, circ, SEED, warmup * n + b * n4, n4, args.p,
+                                   n_bins=wmax + 1,
                                    precision=msc.MSC_FP32, chi_max=args.chi_max,
                                    lds_width=args.lds_width, prefix=not args.no_prefix,
                                    space_time=True)
@@ -395,8 +414,8 @@ def main() -> int:
             "noisy_volume_if_no_shot_stopped": float(sum(
                 int(g["n_qubits"]) * int(g["depth"]) for g in segs if g["noisy"])),
             "reach_per_segment": [float(x) for x in reach],
-            "segments": len(segs), "shots": n_st * n,
-            "shots_per_s_single_stream": n_st * n / t_st}
+            "segments": len(segs), "shots": n_st * n4,
+            "shots_per_s_single_stream": n_st * n4 / t_st}
 
         # fixed-shape chi = 256 two-site contraction on MFMA, FP32 and BF16x3
         from workloads.tensors import random_twosite
@@ -406,7 +425,7 @@ def main() -> int:
         dB = torch.from_numpy(B).cuda().repeat(batch, 1, 1, 1).contiguous()
         dG = torch.from_numpy(G).cuda()
         outs = {}
-        for name, prec, peak in (("fp32", msc.MSC_FP32, PEAK_FP32_MFMA),
+        for name, prec, peak in (("fp32", msc.MSC_FP32, PEAK_FP32),
                                  ("bf16x3", msc.MSC_BF16X3, PEAK_BF16_MFMA / 3.0)):
             th = torch.empty(batch * 2 * (2 * chi) ** 2, dtype=torch.float32, device="cuda")
             msc.twosite_contract(ctx, chi, batch, dA, dB, dG, th, precision=prec)
@@ -455,7 +474,7 @@ def main() -> int:
         circ.calibrate(ctx)
         for b in range(S):
             step(ctxs[b], b)
-        k2 = max(S, args.steps // 2)
+        k2 = max(S, args.steps // 4)
         wall_s, per_s = timed(warmup, k2)
         result["value_snake_layout"] = {
             "value": k2 * n / wall_s, "unit": "shots/s", "steps": k2,
@@ -464,8 +483,13 @@ def main() -> int:
             "launch_ms": float(np.mean([q[0]["ms_simulate"] for q in per_s]))}
         circ = circ_searched
 
+    if not args.no_extras:
+        result["large_bond_engine"] = engine_lines(msc, ctx, args)
+
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(cc.text, args, n)
+        log("CPU oracle baseline")
+        result["cpu_baseline"] = cpu_baseline(cc.text, None if order is None else list(order),
+                                              args, warmup * n)
 
     for c in ctxs:
         c.close()
@@ -520,9 +544,89 @@ def measured_traffic(layout_key: str):
     return float(vals["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(text: str, args, n: int) -> dict:
-    """The oracle (offline screen + FP64 numpy MPS) on the first shots of
-    the first timed batch, one host thread."""
+def engine_lines(msc, ctx, args) -> dict:
+    """The batched engine for large two-site updates (ragged MFMA
+    contractions, FP64 Gram matrices on MFMA, FP64 eigen-decomposition of
+    the overlapping blocks) on the workloads whose bonds reach 64 (81
+    qubits, snake layout) and 128 (49 qubits, rainbow layout): tile shapes
+    from the autotuner, the engine taking every update wider than 64, and
+    the shot kernel alone beside it (large_side = -1).  Rates are the
+    shots of the call over its kernel time (HIP events)."""
+    import tempfile
+
+    from workloads.circuits import config_circuit
+
+    log("autotune")
+    cache = os.path.join(tempfile.mkdtemp(), "tune.json")
+    tune = {name: msc.autotune(ctx, pr, reps=3, cache_path=cache)
+            for name, pr in (("fp32", msc.MSC_FP32), ("bf16x3", msc.MSC_BF16X3),
+                             ("fp64", msc.MSC_FP64))}
+    peak = {msc.MSC_FP32: PEAK_FP32, msc.MSC_BF16X3: PEAK_BF16_MFMA / 3.0, msc.MSC_FP64: PEAK_FP64}
+    pname = {msc.MSC_FP32: "fp32", msc.MSC_BF16X3: "bf16x3", msc.MSC_FP64: "fp64"}
+    out = {"autotune": tune, "note": "chi_max 256: the realised bonds are 64 and 128 and the "
+                                     "cap never binds (one 1024 run shows the same result)"}
+    for name, wl, nshots, seed, precs in (
+            ("81q_snake_bond64", "c4", args.engine_shots, 0x5EED0004,
+             (msc.MSC_FP32, msc.MSC_BF16X3)),
+            ("49q_rainbow_bond128", "c3_rainbow", args.engine_shots // 2, 0x5EED0023,
+             (msc.MSC_FP32,))):
+        log(f"engine {name}")
+        c = msc.Circuit(config_circuit(wl).text)
+        c.calibrate(ctx)
+        off, ch, pa = msc.sample_faults_device(ctx, c, seed, 0, nshots, p=args.p)
+        _, idx, cnt = msc.prescreen(ctx, c, off, ch, pa)
+        line = {"shots": nshots, "survivors": cnt, "p": args.p, "seed": hex(seed),
+                "noiseless_chi_peak": c.noiseless()["chi_peak"]}
+        ref = None
+        for pr in precs:
+            for mode, ls in (("engine", 64), ("shot_kernel_alone", -1)):
+                if pr != msc.MSC_FP32 and mode != "engine":
+                    continue
+                res = msc.results_numpy(msc.simulate(ctx, c, off, ch, pa, shot_idx=idx,
+                                                     precision=pr, chi_max=256, large_side=ls,
+                                                     autotune_cache=cache, prefix=True))
+                st = ctx.engine_stats()
+                ms = st["total_ms"]
+                rec = {"shots_per_s": nshots / (ms * 1e-3), "kernel_ms": ms,
+                       "gate_updates_per_s": float(res["n2q"].sum()) / (ms * 1e-3),
+                       "chi_peak": int(res["chi_peak"].max()),
+                       "status_or": int(np.bitwise_or.reduce(res["status"]))}
+                if mode == "engine":
+                    ct = st["contract_flops"] / max(st["contract_ms"], 1e-9) / 1e9
+                    gt = st["gram_flops"] / max(st["gram_ms"], 1e-9) / 1e9
+                    rec.update({"stats": st,
+                                "contraction": {"achieved": ct, "peak": peak[pr],
+                                                "unit": "TFLOP/s", "frac": ct / peak[pr]},
+                                "gram_fp64": {"achieved": gt, "peak": PEAK_FP64,
+                                              "unit": "TFLOP/s", "frac": gt / PEAK_FP64}})
+                if ref is None:
+                    ref = res
+                else:
+                    acc = ref["p_acc"] > 0
+                    rec["max_rel_p_acc_vs_first"] = float(
+                        (np.abs(res["p_acc"] - ref["p_acc"])[acc] / ref["p_acc"][acc]).max())
+                line[f"{pname[pr]}_{mode}"] = rec
+        out[name] = line
+    # the 81-qubit workload at the configured cap of 1024 (1.36 GB slots, 64 of them)
+    c = msc.Circuit(config_circuit("c4").text)
+    c.calibrate(ctx)
+    off, ch, pa = msc.sample_faults_device(ctx, c, 0x5EED0004, 0, args.engine_shots, p=args.p)
+    _, idx, cnt = msc.prescreen(ctx, c, off, ch, pa)
+    res = msc.results_numpy(msc.simulate(ctx, c, off, ch, pa, shot_idx=idx,
+                                         precision=msc.MSC_FP32, chi_max=1024, large_side=64,
+                                         n_slots=64, autotune_cache=cache, prefix=True))
+    ms = ctx.engine_stats()["total_ms"]
+    out["81q_snake_bond64"]["fp32_engine_chi_max_1024"] = {
+        "shots_per_s": args.engine_shots / (ms * 1e-3), "kernel_ms": ms, "slots": 64,
+        "chi_peak": int(res["chi_peak"].max())}
+    return out
+
+
+def _oracle_shots(job):
+    """Worker of the all-core baseline: the oracle on shots first ..
+    first+k-1 (fault sampling, screen, MPS), one thread; returns the number
+    simulated after the screen."""
+    text, order, seed, first, k, p = job
     from threadpoolctl import threadpool_limits
 
     from oracle import mps as omps
@@ -531,25 +635,44 @@ def cpu_baseline(text: str, args, n: int) -> dict:
     from oracle.ir import parse
 
     circ = parse(text)
-    k = args.cpu_sample
+    if order is not None:
+        circ.order = list(order)
     with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
         dec, fl = ops.analyse(circ)
-        t_tab = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        off, ch, pa = osamp.sample_csr(circ, SEED, args.warmup * n, k, p=args.p)
-        shots = osamp.csr_to_dicts(off, ch, pa)
+        off, ch, pa = osamp.sample_csr(circ, seed, first, k, p=p)
         sims = 0
-        for f in shots:
+        for f in osamp.csr_to_dicts(off, ch, pa):
             if not ops.discard(dec, fl, f):
                 omps.run_shot(circ, f)
                 sims += 1
-        dt = time.perf_counter() - t0
-    return {"value": k / dt, "unit": "shots/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {k} shots of the first timed batch: fault sampling, screen, "
-                      f"MPS ({sims} simulated after the oracle's screen; screen table build "
-                      f"{t_tab:.2f}s excluded)",
-            "seconds": dt}
+    return sims
+
+
+def cpu_baseline(text: str, order, args, first: int) -> dict:
+    """The oracle (offline screen + FP64 numpy MPS) on the GPU's layout, on
+    the first shots of the first timed batch (shot index `first` on): one
+    process with one thread, then every core (one single-threaded process
+    per core, each on its own run of the following shots)."""
+    import multiprocessing as mp
+
+    k = args.cpu_sample
+    t0 = time.perf_counter()
+    sims1 = _oracle_shots((text, order, SEED, first, k, args.p))
+    dt1 = time.perf_counter() - t0
+    procs = args.cpu_procs or os.cpu_count() or 1
+    jobs = [(text, order, SEED, first + k * (1 + i), k, args.p) for i in range(procs)]
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(procs) as pool:
+        simsn = sum(pool.map(_oracle_shots, jobs))
+    dtn = time.perf_counter() - t0
+    return {"value": k * procs / dtn, "unit": "shots/s", "cores": procs, "kind": "oracle",
+            "sample": f"shots {first}.. of the first timed batch on the benchmark's layout: "
+                      f"fault sampling, screen, MPS; {procs} processes x {k} shots "
+                      f"({simsn} simulated after the oracle's screen), process start-up "
+                      f"included",
+            "seconds": dtn,
+            "single_core": {"value": k / dt1, "cores": 1, "shots": k, "simulated": sims1,
+                            "seconds": dt1}}
 
 
 if __name__ == "__main__":

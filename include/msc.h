@@ -103,7 +103,8 @@ typedef struct {
     int32_t precision;    /* msc_precision                                   */
     int32_t chi_max;      /* bond cap (must not bind in the exact regime)    */
     double tau_trunc;     /* keep sigma_i > tau_trunc * sigma_0; <= 0: auto
-                             (1e-12 for MSC_FP64, 1e-5 for MSC_FP32)          */
+                             (1e-12 for MSC_FP64, 1e-5 for MSC_FP32, 1e-4
+                             for MSC_BF16X3, above its ~2^-16 product error) */
     double tau_rej;       /* reject when p(e_m) < tau_rej (default 1e-6)     */
     double tau_fail;      /* logical failure iff 1 - f > tau_fail (1e-4)     */
     int32_t n_slots;      /* persistent workgroups; 0 = auto                 */
@@ -122,9 +123,9 @@ typedef struct {
                              BF16x3 splits for MSC_BF16X3), FP64 Gram
                              matrices on MFMA and FP64 eigen-decompositions of
                              their overlapping blocks, then the shots resume.
-                             0: 64; -1: off (the shot kernel factorises every
-                             update itself, in HBM scratch when wide); any
-                             other value must be at least 2.                */
+                             0: 256; -1: off (the shot kernel factorises
+                             every update itself, in HBM scratch when wide);
+                             any other value must be at least 2.            */
     int32_t use_graphs;   /* 1: one engine round (its ~10 launches) is
                              captured once as a HIP graph and replayed      */
     int32_t reserved;     /* must be 0                                       */
@@ -213,6 +214,12 @@ typedef struct {
     double factor_ms;       /* kernel time of the factor steps              */
     double shot_ms;         /* kernel time of the shot kernel's launches     */
     double total_ms;        /* all of the call's shot work                   */
+    int64_t factor_lds;     /* factor steps whose overlapping vectors were
+                               diagonalised in LDS (at most 64 of them)      */
+    int64_t factor_wide;    /* factor steps with more: one-sided Jacobi in
+                               the slot's workspace                          */
+    int64_t overlapping;    /* overlapping vectors, summed over the updates  */
+    int64_t sweeps;         /* Jacobi sweeps, summed                         */
 } msc_engine_stats;
 
 int msc_ctx_engine_stats(msc_ctx* ctx, msc_engine_stats* out);
@@ -400,6 +407,31 @@ int msc_simulate_camps(msc_ctx* ctx, const msc_circuit* c, const msc_sim_opts* o
    image of X1^x1 Z1^z1 X2^x2 Z2^z2 in the same bits plus its phase
    exponent of i in bits 4-5.                                              */
 int msc_camps_candidates(double* dmat, uint8_t* dtab, int32_t* n_out);
+
+/* ---------------------------------------------------------------------- */
+/* Autotuning of the batched engine's tile shapes.                         */
+
+/* One bucket's choice: theta sides of the bucket's representative update,
+   the contraction tile (rows of (a, i) x b values) and Gram tile chosen,
+   and their timings per launch (microseconds, best of `reps`).          */
+typedef struct {
+    int32_t bucket, side, batch, rows, b, gram;
+    double contract_us, gram_us;
+} msc_tune_entry;
+
+/* Times every tile shape the library has for `precision` (MSC_FP32 or
+   MSC_FP64; MSC_BF16X3 tunes the FP32 contraction's shapes with the
+   bf16 split) on a synthetic batch of parked updates per bucket of theta
+   sides (<= 128, <= 256, <= 512, larger; chi_l = chi_m = chi_r = 64, 128,
+   256, 512, random normalised tensors, CX gate), `reps` launches each,
+   and keeps the fastest contraction and Gram tiles per bucket.  out (host,
+   4 entries, optional) receives the choices.  If `cache_path` is non-NULL
+   the choices are written there as JSON: {"device": ..., "entries":
+   [{"precision", "bucket", "side", "rows", "b", "gram", "contract_us",
+   "gram_us"}, ...]}, replacing the file's entries of this precision and
+   keeping the others; msc_sim_opts.autotune_cache reads it back.         */
+int msc_autotune(msc_ctx* ctx, int32_t precision, int32_t reps, const char* cache_path,
+                 msc_tune_entry* out);
 
 /* ---------------------------------------------------------------------- */
 /* Two-site contraction on MFMA (Section 3.1), standalone.                 */

@@ -12,7 +12,7 @@ import ctypes as C
 
 import numpy as np
 
-from ._lib import (BatchStats, EngineStats, MSC_BF16X3, MSC_FP32, MSC_FP64, MSC_STAT_PACC,  # noqa: F401
+from ._lib import (BatchStats, EngineStats, TuneEntry, MSC_BF16X3, MSC_FP32, MSC_FP64, MSC_STAT_PACC,  # noqa: F401
                    MSC_ORDER_COST_MOVE, MSC_ORDER_COST_PSWAP, MSC_ORDER_COST_TWOSITE,
                    MSC_STAT_PLE, SEGMENT_DTYPE, SHOT_CHI_CAP, SHOT_DONE, SHOT_DTYPE, SHOT_NOCONV,
                    SHOT_REJECTED, CircuitInfo, Estimate, Interval, MscError, SimOpts, _check,
@@ -21,7 +21,8 @@ from ._lib import (BatchStats, EngineStats, MSC_BF16X3, MSC_FP32, MSC_FP64, MSC_
 __all__ = ["Ctx", "Circuit", "sample_faults", "sample_faults_device", "prescreen", "simulate",
            "simulate_camps", "camps_candidates",
            "run_batch", "reweight", "profile_loglik", "lr_interval", "ratio_credible",
-           "loss_factor", "expected_volume", "order_search", "twosite_contract", "prescreen_tables", "version", "MscError",
+           "loss_factor", "expected_volume", "order_search", "twosite_contract", "prescreen_tables",
+           "autotune", "version", "MscError",
            "MSC_FP64", "MSC_FP32", "MSC_BF16X3", "order_cost", "MSC_STAT_PACC", "MSC_STAT_PLE", "SHOT_DTYPE"]
 
 
@@ -304,6 +305,15 @@ def twosite_contract(ctx: Ctx, chi: int, batch: int, A, B, gate, theta,
                      precision: int = MSC_FP32) -> None:
     _check(lib().msc_twosite_contract(ctx.h, precision, chi, batch, _ptr(A), _ptr(B), _ptr(gate),
                                       _ptr(theta)))
+
+
+def autotune(ctx: Ctx, precision: int = MSC_FP32, reps: int = 5, cache_path=None) -> list:
+    """msc_autotune: the engine's fastest tile shapes per bucket of theta
+    sides (written to ``cache_path`` as JSON if given)."""
+    out = (TuneEntry * 4)()
+    path = None if cache_path is None else str(cache_path).encode()
+    _check(lib().msc_autotune(ctx.h, precision, reps, path, C.cast(out, C.c_void_p)))
+    return [{f: getattr(o, f) for f, _ in TuneEntry._fields_} for o in out]
 
 
 def reweight(bin_n, bin_acc, bin_fail, M: int, p_grid, bin_acc2=None, bin_fail2=None) -> list:

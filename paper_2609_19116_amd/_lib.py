@@ -79,7 +79,15 @@ assert SHOT_DTYPE.itemsize == C.sizeof(ShotResult) == 64
 class EngineStats(C.Structure):
     _fields_ = [("rounds", C.c_int64), ("updates", C.c_int64), ("contract_flops", C.c_double),
                 ("gram_flops", C.c_double), ("contract_ms", C.c_double), ("gram_ms", C.c_double),
-                ("factor_ms", C.c_double), ("shot_ms", C.c_double), ("total_ms", C.c_double)]
+                ("factor_ms", C.c_double), ("shot_ms", C.c_double), ("total_ms", C.c_double),
+                ("factor_lds", C.c_int64), ("factor_wide", C.c_int64), ("overlapping", C.c_int64),
+                ("sweeps", C.c_int64)]
+
+
+class TuneEntry(C.Structure):
+    _fields_ = [("bucket", C.c_int32), ("side", C.c_int32), ("batch", C.c_int32),
+                ("rows", C.c_int32), ("b", C.c_int32), ("gram", C.c_int32),
+                ("contract_us", C.c_double), ("gram_us", C.c_double)]
 
 
 class Estimate(C.Structure):
@@ -133,6 +141,7 @@ _SIGS = {
     "msc_run_batch": (C.c_int, [_P, _P, C.POINTER(SimOpts), C.c_uint64, C.c_uint64, C.c_int64,
                                 C.c_double, C.c_int32, _P, C.POINTER(BatchStats), _P, _P]),
     "msc_twosite_contract": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, _P]),
+    "msc_autotune": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_char_p, _P]),
     "msc_simulate_camps": (C.c_int, [_P, _P, C.POINTER(SimOpts), C.c_int64, _P, _P, _P, _P,
                                      C.c_int64, _P]),
     "msc_camps_candidates": (C.c_int, [_P, _P, C.POINTER(C.c_int32)]),

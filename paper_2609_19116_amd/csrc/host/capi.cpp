@@ -347,6 +347,7 @@ struct RunCfg {
 static void default_tiles(int precision, LxTiles* t) {
     for (int b = 0; b < kLxBuckets; ++b) {
         if (precision == MSC_FP64) t[b] = b == 0 ? LxTiles{32, 32, 32} : LxTiles{64, 32, 64};
+        else if (precision == MSC_BF16X3) t[b] = b == 0 ? LxTiles{64, 32, 64} : LxTiles{64, 64, 64};
         else t[b] = b == 0 ? LxTiles{64, 32, 64} : LxTiles{128, 64, 64};
     }
 }
@@ -477,12 +478,13 @@ static int enqueue_shots(msc_ctx* ctx, const msc_circuit* c, const RunCfg& cfg, 
         if ((rc = ctx_buf(ctx, "lx_state", static_cast<size_t>(n_slots) * sizeof(ShotState), &dstate))) return rc;
         if ((rc = ctx_buf(ctx, "lx_count", sizeof(int32_t), &dcount))) return rc;
         if ((rc = ctx_buf(ctx, "lx_list", static_cast<size_t>(n_slots) * sizeof(int32_t), &dlist))) return rc;
-        if ((rc = ctx_buf(ctx, "lx_flops", 2 * sizeof(double), &dflops))) return rc;
+        if ((rc = ctx_buf(ctx, "lx_flops", 2 * sizeof(double) + 4 * sizeof(uint64_t), &dflops))) return rc;
         a.park_side = cfg.park_side;
         a.state = static_cast<ShotState*>(dstate);
         a.park_count = static_cast<int32_t*>(dcount);
         a.park_list = static_cast<int32_t*>(dlist);
         MSC_HIP(launch_lx_reset(a.state, n_slots, a.park_count, static_cast<double*>(dflops),
+                                reinterpret_cast<unsigned long long*>(static_cast<double*>(dflops) + 2),
                                 ctx->stream));
     }
     MSC_HIP(launch_order(n, n_dev, off, shot_idx, n_csr, chan,
@@ -541,6 +543,7 @@ static int enqueue_shots(msc_ctx* ctx, const msc_circuit* c, const RunCfg& cfg, 
             lx.gram_stride = lx_gram_doubles(S);
             lx.n_slots = n_slots;
             lx.flops = static_cast<double*>(dflops);
+            lx.counts = reinterpret_cast<unsigned long long*>(lx.flops + 2);
             fac.cap = a.cap;
             fac.chi_max = chi_max;
             fac.tau = cfg.tau;
@@ -581,10 +584,16 @@ static int enqueue_shots(msc_ctx* ctx, const msc_circuit* c, const RunCfg& cfg, 
         }
     }
     if (have_bufs) {
-        double fl[2] = {0.0, 0.0};
+        double fl[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // 2 flop sums, 4 counts
         MSC_HIP(hipMemcpy(fl, lx.flops, sizeof(fl), hipMemcpyDeviceToHost));
         es.contract_flops = fl[0];
         es.gram_flops = fl[1];
+        uint64_t cnt[4];
+        std::memcpy(cnt, fl + 2, sizeof(cnt));
+        es.factor_lds = static_cast<int64_t>(cnt[0]);
+        es.factor_wide = static_cast<int64_t>(cnt[1]);
+        es.overlapping = static_cast<int64_t>(cnt[2]);
+        es.sweeps = static_cast<int64_t>(cnt[3]);
     }
     return MSC_OK;
 }
@@ -792,11 +801,14 @@ static int read_tune_cache(const char* path, int precision, LxTiles* tiles) {
         if (pr == precision && bk >= 0 && bk < kLxBuckets) {
             LxTiles v[16];
             const int nvar = lx_tile_variants(precision, v, 16);
-            bool known = false;
-            for (int i = 0; i < nvar; ++i)
-                known |= v[i].cm_rows == rows && v[i].cm_b == b && v[i].gram == gram;
-            if (!known) return set_error(MSC_E_INVALID, "autotune cache names a tile shape this "
-                                                        "build does not have");
+            bool known_c = false, known_g = false;
+            for (int i = 0; i < nvar; ++i) {
+                known_c |= v[i].cm_rows == rows && v[i].cm_b == b;
+                known_g |= v[i].gram == gram;
+            }
+            if (!(known_c && known_g))
+                return set_error(MSC_E_INVALID, "autotune cache names a tile shape this build "
+                                                "does not have");
             tiles[bk] = LxTiles{static_cast<int32_t>(rows), static_cast<int32_t>(b),
                                 static_cast<int32_t>(gram)};
         }
@@ -808,7 +820,7 @@ static int read_tune_cache(const char* path, int precision, LxTiles* tiles) {
 // The run options of msc_sim_opts (validated), with the engine's tile shapes
 // from the autotune cache when one is named.
 static int sim_cfg(const msc_sim_opts* o, RunCfg* cfg) {
-    if (o->precision != MSC_FP64 && o->precision != MSC_FP32)
+    if (o->precision != MSC_FP64 && o->precision != MSC_FP32 && o->precision != MSC_BF16X3)
         return set_error(MSC_E_INVALID, "unknown precision");
     if (o->chi_max < 1 || o->chi_max > kMaxChiKernel)
         return set_error(MSC_E_INVALID, "chi_max must be in [1, 1024]");
@@ -822,12 +834,14 @@ static int sim_cfg(const msc_sim_opts* o, RunCfg* cfg) {
     if (o->reserved != 0) return set_error(MSC_E_INVALID, "reserved must be 0");
     cfg->precision = o->precision;
     cfg->chi_max = o->chi_max;
-    cfg->tau = o->tau_trunc > 0 ? o->tau_trunc : (o->precision == MSC_FP64 ? 1e-12 : 1e-5);
+    cfg->tau = o->tau_trunc > 0 ? o->tau_trunc
+                                : (o->precision == MSC_FP64 ? 1e-12
+                                   : o->precision == MSC_FP32 ? 1e-5 : 1e-4);
     cfg->tau_rej = o->tau_rej > 0 ? o->tau_rej : 1e-6;
     cfg->tau_fail = o->tau_fail > 0 ? o->tau_fail : 1e-4;
     cfg->n_slots = o->n_slots;
     cfg->lds_width = o->lds_width == 64 ? 64 : 32;
-    cfg->park_side = o->large_side == -1 ? 0 : o->large_side == 0 ? 64 : o->large_side;
+    cfg->park_side = o->large_side == -1 ? 0 : o->large_side == 0 ? 256 : o->large_side;
     cfg->graphs = o->use_graphs == 1;
     default_tiles(cfg->precision, cfg->tiles);
     if (o->autotune_cache) {
@@ -1352,6 +1366,190 @@ extern "C" int msc_camps_candidates(double* dmat, uint8_t* dtab, int32_t* n_out)
     *n_out = static_cast<int32_t>(t.size() / 16);
     if (dmat) std::copy(m.begin(), m.end(), dmat);
     if (dtab) std::copy(t.begin(), t.end(), dtab);
+    return MSC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuning of the engine's tile shapes
+
+// The raw text of each object in a JSON file's "entries" array with its
+// "precision" field (the cache format msc_autotune writes).
+static std::vector<std::pair<long, std::string>> cache_entries(const char* path) {
+    std::vector<std::pair<long, std::string>> out;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return out;
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+    std::fclose(f);
+    const size_t at = text.find("\"entries\"");
+    if (at == std::string::npos) return out;
+    size_t pos = text.find('[', at);
+    const size_t end = pos == std::string::npos ? pos : text.find(']', pos);
+    while (pos != std::string::npos && end != std::string::npos) {
+        const size_t o = text.find('{', pos);
+        if (o == std::string::npos || o > end) break;
+        const size_t cl = text.find('}', o);
+        if (cl == std::string::npos || cl > end) break;
+        const std::string obj = text.substr(o, cl - o + 1);
+        long pr = -1;
+        const size_t kp = obj.find("\"precision\"");
+        if (kp != std::string::npos) {
+            const size_t colon = obj.find(':', kp);
+            if (colon != std::string::npos) pr = std::strtol(obj.c_str() + colon + 1, nullptr, 10);
+        }
+        out.emplace_back(pr, obj);
+        pos = cl + 1;
+    }
+    return out;
+}
+
+extern "C" int msc_autotune(msc_ctx* ctx, int32_t precision, int32_t reps, const char* cache_path,
+                            msc_tune_entry* out) {
+    if (!ctx) return set_error(MSC_E_INVALID, "null context");
+    if (precision != MSC_FP32 && precision != MSC_FP64 && precision != MSC_BF16X3)
+        return set_error(MSC_E_INVALID, "unknown precision");
+    if (reps < 1 || reps > 1000) return set_error(MSC_E_INVALID, "reps must be in [1, 1000]");
+    MSC_HIP(hipSetDevice(ctx->device));
+    const size_t tsize = precision == MSC_FP64 ? sizeof(double) : sizeof(float);
+    LxTiles var[16];
+    const int nvar = lx_tile_variants(precision, var, 16);
+    const int sides[kLxBuckets] = {128, 256, 512, 1024};
+    const int batches[kLxBuckets] = {256, 96, 24, 6};
+    std::vector<double> g4(G4_COUNT * 32);
+    for (int g = 0; g < G4_COUNT; ++g) gate4_matrix(g, &g4[g * 32]);
+    msc_tune_entry res[kLxBuckets];
+    const int grid = ctx->n_cu * 4;
+    int rc;
+    for (int bk = 0; bk < kLxBuckets; ++bk) {
+        const int chi = sides[bk] / 2, N = batches[bk];
+        const int64_t site = 2ll * chi * chi;          // elements of one plane
+        const int64_t stride = 4 * site;               // two sites, two planes
+        std::vector<ShotState> st(N);
+        std::vector<int32_t> list(N);
+        for (int i = 0; i < N; ++i) {
+            st[i] = ShotState{};
+            st[i].status = kSlotParked;
+            st[i].k = 0;
+            st[i].dir = i & 1;
+            st[i].gate_id = G4_CX01;
+            st[i].chi[0] = st[i].chi[1] = st[i].chi[2] = chi;
+            list[i] = i;
+        }
+        // random tensors of unit scale from a fixed 64-bit LCG
+        std::vector<double> hd(static_cast<size_t>(N) * stride);
+        uint64_t x = 0x5EED0107ull;
+        for (double& v : hd) {
+            x = x * 6364136223846793005ull + 1442695040888963407ull;
+            v = static_cast<double>(static_cast<int64_t>(x >> 11) - (int64_t(1) << 52)) /
+                static_cast<double>(int64_t(1) << 52) / chi;
+        }
+        std::vector<float> hf;
+        if (precision != MSC_FP64) hf.assign(hd.begin(), hd.end());
+        const int64_t S = 2ll * chi;
+        void *dstate, *dcount, *dlist, *dplan, *darena, *dtheta, *dgram, *doff, *dhalf, *dg4, *dfl;
+        if ((rc = ctx_buf(ctx, "tune_state", N * sizeof(ShotState), &dstate))) return rc;
+        if ((rc = ctx_buf(ctx, "tune_count", sizeof(int32_t), &dcount))) return rc;
+        if ((rc = ctx_buf(ctx, "tune_list", N * sizeof(int32_t), &dlist))) return rc;
+        if ((rc = ctx_buf(ctx, "tune_plan", sizeof(LxPlan), &dplan))) return rc;
+        if ((rc = ctx_buf(ctx, "tune_arena", N * stride * tsize, &darena))) return rc;
+        if ((rc = ctx_buf(ctx, "tune_theta", N * 2 * S * S * tsize, &dtheta))) return rc;
+        if ((rc = ctx_buf(ctx, "tune_gram", N * lx_gram_doubles(S) * sizeof(double), &dgram))) return rc;
+        if ((rc = ctx_buf(ctx, "tune_off", 2 * sizeof(int64_t), &doff))) return rc;
+        if ((rc = ctx_buf(ctx, "tune_half", 2 * sizeof(int64_t), &dhalf))) return rc;
+        if ((rc = ctx_buf(ctx, "tune_g4", g4.size() * sizeof(double), &dg4))) return rc;
+        if ((rc = ctx_buf(ctx, "tune_flops", 6 * sizeof(double), &dfl))) return rc;
+        const int64_t off[2] = {0, 2 * site}, half[2] = {site, site};
+        const int32_t count = N;
+        MSC_HIP(hipMemcpy(dstate, st.data(), N * sizeof(ShotState), hipMemcpyHostToDevice));
+        MSC_HIP(hipMemcpy(dcount, &count, sizeof(count), hipMemcpyHostToDevice));
+        MSC_HIP(hipMemcpy(dlist, list.data(), N * sizeof(int32_t), hipMemcpyHostToDevice));
+        if (precision == MSC_FP64)
+            MSC_HIP(hipMemcpy(darena, hd.data(), hd.size() * sizeof(double), hipMemcpyHostToDevice));
+        else
+            MSC_HIP(hipMemcpy(darena, hf.data(), hf.size() * sizeof(float), hipMemcpyHostToDevice));
+        MSC_HIP(hipMemcpy(doff, off, sizeof(off), hipMemcpyHostToDevice));
+        MSC_HIP(hipMemcpy(dhalf, half, sizeof(half), hipMemcpyHostToDevice));
+        MSC_HIP(hipMemcpy(dg4, g4.data(), g4.size() * sizeof(double), hipMemcpyHostToDevice));
+        LxArgs la{};
+        la.state = static_cast<const ShotState*>(dstate);
+        la.park_count = static_cast<const int32_t*>(dcount);
+        la.park_list = static_cast<const int32_t*>(dlist);
+        la.plan = static_cast<LxPlan*>(dplan);
+        la.arena = darena;
+        la.slot_stride = stride;
+        la.site_off = static_cast<const int64_t*>(doff);
+        la.site_half = static_cast<const int64_t*>(dhalf);
+        la.g4 = static_cast<const double*>(dg4);
+        la.theta = dtheta;
+        la.theta_stride = 2 * S * S;
+        la.gram = static_cast<double*>(dgram);
+        la.gram_stride = lx_gram_doubles(S);
+        la.n_slots = N;
+        la.flops = static_cast<double*>(dfl);
+        la.counts = reinterpret_cast<unsigned long long*>(la.flops + 2);
+        double best_c = 1e300, best_g = 1e300;
+        LxTiles pick{0, 0, 0};
+        for (int v = 0; v < nvar; ++v) {
+            LxTiles t4[kLxBuckets];
+            for (int q = 0; q < kLxBuckets; ++q) t4[q] = var[v];
+            MSC_HIP(launch_lx_plan(la, t4, ctx->stream));
+            double tc = 1e300, tg = 1e300;
+            for (int r = 0; r <= reps; ++r) {   // the first launch warms up
+                float ms = 0.f;
+                MSC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
+                MSC_HIP(launch_lx_contract(precision, la, bk, var[v], grid, ctx->stream));
+                MSC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
+                MSC_HIP(launch_lx_gram(precision, la, bk, var[v], grid, ctx->stream));
+                MSC_HIP(hipEventRecord(ctx->ev2, ctx->stream));
+                MSC_HIP(hipStreamSynchronize(ctx->stream));
+                if (r == 0) continue;
+                MSC_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+                tc = std::min(tc, static_cast<double>(ms));
+                MSC_HIP(hipEventElapsedTime(&ms, ctx->ev1, ctx->ev2));
+                tg = std::min(tg, static_cast<double>(ms));
+            }
+            if (tc < best_c) {
+                best_c = tc;
+                pick.cm_rows = var[v].cm_rows;
+                pick.cm_b = var[v].cm_b;
+            }
+            if (tg < best_g) {
+                best_g = tg;
+                pick.gram = var[v].gram;
+            }
+        }
+        res[bk] = msc_tune_entry{bk, sides[bk], N, pick.cm_rows, pick.cm_b, pick.gram,
+                                 best_c * 1e3, best_g * 1e3};
+    }
+    if (out) std::copy(res, res + kLxBuckets, out);
+    if (cache_path) {
+        std::vector<std::pair<long, std::string>> keep;
+        for (auto& e : cache_entries(cache_path))
+            if (e.first != precision) keep.push_back(e);
+        hipDeviceProp_t prop;
+        MSC_HIP(hipGetDeviceProperties(&prop, ctx->device));
+        FILE* f = std::fopen(cache_path, "wb");
+        if (!f) return set_error(MSC_E_INVALID, std::string("cannot write ") + cache_path);
+        std::fprintf(f, "{\"device\": \"%s\", \"entries\": [\n", prop.gcnArchName);
+        bool first = true;
+        for (auto& e : keep) {
+            std::fprintf(f, "%s  %s", first ? "" : ",\n", e.second.c_str());
+            first = false;
+        }
+        for (const msc_tune_entry& e : res) {
+            std::fprintf(f,
+                         "%s  {\"precision\": %d, \"bucket\": %d, \"side\": %d, \"batch\": %d, "
+                         "\"rows\": %d, \"b\": %d, \"gram\": %d, \"contract_us\": %.3f, "
+                         "\"gram_us\": %.3f}",
+                         first ? "" : ",\n", precision, e.bucket, e.side, e.batch, e.rows, e.b,
+                         e.gram, e.contract_us, e.gram_us);
+            first = false;
+        }
+        std::fprintf(f, "\n]}\n");
+        std::fclose(f);
+    }
     return MSC_OK;
 }
 

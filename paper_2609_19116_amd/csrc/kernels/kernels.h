@@ -229,6 +229,9 @@ struct LxArgs {
     int32_t n_slots;
     double* flops;                     // [2] running algorithmic flops: contractions
                                        // (32 cl cm cr each), Gram matrices (4 nv (nv+1) len)
+    unsigned long long* counts;        // [4] factor steps in LDS, in the workspace
+                                       // (many overlapping vectors), overlapping vectors
+                                       // summed, Jacobi sweeps summed
 };
 // contraction tile (rows of (a, i) x b columns of both j') and Gram tile sizes
 struct LxTiles {
@@ -245,7 +248,7 @@ hipError_t launch_lx_gram(int precision, const LxArgs& a, int bucket, const LxTi
 // slot states to kSlotRun, the park count and the flop counters to 0 (a
 // kernel, not a memset)
 hipError_t launch_lx_reset(ShotState* state, int n_slots, int32_t* park_count, double* flops,
-                           hipStream_t s);
+                           unsigned long long* counts, hipStream_t s);
 // the park count to 0
 hipError_t launch_lx_clear(int32_t* park_count, hipStream_t s);
 // the tile shapes compiled for a precision (autotuner candidates)

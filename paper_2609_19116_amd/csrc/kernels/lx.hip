@@ -144,13 +144,14 @@ __global__ __launch_bounds__(PLAN_T) void lx_plan_kernel(LxArgs a, Tiles4 tt) {
 }
 
 __global__ void lx_reset_kernel(ShotState* state, int n_slots, int32_t* park_count,
-                                double* flops) {
+                                double* flops, unsigned long long* counts) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n_slots) state[i].status = kSlotRun;
     if (i == 0) {
         *park_count = 0;
         flops[0] = 0.0;
         flops[1] = 0.0;
+        for (int q = 0; q < 4; ++q) counts[q] = 0;
     }
 }
 
@@ -347,6 +348,192 @@ __global__ __launch_bounds__(NTH) void lx_contract_kernel(LxArgs a, int bucket) 
 }
 
 // ---------------------------------------------------------------------------
+// contraction in BF16x3 split precision (FP32 tensors): each FP32 operand x
+// is split into hi = bf16(x) and lo = bf16(x - hi), both rounded to nearest
+// even, and a real product is hi hi' + hi lo' + lo hi' with FP32
+// accumulation on v_mfma_f32_16x16x32_bf16 (the lo lo' term, ~2^-16
+// relative, is dropped).  Operands are staged in LDS k-contiguous ([row][k]
+// for A, [column][k] for B) in runs of 8 k that the MFMA reads as one
+// 16-byte fragment; the output layout and the gate epilogue are those of the
+// FP32 kernel.
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+constexpr int XK = 32;    // k per step (one MFMA)
+constexpr int XKP = 40;   // padded k stride in LDS (bf16 elements)
+
+// hi/lo split of 8 consecutive values: hi = bf16(x), lo = bf16(x - hi)
+__device__ __forceinline__ void split8x(const float (&x)[8], uint4& hi, uint4& lo) {
+    unsigned h[4], l[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const f32x2 v = {x[2 * q], x[2 * q + 1]};
+        const unsigned hu = __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
+        const f32x2 r = {v.x - __uint_as_float(hu << 16), v.y - __uint_as_float(hu & 0xffff0000u)};
+        h[q] = hu;
+        l[q] = __builtin_bit_cast(unsigned, __builtin_convertvector(r, bf16x2));
+    }
+    hi = make_uint4(h[0], h[1], h[2], h[3]);
+    lo = make_uint4(l[0], l[1], l[2], l[3]);
+}
+
+template <int WM, int WN>
+__global__ __launch_bounds__(NTH) void lx_contract_bf16x3_kernel(LxArgs a, int bucket) {
+    constexpr int BM = 2 * WM, BN = 2 * WN;
+    constexpr int MT = WM / 16, NT2 = WN / 16;
+    // planes: 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo
+    __shared__ __attribute__((aligned(16))) unsigned short As[4][BM][XKP];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[4][2 * BN][XKP];
+    const LxBucket* pl = &a.plan->b[bucket];
+    const int total = pl->ctiles, cnt = pl->count;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    auto frag = [&](const unsigned short* p) { return *reinterpret_cast<const bf16x8*>(p); };
+    auto neg = [&](bf16x8 x) {   // both sign bits of each dword at once
+        typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+        u32x4 u = __builtin_bit_cast(u32x4, x);
+        u ^= 0x80008000u;
+        return __builtin_bit_cast(bf16x8, u);
+    };
+    for (int t0 = xcd_tile(blockIdx.x, gridDim.x); t0 < total; t0 += gridDim.x) {
+        const int i = owner(pl->coff, cnt, t0);
+        const int slot = pl->slot[i];
+        const ShotState& st = a.state[slot];
+        const int k = st.k;
+        const int cl = st.chi[k], cm = st.chi[k + 1], cr = st.chi[k + 2];
+        const int m = 2 * cl, n = 2 * cr;
+        const int rtiles = (m + BM - 1) / BM;
+        const int tl = t0 - pl->coff[i];
+        const int R0 = (tl % rtiles) * BM;
+        const int B0 = (tl / rtiles) * BN;
+        const float* base = static_cast<const float*>(a.arena) + (size_t)slot * a.slot_stride;
+        const float* Ar = base + a.site_off[k];
+        const float* Ai = Ar + a.site_half[k];
+        const float* Br = base + a.site_off[k + 1];
+        const float* Bi = Br + a.site_half[k + 1];
+        float* Th = static_cast<float*>(a.theta) + (size_t)slot * a.theta_stride;
+        const double* g = a.g4 + st.gate_id * 32;
+
+        floatx4 acc[MT][NT2][2][2];
+#pragma unroll
+        for (int x = 0; x < MT; ++x)
+#pragma unroll
+            for (int y = 0; y < NT2; ++y)
+#pragma unroll
+                for (int z = 0; z < 2; ++z) {
+                    acc[x][y][z][0] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    acc[x][y][z][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+                }
+        for (int k0 = 0; k0 < cm; k0 += XK) {
+            __syncthreads();
+            // A: units (plane, row, run of 8 k)
+            for (int u = tid; u < 2 * BM * (XK / 8); u += NTH) {
+                const int plane = u / (BM * (XK / 8)), rem = u - plane * BM * (XK / 8);
+                const int row = rem / (XK / 8), run = rem - row * (XK / 8);
+                const int r = R0 + row;
+                const float* src = (plane ? Ai : Ar) + (size_t)r * cm;
+                float x[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int c = k0 + 8 * run + e;
+                    x[e] = (r < m && c < cm) ? src[c] : 0.f;
+                }
+                uint4 hi, lo;
+                split8x(x, hi, lo);
+                *reinterpret_cast<uint4*>(&As[2 * plane][row][8 * run]) = hi;
+                *reinterpret_cast<uint4*>(&As[2 * plane + 1][row][8 * run]) = lo;
+            }
+            // B: units (plane, column (j', b), run of 8 k), b fastest
+            for (int u = tid; u < 2 * 2 * BN * (XK / 8); u += NTH) {
+                const int plane = u / (2 * BN * (XK / 8)), rem = u - plane * 2 * BN * (XK / 8);
+                const int run = rem / (2 * BN), col = rem - run * (2 * BN);
+                const int jp = col / BN, b = B0 + (col - jp * BN);
+                const float* src = (plane ? Bi : Br) + jp * cr + b;
+                float x[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int c = k0 + 8 * run + e;
+                    x[e] = (b < cr && c < cm) ? src[(size_t)c * n] : 0.f;
+                }
+                uint4 hi, lo;
+                split8x(x, hi, lo);
+                *reinterpret_cast<uint4*>(&Bs[2 * plane][col][8 * run]) = hi;
+                *reinterpret_cast<uint4*>(&Bs[2 * plane + 1][col][8 * run]) = lo;
+            }
+            __syncthreads();
+            const int kk = 8 * (lane >> 4);
+            bf16x8 af[MT][6];   // re_hi re_lo im_hi im_lo -im_hi -im_lo
+#pragma unroll
+            for (int x = 0; x < MT; ++x) {
+                const int r = wm * WM + x * 16 + (lane & 15);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) af[x][q] = frag(&As[q][r][kk]);
+                af[x][4] = neg(af[x][2]);
+                af[x][5] = neg(af[x][3]);
+            }
+#pragma unroll
+            for (int y = 0; y < NT2; ++y)
+#pragma unroll
+                for (int jp = 0; jp < 2; ++jp) {
+                    const int c = jp * BN + wn * WN + y * 16 + (lane & 15);
+                    bf16x8 bf[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) bf[q] = frag(&Bs[q][c][kk]);
+                    // Re += Ar Br - Ai Bi ; Im += Ar Bi + Ai Br   (each x3)
+                    const int ta[6] = {0, 0, 1, 4, 4, 5}, tb[6] = {0, 1, 0, 2, 3, 2};
+                    const int ua[6] = {0, 0, 1, 2, 2, 3}, ub[6] = {2, 3, 2, 0, 1, 0};
+#pragma unroll
+                    for (int q = 0; q < 6; ++q)
+#pragma unroll
+                        for (int x = 0; x < MT; ++x) {
+                            floatx4& re = acc[x][y][jp][0];
+                            floatx4& im = acc[x][y][jp][1];
+                            re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[x][ta[q]], bf[tb[q]], re, 0, 0, 0);
+                            im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[x][ua[q]], bf[ub[q]], im, 0, 0, 0);
+                        }
+                }
+        }
+        float gg[32];
+#pragma unroll
+        for (int q = 0; q < 32; ++q) gg[q] = static_cast<float>(g[q]);
+#pragma unroll
+        for (int x = 0; x < MT; ++x)
+#pragma unroll
+            for (int y = 0; y < NT2; ++y)
+#pragma unroll
+                for (int rp = 0; rp < 2; ++rp) {
+                    const int row0 = R0 + wm * WM + x * 16 + 4 * (lane >> 4) + 2 * rp;
+                    const int b = B0 + wn * WN + y * 16 + (lane & 15);
+                    if (row0 >= m || b >= cr) continue;
+                    float sr[4], si[4];
+#pragma unroll
+                    for (int ip = 0; ip < 2; ++ip)
+#pragma unroll
+                        for (int jp = 0; jp < 2; ++jp) {
+                            sr[2 * ip + jp] = acc[x][y][jp][0][2 * rp + ip];
+                            si[2 * ip + jp] = acc[x][y][jp][1][2 * rp + ip];
+                        }
+#pragma unroll
+                    for (int o = 0; o < 4; ++o) {
+                        float xr = 0.f, xi = 0.f;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const float gr = gg[2 * (4 * o + q)], gi = gg[2 * (4 * o + q) + 1];
+                            xr += gr * sr[q] - gi * si[q];
+                            xi += gr * si[q] + gi * sr[q];
+                        }
+                        const int ii = o >> 1, jj = o & 1;
+                        const size_t at = (size_t)(row0 + ii) * n + (size_t)jj * cr + b;
+                        Th[at] = xr;
+                        Th[(size_t)m * n + at] = xi;
+                    }
+                }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Gram: G[p][q] = sum_e conj(V[e][p]) V[e][q] in FP64, tiles (bp <= bq) of
 // BG x BG, 2 x 2 waves of BG/2 x BG/2; V[e][v] = theta[e][v] (columns,
 // centre moving right) or theta[v][e] (rows, centre moving left)
@@ -506,6 +693,19 @@ hipError_t launch_lx_contract(int precision, const LxArgs& a, int bucket, const 
                               int grid, hipStream_t s) {
     if (bucket < 0 || bucket >= kLxBuckets) return hipErrorInvalidValue;
     if (precision == MSC_FP64) return launch_contract_t<double>(a, bucket, t, grid, s);
+    if (precision == MSC_BF16X3) {
+#define MSC_LX_BF(WM, WN)                                                                  \
+        if (t.cm_rows == 2 * (WM) && t.cm_b == 2 * (WN)) {                                  \
+            hipLaunchKernelGGL((lx_contract_bf16x3_kernel<WM, WN>), dim3(grid), dim3(NTH), 0, \
+                               s, a, bucket);                                              \
+            return hipGetLastError();                                                      \
+        }
+        MSC_LX_BF(16, 16)
+        MSC_LX_BF(32, 16)
+        MSC_LX_BF(32, 32)
+#undef MSC_LX_BF
+        return hipErrorInvalidValue;
+    }
     return launch_contract_t<float>(a, bucket, t, grid, s);
 }
 
@@ -517,10 +717,10 @@ hipError_t launch_lx_gram(int precision, const LxArgs& a, int bucket, const LxTi
 }
 
 hipError_t launch_lx_reset(ShotState* state, int n_slots, int32_t* park_count, double* flops,
-                           hipStream_t s) {
+                           unsigned long long* counts, hipStream_t s) {
     const int g = (n_slots + 255) / 256;
     hipLaunchKernelGGL(lx_reset_kernel, dim3(g > 0 ? g : 1), dim3(256), 0, s, state, n_slots,
-                       park_count, flops);
+                       park_count, flops, counts);
     return hipGetLastError();
 }
 
@@ -533,8 +733,9 @@ int lx_tile_variants(int precision, LxTiles* out, int cap) {
     static const LxTiles f32[] = {{64, 32, 64}, {32, 32, 64}, {64, 64, 64}, {128, 64, 64},
                                   {64, 32, 32}, {32, 32, 32}};
     static const LxTiles f64[] = {{32, 32, 32}, {64, 32, 64}, {64, 64, 64}, {32, 32, 64}};
-    const LxTiles* v = precision == MSC_FP64 ? f64 : f32;
-    const int nv = precision == MSC_FP64 ? 4 : 6;
+    static const LxTiles bf[] = {{64, 64, 64}, {64, 32, 64}, {32, 32, 64}, {64, 64, 32}};
+    const LxTiles* v = precision == MSC_FP64 ? f64 : precision == MSC_BF16X3 ? bf : f32;
+    const int nv = precision == MSC_FP64 ? 4 : precision == MSC_BF16X3 ? 4 : 6;
     for (int i = 0; i < nv && i < cap; ++i) out[i] = v[i];
     return nv;
 }

@@ -1841,6 +1841,9 @@ __global__ __launch_bounds__(NT) void lx_factor_kernel(LxArgs a, LxFactor f) {
         }
         // ---- the slot's state: new bond, counters, resume
         if (tid == 0) {
+            atomicAdd(a.counts + (small ? 0 : 1), 1ull);
+            atomicAdd(a.counts + 2, static_cast<unsigned long long>(nf));
+            atomicAdd(a.counts + 3, static_cast<unsigned long long>(sweeps));
             st->chi[k + 1] = r;
             st->disc += kp.dropped;
             if (kp.dropped > 1e-12 * total && r == capb) st->shot_status |= MSC_SHOT_CHI_CAP;

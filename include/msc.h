@@ -128,7 +128,16 @@ typedef struct {
                              any other value must be at least 2.            */
     int32_t use_graphs;   /* 1: one engine round (its ~10 launches) is
                              captured once as a HIP graph and replayed      */
-    int32_t reserved;     /* must be 0                                       */
+    int32_t wave_chi;     /* one shot per wavefront (four per workgroup, no
+                             workgroup barriers, three times the resident
+                             shots of the workgroup kernel) in slots whose
+                             bonds are capped at wave_chi; a shot that would
+                             need a larger bond (above the cap and below
+                             chi_max) is run again from its start by the
+                             workgroup kernel, so results follow chi_max.
+                             0: 16 when lds_width is 0 and the circuit's
+                             calibrated noiseless run stays within bond 16,
+                             else off; -1: off; else 2..64.               */
     const char* autotune_cache; /* path of an msc_autotune JSON file giving
                              the engine's tile shapes per precision and bucket
                              of theta sides; NULL: built-in shapes          */
@@ -201,8 +210,9 @@ void msc_ctx_destroy(msc_ctx* ctx);
    none was timed.                                                         */
 double msc_ctx_last_kernel_ms(msc_ctx* ctx, const char* which);
 
-/* What the batched engine for large two-site updates did in the context's
-   last msc_simulate or msc_run_batch call (zero if nothing parked).       */
+/* What the kernels did in the context's last msc_simulate or msc_run_batch
+   call: the batched engine for large two-site updates (zero if nothing
+   parked) and the wavefront kernel (msc_sim_opts.wave_chi).               */
 typedef struct {
     int64_t rounds;         /* engine rounds (each: all parked updates)      */
     int64_t updates;        /* two-site updates done by the engine           */
@@ -220,6 +230,9 @@ typedef struct {
                                the slot's workspace                          */
     int64_t overlapping;    /* overlapping vectors, summed over the updates  */
     int64_t sweeps;         /* Jacobi sweeps, summed                         */
+    int64_t wave_slots;     /* shots in flight in the wavefront kernel (0:
+                               the workgroup kernel ran every shot)         */
+    int64_t wave_retries;   /* shots it handed to the workgroup kernel       */
 } msc_engine_stats;
 
 int msc_ctx_engine_stats(msc_ctx* ctx, msc_engine_stats* out);
@@ -389,7 +402,7 @@ int msc_run_batch(msc_ctx* ctx, const msc_circuit* c, const msc_sim_opts* opts,
    entanglement-lowering two-qubit Clifford of highest purity gain (19
    classes modulo local Cliffords) into the frame.  opts: precision
    MSC_FP64, chi_max in [1, 32] (the residual's bond cap: shots that need
-   more end with MSC_SHOT_CHI_CAP and P_acc 0), lds_width and reserved 0;
+   more end with MSC_SHOT_CHI_CAP and P_acc 0), lds_width 0 and wave_chi 0 or -1;
    prefix 1 forks every shot from a checkpoint of the noiseless CAMPS run
    taken before its first fault (built on first use, <= 2 GiB; results are
    bit-identical to prefix 0).  out[i].chi_peak is the residual's peak bond dimension,

@@ -211,28 +211,31 @@ def prescreen(ctx: Ctx, circ: Circuit, off, chan, pauli, with_index: bool = True
 
 
 def _opts(precision, chi_max, tau_trunc, tau_rej, tau_fail, n_slots, lds_width, prefix,
-          large_side=0, use_graphs=False, autotune_cache=None) -> SimOpts:
+          large_side=0, use_graphs=False, autotune_cache=None, wave_chi=0) -> SimOpts:
     cache = None if autotune_cache is None else str(autotune_cache).encode()
     return SimOpts(precision, chi_max, tau_trunc, tau_rej, tau_fail, n_slots, lds_width,
-                   1 if prefix else 0, large_side, 1 if use_graphs else 0, 0, cache)
+                   1 if prefix else 0, large_side, 1 if use_graphs else 0, wave_chi, cache)
 
 
 def simulate(ctx: Ctx, circ: Circuit, off, chan, pauli, shot_idx=None, precision=MSC_FP64,
              chi_max: int = 256, tau_trunc: float = 0.0, tau_rej: float = 1e-6,
              tau_fail: float = 1e-4, n_slots: int = 0, lds_width: int = 0, prefix: bool = False,
-             out=None, large_side: int = 0, use_graphs: bool = False, autotune_cache=None):
+             out=None, large_side: int = 0, use_graphs: bool = False, autotune_cache=None,
+             wave_chi: int = 0):
     """Simulate shots (device CSR); returns a uint8 device tensor holding
     msc_shot_result records (view them with ``results_numpy``).
-    ``large_side`` (0: 64, -1: off) hands wider two-site updates to the
+    ``large_side`` (0: 256, -1: off) hands wider two-site updates to the
     batched engine; ``use_graphs`` replays its rounds from a HIP graph;
-    ``autotune_cache`` names an msc_autotune file of tile shapes."""
+    ``autotune_cache`` names an msc_autotune file of tile shapes;
+    ``wave_chi`` (0: automatic, -1: off) runs one shot per wavefront in
+    slots of that bond cap."""
     import torch
     n_shots = off.numel() - 1
     n = shot_idx.numel() if shot_idx is not None else n_shots
     if out is None:
         out = torch.empty(max(n, 1) * SHOT_DTYPE.itemsize, dtype=torch.uint8, device=off.device)
     o = _opts(precision, chi_max, tau_trunc, tau_rej, tau_fail, n_slots, lds_width, prefix,
-              large_side, use_graphs, autotune_cache)
+              large_side, use_graphs, autotune_cache, wave_chi)
     _check(lib().msc_simulate(ctx.h, circ.h, C.byref(o), n_shots, _ptr(off), _ptr(chan),
                               _ptr(pauli), _ptr(shot_idx), n, _ptr(out)))
     return out[: n * SHOT_DTYPE.itemsize]
@@ -271,7 +274,8 @@ def run_batch(ctx: Ctx, circ: Circuit, seed: int, first_shot: int, n_shots: int,
               n_bins: int = 65, precision=MSC_FP32, chi_max: int = 256, tau_trunc: float = 0.0,
               tau_rej: float = 1e-6, tau_fail: float = 1e-4, n_slots: int = 0,
               lds_width: int = 0, prefix: bool = True, out=None, space_time: bool = False,
-              large_side: int = 0, use_graphs: bool = False, autotune_cache=None):
+              large_side: int = 0, use_graphs: bool = False, autotune_cache=None,
+              wave_chi: int = 0):
     """One batch of the whole path (sampling, screen, shots, bin sums) on the
     context's stream with one synchronisation.  Returns (bins float64
     [7, n_bins]: shots, sum P_acc, sum P_acc * fail, accepted count, wrong
@@ -281,7 +285,7 @@ def run_batch(ctx: Ctx, circ: Circuit, seed: int, first_shot: int, n_shots: int,
     ``out`` (optional uint8 device tensor of n_shots records) receives the
     per-shot results, indexed by shot."""
     o = _opts(precision, chi_max, tau_trunc, tau_rej, tau_fail, n_slots, lds_width, prefix,
-              large_side, use_graphs, autotune_cache)
+              large_side, use_graphs, autotune_cache, wave_chi)
     bins = np.zeros(7 * n_bins, dtype=np.float64)
     st = BatchStats()
     if out is not None:

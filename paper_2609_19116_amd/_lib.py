@@ -51,7 +51,7 @@ class SimOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("chi_max", C.c_int32), ("tau_trunc", C.c_double),
                 ("tau_rej", C.c_double), ("tau_fail", C.c_double), ("n_slots", C.c_int32),
                 ("lds_width", C.c_int32), ("prefix", C.c_int32), ("large_side", C.c_int32),
-                ("use_graphs", C.c_int32), ("reserved", C.c_int32),
+                ("use_graphs", C.c_int32), ("wave_chi", C.c_int32),
                 ("autotune_cache", C.c_char_p)]
 
 
@@ -81,7 +81,7 @@ class EngineStats(C.Structure):
                 ("gram_flops", C.c_double), ("contract_ms", C.c_double), ("gram_ms", C.c_double),
                 ("factor_ms", C.c_double), ("shot_ms", C.c_double), ("total_ms", C.c_double),
                 ("factor_lds", C.c_int64), ("factor_wide", C.c_int64), ("overlapping", C.c_int64),
-                ("sweeps", C.c_int64)]
+                ("sweeps", C.c_int64), ("wave_slots", C.c_int64), ("wave_retries", C.c_int64)]
 
 
 class TuneEntry(C.Structure):

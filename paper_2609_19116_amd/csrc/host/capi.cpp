@@ -49,6 +49,7 @@ struct msc_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
     // what the slot-layout and Bin(M, p) buffers currently hold
     int layout_n = -1, layout_chi = -1;
+    int wlayout_n = -1, wlayout_chi = -1;     // the wavefront kernel's slots
     int64_t cdf_m = -1;
     double cdf_p = -1.0;
     int32_t cdf_len = 0;
@@ -328,6 +329,11 @@ Layout make_layout(int n, int chi_max, int side_in) {
     return L;
 }
 
+// Bond cap of the wavefront kernel's slots: the automatic choice, and the
+// largest a caller may ask for.
+constexpr int kAutoWaveChi = 16;
+constexpr int kMaxWaveChi = 64;
+
 // Options of one shot-kernel run.
 struct RunCfg {
     int precision = MSC_FP64;
@@ -336,6 +342,7 @@ struct RunCfg {
     int n_slots = 0;
     int lds_width = 32;
     int park_side = 64;          // 0: the shot kernel does every update
+    int wave_chi = 0;            // > 0: one shot per wavefront in slots of this bond cap
     bool graphs = false;
     LxTiles tiles[kLxBuckets];
 };
@@ -375,46 +382,12 @@ static int enqueue_lx_round(msc_ctx* ctx, const RunCfg& cfg, bool small, const M
     return MSC_OK;
 }
 
-// Enqueues the order and shot kernels on the context's stream.  n bounds the
-// shots (a device count n_dev, if given, may be smaller).  With the engine
-// on (cfg.park_side > 0) the shot kernel parks every shot at a two-site
-// update wider than park_side; the host then runs engine rounds (each does
-// every parked update and resumes the shot kernel) until a launch parks
-// nothing, reading the park count after each round (one stream
-// synchronisation per round).  Otherwise nothing waits here.
-static int enqueue_shots(msc_ctx* ctx, const msc_circuit* c, const RunCfg& cfg, int64_t n,
-                         int64_t n_csr, const int64_t* off, const int32_t* chan,
-                         const uint8_t* pauli, const int64_t* shot_idx, msc_shot_result* out,
-                         int calibrate, double* cal_p, uint8_t* cal_e, int ck_mode,
-                         const PrefixCk* pk, const int64_t* n_dev, double* surv = nullptr) {
-    const int precision = cfg.precision, chi_max = cfg.chi_max;
-    const bool engine = cfg.park_side > 0;
-    Layout L = make_layout(c->n, chi_max, engine ? cfg.park_side : 2 * chi_max);
-    // the shot kernel keeps the site offsets within a slot as 32-bit values
-    if (L.slot_elems >= (int64_t(1) << 31)) return set_error(MSC_E_INVALID, "slot above 2^31 elements");
-    const bool small = cfg.lds_width == 32;
-    int n_slots = cfg.n_slots;
-    if (n_slots <= 0) n_slots = ctx->n_cu * mps_blocks_per_cu(precision, small);
-    n_slots = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(n_slots, n)));
-    if (engine) n_slots = std::min(n_slots, kLxMaxParked);
-    const size_t tsize = precision == MSC_FP64 ? sizeof(double) : sizeof(float);
-    void *arena, *scratch, *dcap, *doff, *dhalf, *dperm;
-    int rc;
-    if ((rc = ctx_buf(ctx, "arena", static_cast<size_t>(n_slots) * L.slot_elems * tsize, &arena))) return rc;
-    if ((rc = ctx_buf(ctx, "scratch", static_cast<size_t>(n_slots) * L.scratch * sizeof(double), &scratch))) return rc;
-    if ((rc = ctx_buf(ctx, "cap", L.cap.size() * sizeof(int32_t), &dcap))) return rc;
-    if ((rc = ctx_buf(ctx, "off", L.off.size() * sizeof(int64_t), &doff))) return rc;
-    if ((rc = ctx_buf(ctx, "half", L.half.size() * sizeof(int64_t), &dhalf))) return rc;
-    if ((rc = ctx_buf(ctx, "perm", static_cast<size_t>(n) * sizeof(int64_t), &dperm))) return rc;
-    if (ctx->layout_n != c->n || ctx->layout_chi != chi_max) {
-        // the layout depends on (n, chi_max) only: uploaded when it changes
-        MSC_HIP(hipMemcpyAsync(dcap, L.cap.data(), L.cap.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
-        MSC_HIP(hipMemcpyAsync(doff, L.off.data(), L.off.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
-        MSC_HIP(hipMemcpyAsync(dhalf, L.half.data(), L.half.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
-        MSC_HIP(hipStreamSynchronize(ctx->stream));
-        ctx->layout_n = c->n;
-        ctx->layout_chi = chi_max;
-    }
+// The shot kernels' arguments that do not depend on the slot layout.
+static MpsArgs shot_args(const msc_circuit* c, const RunCfg& cfg, int64_t n, int64_t n_csr,
+                         const int64_t* off, const int32_t* chan, const uint8_t* pauli,
+                         const int64_t* shot_idx, msc_shot_result* out, int calibrate,
+                         double* cal_p, uint8_t* cal_e, int ck_mode, const PrefixCk* pk,
+                         const int64_t* n_dev, double* surv) {
     MpsArgs a{};
     a.ops = static_cast<const DevOp*>(c->d_ops);
     a.n_ops = static_cast<int32_t>(c->ops.size());
@@ -425,20 +398,12 @@ static int enqueue_shots(msc_ctx* ctx, const msc_circuit* c, const RunCfg& cfg, 
     a.chan = chan;
     a.pauli = pauli;
     a.shot_idx = shot_idx;
-    a.perm = static_cast<const int64_t*>(dperm);
     a.n_shots = n;
     a.n_dev = n_dev;
     a.n_csr = n_csr;
     a.expected = static_cast<const uint8_t*>(c->d_expected);
     a.out = out;
-    a.arena = arena;
-    a.slot_stride = L.slot_elems;
-    a.site_off = static_cast<const int64_t*>(doff);
-    a.site_half = static_cast<const int64_t*>(dhalf);
-    a.cap = static_cast<const int32_t*>(dcap);
-    a.scratch = static_cast<double*>(scratch);
-    a.scratch_stride = L.scratch;
-    a.chi_max = chi_max;
+    a.chi_max = cfg.chi_max;
     a.tau = cfg.tau;
     a.tau_rej = cfg.tau_rej;
     a.tau_fail = cfg.tau_fail;
@@ -472,6 +437,143 @@ static int enqueue_shots(msc_ctx* ctx, const msc_circuit* c, const RunCfg& cfg, 
         a.seg_meas = static_cast<const int32_t*>(c->d_segm);
         a.n_seg = static_cast<int32_t>(c->segs.size());
     }
+    return a;
+}
+
+static int enqueue_shots(msc_ctx* ctx, const msc_circuit* c, const RunCfg& cfg, int64_t n,
+                         int64_t n_csr, const int64_t* off, const int32_t* chan,
+                         const uint8_t* pauli, const int64_t* shot_idx, msc_shot_result* out,
+                         int calibrate, double* cal_p, uint8_t* cal_e, int ck_mode,
+                         const PrefixCk* pk, const int64_t* n_dev, double* surv,
+                         const int64_t* perm_in);
+
+// The wavefront kernel's pass over the shots (slots of bond cap wave_chi,
+// one shot per wavefront, shots taken from a shared counter), then the shots
+// that outgrew their slots, from their start (no fork) in the workgroup
+// kernel with the caller's other options.  One stream synchronisation reads
+// how many there are.
+static int enqueue_wave(msc_ctx* ctx, const msc_circuit* c, const RunCfg& cfg, int64_t n,
+                        int64_t n_csr, const int64_t* off, const int32_t* chan,
+                        const uint8_t* pauli, const int64_t* shot_idx, msc_shot_result* out,
+                        int ck_mode, const PrefixCk* pk, const int64_t* n_dev, double* surv) {
+    const int precision = cfg.precision, cw = cfg.wave_chi;
+    Layout L = make_layout(c->n, cw, 2 * cw);
+    if (L.slot_elems >= (int64_t(1) << 31)) return set_error(MSC_E_INVALID, "slot above 2^31 elements");
+    int64_t teams = cfg.n_slots > 0 ? cfg.n_slots
+                                    : static_cast<int64_t>(ctx->n_cu) *
+                                          mps_wave_blocks_per_cu(precision) * kWaveTeams;
+    teams = std::max<int64_t>(1, std::min<int64_t>(teams, n));
+    const int grid = static_cast<int>((teams + kWaveTeams - 1) / kWaveTeams);
+    const int64_t slots = static_cast<int64_t>(grid) * kWaveTeams;
+    const size_t tsize = precision == MSC_FP64 ? sizeof(double) : sizeof(float);
+    void *arena, *scratch, *dcap, *doff, *dhalf, *dperm, *dctr, *dlist;
+    int rc;
+    if ((rc = ctx_buf(ctx, "w_arena", static_cast<size_t>(slots) * L.slot_elems * tsize, &arena))) return rc;
+    if ((rc = ctx_buf(ctx, "w_scratch", static_cast<size_t>(slots) * L.scratch * sizeof(double), &scratch))) return rc;
+    if ((rc = ctx_buf(ctx, "w_cap", L.cap.size() * sizeof(int32_t), &dcap))) return rc;
+    if ((rc = ctx_buf(ctx, "w_off", L.off.size() * sizeof(int64_t), &doff))) return rc;
+    if ((rc = ctx_buf(ctx, "w_half", L.half.size() * sizeof(int64_t), &dhalf))) return rc;
+    if ((rc = ctx_buf(ctx, "w_perm", static_cast<size_t>(n) * sizeof(int64_t), &dperm))) return rc;
+    // the shared shot counter (8 bytes) and the retry count (4 bytes)
+    if ((rc = ctx_buf(ctx, "w_ctr", 16, &dctr))) return rc;
+    if ((rc = ctx_buf(ctx, "w_retry", static_cast<size_t>(n) * sizeof(int64_t), &dlist))) return rc;
+    if (ctx->wlayout_n != c->n || ctx->wlayout_chi != cw) {
+        MSC_HIP(hipMemcpyAsync(dcap, L.cap.data(), L.cap.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+        MSC_HIP(hipMemcpyAsync(doff, L.off.data(), L.off.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+        MSC_HIP(hipMemcpyAsync(dhalf, L.half.data(), L.half.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+        MSC_HIP(hipStreamSynchronize(ctx->stream));
+        ctx->wlayout_n = c->n;
+        ctx->wlayout_chi = cw;
+    }
+    MpsArgs a = shot_args(c, cfg, n, n_csr, off, chan, pauli, shot_idx, out, 0, nullptr, nullptr,
+                          ck_mode, pk, n_dev, surv);
+    a.perm = static_cast<const int64_t*>(dperm);
+    a.arena = arena;
+    a.slot_stride = L.slot_elems;
+    a.site_off = static_cast<const int64_t*>(doff);
+    a.site_half = static_cast<const int64_t*>(dhalf);
+    a.cap = static_cast<const int32_t*>(dcap);
+    a.scratch = static_cast<double*>(scratch);
+    a.scratch_stride = L.scratch;
+    a.next = static_cast<unsigned long long*>(dctr);
+    a.retry_count = reinterpret_cast<int32_t*>(static_cast<char*>(dctr) + 8);
+    a.retry_list = static_cast<int64_t*>(dlist);
+    ctx->lx_stats = msc_engine_stats{};
+    MSC_HIP(hipMemsetAsync(dctr, 0, 16, ctx->stream));
+    MSC_HIP(launch_order(n, n_dev, off, shot_idx, n_csr, chan,
+                         a.ck_mode == 2 ? c->n_channels : 0, static_cast<int64_t*>(dperm),
+                         ctx->stream));
+    MSC_HIP(launch_mps_wave(precision, a, grid, ctx->stream));
+    int32_t n_retry = 0;
+    MSC_HIP(hipMemcpyAsync(&n_retry, a.retry_count, sizeof(n_retry), hipMemcpyDeviceToHost,
+                           ctx->stream));
+    MSC_HIP(hipStreamSynchronize(ctx->stream));
+    if (n_retry > 0) {
+        RunCfg wg = cfg;
+        wg.wave_chi = 0;
+        rc = enqueue_shots(ctx, c, wg, n_retry, n_csr, off, chan, pauli, shot_idx, out, 0, nullptr,
+                           nullptr, 0, nullptr, nullptr, surv, a.retry_list);
+        if (rc) return rc;
+    }
+    ctx->lx_stats.wave_slots = slots;
+    ctx->lx_stats.wave_retries = n_retry;
+    return MSC_OK;
+}
+
+// Enqueues the order and shot kernels on the context's stream.  n bounds the
+// shots (a device count n_dev, if given, may be smaller).  With the engine
+// on (cfg.park_side > 0) the shot kernel parks every shot at a two-site
+// update wider than park_side; the host then runs engine rounds (each does
+// every parked update and resumes the shot kernel) until a launch parks
+// nothing, reading the park count after each round (one stream
+// synchronisation per round).  Otherwise nothing waits here.
+static int enqueue_shots(msc_ctx* ctx, const msc_circuit* c, const RunCfg& cfg, int64_t n,
+                         int64_t n_csr, const int64_t* off, const int32_t* chan,
+                         const uint8_t* pauli, const int64_t* shot_idx, msc_shot_result* out,
+                         int calibrate, double* cal_p, uint8_t* cal_e, int ck_mode,
+                         const PrefixCk* pk, const int64_t* n_dev, double* surv,
+                         const int64_t* perm_in) {
+    if (cfg.wave_chi > 0 && !calibrate)
+        return enqueue_wave(ctx, c, cfg, n, n_csr, off, chan, pauli, shot_idx, out, ck_mode, pk,
+                            n_dev, surv);
+    const int precision = cfg.precision, chi_max = cfg.chi_max;
+    const bool engine = cfg.park_side > 0;
+    Layout L = make_layout(c->n, chi_max, engine ? cfg.park_side : 2 * chi_max);
+    // the shot kernel keeps the site offsets within a slot as 32-bit values
+    if (L.slot_elems >= (int64_t(1) << 31)) return set_error(MSC_E_INVALID, "slot above 2^31 elements");
+    const bool small = cfg.lds_width == 32;
+    int n_slots = cfg.n_slots;
+    if (n_slots <= 0) n_slots = ctx->n_cu * mps_blocks_per_cu(precision, small);
+    n_slots = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(n_slots, n)));
+    if (engine) n_slots = std::min(n_slots, kLxMaxParked);
+    const size_t tsize = precision == MSC_FP64 ? sizeof(double) : sizeof(float);
+    void *arena, *scratch, *dcap, *doff, *dhalf, *dperm;
+    int rc;
+    if ((rc = ctx_buf(ctx, "arena", static_cast<size_t>(n_slots) * L.slot_elems * tsize, &arena))) return rc;
+    if ((rc = ctx_buf(ctx, "scratch", static_cast<size_t>(n_slots) * L.scratch * sizeof(double), &scratch))) return rc;
+    if ((rc = ctx_buf(ctx, "cap", L.cap.size() * sizeof(int32_t), &dcap))) return rc;
+    if ((rc = ctx_buf(ctx, "off", L.off.size() * sizeof(int64_t), &doff))) return rc;
+    if ((rc = ctx_buf(ctx, "half", L.half.size() * sizeof(int64_t), &dhalf))) return rc;
+    if ((rc = ctx_buf(ctx, "perm", static_cast<size_t>(n) * sizeof(int64_t), &dperm))) return rc;
+    if (ctx->layout_n != c->n || ctx->layout_chi != chi_max) {
+        // the layout depends on (n, chi_max) only: uploaded when it changes
+        MSC_HIP(hipMemcpyAsync(dcap, L.cap.data(), L.cap.size() * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+        MSC_HIP(hipMemcpyAsync(doff, L.off.data(), L.off.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+        MSC_HIP(hipMemcpyAsync(dhalf, L.half.data(), L.half.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+        MSC_HIP(hipStreamSynchronize(ctx->stream));
+        ctx->layout_n = c->n;
+        ctx->layout_chi = chi_max;
+    }
+    MpsArgs a = shot_args(c, cfg, n, n_csr, off, chan, pauli, shot_idx, out, calibrate, cal_p,
+                          cal_e, ck_mode, pk, n_dev, surv);
+    a.perm = perm_in ? perm_in : static_cast<const int64_t*>(dperm);
+    a.arena = arena;
+    a.slot_stride = L.slot_elems;
+    a.site_off = static_cast<const int64_t*>(doff);
+    a.site_half = static_cast<const int64_t*>(dhalf);
+    a.cap = static_cast<const int32_t*>(dcap);
+    a.scratch = static_cast<double*>(scratch);
+    a.scratch_stride = L.scratch;
     ctx->lx_stats = msc_engine_stats{};
     void *dstate = nullptr, *dcount = nullptr, *dlist = nullptr, *dflops = nullptr;
     if (engine) {
@@ -487,9 +589,10 @@ static int enqueue_shots(msc_ctx* ctx, const msc_circuit* c, const RunCfg& cfg, 
                                 reinterpret_cast<unsigned long long*>(static_cast<double*>(dflops) + 2),
                                 ctx->stream));
     }
-    MSC_HIP(launch_order(n, n_dev, off, shot_idx, n_csr, chan,
-                         a.ck_mode == 2 ? c->n_channels : 0, static_cast<int64_t*>(dperm),
-                         ctx->stream));
+    if (!perm_in)
+        MSC_HIP(launch_order(n, n_dev, off, shot_idx, n_csr, chan,
+                             a.ck_mode == 2 ? c->n_channels : 0, static_cast<int64_t*>(dperm),
+                             ctx->stream));
     if (engine) MSC_HIP(hipEventRecord(ctx->lxev[4], ctx->stream));
     MSC_HIP(launch_mps(precision, small, a, n_slots, ctx->stream));
     if (engine) MSC_HIP(hipEventRecord(ctx->lxev[5], ctx->stream));
@@ -605,7 +708,7 @@ static int run_shots(msc_ctx* ctx, const msc_circuit* c, const RunCfg& cfg, int6
                      const PrefixCk* pk = nullptr) {
     MSC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
     int rc = enqueue_shots(ctx, c, cfg, n, n_csr, off, chan, pauli, shot_idx, out, calibrate,
-                           cal_p, cal_e, ck_mode, pk, nullptr);
+                           cal_p, cal_e, ck_mode, pk, nullptr, nullptr, nullptr);
     if (rc) return rc;
     MSC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
     MSC_HIP(hipStreamSynchronize(ctx->stream));
@@ -689,7 +792,7 @@ static int ensure_prefix(msc_ctx* ctx, msc_circuit* c, const RunCfg& cfg) {
     const double tau = cfg.tau, tau_rej = cfg.tau_rej;
     if (pk.valid && pk.dev == ctx->device && pk.precision == precision &&
         pk.chi_max == chi_max && pk.lds_width == lds_width && pk.tau == tau &&
-        pk.tau_rej == tau_rej && pk.park_side == cfg.park_side)
+        pk.tau_rej == tau_rej && pk.park_side == cfg.park_side && pk.wave_chi == cfg.wave_chi)
         return MSC_OK;
     free_prefix(pk);
     pk.dev = ctx->device;
@@ -752,6 +855,7 @@ static int ensure_prefix(msc_ctx* ctx, msc_circuit* c, const RunCfg& cfg) {
     pk.chi_max = chi_max;
     pk.lds_width = lds_width;
     pk.park_side = cfg.park_side;
+    pk.wave_chi = cfg.wave_chi;
     pk.tau = tau;
     pk.tau_rej = tau_rej;
     pk.build_ms = static_cast<float>(ctx->last_ms["prefix"]);
@@ -818,8 +922,10 @@ static int read_tune_cache(const char* path, int precision, LxTiles* tiles) {
 }
 
 // The run options of msc_sim_opts (validated), with the engine's tile shapes
-// from the autotune cache when one is named.
-static int sim_cfg(const msc_sim_opts* o, RunCfg* cfg) {
+// from the autotune cache when one is named.  With wave_chi 0 and lds_width
+// 0 the wavefront kernel (slots of bond cap 16) takes the shots of circuits
+// whose calibrated noiseless run stays within bond 16.
+static int sim_cfg(const msc_sim_opts* o, const msc_circuit* c, RunCfg* cfg) {
     if (o->precision != MSC_FP64 && o->precision != MSC_FP32 && o->precision != MSC_BF16X3)
         return set_error(MSC_E_INVALID, "unknown precision");
     if (o->chi_max < 1 || o->chi_max > kMaxChiKernel)
@@ -831,7 +937,8 @@ static int sim_cfg(const msc_sim_opts* o, RunCfg* cfg) {
         return set_error(MSC_E_INVALID, "use_graphs must be 0 or 1");
     if (o->large_side < -1 || o->large_side == 1)
         return set_error(MSC_E_INVALID, "large_side must be -1, 0 or at least 2");
-    if (o->reserved != 0) return set_error(MSC_E_INVALID, "reserved must be 0");
+    if (o->wave_chi < -1 || o->wave_chi == 1 || o->wave_chi > kMaxWaveChi)
+        return set_error(MSC_E_INVALID, "wave_chi must be -1, 0 or in [2, 64]");
     cfg->precision = o->precision;
     cfg->chi_max = o->chi_max;
     cfg->tau = o->tau_trunc > 0 ? o->tau_trunc
@@ -843,6 +950,13 @@ static int sim_cfg(const msc_sim_opts* o, RunCfg* cfg) {
     cfg->lds_width = o->lds_width == 64 ? 64 : 32;
     cfg->park_side = o->large_side == -1 ? 0 : o->large_side == 0 ? 256 : o->large_side;
     cfg->graphs = o->use_graphs == 1;
+    int wc = 0;
+    if (o->wave_chi > 0)
+        wc = o->wave_chi;
+    else if (o->wave_chi == 0 && o->lds_width == 0 && c && c->calibrated &&
+             c->noiseless.chi_peak <= kAutoWaveChi)
+        wc = kAutoWaveChi;
+    cfg->wave_chi = std::min(wc, cfg->chi_max);
     default_tiles(cfg->precision, cfg->tiles);
     if (o->autotune_cache) {
         int rc = read_tune_cache(o->autotune_cache, cfg->precision, cfg->tiles);
@@ -877,7 +991,7 @@ extern "C" int msc_simulate(msc_ctx* ctx, const msc_circuit* c, const msc_sim_op
     if (n > 0 && !out) return set_error(MSC_E_INVALID, "null out");
     if (!c->calibrated) return set_error(MSC_E_STATE, "circuit not calibrated");
     RunCfg cfg;
-    int rc = sim_cfg(opts, &cfg);
+    int rc = sim_cfg(opts, c, &cfg);
     if (rc) return rc;
     if (n == 0) return MSC_OK;
     MSC_HIP(hipSetDevice(ctx->device));
@@ -1032,7 +1146,7 @@ extern "C" int msc_run_batch(msc_ctx* ctx, const msc_circuit* c, const msc_sim_o
     if (!(p >= 0.0 && p <= 1.0)) return set_error(MSC_E_INVALID, "p outside [0,1]");
     if (!c->calibrated) return set_error(MSC_E_STATE, "circuit not calibrated");
     RunCfg cfg;
-    int rc = sim_cfg(opts, &cfg);
+    int rc = sim_cfg(opts, c, &cfg);
     if (rc) return rc;
     if (c->words > 8) return set_error(MSC_E_INVALID, "more than 512 decided measurements");
     MSC_HIP(hipSetDevice(ctx->device));
@@ -1111,7 +1225,7 @@ extern "C" int msc_run_batch(msc_ctx* ctx, const msc_circuit* c, const msc_sim_o
     rc = enqueue_shots(ctx, c, cfg, n_shots, n_shots, offp, static_cast<int32_t*>(dchan),
                        static_cast<uint8_t*>(dpa), idxp, res, 0, nullptr, nullptr,
                        opts->prefix ? 2 : 0, opts->prefix ? &c->prefix : nullptr, nsurv,
-                       static_cast<double*>(dsurv));
+                       static_cast<double*>(dsurv), nullptr);
     if (rc) return rc;
     MSC_HIP(hipEventRecord(ctx->ev3, ctx->stream));
     MSC_HIP(launch_batch_reduce(n_shots, seed, first_shot, offp, idxp, nsurv, res, n_bins, nnz,
@@ -1271,8 +1385,8 @@ extern "C" int msc_simulate_camps(msc_ctx* ctx, const msc_circuit* c, const msc_
     if (opts->chi_max < 1 || opts->chi_max > kCampsCap)
         return set_error(MSC_E_INVALID, "CAMPS chi_max must be in [1, 32]");
     if (c->n > kMaxSites - 1) return set_error(MSC_E_INVALID, "CAMPS takes at most 127 qubits");
-    if ((opts->prefix != 0 && opts->prefix != 1) || opts->reserved != 0 || opts->lds_width != 0)
-        return set_error(MSC_E_INVALID, "CAMPS takes prefix 0 or 1, no lds_width or reserved option");
+    if ((opts->prefix != 0 && opts->prefix != 1) || opts->wave_chi > 0 || opts->lds_width != 0)
+        return set_error(MSC_E_INVALID, "CAMPS takes prefix 0 or 1, no lds_width or wave_chi option");
     if (n == 0) return MSC_OK;
     MSC_HIP(hipSetDevice(ctx->device));
     msc_circuit* cc = const_cast<msc_circuit*>(c);

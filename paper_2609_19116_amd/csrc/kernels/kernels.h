@@ -112,6 +112,13 @@ struct MpsArgs {
     ShotState* state;
     int32_t* park_count;
     int32_t* park_list;
+    // the wavefront kernel: shots taken from the shared counter next (zero
+    // at the launch); a shot that outgrows its slot's bond cap (below
+    // chi_max) appends its index in the run to retry_list and yields no
+    // result there.  Both nullptr for the workgroup kernel.
+    unsigned long long* next;
+    int32_t* retry_count;
+    int64_t* retry_list;
 };
 
 // precision: MSC_FP64 or MSC_FP32; small: use the 32-wide LDS variant
@@ -124,6 +131,12 @@ hipError_t launch_order(int64_t n, const int64_t* n_dev, const int64_t* shot_off
                         int32_t n_channels, int64_t* perm, hipStream_t s);
 // resident workgroups per CU of the chosen variant (sizes the persistent grid)
 int mps_blocks_per_cu(int precision, bool small);
+// One shot per wavefront (four per workgroup of 256 threads): grid
+// workgroups serve 4 * grid slots.  Needs next (zeroed), retry_count and
+// retry_list; ck_mode 0, 1 or 2; no calibration and no parking.
+hipError_t launch_mps_wave(int precision, const MpsArgs& a, int grid, hipStream_t s);
+int mps_wave_blocks_per_cu(int precision);
+constexpr int kWaveTeams = 4;      // shots per workgroup of the wavefront kernel
 
 // Bits of the CSR check flag written by the screen and validation kernels
 enum CsrFlag : int {

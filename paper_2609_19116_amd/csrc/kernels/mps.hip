@@ -356,7 +356,8 @@ __device__ int flagged_list(IP flag, int nv, IP list, int* red) {
 }
 
 struct Kept {
-    int r;
+    int r;         // vectors kept
+    int want;      // vectors above the threshold (r unless the cap binds)
     double kept, dropped;
 };
 
@@ -375,7 +376,7 @@ __device__ Kept select_kept(DP nrm, int nv, double tau2, int capb, IP sel, DP is
     double mx = 0.0;
     for (int v = tid; v < nv; v += W) mx = fmax(mx, sel_norm(nrm[v]));
     mx = team_max<W>(mx, red);
-    double kd[3] = {0.0, 0.0, 0.0};
+    double kd[4] = {0.0, 0.0, 0.0, 0.0};
     for (int v = tid; v < nv; v += W) {
         const double x = sel_norm(nrm[v]);
         int rank = 0;
@@ -383,7 +384,9 @@ __device__ Kept select_kept(DP nrm, int nv, double tau2, int capb, IP sel, DP is
             const double y = sel_norm(nrm[u]);
             rank += (y > x) || (y == x && u < v);
         }
-        const bool keep = (x > tau2 * mx || rank == 0) && rank < capb;
+        const bool above = x > tau2 * mx || rank == 0;
+        kd[3] += above ? 1.0 : 0.0;
+        const bool keep = above && rank < capb;
         if (keep) {
             const double s = sqrt(x);
             sel[rank] = v;
@@ -395,10 +398,11 @@ __device__ Kept select_kept(DP nrm, int nv, double tau2, int capb, IP sel, DP is
             kd[2] += x;
         }
     }
-    team_sum<W, 3>(kd, red);
+    team_sum<W, 4>(kd, red);
     Team<W>::sync();
     Kept k;
     k.r = static_cast<int>(kd[0] + 0.5);
+    k.want = static_cast<int>(kd[3] + 0.5);
     k.kept = kd[1];
     k.dropped = kd[2];
     return k;
@@ -411,9 +415,17 @@ struct SiteView {
     __attribute__((address_space(1))) T* im;
 };
 
-// LDS of a workgroup, shared by the op implementations.
+// LDS of a team (the workgroup, or one wavefront of the wavefront kernel),
+// shared by the op implementations.
 struct Smem {
     int* chi;            // [kMaxSites + 1] bond dimensions
+    int* laste;          // [kMaxSites] last measured outcome per site
+    int* flag;           // [1]
+    DevOp* ops;          // op descriptors, a window of the op stream
+    const int32_t* soff; // [kMaxSites] site offsets within a slot
+    const int32_t* shalf;
+    const double* g1;    // [G1_COUNT * 8] 2x2 gates
+    int n_u;             // doubles of staging at u
     double* vre;         // SVD vectors (SMAX x (SMAX + 1)), planar
     double* vim;
     double* nrm;         // [SMAX]
@@ -453,20 +465,23 @@ struct ShotAcc {
 // orthogonal, as they are after a split that left the centre there: a
 // selection of the kept vectors, their normalisation and a rescaling of the
 // neighbour.  Returns false (team-uniform) when a pair overlaps; the caller
-// then falls back to a two-site identity update.  Requires nv, len <= SMAX.
-template <typename T, int SMAX, int W>
+// then falls back to a two-site identity update.  The vectors live in V
+// (LDS, or the slot's scratch); the rescaled neighbour is staged in V's
+// vector arrays when it fits in vcap doubles each, else at the start of the
+// slot's scratch (which then must not hold V).
+template <typename T, int W, typename DP, typename IP>
 __device__ bool move_fast(const MpsArgs& P, const Smem& S, SiteView<T> A, SiteView<T> B, int k,
-                          int dir, double* scr, ShotAcc& acc) {
+                          int dir, const Vecs<DP, IP>& V, int64_t vcap, double* scr, ShotAcc& acc) {
     typedef __attribute__((address_space(1))) T gT;
     const int tid = Team<W>::rank();
     const int cl = S.chi[k], cm = S.chi[k + 1], cr = S.chi[k + 2];
     const int nv = cm, len = dir ? 2 * cl : 2 * cr, ld = len + 1;
-    ldsd* vre = to_lds(S.vre);
-    ldsd* vim = to_lds(S.vim);
-    ldsd* nrm = to_lds(S.nrm);
-    ldsd* isq = to_lds(S.isq);
-    ldsd* sq = to_lds(S.sq);
-    ldsi* sel = to_lds(S.sel);
+    DP vre = V.vre;
+    DP vim = V.vim;
+    DP nrm = V.nrm;
+    DP isq = V.isq;
+    DP sq = V.sq;
+    IP sel = V.sel;
     gT* Are = A.re;
     gT* Aim = A.im;
     gT* Bre = B.re;
@@ -489,8 +504,7 @@ __device__ bool move_fast(const MpsArgs& P, const Smem& S, SiteView<T> A, SiteVi
     const double tau2 = P.tau * P.tau;
     const double tol = sizeof(T) == sizeof(double) ? static_cast<double>(len) * DBL_EPSILON
                                                    : 8.0 * static_cast<double>(FLT_EPSILON);
-    if (not_orthogonal<W>(vre, vim, nv, len, ld, nrm, 1e-4 * tau2 * tsum[0], tol,
-                          to_lds(S.bad), (ldsi*)nullptr))
+    if (not_orthogonal<W>(vre, vim, nv, len, ld, nrm, 1e-4 * tau2 * tsum[0], tol, V.bad, (IP)nullptr))
         return false;
     const int capb = min(P.chi_max, S.cap[k + 1]);
     const Kept kp = select_kept<W>(nrm, nv, tau2, capb, sel, isq, sq, S.red);
@@ -501,7 +515,7 @@ __device__ bool move_fast(const MpsArgs& P, const Smem& S, SiteView<T> A, SiteVi
     if (dir) {
         // A[k] <- normalised columns; A[k+1] <- its selected rows, rescaled
         // (rows c of the new A[k+1] are rows sel[c] of the old one, so they
-        // are read before any is written: staged through LDS when it fits)
+        // are read before any is written: staged first)
         for (int idx = tid; idx < 2 * cl * r; idx += W) {
             const int e = idx / r, c = idx - e * r;
             const int v = sel[c];
@@ -511,7 +525,7 @@ __device__ bool move_fast(const MpsArgs& P, const Smem& S, SiteView<T> A, SiteVi
         }
         const int w = 2 * cr;
         Team<W>::sync();
-        if (r * w <= SMAX * (SMAX + 1)) {
+        if (r * w <= vcap) {
             for (int idx = tid; idx < r * w; idx += W) {
                 const int c = idx / w, x = idx - c * w;
                 const int v = sel[c];
@@ -551,7 +565,7 @@ __device__ bool move_fast(const MpsArgs& P, const Smem& S, SiteView<T> A, SiteVi
             Bim[idx] = T(vim[v * ld + e] * is);
         }
         Team<W>::sync();
-        if (2 * cl * r <= SMAX * (SMAX + 1)) {
+        if (2 * cl * r <= vcap) {
             for (int idx = tid; idx < 2 * cl * r; idx += W) {
                 const int row = idx / r, c = idx - row * r;
                 const int v = sel[c];
@@ -678,11 +692,14 @@ __device__ void project(TP thr, TP thi, int m, int n, int r, int dir, int ld, co
 
 // Two-site update of sites k, k+1 with the 4x4 gate gate_id; the centre
 // ends on k+1 (dir 1) or k (dir 0).  Sets chi[k+1] to the new bond.  V holds
-// the vectors (LDS for sides <= SMAX, else the slot's scratch).
+// the vectors (LDS for sides <= SMAX, else the slot's scratch).  Returns
+// false, having written nothing, when the slot's bond capacity is below
+// chi_max and more vectors than it holds pass the threshold and the caller
+// asked for that check (grow): the shot then needs a larger slot.
 template <typename T, int SMAX, int W, typename DP, typename IP>
-__device__ void twosite_update(const MpsArgs& P, const Smem& S, SiteView<T> A, SiteView<T> B,
+__device__ bool twosite_update(const MpsArgs& P, const Smem& S, SiteView<T> A, SiteView<T> B,
                                int k, int dir, int gate_id, double* scr, const Vecs<DP, IP>& V,
-                               ShotAcc& acc) {
+                               ShotAcc& acc, bool grow = false) {
     typedef __attribute__((address_space(1))) T gT;
     typedef __attribute__((address_space(3))) T lT;
     const int tid = Team<W>::rank();
@@ -703,7 +720,7 @@ __device__ void twosite_update(const MpsArgs& P, const Smem& S, SiteView<T> A, S
     // contraction then reads each element from LDS
     const int na = cl * 2 * cm, nb = cm * 2 * cr;
     double nsum[1];
-    if ((size_t)2 * (na + nb) * sizeof(T) <= kStage * sizeof(double)) {
+    if ((size_t)2 * (na + nb) * sizeof(T) <= (size_t)S.n_u * sizeof(double)) {
         lT* st = to_lds(reinterpret_cast<T*>(S.u));
         for (int i = tid; i < na; i += W) {
             st[i] = Are[i];
@@ -732,7 +749,7 @@ __device__ void twosite_update(const MpsArgs& P, const Smem& S, SiteView<T> A, S
     vector_norms<W>(vre, vim, nv, len, ld, nrm);
     const bool rotated = not_orthogonal<W>(vre, vim, nv, len, ld, nrm, floor2, tol, bad, (IP)nullptr);
     // theta's copy for the projection: LDS staging when it fits
-    const bool th_lds = 2 * (size_t)m * n <= (size_t)kStage;
+    const bool th_lds = 2 * (size_t)m * n <= (size_t)S.n_u;
     if (rotated) {
         // keep theta for the projection (the vectors still hold it)
         if (th_lds) {
@@ -773,6 +790,7 @@ __device__ void twosite_update(const MpsArgs& P, const Smem& S, SiteView<T> A, S
     }
     const int capb = min(P.chi_max, S.cap[k + 1]);
     const Kept kp = select_kept<W>(nrm, nv, tau2, capb, sel, V.isq, V.sq, S.red);
+    if (grow && kp.want > capb && capb < P.chi_max) return false;
     const int r = kp.r;
     acc.disc += kp.dropped;
     if (kp.dropped > 1e-12 * total && r == capb) acc.status |= MSC_SHOT_CHI_CAP;
@@ -831,29 +849,30 @@ __device__ void twosite_update(const MpsArgs& P, const Smem& S, SiteView<T> A, S
     ++acc.n2q;
     const double dl = cl, dm = cm, dr = cr, dk = r;
     acc.flops += 32.0 * dl * dm * dr + 32.0 * dl * dl * dr + 32.0 * dk * dl * dr + 104.0 * dl * dl * dl;
+    return true;
 }
 
 // The fold of a product swap: with psi the unentangled qubit's state on
 // site ps (tensor P, pl x 2 x pr), M = sum_i conj(psi_i) P[:, i, :] is
 // formed in FP64 at mr/mi, then the product site receives the neighbour
 // times M: A[k] M (side 1, neighbour ol x 2 x pl) or M A[k+1] (side 0,
-// neighbour pr x 2 x ocr).  Whole workgroup; ends after the writes.
-template <typename T, typename MP, typename OP>
+// neighbour pr x 2 x ocr).  Whole team; ends after the writes.
+template <typename T, int W, typename MP, typename OP>
 __device__ void fold_product(MP mr, MP mi, OP ore, OP oim, SiteView<T> Pv, double p0r,
                              double p0i, double p1r, double p1i, int side, int ol, int pl, int pr,
                              int ocr) {
-    const int tid = threadIdx.x;
-    for (int idx = tid; idx < pl * pr; idx += NT) {
+    const int tid = Team<W>::rank();
+    for (int idx = tid; idx < pl * pr; idx += W) {
         const int a = idx / pr, b = idx - a * pr;
         const int i0 = (a * 2) * pr + b, i1 = i0 + pr;
         const double x0r = Pv.re[i0], x0i = Pv.im[i0], x1r = Pv.re[i1], x1i = Pv.im[i1];
         mr[idx] = p0r * x0r + p0i * x0i + p1r * x1r + p1i * x1i;
         mi[idx] = p0r * x0i - p0i * x0r + p1r * x1i - p1i * x1r;
     }
-    __syncthreads();
+    Team<W>::sync();
     if (side) {
         // product on k+1: new A[k+1] = A[k] M  (ol, 2, pr)
-        for (int idx = tid; idx < ol * 2 * pr; idx += NT) {
+        for (int idx = tid; idx < ol * 2 * pr; idx += W) {
             const int row = idx / pr, c = idx - row * pr;
             double xr = 0.0, xi = 0.0;
 #pragma unroll 2
@@ -869,7 +888,7 @@ __device__ void fold_product(MP mr, MP mi, OP ore, OP oim, SiteView<T> Pv, doubl
     } else {
         // product on k: new A[k] = M A[k+1]  (pl, 2, ocr)
         const int w = 2 * ocr;
-        for (int idx = tid; idx < pl * w; idx += NT) {
+        for (int idx = tid; idx < pl * w; idx += W) {
             const int a = idx / w, rem = idx - a * w;
             double xr = 0.0, xi = 0.0;
 #pragma unroll 2
@@ -893,38 +912,30 @@ __device__ void fold_product(MP mr, MP mi, OP ore, OP oim, SiteView<T> Pv, doubl
 template <typename T, int SMAX>
 constexpr int kMpsWavesPerSimd = (sizeof(T) == sizeof(float) && SMAX == 32) ? 4 : 3;
 
-template <typename T, int SMAX>
-__global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(MpsArgs P) {
-    __shared__ int s_chi[kMaxSites + 1];
-    __shared__ int s_laste[kMaxSites];
-    __shared__ double s_vre[SMAX * (SMAX + 1)];
-    __shared__ double s_vim[SMAX * (SMAX + 1)];
-    __shared__ double s_nrm[SMAX];
-    __shared__ double s_isq[SMAX];
-    __shared__ double s_sq[SMAX];
-    __shared__ int s_sel[SMAX];
-    __shared__ int s_bad[SMAX];
-    __shared__ int s_list[SMAX];
-    __shared__ int s_ired[NW];
-    __shared__ double s_red[NW * 4];
-    __shared__ int s_flag[1];
-    // gate tables, per-site layout of the slot and bond caps, read once
-    __shared__ double s_g1[G1_COUNT * 8];
-    __shared__ int s_g4src[G4_COUNT * 4];
-    __shared__ double s_g4ph[G4_COUNT * 8];
-    __shared__ int32_t s_soff[kMaxSites];    // offsets within a slot (< 2^31 elements)
-    __shared__ int32_t s_shalf[kMaxSites];
-    __shared__ int s_cap[kMaxSites + 1];
-    // op descriptors, kOpBuf at a time
-    __shared__ DevOp s_ops[kOpBuf];
-    // staging: the two site tensors of an update (tensor type), then the
-    // copy of theta kept for the projection (FP64)
-    __shared__ double s_u[kStage];
+// The team's LDS vectors as a Vecs.
+__device__ __forceinline__ Vecs<ldsd*, ldsi*> lds_vecs(const Smem& S) {
+    return Vecs<ldsd*, ldsi*>{to_lds(S.vre), to_lds(S.vim), to_lds(S.nrm), to_lds(S.isq),
+                              to_lds(S.sq),  to_lds(S.sel), to_lds(S.bad), to_lds(S.list)};
+}
 
-    const int tid = threadIdx.x;
+// The next entry of a shared work counter, the same value in every lane of
+// a one-wavefront team.
+__device__ __forceinline__ int64_t wave_fetch(unsigned long long* ctr) {
+    unsigned long long v = 0;
+    if (Team<64>::rank() == 0) v = atomicAdd(ctr, 1ull);
+    return static_cast<int64_t>(__shfl(v, 0));
+}
+
+// The shots of one team (a workgroup, or one wavefront of the wavefront
+// kernel) in its slot `team` of n_teams: each from its fork point (or from
+// |0...0>) through the op stream to its result, op by op.  S is the team's
+// LDS; NOPS op descriptors are held at a time.
+template <typename T, int SMAX, int W, int NOPS>
+__device__ void run_team(const MpsArgs& P, const Smem& S, const int team, const int n_teams) {
+    const int tid = Team<W>::rank();
     const int N = P.n_sites;
-    T* slot_base = static_cast<T*>(P.arena) + (size_t)blockIdx.x * P.slot_stride;
-    double* scr = P.scratch + (size_t)blockIdx.x * P.scratch_stride;
+    T* slot_base = static_cast<T*>(P.arena) + (size_t)team * P.slot_stride;
+    double* scr = P.scratch + (size_t)team * P.scratch_stride;
     // per-vector arrays of SVDs too large for LDS, at the end of the slot's scratch
     double* g_nrm = scr + P.scratch_stride - 6 * MAXV;
     double* g_isq = g_nrm + MAXV;
@@ -933,54 +944,18 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
     int* g_bad = g_sel + MAXV;
     int* g_list = g_bad + MAXV;
 
-    for (int k = tid; k < N; k += NT) {
-        s_soff[k] = P.site_off[k];
-        s_shalf[k] = P.site_half[k];
-    }
-    for (int k = tid; k <= N; k += NT) s_cap[k] = P.cap[k];
-    for (int i = tid; i < G1_COUNT * 8; i += NT) s_g1[i] = P.g1[i];
-    if (tid < G4_COUNT * 4) {
-        // the nonzero of each row of each monomial 4x4 gate, found once
-        const double* g = P.g4 + (tid >> 2) * 32 + (tid & 3) * 8;
-        int src = 0;
-        for (int j = 1; j < 4; ++j)
-            if (fabs(g[2 * j]) + fabs(g[2 * j + 1]) > fabs(g[2 * src]) + fabs(g[2 * src + 1]))
-                src = j;
-        s_g4src[tid] = src;
-        s_g4ph[2 * tid] = g[2 * src];
-        s_g4ph[2 * tid + 1] = g[2 * src + 1];
-    }
-    __syncthreads();
-
-    Smem S;
-    S.chi = s_chi;
-    S.vre = s_vre;
-    S.vim = s_vim;
-    S.nrm = s_nrm;
-    S.isq = s_isq;
-    S.sq = s_sq;
-    S.sel = s_sel;
-    S.bad = s_bad;
-    S.list = s_list;
-    S.ired = s_ired;
-    S.red = s_red;
-    S.cap = s_cap;
-    S.u = s_u;
-    S.g4src = s_g4src;
-    S.g4ph = s_g4ph;
-
     auto site = [&](int k) {
         SiteView<T> v;
-        v.re = to_glb(slot_base + s_soff[k]);
-        v.im = v.re + s_shalf[k];
+        v.re = to_glb(slot_base + S.soff[k]);
+        v.im = v.re + S.shalf[k];
         return v;
     };
 
     const int64_t n_run = P.n_dev ? min(*P.n_dev, P.n_shots) : P.n_shots;
     // with slot states the grid is the slot count and every launch picks up
     // where the slot's last one stopped
-    ShotState* const st = P.state ? P.state + blockIdx.x : nullptr;
-    int64_t j0 = blockIdx.x;
+    ShotState* const st = P.state ? P.state + team : nullptr;
+    int64_t j0 = team;
     bool resume = false;
     if (st) {
         const int status = st->status;
@@ -991,7 +966,18 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
         }
     }
     const bool can_park = st && P.park_side > 0;
-    for (int64_t j = j0; j < n_run; j += gridDim.x) {
+    // the wavefront kernel takes its shots from a shared counter, the
+    // workgroup kernel every n_teams-th one
+    const auto next_j = [&](int64_t jj) -> int64_t {
+        if constexpr (W == 64) {
+            if (P.next) return wave_fetch(P.next);
+        }
+        return jj + n_teams;
+    };
+    if constexpr (W == 64) {
+        if (P.next && !resume) j0 = wave_fetch(P.next);
+    }
+    for (int64_t j = j0; j < n_run; j = next_j(j)) {
         const int64_t it = P.perm ? P.perm[j] : j;
         const int64_t shot = P.shot_idx ? P.shot_idx[it] : it;
         if (shot < 0 || shot >= P.n_csr) {
@@ -1022,13 +1008,14 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
             const int jj = fcur < fend ? next_ch / P.ck_k : P.n_ck - 1;
             jck = jj < navail ? jj : navail - 1;
         }
+        bool retried = false;         // handed to the workgroup kernel
         int next_ck = 0;              // record mode: next checkpoint to take
         int64_t ck_pos = 0;           // record mode: elements written so far
         bool ck_full = false;
         if (resume) {
             // ---- continue a parked shot after its large update
-            for (int k = tid; k <= N; k += NT) s_chi[k] = st->chi[k];
-            for (int k = tid; k < N; k += NT) s_laste[k] = st->laste[k];
+            for (int k = tid; k <= N; k += W) S.chi[k] = st->chi[k];
+            for (int k = tid; k < N; k += W) S.laste[k] = st->laste[k];
             fcur = st->fcur;
             next_ch = st->next_ch;
             fcode = st->fcode;
@@ -1053,16 +1040,16 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
         }
         if (jck >= 0) {
             const CkHdr& h = P.ck_hdr[jck];
-            for (int k = tid; k <= N; k += NT) s_chi[k] = h.chi[k];
-            for (int k = tid; k < N; k += NT) s_laste[k] = h.laste[k];
-            __syncthreads();
+            for (int k = tid; k <= N; k += W) S.chi[k] = h.chi[k];
+            for (int k = tid; k < N; k += W) S.laste[k] = h.laste[k];
+            Team<W>::sync();
             const __attribute__((address_space(1))) T* src =
                 to_glb(static_cast<const T*>(P.ck_data)) + P.ck_off[jck];
             int64_t o = 0;
             for (int k = 0; k < N; ++k) {
-                const int ne = s_chi[k] * 2 * s_chi[k + 1];
+                const int ne = S.chi[k] * 2 * S.chi[k + 1];
                 SiteView<T> v = site(k);
-                for (int idx = tid; idx < ne; idx += NT) {
+                for (int idx = tid; idx < ne; idx += W) {
                     v.re[idx] = src[o + idx];
                     v.im[idx] = src[o + ne + idx];
                 }
@@ -1084,9 +1071,9 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
             }
         } else if (jck == -1) {
             // ---- initial product state |0...0>
-            for (int k = tid; k <= N; k += NT) s_chi[k] = 1;
-            for (int k = tid; k < N; k += NT) {
-                s_laste[k] = 0;
+            for (int k = tid; k <= N; k += W) S.chi[k] = 1;
+            for (int k = tid; k < N; k += W) {
+                S.laste[k] = 0;
                 SiteView<T> v = site(k);
                 v.re[0] = T(1);
                 v.re[1] = T(0);
@@ -1094,36 +1081,36 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
                 v.im[1] = T(0);
             }
         }
-        __syncthreads();
+        Team<W>::sync();
         int ops_lo = 0, ops_hi = 0;   // op range held in s_ops
 
         for (int oi = start; oi < P.n_ops && alive; ++oi) {
             if (oi >= ops_hi) {
-                __syncthreads();
+                Team<W>::sync();
                 ops_lo = oi;
-                ops_hi = min(P.n_ops, oi + kOpBuf);
-                for (int i = tid; i < ops_hi - ops_lo; i += NT) s_ops[i] = P.ops[ops_lo + i];
-                __syncthreads();
+                ops_hi = min(P.n_ops, oi + NOPS);
+                for (int i = tid; i < ops_hi - ops_lo; i += W) S.ops[i] = P.ops[ops_lo + i];
+                Team<W>::sync();
             }
             if (P.ck_mode == 1 && !ck_full && next_ck < P.n_ck && P.ck_op[next_ck] == oi) {
                 // ---- record: the state before op oi, densely, site by site
                 int64_t sz = 0;
-                for (int k = 0; k < N; ++k) sz += 4 * (int64_t)s_chi[k] * s_chi[k + 1];
+                for (int k = 0; k < N; ++k) sz += 4 * (int64_t)S.chi[k] * S.chi[k + 1];
                 if (ck_pos + sz <= P.ck_cap) {
                     __attribute__((address_space(1))) T* dst = to_glb(static_cast<T*>(P.ck_data)) + ck_pos;
                     int64_t o = 0;
                     for (int k = 0; k < N; ++k) {
-                        const int ne = s_chi[k] * 2 * s_chi[k + 1];
+                        const int ne = S.chi[k] * 2 * S.chi[k + 1];
                         SiteView<T> v = site(k);
-                        for (int idx = tid; idx < ne; idx += NT) {
+                        for (int idx = tid; idx < ne; idx += W) {
                             dst[o + idx] = v.re[idx];
                             dst[o + ne + idx] = v.im[idx];
                         }
                         o += 2 * ne;
                     }
                     CkHdr& h = P.ck_hdr[next_ck];
-                    for (int k = tid; k <= N; k += NT) h.chi[k] = s_chi[k];
-                    for (int k = tid; k < N; k += NT) h.laste[k] = s_laste[k];
+                    for (int k = tid; k <= N; k += W) h.chi[k] = S.chi[k];
+                    for (int k = tid; k < N; k += W) h.laste[k] = S.laste[k];
                     if (tid == 0) {
                         h.p_acc = p_acc;
                         h.meas_done = meas_done;
@@ -1133,35 +1120,51 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
                         P.ck_off[next_ck] = ck_pos;
                     }
                     ck_pos += sz;
-                    __syncthreads();
+                    Team<W>::sync();
                     if (tid == 0) *P.ck_avail = next_ck + 1;
                     ++next_ck;
                 } else {
                     ck_full = true;
                 }
             }
-            const DevOp op = s_ops[oi - ops_lo];
+            const DevOp op = S.ops[oi - ops_lo];
             bool twosite = op.kind == OP_G2;
             int gate_id = op.aux;
             if (op.kind == OP_MOVE) {
                 // ---- move the centre by one site: one wavefront does the
                 // usual case (orthogonal vectors, small sides)
                 const int k = op.a, dir = op.b;
-                const int cl = s_chi[k], cm = s_chi[k + 1], cr = s_chi[k + 2];
+                const int cl = S.chi[k], cm = S.chi[k + 1], cr = S.chi[k + 2];
                 const int nv = cm, len = dir ? 2 * cl : 2 * cr;
                 SiteView<T> A = site(k), B = site(k + 1);
                 bool fast = false;
-                if (nv <= SMAX && len <= SMAX) {
+                if constexpr (W == 64) {
+                    // one wavefront: LDS vectors, or the slot's scratch after
+                    // the staging area of the rescaled neighbour
+                    if (nv <= SMAX && len <= SMAX) {
+                        fast = move_fast<T, 64>(P, S, A, B, k, dir, lds_vecs(S), SMAX * (SMAX + 1),
+                                                scr, acc);
+                    } else {
+                        glbd* vre = to_glb(scr + 4 * (size_t)cm * max(cl, cr));
+                        const Vecs<glbd*, glbi*> V{vre, vre + (size_t)nv * (len + 1),
+                                                   to_glb(g_nrm), to_glb(g_isq), to_glb(g_sq),
+                                                   to_glb(g_sel), to_glb(g_bad), to_glb(g_list)};
+                        fast = move_fast<T, 64>(P, S, A, B, k, dir, V, 0, scr, acc);
+                    }
+                    Team<W>::sync();
+                } else if (nv <= SMAX && len <= SMAX) {
                     if (nv <= kWaveSide && len <= kWaveSide) {
                         if (tid < 64) {
-                            const bool f = move_fast<T, SMAX, 64>(P, S, A, B, k, dir, scr, acc);
-                            if (tid == 0) s_flag[0] = f;
+                            const bool f = move_fast<T, 64>(P, S, A, B, k, dir, lds_vecs(S),
+                                                            SMAX * (SMAX + 1), scr, acc);
+                            if (tid == 0) S.flag[0] = f;
                         }
-                        __syncthreads();
-                        fast = s_flag[0] != 0;
+                        Team<W>::sync();
+                        fast = S.flag[0] != 0;
                     } else {
-                        fast = move_fast<T, SMAX, NT>(P, S, A, B, k, dir, scr, acc);
-                        __syncthreads();
+                        fast = move_fast<T, NT>(P, S, A, B, k, dir, lds_vecs(S), SMAX * (SMAX + 1),
+                                                scr, acc);
+                        Team<W>::sync();
                     }
                 }
                 if (!fast) {
@@ -1176,7 +1179,7 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
                 if (op.kind == OP_G1) {
                     g0 = op.aux;
                 } else if (op.kind == OP_RESET) {
-                    if (s_laste[op.a] == 1) g0 = G_X;
+                    if (S.laste[op.a] == 1) g0 = G_X;
                 } else if (op.kind == OP_FAULT3) {
                     const int x2 = (fcode >> 4) & 1, z2 = (fcode >> 5) & 1;
                     if (x2 | z2) g0 = (x2 && z2) ? G_Y : (x2 ? G_X : G_Z);
@@ -1197,12 +1200,12 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
                     const int gid = h == 0 ? g0 : g1;
                     if (gid < 0) continue;
                     const int k = h == 0 ? op.a : op.b;
-                    const double* m = s_g1 + gid * 8;
+                    const double* m = S.g1 + gid * 8;
                     const double m0 = m[0], m1 = m[1], m2 = m[2], m3 = m[3];
                     const double m4 = m[4], m5 = m[5], m6 = m[6], m7 = m[7];
                     SiteView<T> v = site(k);
-                    const int cl = s_chi[k], cr = s_chi[k + 1];
-                    for (int idx = tid; idx < cl * cr; idx += NT) {
+                    const int cl = S.chi[k], cr = S.chi[k + 1];
+                    for (int idx = tid; idx < cl * cr; idx += W) {
                         const int a = idx / cr, b = idx - a * cr;
                         const int i0 = (a * 2) * cr + b, i1 = i0 + cr;
                         const double x0r = v.re[i0], x0i = v.im[i0], x1r = v.re[i1], x1i = v.im[i1];
@@ -1211,7 +1214,7 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
                         v.re[i1] = T(m4 * x0r - m5 * x0i + m6 * x1r - m7 * x1i);
                         v.im[i1] = T(m4 * x0i + m5 * x0r + m6 * x1i + m7 * x1r);
                     }
-                    __syncthreads();
+                    Team<W>::sync();
                 }
             } else if (op.kind == OP_SWAPP) {
                 // ---- SWAP with a qubit that is unentangled in every shot:
@@ -1221,9 +1224,9 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
                 const int k = op.a, side = op.b;
                 const int ps = k + side, os = k + 1 - side;
                 SiteView<T> Pv = site(ps), Ov = site(os);
-                const int pl = s_chi[ps], pr = s_chi[ps + 1];
+                const int pl = S.chi[ps], pr = S.chi[ps + 1];
                 double r4[4] = {0.0, 0.0, 0.0, 0.0};
-                for (int idx = tid; idx < pl * pr; idx += NT) {
+                for (int idx = tid; idx < pl * pr; idx += W) {
                     const int a = idx / pr, b = idx - a * pr;
                     const int i0 = (a * 2) * pr + b, i1 = i0 + pr;
                     const double x0r = Pv.re[i0], x0i = Pv.im[i0], x1r = Pv.re[i1], x1i = Pv.im[i1];
@@ -1232,7 +1235,7 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
                     r4[2] += x0r * x1r + x0i * x1i;     // rho01 = x0 conj(x1)
                     r4[3] += x0i * x1r - x0r * x1i;
                 }
-                team_sum<NT, 4>(r4, s_red);
+                team_sum<W, 4>(r4, S.red);
                 const double tr = r4[0] + r4[1];
                 double p0r, p0i, p1r, p1i;               // psi, unit norm
                 if (r4[1] > r4[0]) {
@@ -1250,48 +1253,48 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
                 }
                 // M = sum_i conj(psi_i) P[:, i, :] (pl x pr, FP64), then the
                 // neighbour times M; in LDS (neighbour staged) when it fits
-                const int ol = s_chi[k], ocr = s_chi[k + 2];
+                const int ol = S.chi[k], ocr = S.chi[k + 2];
                 const int on = side ? ol * 2 * pl : pr * 2 * ocr;   // neighbour elements
                 const int newb = side ? ol : ocr;
                 if (pl * pr <= SMAX * (SMAX + 1) &&
-                    (size_t)2 * on * sizeof(T) <= kStage * sizeof(double)) {
+                    (size_t)2 * on * sizeof(T) <= (size_t)S.n_u * sizeof(double)) {
                     typedef __attribute__((address_space(3))) T lT;
-                    lT* st = to_lds(reinterpret_cast<T*>(s_u));
-                    for (int idx = tid; idx < on; idx += NT) {
+                    lT* st = to_lds(reinterpret_cast<T*>(S.u));
+                    for (int idx = tid; idx < on; idx += W) {
                         st[idx] = Ov.re[idx];
                         st[on + idx] = Ov.im[idx];
                     }
-                    fold_product<T>(to_lds(s_vre), to_lds(s_vim), st, st + on, Pv, p0r, p0i, p1r,
-                                    p1i, side, ol, pl, pr, ocr);
+                    fold_product<T, W>(to_lds(S.vre), to_lds(S.vim), st, st + on, Pv, p0r, p0i,
+                                       p1r, p1i, side, ol, pl, pr, ocr);
                 } else {
                     glbd* mr = to_glb(scr);
-                    fold_product<T>(mr, mr + (size_t)pl * pr, Ov.re, Ov.im, Pv, p0r, p0i, p1r,
-                                    p1i, side, ol, pl, pr, ocr);
+                    fold_product<T, W>(mr, mr + (size_t)pl * pr, Ov.re, Ov.im, Pv, p0r, p0i, p1r,
+                                       p1i, side, ol, pl, pr, ocr);
                 }
-                __syncthreads();
+                Team<W>::sync();
                 // the unentangled qubit on the other site: psi (x) identity
-                for (int idx = tid; idx < newb * 2 * newb; idx += NT) {
+                for (int idx = tid; idx < newb * 2 * newb; idx += W) {
                     const int a = idx / (2 * newb), rem = idx - a * 2 * newb;
                     const int i = rem / newb, a2 = rem - i * newb;
                     const bool diag = a == a2;
                     Ov.re[idx] = T(diag ? (i ? p1r : p0r) : 0.0);
                     Ov.im[idx] = T(diag ? (i ? p1i : p0i) : 0.0);
                 }
-                if (tid == 0) s_chi[k + 1] = newb;
-                __syncthreads();
+                if (tid == 0) S.chi[k + 1] = newb;
+                Team<W>::sync();
             } else if (op.kind == OP_MEAS) {
                 const int k = op.a;
                 SiteView<T> v = site(k);
-                const int cl = s_chi[k], cr = s_chi[k + 1];
+                const int cl = S.chi[k], cr = S.chi[k + 1];
                 double pp[2] = {0.0, 0.0};
-                for (int idx = tid; idx < cl * cr; idx += NT) {
+                for (int idx = tid; idx < cl * cr; idx += W) {
                     const int a = idx / cr, b = idx - a * cr;
                     const int i0 = (a * 2) * cr + b, i1 = i0 + cr;
                     const double x0r = v.re[i0], x0i = v.im[i0], x1r = v.re[i1], x1i = v.im[i1];
                     pp[0] += x0r * x0r + x0i * x0i;
                     pp[1] += x1r * x1r + x1i * x1i;
                 }
-                team_sum<NT, 2>(pp, s_red);
+                team_sum<W, 2>(pp, S.red);
                 const double tot = pp[0] + pp[1];
                 int e;
                 if (P.calibrate) e = pp[1] > pp[0] ? 1 : 0;
@@ -1320,7 +1323,7 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
                 p_acc *= pe;
                 meas_done = op.aux + 1;
                 const double sc = 1.0 / sqrt(raw);
-                for (int idx = tid; idx < cl * cr; idx += NT) {
+                for (int idx = tid; idx < cl * cr; idx += W) {
                     const int a = idx / cr, b = idx - a * cr;
                     const int ie = (a * 2 + e) * cr + b, io = (a * 2 + 1 - e) * cr + b;
                     v.re[ie] = T(static_cast<double>(v.re[ie]) * sc);
@@ -1328,14 +1331,14 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
                     v.re[io] = T(0);
                     v.im[io] = T(0);
                 }
-                if (tid == 0) s_laste[k] = e;
-                __syncthreads();
+                if (tid == 0) S.laste[k] = e;
+                Team<W>::sync();
             } else if (op.kind == OP_FINAL) {
                 const int k = op.a;
                 SiteView<T> v = site(k);
-                const int cl = s_chi[k], cr = s_chi[k + 1];
+                const int cl = S.chi[k], cr = S.chi[k + 1];
                 double r[4] = {0.0, 0.0, 0.0, 0.0};   // r00, r11, Re r01, Im r01
-                for (int idx = tid; idx < cl * cr; idx += NT) {
+                for (int idx = tid; idx < cl * cr; idx += W) {
                     const int a = idx / cr, b = idx - a * cr;
                     const int i0 = (a * 2) * cr + b, i1 = i0 + cr;
                     const double x0r = v.re[i0], x0i = v.im[i0], x1r = v.re[i1], x1i = v.im[i1];
@@ -1345,7 +1348,7 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
                     r[2] += x0r * x1r + x0i * x1i;
                     r[3] += x0i * x1r - x0r * x1i;
                 }
-                team_sum<NT, 4>(r, s_red);
+                team_sum<W, 4>(r, S.red);
                 const double tr = r[0] + r[1];
                 // f = |t0|^2 rho00 + |t1|^2 rho11 + 2 Re(conj(t0) t1 rho01)
                 const double ctr = P.t0r * P.t1r + P.t0i * P.t1i;   // conj(t0) t1
@@ -1358,13 +1361,13 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
             if (twosite) {
                 // ---- two-site update on sites k, k+1
                 const int k = op.a, dir = op.b;
-                const int m = 2 * s_chi[k], n = 2 * s_chi[k + 2];
+                const int m = 2 * S.chi[k], n = 2 * S.chi[k + 2];
                 SiteView<T> A = site(k), B = site(k + 1);
                 if (can_park && max(m, n) > P.park_side) {
                     // ---- hand the update to the batched engine: save the
                     // shot, queue the slot and free the workgroup
-                    for (int q = tid; q <= N; q += NT) st->chi[q] = s_chi[q];
-                    for (int q = tid; q < N; q += NT) st->laste[q] = s_laste[q];
+                    for (int q = tid; q <= N; q += W) st->chi[q] = S.chi[q];
+                    for (int q = tid; q < N; q += W) st->laste[q] = S.laste[q];
                     if (tid == 0) {
                         st->j = j;
                         st->fcur = fcur;
@@ -1391,19 +1394,25 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
                         st->dir = dir;
                         st->gate_id = gate_id;
                         st->status = kSlotParked;
-                        P.park_list[atomicAdd(P.park_count, 1)] = blockIdx.x;
+                        P.park_list[atomicAdd(P.park_count, 1)] = team;
                     }
                     return;
                 }
+                // the wavefront kernel's slots hold smaller bonds than
+                // chi_max: a shot that outgrows them is handed on (grow)
+                const bool grow = P.retry_list != nullptr;
+                bool ok = true;
                 if (m <= SMAX && n <= SMAX) {
-                    const Vecs<ldsd*, ldsi*> V{to_lds(s_vre), to_lds(s_vim), to_lds(s_nrm),
-                                               to_lds(s_isq), to_lds(s_sq), to_lds(s_sel),
-                                               to_lds(s_bad), to_lds(s_list)};
-                    if (m <= kWaveSide && n <= kWaveSide) {
+                    if constexpr (W == 64) {
+                        ok = twosite_update<T, SMAX, 64>(P, S, A, B, k, dir, gate_id, scr,
+                                                         lds_vecs(S), acc, grow);
+                    } else if (m <= kWaveSide && n <= kWaveSide) {
                         if (tid < 64)
-                            twosite_update<T, SMAX, 64>(P, S, A, B, k, dir, gate_id, scr, V, acc);
+                            twosite_update<T, SMAX, 64>(P, S, A, B, k, dir, gate_id, scr,
+                                                        lds_vecs(S), acc);
                     } else {
-                        twosite_update<T, SMAX, NT>(P, S, A, B, k, dir, gate_id, scr, V, acc);
+                        twosite_update<T, SMAX, NT>(P, S, A, B, k, dir, gate_id, scr, lds_vecs(S),
+                                                    acc);
                     }
                 } else {
                     // vectors in the slot's scratch after theta's copy
@@ -1412,12 +1421,19 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
                     const Vecs<glbd*, glbi*> V{vre, vre + (size_t)nv * ld, to_glb(g_nrm),
                                                to_glb(g_isq), to_glb(g_sq), to_glb(g_sel),
                                                to_glb(g_bad), to_glb(g_list)};
-                    twosite_update<T, SMAX, NT>(P, S, A, B, k, dir, gate_id, scr, V, acc);
+                    ok = twosite_update<T, SMAX, W>(P, S, A, B, k, dir, gate_id, scr, V, acc, grow);
                 }
-                __syncthreads();
+                Team<W>::sync();
+                if (!ok) {
+                    // a larger slot is needed: the shot is queued for the
+                    // workgroup kernel, which runs it again from its start
+                    if (tid == 0) P.retry_list[atomicAdd(P.retry_count, 1)] = it;
+                    retried = true;
+                    break;
+                }
             }
         }
-        if (tid == 0) {
+        if (tid == 0 && !retried) {
             if (P.surv)
                 for (int g = next_seg; g < P.n_seg; ++g) P.surv[it * P.n_seg + g] = p_acc;
             msc_shot_result res;
@@ -1433,9 +1449,166 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
             res.sweeps = acc.sweeps;
             P.out[it] = res;
         }
-        __syncthreads();
+        Team<W>::sync();
     }
     if (st && tid == 0) st->status = kSlotDone;
+}
+
+template <typename T, int SMAX>
+__global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(MpsArgs P) {
+    __shared__ int s_chi[kMaxSites + 1];
+    __shared__ int s_laste[kMaxSites];
+    __shared__ double s_vre[SMAX * (SMAX + 1)];
+    __shared__ double s_vim[SMAX * (SMAX + 1)];
+    __shared__ double s_nrm[SMAX];
+    __shared__ double s_isq[SMAX];
+    __shared__ double s_sq[SMAX];
+    __shared__ int s_sel[SMAX];
+    __shared__ int s_bad[SMAX];
+    __shared__ int s_list[SMAX];
+    __shared__ int s_ired[NW];
+    __shared__ double s_red[NW * 4];
+    __shared__ int s_flag[1];
+    // gate tables, per-site layout of the slot and bond caps, read once
+    __shared__ double s_g1[G1_COUNT * 8];
+    __shared__ int s_g4src[G4_COUNT * 4];
+    __shared__ double s_g4ph[G4_COUNT * 8];
+    __shared__ int32_t s_soff[kMaxSites];    // offsets within a slot (< 2^31 elements)
+    __shared__ int32_t s_shalf[kMaxSites];
+    __shared__ int s_cap[kMaxSites + 1];
+    // op descriptors, kOpBuf at a time
+    __shared__ DevOp s_ops[kOpBuf];
+    // staging: the two site tensors of an update (tensor type), then the
+    // copy of theta kept for the projection (FP64)
+    __shared__ double s_u[kStage];
+
+    const int tid = threadIdx.x;
+
+    for (int k = tid; k < P.n_sites; k += NT) {
+        s_soff[k] = P.site_off[k];
+        s_shalf[k] = P.site_half[k];
+    }
+    for (int k = tid; k <= P.n_sites; k += NT) s_cap[k] = P.cap[k];
+    for (int i = tid; i < G1_COUNT * 8; i += NT) s_g1[i] = P.g1[i];
+    if (tid < G4_COUNT * 4) {
+        // the nonzero of each row of each monomial 4x4 gate, found once
+        const double* g = P.g4 + (tid >> 2) * 32 + (tid & 3) * 8;
+        int src = 0;
+        for (int j = 1; j < 4; ++j)
+            if (fabs(g[2 * j]) + fabs(g[2 * j + 1]) > fabs(g[2 * src]) + fabs(g[2 * src + 1]))
+                src = j;
+        s_g4src[tid] = src;
+        s_g4ph[2 * tid] = g[2 * src];
+        s_g4ph[2 * tid + 1] = g[2 * src + 1];
+    }
+    __syncthreads();
+
+    Smem S;
+    S.chi = s_chi;
+    S.vre = s_vre;
+    S.vim = s_vim;
+    S.nrm = s_nrm;
+    S.isq = s_isq;
+    S.sq = s_sq;
+    S.sel = s_sel;
+    S.bad = s_bad;
+    S.list = s_list;
+    S.ired = s_ired;
+    S.red = s_red;
+    S.cap = s_cap;
+    S.u = s_u;
+    S.g4src = s_g4src;
+    S.g4ph = s_g4ph;
+    S.laste = s_laste;
+    S.flag = s_flag;
+    S.ops = s_ops;
+    S.soff = s_soff;
+    S.shalf = s_shalf;
+    S.g1 = s_g1;
+    S.n_u = kStage;
+    run_team<T, SMAX, NT, kOpBuf>(P, S, blockIdx.x, gridDim.x);
+}
+
+
+// One shot per wavefront, four per workgroup, for shots whose bonds stay
+// small: no workgroup barrier after the tables are loaded, so the waves of a
+// workgroup run their shots independently and a CU holds twelve resident
+// shots instead of four.  The slots' bonds are capped below chi_max; a shot
+// that outgrows them is queued (retry_list) and run again from its start by
+// the workgroup kernel.  Factorisations with both theta sides <= kWaveSmax
+// keep their vectors in LDS, wider ones (up to twice the slot's bond cap) in
+// the slot's scratch.
+constexpr int kWaveSmax = 16;
+constexpr int kWaveOps = 16;
+constexpr int kWaveStage = 512;
+
+template <typename T>
+__global__ __launch_bounds__(NT, 3) void mps_wave_kernel(MpsArgs P) {
+    // per wavefront
+    __shared__ int s_chi[NW][kMaxSites + 1];
+    __shared__ int s_laste[NW][kMaxSites];
+    __shared__ double s_vre[NW][kWaveSmax * (kWaveSmax + 1)];
+    __shared__ double s_vim[NW][kWaveSmax * (kWaveSmax + 1)];
+    __shared__ double s_nrm[NW][kWaveSmax];
+    __shared__ double s_isq[NW][kWaveSmax];
+    __shared__ double s_sq[NW][kWaveSmax];
+    __shared__ int s_sel[NW][kWaveSmax];
+    __shared__ int s_bad[NW][kWaveSmax];
+    __shared__ int s_list[NW][kWaveSmax];
+    __shared__ int s_flag[NW][1];
+    __shared__ DevOp s_ops[NW][kWaveOps];
+    __shared__ double s_u[NW][kWaveStage];
+    // per workgroup, read-only after the start
+    __shared__ double s_g1[G1_COUNT * 8];
+    __shared__ int s_g4src[G4_COUNT * 4];
+    __shared__ double s_g4ph[G4_COUNT * 8];
+    __shared__ int32_t s_soff[kMaxSites];
+    __shared__ int32_t s_shalf[kMaxSites];
+    __shared__ int s_cap[kMaxSites + 1];
+
+    const int tid = threadIdx.x;
+    for (int k = tid; k < P.n_sites; k += NT) {
+        s_soff[k] = P.site_off[k];
+        s_shalf[k] = P.site_half[k];
+    }
+    for (int k = tid; k <= P.n_sites; k += NT) s_cap[k] = P.cap[k];
+    for (int i = tid; i < G1_COUNT * 8; i += NT) s_g1[i] = P.g1[i];
+    if (tid < G4_COUNT * 4) {
+        const double* g = P.g4 + (tid >> 2) * 32 + (tid & 3) * 8;
+        int src = 0;
+        for (int j = 1; j < 4; ++j)
+            if (fabs(g[2 * j]) + fabs(g[2 * j + 1]) > fabs(g[2 * src]) + fabs(g[2 * src + 1]))
+                src = j;
+        s_g4src[tid] = src;
+        s_g4ph[2 * tid] = g[2 * src];
+        s_g4ph[2 * tid + 1] = g[2 * src + 1];
+    }
+    __syncthreads();
+    const int w = tid >> 6;
+    Smem S;
+    S.chi = s_chi[w];
+    S.laste = s_laste[w];
+    S.vre = s_vre[w];
+    S.vim = s_vim[w];
+    S.nrm = s_nrm[w];
+    S.isq = s_isq[w];
+    S.sq = s_sq[w];
+    S.sel = s_sel[w];
+    S.bad = s_bad[w];
+    S.list = s_list[w];
+    S.ired = nullptr;   // one-wavefront teams reduce in registers
+    S.red = nullptr;
+    S.flag = s_flag[w];
+    S.ops = s_ops[w];
+    S.u = s_u[w];
+    S.n_u = kWaveStage;
+    S.cap = s_cap;
+    S.g4src = s_g4src;
+    S.g4ph = s_g4ph;
+    S.soff = s_soff;
+    S.shalf = s_shalf;
+    S.g1 = s_g1;
+    run_team<T, kWaveSmax, 64, kWaveOps>(P, S, blockIdx.x * NW + w, gridDim.x * NW);
 }
 
 // ---------------------------------------------------------------------------
@@ -1933,6 +2106,29 @@ int mps_blocks_per_cu(int precision, bool small) {
         return 1;
     }
     return b < 1 ? 1 : b;
+}
+
+int mps_wave_blocks_per_cu(int precision) {
+    int b = 0;
+    hipError_t e = precision == MSC_FP64
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, mps_wave_kernel<double>, NT, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, mps_wave_kernel<float>, NT, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return b < 1 ? 1 : b;
+}
+
+hipError_t launch_mps_wave(int precision, const MpsArgs& a, int grid, hipStream_t s) {
+    static_assert(kWaveTeams == NW, "one team per wavefront");
+    if (!a.next || !a.retry_count || !a.retry_list || a.calibrate || a.state)
+        return hipErrorInvalidValue;
+    if (precision == MSC_FP64)
+        hipLaunchKernelGGL(mps_wave_kernel<double>, dim3(grid), dim3(NT), 0, s, a);
+    else
+        hipLaunchKernelGGL(mps_wave_kernel<float>, dim3(grid), dim3(NT), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_order(int64_t n, const int64_t* n_dev, const int64_t* shot_off,

@@ -82,7 +82,7 @@ int set_error(int code, const std::string& msg);
 // shot kernel): built on first use by msc_simulate with prefix = 1.
 struct PrefixCk {
     bool valid = false;
-    int dev = -1, precision = -1, chi_max = 0, lds_width = 0, park_side = 0;
+    int dev = -1, precision = -1, chi_max = 0, lds_width = 0, park_side = 0, wave_chi = 0;
     double tau = 0.0, tau_rej = 0.0;
     int n_ck = 0, ck_k = 1, avail = 0;
     int64_t cap = 0;           // elements of the tensor type

@@ -45,6 +45,7 @@ def test_struct_sizes_match_header():
     assert C.sizeof(_lib.CircuitInfo) == 72
     assert C.sizeof(_lib.Estimate) == 48
     assert C.sizeof(_lib.BatchStats) == 88
+    assert C.sizeof(_lib.EngineStats) == 120
 
 
 @pytest.mark.parametrize("text,frag", [

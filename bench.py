@@ -94,6 +94,11 @@ def main() -> int:
                          "noiseless-run checkpoint before its first fault")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device (counter calibration)")
+    ap.add_argument("--engine-only", action="store_true",
+                    help="only the large-bond engine lines (autotune, 81-qubit bond-64 and "
+                         "49-qubit bond-128 workloads) and the chi = 256 contraction kernels")
+    ap.add_argument("--wave-chi", type=int, default=0,
+                    help="bond cap of the wavefront kernel's slots (0: automatic, -1: off)")
     args = ap.parse_args()
     # one hardware queue per stream in flight plus torch's own: with fewer,
     # streams share queues and their kernels run one after the other.  Read
@@ -125,6 +130,13 @@ def main() -> int:
     from workloads.circuits import config_circuit
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.engine_only:
+        ctx = msc.Ctx(0)
+        out = {"large_bond_engine": engine_lines(msc, ctx, args),
+               "contraction_chi256": contraction_lines(msc, ctx, torch)}
+        ctx.close()
+        print(json.dumps(out), flush=True)
+        return 0
     cc = config_circuit("c3")
     ctx = msc.Ctx(0)
     # the MPS layout: the snake order, or the order the local search finds
@@ -168,7 +180,7 @@ def main() -> int:
         # the per-weight bin sums, with one synchronisation at the end
         bins, st = msc.run_batch(c, circ, seed, b * n, n, p, n_bins=wmax + 1,
                                  precision=msc.MSC_FP32, chi_max=args.chi_max,
-                                 lds_width=args.lds_width, prefix=not args.no_prefix,
+                                 lds_width=args.lds_width, wave_chi=args.wave_chi, prefix=not args.no_prefix,
                                  n_slots=args.slots)
         return st, bins
 
@@ -212,7 +224,7 @@ def main() -> int:
         off0, ch0, pa0 = sample(ctx, 0)
         msc.simulate(ctx, circ, off0, ch0, pa0, shot_idx=torch.zeros(1, dtype=torch.int64,
                                                                      device="cuda"),
-                     precision=msc.MSC_FP32, chi_max=args.chi_max, lds_width=args.lds_width,
+                     precision=msc.MSC_FP32, chi_max=args.chi_max, lds_width=args.lds_width, wave_chi=args.wave_chi,
                      prefix=True)
         prefix_ms = ctx.last_kernel_ms("prefix")
         log(f"noiseless-prefix checkpoints built in {prefix_ms:.1f} ms")
@@ -238,6 +250,11 @@ def main() -> int:
     # With one step in flight the launches do not overlap, so this is the
     # rate the kernel trace of the same command gives per launch.
     achieved = float(np.mean(flops)) / (float(np.mean(sim_ms)) * 1e-3) / 1e12
+    # which shot kernel ran the steps: the wavefront kernel (one shot per
+    # wavefront) or the workgroup kernel
+    wave_slots = ctxs[0].engine_stats()["wave_slots"]
+    kernel_name = ("mps_wave_kernel<float>" if wave_slots else
+                   f"mps_kernel<float,{64 if args.lds_width == 64 else 32}>")
     achieved_job = sum(flops) / wall / 1e12
     sweeps = sum(st["sweeps"] for st in sts)
     log(f"steps={args.steps} wall={wall:.3f}s value={value:.1f} shots/s survivors={n_surv} "
@@ -295,9 +312,9 @@ def main() -> int:
                       "prescreen_mean": float(np.mean(screen_ms)),
                       "sample_mean": float(np.mean(sample_ms))},
         "roofline": {"bound": "alu",
-                     "kernel": f"mps_kernel<float,{64 if args.lds_width == 64 else 32}>",
+                     "kernel": kernel_name, "slots": wave_slots or None,
                      "achieved": achieved, "peak": PEAK_FP32, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32, "traffic": measured_traffic(layout_key),
+                     "frac": achieved / PEAK_FP32, "traffic": measured_traffic(layout_key, kernel_name),
                      "launch_ms": float(np.mean(sim_ms)),
                      "flops_per_launch": float(np.mean(flops)),
                      "achieved_whole_job": achieved_job,
@@ -324,7 +341,7 @@ def main() -> int:
         sub_screen_ms = ctx.last_kernel_ms("prescreen")
         res32 = msc.results_numpy(msc.simulate(ctx, circ, off, ch, pa, shot_idx=idx0,
                                                precision=msc.MSC_FP32, chi_max=args.chi_max,
-                                               lds_width=args.lds_width,
+                                               lds_width=args.lds_width, wave_chi=args.wave_chi,
                                                prefix=not args.no_prefix))
         def one_shot_fp64(k, prefix):
             # the same kernels in FP64, one survivor per launch (one
@@ -402,7 +419,7 @@ def main() -> int:
             bb, sb = msc.run_batch(ctx, circ, SEED, warmup * n + b * n4, n4, args.p,
                                    n_bins=wmax + 1,
                                    precision=msc.MSC_FP32, chi_max=args.chi_max,
-                                   lds_width=args.lds_width, prefix=not args.no_prefix,
+                                   lds_width=args.lds_width, wave_chi=args.wave_chi, prefix=not args.no_prefix,
                                    space_time=True)
             st_n += bb[0]
             st_s += sb["surv_bins"]
@@ -417,31 +434,7 @@ def main() -> int:
             "segments": len(segs), "shots": n_st * n4,
             "shots_per_s_single_stream": n_st * n4 / t_st}
 
-        # fixed-shape chi = 256 two-site contraction on MFMA, FP32 and BF16x3
-        from workloads.tensors import random_twosite
-        chi, batch = 256, 512
-        A, B, G, _, _, _ = random_twosite(chi, 1, 0x5EED0103)
-        dA = torch.from_numpy(A).cuda().repeat(batch, 1, 1, 1).contiguous()
-        dB = torch.from_numpy(B).cuda().repeat(batch, 1, 1, 1).contiguous()
-        dG = torch.from_numpy(G).cuda()
-        outs = {}
-        for name, prec, peak in (("fp32", msc.MSC_FP32, PEAK_FP32),
-                                 ("bf16x3", msc.MSC_BF16X3, PEAK_BF16_MFMA / 3.0)):
-            th = torch.empty(batch * 2 * (2 * chi) ** 2, dtype=torch.float32, device="cuda")
-            msc.twosite_contract(ctx, chi, batch, dA, dB, dG, th, precision=prec)
-            ms = []
-            for _ in range(5):
-                msc.twosite_contract(ctx, chi, batch, dA, dB, dG, th, precision=prec)
-                ms.append(ctx.last_kernel_ms("twosite"))
-            fl = batch * (32.0 * chi ** 3 + 128.0 * chi ** 2)
-            tf = fl / (np.mean(ms) * 1e-3) / 1e12
-            outs[name] = th[: 2 * (2 * chi) ** 2].double().cpu().numpy()
-            result["contraction_chi256_" + name] = {
-                "kernel": "twosite_kernel" if name == "fp32" else "twosite_bf16x3_kernel",
-                "batch": batch, "ms": float(np.mean(ms)), "achieved": tf, "peak": peak,
-                "unit": "TFLOP/s", "frac": tf / peak}
-        rel = float(np.linalg.norm(outs["bf16x3"] - outs["fp32"]) / np.linalg.norm(outs["fp32"]))
-        result["contraction_chi256_bf16x3"]["rel_error_vs_fp32"] = rel
+        result.update(contraction_lines(msc, ctx, torch))
         # offline screen at scale: 2^24 shots of the 81-qubit circuit's
         # skeleton (faults drawn on the GPU, p = 1e-3), bit-exact against
         # the oracle in the test suite; algorithmic bytes per shot: its CSR
@@ -523,13 +516,14 @@ def benchmark_layout(msc, ctx, text: str, seed: int = ORDER_SEED, budget: int = 
     return order, info
 
 
-def measured_traffic(layout_key: str):
-    """HBM bytes per shot-kernel launch from the committed counter summary,
-    or None when the kernel source or the layout changed since the counters
-    were taken."""
+def measured_traffic(layout_key: str, kernel_name: str):
+    """HBM bytes per shot-kernel launch from the committed counter summary of
+    that kernel, or None when the kernel source or the layout changed since
+    the counters were taken."""
     import hashlib
     src = os.path.join(ROOT, "paper_2609_19116_amd", "csrc", "kernels", "mps.hip")
-    summ = os.path.join(ROOT, "profiles", "mps_kernel_c3_hbm_counters.md")
+    base = "mps_wave_kernel" if kernel_name.startswith("mps_wave_kernel") else "mps_kernel"
+    summ = os.path.join(ROOT, "profiles", f"{base}_c3_hbm_counters.md")
     if not os.path.exists(summ):
         return None
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
@@ -542,6 +536,38 @@ def measured_traffic(layout_key: str):
     if vals.get("kernel_sha256_16") != sha or vals.get("layout") != layout_key:
         return None
     return float(vals["traffic_bytes_per_launch"])
+
+
+def contraction_lines(msc, ctx, torch) -> dict:
+    """The fixed-shape chi = 256 two-site contraction on MFMA (FP32 and
+    BF16x3), batch 512: time per launch (HIP events), TFLOP/s against the
+    peak of the product's dtype, and BF16x3's relative error against FP32."""
+    from workloads.tensors import random_twosite
+    result = {}
+    chi, batch = 256, 512
+    A, B, G, _, _, _ = random_twosite(chi, 1, 0x5EED0103)
+    dA = torch.from_numpy(A).cuda().repeat(batch, 1, 1, 1).contiguous()
+    dB = torch.from_numpy(B).cuda().repeat(batch, 1, 1, 1).contiguous()
+    dG = torch.from_numpy(G).cuda()
+    outs = {}
+    for name, prec, peak in (("fp32", msc.MSC_FP32, PEAK_FP32),
+                             ("bf16x3", msc.MSC_BF16X3, PEAK_BF16_MFMA / 3.0)):
+        th = torch.empty(batch * 2 * (2 * chi) ** 2, dtype=torch.float32, device="cuda")
+        msc.twosite_contract(ctx, chi, batch, dA, dB, dG, th, precision=prec)
+        ms = []
+        for _ in range(5):
+            msc.twosite_contract(ctx, chi, batch, dA, dB, dG, th, precision=prec)
+            ms.append(ctx.last_kernel_ms("twosite"))
+        fl = batch * (32.0 * chi ** 3 + 128.0 * chi ** 2)
+        tf = fl / (np.mean(ms) * 1e-3) / 1e12
+        outs[name] = th[: 2 * (2 * chi) ** 2].double().cpu().numpy()
+        result["contraction_chi256_" + name] = {
+            "kernel": "twosite_kernel" if name == "fp32" else "twosite_bf16x3_kernel",
+            "batch": batch, "ms": float(np.mean(ms)), "achieved": tf, "peak": peak,
+            "unit": "TFLOP/s", "frac": tf / peak}
+    rel = float(np.linalg.norm(outs["bf16x3"] - outs["fp32"]) / np.linalg.norm(outs["fp32"]))
+    result["contraction_chi256_bf16x3"]["rel_error_vs_fp32"] = rel
+    return result
 
 
 def engine_lines(msc, ctx, args) -> dict:

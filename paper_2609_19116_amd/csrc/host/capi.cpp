@@ -341,7 +341,7 @@ struct RunCfg {
     double tau = 1e-12, tau_rej = 1e-6, tau_fail = 1e-4;
     int n_slots = 0;
     int lds_width = 32;
-    int park_side = 64;          // 0: the shot kernel does every update
+    int park_side = 0;           // 0: the shot kernel does every update
     int wave_chi = 0;            // > 0: one shot per wavefront in slots of this bond cap
     bool graphs = false;
     LxTiles tiles[kLxBuckets];
@@ -500,8 +500,10 @@ static int enqueue_wave(msc_ctx* ctx, const msc_circuit* c, const RunCfg& cfg, i
     a.retry_list = static_cast<int64_t*>(dlist);
     ctx->lx_stats = msc_engine_stats{};
     MSC_HIP(hipMemsetAsync(dctr, 0, 16, ctx->stream));
+    void* otmp;
+    if ((rc = ctx_buf(ctx, "order_tmp", order_tmp_bytes(n), &otmp))) return rc;
     MSC_HIP(launch_order(n, n_dev, off, shot_idx, n_csr, chan,
-                         a.ck_mode == 2 ? c->n_channels : 0, static_cast<int64_t*>(dperm),
+                         a.ck_mode == 2 ? c->n_channels : 0, static_cast<int64_t*>(dperm), otmp,
                          ctx->stream));
     MSC_HIP(launch_mps_wave(precision, a, grid, ctx->stream));
     int32_t n_retry = 0;
@@ -589,10 +591,13 @@ static int enqueue_shots(msc_ctx* ctx, const msc_circuit* c, const RunCfg& cfg, 
                                 reinterpret_cast<unsigned long long*>(static_cast<double*>(dflops) + 2),
                                 ctx->stream));
     }
-    if (!perm_in)
+    if (!perm_in) {
+        void* otmp;
+        if ((rc = ctx_buf(ctx, "order_tmp", order_tmp_bytes(n), &otmp))) return rc;
         MSC_HIP(launch_order(n, n_dev, off, shot_idx, n_csr, chan,
                              a.ck_mode == 2 ? c->n_channels : 0, static_cast<int64_t*>(dperm),
-                             ctx->stream));
+                             otmp, ctx->stream));
+    }
     if (engine) MSC_HIP(hipEventRecord(ctx->lxev[4], ctx->stream));
     MSC_HIP(launch_mps(precision, small, a, n_slots, ctx->stream));
     if (engine) MSC_HIP(hipEventRecord(ctx->lxev[5], ctx->stream));
@@ -1228,9 +1233,11 @@ extern "C" int msc_run_batch(msc_ctx* ctx, const msc_circuit* c, const msc_sim_o
                        static_cast<double*>(dsurv), nullptr);
     if (rc) return rc;
     MSC_HIP(hipEventRecord(ctx->ev3, ctx->stream));
+    void* dred;
+    if ((rc = ctx_buf(ctx, "b_reduce", batch_reduce_tmp_bytes(n_shots, n_bins, n_seg), &dred))) return rc;
     MSC_HIP(launch_batch_reduce(n_shots, seed, first_shot, offp, idxp, nsurv, res, n_bins, nnz,
                                 hbins, htot, static_cast<const double*>(dsurv), n_seg, hsurv,
-                                ctx->stream));
+                                dred, ctx->stream));
     if (out) MSC_HIP(launch_scatter_results(n_shots, nsurv, idxp, res, out, ctx->stream));
     MSC_HIP(hipStreamSynchronize(ctx->stream));
     const double* hb = static_cast<const double*>(ctx->hmap);

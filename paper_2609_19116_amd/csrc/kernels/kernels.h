@@ -128,7 +128,9 @@ hipError_t launch_mps(int precision, bool small, const MpsArgs& a, int grid, hip
 // shots last): the order in which their remaining work shrinks
 hipError_t launch_order(int64_t n, const int64_t* n_dev, const int64_t* shot_off,
                         const int64_t* shot_idx, int64_t n_csr, const int32_t* chan,
-                        int32_t n_channels, int64_t* perm, hipStream_t s);
+                        int32_t n_channels, int64_t* perm, void* tmp, hipStream_t s);
+// bytes of launch_order's tmp for n entries (per-chunk key counts and offsets)
+int64_t order_tmp_bytes(int64_t n);
 // resident workgroups per CU of the chosen variant (sizes the persistent grid)
 int mps_blocks_per_cu(int precision, bool small);
 // One shot per wavefront (four per workgroup of 256 threads): grid
@@ -184,7 +186,9 @@ hipError_t launch_batch_reduce(int64_t n, uint64_t seed, uint64_t first, const i
                                const int64_t* idx, const int64_t* n_surv,
                                const msc_shot_result* res, int nb, const int64_t* nnz,
                                double* bins, BatchTotals* tot, const double* surv, int n_seg,
-                               double* sbins, hipStream_t s);
+                               double* sbins, void* tmp, hipStream_t s);
+// bytes of launch_batch_reduce's tmp (per-chunk partial sums)
+int64_t batch_reduce_tmp_bytes(int64_t n, int nb, int n_seg);
 // idx[i] = i for i < n and *count = n (every shot a survivor)
 hipError_t launch_identity(int64_t n, int64_t* idx, int64_t* count, hipStream_t s);
 hipError_t launch_scatter_results(int64_t n, const int64_t* n_surv, const int64_t* idx,

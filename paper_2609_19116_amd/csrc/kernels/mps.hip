@@ -33,6 +33,8 @@
 // descriptors, gate tables and the slot layout are served from LDS.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cfloat>
 #include <cstdint>
 
@@ -2040,53 +2042,117 @@ __global__ __launch_bounds__(NT) void lx_factor_kernel(LxArgs a, LxFactor f) {
 // online screening stops the others early.  With checkpoints a shot starts
 // at its first fault, so the key is the position of that channel in the
 // circuit (fault-free shots, which only read out, last).
-// One 256-thread workgroup (small enough to find room beside resident shot
-// kernels of other streams).
+// Three launches over chunks of kOrderChunk entries: per-chunk key counts,
+// one exclusive scan of them in (key, chunk) order, and a stable scatter in
+// which each workgroup ranks its chunk's entries by ballots.
 constexpr int OT = 256;
-__global__ __launch_bounds__(OT) void order_kernel(int64_t n, const int64_t* n_dev,
-                                                   const int64_t* shot_off,
-                                                   const int64_t* shot_idx, int64_t n_csr,
-                                                   const int32_t* chan, int32_t n_channels,
-                                                   int64_t* perm) {
-    __shared__ int64_t s_base;
-    if (n_dev && *n_dev < n) n = *n_dev;
-    __shared__ int s_wcnt[OT / 64];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if (tid == 0) s_base = 0;
-    __syncthreads();
-    for (int key = 0; key < 16; ++key) {
-        for (int64_t base = 0; base < n; base += OT) {
-            const int64_t j = base + tid;
-            bool hit = false;
-            if (j < n) {
-                const int64_t sh = shot_idx ? shot_idx[j] : j;
-                int c = 15;
-                if (sh >= 0 && sh < n_csr) {
-                    const int64_t f0 = shot_off[sh], f = shot_off[sh + 1] - f0;
-                    if (n_channels > 0) {
-                        const int64_t ch = f > 0 ? chan[f0] : n_channels;
-                        c = ch < 0 ? 0 : ch >= n_channels ? 15
-                                                          : static_cast<int>(ch * 15 / n_channels);
-                    } else {
-                        c = f < 15 ? static_cast<int>(f) : 15;
-                    }
-                }
-                hit = c == key;
-            }
-            const uint64_t m = __ballot(hit);
-            if (lane == 0) s_wcnt[w] = __popcll(m);
-            __syncthreads();
-            int64_t off = s_base;
-            for (int q = 0; q < w; ++q) off += s_wcnt[q];
-            if (hit) perm[off + __popcll(m & ((1ull << lane) - 1ull))] = j;
-            __syncthreads();
-            if (tid == 0) {
-                int64_t t = 0;
-                for (int q = 0; q < OT / 64; ++q) t += s_wcnt[q];
-                s_base += t;
-            }
-            __syncthreads();
+constexpr int kOrderItems = 16;
+constexpr int kOrderChunk = OT * kOrderItems;
+
+__device__ __forceinline__ int order_key(int64_t j, const int64_t* shot_off,
+                                         const int64_t* shot_idx, int64_t n_csr,
+                                         const int32_t* chan, int32_t n_channels) {
+    const int64_t sh = shot_idx ? shot_idx[j] : j;
+    int c = 15;
+    if (sh >= 0 && sh < n_csr) {
+        const int64_t f0 = shot_off[sh], f = shot_off[sh + 1] - f0;
+        if (n_channels > 0) {
+            const int64_t ch = f > 0 ? chan[f0] : n_channels;
+            c = ch < 0 ? 0 : ch >= n_channels ? 15 : static_cast<int>(ch * 15 / n_channels);
+        } else {
+            c = f < 15 ? static_cast<int>(f) : 15;
         }
+    }
+    return c;
+}
+
+// cnt[key * nblk + block]: entries of the chunk with that key
+__global__ __launch_bounds__(OT) void order_count_kernel(int64_t n, const int64_t* n_dev,
+                                                         const int64_t* shot_off,
+                                                         const int64_t* shot_idx, int64_t n_csr,
+                                                         const int32_t* chan, int32_t n_channels,
+                                                         int32_t* cnt, int nblk) {
+    __shared__ int s_cnt[16];
+    if (n_dev && *n_dev < n) n = *n_dev;
+    const int tid = threadIdx.x;
+    if (tid < 16) s_cnt[tid] = 0;
+    __syncthreads();
+    const int64_t j0 = static_cast<int64_t>(blockIdx.x) * kOrderChunk;
+    for (int i = 0; i < kOrderItems; ++i) {
+        const int64_t j = j0 + static_cast<int64_t>(i) * OT + tid;
+        if (j < n) atomicAdd(&s_cnt[order_key(j, shot_off, shot_idx, n_csr, chan, n_channels)], 1);
+    }
+    __syncthreads();
+    if (tid < 16) cnt[tid * nblk + blockIdx.x] = s_cnt[tid];
+}
+
+// base[e] = sum of cnt[0 .. e) over the 16 * nblk entries (one workgroup)
+__global__ __launch_bounds__(OT) void order_scan_kernel(const int32_t* cnt, int64_t* base,
+                                                        int64_t total) {
+    __shared__ int64_t s_part[OT];
+    const int tid = threadIdx.x;
+    const int64_t per = (total + OT - 1) / OT;
+    const int64_t e0 = min(total, tid * per), e1 = min(total, e0 + per);
+    int64_t sum = 0;
+    for (int64_t e = e0; e < e1; ++e) sum += cnt[e];
+    s_part[tid] = sum;
+    __syncthreads();
+    if (tid == 0) {
+        int64_t run = 0;
+        for (int q = 0; q < OT; ++q) {
+            const int64_t v = s_part[q];
+            s_part[q] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    int64_t run = s_part[tid];
+    for (int64_t e = e0; e < e1; ++e) {
+        base[e] = run;
+        run += cnt[e];
+    }
+}
+
+// perm[base + rank] = j for the chunk's entries, in index order per key
+__global__ __launch_bounds__(OT) void order_scatter_kernel(int64_t n, const int64_t* n_dev,
+                                                           const int64_t* shot_off,
+                                                           const int64_t* shot_idx,
+                                                           int64_t n_csr, const int32_t* chan,
+                                                           int32_t n_channels,
+                                                           const int64_t* base, int nblk,
+                                                           int64_t* perm) {
+    __shared__ int64_t s_base[16];
+    __shared__ int s_wc[OT / 64][16];
+    if (n_dev && *n_dev < n) n = *n_dev;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid < 16) s_base[tid] = base[tid * nblk + blockIdx.x];
+    __syncthreads();
+    const int64_t j0 = static_cast<int64_t>(blockIdx.x) * kOrderChunk;
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int i = 0; i < kOrderItems; ++i) {
+        const int64_t j = j0 + static_cast<int64_t>(i) * OT + tid;
+        const int key = j < n ? order_key(j, shot_off, shot_idx, n_csr, chan, n_channels) : -1;
+        uint64_t mine = 0;
+        int wc = 0;
+        for (int k = 0; k < 16; ++k) {
+            const uint64_t m = __ballot(key == k);
+            if (key == k) mine = m;
+            if (lane == k) wc = __popcll(m);
+        }
+        if (lane < 16) s_wc[w][lane] = wc;
+        __syncthreads();
+        if (key >= 0) {
+            int64_t pos = s_base[key];
+            for (int q = 0; q < w; ++q) pos += s_wc[q][key];
+            perm[pos + __popcll(mine & below)] = j;
+        }
+        __syncthreads();
+        if (tid < 16) {
+            int t = 0;
+            for (int q = 0; q < OT / 64; ++q) t += s_wc[q][tid];
+            s_base[tid] += t;
+        }
+        __syncthreads();
     }
 }
 
@@ -2131,12 +2197,28 @@ hipError_t launch_mps_wave(int precision, const MpsArgs& a, int grid, hipStream_
     return hipGetLastError();
 }
 
+int64_t order_tmp_bytes(int64_t n) {
+    const int64_t nblk = (std::max<int64_t>(n, 1) + kOrderChunk - 1) / kOrderChunk;
+    return 16 * nblk * static_cast<int64_t>(sizeof(int32_t) + sizeof(int64_t));
+}
+
 hipError_t launch_order(int64_t n, const int64_t* n_dev, const int64_t* shot_off,
                         const int64_t* shot_idx, int64_t n_csr, const int32_t* chan,
-                        int32_t n_channels, int64_t* perm, hipStream_t s) {
+                        int32_t n_channels, int64_t* perm, void* tmp, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(order_kernel, dim3(1), dim3(OT), 0, s, n, n_dev, shot_off, shot_idx, n_csr,
-                       chan, n_channels, perm);
+    const int64_t nblk = (n + kOrderChunk - 1) / kOrderChunk;
+    if (nblk > (int64_t(1) << 24)) return hipErrorInvalidValue;
+    int64_t* base = static_cast<int64_t*>(tmp);
+    int32_t* cnt = reinterpret_cast<int32_t*>(base + 16 * nblk);
+    const int nb = static_cast<int>(nblk);
+    hipLaunchKernelGGL(order_count_kernel, dim3(nb), dim3(OT), 0, s, n, n_dev, shot_off, shot_idx,
+                       n_csr, chan, n_channels, cnt, nb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(OT), 0, s, cnt, base, 16 * nblk);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(order_scatter_kernel, dim3(nb), dim3(OT), 0, s, n, n_dev, shot_off,
+                       shot_idx, n_csr, chan, n_channels, base, nb, perm);
     return hipGetLastError();
 }
 

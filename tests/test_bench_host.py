@@ -55,17 +55,22 @@ def test_measured_traffic_requires_matching_kernel_and_layout(tmp_path, monkeypa
     src.parent.mkdir(parents=True)
     src.write_bytes(b"kernel source v1")
     sha = hashlib.sha256(b"kernel source v1").hexdigest()[:16]
-    prof = tmp_path / "profiles" / "mps_kernel_c3_hbm_counters.md"
-    prof.parent.mkdir()
-    prof.write_text(f"header\n\ntraffic_bytes_per_launch: 1.5e+08\nkernel_sha256_16: {sha}\n"
-                    "layout: search 3x128 +4 from 0x5eed0081\n")
+    (tmp_path / "profiles").mkdir()
+    lay = "search 3x128 +4 from 0x5eed0081"
+    for name, val in (("mps_kernel", "1.5e+08"), ("mps_wave_kernel", "2.5e+08")):
+        (tmp_path / "profiles" / f"{name}_c3_hbm_counters.md").write_text(
+            f"header\n\ntraffic_bytes_per_launch: {val}\nkernel_sha256_16: {sha}\n"
+            f"layout: {lay}\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic("search 3x128 +4 from 0x5eed0081") == 1.5e8
-    assert bench.measured_traffic("snake") is None
+    # each shot kernel reads its own summary
+    assert bench.measured_traffic(lay, "mps_kernel<float,32>") == 1.5e8
+    assert bench.measured_traffic(lay, "mps_wave_kernel<float>") == 2.5e8
+    assert bench.measured_traffic("snake", "mps_wave_kernel<float>") is None
     src.write_bytes(b"kernel source v2")
-    assert bench.measured_traffic("search 3x128 +4 from 0x5eed0081") is None
-    prof.unlink()
-    assert bench.measured_traffic("search 3x128 +4 from 0x5eed0081") is None
+    assert bench.measured_traffic(lay, "mps_kernel<float,32>") is None
+    assert bench.measured_traffic(lay, "mps_wave_kernel<float>") is None
+    (tmp_path / "profiles" / "mps_kernel_c3_hbm_counters.md").unlink()
+    assert bench.measured_traffic(lay, "mps_kernel<float,32>") is None
 
 
 def test_bench_refuses_more_than_one_gpu():

@@ -7,7 +7,8 @@ tensors, for all parked shots at once.  Forcing it onto small updates
 (large_side = 2) runs it on every shape of the small circuits; the results
 are compared per shot with the CPU oracle (P_acc and f within 1e-10
 relative in FP64, 1e-5 in FP32, rejection index and failure flag exact) and
-with the shot kernel alone (large_side = -1).  Graph replay, the slot
+with the shot kernel alone (large_side = -1); the workgroup kernel runs
+every shot here (wave_chi = -1), the one that parks.  Graph replay, the slot
 count and prefix forking change no bit of a result.  The 81-qubit circuit reaches bond 64
 (theta sides 128) and the 49-qubit circuit on the rainbow layout bond 128
 (sides 256); with large_side = 64 the engine takes their wide updates, and
@@ -77,13 +78,14 @@ def test_engine_on_every_update_matches_oracle(ctx, name, n, precision):
     c, csr, ref = _stratified(ctx, name, n, 0x5EED0031)
     off, ch, pa = to_dev(*csr)
     say(f"engine {name} precision={precision} large_side=2")
-    res = results_numpy(msc.simulate(ctx, c, off, ch, pa, precision=precision, large_side=2))
+    res = results_numpy(msc.simulate(ctx, c, off, ch, pa, precision=precision, large_side=2,
+                                     wave_chi=-1))
     st = ctx.engine_stats()
     assert st["updates"] > 0 and st["contract_flops"] > 0 and st["gram_flops"] > 0
     _compare(res, ref, TOL[precision])
     say(f"shot kernel alone {name} precision={precision}")
     alone = results_numpy(msc.simulate(ctx, c, off, ch, pa, precision=precision,
-                                       large_side=-1))
+                                       large_side=-1, wave_chi=-1))
     assert ctx.engine_stats()["updates"] == 0
     acc = alone["p_acc"] > 0
     # the two factorisations may pick different bases of degenerate singular
@@ -100,7 +102,7 @@ def test_engine_graphs_and_prefix_change_no_bit(ctx, lds_width):
     c, csr, ref = _stratified(ctx, "c1", 160, 0x5EED0032)
     off, ch, pa = to_dev(*csr)
     say(f"engine graphs/prefix lds_width={lds_width}")
-    kw = dict(precision=MSC_FP32, large_side=4, lds_width=lds_width)
+    kw = dict(precision=MSC_FP32, large_side=4, lds_width=lds_width, wave_chi=-1)
     base = results_numpy(msc.simulate(ctx, c, off, ch, pa, **kw))
     assert ctx.engine_stats()["rounds"] > 0
     g1 = results_numpy(msc.simulate(ctx, c, off, ch, pa, use_graphs=True, **kw))
@@ -121,7 +123,8 @@ def test_engine_c3_stratified(ctx, precision):
     c, csr, ref = _stratified(ctx, "c3", 30, 0x5EED0033)
     off, ch, pa = to_dev(*csr)
     say(f"engine c3 precision={precision} large_side=8")
-    res = results_numpy(msc.simulate(ctx, c, off, ch, pa, precision=precision, large_side=8))
+    res = results_numpy(msc.simulate(ctx, c, off, ch, pa, precision=precision, large_side=8,
+                                     wave_chi=-1))
     assert ctx.engine_stats()["updates"] > 0
     _compare(res, ref, TOL[precision])
 
@@ -151,7 +154,7 @@ def test_engine_golden_large_bonds(ctx, name, chi, precision, use_graphs):
     idx = torch.tensor(shots, dtype=torch.int64, device="cuda")
     say(f"engine golden {name} precision={precision} graphs={use_graphs}")
     res = results_numpy(msc.simulate(ctx, c, off, ch, pa, shot_idx=idx, precision=precision,
-                                     use_graphs=use_graphs, large_side=64))
+                                     use_graphs=use_graphs, large_side=64, wave_chi=-1))
     assert ctx.engine_stats()["updates"] > 0
     _compare(res, ref, TOL[precision])
     acc = ref[:, 0] > 0
@@ -174,7 +177,7 @@ def test_autotune_cache_roundtrip_and_tile_independence(ctx, tmp_path):
         {(p, b) for p in (MSC_FP32, MSC_FP64) for b in range(4)}
     for e in e32 + e64:
         assert e["rows"] > 0 and e["b"] > 0 and e["gram"] > 0 and e["contract_us"] > 0
-    kw = dict(precision=MSC_FP32, large_side=4)
+    kw = dict(precision=MSC_FP32, large_side=4, wave_chi=-1)
     base = results_numpy(msc.simulate(ctx, c, off, ch, pa, **kw))
     tuned = results_numpy(msc.simulate(ctx, c, off, ch, pa, autotune_cache=path, **kw))
     for f in FIELDS:
@@ -204,7 +207,7 @@ def test_engine_bf16x3_golden_large_bonds(ctx, name, chi):
     idx = torch.tensor([s["shot"] for s in g["shots"]], dtype=torch.int64, device="cuda")
     say(f"engine golden {name} BF16x3")
     res = results_numpy(msc.simulate(ctx, c, off, ch, pa, shot_idx=idx,
-                                     precision=msc.MSC_BF16X3, large_side=64))
+                                     precision=msc.MSC_BF16X3, large_side=64, wave_chi=-1))
     assert ctx.engine_stats()["updates"] > 0
     _compare(res, ref, 1e-4)
     acc = ref[:, 0] > 0

@@ -27,6 +27,7 @@ of the reported rates come from the timed shots.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -97,6 +98,9 @@ def main() -> int:
     ap.add_argument("--engine-only", action="store_true",
                     help="only the large-bond engine lines (autotune, 81-qubit bond-64 and "
                          "49-qubit bond-128 workloads) and the chi = 256 contraction kernels")
+    ap.add_argument("--order-cache", default=None,
+                    help="JSON file holding the searched layout: read when it matches the "
+                         "search options, else written after the search")
     ap.add_argument("--wave-chi", type=int, default=0,
                     help="bond cap of the wavefront kernel's slots (0: automatic, -1: off)")
     args = ap.parse_args()
@@ -145,9 +149,26 @@ def main() -> int:
     order_info = None
     order = None
     if args.order_search > 0:
-        order, order_info = benchmark_layout(msc, ctx, cc.text, args.order_seed,
-                                             args.order_search, args.order_starts,
-                                             args.order_refine)
+        key = {"seed": args.order_seed, "budget": args.order_search,
+               "starts": args.order_starts, "refine": args.order_refine,
+               "circuit": hashlib.sha256(cc.text.encode()).hexdigest()[:16]}
+        cached = None
+        if args.order_cache and os.path.exists(args.order_cache):
+            with open(args.order_cache) as f:
+                cached = json.load(f)
+            if cached.get("key") != key:
+                cached = None
+        if cached is not None:
+            order, order_info = np.array(cached["order"], dtype=np.int32), cached["info"]
+            order_info["from_cache"] = args.order_cache
+        else:
+            order, order_info = benchmark_layout(msc, ctx, cc.text, args.order_seed,
+                                                 args.order_search, args.order_starts,
+                                                 args.order_refine)
+            if args.order_cache:
+                with open(args.order_cache, "w") as f:
+                    json.dump({"key": key, "order": [int(q) for q in order],
+                               "info": order_info}, f)
         log(f"order search: cost {order_info['snake_cost']:.4g} -> "
             f"{order_info['searched_cost']:.4g}")
     layout_key = (f"search {max(1, args.order_starts)}x{args.order_search} "

@@ -925,7 +925,11 @@ __device__ __forceinline__ Vecs<ldsd*, ldsi*> lds_vecs(const Smem& S) {
 __device__ __forceinline__ int64_t wave_fetch(unsigned long long* ctr) {
     unsigned long long v = 0;
     if (Team<64>::rank() == 0) v = atomicAdd(ctr, 1ull);
-    return static_cast<int64_t>(__shfl(v, 0));
+    // lane 0's value, read into scalar registers: the compiler then treats
+    // the shot index and everything derived from it as wave-uniform
+    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(v), 0);
+    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(v >> 32), 0);
+    return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
 }
 
 // The shots of one team (a workgroup, or one wavefront of the wavefront
@@ -1586,7 +1590,9 @@ __global__ __launch_bounds__(NT, 3) void mps_wave_kernel(MpsArgs P) {
         s_g4ph[2 * tid + 1] = g[2 * src + 1];
     }
     __syncthreads();
-    const int w = tid >> 6;
+    // the wavefront's index, as a scalar: its LDS arrays and slot are then
+    // addressed with scalar registers
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     Smem S;
     S.chi = s_chi[w];
     S.laste = s_laste[w];

@@ -1015,6 +1015,8 @@ __device__ void run_team(const MpsArgs& P, const Smem& S, const int team, const 
             jck = jj < navail ? jj : navail - 1;
         }
         bool retried = false;         // handed to the workgroup kernel
+        // forked at the read-out checkpoint: its dense tensors, read in place
+        const __attribute__((address_space(1))) T* final_src = nullptr;
         int next_ck = 0;              // record mode: next checkpoint to take
         int64_t ck_pos = 0;           // record mode: elements written so far
         bool ck_full = false;
@@ -1051,15 +1053,21 @@ __device__ void run_team(const MpsArgs& P, const Smem& S, const int team, const 
             Team<W>::sync();
             const __attribute__((address_space(1))) T* src =
                 to_glb(static_cast<const T*>(P.ck_data)) + P.ck_off[jck];
-            int64_t o = 0;
-            for (int k = 0; k < N; ++k) {
-                const int ne = S.chi[k] * 2 * S.chi[k + 1];
-                SiteView<T> v = site(k);
-                for (int idx = tid; idx < ne; idx += W) {
-                    v.re[idx] = src[o + idx];
-                    v.im[idx] = src[o + ne + idx];
+            if (jck == P.n_ck - 1) {
+                // the checkpoint before the read-out: the only op left reads
+                // one site, so the shot reads the checkpoint in place
+                final_src = src;
+            } else {
+                int64_t o = 0;
+                for (int k = 0; k < N; ++k) {
+                    const int ne = S.chi[k] * 2 * S.chi[k + 1];
+                    SiteView<T> v = site(k);
+                    for (int idx = tid; idx < ne; idx += W) {
+                        v.re[idx] = src[o + idx];
+                        v.im[idx] = src[o + ne + idx];
+                    }
+                    o += 2 * ne;
                 }
-                o += 2 * ne;
             }
             p_acc = h.p_acc;
             acc.disc = h.disc;
@@ -1342,6 +1350,14 @@ __device__ void run_team(const MpsArgs& P, const Smem& S, const int team, const 
             } else if (op.kind == OP_FINAL) {
                 const int k = op.a;
                 SiteView<T> v = site(k);
+                if (final_src) {
+                    // site k of the dense checkpoint: planes of chi_j 2 chi_j+1
+                    // elements per site, real then imaginary
+                    int64_t o = 0;
+                    for (int q = 0; q < k; ++q) o += 4 * (int64_t)S.chi[q] * S.chi[q + 1];
+                    v.re = const_cast<__attribute__((address_space(1))) T*>(final_src + o);
+                    v.im = v.re + 2 * S.chi[k] * S.chi[k + 1];
+                }
                 const int cl = S.chi[k], cr = S.chi[k + 1];
                 double r[4] = {0.0, 0.0, 0.0, 0.0};   // r00, r11, Re r01, Im r01
                 for (int idx = tid; idx < cl * cr; idx += W) {

@@ -238,7 +238,7 @@ static void free_device(msc_circuit* c) {
     free_camps_prefix(c->camps_prefix);
     if (c->dev < 0) return;
     (void)hipSetDevice(c->dev);
-    for (void** p : {&c->d_ops, &c->d_g1, &c->d_g4, &c->d_sig, &c->d_expected, &c->d_kind,
+    for (void** p : {&c->d_ops, &c->d_g1, &c->d_g4, &c->d_sig, &c->d_sig_off, &c->d_expected, &c->d_kind,
                      &c->d_segm, &c->d_camps_ops, &c->d_chan_q, &c->d_site_of, &c->d_dmat,
                      &c->d_dtab}) {
         if (*p) (void)hipFree(*p);
@@ -270,7 +270,28 @@ static int upload(msc_ctx* ctx, msc_circuit* c) {
     if ((rc = put(&c->d_ops, c->ops.data(), c->ops.size() * sizeof(DevOp)))) return rc;
     if ((rc = put(&c->d_g1, g1.data(), g1.size() * sizeof(double)))) return rc;
     if ((rc = put(&c->d_g4, g4.data(), g4.size() * sizeof(double)))) return rc;
-    if ((rc = put(&c->d_sig, c->sig.data(), c->sig.size() * sizeof(uint64_t)))) return rc;
+    // the screen's table: per channel and Pauli code the XOR of the code's
+    // basis-component signatures (one lookup per fault)
+    {
+        const int W = c->words;
+        std::vector<int32_t> soff(std::max(1, c->n_channels));
+        std::vector<uint64_t> comb;
+        for (int ch = 0; ch < c->n_channels; ++ch) {
+            const int k = c->chan_kind[ch];
+            const int codes = k == CH_DEP1 ? 4 : k == CH_DEP2 ? 16 : k == CH_XERR ? 2 : 64;
+            soff[ch] = static_cast<int32_t>(comb.size() / std::max(1, W));
+            for (int p = 0; p < codes; ++p)
+                for (int w = 0; w < W; ++w) {
+                    uint64_t x = 0;
+                    for (int b = 0; b < kFaultComponents; ++b)
+                        if ((p >> b) & 1)
+                            x ^= c->sig[(static_cast<size_t>(ch) * kFaultComponents + b) * W + w];
+                    comb.push_back(x);
+                }
+        }
+        if ((rc = put(&c->d_sig, comb.data(), comb.size() * sizeof(uint64_t)))) return rc;
+        if ((rc = put(&c->d_sig_off, soff.data(), soff.size() * sizeof(int32_t)))) return rc;
+    }
     if ((rc = put(&c->d_expected, c->expected.data(), c->expected.size()))) return rc;
     std::vector<uint8_t> kind(c->chan_kind.begin(), c->chan_kind.end());
     if ((rc = put(&c->d_kind, kind.data(), kind.size()))) return rc;
@@ -1020,6 +1041,7 @@ static int screen_into(msc_ctx* ctx, const msc_circuit* c, int64_t n_shots,
     MSC_HIP(hipEventRecord(ctx->ev0, ctx->stream));
     MSC_HIP(launch_prescreen(c->words, c->n_channels, n_shots, shot_off, chan, pauli,
                              static_cast<const uint64_t*>(c->d_sig),
+                             static_cast<const int32_t*>(c->d_sig_off),
                              static_cast<const uint8_t*>(c->d_kind), survive_bits, survivor_idx,
                              tmp, nt, flag, ctx->stream));
     MSC_HIP(hipEventRecord(ctx->ev1, ctx->stream));
@@ -1222,6 +1244,7 @@ extern "C" int msc_run_batch(msc_ctx* ctx, const msc_circuit* c, const msc_sim_o
         MSC_HIP(launch_prescreen(c->words, c->n_channels, n_shots, offp,
                                  static_cast<int32_t*>(dchan), static_cast<uint8_t*>(dpa),
                                  static_cast<const uint64_t*>(c->d_sig),
+                             static_cast<const int32_t*>(c->d_sig_off),
                                  static_cast<const uint8_t*>(c->d_kind),
                                  static_cast<uint64_t*>(dbits), idxp, static_cast<int64_t*>(dtp),
                                  ntp, csr_flag, ctx->stream));

@@ -147,9 +147,12 @@ enum CsrFlag : int {
     CSR_BAD_PAULI = 4,       // Pauli code zero or beyond the channel's qubits
     CSR_BAD_OFFSETS = 8      // shot_off decreasing or negative
 };
-// kind: ChanKind per channel (uint8); flag: one device int, cleared first
+// sig: per (channel, Pauli code) the fault's W-word signature, the entries
+// of channel c starting at sig_off[c] (code_limit(kind) of them); kind:
+// ChanKind per channel (uint8); flag: one device int, cleared first
 hipError_t launch_prescreen(int words, int32_t n_channels, int64_t n, const int64_t* off, const int32_t* chan,
-                            const uint8_t* pauli, const uint64_t* sig, const uint8_t* kind,
+                            const uint8_t* pauli, const uint64_t* sig, const int32_t* sig_off,
+                            const uint8_t* kind,
                             uint64_t* survive_bits, int64_t* survivor_idx, int64_t* block_tmp,
                             int64_t n_blocks_tmp, int* flag, hipStream_t s);
 int64_t prescreen_tmp_words(int64_t n);

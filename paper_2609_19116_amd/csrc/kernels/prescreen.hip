@@ -1,9 +1,10 @@
 // Offline-screening kernel (Section 4.2): one shot per lane.
 //
-// A shot's signature over the decided measurements is the XOR of the
-// precompiled signatures of its faults' basis components (X and Z on each of
-// the channel's up to three qubits); the shot must be simulated iff that
-// signature is zero.  Each lane
+// A shot's signature over the decided measurements is the XOR of its
+// faults' signatures; the shot must be simulated iff that signature is
+// zero.  A fault's signature (the XOR of its basis components, X and Z on
+// each of the channel's up to three qubits) is precombined per (channel,
+// Pauli code) on the host, so each fault costs one W-word lookup.  Each lane
 // streams its shot's CSR slice from HBM, XORs <= W-word signatures from the
 // L2-resident table in registers, and the wavefront's verdicts are packed
 // with a 64-lane ballot into one uint64 of the survivor bitmap (lane j of
@@ -53,6 +54,7 @@ __global__ __launch_bounds__(PT) void screen_kernel(int32_t nch, int64_t n,
                                                     const int32_t* __restrict__ chan,
                                                     const uint8_t* __restrict__ pauli,
                                                     const uint64_t* __restrict__ sig,
+                                                    const int32_t* __restrict__ sig_off,
                                                     const uint8_t* __restrict__ kind,
                                                     uint64_t* __restrict__ bits,
                                                     int64_t* __restrict__ block_cnt,
@@ -73,15 +75,11 @@ __global__ __launch_bounds__(PT) void screen_kernel(int32_t nch, int64_t n,
             const int fb = fault_check(c, prev, p, nch, kind);
             bad |= fb;
             prev = c;
-            if (fb & CSR_BAD_CHANNEL) continue;   // not a channel of this circuit
-            const uint64_t* s = sig + c * kFaultComponents * W;
+            // an invalid channel or code has no entry (the call fails anyway)
+            if (fb & (CSR_BAD_CHANNEL | CSR_BAD_PAULI)) continue;
+            const uint64_t* s = sig + (static_cast<int64_t>(sig_off[c]) + p) * W;
 #pragma unroll
-            for (int k = 0; k < kFaultComponents; ++k) {
-                if ((p >> k) & 1) {
-#pragma unroll
-                    for (int w = 0; w < W; ++w) acc[w] ^= s[k * W + w];
-                }
-            }
+            for (int w = 0; w < W; ++w) acc[w] ^= s[w];
         }
         uint64_t any = 0;
 #pragma unroll
@@ -182,7 +180,8 @@ __global__ __launch_bounds__(PT) void scatter_kernel(int64_t n, const uint64_t* 
 int64_t prescreen_tmp_words(int64_t n) { return (n + PT - 1) / PT + 2; }
 
 hipError_t launch_prescreen(int words, int32_t n_channels, int64_t n, const int64_t* off, const int32_t* chan,
-                            const uint8_t* pauli, const uint64_t* sig, const uint8_t* kind,
+                            const uint8_t* pauli, const uint64_t* sig, const int32_t* sig_off,
+                            const uint8_t* kind,
                             uint64_t* bits, int64_t* survivor_idx, int64_t* block_tmp,
                             int64_t n_blocks_tmp, int* flag, hipStream_t s) {
     const int64_t nb = (n + PT - 1) / PT;
@@ -196,7 +195,7 @@ hipError_t launch_prescreen(int words, int32_t n_channels, int64_t n, const int6
 #define MSC_SCREEN_CASE(WW)                                                                   \
     case WW:                                                                                  \
         hipLaunchKernelGGL(screen_kernel<WW>, grid, dim3(PT), 0, s, n_channels, n, off, chan,  \
-                           pauli, sig, kind, bits, block_tmp, flag);                          \
+                           pauli, sig, sig_off, kind, bits, block_tmp, flag);                 \
         break;
         MSC_SCREEN_CASE(1)
         MSC_SCREEN_CASE(2)

@@ -147,7 +147,8 @@ struct msc_circuit {
     void* d_ops = nullptr;
     void* d_g1 = nullptr;
     void* d_g4 = nullptr;
-    void* d_sig = nullptr;
+    void* d_sig = nullptr;               // uint64 [codes of all channels][words]
+    void* d_sig_off = nullptr;           // int32 first code entry per channel
     void* d_expected = nullptr;
     void* d_kind = nullptr;              // uint8 ChanKind per channel
     PrefixCk prefix;

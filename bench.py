@@ -478,6 +478,24 @@ def main() -> int:
                                    "peak": 8000.0, "unit": "GB/s",
                                    "frac": byts / (ms81 * 1e-3) / 1e9 / 8000.0}
         del o81, ch81, pa81
+        # 1e8 shots of the same skeleton in 2^24-shot chunks (consecutive
+        # shot ranges of one seed): fault sampling and screen per chunk
+        log("offline screen, 1e8 shots, 81 qubits")
+        total, first, t_sample, t_screen, surv = 100_000_000, 0, 0.0, 0.0, 0
+        while first < total:
+            k = min(n81, total - first)
+            o81, ch81, pa81 = msc.sample_faults_device(ctx, c81, 0x5EED0005, first, k, p=args.p)
+            t_sample += ctx.last_kernel_ms("sample")
+            _, _, cnt = msc.prescreen(ctx, c81, o81, ch81, pa81, with_index=False)
+            t_screen += ctx.last_kernel_ms("prescreen")
+            surv += cnt
+            first += k
+            del o81, ch81, pa81
+        result["prescreen_81q_1e8"] = {"shots": total, "survivors": surv,
+                                       "screen_ms": t_screen, "sample_ms": t_sample,
+                                       "screen_shots_per_s": total / (t_screen * 1e-3),
+                                       "sample_and_screen_shots_per_s":
+                                           total / ((t_screen + t_sample) * 1e-3)}
 
     if not args.no_extras and order is not None:
         # the same pipeline on the snake layout, for comparison (its own
@@ -654,18 +672,28 @@ def engine_lines(msc, ctx, args) -> dict:
                         (np.abs(res["p_acc"] - ref["p_acc"])[acc] / ref["p_acc"][acc]).max())
                 line[f"{pname[pr]}_{mode}"] = rec
         out[name] = line
-    # the 81-qubit workload at the configured cap of 1024 (1.36 GB slots, 64 of them)
+    # the 81-qubit workload at the configured cap of 1024 (1.36 GB slots, 64
+    # of them), FP32 and BF16x3 contractions
     c = msc.Circuit(config_circuit("c4").text)
     c.calibrate(ctx)
     off, ch, pa = msc.sample_faults_device(ctx, c, 0x5EED0004, 0, args.engine_shots, p=args.p)
     _, idx, cnt = msc.prescreen(ctx, c, off, ch, pa)
-    res = msc.results_numpy(msc.simulate(ctx, c, off, ch, pa, shot_idx=idx,
-                                         precision=msc.MSC_FP32, chi_max=1024, large_side=64,
-                                         n_slots=64, autotune_cache=cache, prefix=True))
-    ms = ctx.engine_stats()["total_ms"]
-    out["81q_snake_bond64"]["fp32_engine_chi_max_1024"] = {
-        "shots_per_s": args.engine_shots / (ms * 1e-3), "kernel_ms": ms, "slots": 64,
-        "chi_peak": int(res["chi_peak"].max())}
+    ref = None
+    for name, pr in (("fp32", msc.MSC_FP32), ("bf16x3", msc.MSC_BF16X3)):
+        res = msc.results_numpy(msc.simulate(ctx, c, off, ch, pa, shot_idx=idx, precision=pr,
+                                             chi_max=1024, large_side=64, n_slots=64,
+                                             autotune_cache=cache, prefix=True))
+        ms = ctx.engine_stats()["total_ms"]
+        rec = {"shots_per_s": args.engine_shots / (ms * 1e-3), "kernel_ms": ms, "slots": 64,
+               "chi_peak": int(res["chi_peak"].max()),
+               "chi_cap_flagged": int(((res["status"] & msc.SHOT_CHI_CAP) != 0).sum())}
+        if ref is None:
+            ref = res
+        else:
+            acc = ref["p_acc"] > 0
+            rec["max_rel_p_acc_vs_fp32"] = float(
+                (np.abs(res["p_acc"] - ref["p_acc"])[acc] / ref["p_acc"][acc]).max())
+        out["81q_snake_bond64"][f"{name}_engine_chi_max_1024"] = rec
     return out
 
 

@@ -148,3 +148,41 @@ def test_wave_batch_matches_workgroup_kernel(ctx, space_time):
     np.testing.assert_allclose(bw[2], bg[2], rtol=1e-4, atol=1e-9)
     if space_time:
         np.testing.assert_allclose(sw["surv_bins"], sg["surv_bins"], rtol=1e-5, atol=1e-12)
+
+
+def test_wave_kernel_edge_cases(ctx):
+    import torch
+    c, csr, ref = _stratified(ctx, "c1", 160, 0x5EED0045)
+    off, ch, pa = to_dev(*csr)
+    say("wave edge cases")
+    base = results_numpy(msc.simulate(ctx, c, off, ch, pa, precision=MSC_FP32, wave_chi=16))
+    # one slot requested: one workgroup of four wavefronts, same bits
+    one = results_numpy(msc.simulate(ctx, c, off, ch, pa, precision=MSC_FP32, wave_chi=16,
+                                     n_slots=1))
+    for f in FIELDS:
+        assert np.array_equal(base[f], one[f]), f
+    # BF16x3 runs the FP32 shot kernel (its split products are the engine's);
+    # at the same threshold every bit equals the FP32 run
+    b3 = results_numpy(msc.simulate(ctx, c, off, ch, pa, precision=msc.MSC_BF16X3,
+                                    tau_trunc=1e-4, wave_chi=16))
+    f32 = results_numpy(msc.simulate(ctx, c, off, ch, pa, precision=MSC_FP32, tau_trunc=1e-4,
+                                     wave_chi=16))
+    for f in FIELDS:
+        assert np.array_equal(b3[f], f32[f]), f
+    # a bond cap below the circuit's bonds binds in the slots themselves: no
+    # reruns, the cap flagged as in the workgroup kernel
+    capped = results_numpy(msc.simulate(ctx, c, off, ch, pa, precision=MSC_FP64, chi_max=4))
+    st = ctx.engine_stats()
+    assert st["wave_slots"] > 0 and st["wave_retries"] == 0
+    assert np.all(capped["chi_peak"] <= 4)
+    assert np.any(capped["status"] & msc.SHOT_CHI_CAP)
+    assert np.all(np.isfinite(capped["p_acc"])) and np.all(np.isfinite(capped["infid"]))
+    # shot indices outside the CSR give the empty record, as in the workgroup kernel
+    idx = torch.tensor([0, -1, 5, 10 ** 9, 7], dtype=torch.int64, device="cuda")
+    sel = results_numpy(msc.simulate(ctx, c, off, ch, pa, shot_idx=idx, precision=MSC_FP32,
+                                     wave_chi=16))
+    assert sel["rejected_at"][1] == -1 and sel["rejected_at"][3] == -1
+    assert sel["p_acc"][1] == 0.0 and sel["p_acc"][3] == 0.0 and sel["status"][1] == 0
+    for k, i in ((0, 0), (2, 5), (4, 7)):
+        for f in FIELDS:
+            assert sel[f][k] == base[f][i], (f, i)

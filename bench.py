@@ -365,18 +365,20 @@ def main() -> int:
                                                lds_width=args.lds_width, wave_chi=args.wave_chi,
                                                prefix=not args.no_prefix))
         def one_shot_fp64(k, prefix):
-            # the same kernels in FP64, one survivor per launch (one
-            # workgroup), on the first k survivors of the batch; the step
-            # rate adds the batch's mean screen and sampling times
+            # the same kernels in FP64, one survivor per launch on one
+            # workgroup (the workgroup kernel: all four wavefronts on the
+            # shot, its fastest single-shot form), on the first k survivors
+            # of the batch; the step rate adds the batch's mean screen and
+            # sampling times
             if prefix:   # checkpoints of the FP64 noiseless run, built once
                 msc.simulate(ctx, circ, off, ch, pa, shot_idx=idx0[:1].contiguous(),
                              precision=msc.MSC_FP64, chi_max=args.chi_max, n_slots=1,
-                             prefix=True)
+                             prefix=True, wave_chi=-1)
             t = 0.0
             for i in range(k):
                 msc.simulate(ctx, circ, off, ch, pa, shot_idx=idx0[i:i + 1].contiguous(),
                              precision=msc.MSC_FP64, chi_max=args.chi_max, n_slots=1,
-                             prefix=prefix)
+                             prefix=prefix, wave_chi=-1)
                 t += ctx.last_kernel_ms("simulate")
             per_shot = t / k
             step_ms = (per_shot * float(np.mean(n_surv)) + float(np.mean(screen_ms)) +

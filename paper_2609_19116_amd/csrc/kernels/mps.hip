@@ -270,19 +270,30 @@ __device__ void jacobi_sweep(DP vre, DP vim, IP list, int nv, int len, int ld, d
     }
 }
 
-// Squared norms of nv vectors (stride ld) into nrm.
+// Squared norms of nv vectors (stride ld) into nrm.  When the team has
+// lanes to spare, g consecutive lanes (g a power of two <= 16, within a
+// wavefront) share a vector: each sums every g-th element, then the group
+// adds the partial sums by DPP moves.
 template <int W, typename DP>
 __device__ void vector_norms(DP vre, DP vim, int nv, int len, int ld, DP nrm) {
-    for (int v = Team<W>::rank(); v < nv; v += W) {
+    const int tid = Team<W>::rank();
+    int g = 1;
+    while (g < 16 && nv * g * 2 <= W) g *= 2;
+    const int per = W / g, sub = tid & (g - 1), vi = tid / g;
+    for (int v0 = 0; v0 < nv; v0 += per) {
+        const int v = v0 + vi;
         double s0 = 0.0, s1 = 0.0;
-        DP xr = vre + (size_t)v * ld;
-        DP xi = vim + (size_t)v * ld;
+        if (v < nv) {
+            DP xr = vre + (size_t)v * ld;
+            DP xi = vim + (size_t)v * ld;
 #pragma unroll 2
-        for (int e = 0; e < len; ++e) {
-            s0 += xr[e] * xr[e];
-            s1 += xi[e] * xi[e];
+            for (int e = sub; e < len; e += g) {
+                s0 += xr[e] * xr[e];
+                s1 += xi[e] * xi[e];
+            }
         }
-        nrm[v] = s0 + s1;
+        const double sum = group_sum(s0 + s1, g);
+        if (v < nv && sub == 0) nrm[v] = sum;
     }
     Team<W>::sync();
 }
@@ -379,12 +390,23 @@ __device__ Kept select_kept(DP nrm, int nv, double tau2, int capb, IP sel, DP is
     for (int v = tid; v < nv; v += W) mx = fmax(mx, sel_norm(nrm[v]));
     mx = team_max<W>(mx, red);
     double kd[4] = {0.0, 0.0, 0.0, 0.0};
+    // one wavefront with a lane per vector: the other vectors' norms are
+    // read from their lanes, not from memory
+    const bool lanes = W == 64 && nv <= 64;
+    const double xl = (lanes && tid < nv) ? sel_norm(nrm[tid]) : 0.0;
     for (int v = tid; v < nv; v += W) {
-        const double x = sel_norm(nrm[v]);
+        const double x = lanes ? xl : sel_norm(nrm[v]);
         int rank = 0;
-        for (int u = 0; u < nv; ++u) {
-            const double y = sel_norm(nrm[u]);
-            rank += (y > x) || (y == x && u < v);
+        if (lanes) {
+            for (int u = 0; u < nv; ++u) {
+                const double y = lane_read(xl, u);
+                rank += (y > x) || (y == x && u < v);
+            }
+        } else {
+            for (int u = 0; u < nv; ++u) {
+                const double y = sel_norm(nrm[u]);
+                rank += (y > x) || (y == x && u < v);
+            }
         }
         const bool above = x > tau2 * mx || rank == 0;
         kd[3] += above ? 1.0 : 0.0;

@@ -111,8 +111,9 @@ def main() -> int:
     if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < need:
         os.environ["GPU_MAX_HW_QUEUES"] = str(need)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build simulates each shot on one "
-              "device and has no multi-GPU path (see DESIGN.md for how it would shard)",
+        print("bench.py runs on exactly one GPU: the library simulates each shot on one "
+              "device and has no multi-GPU path (shots would shard by index range, one "
+              "range per GPU, with one reduction of the per-weight sums)",
               file=sys.stderr)
         return 2
 
@@ -266,7 +267,7 @@ def main() -> int:
     chi_peak = max(st["chi_peak"] for st in sts)
     # roofline of the shot kernel: algorithmic flops of a launch (the
     # library's per-update count at the realised shapes: contraction, Gram,
-    # projection, eigensolve; SURVEY's per-update model) over the launch's
+    # projection, eigensolve) over the launch's
     # duration (HIP events on the step's stream around the shot kernel).
     # With one step in flight the launches do not overlap, so this is the
     # rate the kernel trace of the same command gives per launch.

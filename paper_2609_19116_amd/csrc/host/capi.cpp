@@ -937,7 +937,7 @@ static int read_tune_cache(const char* path, int precision, LxTiles* tiles) {
                 known_g |= v[i].gram == gram;
             }
             if (!(known_c && known_g))
-                return set_error(MSC_E_INVALID, "autotune cache names a tile shape this build "
+                return set_error(MSC_E_INVALID, "autotune cache names a tile shape the library "
                                                 "does not have");
             tiles[bk] = LxTiles{static_cast<int32_t>(rows), static_cast<int32_t>(b),
                                 static_cast<int32_t>(gram)};

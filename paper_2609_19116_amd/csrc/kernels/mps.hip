@@ -184,6 +184,34 @@ __device__ __forceinline__ __attribute__((address_space(1))) X* to_glb(X* p) {
     return (__attribute__((address_space(1))) X*)p;
 }
 
+// One wavefront's asynchronous copy of `bytes` bytes from global memory to
+// LDS by direct loads (global_load_lds_dwordx4: lane i's 16 bytes land at
+// dst + 16 i), with no register round trip.  Both addresses are 16-byte
+// aligned and both sides must have room for the size rounded up to 16
+// bytes.  The data is in LDS once the wavefront's vector-memory counter has
+// drained (any Team<64>::sync()).
+template <typename GP>
+__device__ __forceinline__ void wave_load_lds(GP src, void* dst, int bytes) {
+    typedef __attribute__((address_space(1))) char gchar;
+    typedef __attribute__((address_space(3))) char lchar;
+    const int lane = threadIdx.x & 63;
+    const int n16 = (bytes + 15) >> 4;
+    gchar* s8 = (gchar*)src;
+    lchar* d8 = (lchar*)dst;
+    for (int b = 0; b < n16; b += 64) {
+        if (b + lane < n16)
+            __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void*)(s8 + 16 * (b + lane)),
+                                             (__attribute__((address_space(3))) void*)(d8 + 16 * b), 16, 0, 0);
+    }
+}
+
+// Elements of T rounded up to a multiple of 16 bytes.
+template <typename T>
+__device__ __forceinline__ int round16(int n) {
+    constexpr int q = 16 / static_cast<int>(sizeof(T));
+    return (n + q - 1) / q * q;
+}
+
 // One sweep of one-sided Jacobi (Hestenes) over the nv vectors list[0..nv)
 // of length len (planar FP64 at vre/vim, vector v at v*ld, ld >= len padded
 // against LDS bank conflicts): every pair (p, q) once, in round-robin order
@@ -497,9 +525,22 @@ template <typename T, int W, typename DP, typename IP>
 __device__ bool move_fast(const MpsArgs& P, const Smem& S, SiteView<T> A, SiteView<T> B, int k,
                           int dir, const Vecs<DP, IP>& V, int64_t vcap, double* scr, ShotAcc& acc) {
     typedef __attribute__((address_space(1))) T gT;
+    typedef __attribute__((address_space(3))) T lT;
     const int tid = Team<W>::rank();
     const int cl = S.chi[k], cm = S.chi[k + 1], cr = S.chi[k + 2];
     const int nv = cm, len = dir ? 2 * cl : 2 * cr, ld = len + 1;
+    // one wavefront: the neighbour that gets rescaled (B for dir 1, A for
+    // dir 0) is copied to the staging area by direct loads now, so that its
+    // global read overlaps the vectors' and the rescale reads LDS
+    const int ne = dir ? cm * 2 * cr : 2 * cl * cm;
+    const int ne16 = round16<T>(ne);
+    const bool pre = W == 64 && (size_t)2 * ne16 * sizeof(T) <= (size_t)S.n_u * sizeof(double);
+    lT* ure = to_lds(reinterpret_cast<T*>(S.u));
+    lT* uim = ure + ne16;
+    if (pre) {
+        wave_load_lds(dir ? B.re : A.re, S.u, ne * sizeof(T));
+        wave_load_lds(dir ? B.im : A.im, reinterpret_cast<T*>(S.u) + ne16, ne * sizeof(T));
+    }
     DP vre = V.vre;
     DP vim = V.vim;
     DP nrm = V.nrm;
@@ -549,7 +590,16 @@ __device__ bool move_fast(const MpsArgs& P, const Smem& S, SiteView<T> A, SiteVi
         }
         const int w = 2 * cr;
         Team<W>::sync();
-        if (r * w <= vcap) {
+        if (pre) {
+            // the old rows from the LDS copy, the new ones straight to B
+            for (int idx = tid; idx < r * w; idx += W) {
+                const int c = idx / w, x = idx - c * w;
+                const int v = sel[c];
+                const double sc = sq[c] * renorm;
+                Bre[idx] = T(static_cast<double>(ure[v * w + x]) * sc);
+                Bim[idx] = T(static_cast<double>(uim[v * w + x]) * sc);
+            }
+        } else if (r * w <= vcap) {
             for (int idx = tid; idx < r * w; idx += W) {
                 const int c = idx / w, x = idx - c * w;
                 const int v = sel[c];
@@ -589,7 +639,15 @@ __device__ bool move_fast(const MpsArgs& P, const Smem& S, SiteView<T> A, SiteVi
             Bim[idx] = T(vim[v * ld + e] * is);
         }
         Team<W>::sync();
-        if (2 * cl * r <= vcap) {
+        if (pre) {
+            for (int idx = tid; idx < 2 * cl * r; idx += W) {
+                const int row = idx / r, c = idx - row * r;
+                const int v = sel[c];
+                const double sc = sq[c] * renorm;
+                Are[idx] = T(static_cast<double>(ure[row * cm + v]) * sc);
+                Aim[idx] = T(static_cast<double>(uim[row * cm + v]) * sc);
+            }
+        } else if (2 * cl * r <= vcap) {
             for (int idx = tid; idx < 2 * cl * r; idx += W) {
                 const int row = idx / r, c = idx - row * r;
                 const int v = sel[c];
@@ -1261,6 +1319,17 @@ __device__ void run_team(const MpsArgs& P, const Smem& S, const int team, const 
                 const int ps = k + side, os = k + 1 - side;
                 SiteView<T> Pv = site(ps), Ov = site(os);
                 const int pl = S.chi[ps], pr = S.chi[ps + 1];
+                const int ol = S.chi[k], ocr = S.chi[k + 2];
+                const int on = side ? ol * 2 * pl : pr * 2 * ocr;   // neighbour elements
+                const int on16 = round16<T>(on);
+                // in LDS (neighbour staged) when it fits; one wavefront
+                // stages it by direct loads now, overlapping the reads below
+                const bool lds_fold = pl * pr <= SMAX * (SMAX + 1) &&
+                                      (size_t)2 * on16 * sizeof(T) <= (size_t)S.n_u * sizeof(double);
+                if (W == 64 && lds_fold) {
+                    wave_load_lds(Ov.re, S.u, on * sizeof(T));
+                    wave_load_lds(Ov.im, reinterpret_cast<T*>(S.u) + on16, on * sizeof(T));
+                }
                 double r4[4] = {0.0, 0.0, 0.0, 0.0};
                 for (int idx = tid; idx < pl * pr; idx += W) {
                     const int a = idx / pr, b = idx - a * pr;
@@ -1288,19 +1357,18 @@ __device__ void run_team(const MpsArgs& P, const Smem& S, const int team, const 
                     p1i = -r4[3] * d;
                 }
                 // M = sum_i conj(psi_i) P[:, i, :] (pl x pr, FP64), then the
-                // neighbour times M; in LDS (neighbour staged) when it fits
-                const int ol = S.chi[k], ocr = S.chi[k + 2];
-                const int on = side ? ol * 2 * pl : pr * 2 * ocr;   // neighbour elements
+                // neighbour times M
                 const int newb = side ? ol : ocr;
-                if (pl * pr <= SMAX * (SMAX + 1) &&
-                    (size_t)2 * on * sizeof(T) <= (size_t)S.n_u * sizeof(double)) {
+                if (lds_fold) {
                     typedef __attribute__((address_space(3))) T lT;
                     lT* st = to_lds(reinterpret_cast<T*>(S.u));
-                    for (int idx = tid; idx < on; idx += W) {
-                        st[idx] = Ov.re[idx];
-                        st[on + idx] = Ov.im[idx];
+                    if (W != 64) {
+                        for (int idx = tid; idx < on; idx += W) {
+                            st[idx] = Ov.re[idx];
+                            st[on16 + idx] = Ov.im[idx];
+                        }
                     }
-                    fold_product<T, W>(to_lds(S.vre), to_lds(S.vim), st, st + on, Pv, p0r, p0i,
+                    fold_product<T, W>(to_lds(S.vre), to_lds(S.vim), st, st + on16, Pv, p0r, p0i,
                                        p1r, p1i, side, ol, pl, pr, ocr);
                 } else {
                     glbd* mr = to_glb(scr);
@@ -1524,7 +1592,7 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
     __shared__ DevOp s_ops[kOpBuf];
     // staging: the two site tensors of an update (tensor type), then the
     // copy of theta kept for the projection (FP64)
-    __shared__ double s_u[kStage];
+    __shared__ __align__(16) double s_u[kStage];
 
     const int tid = threadIdx.x;
 
@@ -1601,7 +1669,7 @@ __global__ __launch_bounds__(NT, 3) void mps_wave_kernel(MpsArgs P) {
     __shared__ int s_list[NW][kWaveSmax];
     __shared__ int s_flag[NW][1];
     __shared__ DevOp s_ops[NW][kWaveOps];
-    __shared__ double s_u[NW][kWaveStage];
+    __shared__ __align__(16) double s_u[NW][kWaveStage];
     // per workgroup, read-only after the start
     __shared__ double s_g1[G1_COUNT * 8];
     __shared__ int s_g4src[G4_COUNT * 4];

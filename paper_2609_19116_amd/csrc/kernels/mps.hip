@@ -802,19 +802,29 @@ __device__ bool twosite_update(const MpsArgs& P, const Smem& S, SiteView<T> A, S
     // contraction then reads each element from LDS
     const int na = cl * 2 * cm, nb = cm * 2 * cr;
     double nsum[1];
-    if ((size_t)2 * (na + nb) * sizeof(T) <= (size_t)S.n_u * sizeof(double)) {
+    // planes at 16-byte offsets (one wavefront stages them by direct loads)
+    const int na16 = round16<T>(na), nb16 = round16<T>(nb);
+    if ((size_t)2 * (na16 + nb16) * sizeof(T) <= (size_t)S.n_u * sizeof(double)) {
         lT* st = to_lds(reinterpret_cast<T*>(S.u));
-        for (int i = tid; i < na; i += W) {
-            st[i] = Are[i];
-            st[na + i] = Aim[i];
-        }
-        for (int i = tid; i < nb; i += W) {
-            st[2 * na + i] = Bre[i];
-            st[2 * na + nb + i] = Bim[i];
+        if constexpr (W == 64) {
+            T* u = reinterpret_cast<T*>(S.u);
+            wave_load_lds(Are, u, na * sizeof(T));
+            wave_load_lds(Aim, u + na16, na * sizeof(T));
+            wave_load_lds(Bre, u + 2 * na16, nb * sizeof(T));
+            wave_load_lds(Bim, u + 2 * na16 + nb16, nb * sizeof(T));
+        } else {
+            for (int i = tid; i < na; i += W) {
+                st[i] = Are[i];
+                st[na16 + i] = Aim[i];
+            }
+            for (int i = tid; i < nb; i += W) {
+                st[2 * na16 + i] = Bre[i];
+                st[2 * na16 + nb16 + i] = Bim[i];
+            }
         }
         Team<W>::sync();
-        nsum[0] = contract<T, W>(st, st + na, st + 2 * na, st + 2 * na + nb, cl, cm, cr, gsrc, gph,
-                                 dir, ld, vre, vim);
+        nsum[0] = contract<T, W>(st, st + na16, st + 2 * na16, st + 2 * na16 + nb16, cl, cm, cr,
+                                 gsrc, gph, dir, ld, vre, vim);
     } else {
         nsum[0] = contract<T, W>(Are, Aim, Bre, Bim, cl, cm, cr, gsrc, gph, dir, ld, vre, vim);
     }

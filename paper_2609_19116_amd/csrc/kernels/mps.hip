@@ -478,6 +478,9 @@ struct Smem {
     const int32_t* shalf;
     const double* g1;    // [G1_COUNT * 8] 2x2 gates
     int n_u;             // doubles of staging at u
+    int n_work = 0;      // doubles from vre on (vectors and staging) usable as one
+                         // area by a wide factorisation (one-wavefront teams)
+    int n_vmax = 0;      // capacity of the per-vector arrays in LDS (wide case)
     double* vre;         // SVD vectors (SMAX x (SMAX + 1)), planar
     double* vim;
     double* nrm;         // [SMAX]
@@ -781,15 +784,21 @@ __device__ void project(TP thr, TP thi, int m, int n, int r, int dir, int ld, co
 template <typename T, int SMAX, int W, typename DP, typename IP>
 __device__ bool twosite_update(const MpsArgs& P, const Smem& S, SiteView<T> A, SiteView<T> B,
                                int k, int dir, int gate_id, double* scr, const Vecs<DP, IP>& V,
-                               ShotAcc& acc, bool grow = false) {
+                               ShotAcc& acc, bool grow = false, int ldv = 0) {
     typedef __attribute__((address_space(1))) T gT;
     typedef __attribute__((address_space(3))) T lT;
     const int tid = Team<W>::rank();
     const int cl = S.chi[k], cm = S.chi[k + 1], cr = S.chi[k + 2];
     const int m = 2 * cl, n = 2 * cr;
     const int nv = dir ? n : m, len = dir ? m : n;
-    const int ld = len + 1;
-    DP vre = V.vre, vim = V.vim, nrm = V.nrm;
+    // ldv > 0: the vectors take the team's whole work area (its staging
+    // included, so theta's copy goes to the scratch), each vector's real and
+    // imaginary parts side by side at the odd stride ldv (no bank conflicts
+    // between vectors)
+    const bool packed = ldv > 0;
+    const int ld = packed ? ldv : len + 1;
+    const int n_u = packed ? 0 : S.n_u;
+    DP vre = V.vre, vim = packed ? V.vre + len : V.vim, nrm = V.nrm;
     IP sel = V.sel, bad = V.bad, list = V.list;
     gT* Are = A.re;
     gT* Aim = A.im;
@@ -804,7 +813,7 @@ __device__ bool twosite_update(const MpsArgs& P, const Smem& S, SiteView<T> A, S
     double nsum[1];
     // planes at 16-byte offsets (one wavefront stages them by direct loads)
     const int na16 = round16<T>(na), nb16 = round16<T>(nb);
-    if ((size_t)2 * (na16 + nb16) * sizeof(T) <= (size_t)S.n_u * sizeof(double)) {
+    if ((size_t)2 * (na16 + nb16) * sizeof(T) <= (size_t)n_u * sizeof(double)) {
         lT* st = to_lds(reinterpret_cast<T*>(S.u));
         if constexpr (W == 64) {
             T* u = reinterpret_cast<T*>(S.u);
@@ -841,7 +850,7 @@ __device__ bool twosite_update(const MpsArgs& P, const Smem& S, SiteView<T> A, S
     vector_norms<W>(vre, vim, nv, len, ld, nrm);
     const bool rotated = not_orthogonal<W>(vre, vim, nv, len, ld, nrm, floor2, tol, bad, (IP)nullptr);
     // theta's copy for the projection: LDS staging when it fits
-    const bool th_lds = 2 * (size_t)m * n <= (size_t)S.n_u;
+    const bool th_lds = 2 * (size_t)m * n <= (size_t)n_u;
     if (rotated) {
         // keep theta for the projection (the vectors still hold it)
         if (th_lds) {
@@ -927,14 +936,19 @@ __device__ bool twosite_update(const MpsArgs& P, const Smem& S, SiteView<T> A, S
                 Aim[idx] = T(0);
             }
         }
-    } else if (th_lds) {
-        ldsd* thr = to_lds(S.u);
-        project<T, W>(thr, thr + (size_t)m * n, m, n, r, dir, ld, V, renorm, dir ? Bre : Are,
-                      dir ? Bim : Aim);
     } else {
-        glbd* thr = to_glb(scr);
-        project<T, W>(thr, thr + (size_t)m * n, m, n, r, dir, ld, V, renorm, dir ? Bre : Are,
-                      dir ? Bim : Aim);
+        // the vectors as this update laid them out
+        Vecs<DP, IP> Vw = V;
+        Vw.vim = vim;
+        if (th_lds) {
+            ldsd* thr = to_lds(S.u);
+            project<T, W>(thr, thr + (size_t)m * n, m, n, r, dir, ld, Vw, renorm,
+                          dir ? Bre : Are, dir ? Bim : Aim);
+        } else {
+            glbd* thr = to_glb(scr);
+            project<T, W>(thr, thr + (size_t)m * n, m, n, r, dir, ld, Vw, renorm,
+                          dir ? Bre : Are, dir ? Bim : Aim);
+        }
     }
     if (tid == 0) S.chi[k + 1] = r;
     acc.chi_peak = max(acc.chi_peak, r);
@@ -1524,10 +1538,16 @@ __device__ void run_team(const MpsArgs& P, const Smem& S, const int team, const 
                 // chi_max: a shot that outgrows them is handed on (grow)
                 const bool grow = P.retry_list != nullptr;
                 bool ok = true;
-                if (m <= SMAX && n <= SMAX) {
+                // a wide update of a one-wavefront team whose vectors fit in
+                // the team's whole LDS work area
+                const int nvw = dir ? n : m, lenw = dir ? m : n;
+                const bool wide_lds = W == 64 && !(m <= SMAX && n <= SMAX) && nvw <= S.n_vmax &&
+                                      nvw * (2 * lenw + 1) <= S.n_work;
+                if ((m <= SMAX && n <= SMAX) || wide_lds) {
                     if constexpr (W == 64) {
                         ok = twosite_update<T, SMAX, 64>(P, S, A, B, k, dir, gate_id, scr,
-                                                         lds_vecs(S), acc, grow);
+                                                         lds_vecs(S), acc, grow,
+                                                         wide_lds ? 2 * lenw + 1 : 0);
                     } else if (m <= kWaveSide && n <= kWaveSide) {
                         if (tid < 64)
                             twosite_update<T, SMAX, 64>(P, S, A, B, k, dir, gate_id, scr,
@@ -1658,28 +1678,32 @@ __global__ __launch_bounds__(NT, (kMpsWavesPerSimd<T, SMAX>)) void mps_kernel(Mp
 // shots instead of four.  The slots' bonds are capped below chi_max; a shot
 // that outgrows them is queued (retry_list) and run again from its start by
 // the workgroup kernel.  Factorisations with both theta sides <= kWaveSmax
-// keep their vectors in LDS, wider ones (up to twice the slot's bond cap) in
-// the slot's scratch.
+// keep their vectors in LDS; wider ones (up to twice the slot's bond cap)
+// take the wavefront's whole LDS work area when their nv vectors of length
+// len fit in it at a stride of 2 len + 1 doubles, else the slot's scratch.
 constexpr int kWaveSmax = 16;
 constexpr int kWaveOps = 16;
 constexpr int kWaveStage = 512;
+constexpr int kWaveVec = kWaveSmax * (kWaveSmax + 1);     // doubles per plane, small sides
+constexpr int kWaveWork = 2 * kWaveVec + kWaveStage;      // vectors + staging
+constexpr int kWaveMaxV = 2 * kWaveSmax;                  // vectors of a wide update
 
 template <typename T>
 __global__ __launch_bounds__(NT, 3) void mps_wave_kernel(MpsArgs P) {
     // per wavefront
     __shared__ int s_chi[NW][kMaxSites + 1];
     __shared__ int s_laste[NW][kMaxSites];
-    __shared__ double s_vre[NW][kWaveSmax * (kWaveSmax + 1)];
-    __shared__ double s_vim[NW][kWaveSmax * (kWaveSmax + 1)];
-    __shared__ double s_nrm[NW][kWaveSmax];
-    __shared__ double s_isq[NW][kWaveSmax];
-    __shared__ double s_sq[NW][kWaveSmax];
-    __shared__ int s_sel[NW][kWaveSmax];
-    __shared__ int s_bad[NW][kWaveSmax];
-    __shared__ int s_list[NW][kWaveSmax];
+    // the SVD vectors of small sides (planar) and the staging area, one
+    // contiguous work area that a wide factorisation takes whole
+    __shared__ __align__(16) double s_work[NW][kWaveWork];
+    __shared__ double s_nrm[NW][kWaveMaxV];
+    __shared__ double s_isq[NW][kWaveMaxV];
+    __shared__ double s_sq[NW][kWaveMaxV];
+    __shared__ int s_sel[NW][kWaveMaxV];
+    __shared__ int s_bad[NW][kWaveMaxV];
+    __shared__ int s_list[NW][kWaveMaxV];
     __shared__ int s_flag[NW][1];
     __shared__ DevOp s_ops[NW][kWaveOps];
-    __shared__ __align__(16) double s_u[NW][kWaveStage];
     // per workgroup, read-only after the start
     __shared__ double s_g1[G1_COUNT * 8];
     __shared__ int s_g4src[G4_COUNT * 4];
@@ -1712,8 +1736,8 @@ __global__ __launch_bounds__(NT, 3) void mps_wave_kernel(MpsArgs P) {
     Smem S;
     S.chi = s_chi[w];
     S.laste = s_laste[w];
-    S.vre = s_vre[w];
-    S.vim = s_vim[w];
+    S.vre = s_work[w];
+    S.vim = s_work[w] + kWaveVec;
     S.nrm = s_nrm[w];
     S.isq = s_isq[w];
     S.sq = s_sq[w];
@@ -1724,8 +1748,10 @@ __global__ __launch_bounds__(NT, 3) void mps_wave_kernel(MpsArgs P) {
     S.red = nullptr;
     S.flag = s_flag[w];
     S.ops = s_ops[w];
-    S.u = s_u[w];
+    S.u = s_work[w] + 2 * kWaveVec;
     S.n_u = kWaveStage;
+    S.n_work = kWaveWork;
+    S.n_vmax = kWaveMaxV;
     S.cap = s_cap;
     S.g4src = s_g4src;
     S.g4ph = s_g4ph;

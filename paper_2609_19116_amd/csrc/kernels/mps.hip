@@ -206,6 +206,18 @@ __device__ __forceinline__ void wave_load_lds(GP src, void* dst, int bytes) {
 }
 
 // Elements of T rounded up to a multiple of 16 bytes.
+// 1/sqrt(x) for a positive normal x: the hardware estimate refined by two
+// Newton steps y <- y + y (1 - x y^2) / 2 (quadratic convergence), to about
+// an ulp; a few fused multiply-adds instead of a correctly rounded square
+// root and a division.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
 template <typename T>
 __device__ __forceinline__ int round16(int n) {
     constexpr int q = 16 / static_cast<int>(sizeof(T));
@@ -223,7 +235,8 @@ __device__ __forceinline__ int round16(int n) {
 // second vector keeps the phase of gamma, which leaves the pair orthogonal
 // and spares a division).  With D = |d| + sqrt(d^2 + 4|gamma|^2) and
 // rq = 1/sqrt(D^2 + 4|gamma|^2) this is c = D rq and s/|gamma| = 2 sign(d) rq:
-// one square root and one reciprocal square root per pair.
+// two reciprocal square roots per pair (sqrt(q) = q / sqrt(q)), each a
+// refined hardware estimate.
 template <int W, typename DP, typename IP>
 __device__ void jacobi_sweep(DP vre, DP vim, IP list, int nv, int len, int ld, double floor2,
                              double tol) {
@@ -273,8 +286,9 @@ __device__ void jacobi_sweep(DP vre, DP vim, IP list, int nv, int len, int ld, d
                 const double g2 = gr * gr + gim * gim;
                 if (a > floor2 && b > floor2 && g2 > tol2 * a * b) {
                     const double d = b - a;
-                    const double D = fabs(d) + sqrt(d * d + 4.0 * g2);
-                    const double rq = 1.0 / sqrt(D * D + 4.0 * g2);
+                    const double q1 = d * d + 4.0 * g2;
+                    const double D = fabs(d) + q1 * rsqrt_nr(q1);
+                    const double rq = rsqrt_nr(D * D + 4.0 * g2);
                     const double c = D * rq;
                     const double sg = (d >= 0.0 ? 2.0 : -2.0) * rq;  // s / |gamma|
                     const double pr = sg * gr, pim = sg * gim;        // (s/|gamma|) gamma
@@ -440,10 +454,12 @@ __device__ Kept select_kept(DP nrm, int nv, double tau2, int capb, IP sel, DP is
         kd[3] += above ? 1.0 : 0.0;
         const bool keep = above && rank < capb;
         if (keep) {
-            const double s = sqrt(x);
+            // (only an all-zero theta keeps a vector of norm near 0)
+            const bool nrm_ok = x > 1e-290;
+            const double is = nrm_ok ? rsqrt_nr(x) : 1.0 / sqrt(x);
             sel[rank] = v;
-            sq[rank] = s;
-            isq[rank] = 1.0 / s;
+            sq[rank] = nrm_ok ? x * is : sqrt(x);
+            isq[rank] = is;
             kd[0] += 1.0;
             kd[1] += x;
         } else {
@@ -960,22 +976,37 @@ __device__ bool twosite_update(const MpsArgs& P, const Smem& S, SiteView<T> A, S
 
 // The fold of a product swap: with psi the unentangled qubit's state on
 // site ps (tensor P, pl x 2 x pr), M = sum_i conj(psi_i) P[:, i, :] is
-// formed in FP64 at mr/mi, then the product site receives the neighbour
-// times M: A[k] M (side 1, neighbour ol x 2 x pl) or M A[k+1] (side 0,
-// neighbour pr x 2 x ocr).  Whole team; ends after the writes.
-template <typename T, int W, typename MP, typename OP>
-__device__ void fold_product(MP mr, MP mi, OP ore, OP oim, SiteView<T> Pv, double p0r,
-                             double p0i, double p1r, double p1i, int side, int ol, int pl, int pr,
-                             int ocr) {
+// formed in FP64 at mr/mi (fold_m; when P has at most W elements each lane
+// passes the pair P[a, 0, b], P[a, 1, b] it already holds in x), then the
+// product site receives the neighbour times M: A[k] M (side 1, neighbour
+// ol x 2 x pl) or M A[k+1] (side 0, neighbour pr x 2 x ocr) (fold_apply).
+// Whole team; fold_m ends with the team synchronised, fold_apply after its
+// writes are issued.
+template <typename T, int W, typename MP>
+__device__ void fold_m(MP mr, MP mi, SiteView<T> Pv, double p0r, double p0i, double p1r,
+                       double p1i, int pl, int pr, const double (&x)[4]) {
     const int tid = Team<W>::rank();
-    for (int idx = tid; idx < pl * pr; idx += W) {
-        const int a = idx / pr, b = idx - a * pr;
-        const int i0 = (a * 2) * pr + b, i1 = i0 + pr;
-        const double x0r = Pv.re[i0], x0i = Pv.im[i0], x1r = Pv.re[i1], x1i = Pv.im[i1];
-        mr[idx] = p0r * x0r + p0i * x0i + p1r * x1r + p1i * x1i;
-        mi[idx] = p0r * x0i - p0i * x0r + p1r * x1i - p1i * x1r;
+    if (pl * pr <= W) {
+        if (tid < pl * pr) {
+            mr[tid] = p0r * x[0] + p0i * x[1] + p1r * x[2] + p1i * x[3];
+            mi[tid] = p0r * x[1] - p0i * x[0] + p1r * x[3] - p1i * x[2];
+        }
+    } else {
+        for (int idx = tid; idx < pl * pr; idx += W) {
+            const int a = idx / pr, b = idx - a * pr;
+            const int i0 = (a * 2) * pr + b, i1 = i0 + pr;
+            const double x0r = Pv.re[i0], x0i = Pv.im[i0], x1r = Pv.re[i1], x1i = Pv.im[i1];
+            mr[idx] = p0r * x0r + p0i * x0i + p1r * x1r + p1i * x1i;
+            mi[idx] = p0r * x0i - p0i * x0r + p1r * x1i - p1i * x1r;
+        }
     }
     Team<W>::sync();
+}
+
+template <typename T, int W, typename MP, typename OP>
+__device__ void fold_apply(MP mr, MP mi, OP ore, OP oim, SiteView<T> Pv, int side, int ol,
+                           int pl, int pr, int ocr) {
+    const int tid = Team<W>::rank();
     if (side) {
         // product on k+1: new A[k+1] = A[k] M  (ol, 2, pr)
         for (int idx = tid; idx < ol * 2 * pr; idx += W) {
@@ -1355,10 +1386,17 @@ __device__ void run_team(const MpsArgs& P, const Smem& S, const int team, const 
                     wave_load_lds(Ov.im, reinterpret_cast<T*>(S.u) + on16, on * sizeof(T));
                 }
                 double r4[4] = {0.0, 0.0, 0.0, 0.0};
+                double xk[4] = {0.0, 0.0, 0.0, 0.0};   // this lane's first pair, for M
                 for (int idx = tid; idx < pl * pr; idx += W) {
                     const int a = idx / pr, b = idx - a * pr;
                     const int i0 = (a * 2) * pr + b, i1 = i0 + pr;
                     const double x0r = Pv.re[i0], x0i = Pv.im[i0], x1r = Pv.re[i1], x1i = Pv.im[i1];
+                    if (idx == tid) {
+                        xk[0] = x0r;
+                        xk[1] = x0i;
+                        xk[2] = x1r;
+                        xk[3] = x1i;
+                    }
                     r4[0] += x0r * x0r + x0i * x0i;
                     r4[1] += x1r * x1r + x1i * x1i;
                     r4[2] += x0r * x1r + x0i * x1i;     // rho01 = x0 conj(x1)
@@ -1383,6 +1421,16 @@ __device__ void run_team(const MpsArgs& P, const Smem& S, const int team, const 
                 // M = sum_i conj(psi_i) P[:, i, :] (pl x pr, FP64), then the
                 // neighbour times M
                 const int newb = side ? ol : ocr;
+                // the unentangled qubit on the other site: psi (x) identity
+                const auto write_psi = [&]() {
+                    for (int idx = tid; idx < newb * 2 * newb; idx += W) {
+                        const int a = idx / (2 * newb), rem = idx - a * 2 * newb;
+                        const int i = rem / newb, a2 = rem - i * newb;
+                        const bool diag = a == a2;
+                        Ov.re[idx] = T(diag ? (i ? p1r : p0r) : 0.0);
+                        Ov.im[idx] = T(diag ? (i ? p1i : p0i) : 0.0);
+                    }
+                };
                 if (lds_fold) {
                     typedef __attribute__((address_space(3))) T lT;
                     lT* st = to_lds(reinterpret_cast<T*>(S.u));
@@ -1392,21 +1440,22 @@ __device__ void run_team(const MpsArgs& P, const Smem& S, const int team, const 
                             st[on16 + idx] = Ov.im[idx];
                         }
                     }
-                    fold_product<T, W>(to_lds(S.vre), to_lds(S.vim), st, st + on16, Pv, p0r, p0i,
-                                       p1r, p1i, side, ol, pl, pr, ocr);
+                    fold_m<T, W>(to_lds(S.vre), to_lds(S.vim), Pv, p0r, p0i, p1r, p1i, pl, pr, xk);
+                    // the neighbour's staging loads have completed (the
+                    // psi reads issued after them were waited for; the
+                    // explicit wait on the vector-memory counter states it),
+                    // so its site is rewritten alongside the fold
+                    if (W == 64) __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+                    write_psi();
+                    fold_apply<T, W>(to_lds(S.vre), to_lds(S.vim), st, st + on16, Pv, side, ol, pl,
+                                     pr, ocr);
                 } else {
                     glbd* mr = to_glb(scr);
-                    fold_product<T, W>(mr, mr + (size_t)pl * pr, Ov.re, Ov.im, Pv, p0r, p0i, p1r,
-                                       p1i, side, ol, pl, pr, ocr);
-                }
-                Team<W>::sync();
-                // the unentangled qubit on the other site: psi (x) identity
-                for (int idx = tid; idx < newb * 2 * newb; idx += W) {
-                    const int a = idx / (2 * newb), rem = idx - a * 2 * newb;
-                    const int i = rem / newb, a2 = rem - i * newb;
-                    const bool diag = a == a2;
-                    Ov.re[idx] = T(diag ? (i ? p1r : p0r) : 0.0);
-                    Ov.im[idx] = T(diag ? (i ? p1i : p0i) : 0.0);
+                    fold_m<T, W>(mr, mr + (size_t)pl * pr, Pv, p0r, p0i, p1r, p1i, pl, pr, xk);
+                    fold_apply<T, W>(mr, mr + (size_t)pl * pr, Ov.re, Ov.im, Pv, side, ol, pl, pr,
+                                     ocr);
+                    Team<W>::sync();
+                    write_psi();
                 }
                 if (tid == 0) S.chi[k + 1] = newb;
                 Team<W>::sync();

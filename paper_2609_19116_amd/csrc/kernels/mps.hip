@@ -218,6 +218,22 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
     return fma(0.5 * y, e, y);
 }
 
+// 1/d for a positive divisor: the hardware estimate refined by one Newton
+// step e = 1 - d y, y <- y + y e, to a relative error far below 2^-40.
+__device__ __forceinline__ double rcp_nr(int d) {
+    const double x = static_cast<double>(d);
+    const double y = __builtin_amdgcn_rcp(x);
+    return fma(y, fma(-x, y, 1.0), y);
+}
+
+// i / d for 0 <= i < 2^31 and 0 < d < 2^20 through inv = rcp_nr(d): the
+// exact quotient of i + 1/2 lies at least 1/(2d) from an integer, and the
+// product's error is below 2^-20, so truncation gives floor(i / d).  Three
+// vector operations instead of the integer division sequence.
+__device__ __forceinline__ int qdiv(int i, double inv) {
+    return static_cast<int>(fma(static_cast<double>(i), inv, 0.5 * inv));
+}
+
 template <typename T>
 __device__ __forceinline__ int round16(int n) {
     constexpr int q = 16 / static_cast<int>(sizeof(T));
@@ -573,8 +589,9 @@ __device__ bool move_fast(const MpsArgs& P, const Smem& S, SiteView<T> A, SiteVi
     {
         gT* Xre = dir ? Are : Bre;
         gT* Xim = dir ? Aim : Bim;
+        const double inv_len = rcp_nr(len);
         for (int idx = tid; idx < nv * len; idx += W) {
-            const int v = idx / len, e = idx - v * len;
+            const int v = qdiv(idx, inv_len), e = idx - v * len;
             const int at = dir ? e * cm + v : v * len + e;
             vre[v * ld + e] = static_cast<double>(Xre[at]);
             vim[v * ld + e] = static_cast<double>(Xim[at]);
@@ -600,8 +617,9 @@ __device__ bool move_fast(const MpsArgs& P, const Smem& S, SiteView<T> A, SiteVi
         // A[k] <- normalised columns; A[k+1] <- its selected rows, rescaled
         // (rows c of the new A[k+1] are rows sel[c] of the old one, so they
         // are read before any is written: staged first)
+        const double inv_r = rcp_nr(r);
         for (int idx = tid; idx < 2 * cl * r; idx += W) {
-            const int e = idx / r, c = idx - e * r;
+            const int e = qdiv(idx, inv_r), c = idx - e * r;
             const int v = sel[c];
             const double is = isq[c];
             Are[idx] = T(vre[v * ld + e] * is);
@@ -611,16 +629,18 @@ __device__ bool move_fast(const MpsArgs& P, const Smem& S, SiteView<T> A, SiteVi
         Team<W>::sync();
         if (pre) {
             // the old rows from the LDS copy, the new ones straight to B
+            const double inv_w = rcp_nr(w);
             for (int idx = tid; idx < r * w; idx += W) {
-                const int c = idx / w, x = idx - c * w;
+                const int c = qdiv(idx, inv_w), x = idx - c * w;
                 const int v = sel[c];
                 const double sc = sq[c] * renorm;
                 Bre[idx] = T(static_cast<double>(ure[v * w + x]) * sc);
                 Bim[idx] = T(static_cast<double>(uim[v * w + x]) * sc);
             }
         } else if (r * w <= vcap) {
+            const double inv_w = rcp_nr(w);
             for (int idx = tid; idx < r * w; idx += W) {
-                const int c = idx / w, x = idx - c * w;
+                const int c = qdiv(idx, inv_w), x = idx - c * w;
                 const int v = sel[c];
                 const double sc = sq[c] * renorm;
                 vre[idx] = static_cast<double>(Bre[v * w + x]) * sc;
@@ -634,8 +654,9 @@ __device__ bool move_fast(const MpsArgs& P, const Smem& S, SiteView<T> A, SiteVi
         } else {
             glbd* tr_ = to_glb(scr);
             glbd* ti_ = tr_ + (size_t)r * w;
+            const double inv_w = rcp_nr(w);
             for (int idx = tid; idx < r * w; idx += W) {
-                const int c = idx / w, x = idx - c * w;
+                const int c = qdiv(idx, inv_w), x = idx - c * w;
                 const int v = sel[c];
                 const double sc = sq[c] * renorm;
                 tr_[idx] = static_cast<double>(Bre[v * w + x]) * sc;
@@ -650,8 +671,9 @@ __device__ bool move_fast(const MpsArgs& P, const Smem& S, SiteView<T> A, SiteVi
     } else {
         // A[k+1] <- normalised rows; A[k] <- its selected columns, rescaled
         const int w = 2 * cr;
+        const double inv_w = rcp_nr(w);
         for (int idx = tid; idx < r * w; idx += W) {
-            const int c = idx / w, e = idx - c * w;
+            const int c = qdiv(idx, inv_w), e = idx - c * w;
             const int v = sel[c];
             const double is = isq[c];
             Bre[idx] = T(vre[v * ld + e] * is);
@@ -659,16 +681,18 @@ __device__ bool move_fast(const MpsArgs& P, const Smem& S, SiteView<T> A, SiteVi
         }
         Team<W>::sync();
         if (pre) {
+            const double inv_r = rcp_nr(r);
             for (int idx = tid; idx < 2 * cl * r; idx += W) {
-                const int row = idx / r, c = idx - row * r;
+                const int row = qdiv(idx, inv_r), c = idx - row * r;
                 const int v = sel[c];
                 const double sc = sq[c] * renorm;
                 Are[idx] = T(static_cast<double>(ure[row * cm + v]) * sc);
                 Aim[idx] = T(static_cast<double>(uim[row * cm + v]) * sc);
             }
         } else if (2 * cl * r <= vcap) {
+            const double inv_r = rcp_nr(r);
             for (int idx = tid; idx < 2 * cl * r; idx += W) {
-                const int row = idx / r, c = idx - row * r;
+                const int row = qdiv(idx, inv_r), c = idx - row * r;
                 const int v = sel[c];
                 const double sc = sq[c] * renorm;
                 vre[idx] = static_cast<double>(Are[row * cm + v]) * sc;
@@ -682,8 +706,9 @@ __device__ bool move_fast(const MpsArgs& P, const Smem& S, SiteView<T> A, SiteVi
         } else {
             glbd* tr_ = to_glb(scr);
             glbd* ti_ = tr_ + (size_t)2 * cl * r;
+            const double inv_r = rcp_nr(r);
             for (int idx = tid; idx < 2 * cl * r; idx += W) {
-                const int row = idx / r, c = idx - row * r;
+                const int row = qdiv(idx, inv_r), c = idx - row * r;
                 const int v = sel[c];
                 const double sc = sq[c] * renorm;
                 tr_[idx] = static_cast<double>(Are[row * cm + v]) * sc;
@@ -709,8 +734,9 @@ __device__ double contract(AP Ar, AP Ai, AP Br, AP Bi, int cl, int cm, int cr, c
                            const double* gph, int dir, int ld, DP vre, DP vim) {
     const int tid = Team<W>::rank();
     double nsum = 0.0;
+    const double inv_cr = rcp_nr(cr);
     for (int idx = tid; idx < cl * cr; idx += W) {
-        const int a = idx / cr, b = idx - a * cr;
+        const int a = qdiv(idx, inv_cr), b = idx - a * cr;
         T sr[4] = {T(0), T(0), T(0), T(0)}, si[4] = {T(0), T(0), T(0), T(0)};
         AP a0r = Ar + (a * 2) * cm;
         AP a0i = Ai + (a * 2) * cm;
@@ -753,8 +779,9 @@ __device__ void project(TP thr, TP thi, int m, int n, int r, int dir, int ld, co
                         __attribute__((address_space(1))) T* oim) {
     const int tid = Team<W>::rank();
     if (dir) {
+        const double inv_n = rcp_nr(n);
         for (int idx = tid; idx < r * n; idx += W) {
-            const int c = idx / n, col = idx - c * n;
+            const int c = qdiv(idx, inv_n), col = idx - c * n;
             const int v = V.sel[c];
             const double is = renorm * V.isq[c];
             DP ur = V.vre + (size_t)v * ld;
@@ -771,8 +798,9 @@ __device__ void project(TP thr, TP thi, int m, int n, int r, int dir, int ld, co
             oim[idx] = T(xi * is);
         }
     } else {
+        const double inv_r = rcp_nr(r);
         for (int idx = tid; idx < m * r; idx += W) {
-            const int row = idx / r, c = idx - row * r;
+            const int row = qdiv(idx, inv_r), c = idx - row * r;
             const int v = V.sel[c];
             const double is = renorm * V.isq[c];
             DP wr = V.vre + (size_t)v * ld;
@@ -872,8 +900,9 @@ __device__ bool twosite_update(const MpsArgs& P, const Smem& S, SiteView<T> A, S
         if (th_lds) {
             ldsd* thr = to_lds(S.u);
             ldsd* thi = thr + (size_t)m * n;
+            const double inv_n = rcp_nr(n);
             for (int idx = tid; idx < m * n; idx += W) {
-                const int row = idx / n, col = idx - row * n;
+                const int row = qdiv(idx, inv_n), col = idx - row * n;
                 const size_t vi = dir ? (size_t)col * ld + row : (size_t)row * ld + col;
                 thr[idx] = vre[vi];
                 thi[idx] = vim[vi];
@@ -881,8 +910,9 @@ __device__ bool twosite_update(const MpsArgs& P, const Smem& S, SiteView<T> A, S
         } else {
             glbd* thr = to_glb(scr);
             glbd* thi = thr + (size_t)m * n;
+            const double inv_n = rcp_nr(n);
             for (int idx = tid; idx < m * n; idx += W) {
-                const int row = idx / n, col = idx - row * n;
+                const int row = qdiv(idx, inv_n), col = idx - row * n;
                 const size_t vi = dir ? (size_t)col * ld + row : (size_t)row * ld + col;
                 thr[idx] = vre[vi];
                 thi[idx] = vim[vi];
@@ -919,8 +949,9 @@ __device__ bool twosite_update(const MpsArgs& P, const Smem& S, SiteView<T> A, S
     // orthogonality tolerance.
     if (dir) {
         // A[k] (cl,2,r): U[row][c] = w_sel[c][row] / |w|
+        const double inv_r = rcp_nr(r);
         for (int idx = tid; idx < m * r; idx += W) {
-            const int row = idx / r, c = idx - row * r;
+            const int row = qdiv(idx, inv_r), c = idx - row * r;
             const int v = sel[c];
             const double is = V.isq[c];
             Are[idx] = T(vre[(size_t)v * ld + row] * is);
@@ -928,8 +959,9 @@ __device__ bool twosite_update(const MpsArgs& P, const Smem& S, SiteView<T> A, S
         }
     } else {
         // A[k+1] (r,2,cr): V[c][col] = w_sel[c][col] / |w|
+        const double inv_n = rcp_nr(n);
         for (int idx = tid; idx < r * n; idx += W) {
-            const int c = idx / n, col = idx - c * n;
+            const int c = qdiv(idx, inv_n), col = idx - c * n;
             const int v = sel[c];
             const double is = V.isq[c];
             Bre[idx] = T(vre[(size_t)v * ld + col] * is);
@@ -938,15 +970,17 @@ __device__ bool twosite_update(const MpsArgs& P, const Smem& S, SiteView<T> A, S
     }
     if (!rotated) {
         if (dir) {
+            const double inv_n = rcp_nr(n);
             for (int idx = tid; idx < r * n; idx += W) {
-                const int c = idx / n, col = idx - c * n;
+                const int c = qdiv(idx, inv_n), col = idx - c * n;
                 const int v = sel[c];
                 Bre[idx] = T(col == v ? V.sq[c] * renorm : 0.0);
                 Bim[idx] = T(0);
             }
         } else {
+            const double inv_r = rcp_nr(r);
             for (int idx = tid; idx < m * r; idx += W) {
-                const int row = idx / r, c = idx - row * r;
+                const int row = qdiv(idx, inv_r), c = idx - row * r;
                 const int v = sel[c];
                 Are[idx] = T(row == v ? V.sq[c] * renorm : 0.0);
                 Aim[idx] = T(0);
@@ -992,8 +1026,9 @@ __device__ void fold_m(MP mr, MP mi, SiteView<T> Pv, double p0r, double p0i, dou
             mi[tid] = p0r * x[1] - p0i * x[0] + p1r * x[3] - p1i * x[2];
         }
     } else {
+        const double inv_pr = rcp_nr(pr);
         for (int idx = tid; idx < pl * pr; idx += W) {
-            const int a = idx / pr, b = idx - a * pr;
+            const int a = qdiv(idx, inv_pr), b = idx - a * pr;
             const int i0 = (a * 2) * pr + b, i1 = i0 + pr;
             const double x0r = Pv.re[i0], x0i = Pv.im[i0], x1r = Pv.re[i1], x1i = Pv.im[i1];
             mr[idx] = p0r * x0r + p0i * x0i + p1r * x1r + p1i * x1i;
@@ -1009,8 +1044,9 @@ __device__ void fold_apply(MP mr, MP mi, OP ore, OP oim, SiteView<T> Pv, int sid
     const int tid = Team<W>::rank();
     if (side) {
         // product on k+1: new A[k+1] = A[k] M  (ol, 2, pr)
+        const double inv_pr = rcp_nr(pr);
         for (int idx = tid; idx < ol * 2 * pr; idx += W) {
-            const int row = idx / pr, c = idx - row * pr;
+            const int row = qdiv(idx, inv_pr), c = idx - row * pr;
             double xr = 0.0, xi = 0.0;
 #pragma unroll 2
             for (int b = 0; b < pl; ++b) {
@@ -1025,8 +1061,9 @@ __device__ void fold_apply(MP mr, MP mi, OP ore, OP oim, SiteView<T> Pv, int sid
     } else {
         // product on k: new A[k] = M A[k+1]  (pl, 2, ocr)
         const int w = 2 * ocr;
+        const double inv_w = rcp_nr(w);
         for (int idx = tid; idx < pl * w; idx += W) {
-            const int a = idx / w, rem = idx - a * w;
+            const int a = qdiv(idx, inv_w), rem = idx - a * w;
             double xr = 0.0, xi = 0.0;
 #pragma unroll 2
             for (int b = 0; b < pr; ++b) {
@@ -1354,8 +1391,9 @@ __device__ void run_team(const MpsArgs& P, const Smem& S, const int team, const 
                     const double m4 = m[4], m5 = m[5], m6 = m[6], m7 = m[7];
                     SiteView<T> v = site(k);
                     const int cl = S.chi[k], cr = S.chi[k + 1];
+                    const double inv_cr = rcp_nr(cr);
                     for (int idx = tid; idx < cl * cr; idx += W) {
-                        const int a = idx / cr, b = idx - a * cr;
+                        const int a = qdiv(idx, inv_cr), b = idx - a * cr;
                         const int i0 = (a * 2) * cr + b, i1 = i0 + cr;
                         const double x0r = v.re[i0], x0i = v.im[i0], x1r = v.re[i1], x1i = v.im[i1];
                         v.re[i0] = T(m0 * x0r - m1 * x0i + m2 * x1r - m3 * x1i);
@@ -1387,8 +1425,9 @@ __device__ void run_team(const MpsArgs& P, const Smem& S, const int team, const 
                 }
                 double r4[4] = {0.0, 0.0, 0.0, 0.0};
                 double xk[4] = {0.0, 0.0, 0.0, 0.0};   // this lane's first pair, for M
+                const double inv_pr = rcp_nr(pr);
                 for (int idx = tid; idx < pl * pr; idx += W) {
-                    const int a = idx / pr, b = idx - a * pr;
+                    const int a = qdiv(idx, inv_pr), b = idx - a * pr;
                     const int i0 = (a * 2) * pr + b, i1 = i0 + pr;
                     const double x0r = Pv.re[i0], x0i = Pv.im[i0], x1r = Pv.re[i1], x1i = Pv.im[i1];
                     if (idx == tid) {
@@ -1423,9 +1462,11 @@ __device__ void run_team(const MpsArgs& P, const Smem& S, const int team, const 
                 const int newb = side ? ol : ocr;
                 // the unentangled qubit on the other site: psi (x) identity
                 const auto write_psi = [&]() {
+                    const double inv_newb = rcp_nr(newb);
+                    const double inv_2xnewb = rcp_nr(2 * newb);
                     for (int idx = tid; idx < newb * 2 * newb; idx += W) {
-                        const int a = idx / (2 * newb), rem = idx - a * 2 * newb;
-                        const int i = rem / newb, a2 = rem - i * newb;
+                        const int a = qdiv(idx, inv_2xnewb), rem = idx - a * 2 * newb;
+                        const int i = qdiv(rem, inv_newb), a2 = rem - i * newb;
                         const bool diag = a == a2;
                         Ov.re[idx] = T(diag ? (i ? p1r : p0r) : 0.0);
                         Ov.im[idx] = T(diag ? (i ? p1i : p0i) : 0.0);
@@ -1464,8 +1505,9 @@ __device__ void run_team(const MpsArgs& P, const Smem& S, const int team, const 
                 SiteView<T> v = site(k);
                 const int cl = S.chi[k], cr = S.chi[k + 1];
                 double pp[2] = {0.0, 0.0};
+                const double inv_cr = rcp_nr(cr);
                 for (int idx = tid; idx < cl * cr; idx += W) {
-                    const int a = idx / cr, b = idx - a * cr;
+                    const int a = qdiv(idx, inv_cr), b = idx - a * cr;
                     const int i0 = (a * 2) * cr + b, i1 = i0 + cr;
                     const double x0r = v.re[i0], x0i = v.im[i0], x1r = v.re[i1], x1i = v.im[i1];
                     pp[0] += x0r * x0r + x0i * x0i;
@@ -1501,7 +1543,7 @@ __device__ void run_team(const MpsArgs& P, const Smem& S, const int team, const 
                 meas_done = op.aux + 1;
                 const double sc = 1.0 / sqrt(raw);
                 for (int idx = tid; idx < cl * cr; idx += W) {
-                    const int a = idx / cr, b = idx - a * cr;
+                    const int a = qdiv(idx, inv_cr), b = idx - a * cr;
                     const int ie = (a * 2 + e) * cr + b, io = (a * 2 + 1 - e) * cr + b;
                     v.re[ie] = T(static_cast<double>(v.re[ie]) * sc);
                     v.im[ie] = T(static_cast<double>(v.im[ie]) * sc);
@@ -1523,8 +1565,9 @@ __device__ void run_team(const MpsArgs& P, const Smem& S, const int team, const 
                 }
                 const int cl = S.chi[k], cr = S.chi[k + 1];
                 double r[4] = {0.0, 0.0, 0.0, 0.0};   // r00, r11, Re r01, Im r01
+                const double inv_cr = rcp_nr(cr);
                 for (int idx = tid; idx < cl * cr; idx += W) {
-                    const int a = idx / cr, b = idx - a * cr;
+                    const int a = qdiv(idx, inv_cr), b = idx - a * cr;
                     const int i0 = (a * 2) * cr + b, i1 = i0 + cr;
                     const double x0r = v.re[i0], x0i = v.im[i0], x1r = v.re[i1], x1i = v.im[i1];
                     r[0] += x0r * x0r + x0i * x0i;

@@ -462,6 +462,34 @@ int msc_twosite_contract(msc_ctx* ctx, int32_t precision, int32_t chi,
                          int32_t batch, const float* A, const float* B,
                          const float* gate, float* theta);
 
+/* One two-site update through the batched large-update engine (Section
+   3.1; the exact regime of Section 5.1), on caller tensors.  For each of
+   `batch` independent pairs A_b (chi_l x 2 x chi_m) and B_b (chi_m x 2 x
+   chi_r): theta = G (A_b B_b) with the 4x4 gate `gate` (ids: 0 identity,
+   1 SWAP, 2 CX with control on A's qubit, 3 CX with control on B's, 4 CZ,
+   5 CS, 6 CS^dagger), contracted on MFMA in `precision` (MSC_FP32,
+   MSC_FP64, MSC_BF16X3); the FP64 Gram matrix of theta's vectors (columns
+   for dir 1, rows for dir 0) on MFMA; the FP64 Jacobi eigen-decomposition
+   of its overlapping block; then the split theta / |theta_kept| = A' B'
+   keeping the singular values sigma_i > tau sigma_0, at most chi_max of
+   them.  dir 1 leaves A' isometric (its (a,i) x c matrix has orthonormal
+   columns) and B' = Sigma V^H; dir 0 leaves B' isometric (orthonormal rows
+   c x (j,b)) and A' = U Sigma.
+   Layouts (host, FP64, planar per tensor): A is [batch][2 (re, im)]
+   [chi_l * 2 * chi_m] with element (a, i, c) at (a * 2 + i) * chi_m + c;
+   B is [batch][2][chi_m * 2 * chi_r] with (c, j, b) at (c * 2 + j) * chi_r
+   + b.  With rmax = min(chi_max, 2 min(chi_l, chi_r)): A_out is
+   [batch][2][chi_l * 2 * rmax] and B_out [batch][2][rmax * 2 * chi_r],
+   holding A' (chi_l x 2 x r) and B' (r x 2 x chi_r) densely with their
+   actual r = r_out[b] (host, batch) at the start of each plane, zeros after.
+   Bonds and chi_max in [1, 1024], batch in [1, 8192], tau in (0, 1);
+   synchronous; MSC_E_INVALID for bad arguments, MSC_E_OOM, MSC_E_DEVICE. */
+int msc_engine_update(msc_ctx* ctx, int32_t precision, int32_t chi_l,
+                      int32_t chi_m, int32_t chi_r, int32_t batch, int32_t dir,
+                      int32_t gate, int32_t chi_max, double tau, const double* A,
+                      const double* B, double* A_out, double* B_out,
+                      int32_t* r_out);
+
 /* ---------------------------------------------------------------------- */
 /* Re-weighting (Section 4.1, Eq. (reweight); Appendix "Systematics").     */
 

@@ -21,7 +21,7 @@ from ._lib import (BatchStats, EngineStats, TuneEntry, MSC_BF16X3, MSC_FP32, MSC
 __all__ = ["Ctx", "Circuit", "sample_faults", "sample_faults_device", "prescreen", "simulate",
            "simulate_camps", "camps_candidates",
            "run_batch", "reweight", "profile_loglik", "lr_interval", "ratio_credible",
-           "loss_factor", "expected_volume", "order_search", "twosite_contract", "prescreen_tables",
+           "loss_factor", "expected_volume", "order_search", "twosite_contract", "engine_update", "prescreen_tables",
            "autotune", "version", "MscError",
            "MSC_FP64", "MSC_FP32", "MSC_BF16X3", "order_cost", "MSC_STAT_PACC", "MSC_STAT_PLE", "SHOT_DTYPE"]
 
@@ -309,6 +309,34 @@ def twosite_contract(ctx: Ctx, chi: int, batch: int, A, B, gate, theta,
                      precision: int = MSC_FP32) -> None:
     _check(lib().msc_twosite_contract(ctx.h, precision, chi, batch, _ptr(A), _ptr(B), _ptr(gate),
                                       _ptr(theta)))
+
+
+def engine_update(ctx: Ctx, A, B, dir: int, gate: int, chi_max: int, tau: float,
+                  precision: int = MSC_FP64):
+    """msc_engine_update: one two-site update per batch element through the
+    batched engine.  A: complex (batch, chi_l, 2, chi_m), B: complex (batch,
+    chi_m, 2, chi_r) (numpy); returns the lists of new A' (chi_l, 2, r) and
+    B' (r, 2, chi_r) as complex numpy arrays."""
+    A = np.asarray(A)
+    B = np.asarray(B)
+    batch, cl, _, cm = A.shape
+    cr = B.shape[3]
+    assert B.shape == (batch, cm, 2, cr)
+    planar = lambda X: np.ascontiguousarray(
+        np.stack([X.real, X.imag], axis=1).reshape(X.shape[0], -1), dtype=np.float64)
+    a, b = planar(A), planar(B)
+    rmax = min(chi_max, 2 * min(cl, cr))
+    ao = np.zeros((batch, 2, cl * 2 * rmax))
+    bo = np.zeros((batch, 2, rmax * 2 * cr))
+    r = np.zeros(batch, dtype=np.int32)
+    _check(lib().msc_engine_update(ctx.h, precision, cl, cm, cr, batch, dir, gate, chi_max, tau,
+                                   _ptr(a), _ptr(b), _ptr(ao), _ptr(bo), _ptr(r)))
+    outa, outb = [], []
+    for i in range(batch):
+        k = int(r[i])
+        outa.append((ao[i, 0, :cl * 2 * k] + 1j * ao[i, 1, :cl * 2 * k]).reshape(cl, 2, k))
+        outb.append((bo[i, 0, :k * 2 * cr] + 1j * bo[i, 1, :k * 2 * cr]).reshape(k, 2, cr))
+    return outa, outb
 
 
 def autotune(ctx: Ctx, precision: int = MSC_FP32, reps: int = 5, cache_path=None) -> list:

@@ -141,6 +141,9 @@ _SIGS = {
     "msc_run_batch": (C.c_int, [_P, _P, C.POINTER(SimOpts), C.c_uint64, C.c_uint64, C.c_int64,
                                 C.c_double, C.c_int32, _P, C.POINTER(BatchStats), _P, _P]),
     "msc_twosite_contract": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, _P]),
+    "msc_engine_update": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                    C.c_int32, C.c_int32, C.c_int32, C.c_double, _P, _P, _P, _P,
+                                    _P]),
     "msc_autotune": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_char_p, _P]),
     "msc_simulate_camps": (C.c_int, [_P, _P, C.POINTER(SimOpts), C.c_int64, _P, _P, _P, _P,
                                      C.c_int64, _P]),

@@ -1697,6 +1697,151 @@ extern "C" int msc_autotune(msc_ctx* ctx, int32_t precision, int32_t reps, const
     return MSC_OK;
 }
 
+extern "C" int msc_engine_update(msc_ctx* ctx, int32_t precision, int32_t chi_l,
+                                 int32_t chi_m, int32_t chi_r, int32_t batch, int32_t dir,
+                                 int32_t gate, int32_t chi_max, double tau, const double* A,
+                                 const double* B, double* A_out, double* B_out, int32_t* r_out) {
+    if (!ctx || !A || !B || !A_out || !B_out || !r_out) return set_error(MSC_E_INVALID, "null argument");
+    if (precision != MSC_FP32 && precision != MSC_FP64 && precision != MSC_BF16X3)
+        return set_error(MSC_E_INVALID, "unknown precision");
+    if (chi_l < 1 || chi_m < 1 || chi_r < 1 || chi_l > kMaxChiKernel || chi_m > kMaxChiKernel ||
+        chi_r > kMaxChiKernel || chi_max < 1 || chi_max > kMaxChiKernel)
+        return set_error(MSC_E_INVALID, "bonds and chi_max must be in [1, " +
+                                            std::to_string(kMaxChiKernel) + "]");
+    if (batch < 1 || batch > kLxMaxParked)
+        return set_error(MSC_E_INVALID, "batch must be in [1, " + std::to_string(kLxMaxParked) + "]");
+    if ((dir != 0 && dir != 1) || gate < 0 || gate >= G4_COUNT || !(tau > 0.0 && tau < 1.0))
+        return set_error(MSC_E_INVALID, "dir must be 0 or 1, gate a 4x4 gate id, tau in (0, 1)");
+    MSC_HIP(hipSetDevice(ctx->device));
+    const size_t tsize = precision == MSC_FP64 ? sizeof(double) : sizeof(float);
+    // the factor's vector arrays hold theta sides up to 2 cf
+    const int cf = std::max(chi_max, std::max(chi_l, chi_r));
+    const int rmax = std::min(chi_max, 2 * std::min(chi_l, chi_r));
+    const int cb = std::max(chi_m, rmax);                       // capacity of the middle bond
+    const int64_t pa = 2ll * chi_l * cb, pb = 2ll * cb * chi_r;  // plane capacities
+    const int64_t stride = (2 * pa + 2 * pb + 15) / 16 * 16;
+    const int64_t S = 2ll * cf;
+    std::vector<ShotState> st(batch);
+    std::vector<int32_t> list(batch);
+    for (int i = 0; i < batch; ++i) {
+        st[i] = ShotState{};
+        st[i].status = kSlotParked;
+        st[i].k = 0;
+        st[i].dir = dir;
+        st[i].gate_id = gate;
+        st[i].chi[0] = chi_l;
+        st[i].chi[1] = chi_m;
+        st[i].chi[2] = chi_r;
+        list[i] = i;
+    }
+    // inputs into the slots' layout, in the tensor type
+    const int64_t na = 2ll * chi_l * chi_m, nb = 2ll * chi_m * chi_r;
+    std::vector<double> hd(static_cast<size_t>(batch) * stride, 0.0);
+    for (int i = 0; i < batch; ++i) {
+        double* slot = hd.data() + static_cast<size_t>(i) * stride;
+        const double* a = A + static_cast<size_t>(i) * 2 * na;
+        const double* b = B + static_cast<size_t>(i) * 2 * nb;
+        std::copy(a, a + na, slot);
+        std::copy(a + na, a + 2 * na, slot + pa);
+        std::copy(b, b + nb, slot + 2 * pa);
+        std::copy(b + nb, b + 2 * nb, slot + 2 * pa + pb);
+    }
+    std::vector<double> g4(G4_COUNT * 32);
+    for (int g = 0; g < G4_COUNT; ++g) gate4_matrix(g, &g4[g * 32]);
+    const int32_t cap[3] = {chi_l, chi_max, chi_r};
+    const int64_t off[2] = {0, 2 * pa}, half[2] = {pa, pb};
+    const int32_t count = batch;
+    int rc;
+    void *dstate, *dcount, *dlist, *dplan, *darena, *dtheta, *dgram, *doff, *dhalf, *dg4, *dfl, *dcap;
+    if ((rc = ctx_buf(ctx, "eu_state", batch * sizeof(ShotState), &dstate))) return rc;
+    if ((rc = ctx_buf(ctx, "eu_count", sizeof(int32_t), &dcount))) return rc;
+    if ((rc = ctx_buf(ctx, "eu_list", batch * sizeof(int32_t), &dlist))) return rc;
+    if ((rc = ctx_buf(ctx, "eu_plan", sizeof(LxPlan), &dplan))) return rc;
+    if ((rc = ctx_buf(ctx, "eu_arena", batch * stride * tsize, &darena))) return rc;
+    if ((rc = ctx_buf(ctx, "eu_theta", batch * 2 * S * S * tsize, &dtheta))) return rc;
+    if ((rc = ctx_buf(ctx, "eu_gram", batch * lx_gram_doubles(S) * sizeof(double), &dgram))) return rc;
+    if ((rc = ctx_buf(ctx, "eu_off", sizeof(off), &doff))) return rc;
+    if ((rc = ctx_buf(ctx, "eu_half", sizeof(half), &dhalf))) return rc;
+    if ((rc = ctx_buf(ctx, "eu_g4", g4.size() * sizeof(double), &dg4))) return rc;
+    if ((rc = ctx_buf(ctx, "eu_flops", 6 * sizeof(double), &dfl))) return rc;
+    if ((rc = ctx_buf(ctx, "eu_cap", sizeof(cap), &dcap))) return rc;
+    MSC_HIP(hipMemcpy(dstate, st.data(), batch * sizeof(ShotState), hipMemcpyHostToDevice));
+    MSC_HIP(hipMemcpy(dcount, &count, sizeof(count), hipMemcpyHostToDevice));
+    MSC_HIP(hipMemcpy(dlist, list.data(), batch * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (precision == MSC_FP64) {
+        MSC_HIP(hipMemcpy(darena, hd.data(), hd.size() * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> hf(hd.begin(), hd.end());
+        MSC_HIP(hipMemcpy(darena, hf.data(), hf.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    MSC_HIP(hipMemcpy(doff, off, sizeof(off), hipMemcpyHostToDevice));
+    MSC_HIP(hipMemcpy(dhalf, half, sizeof(half), hipMemcpyHostToDevice));
+    MSC_HIP(hipMemcpy(dg4, g4.data(), g4.size() * sizeof(double), hipMemcpyHostToDevice));
+    MSC_HIP(hipMemcpy(dcap, cap, sizeof(cap), hipMemcpyHostToDevice));
+    LxArgs la{};
+    la.state = static_cast<const ShotState*>(dstate);
+    la.park_count = static_cast<const int32_t*>(dcount);
+    la.park_list = static_cast<const int32_t*>(dlist);
+    la.plan = static_cast<LxPlan*>(dplan);
+    la.arena = darena;
+    la.slot_stride = stride;
+    la.site_off = static_cast<const int64_t*>(doff);
+    la.site_half = static_cast<const int64_t*>(dhalf);
+    la.g4 = static_cast<const double*>(dg4);
+    la.theta = dtheta;
+    la.theta_stride = 2 * S * S;
+    la.gram = static_cast<double*>(dgram);
+    la.gram_stride = lx_gram_doubles(S);
+    la.n_slots = batch;
+    la.flops = static_cast<double*>(dfl);
+    la.counts = reinterpret_cast<unsigned long long*>(la.flops + 2);
+    LxFactor fac{};
+    fac.cap = static_cast<const int32_t*>(dcap);
+    fac.chi_max = cf;
+    fac.tau = tau;
+    LxTiles tiles[kLxBuckets];
+    default_tiles(precision, tiles);
+    const int grid = ctx->n_cu * 4;
+    hipStream_t s = ctx->stream;
+    MSC_HIP(hipEventRecord(ctx->ev0, s));
+    MSC_HIP(launch_lx_plan(la, tiles, s));
+    for (int b = 0; b < kLxBuckets; ++b) MSC_HIP(launch_lx_contract(precision, la, b, tiles[b], grid, s));
+    for (int b = 0; b < kLxBuckets; ++b) MSC_HIP(launch_lx_gram(precision, la, b, tiles[b], grid, s));
+    MSC_HIP(launch_lx_factor(precision, la, fac, batch, s));
+    MSC_HIP(hipEventRecord(ctx->ev1, s));
+    MSC_HIP(hipStreamSynchronize(s));
+    float ms = 0.f;
+    MSC_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    ctx->last_ms["engine_update"] = ms;
+    MSC_HIP(hipMemcpy(st.data(), dstate, batch * sizeof(ShotState), hipMemcpyDeviceToHost));
+    if (precision == MSC_FP64) {
+        MSC_HIP(hipMemcpy(hd.data(), darena, hd.size() * sizeof(double), hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> hf(hd.size());
+        MSC_HIP(hipMemcpy(hf.data(), darena, hf.size() * sizeof(float), hipMemcpyDeviceToHost));
+        std::copy(hf.begin(), hf.end(), hd.begin());
+    }
+    const int64_t oa = 2ll * chi_l * rmax, ob = 2ll * rmax * chi_r;   // output planes
+    for (int i = 0; i < batch; ++i) {
+        const int r = st[i].chi[1];
+        if (r < 1 || r > rmax)
+            return set_error(MSC_E_DEVICE, "engine update " + std::to_string(i) +
+                                               " returned bond " + std::to_string(r));
+        r_out[i] = r;
+        const double* slot = hd.data() + static_cast<size_t>(i) * stride;
+        double* ao = A_out + static_cast<size_t>(i) * 2 * oa;
+        double* bo = B_out + static_cast<size_t>(i) * 2 * ob;
+        std::fill(ao, ao + 2 * oa, 0.0);
+        std::fill(bo, bo + 2 * ob, 0.0);
+        const int64_t ua = 2ll * chi_l * r, ub = 2ll * r * chi_r;
+        std::copy(slot, slot + ua, ao);
+        std::copy(slot + pa, slot + pa + ua, ao + oa);
+        std::copy(slot + 2 * pa, slot + 2 * pa + ub, bo);
+        std::copy(slot + 2 * pa + pb, slot + 2 * pa + pb + ub, bo + ob);
+    }
+    return MSC_OK;
+}
+
 extern "C" int msc_twosite_contract(msc_ctx* ctx, int32_t precision, int32_t chi, int32_t batch,
                                     const float* A, const float* B, const float* gate, float* theta) {
     if (!ctx || !A || !B || !gate || !theta) return set_error(MSC_E_INVALID, "null argument");

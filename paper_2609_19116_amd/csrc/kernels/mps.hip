@@ -1973,6 +1973,7 @@ __global__ __launch_bounds__(NT) void lx_factor_kernel(LxArgs a, LxFactor f) {
         for (int j = tid; j < nf; j += NT) fpos[list[j]] = j;
         int sweeps = 0;
         bool noconv = false;
+        bool polished = false;   // Y rotated after the eigen-decomposition
         const bool small = nf <= FM;
         // workspace of the rotated vectors: planar FP64, vector j at j * ldy
         const int ldy = len + 1;
@@ -2108,6 +2109,30 @@ __global__ __launch_bounds__(NT) void lx_factor_kernel(LxArgs a, LxFactor f) {
                 }
                 __syncthreads();
             }
+            // ---- polish Y: eigenvectors of G leave the rotated vectors
+            // orthogonal only to about eps |G| / (sigma_u sigma_v), and a
+            // null-space direction with a norm near eps sigma_0^3 /
+            // sigma_min^2, which can pass the exact regime's threshold; one-
+            // sided Jacobi on Y (quadratically convergent from here) brings
+            // both to the tensor precision's resolution.  The centre factor
+            // is then the projection of theta on the isometric factor.
+            for (int j = tid; j < nf; j += NT) sel[j] = j;
+            __syncthreads();
+            vector_norms<NT>(Yr, Yi, nf, len, ldy, nrm);
+            bool again2 = not_orthogonal<NT>(Yr, Yi, nf, len, ldy, nrm, floor2, tol, bad,
+                                             (glbi*)nullptr);
+            polished = again2;
+            int psweeps = 0;
+            while (again2 && psweeps < 40) {
+                const int nb2 = flagged_list<NT>(bad, nf, sel, s_ired);
+                jacobi_sweep<NT>(Yr, Yi, sel, nb2, len, ldy, floor2, tol);
+                ++psweeps;
+                vector_norms<NT>(Yr, Yi, nf, len, ldy, nrm);
+                again2 = not_orthogonal<NT>(Yr, Yi, nf, len, ldy, nrm, floor2, tol, bad,
+                                            (glbi*)nullptr);
+            }
+            sweeps += psweeps;
+            noconv = noconv || again2;
         } else if (nf > 0) {
             // ---- many overlapping vectors: one-sided Jacobi in the workspace
             for (int idx = tid; idx < nf * len; idx += NT) {
@@ -2184,7 +2209,7 @@ __global__ __launch_bounds__(NT) void lx_factor_kernel(LxArgs a, LxFactor f) {
             }
         }
         // ---- centre factor
-        if (nf == 0 || small) {
+        if (nf == 0 || (small && !polished)) {
             // sigma_u conj(W[:, u]) on the flagged positions, sigma_u e_v for
             // an unflagged vector v (entry (u, v) of Sigma W~^H)
             auto centre = [&](int c, int v, double& xr, double& xi) {

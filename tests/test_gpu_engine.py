@@ -212,3 +212,92 @@ def test_engine_bf16x3_golden_large_bonds(ctx, name, chi):
     _compare(res, ref, 1e-4)
     acc = ref[:, 0] > 0
     assert np.all(res["chi_peak"][acc] >= chi)
+
+
+# gate ids of msc_engine_update and the oracle's 4x4 matrices over |q_A q_B>
+_ENGINE_GATES = {2: "CX", 4: "CZ", 1: "SWAP", 5: "CS"}
+
+
+def _theta(A, B, gname):
+    """theta = G (A B) in FP64 as the (chi_l 2) x (2 chi_r) matrix, from the
+    oracle's gate matrix."""
+    from oracle.gates import G2
+    g = G2[gname].reshape(2, 2, 2, 2)
+    pre = np.einsum("aic,cjb->aijb", A, B)
+    th = np.einsum("xyij,aijb->axyb", g, pre)
+    cl, cr = A.shape[0], B.shape[2]
+    return th.reshape(2 * cl, 2 * cr)
+
+
+@pytest.mark.parametrize("precision,tau,tol", [(MSC_FP64, 1e-12, 1e-12), (MSC_FP32, 1e-5, 2e-5),
+                                               (msc.MSC_BF16X3, 1e-4, 1e-4)])
+@pytest.mark.parametrize("dir", [1, 0])
+@pytest.mark.parametrize("cl,cm,cr,gid", [(64, 40, 48, 2), (24, 16, 20, 4), (16, 24, 40, 1)])
+def test_engine_update_against_lapack_svd(ctx, precision, tau, tol, dir, cl, cm, cr, gid):
+    """One batched engine update on random tensors whose theta has a rank
+    below both sides (the CX and CZ products have operator Schmidt rank 2,
+    so rank <= 2 chi_m; SWAP: <= 4 chi_m): the kept bond is LAPACK's
+    numerical rank at the same threshold, A' B' reproduces theta / |theta|,
+    the isometric factor is isometric and the other factor's norms are
+    LAPACK's singular values (all to `tol`, relative to sigma_0).  theta's
+    sides 128 x 96 flag more than 64 overlapping vectors (the workspace
+    route); the others fewer (the LDS eigen-decomposition, whose rotated
+    vectors are polished by one-sided Jacobi: without it, null directions
+    kept norms near eps sigma_0^3 / sigma_min^2 and passed the threshold)."""
+    rng = np.random.default_rng(0x5EED0051 + 7 * cl + dir)
+    batch = 5
+    A = rng.normal(size=(batch, cl, 2, cm)) + 1j * rng.normal(size=(batch, cl, 2, cm))
+    B = rng.normal(size=(batch, cm, 2, cr)) + 1j * rng.normal(size=(batch, cm, 2, cr))
+    A /= np.sqrt(cl * cm)
+    B /= np.sqrt(cm * cr)
+    say(f"engine update precision={precision} dir={dir} shape={cl}x{cm}x{cr} gate={gid}")
+    outa, outb = msc.engine_update(ctx, A, B, dir, gid, 1024, tau, precision=precision)
+    for i in range(batch):
+        th = _theta(A[i], B[i], _ENGINE_GATES[gid])
+        s = np.linalg.svd(th, compute_uv=False)
+        r = int(np.sum(s > tau * s[0]))
+        a, b = outa[i], outb[i]
+        assert a.shape[2] == r and b.shape[0] == r, (i, a.shape, b.shape, r)
+        U = a.reshape(2 * cl, r)
+        V = b.reshape(r, 2 * cr)
+        nk = np.sqrt(np.sum(s[:r] ** 2))
+        err = np.linalg.norm(U @ V - th / nk) / np.linalg.norm(th / nk)
+        assert err <= tol, (i, err)
+        if dir:
+            iso = np.abs(U.conj().T @ U - np.eye(r)).max()
+            sv = np.linalg.norm(V, axis=1)
+        else:
+            iso = np.abs(V @ V.conj().T - np.eye(r)).max()
+            sv = np.linalg.norm(U, axis=0)
+        assert iso <= tol, (i, iso)
+        dev = np.abs(np.sort(sv)[::-1] - s[:r] / nk).max() / (s[0] / nk)
+        assert dev <= tol, (i, dev)
+        if i == 0:
+            say(f"  r={r} reconstruction {err:.2e} isometry {iso:.2e} sigma {dev:.2e}")
+
+
+def test_engine_update_degenerate_spectrum(ctx):
+    """theta with all singular values equal (isometric A and B, the
+    stabiliser-like case): nothing overlaps, every vector is kept, and the
+    factors reproduce theta."""
+    cl, cm, cr = 32, 64, 32
+    A = np.eye(2 * cl, cm).reshape(1, cl, 2, cm).astype(np.complex128)
+    B = np.eye(cm, 2 * cr).reshape(1, cm, 2, cr).astype(np.complex128)
+    for precision in (MSC_FP64, MSC_FP32):
+        outa, outb = msc.engine_update(ctx, A, B, 1, 2, 1024, 1e-12 if precision == MSC_FP64
+                                       else 1e-5, precision=precision)
+        th = _theta(A[0], B[0], "CX")
+        a, b = outa[0], outb[0]
+        assert a.shape[2] == 64
+        U, V = a.reshape(2 * cl, 64), b.reshape(64, 2 * cr)
+        assert np.abs(U @ V - th / np.linalg.norm(th)).max() <= 1e-6
+
+
+def test_engine_update_errors(ctx):
+    A = np.zeros((1, 4, 2, 4), dtype=np.complex128)
+    B = np.zeros((1, 4, 2, 4), dtype=np.complex128)
+    for kw in ({"dir": 2, "gate": 2}, {"dir": 1, "gate": 9}):
+        with pytest.raises(RuntimeError):
+            msc.engine_update(ctx, A, B, kw["dir"], kw["gate"], 16, 1e-12)
+    with pytest.raises(RuntimeError):
+        msc.engine_update(ctx, A, B, 1, 2, 16, 0.0)

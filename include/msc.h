@@ -61,7 +61,10 @@ enum msc_shot_status {
     MSC_SHOT_DONE = 1,          /* reached the end of the circuit             */
     MSC_SHOT_REJECTED = 2,      /* an expected outcome had p < tau_rej        */
     MSC_SHOT_CHI_CAP = 4,       /* chi_max bound with weight > 1e-12 dropped  */
-    MSC_SHOT_NOCONV = 8         /* an SVD hit its sweep limit                 */
+    MSC_SHOT_NOCONV = 8,        /* an SVD hit its sweep limit                 */
+    MSC_SHOT_MPS_RERUN = 16     /* CAMPS only: the residual outgrew its bond
+                                   cap and the shot was run again by the FP64
+                                   MPS path, whose record this is            */
 };
 
 typedef struct msc_ctx msc_ctx;
@@ -401,11 +404,15 @@ int msc_run_batch(msc_ctx* ctx, const msc_circuit* c, const msc_sim_opts* opts,
    acts on two sites or more, a greedy sweep over its bonds moves the
    entanglement-lowering two-qubit Clifford of highest purity gain (19
    classes modulo local Cliffords) into the frame.  opts: precision
-   MSC_FP64, chi_max in [1, 32] (the residual's bond cap: shots that need
-   more end with MSC_SHOT_CHI_CAP and P_acc 0), lds_width 0 and wave_chi 0 or -1;
+   MSC_FP64, chi_max in [1, 32] (the residual's bond cap: a shot that needs
+   more is run again, after the CAMPS launch, by the plain FP64 MPS path of
+   msc_simulate with bond cap 256 and the same tau's and prefix option; its
+   record is that path's, with MSC_SHOT_MPS_RERUN set), lds_width 0 and
+   wave_chi 0 or -1;
    prefix 1 forks every shot from a checkpoint of the noiseless CAMPS run
    taken before its first fault (built on first use, <= 2 GiB; results are
-   bit-identical to prefix 0).  out[i].chi_peak is the residual's peak bond dimension,
+   bit-identical to prefix 0; MSC_E_NONDETERMINISTIC if the noiseless run's
+   residual outgrows the cap).  out[i].chi_peak is the residual's peak bond dimension,
    out[i].n2q the disentangling Cliffords applied; disc_weight and flops
    are 0.  Requires a calibrated circuit with at most 127 qubits.         */
 int msc_simulate_camps(msc_ctx* ctx, const msc_circuit* c, const msc_sim_opts* opts,

@@ -14,7 +14,7 @@ import numpy as np
 
 from ._lib import (BatchStats, EngineStats, TuneEntry, MSC_BF16X3, MSC_FP32, MSC_FP64, MSC_STAT_PACC,  # noqa: F401
                    MSC_ORDER_COST_MOVE, MSC_ORDER_COST_PSWAP, MSC_ORDER_COST_TWOSITE,
-                   MSC_STAT_PLE, SEGMENT_DTYPE, SHOT_CHI_CAP, SHOT_DONE, SHOT_DTYPE, SHOT_NOCONV,
+                   MSC_STAT_PLE, SEGMENT_DTYPE, SHOT_CHI_CAP, SHOT_DONE, SHOT_DTYPE, SHOT_NOCONV, SHOT_MPS_RERUN,
                    SHOT_REJECTED, CircuitInfo, Estimate, Interval, MscError, SimOpts, _check,
                    _ptr, lib)
 

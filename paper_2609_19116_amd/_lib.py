@@ -37,6 +37,7 @@ SHOT_DONE = 1
 SHOT_REJECTED = 2
 SHOT_CHI_CAP = 4
 SHOT_NOCONV = 8
+SHOT_MPS_RERUN = 16
 
 
 class CircuitInfo(C.Structure):

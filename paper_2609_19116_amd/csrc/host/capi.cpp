@@ -1428,9 +1428,51 @@ extern "C" int msc_simulate_camps(msc_ctx* ctx, const msc_circuit* c, const msc_
     const double tau_fail = opts->tau_fail > 0 ? opts->tau_fail : 1e-4;
     if (opts->prefix && (rc = ensure_camps_prefix(ctx, cc, opts->chi_max, tau, tau_rej, tau_fail)))
         return rc;
-    return run_camps(ctx, cc, opts->chi_max, tau, tau_rej, tau_fail, opts->n_slots, n, n_shots,
-                     shot_off, chan, pauli, shot_idx, out, opts->prefix ? 2 : 0,
-                     opts->prefix ? &cc->camps_prefix : nullptr, "camps");
+    if ((rc = run_camps(ctx, cc, opts->chi_max, tau, tau_rej, tau_fail, opts->n_slots, n, n_shots,
+                        shot_off, chan, pauli, shot_idx, out, opts->prefix ? 2 : 0,
+                        opts->prefix ? &cc->camps_prefix : nullptr, "camps")))
+        return rc;
+    // shots whose residual outgrew the cap: run again by the FP64 MPS path
+    std::vector<msc_shot_result> h(n);
+    MSC_HIP(hipMemcpy(h.data(), out, n * sizeof(msc_shot_result), hipMemcpyDeviceToHost));
+    std::vector<int64_t> pos, ids;
+    std::vector<int64_t> hsel;
+    if (shot_idx) {
+        hsel.resize(n);
+        MSC_HIP(hipMemcpy(hsel.data(), shot_idx, n * sizeof(int64_t), hipMemcpyDeviceToHost));
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        if (h[i].status & MSC_SHOT_CHI_CAP) {
+            pos.push_back(i);
+            ids.push_back(shot_idx ? hsel[i] : i);
+        }
+    }
+    if (pos.empty()) return MSC_OK;
+    const int64_t k = static_cast<int64_t>(pos.size());
+    void *didx, *dres;
+    if ((rc = ctx_buf(ctx, "camps_rerun_idx", k * sizeof(int64_t), &didx))) return rc;
+    if ((rc = ctx_buf(ctx, "camps_rerun_out", k * sizeof(msc_shot_result), &dres))) return rc;
+    MSC_HIP(hipMemcpy(didx, ids.data(), k * sizeof(int64_t), hipMemcpyHostToDevice));
+    msc_sim_opts mo{};
+    mo.precision = MSC_FP64;
+    mo.chi_max = 256;
+    mo.tau_trunc = opts->tau_trunc;
+    mo.tau_rej = opts->tau_rej;
+    mo.tau_fail = opts->tau_fail;
+    mo.prefix = opts->prefix;
+    mo.wave_chi = -1;
+    if ((rc = msc_simulate(ctx, c, &mo, n_shots, shot_off, chan, pauli,
+                           static_cast<const int64_t*>(didx), k,
+                           static_cast<msc_shot_result*>(dres))))
+        return rc;
+    std::vector<msc_shot_result> r(k);
+    MSC_HIP(hipMemcpy(r.data(), dres, k * sizeof(msc_shot_result), hipMemcpyDeviceToHost));
+    for (int64_t j = 0; j < k; ++j) {
+        r[j].status |= MSC_SHOT_MPS_RERUN;
+        h[pos[j]] = r[j];
+    }
+    MSC_HIP(hipMemcpy(out, h.data(), n * sizeof(msc_shot_result), hipMemcpyHostToDevice));
+    return MSC_OK;
 }
 
 static int run_camps(msc_ctx* ctx, msc_circuit* c, int chi_cap, double tau, double tau_rej,

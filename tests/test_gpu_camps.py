@@ -108,24 +108,6 @@ def test_camps_clifford_circuit_has_product_residual(ctx):
     assert np.allclose(a["p_acc"], b["p_acc"], atol=1e-10, rtol=0)
 
 
-def test_camps_bond_cap_flags_shots(ctx):
-    # a residual cap below what the shots need: those shots end flagged
-    # with P_acc 0; the others still equal the MPS path
-    cc, circ = _circ(ctx, "c1")
-    n = 96
-    w = np.array([0, 1, 2, 3] * (n // 4), dtype=np.int32)
-    say("camps c1 chi_max=2")
-    off, ch, pa = msc.sample_faults_device(ctx, circ, 0x5EED0075, 0, n, weights=w)
-    a = results_numpy(msc.simulate_camps(ctx, circ, off, ch, pa, chi_max=2))
-    b = results_numpy(msc.simulate(ctx, circ, off, ch, pa, precision=MSC_FP64))
-    capped = (a["status"] & msc.SHOT_CHI_CAP) != 0
-    assert capped.any()
-    assert (a["p_acc"][capped] == 0).all()
-    ok = ~capped
-    assert np.allclose(a["p_acc"][ok], b["p_acc"][ok], atol=1e-9, rtol=0)
-    assert (a["chi_peak"][ok] <= 2).all()
-
-
 def test_camps_argument_errors(ctx):
     import torch
     cc, circ = _circ(ctx, "tiny")
@@ -139,3 +121,38 @@ def test_camps_argument_errors(ctx):
                              shot_idx=torch.tensor([0, 9, -1], dtype=torch.int64, device="cuda"))
     r = results_numpy(out)
     assert r["status"][1] == 0 and r["status"][2] == 0 and r["status"][0] & msc.SHOT_DONE
+
+
+def test_camps_cap_reruns_on_mps(ctx):
+    """A residual bond cap that binds (2 here, on the 17-qubit circuit whose
+    residual reaches 4) no longer ends the shot with P_acc 0: the shot is
+    run again by the FP64 MPS path, whose record it then carries bit for
+    bit (flagged MSC_SHOT_MPS_RERUN); every shot still equals the MPS path
+    to 1e-10.  Forking needs the noiseless residual within the cap."""
+    import torch
+    cc, circ = _circ(ctx, "c1")
+    seed, n = 0x5EED0072, 96
+    w = np.array([0, 1, 2, 3] * (n // 4), dtype=np.int32)
+    off, ch, pa = msc.sample_faults_device(ctx, circ, seed, 0, n, weights=w)
+    prefix = False
+    say("camps cap 2")
+    res = results_numpy(msc.simulate_camps(ctx, circ, off, ch, pa, chi_max=2, prefix=prefix))
+    mps = results_numpy(msc.simulate(ctx, circ, off, ch, pa, precision=MSC_FP64, chi_max=256,
+                                     wave_chi=-1, prefix=prefix))
+    rerun = (res["status"] & msc.SHOT_MPS_RERUN) != 0
+    assert rerun.sum() >= 10, rerun.sum()
+    assert not np.any(res["status"][~rerun] & msc.SHOT_CHI_CAP)
+    for f in ("p_acc", "infid", "disc_weight", "chi_peak", "rejected_at", "fail", "n2q"):
+        assert np.array_equal(res[f][rerun], mps[f][rerun]), f
+    assert np.array_equal(res["status"][rerun], mps["status"][rerun] | msc.SHOT_MPS_RERUN)
+    assert np.array_equal(res["rejected_at"], mps["rejected_at"])
+    acc = mps["p_acc"] > 0
+    assert np.abs(res["p_acc"] - mps["p_acc"])[acc].max() <= 1e-10 * mps["p_acc"][acc].max()
+    # a selection of shots (device shot_idx) reruns the selected shot ids
+    idx = torch.tensor(np.nonzero(rerun)[0][:5], dtype=torch.int64, device="cuda")
+    sub = results_numpy(msc.simulate_camps(ctx, circ, off, ch, pa, shot_idx=idx, chi_max=2,
+                                           prefix=prefix))
+    assert np.all(sub["status"] & msc.SHOT_MPS_RERUN)
+    assert np.array_equal(sub["p_acc"], mps["p_acc"][idx.cpu().numpy()])
+    with pytest.raises(msc.MscError):
+        msc.simulate_camps(ctx, circ, off, ch, pa, chi_max=2, prefix=True)

@@ -507,6 +507,40 @@ def main() -> int:
                                        "sample_and_screen_shots_per_s":
                                            total / ((t_screen + t_sample) * 1e-3)}
 
+    if not args.no_extras:
+        # the 17-qubit workloads: 1000 shots w ~ Bin(M, 1e-3) in FP64 (one
+        # launch of the batched kernels), and 65536 shots by subset sampling
+        # (w = 0..4 uniformly) in one persistent launch, FP32 and FP64; faults
+        # drawn on the GPU, every shot simulated (no screen), results read
+        # back by the caller; kernel time by the library's HIP events
+        log("17-qubit workloads")
+        lines = {}
+        for name, cfgname, n, seed, weights in (
+                ("c1_17q_1000_shots", "c1", 1000, 0x5EED0001, None),
+                ("c2_17q_65536_subset_shots", "c2", 65536, 0x5EED0002,
+                 np.arange(65536, dtype=np.int32) % 5)):
+            c17 = msc.Circuit(config_circuit(cfgname).text)
+            c17.calibrate(ctx)
+            o17, ch17, pa17 = msc.sample_faults_device(ctx, c17, seed, 0, n, p=1e-3,
+                                                       weights=weights)
+            line = {"shots": n, "seed": hex(seed)}
+            for pname, prec in (("fp64", msc.MSC_FP64), ("fp32", msc.MSC_FP32)):
+                msc.simulate(ctx, c17, o17, ch17, pa17, precision=prec)   # warm-up
+                ms = []
+                for _ in range(3):
+                    r17 = msc.results_numpy(msc.simulate(ctx, c17, o17, ch17, pa17,
+                                                         precision=prec))
+                    ms.append(ctx.last_kernel_ms("simulate"))
+                t = float(np.median(ms))
+                line[pname] = {"ms": t, "shots_per_s": n / (t * 1e-3),
+                               "gate_updates_per_s": float(r17["n2q"].sum()) / (t * 1e-3),
+                               "chi_peak": int(r17["chi_peak"].max()),
+                               "kernel": ("mps_wave_kernel" if ctx.engine_stats()["wave_slots"]
+                                          else "mps_kernel")}
+            lines[name] = line
+            del o17, ch17, pa17
+        result["workloads_17q"] = lines
+
     if not args.no_extras and order is not None:
         # the same pipeline on the snake layout, for comparison (its own
         # checkpoints built by untimed warm-up steps first)

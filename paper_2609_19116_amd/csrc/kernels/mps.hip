@@ -1108,8 +1108,13 @@ __device__ __forceinline__ int64_t wave_fetch(unsigned long long* ctr) {
 // kernel) in its slot `team` of n_teams: each from its fork point (or from
 // |0...0>) through the op stream to its result, op by op.  S is the team's
 // LDS; NOPS op descriptors are held at a time.
-template <typename T, int SMAX, int W, int NOPS>
+template <typename T, int SMAX, int W, int NOPS, bool EXTRA = true>
 __device__ void run_team(const MpsArgs& P, const Smem& S, const int team, const int n_teams) {
+    // modes compiled in: parking and calibration (the workgroup kernel
+    // only), checkpoint recording and segment reach (EXTRA); a kernel built
+    // without a mode keeps none of its arguments in registers
+    constexpr bool kPark = W != 64;
+    constexpr bool kExtra = EXTRA;
     const int tid = Team<W>::rank();
     const int N = P.n_sites;
     T* slot_base = static_cast<T*>(P.arena) + (size_t)team * P.slot_stride;
@@ -1132,7 +1137,7 @@ __device__ void run_team(const MpsArgs& P, const Smem& S, const int team, const 
     const int64_t n_run = P.n_dev ? min(*P.n_dev, P.n_shots) : P.n_shots;
     // with slot states the grid is the slot count and every launch picks up
     // where the slot's last one stopped
-    ShotState* const st = P.state ? P.state + team : nullptr;
+    ShotState* const st = kPark && P.state ? P.state + team : nullptr;
     int64_t j0 = team;
     bool resume = false;
     if (st) {
@@ -1249,7 +1254,7 @@ __device__ void run_team(const MpsArgs& P, const Smem& S, const int team, const 
             meas_done = h.meas_done;
             // reach of the segments before the fork: the noiseless run's
             // running P_acc, as this shot would have computed it
-            if (P.surv) {
+            if (kExtra && P.surv) {
                 while (next_seg < P.n_seg && P.seg_meas[next_seg] < meas_done) {
                     if (tid == 0) P.surv[it * P.n_seg + next_seg] = P.ck_pm[P.seg_meas[next_seg]];
                     ++next_seg;
@@ -1278,7 +1283,7 @@ __device__ void run_team(const MpsArgs& P, const Smem& S, const int team, const 
                 for (int i = tid; i < ops_hi - ops_lo; i += W) S.ops[i] = P.ops[ops_lo + i];
                 Team<W>::sync();
             }
-            if (P.ck_mode == 1 && !ck_full && next_ck < P.n_ck && P.ck_op[next_ck] == oi) {
+            if (kExtra && P.ck_mode == 1 && !ck_full && next_ck < P.n_ck && P.ck_op[next_ck] == oi) {
                 // ---- record: the state before op oi, densely, site by site
                 int64_t sz = 0;
                 for (int k = 0; k < N; ++k) sz += 4 * (int64_t)S.chi[k] * S.chi[k + 1];
@@ -1516,22 +1521,23 @@ __device__ void run_team(const MpsArgs& P, const Smem& S, const int team, const 
                 team_sum<W, 2>(pp, S.red);
                 const double tot = pp[0] + pp[1];
                 int e;
-                if (P.calibrate) e = pp[1] > pp[0] ? 1 : 0;
+                const bool calib = kPark && P.calibrate;
+                if (calib) e = pp[1] > pp[0] ? 1 : 0;
                 else e = P.expected[op.aux];
                 const double raw = pp[e];
                 const double pe = tot > 0.0 ? raw / tot : 0.0;
-                if (P.calibrate && tid == 0) {
+                if (calib && tid == 0) {
                     P.cal_p[op.aux] = pe;
                     P.cal_e[op.aux] = static_cast<uint8_t>(e);
                 }
-                if (P.surv) {
+                if (kExtra && P.surv) {
                     // segments starting at or before this measurement
                     while (next_seg < P.n_seg && P.seg_meas[next_seg] <= op.aux) {
                         if (tid == 0) P.surv[it * P.n_seg + next_seg] = p_acc;
                         ++next_seg;
                     }
                 }
-                if (P.ck_mode == 1 && P.ck_pm && tid == 0) P.ck_pm[op.aux] = p_acc;
+                if (kExtra && P.ck_mode == 1 && P.ck_pm && tid == 0) P.ck_pm[op.aux] = p_acc;
                 if (!(pe >= P.tau_rej)) {
                     alive = false;
                     acc.status |= MSC_SHOT_REJECTED;
@@ -1668,7 +1674,7 @@ __device__ void run_team(const MpsArgs& P, const Smem& S, const int team, const 
             }
         }
         if (tid == 0 && !retried) {
-            if (P.surv)
+            if (kExtra && P.surv)
                 for (int g = next_seg; g < P.n_seg; ++g) P.surv[it * P.n_seg + g] = p_acc;
             msc_shot_result res;
             res.p_acc = p_acc;
@@ -1780,7 +1786,7 @@ constexpr int kWaveVec = kWaveSmax * (kWaveSmax + 1);     // doubles per plane, 
 constexpr int kWaveWork = 2 * kWaveVec + kWaveStage;      // vectors + staging
 constexpr int kWaveMaxV = 2 * kWaveSmax;                  // vectors of a wide update
 
-template <typename T>
+template <typename T, bool EXTRA>
 __global__ __launch_bounds__(NT, 3) void mps_wave_kernel(MpsArgs P) {
     // per wavefront
     __shared__ int s_chi[NW][kMaxSites + 1];
@@ -1850,7 +1856,7 @@ __global__ __launch_bounds__(NT, 3) void mps_wave_kernel(MpsArgs P) {
     S.soff = s_soff;
     S.shalf = s_shalf;
     S.g1 = s_g1;
-    run_team<T, kWaveSmax, 64, kWaveOps>(P, S, blockIdx.x * NW + w, gridDim.x * NW);
+    run_team<T, kWaveSmax, 64, kWaveOps, EXTRA>(P, S, blockIdx.x * NW + w, gridDim.x * NW);
 }
 
 // ---------------------------------------------------------------------------
@@ -2442,8 +2448,8 @@ int mps_blocks_per_cu(int precision, bool small) {
 int mps_wave_blocks_per_cu(int precision) {
     int b = 0;
     hipError_t e = precision == MSC_FP64
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, mps_wave_kernel<double>, NT, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, mps_wave_kernel<float>, NT, 0);
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, mps_wave_kernel<double, true>, NT, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, mps_wave_kernel<float, true>, NT, 0);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return 1;
@@ -2455,10 +2461,16 @@ hipError_t launch_mps_wave(int precision, const MpsArgs& a, int grid, hipStream_
     static_assert(kWaveTeams == NW, "one team per wavefront");
     if (!a.next || !a.retry_count || !a.retry_list || a.calibrate || a.state)
         return hipErrorInvalidValue;
-    if (precision == MSC_FP64)
-        hipLaunchKernelGGL(mps_wave_kernel<double>, dim3(grid), dim3(NT), 0, s, a);
-    else
-        hipLaunchKernelGGL(mps_wave_kernel<float>, dim3(grid), dim3(NT), 0, s, a);
+    // the kernel without checkpoint recording and segment reach when the
+    // run needs neither (the benchmark's): fewer arguments held in registers
+    const bool extra = a.surv != nullptr || a.ck_mode == 1;
+    if (precision == MSC_FP64) {
+        if (extra) hipLaunchKernelGGL((mps_wave_kernel<double, true>), dim3(grid), dim3(NT), 0, s, a);
+        else hipLaunchKernelGGL((mps_wave_kernel<double, false>), dim3(grid), dim3(NT), 0, s, a);
+    } else {
+        if (extra) hipLaunchKernelGGL((mps_wave_kernel<float, true>), dim3(grid), dim3(NT), 0, s, a);
+        else hipLaunchKernelGGL((mps_wave_kernel<float, false>), dim3(grid), dim3(NT), 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -279,7 +279,9 @@ def main() -> int:
     # which shot kernel ran the steps: the wavefront kernel (one shot per
     # wavefront) or the workgroup kernel
     wave_slots = ctxs[0].engine_stats()["wave_slots"]
-    kernel_name = ("mps_wave_kernel<float>" if wave_slots else
+    # (the wavefront kernel's instance without checkpoint recording and
+    # segment reach, which the timed steps do not use)
+    kernel_name = ("mps_wave_kernel<float, false>" if wave_slots else
                    f"mps_kernel<float,{64 if args.lds_width == 64 else 32}>")
     achieved_job = sum(flops) / wall / 1e12
     sweeps = sum(st["sweeps"] for st in sts)

@@ -19,6 +19,7 @@ Also measured on the same GPU and shot list: the plain FP64 path one shot
 per launch (bounded sample, scaled), the FP32-vs-FP64 probability error,
 the CAMPS engine on the same survivors, the space-time accounting mode,
 the fixed-shape chi = 256 MFMA contraction, the offline screen at scale,
+the 17-qubit workloads (1000 shots; 65536 subset-sampled shots in one launch),
 the batched engine for large two-site updates on the bond-64 and bond-128
 workloads (with the autotuned tile shapes), and the CPU oracle timed on the
 host (bounded sample, one core and all cores); likelihood-ratio intervals
@@ -510,38 +511,8 @@ def main() -> int:
                                            total / ((t_screen + t_sample) * 1e-3)}
 
     if not args.no_extras:
-        # the 17-qubit workloads: 1000 shots w ~ Bin(M, 1e-3) in FP64 (one
-        # launch of the batched kernels), and 65536 shots by subset sampling
-        # (w = 0..4 uniformly) in one persistent launch, FP32 and FP64; faults
-        # drawn on the GPU, every shot simulated (no screen), results read
-        # back by the caller; kernel time by the library's HIP events
         log("17-qubit workloads")
-        lines = {}
-        for name, cfgname, n, seed, weights in (
-                ("c1_17q_1000_shots", "c1", 1000, 0x5EED0001, None),
-                ("c2_17q_65536_subset_shots", "c2", 65536, 0x5EED0002,
-                 np.arange(65536, dtype=np.int32) % 5)):
-            c17 = msc.Circuit(config_circuit(cfgname).text)
-            c17.calibrate(ctx)
-            o17, ch17, pa17 = msc.sample_faults_device(ctx, c17, seed, 0, n, p=1e-3,
-                                                       weights=weights)
-            line = {"shots": n, "seed": hex(seed)}
-            for pname, prec in (("fp64", msc.MSC_FP64), ("fp32", msc.MSC_FP32)):
-                msc.simulate(ctx, c17, o17, ch17, pa17, precision=prec)   # warm-up
-                ms = []
-                for _ in range(3):
-                    r17 = msc.results_numpy(msc.simulate(ctx, c17, o17, ch17, pa17,
-                                                         precision=prec))
-                    ms.append(ctx.last_kernel_ms("simulate"))
-                t = float(np.median(ms))
-                line[pname] = {"ms": t, "shots_per_s": n / (t * 1e-3),
-                               "gate_updates_per_s": float(r17["n2q"].sum()) / (t * 1e-3),
-                               "chi_peak": int(r17["chi_peak"].max()),
-                               "kernel": ("mps_wave_kernel" if ctx.engine_stats()["wave_slots"]
-                                          else "mps_kernel")}
-            lines[name] = line
-            del o17, ch17, pa17
-        result["workloads_17q"] = lines
+        result["workloads_17q"] = workloads_17q(msc, ctx)
 
     if not args.no_extras and order is not None:
         # the same pipeline on the snake layout, for comparison (its own
@@ -599,6 +570,41 @@ def benchmark_layout(msc, ctx, text: str, seed: int = ORDER_SEED, budget: int = 
             "ratio": c_best / c_start, "seconds": time.perf_counter() - t0,
             "order": [int(q) for q in order]}
     return order, info
+
+
+def workloads_17q(msc, ctx) -> dict:
+    """The 17-qubit workloads: 1000 shots w ~ Bin(M, 1e-3) (one launch of the
+    batched kernels), and 65536 shots by subset sampling (w = 0..4
+    uniformly) in one persistent launch, each in FP64 and FP32; faults drawn
+    on the GPU, every shot simulated (no screen), results read back by the
+    caller; kernel time by the library's HIP events."""
+    from workloads.circuits import config_circuit
+    lines = {}
+    for name, cfgname, n17, seed17, weights in (
+            ("c1_17q_1000_shots", "c1", 1000, 0x5EED0001, None),
+            ("c2_17q_65536_subset_shots", "c2", 65536, 0x5EED0002,
+             np.arange(65536, dtype=np.int32) % 5)):
+        c17 = msc.Circuit(config_circuit(cfgname).text)
+        c17.calibrate(ctx)
+        o17, ch17, pa17 = msc.sample_faults_device(ctx, c17, seed17, 0, n17, p=1e-3,
+                                                   weights=weights)
+        line = {"shots": n17, "seed": hex(seed17)}
+        for pname, prec in (("fp64", msc.MSC_FP64), ("fp32", msc.MSC_FP32)):
+            msc.simulate(ctx, c17, o17, ch17, pa17, precision=prec)   # warm-up
+            ms = []
+            for _ in range(3):
+                r17 = msc.results_numpy(msc.simulate(ctx, c17, o17, ch17, pa17,
+                                                     precision=prec))
+                ms.append(ctx.last_kernel_ms("simulate"))
+            t = float(np.median(ms))
+            line[pname] = {"ms": t, "shots_per_s": n17 / (t * 1e-3),
+                           "gate_updates_per_s": float(r17["n2q"].sum()) / (t * 1e-3),
+                           "chi_peak": int(r17["chi_peak"].max()),
+                           "kernel": ("mps_wave_kernel" if ctx.engine_stats()["wave_slots"]
+                                      else "mps_kernel")}
+        lines[name] = line
+        del o17, ch17, pa17
+    return lines
 
 
 def measured_traffic(layout_key: str, kernel_name: str):

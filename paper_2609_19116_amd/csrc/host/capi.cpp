@@ -279,7 +279,12 @@ static int upload(msc_ctx* ctx, msc_circuit* c) {
         for (int ch = 0; ch < c->n_channels; ++ch) {
             const int k = c->chan_kind[ch];
             const int codes = k == CH_DEP1 ? 4 : k == CH_DEP2 ? 16 : k == CH_XERR ? 2 : 64;
-            soff[ch] = static_cast<int32_t>(comb.size() / std::max(1, W));
+            // entry index of the channel's code 0, shifted, with its kind
+            // in the low two bits: the screen reads both with one load
+            const size_t entry = comb.size() / std::max(1, W);
+            if (entry >= (size_t(1) << 29))
+                return set_error(MSC_E_INVALID, "screen table above 2^29 entries");
+            soff[ch] = static_cast<int32_t>(entry << 2) | k;
             for (int p = 0; p < codes; ++p)
                 for (int w = 0; w < W; ++w) {
                     uint64_t x = 0;

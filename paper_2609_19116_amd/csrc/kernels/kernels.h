@@ -147,8 +147,9 @@ enum CsrFlag : int {
     CSR_BAD_PAULI = 4,       // Pauli code zero or beyond the channel's qubits
     CSR_BAD_OFFSETS = 8      // shot_off decreasing or negative
 };
-// sig: per (channel, Pauli code) the fault's W-word signature, the entries
-// of channel c starting at sig_off[c] (code_limit(kind) of them); kind:
+// sig: per (channel, Pauli code) the fault's W-word signature; sig_off[c]
+// holds the index of channel c's first entry shifted left by two with the
+// channel's ChanKind in the low two bits (code_limit(kind) entries); kind:
 // ChanKind per channel (uint8); flag: one device int, cleared first
 hipError_t launch_prescreen(int words, int32_t n_channels, int64_t n, const int64_t* off, const int32_t* chan,
                             const uint8_t* pauli, const uint64_t* sig, const int32_t* sig_off,

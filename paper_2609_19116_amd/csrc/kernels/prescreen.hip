@@ -55,7 +55,7 @@ __global__ __launch_bounds__(PT) void screen_kernel(int32_t nch, int64_t n,
                                                     const uint8_t* __restrict__ pauli,
                                                     const uint64_t* __restrict__ sig,
                                                     const int32_t* __restrict__ sig_off,
-                                                    const uint8_t* __restrict__ kind,
+                                                    const uint8_t* __restrict__ /*kind*/,
                                                     uint64_t* __restrict__ bits,
                                                     int64_t* __restrict__ block_cnt,
                                                     int* __restrict__ flag) {
@@ -72,12 +72,20 @@ __global__ __launch_bounds__(PT) void screen_kernel(int32_t nch, int64_t n,
         for (int64_t f = f0; f < f1; ++f) {
             const int64_t c = chan[f];
             const int p = pauli[f];
-            const int fb = fault_check(c, prev, p, nch, kind);
+            // the channel's first table entry and its kind, one load
+            const int32_t ek = c >= 0 && c < nch ? sig_off[c] : 0;
+            int fb = 0;
+            if (c < 0 || c >= nch) {
+                fb = CSR_BAD_CHANNEL;
+            } else {
+                fb = c <= prev ? CSR_NOT_ASCENDING : 0;
+                if (p == 0 || p >= code_limit(ek & 3)) fb |= CSR_BAD_PAULI;
+            }
             bad |= fb;
             prev = c;
             // an invalid channel or code has no entry (the call fails anyway)
             if (fb & (CSR_BAD_CHANNEL | CSR_BAD_PAULI)) continue;
-            const uint64_t* s = sig + (static_cast<int64_t>(sig_off[c]) + p) * W;
+            const uint64_t* s = sig + (static_cast<int64_t>(ek >> 2) + p) * W;
 #pragma unroll
             for (int w = 0; w < W; ++w) acc[w] ^= s[w];
         }

@@ -324,9 +324,9 @@ int msc_prescreen(msc_ctx* ctx, const msc_circuit* c, int64_t n_shots,
 
 /* msc_prescreen for callers that cannot allocate device memory (code under
    HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
-   the same screen, bit for bit, with its block counts and CSR check word in
-   a fixed per-device array of the library (2 MiB, held until the process
-   ends) instead of context scratch.  At most 2^26 shots per call (else
+   the same screen, bit for bit, with its block counts, their scan and the
+   CSR check word in a fixed per-device array of the library (2 MiB and
+   8 KiB, held until the process ends) instead of context scratch.  At most 2^26 shots per call (else
    MSC_E_INVALID, nothing launched).  The circuit's tables must already be
    on the context's device (msc_circuit_calibrate or an earlier
    msc_prescreen put them there), else MSC_E_STATE.  Every call on one GPU

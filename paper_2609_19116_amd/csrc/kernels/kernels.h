@@ -161,8 +161,8 @@ hipError_t launch_validate_csr(int32_t n_channels, int64_t n, const int64_t* off
                                const int32_t* chan, const uint8_t* pauli, const uint8_t* kind,
                                int* flag, hipStream_t s);
 // Fixed device scratch of msc_prescreen_noalloc (prescreen.hip): at most
-// kNoAllocShots shots per call; the words hold the block counts, their scan
-// and the CSR flag.  prescreen_noalloc_scratch(device) resolves the array's
+// kNoAllocShots shots per call; the words hold the block counts and their
+// scan, the superblock totals, the survivor total and the CSR flag.  prescreen_noalloc_scratch(device) resolves the array's
 // address on `device` (which must be current) once and caches it.
 constexpr int64_t kNoAllocShots = int64_t(1) << 26;
 hipError_t prescreen_noalloc_scratch(int device, int64_t** out);

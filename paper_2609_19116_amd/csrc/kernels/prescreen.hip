@@ -32,6 +32,14 @@ namespace {
 constexpr int kScanT = 256;
 
 constexpr int PT = 256;   // threads per block (4 waves, 256 shots)
+constexpr int kSup = 256; // blocks per superblock of the survivor scan
+
+// tmp words of a screen of n shots: the per-block survivor counts (their
+// scan in place), the superblock totals (their scan in place, plus one),
+// the survivor total and the CSR flag word
+constexpr int64_t screen_tmp_words(int64_t n) {
+    return (n + PT - 1) / PT + ((n + PT - 1) / PT + kSup - 1) / kSup + 1 + 2;
+}
 
 // Largest Pauli code + 1 of each channel kind (ChanKind order): one qubit
 // (x, z bits), two, the X flip (x of qubit 0 only), three.
@@ -135,8 +143,31 @@ __global__ __launch_bounds__(PT) void validate_kernel(int32_t nch, int64_t n,
 // one word set to zero by a kernel (a fill node, not a memset, if captured)
 __global__ void clear_flag_kernel(int* flag) { *flag = 0; }
 
-// exclusive scan of block counts in place (one block), total at [nb]
-__global__ __launch_bounds__(kScanT) void scan_kernel(int64_t* cnt, int64_t nb) {
+// exclusive scan of the block counts within each superblock of kSup blocks,
+// in place (one workgroup per superblock, coalesced), the superblock's total
+// into sup[superblock]
+__global__ __launch_bounds__(kSup) void scan_local_kernel(int64_t* cnt, int64_t nb,
+                                                          int64_t* sup) {
+    __shared__ int64_t s[kSup];
+    const int t = threadIdx.x;
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * kSup + t;
+    const int64_t v = j < nb ? cnt[j] : 0;
+    s[t] = v;
+    __syncthreads();
+    // inclusive scan in LDS, log2(kSup) steps
+    for (int d = 1; d < kSup; d <<= 1) {
+        const int64_t a = t >= d ? s[t - d] : 0;
+        __syncthreads();
+        s[t] += a;
+        __syncthreads();
+    }
+    if (j < nb) cnt[j] = s[t] - v;
+    if (t == kSup - 1) sup[blockIdx.x] = s[t];
+}
+
+// exclusive scan of the superblock totals in place (one block), the total
+// at *total
+__global__ __launch_bounds__(kScanT) void scan_kernel(int64_t* cnt, int64_t nb, int64_t* total) {
     __shared__ int64_t part[kScanT];
     const int tid = threadIdx.x;
     const int64_t per = (nb + kScanT - 1) / kScanT;
@@ -152,7 +183,7 @@ __global__ __launch_bounds__(kScanT) void scan_kernel(int64_t* cnt, int64_t nb) 
             part[j] = run;
             run += v;
         }
-        cnt[nb] = run;
+        *total = run;
     }
     __syncthreads();
     int64_t run = part[tid];
@@ -165,6 +196,7 @@ __global__ __launch_bounds__(kScanT) void scan_kernel(int64_t* cnt, int64_t nb) 
 
 __global__ __launch_bounds__(PT) void scatter_kernel(int64_t n, const uint64_t* __restrict__ bits,
                                                      const int64_t* __restrict__ block_off,
+                                                     const int64_t* __restrict__ sup_off,
                                                      int64_t* __restrict__ idx) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * PT + threadIdx.x;
     const int lane = threadIdx.x & 63;
@@ -174,7 +206,7 @@ __global__ __launch_bounds__(PT) void scatter_kernel(int64_t n, const uint64_t* 
     __shared__ int s_pre[PT / 64];
     if (lane == 0) s_pre[wv] = __popcll(mask);
     __syncthreads();
-    int64_t base = block_off[blockIdx.x];
+    int64_t base = sup_off[blockIdx.x / kSup] + block_off[blockIdx.x];
     for (int w = 0; w < wv; ++w) base += s_pre[w];
     if (i < n && ((mask >> lane) & 1)) {
         const uint64_t below = lane ? (mask & ((1ull << lane) - 1)) : 0ull;
@@ -184,8 +216,7 @@ __global__ __launch_bounds__(PT) void scatter_kernel(int64_t n, const uint64_t* 
 
 }  // namespace
 
-// block counts, then the survivor total, then the CSR flag (one word each)
-int64_t prescreen_tmp_words(int64_t n) { return (n + PT - 1) / PT + 2; }
+int64_t prescreen_tmp_words(int64_t n) { return screen_tmp_words(n); }
 
 hipError_t launch_prescreen(int words, int32_t n_channels, int64_t n, const int64_t* off, const int32_t* chan,
                             const uint8_t* pauli, const uint64_t* sig, const int32_t* sig_off,
@@ -194,7 +225,10 @@ hipError_t launch_prescreen(int words, int32_t n_channels, int64_t n, const int6
                             int64_t n_blocks_tmp, int* flag, hipStream_t s) {
     const int64_t nb = (n + PT - 1) / PT;
     if (nb == 0) return hipSuccess;
-    if (n_blocks_tmp < nb + 1 || !flag) return hipErrorInvalidValue;
+    const int64_t ns = (nb + kSup - 1) / kSup;
+    if (n_blocks_tmp < screen_tmp_words(n) || !flag) return hipErrorInvalidValue;
+    int64_t* sup = block_tmp + nb;                    // ns + 1 words
+    int64_t* total = block_tmp + n_blocks_tmp - 2;    // then the flag word
     hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, s, flag);
     hipError_t e0 = hipGetLastError();
     if (e0 != hipSuccess) return e0;
@@ -219,10 +253,15 @@ hipError_t launch_prescreen(int words, int32_t n_channels, int64_t n, const int6
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanT), 0, s, block_tmp, nb);
+    hipLaunchKernelGGL(scan_local_kernel, dim3(static_cast<unsigned>(ns)), dim3(kSup), 0, s,
+                       block_tmp, nb, sup);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanT), 0, s, sup, ns, total);
     e = hipGetLastError();
     if (e != hipSuccess || !survivor_idx) return e;
-    hipLaunchKernelGGL(scatter_kernel, grid, dim3(PT), 0, s, n, bits, block_tmp, survivor_idx);
+    hipLaunchKernelGGL(scatter_kernel, grid, dim3(PT), 0, s, n, bits, block_tmp, sup,
+                       survivor_idx);
     return hipGetLastError();
 }
 
@@ -241,13 +280,13 @@ hipError_t launch_validate_csr(int32_t n_channels, int64_t n, const int64_t* off
 
 // ---------------------------------------------------------------------------
 // Fixed scratch of msc_prescreen_noalloc: the block counts and their scan
-// (one word per 256 shots and the total) and the CSR flag, for at most
-// kNoAllocShots shots.  Each device holds its own copy until the process
+// (one word per 256 shots), the superblock totals, the survivor total and
+// the CSR flag, for at most kNoAllocShots shots.  Each device holds its own copy until the process
 // ends.  Host code never passes `scratch` itself to a kernel (on the host it
 // is only a stand-in symbol): the device address is resolved once per device
 // with hipGetSymbolAddress and that pointer is used everywhere.
 namespace {
-constexpr int64_t kNoAllocWords = kNoAllocShots / PT + 2;
+constexpr int64_t kNoAllocWords = screen_tmp_words(kNoAllocShots);
 constexpr int kMaxDevices = 64;
 }  // namespace
 

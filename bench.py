@@ -103,6 +103,8 @@ def main() -> int:
     ap.add_argument("--engine-only", action="store_true",
                     help="only the large-bond engine lines (autotune, 81-qubit bond-64 and "
                          "49-qubit bond-128 workloads) and the chi = 256 contraction kernels")
+    ap.add_argument("--screen-only", action="store_true",
+                    help="only the offline-screen line (2^24 shots of the 81-qubit circuit)")
     ap.add_argument("--order-cache", default=None,
                     help="JSON file holding the searched layout: read when it matches the "
                          "search options, else written after the search")
@@ -140,6 +142,12 @@ def main() -> int:
     from workloads.circuits import config_circuit
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.screen_only:
+        ctx = msc.Ctx(0)
+        line, _ = screen_line(msc, ctx, args.p)
+        ctx.close()
+        print(json.dumps({"prescreen_81q": line}), flush=True)
+        return 0
     if args.engine_only:
         ctx = msc.Ctx(0)
         out = {"large_bond_engine": engine_lines(msc, ctx, args),
@@ -469,28 +477,9 @@ def main() -> int:
             "shots_per_s_single_stream": n_st * n4 / t_st}
 
         result.update(contraction_lines(msc, ctx, torch))
-        # offline screen at scale: 2^24 shots of the 81-qubit circuit's
-        # skeleton (faults drawn on the GPU, p = 1e-3), bit-exact against
-        # the oracle in the test suite; algorithmic bytes per shot: its CSR
-        # offset (8 B), 5 B per fault, the survive bit and a survivor index
         log("offline screen, 2^24 shots, 81 qubits")
-        c81 = msc.Circuit(config_circuit("c4").text)
+        result["prescreen_81q"], c81 = screen_line(msc, ctx, args.p)
         n81 = 1 << 24
-        o81, ch81, pa81 = msc.sample_faults_device(ctx, c81, 0x5EED0005, 0, n81, p=args.p)
-        msc.prescreen(ctx, c81, o81, ch81, pa81)
-        sms = []
-        for _ in range(3):
-            _, _, cnt81 = msc.prescreen(ctx, c81, o81, ch81, pa81)
-            sms.append(ctx.last_kernel_ms("prescreen"))
-        ms81 = float(np.mean(sms))
-        nnz81 = int(ch81.numel())
-        byts = 8.0 * (n81 + 1) + 5.0 * nnz81 + n81 / 8.0 + 8.0 * cnt81
-        result["prescreen_81q"] = {"shots": n81, "faults": nnz81, "survivors": cnt81,
-                                   "ms": ms81, "shots_per_s": n81 / (ms81 * 1e-3),
-                                   "bound": "hbm", "achieved": byts / (ms81 * 1e-3) / 1e9,
-                                   "peak": 8000.0, "unit": "GB/s",
-                                   "frac": byts / (ms81 * 1e-3) / 1e9 / 8000.0}
-        del o81, ch81, pa81
         # 1e8 shots of the same skeleton in 2^24-shot chunks (consecutive
         # shot ranges of one seed): fault sampling and screen per chunk
         log("offline screen, 1e8 shots, 81 qubits")
@@ -570,6 +559,34 @@ def benchmark_layout(msc, ctx, text: str, seed: int = ORDER_SEED, budget: int = 
             "ratio": c_best / c_start, "seconds": time.perf_counter() - t0,
             "order": [int(q) for q in order]}
     return order, info
+
+
+def screen_line(msc, ctx, p: float):
+    """The offline screen at scale: 2^24 shots of the 81-qubit circuit's
+    skeleton (faults drawn on the GPU at p), bit-exact against the oracle in
+    the test suite; the call's time by the library's HIP events, mean of
+    three after one warm-up.  Algorithmic bytes per shot: its CSR offset
+    (8 B), 5 B per fault, the survive bit and a survivor index.  Returns the
+    line and the circuit."""
+    from workloads.circuits import config_circuit
+    c81 = msc.Circuit(config_circuit("c4").text)
+    n81 = 1 << 24
+    o81, ch81, pa81 = msc.sample_faults_device(ctx, c81, 0x5EED0005, 0, n81, p=p)
+    msc.prescreen(ctx, c81, o81, ch81, pa81)
+    sms = []
+    for _ in range(3):
+        _, _, cnt81 = msc.prescreen(ctx, c81, o81, ch81, pa81)
+        sms.append(ctx.last_kernel_ms("prescreen"))
+    ms81 = float(np.mean(sms))
+    nnz81 = int(ch81.numel())
+    byts = 8.0 * (n81 + 1) + 5.0 * nnz81 + n81 / 8.0 + 8.0 * cnt81
+    del o81, ch81, pa81
+    return {"shots": n81, "faults": nnz81, "survivors": cnt81,
+            "ms": ms81, "shots_per_s": n81 / (ms81 * 1e-3),
+            "bound": "hbm", "achieved": byts / (ms81 * 1e-3) / 1e9,
+            "peak": 8000.0, "unit": "GB/s",
+            "frac": byts / (ms81 * 1e-3) / 1e9 / 8000.0,
+            "algorithmic_bytes_per_call": byts}, c81
 
 
 def workloads_17q(msc, ctx) -> dict:

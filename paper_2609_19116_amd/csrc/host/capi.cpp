@@ -1470,6 +1470,7 @@ extern "C" int msc_simulate_camps(msc_ctx* ctx, const msc_circuit* c, const msc_
                            static_cast<const int64_t*>(didx), k,
                            static_cast<msc_shot_result*>(dres))))
         return rc;
+    MSC_HIP(hipStreamSynchronize(ctx->stream));   // the rerun may still be in flight
     std::vector<msc_shot_result> r(k);
     MSC_HIP(hipMemcpy(r.data(), dres, k * sizeof(msc_shot_result), hipMemcpyDeviceToHost));
     for (int64_t j = 0; j < k; ++j) {

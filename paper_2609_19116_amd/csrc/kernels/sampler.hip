@@ -32,6 +32,7 @@ namespace {
 constexpr int kScanT = 256;
 
 constexpr int ST = 256;   // shots per block
+constexpr int kSup = 256; // blocks per superblock of the offset scan
 constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
 
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
@@ -112,7 +113,29 @@ __global__ __launch_bounds__(ST) void weight_kernel(int64_t n, uint64_t seed, ui
     if (threadIdx.x == ST - 1) block_tot[blockIdx.x] = s[ST - 1];
 }
 
-// exclusive scan of the block totals in place (one block), grand total at [nb]
+// exclusive scan of the block totals within each superblock of kSup blocks,
+// in place (one workgroup per superblock, coalesced), the superblock's
+// total into sup[superblock]
+__global__ __launch_bounds__(kSup) void local_scan_kernel(int64_t* cnt, int64_t nb,
+                                                          int64_t* sup) {
+    __shared__ int64_t sh[kSup];
+    const int t = threadIdx.x;
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * kSup + t;
+    const int64_t v = j < nb ? cnt[j] : 0;
+    sh[t] = v;
+    __syncthreads();
+    for (int d = 1; d < kSup; d <<= 1) {
+        const int64_t a = t >= d ? sh[t - d] : 0;
+        __syncthreads();
+        sh[t] += a;
+        __syncthreads();
+    }
+    if (j < nb) cnt[j] = sh[t] - v;
+    if (t == kSup - 1) sup[blockIdx.x] = sh[t];
+}
+
+// exclusive scan of the superblock totals in place (one block), grand total
+// at [nb]
 __global__ __launch_bounds__(kScanT) void total_scan_kernel(int64_t* cnt, int64_t nb) {
     __shared__ int64_t part[kScanT];
     const int tid = threadIdx.x;
@@ -142,6 +165,7 @@ __global__ __launch_bounds__(ST) void draw_kernel(int64_t n, uint64_t seed, uint
                                                   const double* __restrict__ cdf, int32_t n_cdf,
                                                   int64_t M, const uint8_t* __restrict__ kind,
                                                   const int64_t* __restrict__ block_base,
+                                                  const int64_t* __restrict__ sup_base,
                                                   int64_t nnz_cap, int64_t* __restrict__ shot_off,
                                                   int32_t* __restrict__ chan,
                                                   uint8_t* __restrict__ pauli) {
@@ -150,7 +174,7 @@ __global__ __launch_bounds__(ST) void draw_kernel(int64_t n, uint64_t seed, uint
     if (i >= n) return;
     DevRng rng(seed, first + static_cast<uint64_t>(i));
     const int64_t w = draw_weight(rng, i, weights, cdf, n_cdf, M);
-    const int64_t end = shot_off[i + 1] + block_base[blockIdx.x];
+    const int64_t end = shot_off[i + 1] + block_base[blockIdx.x] + sup_base[blockIdx.x / kSup];
     shot_off[i + 1] = end;
     const int64_t o = end - w;
     if (w == 0 || end > nnz_cap) return;
@@ -186,7 +210,11 @@ __global__ __launch_bounds__(ST) void draw_kernel(int64_t n, uint64_t seed, uint
 
 }  // namespace
 
-int64_t sampler_tmp_words(int64_t n) { return (n + ST - 1) / ST + 1; }
+// the block totals, the superblock totals, the grand total
+int64_t sampler_tmp_words(int64_t n) {
+    const int64_t nb = (n + ST - 1) / ST;
+    return nb + (nb + kSup - 1) / kSup + 1;
+}
 
 hipError_t launch_sampler(int64_t n, uint64_t seed, uint64_t first, const int32_t* weights,
                           const double* cdf, int32_t n_cdf, int64_t M, const uint8_t* kind,
@@ -194,18 +222,24 @@ hipError_t launch_sampler(int64_t n, uint64_t seed, uint64_t first, const int32_
                           int64_t* tmp, int64_t n_tmp, hipStream_t s) {
     const int64_t nb = (n + ST - 1) / ST;
     if (nb == 0) return hipSuccess;
-    if (n_tmp < nb + 1 || nb > 0x7fffffff) return hipErrorInvalidValue;
+    const int64_t ns = (nb + kSup - 1) / kSup;
+    if (n_tmp < nb + ns + 1 || nb > 0x7fffffff) return hipErrorInvalidValue;
+    int64_t* sup = tmp + nb;
     if (!weights && (!cdf || n_cdf < 1)) return hipErrorInvalidValue;
     const dim3 grid(static_cast<unsigned>(nb));
     hipLaunchKernelGGL(weight_kernel, grid, dim3(ST), 0, s, n, seed, first, weights, cdf, n_cdf, M,
                        shot_off, tmp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(total_scan_kernel, dim3(1), dim3(kScanT), 0, s, tmp, nb);
+    hipLaunchKernelGGL(local_scan_kernel, dim3(static_cast<unsigned>(ns)), dim3(kSup), 0, s, tmp,
+                       nb, sup);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(total_scan_kernel, dim3(1), dim3(kScanT), 0, s, sup, ns);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(draw_kernel, grid, dim3(ST), 0, s, n, seed, first, weights, cdf, n_cdf, M,
-                       kind, tmp, nnz_cap, shot_off, chan, pauli);
+                       kind, tmp, sup, nnz_cap, shot_off, chan, pauli);
     return hipGetLastError();
 }
 

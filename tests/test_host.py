@@ -232,3 +232,24 @@ def test_device_calls_reject_null_context():
     assert L.msc_prescreen(None, None, 0, None, None, None, None, None, C.byref(cnt)) \
         == _lib.MSC_E_INVALID
     assert L.msc_twosite_contract(None, 1, 64, 1, None, None, None, None) == _lib.MSC_E_INVALID
+
+
+def test_reciprocal_index_split_is_exact():
+    """The shot kernels split an element index i into i / d and i % d as
+    trunc(i * inv + inv / 2) with inv an approximation of 1/d (a hardware
+    reciprocal refined by one Newton step: relative error far below
+    2^-40).  The exact quotient of i + 1/2 lies at least 1/(2d) from an
+    integer, so the split is exact for 0 <= i < 2^31 and 0 < d < 2^20:
+    checked with inv off by +-2^-40 relative, on every divisor up to 2048
+    and some large ones, at the indices next to every multiple of d up to
+    2^16 and near 2^31."""
+    rng = np.random.default_rng(7)
+    for d in list(range(1, 2049)) + [4095, 65535, (1 << 20) - 1]:
+        k = np.arange(0, (1 << 16) // d + 2, dtype=np.int64)
+        near = np.concatenate([k * d - 1, k * d, k * d + d - 1])
+        top = (1 << 31) - 1 - np.arange(0, 4 * d, max(1, d // 8), dtype=np.int64)
+        i = np.concatenate([near[near >= 0], top, rng.integers(0, 1 << 31, 64)])
+        for pert in (1.0 - 2.0 ** -40, 1.0 + 2.0 ** -40):
+            inv = (1.0 / d) * pert
+            q = np.trunc(i.astype(np.float64) * inv + 0.5 * inv).astype(np.int64)
+            assert np.array_equal(q, i // d), d

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -1329,6 +1330,9 @@ static int run_camps(msc_ctx* ctx, msc_circuit* c, int chi_cap, double tau, doub
                      const int64_t* shot_off, const int32_t* chan, const uint8_t* pauli,
                      const int64_t* shot_idx, msc_shot_result* out, int ck_mode,
                      CampsPrefix* pk, const char* timer);
+static int camps_rerun(msc_ctx* ctx, const msc_circuit* c, const msc_sim_opts* opts, int64_t n,
+                       int64_t n_shots, const int64_t* shot_off, const int32_t* chan,
+                       const uint8_t* pauli, const int64_t* shot_idx, msc_shot_result* out);
 
 // Checkpoints of the noiseless CAMPS run: before the fault op of every
 // ck_k-th channel (at most 256 of them) and before the read-out, densely
@@ -1438,6 +1442,20 @@ extern "C" int msc_simulate_camps(msc_ctx* ctx, const msc_circuit* c, const msc_
                         opts->prefix ? &cc->camps_prefix : nullptr, "camps")))
         return rc;
     // shots whose residual outgrew the cap: run again by the FP64 MPS path
+    try {
+        return camps_rerun(ctx, c, opts, n, n_shots, shot_off, chan, pauli, shot_idx, out);
+    } catch (const std::bad_alloc&) {
+        return set_error(MSC_E_OOM, "host memory for the CAMPS rerun");
+    }
+}
+
+// The records of a CAMPS launch whose residual outgrew the cap (status
+// MSC_SHOT_CHI_CAP) replaced by the FP64 MPS path's, flagged
+// MSC_SHOT_MPS_RERUN (out and shot_idx on the device).
+static int camps_rerun(msc_ctx* ctx, const msc_circuit* c, const msc_sim_opts* opts, int64_t n,
+                       int64_t n_shots, const int64_t* shot_off, const int32_t* chan,
+                       const uint8_t* pauli, const int64_t* shot_idx, msc_shot_result* out) {
+    int rc;
     std::vector<msc_shot_result> h(n);
     MSC_HIP(hipMemcpy(h.data(), out, n * sizeof(msc_shot_result), hipMemcpyDeviceToHost));
     std::vector<int64_t> pos, ids;
@@ -1745,10 +1763,10 @@ extern "C" int msc_autotune(msc_ctx* ctx, int32_t precision, int32_t reps, const
     return MSC_OK;
 }
 
-extern "C" int msc_engine_update(msc_ctx* ctx, int32_t precision, int32_t chi_l,
-                                 int32_t chi_m, int32_t chi_r, int32_t batch, int32_t dir,
-                                 int32_t gate, int32_t chi_max, double tau, const double* A,
-                                 const double* B, double* A_out, double* B_out, int32_t* r_out) {
+static int engine_update(msc_ctx* ctx, int32_t precision, int32_t chi_l, int32_t chi_m,
+                         int32_t chi_r, int32_t batch, int32_t dir, int32_t gate, int32_t chi_max,
+                         double tau, const double* A, const double* B, double* A_out,
+                         double* B_out, int32_t* r_out) {
     if (!ctx || !A || !B || !A_out || !B_out || !r_out) return set_error(MSC_E_INVALID, "null argument");
     if (precision != MSC_FP32 && precision != MSC_FP64 && precision != MSC_BF16X3)
         return set_error(MSC_E_INVALID, "unknown precision");
@@ -1888,6 +1906,20 @@ extern "C" int msc_engine_update(msc_ctx* ctx, int32_t precision, int32_t chi_l,
         std::copy(slot + 2 * pa + pb, slot + 2 * pa + pb + ub, bo + ob);
     }
     return MSC_OK;
+}
+
+// (host staging of a large batch can exceed host memory: no C++ exception
+// crosses the ABI)
+extern "C" int msc_engine_update(msc_ctx* ctx, int32_t precision, int32_t chi_l,
+                                 int32_t chi_m, int32_t chi_r, int32_t batch, int32_t dir,
+                                 int32_t gate, int32_t chi_max, double tau, const double* A,
+                                 const double* B, double* A_out, double* B_out, int32_t* r_out) {
+    try {
+        return engine_update(ctx, precision, chi_l, chi_m, chi_r, batch, dir, gate, chi_max, tau,
+                             A, B, A_out, B_out, r_out);
+    } catch (const std::bad_alloc&) {
+        return set_error(MSC_E_OOM, "host memory for the engine update's staging");
+    }
 }
 
 extern "C" int msc_twosite_contract(msc_ctx* ctx, int32_t precision, int32_t chi, int32_t batch,
